@@ -1,0 +1,163 @@
+#!/usr/bin/env python3
+"""Throughput of the steady-state memristor-crossbar solver on one MI355X.
+
+One step = one full mca_solve (Newton + preconditioned flexible GMRES) of the
+standard 1024 x 1024 crossbar (about 2.1M unknowns, FP64) from V = 0 to the
+Newton tolerance 1e-10 (||F|| / ||Y||) with GMRES(30) tolerance 1e-8, inputs
+already resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 1024]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--size", type=int, default=1024, help="crossbar is size x size")
+    p.add_argument("--seed", type=int, default=0)
+    p.add_argument("--precond", choices=["literal", "permode"], default="literal")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-timing", action="store_true",
+                   help="do not time kernel classes with HIP events (no roofline object)")
+    return p.parse_args()
+
+
+def cpu_baseline(cb):
+    """The CPU oracle (plain FP64 C, one thread) on the same crossbar: one full
+    Newton solve with CG linear steps (the oracle's large-size method)."""
+    import numpy as np  # noqa: F401
+    import oracle
+    t0 = time.perf_counter()
+    oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="cg")
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full {cb.geom.m}x{cb.geom.n} solve (Newton, CG linear steps, "
+                      f"to the FP64 floor), single thread, {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this solver has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2109_07929_amd import Plan, synth
+    from paper_2109_07929_amd import binding as B
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    m = n = args.size
+    cb = synth.crossbar(m, n, seed=args.seed)
+    g_dev = torch.from_numpy(cb.g_dev).to(dev)
+    v_in = torch.from_numpy(cb.v_in).to(dev)
+
+    t0 = time.perf_counter()
+    plan = Plan(cb.geom, device=dev)
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+
+    form = B.MCA_PRECOND_LITERAL if args.precond == "literal" else B.MCA_PRECOND_PERMODE
+    flags = 0 if args.no_timing else B.MCA_FLAG_TIMING
+    opts = B.options(precond=form, flags=flags)
+    v_t = torch.zeros((m, n), dtype=torch.float64, device=dev)
+    v_b = torch.zeros_like(v_t)
+    ws = plan.workspace(opts)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return B.mca_solve(plan.handle, m, n, g_dev, v_in, v_t, v_b, opts, ws, stream)[1]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"# warmup done ({args.warmup} solves)", file=sys.stderr, flush=True)
+
+    kms = np.zeros(B.MCA_NUM_KCLASS)
+    klaunch = np.zeros(B.MCA_NUM_KCLASS, dtype=np.int64)
+    newton, krylov = [], []
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        st = step()
+        kms += np.array(st.kernel_ms[:])
+        klaunch += np.array(st.kernel_launches[:])
+        newton.append(st.newton_iters)
+        krylov.append(st.krylov_iters)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    total_ms = ev0.elapsed_time(ev1)
+    ms_per_step = total_ms / args.steps
+    value = 1e3 / ms_per_step
+
+    # roofline of the dominant kernel: the FP64 eigenbasis GEMMs
+    roofline = None
+    if not args.no_timing and klaunch[B.MCA_KCLASS_GEMM] > 0:
+        flops_per_launch = 2.0 * m * n * (m if True else n)   # 2 M N K, K = m (= n here)
+        if form == B.MCA_PRECOND_PERMODE:
+            flops_per_launch *= 2.0                            # two layers per launch
+        avg_ms = kms[B.MCA_KCLASS_GEMM] / klaunch[B.MCA_KCLASS_GEMM]
+        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": "k_gemm_tn_f64 (eigenbasis transform)",
+                    "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
+                    "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2),
+                    "flops_per_launch": flops_per_launch}
+    breakdown = {}
+    if not args.no_timing:
+        names = ["gemm", "jacobian", "ortho", "residual"]
+        for c, nm in enumerate(names):
+            breakdown[nm] = {"ms_per_solve": round(kms[c] / args.steps, 4),
+                             "launches_per_solve": int(klaunch[c] // args.steps)}
+
+    out = {
+        "metric": "MCA solves/s at 1024x1024, 1e-8 rel residual: plain FP64 vs batched+warm+mixed",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"plain FP64 Newton-FGMRES(30), {m}x{n} crossbar "
+                               f"({2 * m * n} unknowns), seed {args.seed}",
+                   "precond": args.precond, "newton_tol": opts.newton_tol,
+                   "gmres_tol": opts.gmres_tol, "setup_ms": round(setup_ms, 1),
+                   "newton_iters": newton[-1], "krylov_iters": krylov[-1],
+                   "wall_s": round(wall, 3)},
+        "roofline": roofline,
+        "kernel_breakdown": breakdown,
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cb)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

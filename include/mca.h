@@ -1,0 +1,227 @@
+/*
+ * mca.h -- C ABI of the MI355X (gfx950) steady-state memristor-crossbar solver.
+ *
+ * The method is the one of "A Fast Method for Steady-State Memristor Crossbar
+ * Array Circuit Simulation" (Xie, Song, Zhou, Mei, Chen): Newton's method on
+ * the nodal equations of a crossbar made of two uniform wire grids joined by
+ * one nonlinear device per crosspoint, each Newton system solved by GMRES
+ * preconditioned with the block matrix P of eq. (P), whose inverse is applied
+ * through the block-inversion formula (eq. (block)) and the Kronecker
+ * structure of the wire matrices (eqs. (Gt), (Gb), (M)).
+ *
+ * Conventions shared by every call
+ *   - Crossbar: m rows x n columns.  Row i is one top-layer wire (nodes
+ *     (i,0)..(i,n-1)); column j is one bottom-layer wire (nodes (0,j)..(m-1,j)).
+ *     Both layers use the same row-major index k = i*n + j (the paper's
+ *     perpendicular natural indexing, Section III-A), so every m x n array
+ *     is a row-major block of m*n doubles.
+ *   - Array arguments named *_t / *_b / d / g_dev are DEVICE pointers to m*n
+ *     float64 values, v_in is a device pointer to m float64 values.  Memory is
+ *     owned by the caller; the library allocates no device memory of its own.
+ *     Input arrays may not overlap output arrays unless stated.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  mca_residual,
+ *     mca_jacobian_apply and mca_precond_apply only enqueue work on it and
+ *     return; mca_solve synchronises it (its Newton/GMRES control reads a few
+ *     scalars back per iteration).
+ *   - Every call returns an mca_status; no C++ exception crosses the ABI.
+ *     After MCA_ERR_HIP, mca_last_error() names the failing HIP call.
+ *   - Calls on one plan from several host threads are safe as long as they
+ *     use distinct workspaces and output buffers.
+ */
+#ifndef MCA_H
+#define MCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mca_status;
+#define MCA_OK                 0
+#define MCA_ERR_INVALID_ARG    1   /* a size, conductance, option or pointer is invalid   */
+#define MCA_ERR_NONFINITE      2   /* NaN/Inf met in the inputs or during a solve         */
+#define MCA_ERR_WORKSPACE      3   /* workspace too small, or plan not uploaded            */
+#define MCA_ERR_NOT_CONVERGED  4   /* iteration limit reached; last iterate + stats kept  */
+#define MCA_ERR_BREAKDOWN      5   /* GMRES breakdown before convergence                  */
+#define MCA_ERR_HIP            6   /* a HIP runtime call failed                           */
+
+/* Device models: the current I(u) that flows from the top node into the bottom
+ * node through the device at a crosspoint, u = V_t - V_b.                      */
+#define MCA_DEVICE_SINH    0   /* I = g v0 sinh(u / v0), dI/du = g cosh(u / v0) */
+#define MCA_DEVICE_LINEAR  1   /* I = g u,               dI/du = g              */
+
+/* Arithmetic of the preconditioner's eigenbasis transforms.  The Newton
+ * residual, the Jacobian products, the Arnoldi orthogonalisation and the
+ * Hessenberg least squares are FP64 in every mode.                          */
+#define MCA_PREC_FP64      0
+#define MCA_PREC_FP32      1   /* FP32 transforms (flexible GMRES absorbs the error)      */
+#define MCA_PREC_BF16X3    2   /* split-BF16 (hi+lo) operands, 3 MFMA products, FP32 acc  */
+
+/* How P^{-1} r is evaluated (both give P^{-1} of eq. (P) in exact arithmetic). */
+#define MCA_PRECOND_LITERAL  0 /* the paper's order: w = r_b - D B^{-1} r_t, z_t = M^{-1} w,
+                                  z_b = B^{-1}(r_t - A z_t)  (eqs. (block), (M))            */
+#define MCA_PRECOND_PERMODE  1 /* the same 2x2 block formula applied per Kronecker eigenmode */
+#define MCA_PRECOND_NONE     2 /* z = r (unpreconditioned GMRES, for comparison)            */
+
+#define MCA_FLAG_INITIAL_GUESS 1  /* mca_solve starts from v_t/v_b instead of V = 0       */
+#define MCA_FLAG_TIMING        2  /* mca_solve times its kernel classes with HIP events     */
+
+/* Kernel classes timed under MCA_FLAG_TIMING (mca_stats.kernel_ms / kernel_launches). */
+#define MCA_KCLASS_GEMM      0    /* eigenbasis transforms of the preconditioner          */
+#define MCA_KCLASS_JACOBIAN  1    /* Jacobian products                                    */
+#define MCA_KCLASS_ORTHO     2    /* Arnoldi orthogonalisation and normalisation passes   */
+#define MCA_KCLASS_RESIDUAL  3    /* residual evaluations                                 */
+#define MCA_NUM_KCLASS       4
+
+#define MCA_MAX_RESTART   64
+#define MCA_MAX_NEWTON    64
+
+/* One crossbar geometry (Section II): two uniform wire layers, one segment
+ * conductance per layer, plus the boundary drive and terminations.
+ *   Top wire i:    V_in[i] --g_src-- (i,0) --g_top-- ... --g_top-- (i,n-1) --g_top_end-- ground
+ *   Bottom wire j: ground --g_bot_end0-- (0,j) --g_bot-- ... --g_bot-- (m-1,j) --g_bot_end1-- ground
+ * Each wire's conductance matrix (eq. (G)) is tridiagonal with -g off the
+ * diagonal, 2g inside the diagonal and g + (end conductance) at its two ends;
+ * tying both ends through g gives the paper's eq. (G) exactly.
+ * Valid geometry: m, n >= 1; every conductance finite and >= 0; g_top, g_bot
+ * > 0; g_src + g_top_end > 0; g_bot_end0 + g_bot_end1 > 0 (so that neither
+ * wire matrix is singular); v0 > 0 for the sinh device.                     */
+typedef struct mca_geometry {
+    int32_t m, n;
+    int32_t device_model;          /* MCA_DEVICE_*                                  */
+    int32_t reserved;              /* must be 0                                     */
+    double  g_top, g_bot;          /* wire segment conductance per layer [S]       */
+    double  g_src;                 /* drive source -> top node (i,0) [S]           */
+    double  g_top_end;             /* top node (i,n-1) -> ground [S]               */
+    double  g_bot_end0, g_bot_end1;/* bottom nodes (0,j), (m-1,j) -> ground [S]    */
+    double  v0;                    /* device voltage scale [V]                      */
+} mca_geometry;
+
+/* Newton / flexible-GMRES controls.  mca_options_default fills:
+ * newton_tol 1e-10, gmres_tol 1e-8, restart 30, max_newton 50, max_krylov 600,
+ * precision MCA_PREC_FP64, precond MCA_PRECOND_LITERAL, flags 0.              */
+typedef struct mca_options {
+    double  newton_tol;   /* stop when ||F(V)||_2 <= newton_tol * ||Y||_2              */
+    double  gmres_tol;    /* inner stop: ||J dV + F||_2 <= gmres_tol * ||F||_2          */
+    int32_t restart;      /* flexible GMRES restart length, 1..MCA_MAX_RESTART          */
+    int32_t max_newton;   /* Newton steps, 1..MCA_MAX_NEWTON                            */
+    int32_t max_krylov;   /* GMRES iterations per Newton step (over all restarts)       */
+    int32_t precision;    /* MCA_PREC_*                                                 */
+    int32_t precond;      /* MCA_PRECOND_*                                              */
+    int32_t flags;        /* MCA_FLAG_*                                                 */
+} mca_options;
+
+typedef struct mca_stats {
+    int32_t newton_iters;                 /* Newton steps taken                          */
+    int32_t krylov_iters;                 /* GMRES iterations over all Newton steps      */
+    int32_t backtracks;                   /* step halvings of the line search            */
+    int32_t restarts;                     /* GMRES restarts over all Newton steps        */
+    double  rel_residual;                 /* final ||F||_2 / ||Y||_2                     */
+    double  a_last;                       /* a1 = a2 = mean dI/du of the last Newton step */
+    double  residual_history[MCA_MAX_NEWTON + 1]; /* ||F||/||Y|| before each step        */
+    int32_t krylov_history[MCA_MAX_NEWTON];       /* GMRES iterations of each step       */
+    /* MCA_FLAG_TIMING only (zero otherwise): GPU time of each kernel class between
+     * HIP events recorded on the solve's stream around each group of launches, and
+     * the number of kernel launches in those groups.                             */
+    double  kernel_ms[MCA_NUM_KCLASS];
+    int32_t kernel_launches[MCA_NUM_KCLASS];
+} mca_stats;
+
+typedef struct mca_plan mca_plan;
+
+void        mca_options_default(mca_options *opts);
+const char *mca_status_string(mca_status s);
+const char *mca_last_error(void);     /* thread-local text of the last MCA_ERR_HIP */
+
+/* Validate `geom` and build the preconditioner's geometry data on the host:
+ * the eigen-decompositions G_top = Q_n diag(lt) Q_n^T (n x n) and
+ * G_bot = Q_m diag(lb) Q_m^T (m x m) of the two wire matrices.  The paper
+ * writes P^{-1} through Kronecker products of these matrices (eqs. (M),
+ * (M-1hat), (2matrix4)); their eigenbasis turns every Kronecker factor into a
+ * diagonal, so a1, a2 only shift eigenvalues and nothing is refactorised per
+ * Newton step.  *out receives a host object freed by mca_plan_destroy.
+ * Errors: MCA_ERR_INVALID_ARG (bad geometry or NULL out).                    */
+mca_status mca_plan_create(const mca_geometry *geom, mca_plan **out);
+void       mca_plan_destroy(mca_plan *plan);
+
+/* Host copy of one wire's eigen-decomposition (the plan's set-up data):
+ * layer 0 = top wire (G_top, n x n), layer 1 = bottom wire (G_bot, m x m).
+ * lambda (may be NULL) receives the eigenvalues in ascending order, q (may be
+ * NULL) the row-major eigenvector matrix, q[i*len + k] = entry i of vector k.
+ * Host memory only; needs no GPU.  Errors: MCA_ERR_INVALID_ARG.             */
+mca_status mca_plan_host_eigen(const mca_plan *plan, int32_t layer, double *lambda, double *q);
+
+/* Device bytes the plan needs (Q_m, Q_m^T, Q_n, Q_n^T and the eigenvalues). */
+size_t     mca_plan_device_bytes(const mca_plan *plan);
+
+/* Copy the plan's data into `dev_buf` (caller-owned device memory of at least
+ * mca_plan_device_bytes bytes, 256-byte aligned) on `stream` and remember it.
+ * The buffer must outlive every later call on this plan.  Synchronises stream.
+ * Errors: MCA_ERR_INVALID_ARG, MCA_ERR_WORKSPACE (too small), MCA_ERR_HIP.  */
+mca_status mca_plan_upload(mca_plan *plan, void *dev_buf, size_t bytes, void *stream);
+
+/* Device workspace (bytes, 256-byte aligned) for mca_solve with `opts`
+ * (NULL = defaults), and for mca_precond_apply with a form and precision.   */
+size_t     mca_workspace_bytes(const mca_plan *plan, const mca_options *opts);
+size_t     mca_precond_workspace_bytes(const mca_plan *plan, int32_t form, int32_t precision);
+
+/* MNA residual, eqs. (MNA) and (F):
+ *   f_t = G_t v_t + I(v_t - v_b) - Y_t,   f_b = G_b v_b - I(v_t - v_b)
+ * with G_t = I_m (x) G_top, G_b = G_bot (x) I_n (eqs. (Gt), (Gb)),
+ * Y_t[i,0] = g_src v_in[i] (zero elsewhere), Y_b = 0, and
+ *   d = dI/du at every crosspoint (the diagonal of the device blocks of eq. (J)).
+ * g_dev: device conductances.  f_t, f_b, d: outputs (d may be NULL).
+ * Asynchronous on stream.  Errors: MCA_ERR_INVALID_ARG, MCA_ERR_WORKSPACE
+ * (plan not uploaded), MCA_ERR_HIP.                                         */
+mca_status mca_residual(const mca_plan *plan, const double *g_dev, const double *v_in,
+                        const double *v_t, const double *v_b,
+                        double *f_t, double *f_b, double *d, void *stream);
+
+/* Jacobian product y = J x, eq. (J):
+ *   y_t = G_t x_t + d (x_t - x_b),   y_b = G_b x_b - d (x_t - x_b)
+ * (the four device blocks are diagonal, +-d, Section III-A).  d is the device
+ * slope array of the linearisation point.  Asynchronous on stream.
+ * Errors: MCA_ERR_INVALID_ARG, MCA_ERR_WORKSPACE (plan not uploaded), MCA_ERR_HIP. */
+mca_status mca_jacobian_apply(const mca_plan *plan, const double *d,
+                              const double *x_t, const double *x_b,
+                              double *y_t, double *y_b, void *stream);
+
+/* Preconditioner solve z = P^{-1} r for
+ *   P = [[G_t + a1 I, -a1 I], [-a2 I, G_b + a2 I]]          (eq. (P))
+ * with a1, a2 > 0 (in the solver both are the mean device slope).  `form`
+ * picks the evaluation order (MCA_PRECOND_LITERAL or MCA_PRECOND_PERMODE; see
+ * above), `precision` the arithmetic of the eigenbasis transforms.  The
+ * Kronecker factor M^{-1} of eq. (M) is applied exactly through the wire
+ * eigenbases: M^{-1} w <-> Q_m [(Q_m^T W Q_n) ./ mu] Q_n^T with
+ *   mu_pq = lb_p lt_q / a1 + lb_p + (a2 / a1) lt_q.
+ * ws: device workspace of mca_precond_workspace_bytes(plan, form, precision).
+ * r_* and z_* must not overlap.  Asynchronous on stream.
+ * Errors: MCA_ERR_INVALID_ARG, MCA_ERR_WORKSPACE, MCA_ERR_HIP.               */
+mca_status mca_precond_apply(const mca_plan *plan, int32_t form, int32_t precision,
+                             double a1, double a2,
+                             const double *r_t, const double *r_b,
+                             double *z_t, double *z_b,
+                             void *ws, size_t ws_bytes, void *stream);
+
+/* Steady state: v_t, v_b with F(v_t, v_b) = 0 (eq. (F)), by Newton's method
+ * (eq. (Newton3)); each step solves J dV = -F with flexible GMRES(restart),
+ * modified Gram-Schmidt Arnoldi, right-preconditioned by P (eq. (P)) with
+ * a1 = a2 = mean(dI/du) of the current iterate (Section III-A).  Each Newton
+ * step is damped by halving while ||F(V + s dV)|| > (1 - 1e-4 s) ||F(V)||.
+ * Starts from V = 0 (whose first step is the linear solve J(0)^{-1} Y), or
+ * from v_t/v_b with MCA_FLAG_INITIAL_GUESS.  Writes the final iterate to
+ * v_t, v_b in every outcome except MCA_ERR_INVALID_ARG / MCA_ERR_WORKSPACE.
+ * stats (host, may be NULL) is filled in every outcome.  Synchronises stream.
+ * Errors: MCA_ERR_INVALID_ARG, MCA_ERR_WORKSPACE, MCA_ERR_NONFINITE,
+ * MCA_ERR_NOT_CONVERGED, MCA_ERR_BREAKDOWN, MCA_ERR_HIP.                     */
+mca_status mca_solve(const mca_plan *plan, const double *g_dev, const double *v_in,
+                     double *v_t, double *v_b, const mca_options *opts,
+                     void *ws, size_t ws_bytes, mca_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCA_H */

@@ -1,0 +1,98 @@
+"""MI355X-native steady-state memristor-crossbar (MCA) solver.
+
+The solver is libmca.so (HIP kernels for gfx950 behind the C ABI of
+include/mca.h).  This package is its Python binding: ``binding`` mirrors the
+C entry points name for name, and :class:`Plan` bundles a plan with the torch
+buffers (device memory) it needs.  ``synth`` draws seeded synthetic crossbars.
+"""
+
+from __future__ import annotations
+
+from . import binding, synth
+from .binding import (MCA_DEVICE_LINEAR, MCA_DEVICE_SINH, MCA_FLAG_INITIAL_GUESS,
+                      MCA_PREC_BF16X3, MCA_PREC_FP32, MCA_PREC_FP64, MCA_PRECOND_LITERAL,
+                      MCA_PRECOND_NONE, MCA_PRECOND_PERMODE, MCAError, mca_geometry,
+                      mca_options, mca_stats, options)
+
+__all__ = ["Plan", "binding", "synth", "options", "MCAError", "mca_geometry", "mca_options",
+           "mca_stats"]
+
+
+class Plan:
+    """A crossbar geometry's plan, uploaded to the current GPU.
+
+    Holds the host plan handle and the device block of its eigenbases.  All
+    array arguments are float64 torch tensors on the same GPU.
+    """
+
+    def __init__(self, geom, device="cuda"):
+        import torch
+        self.geom = geom
+        self.m, self.n = int(geom.m), int(geom.n)
+        self.device = torch.device(device)
+        self.handle = binding.mca_plan_create(binding.geometry_from(geom))
+        nbytes = binding.mca_plan_device_bytes(self.handle)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        binding.mca_plan_upload(self.handle, self.buf)
+        self._ws = None
+        self._ws_key = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            binding.mca_plan_destroy(h)
+            self.handle = None
+
+    def _zeros(self):
+        import torch
+        return torch.zeros((self.m, self.n), dtype=torch.float64, device=self.device)
+
+    def residual(self, g_dev, v_in, v_t, v_b):
+        f_t, f_b, d = self._zeros(), self._zeros(), self._zeros()
+        binding.mca_residual(self.handle, self.m, self.n, g_dev, v_in, v_t, v_b, f_t, f_b, d)
+        return f_t, f_b, d
+
+    def jacobian_apply(self, d, x_t, x_b):
+        y_t, y_b = self._zeros(), self._zeros()
+        binding.mca_jacobian_apply(self.handle, self.m, self.n, d, x_t, x_b, y_t, y_b)
+        return y_t, y_b
+
+    def precond_workspace(self, form, precision=MCA_PREC_FP64):
+        import torch
+        nbytes = binding.mca_precond_workspace_bytes(self.handle, form, precision)
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def precond_apply(self, a1, a2, r_t, r_b, form=MCA_PRECOND_LITERAL,
+                      precision=MCA_PREC_FP64, ws=None):
+        z_t, z_b = self._zeros(), self._zeros()
+        if ws is None:
+            ws = self.precond_workspace(form, precision)
+        binding.mca_precond_apply(self.handle, self.m, self.n, form, precision, a1, a2,
+                                  r_t, r_b, z_t, z_b, ws)
+        return z_t, z_b
+
+    def workspace(self, opts=None):
+        import torch
+        nbytes = binding.mca_workspace_bytes(self.handle, opts)
+        key = nbytes
+        if self._ws is None or self._ws_key != key:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._ws_key = key
+        return self._ws
+
+    def solve(self, g_dev, v_in, opts=None, guess=None, out=None, check=True):
+        """(v_t, v_b, status, stats) of the steady state."""
+        if opts is None:
+            opts = options()
+        if out is None:
+            v_t, v_b = self._zeros(), self._zeros()
+        else:
+            v_t, v_b = out
+        if guess is not None:
+            v_t.copy_(guess[0])
+            v_b.copy_(guess[1])
+            opts.flags |= MCA_FLAG_INITIAL_GUESS
+        ws = self.workspace(opts)
+        status, stats = binding.mca_solve(self.handle, self.m, self.n, g_dev, v_in, v_t, v_b,
+                                          opts, ws, check=check)
+        return v_t, v_b, status, stats

@@ -1,0 +1,391 @@
+// kernels.hip -- HBM-bound kernels of the Newton-GMRES hot path (gfx950, FP64).
+//
+// Data layout: every crosspoint array is m x n row-major (index k = i*n + j,
+// the paper's perpendicular natural indexing, Section III-A), and a Krylov
+// vector of the coupled system is the top array followed by the bottom array
+// (length 2mn, the paper's stacking [V_t; V_b] of eq. (F)).
+//
+// Wire stencils are written in branch-current form: the product of a wire
+// matrix (eq. (G), with terminations at both wire ends) with x at node k is
+//   sum over the node's segments of g (x_k - x_neighbour)
+//   + end conductance * x_k at the wire's first / last node,
+// which equals the tridiagonal product exactly in real arithmetic and keeps
+// the residual's rounding proportional to the branch currents.
+#include "mca_internal.h"
+
+namespace mca {
+namespace {
+
+constexpr int TPB = 256;
+constexpr int kMaxReduceBlocks = 1024;
+
+__device__ __forceinline__ double wire_apply(const Wire w, int k, double xk, double xm, double xp)
+{
+    double s = (k > 0) ? w.g * (xk - xm) : w.end0 * xk;
+    s += (k + 1 < w.len) ? w.g * (xk - xp) : w.end1 * xk;
+    return s;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the block in a fixed order; the result is valid in every thread.
+template <int NC>
+__device__ __forceinline__ void block_sum(double (&v)[NC])
+{
+    __shared__ double sh[NC][TPB / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double w = wave_sum(v[c]);
+        if (lane == 0) sh[c][wave] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < TPB / 64; ++w) s += sh[c][w];
+        v[c] = s;
+    }
+    __syncthreads();
+}
+
+// Sum of nb per-block partials, identical in every block (fixed order).
+__device__ __forceinline__ double sum_partials(const double *__restrict__ p, int nb)
+{
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nb; b += TPB) v[0] += p[b];
+    block_sum<1>(v);
+    return v[0];
+}
+
+// --------------------------------------------------------------- residual
+// F_t = G_t V_t + I - Y_t, F_b = G_b V_b - I (eqs. (MNA)/(F)); D = dI/du.
+// partials[2*block + 0] = sum F^2, partials[2*block + 1] = sum D (skipped when null).
+__global__ __launch_bounds__(TPB) void k_residual(
+    int m, int n, Wire top, Wire bot, double v0, int linear,
+    const double *__restrict__ gdev, const double *__restrict__ vin,
+    const double *__restrict__ vt, const double *__restrict__ vb,
+    double *__restrict__ ft, double *__restrict__ fb, double *__restrict__ d,
+    double *__restrict__ partials)
+{
+    const size_t mn = (size_t)m * n;
+    double acc[2] = {0.0, 0.0};
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
+        const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
+        const double t = vt[k], b = vb[k];
+        // top wire i along j; its first node is fed by the drive through g_src (= top.end0)
+        double st = (j > 0) ? top.g * (t - vt[k - 1]) : top.end0 * (t - vin[i]);
+        st += (j + 1 < n) ? top.g * (t - vt[k + 1]) : top.end1 * t;
+        const double sb = wire_apply(bot, i, b, (i > 0) ? vb[k - n] : 0.0,
+                                     (i + 1 < m) ? vb[k + n] : 0.0);
+        const double u = t - b, g = gdev[k];
+        double cur, slope;
+        if (linear) {
+            cur = g * u;
+            slope = g;
+        } else {
+            const double x = u / v0;
+            cur = g * v0 * sinh(x);
+            slope = g * cosh(x);
+        }
+        const double f1 = st + cur, f2 = sb - cur;
+        ft[k] = f1;
+        fb[k] = f2;
+        if (d) d[k] = slope;
+        acc[0] += f1 * f1 + f2 * f2;
+        acc[1] += slope;
+    }
+    if (partials) {   // uniform across the grid
+        block_sum<2>(acc);
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x + 0] = acc[0];
+            partials[2 * blockIdx.x + 1] = acc[1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ p, int nb, int nc,
+                                                double *__restrict__ out)
+{
+    // one block; component c summed in a fixed order
+    for (int c = 0; c < nc; ++c) {
+        double v[1] = {0.0};
+        for (int b = threadIdx.x; b < nb; b += TPB) v[0] += p[(size_t)b * nc + c];
+        block_sum<1>(v);
+        if (threadIdx.x == 0) out[c] = v[0];
+    }
+}
+
+// ---------------------------------------------------------------- Jacobian
+// y_t = G_t x_t + d (x_t - x_b),  y_b = G_b x_b - d (x_t - x_b)     (eq. (J))
+__global__ __launch_bounds__(TPB) void k_jacobian(
+    int m, int n, Wire top, Wire bot, const double *__restrict__ d,
+    const double *__restrict__ xt, const double *__restrict__ xb,
+    double *__restrict__ yt, double *__restrict__ yb)
+{
+    const size_t mn = (size_t)m * n;
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
+        const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
+        const double t = xt[k], b = xb[k];
+        const double st = wire_apply(top, j, t, (j > 0) ? xt[k - 1] : 0.0,
+                                     (j + 1 < n) ? xt[k + 1] : 0.0);
+        const double sb = wire_apply(bot, i, b, (i > 0) ? xb[k - n] : 0.0,
+                                     (i + 1 < m) ? xb[k + n] : 0.0);
+        const double c = d[k] * (t - b);
+        yt[k] = st + c;
+        yb[k] = sb - c;
+    }
+}
+
+// ------------------------------------------------- literal-form stencils
+// With A = G_t + a1 I, B = -a1 I, C = -a2 I, D = G_b + a2 I (eq. (P)),
+// eq. (block) gives z_t = M^{-1} (r_b - D B^{-1} r_t) and z_b = B^{-1} (r_t - A z_t).
+__global__ __launch_bounds__(TPB) void k_precond_pre(
+    int m, int n, Wire bot, double inv_a1, double a2,
+    const double *__restrict__ rt, const double *__restrict__ rb, double *__restrict__ w)
+{
+    const size_t mn = (size_t)m * n;
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
+        const int i = (int)(k / n);
+        const double r = rt[k];
+        const double s = wire_apply(bot, i, r, (i > 0) ? rt[k - n] : 0.0,
+                                    (i + 1 < m) ? rt[k + n] : 0.0);
+        w[k] = rb[k] + (s + a2 * r) * inv_a1;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_precond_post(
+    int m, int n, Wire top, double a1, double inv_a1,
+    const double *__restrict__ zt, const double *__restrict__ rt, double *__restrict__ zb)
+{
+    const size_t mn = (size_t)m * n;
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
+        const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
+        const double z = zt[k];
+        const double s = wire_apply(top, j, z, (j > 0) ? zt[k - 1] : 0.0,
+                                    (j + 1 < n) ? zt[k + 1] : 0.0);
+        zb[k] = (s + a1 * z - rt[k]) * inv_a1;
+    }
+}
+
+// ------------------------------------------------------------------ Krylov
+__global__ __launch_bounds__(TPB) void k_dot_partials(
+    const double *__restrict__ x, const double *__restrict__ y, size_t len,
+    double *__restrict__ partials)
+{
+    double acc[1] = {0.0};
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB)
+        acc[0] += x[k] * y[k];
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+}
+
+// One modified Gram-Schmidt step fused with the next projection:
+//   h = <w, v_prev> (summed from the previous pass's partials); w -= h v_prev;
+//   partial <w, v_next>  (or partial ||w||^2 when v_next is null).
+__global__ __launch_bounds__(TPB) void k_mgs_step(
+    double *__restrict__ w, const double *__restrict__ vprev, const double *__restrict__ vnext,
+    size_t len, const double *__restrict__ pin, int nb, double *__restrict__ pout,
+    double *__restrict__ hout)
+{
+    const double h = sum_partials(pin, nb);
+    if (blockIdx.x == 0 && threadIdx.x == 0) hout[0] = h;
+    double acc[1] = {0.0};
+    if (vnext) {
+        for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB) {
+            const double x = w[k] - h * vprev[k];
+            w[k] = x;
+            acc[0] += x * vnext[k];
+        }
+    } else {
+        for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB) {
+            const double x = w[k] - h * vprev[k];
+            w[k] = x;
+            acc[0] += x * x;
+        }
+    }
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) pout[blockIdx.x] = acc[0];
+}
+
+__global__ __launch_bounds__(TPB) void k_normalize(
+    double *__restrict__ w, size_t len, const double *__restrict__ pin, int nb,
+    double *__restrict__ hout)
+{
+    const double nrm = sqrt(sum_partials(pin, nb));
+    if (blockIdx.x == 0 && threadIdx.x == 0) hout[0] = nrm;
+    if (!(nrm > 0.0)) return;
+    const double inv = 1.0 / nrm;
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB)
+        w[k] *= inv;
+}
+
+__global__ __launch_bounds__(TPB) void k_scale(const double *__restrict__ x, double alpha,
+                                               double *__restrict__ y, size_t len)
+{
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB)
+        y[k] = alpha * x[k];
+}
+
+__global__ __launch_bounds__(TPB) void k_update(
+    const double *__restrict__ Z, size_t zstride, const double *__restrict__ coef, int nvec,
+    size_t len, double *__restrict__ x, int accumulate)
+{
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB) {
+        double s = accumulate ? x[k] : 0.0;
+        for (int v = 0; v < nvec; ++v) s += coef[v] * Z[(size_t)v * zstride + k];
+        x[k] = s;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_axpby(const double *__restrict__ a, double sc,
+                                               const double *__restrict__ b,
+                                               double *__restrict__ out, size_t len)
+{
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB)
+        out[k] = a[k] + sc * b[k];
+}
+
+__global__ __launch_bounds__(TPB) void k_neg_sum(const double *__restrict__ a,
+                                                 const double *__restrict__ b,
+                                                 double *__restrict__ out, size_t len)
+{
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB)
+        out[k] = -(a[k] + b[k]);
+}
+
+__global__ __launch_bounds__(TPB) void k_fill(double *__restrict__ x, double v, size_t len)
+{
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB)
+        x[k] = v;
+}
+
+int elementwise_blocks(size_t len)
+{
+    size_t b = (len + TPB - 1) / TPB;
+    if (b > 8192) b = 8192;
+    return b < 1 ? 1 : (int)b;
+}
+
+}  // namespace
+
+int reduce_blocks(size_t len)
+{
+    size_t b = (len + 4 * TPB - 1) / (4 * TPB);
+    if (b > (size_t)kMaxReduceBlocks) b = kMaxReduceBlocks;
+    return b < 1 ? 1 : (int)b;
+}
+
+hipError_t launch_residual(const mca_plan *P, const double *g_dev, const double *v_in,
+                           const double *vt, const double *vb, double *ft, double *fb,
+                           double *d, double *partials, hipStream_t s)
+{
+    const int m = P->geom.m, n = P->geom.n;
+    const size_t mn = (size_t)m * n;
+    hipLaunchKernelGGL(k_residual, dim3(reduce_blocks(mn)), dim3(TPB), 0, s, m, n, P->top,
+                       P->bot, P->geom.v0, P->geom.device_model == MCA_DEVICE_LINEAR ? 1 : 0,
+                       g_dev, v_in, vt, vb, ft, fb, d, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double *out,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, partials, nblocks, ncomp, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobian(const mca_plan *P, const double *d, const double *xt,
+                           const double *xb, double *yt, double *yb, hipStream_t s)
+{
+    const int m = P->geom.m, n = P->geom.n;
+    hipLaunchKernelGGL(k_jacobian, dim3(elementwise_blocks((size_t)m * n)), dim3(TPB), 0, s, m,
+                       n, P->top, P->bot, d, xt, xb, yt, yb);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_pre(const mca_plan *P, double a1, double a2, const double *rt,
+                              const double *rb, double *w, hipStream_t s)
+{
+    const int m = P->geom.m, n = P->geom.n;
+    hipLaunchKernelGGL(k_precond_pre, dim3(elementwise_blocks((size_t)m * n)), dim3(TPB), 0, s,
+                       m, n, P->bot, 1.0 / a1, a2, rt, rb, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_post(const mca_plan *P, double a1, const double *zt,
+                               const double *rt, double *zb, hipStream_t s)
+{
+    const int m = P->geom.m, n = P->geom.n;
+    hipLaunchKernelGGL(k_precond_post, dim3(elementwise_blocks((size_t)m * n)), dim3(TPB), 0, s,
+                       m, n, P->top, a1, 1.0 / a1, zt, rt, zb);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_partials(const double *x, const double *y, size_t len, double *partials,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot_partials, dim3(reduce_blocks(len)), dim3(TPB), 0, s, x, y, len,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_mgs_step(double *w, const double *v_prev, const double *v_next, size_t len,
+                           const double *partials_in, double *partials_out, double *h_out,
+                           hipStream_t s)
+{
+    const int nb = reduce_blocks(len);
+    hipLaunchKernelGGL(k_mgs_step, dim3(nb), dim3(TPB), 0, s, w, v_prev, v_next, len,
+                       partials_in, nb, partials_out, h_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(double *w, size_t len, const double *partials_in, double *h_out,
+                            hipStream_t s)
+{
+    const int nb = reduce_blocks(len);
+    hipLaunchKernelGGL(k_normalize, dim3(nb), dim3(TPB), 0, s, w, len, partials_in, nb, h_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const double *x, double alpha, double *y, size_t len, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale, dim3(elementwise_blocks(len)), dim3(TPB), 0, s, x, alpha, y, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const double *Z, size_t zstride, const double *coef, int k, size_t len,
+                         double *x, int accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_update, dim3(elementwise_blocks(len)), dim3(TPB), 0, s, Z, zstride,
+                       coef, k, len, x, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(const double *a, double sc, const double *b, double *out, size_t len,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(elementwise_blocks(len)), dim3(TPB), 0, s, a, sc, b, out,
+                       len);
+    return hipGetLastError();
+}
+
+hipError_t launch_neg_sum(const double *a, const double *b, double *out, size_t len,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_neg_sum, dim3(elementwise_blocks(len)), dim3(TPB), 0, s, a, b, out, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *x, double v, size_t len, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(elementwise_blocks(len)), dim3(TPB), 0, s, x, v, len);
+    return hipGetLastError();
+}
+
+}  // namespace mca

@@ -1,0 +1,121 @@
+// mca_internal.h -- shared declarations of the HIP solver library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/mca.h"
+
+namespace mca {
+
+// Coefficients of one uniform wire (Section II, eq. (G)): segment conductance g
+// between neighbours, end0 from the first node and end1 from the last node to
+// their far sides.  Node k of a wire of `len` nodes carries on the diagonal
+// g * (number of neighbouring segments) + end0 [k == 0] + end1 [k == len-1].
+struct Wire {
+    double g, end0, end1;
+    int len;
+};
+
+// Device data of an uploaded plan.
+struct DevPlan {
+    const double *Qm, *QmT;   // m x m: Qm[i*m + p] = entry i of eigenvector p of G_bot
+    const double *Qn, *QnT;   // n x n: Qn[j*n + q] = entry j of eigenvector q of G_top
+    const double *lb, *lt;    // eigenvalues of G_bot (m) and G_top (n), ascending
+    const float *Qm32, *QmT32, *Qn32, *QnT32;           // FP32 copies
+    const uint16_t *QmH, *QmL, *QmTH, *QmTL;            // split-BF16 hi / lo parts
+    const uint16_t *QnH, *QnL, *QnTH, *QnTL;
+};
+
+}  // namespace mca
+
+struct mca_plan {
+    mca_geometry geom;
+    mca::Wire top, bot;
+    std::vector<double> lb, lt;      // host eigenvalues
+    std::vector<double> Qm, Qn;      // host eigenvectors (row-major, columns are vectors)
+    size_t dev_bytes = 0;
+    void *dev_buf = nullptr;         // caller-owned, set by mca_plan_upload
+    mca::DevPlan dev{};
+};
+
+namespace mca {
+
+// Host: eigenpairs of a symmetric tridiagonal matrix (diag a, off b).
+// lam ascending; Q row-major n x n with Q[i*n + k] = entry i of eigenvector k.
+void tridiag_eigen(int n, const double *a, const double *b, double *lam, double *Q);
+
+// Error text of the last failed HIP call on this thread.
+void set_hip_error(const char *what, hipError_t e);
+
+// ---------------------------------------------------------------- kernels
+// All launchers enqueue on `s` and return the launch status.
+
+// Number of per-block partial sums the Krylov reductions of a vector of
+// length len use (fixed per length, so every reduction order is fixed).
+int reduce_blocks(size_t len);
+
+hipError_t launch_residual(const mca_plan *P, const double *g_dev, const double *v_in,
+                           const double *vt, const double *vb, double *ft, double *fb,
+                           double *d, double *partials, hipStream_t s);
+// final sums of partials: out[c] = sum_b partials[b*ncomp + c], c < ncomp
+hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double *out,
+                         hipStream_t s);
+
+hipError_t launch_jacobian(const mca_plan *P, const double *d, const double *xt,
+                           const double *xb, double *yt, double *yb, hipStream_t s);
+
+// w = r_b + ((G_b + a2 I) r_t) / a1            (first step of the literal form)
+hipError_t launch_precond_pre(const mca_plan *P, double a1, double a2, const double *rt,
+                              const double *rb, double *w, hipStream_t s);
+// z_b = ((G_t + a1 I) z_t - r_t) / a1          (last step of the literal form)
+hipError_t launch_precond_post(const mca_plan *P, double a1, const double *zt,
+                               const double *rt, double *zb, hipStream_t s);
+
+// GEMM epilogues
+enum GemmEpi { EPI_STORE = 0, EPI_DIV_MU = 1, EPI_PERMODE = 2 };
+
+// O = L^T R (one or two batches sharing R), FP64 MFMA.
+//   L: K x M row-major (ld = M), R: K x N row-major (ld = N), O: M x N row-major.
+//   EPI_DIV_MU : O[p][q] = acc / (lb[p] lt[q] / a1 + lb[p] + (a2/a1) lt[q])
+//   EPI_PERMODE: (O0, O1) = 2x2 per-mode solve of (acc0, acc1)      (needs 2 batches)
+struct GemmArgs {
+    int M, N, K;
+    const double *L0, *L1;     // L1 may be null (single batch)
+    const double *R;
+    double *O0, *O1;
+    const double *lb, *lt;     // for the epilogues (length M and N)
+    double a1, a2;
+};
+hipError_t launch_gemm_f64(const GemmArgs &a, int epi, hipStream_t s);
+
+// Krylov kernels over vectors of length len (= 2mn).
+// partial dot products x.y -> partials[reduce_blocks(len)]
+hipError_t launch_dot_partials(const double *x, const double *y, size_t len,
+                               double *partials, hipStream_t s);
+// h = sum(partials_in); h_out[0] = h; w -= h * v_prev; partials_out = partial dots (w, v_next),
+// or partial ||w||^2 when v_next == nullptr.
+hipError_t launch_mgs_step(double *w, const double *v_prev, const double *v_next, size_t len,
+                           const double *partials_in, double *partials_out, double *h_out,
+                           hipStream_t s);
+// nrm = sqrt(sum(partials_in)); h_out[0] = nrm; w *= 1/nrm (when nrm > 0)
+hipError_t launch_normalize(double *w, size_t len, const double *partials_in, double *h_out,
+                            hipStream_t s);
+// y = alpha * x
+hipError_t launch_scale(const double *x, double alpha, double *y, size_t len, hipStream_t s);
+// x (+)= sum_i coef[i] * Z[i]  (coef on device, k <= MCA_MAX_RESTART); accumulate: x += ...
+hipError_t launch_update(const double *Z, size_t zstride, const double *coef, int k, size_t len,
+                         double *x, int accumulate, hipStream_t s);
+// out = a + s * b
+hipError_t launch_axpby(const double *a, double sc, const double *b, double *out, size_t len,
+                        hipStream_t s);
+// out = -(a + b)
+hipError_t launch_neg_sum(const double *a, const double *b, double *out, size_t len,
+                          hipStream_t s);
+// fill with a value
+hipError_t launch_fill(double *x, double v, size_t len, hipStream_t s);
+
+}  // namespace mca

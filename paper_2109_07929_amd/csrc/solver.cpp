@@ -1,0 +1,759 @@
+// solver.cpp -- C ABI, plan set-up and the Newton / flexible-GMRES control loop.
+//
+// The control flow is host code; every arithmetic step on crossbar-sized data
+// runs in the HIP kernels of kernels.hip and gemm.hip.  The host reads back a
+// few scalars per iteration (norms and one Hessenberg column) and does the
+// O(restart^2) Givens work of the least-squares problem.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mca_internal.h"
+
+namespace mca {
+
+namespace {
+thread_local std::string g_last_error;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Carves typed sub-buffers out of one caller-owned block (base may be null to
+// only measure the size).
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count)
+    {
+        off = align_up(off);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t size() const { return align_up(off); }
+};
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+mca_status validate_geometry(const mca_geometry *g)
+{
+    if (!g) return MCA_ERR_INVALID_ARG;
+    if (g->m < 1 || g->n < 1 || g->reserved != 0) return MCA_ERR_INVALID_ARG;
+    if ((size_t)g->m * (size_t)g->n > (size_t)1 << 30) return MCA_ERR_INVALID_ARG;
+    if (g->device_model != MCA_DEVICE_SINH && g->device_model != MCA_DEVICE_LINEAR)
+        return MCA_ERR_INVALID_ARG;
+    const double c[] = {g->g_top, g->g_bot, g->g_src, g->g_top_end, g->g_bot_end0, g->g_bot_end1};
+    for (double x : c)
+        if (!finite_nonneg(x)) return MCA_ERR_INVALID_ARG;
+    if (!(g->g_top > 0.0) || !(g->g_bot > 0.0)) return MCA_ERR_INVALID_ARG;
+    if (!(g->g_src + g->g_top_end > 0.0) || !(g->g_bot_end0 + g->g_bot_end1 > 0.0))
+        return MCA_ERR_INVALID_ARG;
+    if (g->device_model == MCA_DEVICE_SINH && !(std::isfinite(g->v0) && g->v0 > 0.0))
+        return MCA_ERR_INVALID_ARG;
+    return MCA_OK;
+}
+
+mca_status validate_options(const mca_options *o)
+{
+    if (!(o->newton_tol >= 0.0) || !(o->gmres_tol > 0.0) || !(o->gmres_tol < 1.0))
+        return MCA_ERR_INVALID_ARG;
+    if (o->restart < 1 || o->restart > MCA_MAX_RESTART) return MCA_ERR_INVALID_ARG;
+    if (o->max_newton < 1 || o->max_newton > MCA_MAX_NEWTON) return MCA_ERR_INVALID_ARG;
+    if (o->max_krylov < 1) return MCA_ERR_INVALID_ARG;
+    if (o->precision != MCA_PREC_FP64 && o->precision != MCA_PREC_FP32 &&
+        o->precision != MCA_PREC_BF16X3)
+        return MCA_ERR_INVALID_ARG;
+    if (o->precond != MCA_PRECOND_LITERAL && o->precond != MCA_PRECOND_PERMODE &&
+        o->precond != MCA_PRECOND_NONE)
+        return MCA_ERR_INVALID_ARG;
+    if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING)) return MCA_ERR_INVALID_ARG;
+    return MCA_OK;
+}
+
+// Wire matrix of eq. (G) with the two end terminations (see mca.h).
+Wire make_wire(int len, double g, double end0, double end1) { return Wire{g, end0, end1, len}; }
+
+void wire_tridiag(const Wire &w, std::vector<double> &diag, std::vector<double> &off)
+{
+    diag.assign(w.len, 0.0);
+    off.assign(w.len > 1 ? w.len - 1 : 0, 0.0);
+    for (int k = 0; k + 1 < w.len; ++k) {
+        diag[k] += w.g;
+        diag[k + 1] += w.g;
+        off[k] = -w.g;
+    }
+    diag[0] += w.end0;
+    diag[w.len - 1] += w.end1;
+}
+
+// Layout of the plan's device block.
+struct PlanLayout {
+    double *Qm, *QmT, *Qn, *QnT, *lb, *lt;
+    size_t bytes;
+};
+
+PlanLayout plan_layout(const mca_plan *P, void *base)
+{
+    const size_t m = P->geom.m, n = P->geom.n;
+    Carver c(base);
+    PlanLayout L;
+    L.Qm = c.take<double>(m * m);
+    L.QmT = c.take<double>(m * m);
+    L.Qn = c.take<double>(n * n);
+    L.QnT = c.take<double>(n * n);
+    L.lb = c.take<double>(m);
+    L.lt = c.take<double>(n);
+    L.bytes = c.size();
+    return L;
+}
+
+// Workspace of the preconditioner: up to four m x n FP64 buffers.
+struct PrecondWs {
+    double *b0t, *b0b, *b1t, *b1b;
+};
+
+PrecondWs precond_layout(const mca_plan *P, Carver &c, int form)
+{
+    const size_t mn = (size_t)P->geom.m * P->geom.n;
+    PrecondWs w{};
+    if (form == MCA_PRECOND_NONE) return w;
+    w.b0t = c.take<double>(mn);
+    w.b1t = c.take<double>(mn);
+    if (form == MCA_PRECOND_PERMODE) {
+        w.b0b = c.take<double>(mn);
+        w.b1b = c.take<double>(mn);
+    }
+    return w;
+}
+
+// Workspace of a solve.
+struct SolveWs {
+    double *V;        // (restart+1) Krylov vectors of length 2mn
+    double *Z;        // restart preconditioned vectors
+    double *X;        // Newton correction
+    double *Vc, *Vn;  // current and trial iterate
+    double *F, *Fn;   // residual at Vc / Vn
+    double *D, *Dn;   // device slopes at Vc / Vn
+    double *tmp;      // J X for restarts
+    double *pa, *pb;  // per-block partial sums (ping-pong)
+    double *H;        // Hessenberg, column-major, ld = restart + 1
+    double *coef;     // least-squares solution y
+    double *scal;     // reduced scalars
+    PrecondWs pw;
+    size_t bytes;
+};
+
+SolveWs solve_layout(const mca_plan *P, const mca_options *o, void *base)
+{
+    const size_t mn = (size_t)P->geom.m * P->geom.n, len = 2 * mn;
+    const size_t R = o->restart;
+    Carver c(base);
+    SolveWs w;
+    w.V = c.take<double>((R + 1) * len);
+    w.Z = c.take<double>(R * len);
+    w.X = c.take<double>(len);
+    w.Vc = c.take<double>(len);
+    w.Vn = c.take<double>(len);
+    w.F = c.take<double>(len);
+    w.Fn = c.take<double>(len);
+    w.D = c.take<double>(mn);
+    w.Dn = c.take<double>(mn);
+    w.tmp = c.take<double>(len);
+    w.pa = c.take<double>(4 * 1024);
+    w.pb = c.take<double>(4 * 1024);
+    w.H = c.take<double>((R + 1) * R);
+    w.coef = c.take<double>(R);
+    w.scal = c.take<double>(8);
+    w.pw = precond_layout(P, c, o->precond);
+    w.bytes = c.size();
+    return w;
+}
+
+// Small pinned host staging area for the scalars read back per iteration.
+double *pinned_scratch()
+{
+    thread_local double *buf = nullptr;
+    if (!buf) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return nullptr;
+        buf = static_cast<double *>(p);
+    }
+    return buf;
+}
+
+#define MCA_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) {                         \
+            set_hip_error(#expr, e_);                   \
+            return MCA_ERR_HIP;                         \
+        }                                               \
+    } while (0)
+
+bool plan_ready(const mca_plan *P) { return P && P->dev_buf != nullptr; }
+
+// GPU time per kernel class, from HIP events recorded around each group of
+// launches; collected after every stream synchronisation of the solve.
+struct Timing {
+    bool on = false;
+    hipEvent_t ev[MCA_NUM_KCLASS][2] = {};
+    int pending[MCA_NUM_KCLASS] = {};
+    double ms[MCA_NUM_KCLASS] = {};
+    int launches[MCA_NUM_KCLASS] = {};
+
+    hipError_t init()
+    {
+        on = true;
+        for (auto &c : ev)
+            for (auto &e : c) {
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+            }
+        return hipSuccess;
+    }
+    ~Timing()
+    {
+        for (auto &c : ev)
+            for (auto &e : c)
+                if (e) (void)hipEventDestroy(e);
+    }
+    hipError_t begin(int c, hipStream_t s) { return on ? hipEventRecord(ev[c][0], s) : hipSuccess; }
+    hipError_t end(int c, hipStream_t s, int nlaunch)
+    {
+        if (!on) return hipSuccess;
+        pending[c] = nlaunch;
+        return hipEventRecord(ev[c][1], s);
+    }
+    hipError_t collect()
+    {
+        if (!on) return hipSuccess;
+        for (int c = 0; c < MCA_NUM_KCLASS; ++c) {
+            if (!pending[c]) continue;
+            float t = 0.f;
+            hipError_t r = hipEventElapsedTime(&t, ev[c][0], ev[c][1]);
+            if (r != hipSuccess) return r;
+            ms[c] += t;
+            launches[c] += pending[c];
+            pending[c] = 0;
+        }
+        return hipSuccess;
+    }
+};
+
+// z = P^{-1} r (eq. (P)) in the chosen evaluation form.
+mca_status precond_run(const mca_plan *P, int form, double a1, double a2, const double *rt,
+                       const double *rb, double *zt, double *zb, const PrecondWs &w,
+                       hipStream_t s, Timing *tm = nullptr)
+{
+    Timing off;
+    if (!tm) tm = &off;
+    const int m = P->geom.m, n = P->geom.n;
+    const size_t mn = (size_t)m * n;
+    const DevPlan &d = P->dev;
+    if (form == MCA_PRECOND_NONE) {
+        MCA_TRY(hipMemcpyAsync(zt, rt, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        MCA_TRY(hipMemcpyAsync(zb, rb, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return MCA_OK;
+    }
+    GemmArgs g{};
+    g.lb = d.lb;
+    g.lt = d.lt;
+    g.a1 = a1;
+    g.a2 = a2;
+    if (form == MCA_PRECOND_LITERAL) {
+        // w = r_b + (G_b + a2 I) r_t / a1
+        MCA_TRY(launch_precond_pre(P, a1, a2, rt, rb, w.b0t, s));
+        // (Q_m^T W)^T = W^T Q_m                      (n x m)
+        MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s));
+        g.M = n; g.N = m; g.K = m; g.L0 = w.b0t; g.L1 = nullptr; g.R = d.Qm; g.O0 = w.b1t;
+        MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
+        // W_hat = Q_m^T W Q_n, then ./ mu             (m x n)
+        g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.R = d.Qn; g.O0 = w.b0t;
+        MCA_TRY(launch_gemm_f64(g, EPI_DIV_MU, s));
+        // (Q_m X_hat)^T                               (n x m)
+        g.M = n; g.N = m; g.K = m; g.L0 = w.b0t; g.R = d.QmT; g.O0 = w.b1t;
+        MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
+        // z_t = Q_m X_hat Q_n^T                       (m x n)
+        g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.R = d.QnT; g.O0 = zt;
+        MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
+        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 4));
+        // z_b = ((G_t + a1 I) z_t - r_t) / a1
+        MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s));
+        return MCA_OK;
+    }
+    // per-mode: transform both layers, solve each mode's 2x2 block, transform back
+    MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s));
+    g.M = n; g.N = m; g.K = m; g.L0 = rt; g.L1 = rb; g.R = d.Qm; g.O0 = w.b1t; g.O1 = w.b1b;
+    MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
+    g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.L1 = w.b1b; g.R = d.Qn; g.O0 = w.b0t; g.O1 = w.b0b;
+    MCA_TRY(launch_gemm_f64(g, EPI_PERMODE, s));
+    g.M = n; g.N = m; g.K = m; g.L0 = w.b0t; g.L1 = w.b0b; g.R = d.QmT; g.O0 = w.b1t; g.O1 = w.b1b;
+    MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
+    g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.L1 = w.b1b; g.R = d.QnT; g.O0 = zt; g.O1 = zb;
+    MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
+    MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 4));
+    return MCA_OK;
+}
+
+struct Givens {
+    double c, s;
+};
+
+// Flexible GMRES(restart) with modified Gram-Schmidt for J X = -F, right
+// preconditioned by P(a, a).  On return X holds the correction.
+mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, double fnorm,
+                  double a, hipStream_t s, Timing *tm, int *its_out, int *restarts_out,
+                  bool *conv_out)
+{
+    const size_t mn = (size_t)P->geom.m * P->geom.n, len = 2 * mn;
+    const int R = o->restart;
+    const size_t ldh = (size_t)R + 1;
+    double *host = pinned_scratch();
+    if (!host) {
+        set_hip_error("hipHostMalloc", hipErrorOutOfMemory);
+        return MCA_ERR_HIP;
+    }
+    std::vector<double> Hc((size_t)(R + 1) * R), gvec(R + 1), y(R);
+    std::vector<Givens> rot(R);
+
+    double beta = fnorm;
+    const double abs_tol = o->gmres_tol * fnorm;
+    int its = 0, restarts = 0;
+    bool converged = false, first = true;
+    // v_0 = -F / ||F||
+    MCA_TRY(launch_scale(w.F, -1.0 / beta, w.V, len, s));
+    for (;;) {
+        std::fill(gvec.begin(), gvec.end(), 0.0);
+        gvec[0] = beta;
+        int k = 0;
+        bool breakdown = false;
+        for (int j = 0; j < R; ++j) {
+            double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
+            double *wv = w.V + (size_t)(j + 1) * len;
+            mca_status st =
+                precond_run(P, o->precond, a, a, vj, vj + mn, zj, zj + mn, w.pw, s, tm);
+            if (st != MCA_OK) return st;
+            MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s));
+            MCA_TRY(launch_jacobian(P, w.D, zj, zj + mn, wv, wv + mn, s));
+            MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1));
+            // modified Gram-Schmidt: h_ij = <w, v_i>, w -= h_ij v_i, i = 0..j
+            double *hcol = w.H + (size_t)j * ldh;
+            MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s));
+            MCA_TRY(launch_dot_partials(wv, w.V, len, w.pa, s));
+            double *pin = w.pa, *pout = w.pb;
+            for (int i = 0; i <= j; ++i) {
+                const double *vnext = (i < j) ? w.V + (size_t)(i + 1) * len : nullptr;
+                MCA_TRY(launch_mgs_step(wv, w.V + (size_t)i * len, vnext, len, pin, pout,
+                                        hcol + i, s));
+                std::swap(pin, pout);
+            }
+            MCA_TRY(launch_normalize(wv, len, pin, hcol + j + 1, s));
+            MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 3));
+            MCA_TRY(hipMemcpyAsync(host, hcol, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+            MCA_TRY(hipStreamSynchronize(s));
+            MCA_TRY(tm->collect());
+            double *h = &Hc[(size_t)j * ldh];
+            for (int i = 0; i <= j + 1; ++i) {
+                h[i] = host[i];
+                if (!std::isfinite(h[i])) return MCA_ERR_NONFINITE;
+            }
+            // apply the previous rotations, then annihilate h[j+1]
+            for (int i = 0; i < j; ++i) {
+                const double t = rot[i].c * h[i] + rot[i].s * h[i + 1];
+                h[i + 1] = -rot[i].s * h[i] + rot[i].c * h[i + 1];
+                h[i] = t;
+            }
+            const double hn = h[j + 1];
+            const double r = std::hypot(h[j], hn);
+            if (r == 0.0) {
+                breakdown = true;
+                k = j;
+                break;
+            }
+            rot[j].c = h[j] / r;
+            rot[j].s = hn / r;
+            h[j] = r;
+            h[j + 1] = 0.0;
+            gvec[j + 1] = -rot[j].s * gvec[j];
+            gvec[j] = rot[j].c * gvec[j];
+            ++its;
+            k = j + 1;
+            if (std::fabs(gvec[j + 1]) <= abs_tol) {
+                converged = true;
+                break;
+            }
+            if (hn == 0.0) {   // exact invariant subspace: the residual above is final
+                breakdown = true;
+                break;
+            }
+            if (its >= o->max_krylov) break;
+        }
+        if (k > 0) {
+            // y = R^{-1} g  (upper triangular, column-major in Hc)
+            for (int i = k - 1; i >= 0; --i) {
+                double t = gvec[i];
+                for (int c2 = i + 1; c2 < k; ++c2) t -= Hc[(size_t)c2 * ldh + i] * y[c2];
+                y[i] = t / Hc[(size_t)i * ldh + i];
+            }
+            for (int i = 0; i < k; ++i) host[i] = y[i];
+            MCA_TRY(hipMemcpyAsync(w.coef, host, k * sizeof(double), hipMemcpyHostToDevice, s));
+            MCA_TRY(launch_update(w.Z, len, w.coef, k, len, w.X, first ? 0 : 1, s));
+            first = false;
+        } else if (first) {
+            MCA_TRY(launch_fill(w.X, 0.0, len, s));
+            first = false;
+        }
+        if (converged || its >= o->max_krylov || breakdown) break;
+        // restart from the true residual  r = -F - J X
+        ++restarts;
+        MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s));
+        MCA_TRY(launch_jacobian(P, w.D, w.X, w.X + mn, w.tmp, w.tmp + mn, s));
+        MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1));
+        MCA_TRY(launch_neg_sum(w.F, w.tmp, w.V, len, s));
+        MCA_TRY(launch_dot_partials(w.V, w.V, len, w.pa, s));
+        MCA_TRY(launch_reduce(w.pa, reduce_blocks(len), 1, w.scal, s));
+        MCA_TRY(hipMemcpyAsync(host, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        MCA_TRY(hipStreamSynchronize(s));
+        MCA_TRY(tm->collect());
+        beta = std::sqrt(host[0]);
+        if (!std::isfinite(beta)) return MCA_ERR_NONFINITE;
+        if (beta <= abs_tol) {
+            converged = true;
+            break;
+        }
+        MCA_TRY(launch_scale(w.V, 1.0 / beta, w.V, len, s));
+    }
+    *its_out = its;
+    *restarts_out = restarts;
+    *conv_out = converged;
+    return MCA_OK;
+}
+
+// Residual at (vt, vb) into F/D, returning ||F|| and sum(D) on the host.
+mca_status residual_norms(const mca_plan *P, const double *g_dev, const double *v_in,
+                          const double *vt, const double *vb, double *F, double *D,
+                          const SolveWs &w, hipStream_t s, Timing *tm, double *fnorm,
+                          double *dsum)
+{
+    const size_t mn = (size_t)P->geom.m * P->geom.n;
+    double *host = pinned_scratch();
+    if (!host) {
+        set_hip_error("hipHostMalloc", hipErrorOutOfMemory);
+        return MCA_ERR_HIP;
+    }
+    MCA_TRY(tm->begin(MCA_KCLASS_RESIDUAL, s));
+    MCA_TRY(launch_residual(P, g_dev, v_in, vt, vb, F, F + mn, D, w.pa, s));
+    MCA_TRY(tm->end(MCA_KCLASS_RESIDUAL, s, 1));
+    MCA_TRY(launch_reduce(w.pa, reduce_blocks(mn), 2, w.scal, s));
+    MCA_TRY(hipMemcpyAsync(host, w.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MCA_TRY(hipStreamSynchronize(s));
+    MCA_TRY(tm->collect());
+    *fnorm = std::sqrt(host[0]);
+    *dsum = host[1];
+    if (!std::isfinite(*fnorm) || !std::isfinite(*dsum)) return MCA_ERR_NONFINITE;
+    return MCA_OK;
+}
+
+}  // namespace
+
+void set_hip_error(const char *what, hipError_t e)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+}
+
+}  // namespace mca
+
+using namespace mca;
+
+extern "C" {
+
+void mca_options_default(mca_options *o)
+{
+    if (!o) return;
+    o->newton_tol = 1e-10;
+    o->gmres_tol = 1e-8;
+    o->restart = 30;
+    o->max_newton = 50;
+    o->max_krylov = 600;
+    o->precision = MCA_PREC_FP64;
+    o->precond = MCA_PRECOND_LITERAL;
+    o->flags = 0;
+}
+
+const char *mca_status_string(mca_status s)
+{
+    switch (s) {
+    case MCA_OK: return "ok";
+    case MCA_ERR_INVALID_ARG: return "invalid argument";
+    case MCA_ERR_NONFINITE: return "non-finite value";
+    case MCA_ERR_WORKSPACE: return "workspace too small or plan not uploaded";
+    case MCA_ERR_NOT_CONVERGED: return "not converged";
+    case MCA_ERR_BREAKDOWN: return "GMRES breakdown";
+    case MCA_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char *mca_last_error(void) { return g_last_error.c_str(); }
+
+mca_status mca_plan_create(const mca_geometry *geom, mca_plan **out)
+{
+    if (!out) return MCA_ERR_INVALID_ARG;
+    *out = nullptr;
+    mca_status st = validate_geometry(geom);
+    if (st != MCA_OK) return st;
+    mca_plan *P = new (std::nothrow) mca_plan();
+    if (!P) return MCA_ERR_INVALID_ARG;
+    P->geom = *geom;
+    P->top = make_wire(geom->n, geom->g_top, geom->g_src, geom->g_top_end);
+    P->bot = make_wire(geom->m, geom->g_bot, geom->g_bot_end0, geom->g_bot_end1);
+    const int m = geom->m, n = geom->n;
+    std::vector<double> diag, off;
+    P->lt.resize(n);
+    P->Qn.resize((size_t)n * n);
+    wire_tridiag(P->top, diag, off);
+    tridiag_eigen(n, diag.data(), off.data(), P->lt.data(), P->Qn.data());
+    P->lb.resize(m);
+    P->Qm.resize((size_t)m * m);
+    wire_tridiag(P->bot, diag, off);
+    tridiag_eigen(m, diag.data(), off.data(), P->lb.data(), P->Qm.data());
+    P->dev_bytes = plan_layout(P, nullptr).bytes;
+    *out = P;
+    return MCA_OK;
+}
+
+void mca_plan_destroy(mca_plan *P) { delete P; }
+
+size_t mca_plan_device_bytes(const mca_plan *P) { return P ? P->dev_bytes : 0; }
+
+mca_status mca_plan_host_eigen(const mca_plan *P, int32_t layer, double *lambda, double *q)
+{
+    if (!P || (layer != 0 && layer != 1)) return MCA_ERR_INVALID_ARG;
+    const std::vector<double> &lam = layer == 0 ? P->lt : P->lb;
+    const std::vector<double> &Q = layer == 0 ? P->Qn : P->Qm;
+    if (lambda) std::memcpy(lambda, lam.data(), lam.size() * sizeof(double));
+    if (q) std::memcpy(q, Q.data(), Q.size() * sizeof(double));
+    return MCA_OK;
+}
+
+mca_status mca_plan_upload(mca_plan *P, void *dev_buf, size_t bytes, void *stream)
+{
+    if (!P || !dev_buf) return MCA_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) return MCA_ERR_INVALID_ARG;
+    if (bytes < P->dev_bytes) return MCA_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t m = P->geom.m, n = P->geom.n;
+    // host image of the whole block (same offsets), then one copy
+    std::vector<char> img(P->dev_bytes);
+    PlanLayout H = plan_layout(P, img.data());
+    for (size_t i = 0; i < m; ++i)
+        for (size_t p = 0; p < m; ++p) {
+            H.Qm[i * m + p] = P->Qm[i * m + p];
+            H.QmT[p * m + i] = P->Qm[i * m + p];
+        }
+    for (size_t j = 0; j < n; ++j)
+        for (size_t q = 0; q < n; ++q) {
+            H.Qn[j * n + q] = P->Qn[j * n + q];
+            H.QnT[q * n + j] = P->Qn[j * n + q];
+        }
+    std::memcpy(H.lb, P->lb.data(), m * sizeof(double));
+    std::memcpy(H.lt, P->lt.data(), n * sizeof(double));
+    MCA_TRY(hipMemcpyAsync(dev_buf, img.data(), P->dev_bytes, hipMemcpyHostToDevice, s));
+    MCA_TRY(hipStreamSynchronize(s));
+    PlanLayout L = plan_layout(P, dev_buf);
+    P->dev_buf = dev_buf;
+    P->dev = DevPlan{};
+    P->dev.Qm = L.Qm;
+    P->dev.QmT = L.QmT;
+    P->dev.Qn = L.Qn;
+    P->dev.QnT = L.QnT;
+    P->dev.lb = L.lb;
+    P->dev.lt = L.lt;
+    return MCA_OK;
+}
+
+size_t mca_workspace_bytes(const mca_plan *P, const mca_options *opts)
+{
+    if (!P) return 0;
+    mca_options o;
+    if (opts) o = *opts;
+    else mca_options_default(&o);
+    if (validate_options(&o) != MCA_OK) return 0;
+    return solve_layout(P, &o, nullptr).bytes;
+}
+
+size_t mca_precond_workspace_bytes(const mca_plan *P, int32_t form, int32_t precision)
+{
+    if (!P) return 0;
+    (void)precision;
+    Carver c(nullptr);
+    precond_layout(P, c, form);
+    return c.size() > 0 ? c.size() : kAlign;
+}
+
+mca_status mca_residual(const mca_plan *P, const double *g_dev, const double *v_in,
+                        const double *v_t, const double *v_b, double *f_t, double *f_b,
+                        double *d, void *stream)
+{
+    if (!P || !g_dev || !v_in || !v_t || !v_b || !f_t || !f_b) return MCA_ERR_INVALID_ARG;
+    if (!plan_ready(P)) return MCA_ERR_WORKSPACE;
+    MCA_TRY(launch_residual(P, g_dev, v_in, v_t, v_b, f_t, f_b, d, nullptr,
+                            static_cast<hipStream_t>(stream)));
+    return MCA_OK;
+}
+
+mca_status mca_jacobian_apply(const mca_plan *P, const double *d, const double *x_t,
+                              const double *x_b, double *y_t, double *y_b, void *stream)
+{
+    if (!P || !d || !x_t || !x_b || !y_t || !y_b) return MCA_ERR_INVALID_ARG;
+    if (!plan_ready(P)) return MCA_ERR_WORKSPACE;
+    MCA_TRY(launch_jacobian(P, d, x_t, x_b, y_t, y_b, static_cast<hipStream_t>(stream)));
+    return MCA_OK;
+}
+
+mca_status mca_precond_apply(const mca_plan *P, int32_t form, int32_t precision, double a1,
+                             double a2, const double *r_t, const double *r_b, double *z_t,
+                             double *z_b, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!P || !r_t || !r_b || !z_t || !z_b) return MCA_ERR_INVALID_ARG;
+    if (form != MCA_PRECOND_LITERAL && form != MCA_PRECOND_PERMODE && form != MCA_PRECOND_NONE)
+        return MCA_ERR_INVALID_ARG;
+    if (precision != MCA_PREC_FP64) return MCA_ERR_INVALID_ARG;
+    if (!(std::isfinite(a1) && a1 > 0.0 && std::isfinite(a2) && a2 > 0.0))
+        return MCA_ERR_INVALID_ARG;
+    if (!plan_ready(P)) return MCA_ERR_WORKSPACE;
+    if (form != MCA_PRECOND_NONE && (!ws || ws_bytes < mca_precond_workspace_bytes(P, form, precision)))
+        return MCA_ERR_WORKSPACE;
+    Carver c(ws);
+    PrecondWs w = precond_layout(P, c, form);
+    return precond_run(P, form, a1, a2, r_t, r_b, z_t, z_b, w, static_cast<hipStream_t>(stream));
+}
+
+mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in, double *v_t,
+                     double *v_b, const mca_options *opts, void *ws, size_t ws_bytes,
+                     mca_stats *stats, void *stream)
+{
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (!P || !g_dev || !v_in || !v_t || !v_b) return MCA_ERR_INVALID_ARG;
+    mca_options o;
+    if (opts) o = *opts;
+    else mca_options_default(&o);
+    mca_status st = validate_options(&o);
+    if (st != MCA_OK) return st;
+    if (o.precision != MCA_PREC_FP64) return MCA_ERR_INVALID_ARG;
+    if (!plan_ready(P)) return MCA_ERR_WORKSPACE;
+    SolveWs w = solve_layout(P, &o, ws);
+    if (!ws || ws_bytes < w.bytes) return MCA_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t mn = (size_t)P->geom.m * P->geom.n, len = 2 * mn;
+    double *host = pinned_scratch();
+    if (!host) {
+        set_hip_error("hipHostMalloc", hipErrorOutOfMemory);
+        return MCA_ERR_HIP;
+    }
+
+    // ||Y|| = g_src ||v_in||
+    MCA_TRY(launch_dot_partials(v_in, v_in, P->geom.m, w.pa, s));
+    MCA_TRY(launch_reduce(w.pa, reduce_blocks(P->geom.m), 1, w.scal, s));
+    MCA_TRY(hipMemcpyAsync(host, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    MCA_TRY(hipStreamSynchronize(s));
+    const double ynorm = P->geom.g_src * std::sqrt(host[0]);
+    if (!std::isfinite(ynorm)) return MCA_ERR_NONFINITE;
+    if (ynorm == 0.0) {
+        // no drive: V = 0 solves F = 0 exactly
+        MCA_TRY(launch_fill(v_t, 0.0, mn, s));
+        MCA_TRY(launch_fill(v_b, 0.0, mn, s));
+        MCA_TRY(hipStreamSynchronize(s));
+        return MCA_OK;
+    }
+    double *Vc = w.Vc, *Vn = w.Vn, *F = w.F, *Fn = w.Fn, *D = w.D, *Dn = w.Dn;
+    if (o.flags & MCA_FLAG_INITIAL_GUESS) {
+        MCA_TRY(hipMemcpyAsync(Vc, v_t, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        MCA_TRY(hipMemcpyAsync(Vc + mn, v_b, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+        MCA_TRY(launch_fill(Vc, 0.0, len, s));
+    }
+    Timing tm;
+    if (o.flags & MCA_FLAG_TIMING) MCA_TRY(tm.init());
+    double fnorm = 0.0, dsum = 0.0;
+    SolveWs wk = w;
+    st = residual_norms(P, g_dev, v_in, Vc, Vc + mn, F, D, wk, s, &tm, &fnorm, &dsum);
+    if (st == MCA_ERR_HIP) return st;
+
+    mca_status result = (st == MCA_OK) ? MCA_ERR_NOT_CONVERGED : st;
+    int k = 0, total_its = 0, backtracks = 0, restarts = 0;
+    double a = 0.0;
+    for (; st == MCA_OK; ++k) {
+        if (stats) stats->residual_history[k] = fnorm / ynorm;
+        if (fnorm <= o.newton_tol * ynorm) {
+            result = MCA_OK;
+            break;
+        }
+        if (k >= o.max_newton) break;
+        a = dsum / (double)mn;   // a1 = a2 = mean device slope (Section III-A)
+        wk.F = F;
+        wk.D = D;
+        int its = 0, rs = 0;
+        bool conv = false;
+        st = fgmres(P, &o, wk, fnorm, a, s, &tm, &its, &rs, &conv);
+        if (st != MCA_OK) {
+            result = st;
+            break;
+        }
+        total_its += its;
+        restarts += rs;
+        if (stats) stats->krylov_history[k] = its;
+        // damped update: halve s while ||F(V + s X)|| > (1 - 1e-4 s) ||F(V)||
+        double step = 1.0, fn_new = 0.0, ds_new = 0.0;
+        int halvings = 0;
+        for (;;) {
+            MCA_TRY(launch_axpby(Vc, step, w.X, Vn, len, s));
+            st = residual_norms(P, g_dev, v_in, Vn, Vn + mn, Fn, Dn, wk, s, &tm, &fn_new,
+                                &ds_new);
+            if (st != MCA_OK && st != MCA_ERR_NONFINITE) return st;
+            if (st == MCA_OK && fn_new <= (1.0 - 1e-4 * step) * fnorm) break;
+            if (halvings >= 30) break;
+            step *= 0.5;
+            ++halvings;
+        }
+        backtracks += halvings;
+        if (!(std::isfinite(fn_new) && fn_new < fnorm)) {
+            // no decrease: the rounding floor (accepted below 1e-12 ||Y||) or a failure
+            result = (fnorm <= 1e-12 * ynorm) ? MCA_OK : MCA_ERR_NOT_CONVERGED;
+            break;
+        }
+        std::swap(Vc, Vn);
+        std::swap(F, Fn);
+        std::swap(D, Dn);
+        fnorm = fn_new;
+        dsum = ds_new;
+    }
+    MCA_TRY(hipMemcpyAsync(v_t, Vc, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    MCA_TRY(hipMemcpyAsync(v_b, Vc + mn, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    MCA_TRY(hipStreamSynchronize(s));
+    if (stats) {
+        stats->newton_iters = k;
+        stats->krylov_iters = total_its;
+        stats->backtracks = backtracks;
+        stats->restarts = restarts;
+        stats->rel_residual = fnorm / ynorm;
+        stats->a_last = a;
+        for (int c = 0; c < MCA_NUM_KCLASS; ++c) {
+            stats->kernel_ms[c] = tm.ms[c];
+            stats->kernel_launches[c] = tm.launches[c];
+        }
+    }
+    return result;
+}
+
+}  // extern "C"

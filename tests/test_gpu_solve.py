@@ -1,0 +1,178 @@
+"""Parity of mca_solve (Newton + preconditioned flexible GMRES on the GPU) with
+the CPU oracle, plus the solver's edge cases and failure paths.
+
+The bar (FP64): the GPU voltages match the oracle's steady state to 1e-8
+relative error, max over both layers of |V_gpu - V_ref| / max |V_ref|.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2109_07929_amd import Plan, synth
+from paper_2109_07929_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_err(gt, gb, rt, rb):
+    scale = max(np.abs(rt).max(), np.abs(rb).max())
+    return max(np.abs(gt - rt).max(), np.abs(gb - rb).max()) / scale
+
+
+def gpu_solve(cb, **opt):
+    plan = Plan(cb.geom)
+    o = B.options(**opt)
+    vt, vb, status, stats = plan.solve(dev(cb.g_dev), dev(cb.v_in), o, check=False)
+    return host(vt), host(vb), status, stats
+
+
+@pytest.mark.parametrize("form", [B.MCA_PRECOND_LITERAL, B.MCA_PRECOND_PERMODE])
+def test_solve_32x32_seed0(form):
+    """The 32 x 32 standard crossbar (2048 unknowns), Newton tol 1e-10, GMRES(30) tol 1e-8."""
+    say(f"solve 32x32 seed0 form={form}")
+    cb = synth.crossbar(32, 32, seed=0)
+    vt, vb, status, st = gpu_solve(cb, precond=form)
+    assert status == B.MCA_OK
+    rt, rb, k, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="band")
+    err = rel_err(vt, vb, rt, rb)
+    say(f"  newton {st.newton_iters} krylov {list(st.krylov_history[:st.newton_iters])} "
+        f"relres {st.rel_residual:.2e} err {err:.2e}")
+    assert err <= TOL
+    assert st.rel_residual <= 1e-10
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "oracle_32x32_seed0.json")))
+    for i, j, t, b in ref["samples"]:
+        assert abs(vt[i, j] - t) <= TOL * ref["max_vt"]
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 9), (9, 1), (5, 3), (17, 33), (64, 48), (70, 130)])
+@pytest.mark.parametrize("form", [B.MCA_PRECOND_LITERAL, B.MCA_PRECOND_PERMODE])
+def test_solve_shapes(m, n, form):
+    say(f"solve {m}x{n} form={form}")
+    cb = synth.crossbar(m, n, seed=100 + m + n)
+    vt, vb, status, st = gpu_solve(cb, precond=form)
+    assert status == B.MCA_OK
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in)
+    err = rel_err(vt, vb, rt, rb)
+    say(f"  newton {st.newton_iters} krylov {st.krylov_iters} err {err:.2e}")
+    assert err <= TOL
+
+
+def test_solve_1024_seed0():
+    """The headline 1024 x 1024 crossbar (~2.1M unknowns) in the benchmark's
+    configuration, against the oracle's Newton-CG steady state."""
+    say("solve 1024x1024 seed0 (oracle B on the host takes ~10 s)")
+    cb = synth.crossbar(1024, 1024, seed=0)
+    vt, vb, status, st = gpu_solve(cb)
+    assert status == B.MCA_OK
+    say(f"  newton {st.newton_iters} krylov {list(st.krylov_history[:st.newton_iters])} "
+        f"relres {st.rel_residual:.2e}")
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="cg")
+    err = rel_err(vt, vb, rt, rb)
+    say(f"  err vs oracle {err:.2e}")
+    assert err <= TOL
+    # Kirchhoff: source current in = termination currents out
+    g = cb.geom
+    i_in = np.sum(g.g_src * (cb.v_in - vt[:, 0]))
+    i_out = np.sum(g.g_top_end * vt[:, -1]) + np.sum(g.g_bot_end0 * vb[0] + g.g_bot_end1 * vb[-1])
+    assert abs(i_in - i_out) <= 1e-9 * abs(i_in)
+
+
+def test_exactness_uniform_linear_devices():
+    """Uniform linear devices make P(a, a) = J: flexible GMRES needs one iteration
+    and Newton one step (the residual is affine)."""
+    for form, (m, n), a in [(B.MCA_PRECOND_PERMODE, (96, 160), 3e-5),
+                            (B.MCA_PRECOND_LITERAL, (16, 24), 3e-5),
+                            (B.MCA_PRECOND_PERMODE, (512, 512), 1e-5)]:
+        say(f"exactness {m}x{n} form={form} a={a}")
+        cb = synth.uniform_crossbar(m, n, a, seed=3, device=synth.DEVICE_LINEAR)
+        vt, vb, status, st = gpu_solve(cb, precond=form)
+        assert status == B.MCA_OK
+        say(f"  newton {st.newton_iters} krylov {list(st.krylov_history[:st.newton_iters])}")
+        assert st.newton_iters == 1 and st.krylov_history[0] == 1
+
+
+def test_sinh_first_newton_step_is_exact_for_uniform_devices():
+    """At V = 0 every sinh device has slope g, so with uniform g the first
+    Newton system is J = P(g, g) and GMRES converges in one iteration."""
+    cb = synth.uniform_crossbar(40, 56, 2e-5, seed=4)
+    vt, vb, status, st = gpu_solve(cb, precond=B.MCA_PRECOND_PERMODE)
+    assert status == B.MCA_OK and st.krylov_history[0] == 1
+
+
+def test_zero_drive_and_odd_symmetry():
+    m, n = 24, 20
+    cb = synth.crossbar(m, n, seed=9)
+    plan = Plan(cb.geom)
+    g = dev(cb.g_dev)
+    z_t, z_b, status, st = plan.solve(g, dev(np.zeros(m)))
+    assert status == B.MCA_OK and not host(z_t).any() and not host(z_b).any()
+    p_t, p_b, _, _ = plan.solve(g, dev(cb.v_in))
+    n_t, n_b, _, _ = plan.solve(g, dev(-cb.v_in))
+    assert rel_err(host(n_t), host(n_b), -host(p_t), -host(p_b)) <= 1e-12
+
+
+def test_initial_guess_at_solution_takes_no_step():
+    cb = synth.crossbar(30, 40, seed=11)
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in)
+    plan = Plan(cb.geom)
+    vt, vb, status, st = plan.solve(dev(cb.g_dev), dev(cb.v_in), guess=(dev(rt), dev(rb)))
+    assert status == B.MCA_OK and st.newton_iters == 0 and st.krylov_iters == 0
+    assert rel_err(host(vt), host(vb), rt, rb) <= 1e-14
+
+
+def test_unpreconditioned_gmres_same_answer_more_iterations():
+    cb = synth.crossbar(12, 12, seed=12)
+    a_t, a_b, s1, st1 = gpu_solve(cb)
+    b_t, b_b, s2, st2 = gpu_solve(cb, precond=B.MCA_PRECOND_NONE, max_krylov=5000)
+    assert s1 == B.MCA_OK and s2 == B.MCA_OK
+    assert st2.krylov_iters > st1.krylov_iters
+    assert rel_err(b_t, b_b, a_t, a_b) <= TOL
+
+
+def test_not_converged_keeps_iterate_and_stats():
+    cb = synth.crossbar(32, 32, seed=0)
+    vt, vb, status, st = gpu_solve(cb, max_newton=1)
+    assert status == B.MCA_ERR_NOT_CONVERGED
+    assert st.newton_iters == 1 and st.krylov_iters >= 1
+    assert 0 < st.rel_residual < 1e-2 and np.abs(vt).max() > 0.1
+
+
+def test_nonfinite_input_reported():
+    cb = synth.crossbar(16, 16, seed=1)
+    g = cb.g_dev.copy()
+    g[3, 4] = np.nan
+    plan = Plan(cb.geom)
+    _, _, status, _ = plan.solve(dev(g), dev(cb.v_in), check=False)
+    assert status == B.MCA_ERR_NONFINITE
+
+
+def test_workspace_too_small_rejected():
+    cb = synth.crossbar(16, 16, seed=1)
+    plan = Plan(cb.geom)
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    vt = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    vb = torch.zeros_like(vt)
+    status, _ = B.mca_solve(plan.handle, 16, 16, dev(cb.g_dev), dev(cb.v_in), vt, vb,
+                            B.options(), small, check=False)
+    assert status == B.MCA_ERR_WORKSPACE

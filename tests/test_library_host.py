@@ -1,0 +1,132 @@
+"""Host-side checks of libmca.so that need no GPU.
+
+* the library loads and exports every entry point include/mca.h declares;
+* geometry and option validation;
+* the plan's host eigen-decomposition of the wire matrices (eq. (G) with
+  terminations), pinned by the DST-I closed form of the paper's uniform G,
+  by orthogonality, and by G Q = Q diag(lambda) against numpy's assembly.
+"""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2109_07929_amd import binding as B
+from paper_2109_07929_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_header_symbols_are_exported():
+    header = open(os.path.join(ROOT, "include", "mca.h")).read()
+    declared = set(re.findall(r"\b(mca_[a-z_]+)\s*\(", header))
+    assert declared == set(B.ABI_SYMBOLS)
+    lib = B.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    assert B.status_string(B.MCA_OK) == "ok"
+    assert "converged" in B.status_string(B.MCA_ERR_NOT_CONVERGED)
+
+
+def test_options_default():
+    o = B.options()
+    assert o.restart == 30 and o.gmres_tol == 1e-8 and o.newton_tol == 1e-10
+    assert o.precision == B.MCA_PREC_FP64 and o.precond == B.MCA_PRECOND_LITERAL
+
+
+@pytest.mark.parametrize("bad", [
+    dict(m=0), dict(n=0), dict(g_top=0.0), dict(g_bot=-1.0), dict(g_src=float("nan")),
+    dict(g_src=0.0, g_top_end=0.0), dict(g_bot_end0=0.0, g_bot_end1=0.0), dict(v0=0.0),
+    dict(device=7),
+])
+def test_invalid_geometry_rejected(bad):
+    kw = dict(m=4, n=5)
+    kw.update(bad)
+    g = B.geometry(**kw)
+    with pytest.raises(B.MCAError) as e:
+        B.mca_plan_create(g)
+    assert e.value.status == B.MCA_ERR_INVALID_ARG
+
+
+def test_linear_device_needs_no_v0():
+    P = B.mca_plan_create(B.geometry(3, 3, v0=0.0, device=B.MCA_DEVICE_LINEAR))
+    B.mca_plan_destroy(P)
+
+
+def test_workspace_bytes_reject_bad_options():
+    P = B.mca_plan_create(B.geometry(8, 8))
+    try:
+        assert B.mca_workspace_bytes(P, B.options(restart=0)) == 0
+        assert B.mca_workspace_bytes(P, B.options(restart=65)) == 0
+        ok = B.mca_workspace_bytes(P, B.options())
+        assert ok > 31 * 2 * 64 * 8
+        assert B.mca_workspace_bytes(P, B.options(restart=10)) < ok
+    finally:
+        B.mca_plan_destroy(P)
+
+
+def _tri(length, g, e0, e1):
+    T = np.zeros((length, length))
+    for k in range(length - 1):
+        T[k, k] += g
+        T[k + 1, k + 1] += g
+        T[k, k + 1] = T[k + 1, k] = -g
+    T[0, 0] += e0
+    T[-1, -1] += e1
+    return T
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 31, 64, 257])
+def test_eigen_matches_dst1_closed_form(n):
+    """Both ends tied through g: G is eq. (G), lambda_k = 2g(1 - cos(k pi/(n+1))),
+    eigenvectors sqrt(2/(n+1)) sin(j k pi/(n+1)) (the DST-I basis)."""
+    g = 0.7
+    P = B.mca_plan_create(B.geometry(2, n, g_top=g, g_src=g, g_top_end=g))
+    try:
+        lam, Q = B.mca_plan_host_eigen(P, 0, n)
+    finally:
+        B.mca_plan_destroy(P)
+    k = np.arange(1, n + 1)
+    ref = 2 * g * (1 - np.cos(k * np.pi / (n + 1)))
+    np.testing.assert_allclose(lam, ref, rtol=0, atol=4e-15 * 4 * g)
+    j = np.arange(1, n + 1)[:, None]
+    S = np.sqrt(2.0 / (n + 1)) * np.sin(j * k[None, :] * np.pi / (n + 1))
+    # equal up to the sign of each column
+    signs = np.sign(np.sum(S * Q, axis=0))
+    np.testing.assert_allclose(Q * signs, S, rtol=0, atol=2e-13)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (33, 17), (128, 96)])
+def test_eigen_of_terminated_wires(m, n):
+    geo = synth.Geometry(m, n)
+    P = B.mca_plan_create(B.geometry_from(geo))
+    try:
+        for layer, L, (g, e0, e1) in ((0, n, (geo.g_top, geo.g_src, geo.g_top_end)),
+                                      (1, m, (geo.g_bot, geo.g_bot_end0, geo.g_bot_end1))):
+            lam, Q = B.mca_plan_host_eigen(P, layer, L)
+            T = _tri(L, g, e0, e1)
+            assert np.all(np.diff(lam) > 0)
+            np.testing.assert_allclose(Q.T @ Q, np.eye(L), rtol=0, atol=1e-13)
+            np.testing.assert_allclose(T @ Q, Q * lam, rtol=0, atol=1e-14)
+            np.testing.assert_allclose(lam, np.linalg.eigvalsh(T), rtol=0, atol=4e-15)
+    finally:
+        B.mca_plan_destroy(P)
+
+
+@pytest.mark.slow
+def test_eigen_1024_orthogonal():
+    geo = synth.Geometry(1024, 1024)
+    P = B.mca_plan_create(B.geometry_from(geo))
+    try:
+        lam, Q = B.mca_plan_host_eigen(P, 0, 1024)
+    finally:
+        B.mca_plan_destroy(P)
+    T = _tri(1024, geo.g_top, geo.g_src, geo.g_top_end)
+    assert np.abs(Q.T @ Q - np.eye(1024)).max() < 2e-14
+    assert np.abs(T @ Q - Q * lam).max() < 1e-14
