@@ -36,6 +36,10 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-timing", action="store_true",
                    help="do not time kernel classes with HIP events (no roofline object)")
+    p.add_argument("--copy-calib", action="store_true",
+                   help="after the timed solves, copy a 256 MiB float64 array device-to-device "
+                        "three times: a kernel of known traffic that calibrates the "
+                        "FETCH_SIZE / WRITE_SIZE counters")
     return p.parse_args()
 
 
@@ -153,6 +157,13 @@ def main():
         "roofline": roofline,
         "kernel_breakdown": breakdown,
     }
+    if args.copy_calib:
+        src = torch.rand(32 << 20, dtype=torch.float64, device=dev)   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = src.numel() * 8
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cb)

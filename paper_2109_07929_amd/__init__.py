@@ -40,7 +40,10 @@ class Plan:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
-            binding.mca_plan_destroy(h)
+            try:
+                binding.mca_plan_destroy(h)
+            except Exception:   # interpreter shutdown: the library may be gone
+                pass
             self.handle = None
 
     def _zeros(self):

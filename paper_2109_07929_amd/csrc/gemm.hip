@@ -15,9 +15,10 @@
 // over the rows of that transposed array, so both operands are always read
 // along contiguous rows and the output is written along contiguous rows.
 //
-// Tiling: 64 x 64 output tile per 256-thread workgroup, four waves of 32 x 32,
-// each wave a 2 x 2 grid of v_mfma_f64_16x16x4 accumulators; K is staged
-// through LDS in double-buffered 16-deep slices.  A second batch (the bottom
+// Tiling: 64 x 64 output tile per 512-thread workgroup, eight waves of 32 x 16
+// (two waves per SIMD), each wave a 2 x 1 grid of v_mfma_f64_16x16x4
+// accumulators; K is staged through LDS in double-buffered 32-deep slices
+// with two slices of global loads in flight.  A second batch (the bottom
 // layer) may share the same R tile: the per-mode 2x2 solve of the block
 // formula (eq. (block)) then runs in the epilogue on both accumulators.
 #include "mca_internal.h"
@@ -27,94 +28,202 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
-constexpr int GTPB = 256;
+constexpr int BM = 64, BN = 64, PAD = 2;
+constexpr int kXcds = 8;      // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kGroupM = 4;    // tile rows per group of the tile order
 
-template <int NB, int EPI>
-__global__ __launch_bounds__(GTPB) void k_gemm_tn_f64(GemmArgs a)
+// Tile of workgroup `bid`.  Consecutive workgroup ids land on different XCDs
+// (each with its own L2), so ids are first regrouped so that every XCD owns a
+// contiguous run of tile ids, and runs are ordered in groups of kGroupM tile
+// rows: the 32 tiles one XCD holds at a time then share 4 row panels of L and
+// 8 column panels of R instead of 16 + 2.
+__device__ __forceinline__ void tile_of(int bid, int nwg, int tiles_m, int tiles_n, int &tm,
+                                        int &tn)
 {
+    int t = bid;
+    if (nwg % kXcds == 0) t = (bid % kXcds) * (nwg / kXcds) + bid / kXcds;
+    const int per_group = kGroupM * tiles_n;
+    const int g = t / per_group;
+    const int first = g * kGroupM;
+    const int gsize = min(tiles_m - first, kGroupM);
+    const int r = t - g * per_group;
+    tm = first + r % gsize;
+    tn = r / gsize;
+}
+
+// One K slice of L (NB batches) and R in registers: rows lr + RP h of the
+// slice (RP = threads / 16 rows per pass), 4 consecutive columns each.
+template <int NB, int H>
+struct Stage {
+    double2 l[NB][H][2];
+    double2 r[H][2];
+};
+
+// WAVES = 4: 2 x 2 waves of 32 x 32 (2 x 2 MFMA tiles each), one wave per SIMD.
+// WAVES = 8: 2 x 4 waves of 32 x 16 (2 x 1 MFMA tiles each), two waves per
+// SIMD, so that one wave's LDS reads overlap the other's MFMAs.
+// UPFRONT: read every MFMA fragment of a K slice from LDS before its MFMAs.
+template <int NB, int EPI, int BK, int WAVES, bool UPFRONT>
+__global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
+{
+    constexpr int NT = 64 * WAVES;
+    constexpr int RP = NT / 16;          // slice rows staged per pass
+    constexpr int H = BK / RP;           // passes per slice
+    constexpr int WJ = (WAVES == 4) ? 2 : 1;    // 16-column MFMA tiles per wave
+    constexpr int WCOLS = 16 * WJ;
+    static_assert(H >= 1 && BK % RP == 0, "slice depth");
     __shared__ double Ls[2][NB][BK][BM + PAD];
     __shared__ double Rs[2][BK][BN + PAD];
+    if (a.skip && *a.skip) return;   // uniform: a converged GMRES cycle
 
     const int M = a.M, N = a.N, K = a.K;
-    const int tiles_n = (N + BN - 1) / BN;
-    const int tile = blockIdx.x;
-    const int m0 = (tile / tiles_n) * BM, n0 = (tile % tiles_n) * BN;
+    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    int tm, tn;
+    tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-
+    const int wm = (wave / (BN / WCOLS)) * 32, wn = (wave % (BN / WCOLS)) * WCOLS;
     const double *Lb[2] = {a.L0, a.L1};
 
-    // global -> register staging: row kk of the K slice, 4 consecutive columns
-    const int lk = tid >> 4, lc = (tid & 15) * 4;
-    double lreg[NB][4], rreg[4];
+    // Interior tiles with 16-byte aligned rows (a.vec) use unconditional
+    // 16-byte loads; edge tiles clamp every address into the array and zero
+    // the out-of-range values, so no load is ever out of bounds.
+    const int lr = tid >> 4, lc = (tid & 15) * 4;
+    const bool inside = a.vec && (m0 + BM <= M) && (n0 + BN <= N);
 
-    auto load = [&](int k0) {
-        const int gk = k0 + lk;
-        const bool krow = gk < K;
+    auto load = [&](Stage<NB, H> &st, int k0) {
+        if (inside && k0 + BK <= K) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const double *src = Lb[b] + (size_t)gk * M;
+            for (int h = 0; h < H; ++h) {
+                const size_t gk = (size_t)(k0 + lr + RP * h);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gm = m0 + lc + e;
-                lreg[b][e] = (krow && gm < M) ? src[gm] : 0.0;
+                for (int b = 0; b < NB; ++b) {
+                    const double2 *p = reinterpret_cast<const double2 *>(Lb[b] + gk * M + m0 + lc);
+                    st.l[b][h][0] = p[0];
+                    st.l[b][h][1] = p[1];
+                }
+                const double2 *q = reinterpret_cast<const double2 *>(a.R + gk * N + n0 + lc);
+                st.r[h][0] = q[0];
+                st.r[h][1] = q[1];
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int gk = k0 + lr + RP * h;
+                const bool krow = gk < K;
+                const size_t kc = (size_t)min(gk, K - 1);
+                double v[4];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int gm = m0 + lc + e;
+                        const double x = Lb[b][kc * M + min(gm, M - 1)];
+                        v[e] = (krow && gm < M) ? x : 0.0;
+                    }
+                    st.l[b][h][0] = double2{v[0], v[1]};
+                    st.l[b][h][1] = double2{v[2], v[3]};
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int gn = n0 + lc + e;
+                    const double x = a.R[kc * N + min(gn, N - 1)];
+                    v[e] = (krow && gn < N) ? x : 0.0;
+                }
+                st.r[h][0] = double2{v[0], v[1]};
+                st.r[h][1] = double2{v[2], v[3]};
             }
         }
-        const double *rsrc = a.R + (size_t)gk * N;
+    };
+    auto stash = [&](const Stage<NB, H> &st, int buf) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int gn = n0 + lc + e;
-            rreg[e] = (krow && gn < N) ? rsrc[gn] : 0.0;
+        for (int h = 0; h < H; ++h) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                double2 *d = reinterpret_cast<double2 *>(&Ls[buf][b][lr + RP * h][lc]);
+                d[0] = st.l[b][h][0];
+                d[1] = st.l[b][h][1];
+            }
+            double2 *d = reinterpret_cast<double2 *>(&Rs[buf][lr + RP * h][lc]);
+            d[0] = st.r[h][0];
+            d[1] = st.r[h][1];
         }
     };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) Ls[buf][b][lk][lc + e] = lreg[b][e];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) Rs[buf][lk][lc + e] = rreg[e];
-    };
 
-    d4 acc[NB][2][2];
+    d4 acc[NB][2][WJ];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[b][i][j] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int j = 0; j < WJ; ++j) acc[b][i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-    const int nk = (K + BK - 1) / BK;
-    load(0);
-    stash(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) load((kt + 1) * BK);
+    // MFMA operands: A (16 x 4) lane l holds row l%16, k l/16; B (4 x 16) lane l
+    // holds k l/16, column l%16.
+    constexpr int NS = UPFRONT ? BK / 4 : 2;
+    double af[NS][NB][2], bf[NS][WJ];
+    auto frag = [&](int buf, int k4, int slot) {
+        const int kr = k4 * 4 + (lane >> 4);
 #pragma unroll
-        for (int k4 = 0; k4 < BK / 4; ++k4) {
-            const int kr = k4 * 4 + (lane >> 4);
-            double af[NB][2], bf[2];
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int b = 0; b < NB; ++b) af[slot][b][i] = Ls[buf][b][kr][wm + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) af[b][i] = Ls[buf][b][kr][wm + i * 16 + (lane & 15)];
-                bf[i] = Rs[buf][kr][wn + i * 16 + (lane & 15)];
+        for (int j = 0; j < WJ; ++j) bf[slot][j] = Rs[buf][kr][wn + j * 16 + (lane & 15)];
+    };
+    auto mfmas = [&](int slot) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < WJ; ++j)
+                    acc[b][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[slot][b][i], bf[slot][j],
+                                                                         acc[b][i][j], 0, 0, 0);
+    };
+    auto compute = [&](int buf) {
+        // sched_barrier fences keep the compiler from sinking the LDS reads
+        // next to their first use, which would expose their latency
+        if constexpr (UPFRONT) {
+#pragma unroll
+            for (int k4 = 0; k4 < BK / 4; ++k4) frag(buf, k4, k4);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k4 = 0; k4 < BK / 4; ++k4) mfmas(k4);
+        } else {
+            frag(buf, 0, 0);
+#pragma unroll
+            for (int k4 = 0; k4 < BK / 4; ++k4) {
+                if (k4 + 1 < BK / 4) frag(buf, k4 + 1, (k4 + 1) & 1);
+                __builtin_amdgcn_sched_barrier(0);
+                mfmas(k4 & 1);
+                __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[b][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[b][i], bf[j],
-                                                                             acc[b][i][j], 0, 0, 0);
         }
-        if (kt + 1 < nk) stash(buf ^ 1);
+    };
+
+    // Two K slices in flight: the registers of slice kt+1 were loaded one step
+    // earlier and slice kt+2 is issued now (two register sets; the loop is
+    // unrolled by two so that the sets swap by name).
+    const int nk = (K + BK - 1) / BK;
+    Stage<NB, H> s0, s1;
+    load(s0, 0);
+    stash(s0, 0);
+    if (nk > 1) load(s1, BK);
+    __syncthreads();
+    int kt = 0;
+    for (; kt + 1 < nk; kt += 2) {
+        if (kt + 2 < nk) load(s0, (kt + 2) * BK);
+        compute(kt & 1);
+        stash(s1, (kt + 1) & 1);
+        __syncthreads();
+        if (kt + 3 < nk) load(s1, (kt + 3) * BK);
+        compute((kt + 1) & 1);
+        if (kt + 2 < nk) stash(s0, (kt + 2) & 1);
         __syncthreads();
     }
+    if (kt < nk) compute(kt & 1);
 
     // epilogue: accumulator element r of lane l is row l/16 + 4r, column l%16
     // (the f64 16x16x4 layout, checked on gfx950)
@@ -122,7 +231,7 @@ __global__ __launch_bounds__(GTPB) void k_gemm_tn_f64(GemmArgs a)
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WJ; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
@@ -150,25 +259,45 @@ __global__ __launch_bounds__(GTPB) void k_gemm_tn_f64(GemmArgs a)
 
 }  // namespace
 
-hipError_t launch_gemm_f64(const GemmArgs &a, int epi, hipStream_t s)
+int gemm_variant = 0;
+
+template <int NB, int EPI>
+static void launch_variant(const GemmArgs &a, int tiles, hipStream_t s)
 {
+    switch (gemm_variant) {
+    case 1:   // 4 waves, fragments double-buffered
+        hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, 32, 4, false>), dim3(tiles), dim3(256), 0, s, a);
+        break;
+    case 3:   // 8 waves, fragments up front
+        hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, 32, 8, true>), dim3(tiles), dim3(512), 0, s, a);
+        break;
+    case 4:   // 8 waves, 64-deep K slices for one batch
+        hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, (NB == 1 ? 64 : 32), 8, false>), dim3(tiles),
+                           dim3(512), 0, s, a);
+        break;
+    default:  // 8 waves (two per SIMD), fragments double-buffered
+        hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, 32, 8, false>), dim3(tiles), dim3(512), 0, s, a);
+        break;
+    }
+}
+
+hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
+{
+    GemmArgs a = in;
+    auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    a.vec = (a.M % 2 == 0) && (a.N % 2 == 0) && al16(a.L0) && al16(a.R) &&
+            (a.L1 == nullptr || al16(a.L1));
     const int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
     const bool dual = a.L1 != nullptr;
     if (epi == EPI_PERMODE && !dual) return hipErrorInvalidValue;
     if (dual) {
-        if (epi == EPI_PERMODE)
-            hipLaunchKernelGGL((k_gemm_tn_f64<2, EPI_PERMODE>), dim3(tiles), dim3(GTPB), 0, s, a);
-        else if (epi == EPI_STORE)
-            hipLaunchKernelGGL((k_gemm_tn_f64<2, EPI_STORE>), dim3(tiles), dim3(GTPB), 0, s, a);
-        else
-            return hipErrorInvalidValue;
+        if (epi == EPI_PERMODE) launch_variant<2, EPI_PERMODE>(a, tiles, s);
+        else if (epi == EPI_STORE) launch_variant<2, EPI_STORE>(a, tiles, s);
+        else return hipErrorInvalidValue;
     } else {
-        if (epi == EPI_DIV_MU)
-            hipLaunchKernelGGL((k_gemm_tn_f64<1, EPI_DIV_MU>), dim3(tiles), dim3(GTPB), 0, s, a);
-        else if (epi == EPI_STORE)
-            hipLaunchKernelGGL((k_gemm_tn_f64<1, EPI_STORE>), dim3(tiles), dim3(GTPB), 0, s, a);
-        else
-            return hipErrorInvalidValue;
+        if (epi == EPI_DIV_MU) launch_variant<1, EPI_DIV_MU>(a, tiles, s);
+        else if (epi == EPI_STORE) launch_variant<1, EPI_STORE>(a, tiles, s);
+        else return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -123,12 +123,18 @@ __global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ p, in
 
 // ---------------------------------------------------------------- Jacobian
 // y_t = G_t x_t + d (x_t - x_b),  y_b = G_b x_b - d (x_t - x_b)     (eq. (J))
+// With v0 (a Krylov vector of length 2mn, top half then bottom half) the
+// kernel also leaves per-block partial sums of <y, v0> in partials: the first
+// projection of the Arnoldi step, fused so that y is not read back.
 __global__ __launch_bounds__(TPB) void k_jacobian(
     int m, int n, Wire top, Wire bot, const double *__restrict__ d,
     const double *__restrict__ xt, const double *__restrict__ xb,
-    double *__restrict__ yt, double *__restrict__ yb)
+    double *__restrict__ yt, double *__restrict__ yb, const double *__restrict__ v0,
+    double *__restrict__ partials, const int *__restrict__ skip)
 {
+    if (skip && *skip) return;
     const size_t mn = (size_t)m * n;
+    double acc[1] = {0.0};
     for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
         const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
         const double t = xt[k], b = xb[k];
@@ -137,8 +143,14 @@ __global__ __launch_bounds__(TPB) void k_jacobian(
         const double sb = wire_apply(bot, i, b, (i > 0) ? xb[k - n] : 0.0,
                                      (i + 1 < m) ? xb[k + n] : 0.0);
         const double c = d[k] * (t - b);
-        yt[k] = st + c;
-        yb[k] = sb - c;
+        const double y1 = st + c, y2 = sb - c;
+        yt[k] = y1;
+        yb[k] = y2;
+        if (v0) acc[0] += y1 * v0[k] + y2 * v0[mn + k];
+    }
+    if (partials) {   // uniform across the grid
+        block_sum<1>(acc);
+        if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
     }
 }
 
@@ -147,8 +159,10 @@ __global__ __launch_bounds__(TPB) void k_jacobian(
 // eq. (block) gives z_t = M^{-1} (r_b - D B^{-1} r_t) and z_b = B^{-1} (r_t - A z_t).
 __global__ __launch_bounds__(TPB) void k_precond_pre(
     int m, int n, Wire bot, double inv_a1, double a2,
-    const double *__restrict__ rt, const double *__restrict__ rb, double *__restrict__ w)
+    const double *__restrict__ rt, const double *__restrict__ rb, double *__restrict__ w,
+    const int *__restrict__ skip)
 {
+    if (skip && *skip) return;
     const size_t mn = (size_t)m * n;
     for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
         const int i = (int)(k / n);
@@ -161,11 +175,13 @@ __global__ __launch_bounds__(TPB) void k_precond_pre(
 
 __global__ __launch_bounds__(TPB) void k_precond_post(
     int m, int n, Wire top, double a1, double inv_a1,
-    const double *__restrict__ zt, const double *__restrict__ rt, double *__restrict__ zb)
+    const double *__restrict__ zt, const double *__restrict__ rt, double *__restrict__ zb,
+    const int *__restrict__ skip)
 {
+    if (skip && *skip) return;
     const size_t mn = (size_t)m * n;
     for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
-        const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
+        const int j = (int)(k % n);
         const double z = zt[k];
         const double s = wire_apply(top, j, z, (j > 0) ? zt[k - 1] : 0.0,
                                     (j + 1 < n) ? zt[k + 1] : 0.0);
@@ -174,6 +190,8 @@ __global__ __launch_bounds__(TPB) void k_precond_post(
 }
 
 // ------------------------------------------------------------------ Krylov
+// Krylov vectors have even length and 16-byte aligned starts, so these
+// kernels stream them as double2 pairs (len2 = len / 2).
 __global__ __launch_bounds__(TPB) void k_dot_partials(
     const double *__restrict__ x, const double *__restrict__ y, size_t len,
     double *__restrict__ partials)
@@ -190,23 +208,33 @@ __global__ __launch_bounds__(TPB) void k_dot_partials(
 //   partial <w, v_next>  (or partial ||w||^2 when v_next is null).
 __global__ __launch_bounds__(TPB) void k_mgs_step(
     double *__restrict__ w, const double *__restrict__ vprev, const double *__restrict__ vnext,
-    size_t len, const double *__restrict__ pin, int nb, double *__restrict__ pout,
-    double *__restrict__ hout)
+    size_t len2, const double *__restrict__ pin, int nb, double *__restrict__ pout,
+    double *__restrict__ hout, const int *__restrict__ skip)
 {
+    if (skip && *skip) return;
     const double h = sum_partials(pin, nb);
     if (blockIdx.x == 0 && threadIdx.x == 0) hout[0] = h;
+    double2 *w2 = reinterpret_cast<double2 *>(w);
+    const double2 *p2 = reinterpret_cast<const double2 *>(vprev);
+    const double2 *n2 = reinterpret_cast<const double2 *>(vnext);
     double acc[1] = {0.0};
     if (vnext) {
-        for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB) {
-            const double x = w[k] - h * vprev[k];
-            w[k] = x;
-            acc[0] += x * vnext[k];
+        for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len2; k += (size_t)gridDim.x * TPB) {
+            double2 x = w2[k];
+            const double2 p = p2[k], q = n2[k];
+            x.x -= h * p.x;
+            x.y -= h * p.y;
+            w2[k] = x;
+            acc[0] += x.x * q.x + x.y * q.y;
         }
     } else {
-        for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB) {
-            const double x = w[k] - h * vprev[k];
-            w[k] = x;
-            acc[0] += x * x;
+        for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len2; k += (size_t)gridDim.x * TPB) {
+            double2 x = w2[k];
+            const double2 p = p2[k];
+            x.x -= h * p.x;
+            x.y -= h * p.y;
+            w2[k] = x;
+            acc[0] += x.x * x.x + x.y * x.y;
         }
     }
     block_sum<1>(acc);
@@ -214,15 +242,88 @@ __global__ __launch_bounds__(TPB) void k_mgs_step(
 }
 
 __global__ __launch_bounds__(TPB) void k_normalize(
-    double *__restrict__ w, size_t len, const double *__restrict__ pin, int nb,
-    double *__restrict__ hout)
+    double *__restrict__ w, size_t len2, const double *__restrict__ pin, int nb,
+    double *__restrict__ hout, const int *__restrict__ skip)
 {
+    if (skip && *skip) return;
     const double nrm = sqrt(sum_partials(pin, nb));
     if (blockIdx.x == 0 && threadIdx.x == 0) hout[0] = nrm;
     if (!(nrm > 0.0)) return;
     const double inv = 1.0 / nrm;
-    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB)
-        w[k] *= inv;
+    double2 *w2 = reinterpret_cast<double2 *>(w);
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len2; k += (size_t)gridDim.x * TPB) {
+        double2 x = w2[k];
+        x.x *= inv;
+        x.y *= inv;
+        w2[k] = x;
+    }
+}
+
+// ------------------------------------------- least squares on the device
+// Control block of one GMRES cycle: ctl[0] stop flag (read by every kernel
+// of later Arnoldi steps), ctl[1] iterations completed, ctl[2] reason.
+// ls: g[R+1] (rotated right-hand side), cs[R], sn[R] (Givens rotations).
+__global__ void k_cycle_init(int *__restrict__ ctl, double *__restrict__ g, int R, double beta)
+{
+    for (int i = threadIdx.x; i <= R; i += blockDim.x) g[i] = (i == 0) ? beta : 0.0;
+    if (threadIdx.x == 0) {
+        ctl[0] = 0;
+        ctl[1] = 0;
+        ctl[2] = CYCLE_RUNNING;
+    }
+}
+
+// Hessenberg column j: apply rotations 0..j-1, then the rotation that zeroes
+// h[j+1]; update g and stop when |g[j+1]| <= abs_tol (the GMRES residual).
+__global__ void k_givens(double *__restrict__ H, int ldh, int j, double *__restrict__ g,
+                         double *__restrict__ cs, double *__restrict__ sn, double abs_tol,
+                         int *__restrict__ ctl, double *__restrict__ resid)
+{
+    if (threadIdx.x != 0 || ctl[0]) return;
+    double *h = H + (size_t)j * ldh;
+    for (int i = 0; i <= j + 1; ++i)
+        if (!isfinite(h[i])) {
+            ctl[0] = 1;
+            ctl[2] = CYCLE_NONFINITE;
+            return;
+        }
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+    }
+    const double hn = h[j + 1];
+    const double r = hypot(h[j], hn);
+    if (r == 0.0) {
+        ctl[0] = 1;
+        ctl[2] = CYCLE_BREAKDOWN;
+        return;
+    }
+    cs[j] = h[j] / r;
+    sn[j] = hn / r;
+    h[j] = r;
+    h[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    ctl[1] = j + 1;
+    resid[j] = fabs(g[j + 1]);
+    if (fabs(g[j + 1]) <= abs_tol) {   // includes hn == 0 (invariant subspace)
+        ctl[0] = 1;
+        ctl[2] = CYCLE_CONVERGED;
+    }
+}
+
+// y = R^{-1} g over the ctl[1] completed columns (upper triangular R in H).
+__global__ void k_backsolve(const double *__restrict__ H, int ldh, const double *__restrict__ g,
+                            const int *__restrict__ ctl, double *__restrict__ y)
+{
+    if (threadIdx.x != 0) return;
+    const int k = ctl[1];
+    for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int c = i + 1; c < k; ++c) t -= H[(size_t)c * ldh + i] * y[c];
+        y[i] = t / H[(size_t)i * ldh + i];
+    }
 }
 
 __global__ __launch_bounds__(TPB) void k_scale(const double *__restrict__ x, double alpha,
@@ -232,14 +333,22 @@ __global__ __launch_bounds__(TPB) void k_scale(const double *__restrict__ x, dou
         y[k] = alpha * x[k];
 }
 
+// x (+)= sum_{v < nvec} coef[v] Z_v, nvec = *kptr (device) when kptr is given
 __global__ __launch_bounds__(TPB) void k_update(
     const double *__restrict__ Z, size_t zstride, const double *__restrict__ coef, int nvec,
-    size_t len, double *__restrict__ x, int accumulate)
+    const int *__restrict__ kptr, size_t len2, double *__restrict__ x, int accumulate)
 {
-    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB) {
-        double s = accumulate ? x[k] : 0.0;
-        for (int v = 0; v < nvec; ++v) s += coef[v] * Z[(size_t)v * zstride + k];
-        x[k] = s;
+    if (kptr) nvec = *kptr;
+    double2 *x2 = reinterpret_cast<double2 *>(x);
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len2; k += (size_t)gridDim.x * TPB) {
+        double2 s = accumulate ? x2[k] : double2{0.0, 0.0};
+        for (int v = 0; v < nvec; ++v) {
+            const double2 z = reinterpret_cast<const double2 *>(Z + (size_t)v * zstride)[k];
+            const double c = coef[v];
+            s.x += c * z.x;
+            s.y += c * z.y;
+        }
+        x2[k] = s;
     }
 }
 
@@ -301,29 +410,33 @@ hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double 
 }
 
 hipError_t launch_jacobian(const mca_plan *P, const double *d, const double *xt,
-                           const double *xb, double *yt, double *yb, hipStream_t s)
+                           const double *xb, double *yt, double *yb, hipStream_t s,
+                           const double *v0, double *partials, const int *skip)
 {
     const int m = P->geom.m, n = P->geom.n;
-    hipLaunchKernelGGL(k_jacobian, dim3(elementwise_blocks((size_t)m * n)), dim3(TPB), 0, s, m,
-                       n, P->top, P->bot, d, xt, xb, yt, yb);
+    const size_t mn = (size_t)m * n;
+    // with a projection the grid matches the Krylov reductions of length 2mn
+    const int blocks = v0 ? reduce_blocks(2 * mn) : elementwise_blocks(mn);
+    hipLaunchKernelGGL(k_jacobian, dim3(blocks), dim3(TPB), 0, s, m, n, P->top, P->bot, d, xt,
+                       xb, yt, yb, v0, v0 ? partials : nullptr, skip);
     return hipGetLastError();
 }
 
 hipError_t launch_precond_pre(const mca_plan *P, double a1, double a2, const double *rt,
-                              const double *rb, double *w, hipStream_t s)
+                              const double *rb, double *w, hipStream_t s, const int *skip)
 {
     const int m = P->geom.m, n = P->geom.n;
     hipLaunchKernelGGL(k_precond_pre, dim3(elementwise_blocks((size_t)m * n)), dim3(TPB), 0, s,
-                       m, n, P->bot, 1.0 / a1, a2, rt, rb, w);
+                       m, n, P->bot, 1.0 / a1, a2, rt, rb, w, skip);
     return hipGetLastError();
 }
 
 hipError_t launch_precond_post(const mca_plan *P, double a1, const double *zt,
-                               const double *rt, double *zb, hipStream_t s)
+                               const double *rt, double *zb, hipStream_t s, const int *skip)
 {
     const int m = P->geom.m, n = P->geom.n;
     hipLaunchKernelGGL(k_precond_post, dim3(elementwise_blocks((size_t)m * n)), dim3(TPB), 0, s,
-                       m, n, P->top, a1, 1.0 / a1, zt, rt, zb);
+                       m, n, P->top, a1, 1.0 / a1, zt, rt, zb, skip);
     return hipGetLastError();
 }
 
@@ -337,19 +450,41 @@ hipError_t launch_dot_partials(const double *x, const double *y, size_t len, dou
 
 hipError_t launch_mgs_step(double *w, const double *v_prev, const double *v_next, size_t len,
                            const double *partials_in, double *partials_out, double *h_out,
-                           hipStream_t s)
+                           hipStream_t s, const int *skip)
 {
     const int nb = reduce_blocks(len);
-    hipLaunchKernelGGL(k_mgs_step, dim3(nb), dim3(TPB), 0, s, w, v_prev, v_next, len,
-                       partials_in, nb, partials_out, h_out);
+    hipLaunchKernelGGL(k_mgs_step, dim3(nb), dim3(TPB), 0, s, w, v_prev, v_next, len / 2,
+                       partials_in, nb, partials_out, h_out, skip);
     return hipGetLastError();
 }
 
 hipError_t launch_normalize(double *w, size_t len, const double *partials_in, double *h_out,
-                            hipStream_t s)
+                            hipStream_t s, const int *skip)
 {
     const int nb = reduce_blocks(len);
-    hipLaunchKernelGGL(k_normalize, dim3(nb), dim3(TPB), 0, s, w, len, partials_in, nb, h_out);
+    hipLaunchKernelGGL(k_normalize, dim3(nb), dim3(TPB), 0, s, w, len / 2, partials_in, nb,
+                       h_out, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_cycle_init(int *ctl, double *g, int R, double beta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, s, ctl, g, R, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_givens(double *H, int ldh, int j, double *g, double *cs, double *sn,
+                         double abs_tol, int *ctl, double *resid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, H, ldh, j, g, cs, sn, abs_tol, ctl,
+                       resid);
+    return hipGetLastError();
+}
+
+hipError_t launch_backsolve(const double *H, int ldh, const double *g, const int *ctl,
+                            double *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, H, ldh, g, ctl, y);
     return hipGetLastError();
 }
 
@@ -359,11 +494,11 @@ hipError_t launch_scale(const double *x, double alpha, double *y, size_t len, hi
     return hipGetLastError();
 }
 
-hipError_t launch_update(const double *Z, size_t zstride, const double *coef, int k, size_t len,
-                         double *x, int accumulate, hipStream_t s)
+hipError_t launch_update(const double *Z, size_t zstride, const double *coef, int k,
+                         const int *kptr, size_t len, double *x, int accumulate, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update, dim3(elementwise_blocks(len)), dim3(TPB), 0, s, Z, zstride,
-                       coef, k, len, x, accumulate);
+    hipLaunchKernelGGL(k_update, dim3(elementwise_blocks(len / 2)), dim3(TPB), 0, s, Z, zstride,
+                       coef, k, kptr, len / 2, x, accumulate);
     return hipGetLastError();
 }
 

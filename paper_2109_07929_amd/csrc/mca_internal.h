@@ -65,15 +65,22 @@ hipError_t launch_residual(const mca_plan *P, const double *g_dev, const double 
 hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double *out,
                          hipStream_t s);
 
+// y = J x (eq. (J)); with v0 also per-block partials of <y, v0> (grid of
+// reduce_blocks(2mn) blocks).  Kernels given a skip flag return at once when
+// it is set (a converged GMRES cycle).
 hipError_t launch_jacobian(const mca_plan *P, const double *d, const double *xt,
-                           const double *xb, double *yt, double *yb, hipStream_t s);
+                           const double *xb, double *yt, double *yb, hipStream_t s,
+                           const double *v0 = nullptr, double *partials = nullptr,
+                           const int *skip = nullptr);
 
 // w = r_b + ((G_b + a2 I) r_t) / a1            (first step of the literal form)
 hipError_t launch_precond_pre(const mca_plan *P, double a1, double a2, const double *rt,
-                              const double *rb, double *w, hipStream_t s);
+                              const double *rb, double *w, hipStream_t s,
+                              const int *skip = nullptr);
 // z_b = ((G_t + a1 I) z_t - r_t) / a1          (last step of the literal form)
 hipError_t launch_precond_post(const mca_plan *P, double a1, const double *zt,
-                               const double *rt, double *zb, hipStream_t s);
+                               const double *rt, double *zb, hipStream_t s,
+                               const int *skip = nullptr);
 
 // GEMM epilogues
 enum GemmEpi { EPI_STORE = 0, EPI_DIV_MU = 1, EPI_PERMODE = 2 };
@@ -89,26 +96,39 @@ struct GemmArgs {
     double *O0, *O1;
     const double *lb, *lt;     // for the epilogues (length M and N)
     double a1, a2;
+    int vec;                   // set by the launcher: rows are 16-byte aligned
+    const int *skip;           // optional: return at once when *skip != 0
 };
 hipError_t launch_gemm_f64(const GemmArgs &a, int epi, hipStream_t s);
+extern int gemm_variant;   // kernel variant (tuning only; 0 = default)
 
-// Krylov kernels over vectors of length len (= 2mn).
-// partial dot products x.y -> partials[reduce_blocks(len)]
+// Krylov kernels over vectors of even length len (= 2mn), 16-byte aligned.
+// partial dot products x.y -> partials[reduce_blocks(len)] (any length)
 hipError_t launch_dot_partials(const double *x, const double *y, size_t len,
                                double *partials, hipStream_t s);
 // h = sum(partials_in); h_out[0] = h; w -= h * v_prev; partials_out = partial dots (w, v_next),
 // or partial ||w||^2 when v_next == nullptr.
 hipError_t launch_mgs_step(double *w, const double *v_prev, const double *v_next, size_t len,
                            const double *partials_in, double *partials_out, double *h_out,
-                           hipStream_t s);
+                           hipStream_t s, const int *skip = nullptr);
 // nrm = sqrt(sum(partials_in)); h_out[0] = nrm; w *= 1/nrm (when nrm > 0)
 hipError_t launch_normalize(double *w, size_t len, const double *partials_in, double *h_out,
-                            hipStream_t s);
+                            hipStream_t s, const int *skip = nullptr);
+
+// Device-side least squares of one GMRES cycle (see k_givens).
+enum CycleReason { CYCLE_RUNNING = 0, CYCLE_CONVERGED = 1, CYCLE_BREAKDOWN = 2,
+                   CYCLE_NONFINITE = 3 };
+hipError_t launch_cycle_init(int *ctl, double *g, int R, double beta, hipStream_t s);
+hipError_t launch_givens(double *H, int ldh, int j, double *g, double *cs, double *sn,
+                         double abs_tol, int *ctl, double *resid, hipStream_t s);
+hipError_t launch_backsolve(const double *H, int ldh, const double *g, const int *ctl,
+                            double *y, hipStream_t s);
+
 // y = alpha * x
 hipError_t launch_scale(const double *x, double alpha, double *y, size_t len, hipStream_t s);
-// x (+)= sum_i coef[i] * Z[i]  (coef on device, k <= MCA_MAX_RESTART); accumulate: x += ...
-hipError_t launch_update(const double *Z, size_t zstride, const double *coef, int k, size_t len,
-                         double *x, int accumulate, hipStream_t s);
+// x (+)= sum_i coef[i] * Z[i], i < (kptr ? *kptr : k)   (coef on device)
+hipError_t launch_update(const double *Z, size_t zstride, const double *coef, int k,
+                         const int *kptr, size_t len, double *x, int accumulate, hipStream_t s);
 // out = a + s * b
 hipError_t launch_axpby(const double *a, double sc, const double *b, double *out, size_t len,
                         hipStream_t s);

@@ -1,9 +1,11 @@
 // solver.cpp -- C ABI, plan set-up and the Newton / flexible-GMRES control loop.
 //
-// The control flow is host code; every arithmetic step on crossbar-sized data
-// runs in the HIP kernels of kernels.hip and gemm.hip.  The host reads back a
-// few scalars per iteration (norms and one Hessenberg column) and does the
-// O(restart^2) Givens work of the least-squares problem.
+// The control flow is host code; every arithmetic step runs in the HIP kernels
+// of kernels.hip and gemm.hip, including the Givens rotations and the small
+// triangular solve of GMRES.  Within a GMRES cycle the host never stalls the
+// GPU: it enqueues Arnoldi step j, then waits for the convergence flag of step
+// j-1 (already computed on the device) while step j runs.  Once the flag is
+// set, the kernels of the one step enqueued beyond it return immediately.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -148,6 +150,8 @@ struct SolveWs {
     double *H;        // Hessenberg, column-major, ld = restart + 1
     double *coef;     // least-squares solution y
     double *scal;     // reduced scalars
+    double *g, *cs, *sn, *resid;   // Givens state of the current cycle
+    int *ctl;         // cycle control block (stop flag, steps done, reason)
     PrecondWs pw;
     size_t bytes;
 };
@@ -173,6 +177,11 @@ SolveWs solve_layout(const mca_plan *P, const mca_options *o, void *base)
     w.H = c.take<double>((R + 1) * R);
     w.coef = c.take<double>(R);
     w.scal = c.take<double>(8);
+    w.g = c.take<double>(R + 1);
+    w.cs = c.take<double>(R);
+    w.sn = c.take<double>(R);
+    w.resid = c.take<double>(R);
+    w.ctl = c.take<int>(4);
     w.pw = precond_layout(P, c, o->precond);
     w.bytes = c.size();
     return w;
@@ -203,48 +212,59 @@ double *pinned_scratch()
 bool plan_ready(const mca_plan *P) { return P && P->dev_buf != nullptr; }
 
 // GPU time per kernel class, from HIP events recorded around each group of
-// launches; collected after every stream synchronisation of the solve.
+// launches.  Two slots alternate between consecutive Arnoldi steps (the host
+// runs one step ahead); a slot is collected once its step has completed, and
+// counted only if the step ran (a step skipped after convergence is not).
 struct Timing {
+    static constexpr int kSlots = 2;
     bool on = false;
-    hipEvent_t ev[MCA_NUM_KCLASS][2] = {};
-    int pending[MCA_NUM_KCLASS] = {};
+    hipEvent_t ev[kSlots][MCA_NUM_KCLASS][2] = {};
+    int pending[kSlots][MCA_NUM_KCLASS] = {};
     double ms[MCA_NUM_KCLASS] = {};
     int launches[MCA_NUM_KCLASS] = {};
 
     hipError_t init()
     {
         on = true;
-        for (auto &c : ev)
-            for (auto &e : c) {
-                hipError_t r = hipEventCreate(&e);
-                if (r != hipSuccess) return r;
-            }
+        for (auto &sl : ev)
+            for (auto &c : sl)
+                for (auto &e : c) {
+                    hipError_t r = hipEventCreate(&e);
+                    if (r != hipSuccess) return r;
+                }
         return hipSuccess;
     }
     ~Timing()
     {
-        for (auto &c : ev)
-            for (auto &e : c)
-                if (e) (void)hipEventDestroy(e);
+        for (auto &sl : ev)
+            for (auto &c : sl)
+                for (auto &e : c)
+                    if (e) (void)hipEventDestroy(e);
     }
-    hipError_t begin(int c, hipStream_t s) { return on ? hipEventRecord(ev[c][0], s) : hipSuccess; }
-    hipError_t end(int c, hipStream_t s, int nlaunch)
+    hipError_t begin(int c, hipStream_t s, int slot = 0)
+    {
+        return on ? hipEventRecord(ev[slot][c][0], s) : hipSuccess;
+    }
+    hipError_t end(int c, hipStream_t s, int nlaunch, int slot = 0)
     {
         if (!on) return hipSuccess;
-        pending[c] = nlaunch;
-        return hipEventRecord(ev[c][1], s);
+        pending[slot][c] = nlaunch;
+        return hipEventRecord(ev[slot][c][1], s);
     }
-    hipError_t collect()
+    // after the events of `slot` have completed
+    hipError_t collect(int slot = 0, bool count = true)
     {
         if (!on) return hipSuccess;
         for (int c = 0; c < MCA_NUM_KCLASS; ++c) {
-            if (!pending[c]) continue;
-            float t = 0.f;
-            hipError_t r = hipEventElapsedTime(&t, ev[c][0], ev[c][1]);
-            if (r != hipSuccess) return r;
-            ms[c] += t;
-            launches[c] += pending[c];
-            pending[c] = 0;
+            if (!pending[slot][c]) continue;
+            if (count) {
+                float t = 0.f;
+                hipError_t r = hipEventElapsedTime(&t, ev[slot][c][0], ev[slot][c][1]);
+                if (r != hipSuccess) return r;
+                ms[c] += t;
+                launches[c] += pending[slot][c];
+            }
+            pending[slot][c] = 0;
         }
         return hipSuccess;
     }
@@ -253,7 +273,8 @@ struct Timing {
 // z = P^{-1} r (eq. (P)) in the chosen evaluation form.
 mca_status precond_run(const mca_plan *P, int form, double a1, double a2, const double *rt,
                        const double *rb, double *zt, double *zb, const PrecondWs &w,
-                       hipStream_t s, Timing *tm = nullptr)
+                       hipStream_t s, Timing *tm = nullptr, int slot = 0,
+                       const int *skip = nullptr)
 {
     Timing off;
     if (!tm) tm = &off;
@@ -270,11 +291,12 @@ mca_status precond_run(const mca_plan *P, int form, double a1, double a2, const 
     g.lt = d.lt;
     g.a1 = a1;
     g.a2 = a2;
+    g.skip = skip;
     if (form == MCA_PRECOND_LITERAL) {
         // w = r_b + (G_b + a2 I) r_t / a1
-        MCA_TRY(launch_precond_pre(P, a1, a2, rt, rb, w.b0t, s));
+        MCA_TRY(launch_precond_pre(P, a1, a2, rt, rb, w.b0t, s, skip));
         // (Q_m^T W)^T = W^T Q_m                      (n x m)
-        MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s));
+        MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
         g.M = n; g.N = m; g.K = m; g.L0 = w.b0t; g.L1 = nullptr; g.R = d.Qm; g.O0 = w.b1t;
         MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
         // W_hat = Q_m^T W Q_n, then ./ mu             (m x n)
@@ -286,13 +308,13 @@ mca_status precond_run(const mca_plan *P, int form, double a1, double a2, const 
         // z_t = Q_m X_hat Q_n^T                       (m x n)
         g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.R = d.QnT; g.O0 = zt;
         MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
-        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 4));
+        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 4, slot));
         // z_b = ((G_t + a1 I) z_t - r_t) / a1
-        MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s));
+        MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s, skip));
         return MCA_OK;
     }
     // per-mode: transform both layers, solve each mode's 2x2 block, transform back
-    MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s));
+    MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
     g.M = n; g.N = m; g.K = m; g.L0 = rt; g.L1 = rb; g.R = d.Qm; g.O0 = w.b1t; g.O1 = w.b1b;
     MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
     g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.L1 = w.b1b; g.R = d.Qn; g.O0 = w.b0t; g.O1 = w.b0b;
@@ -301,13 +323,9 @@ mca_status precond_run(const mca_plan *P, int form, double a1, double a2, const 
     MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
     g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.L1 = w.b1b; g.R = d.QnT; g.O0 = zt; g.O1 = zb;
     MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
-    MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 4));
+    MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 4, slot));
     return MCA_OK;
 }
-
-struct Givens {
-    double c, s;
-};
 
 // Flexible GMRES(restart) with modified Gram-Schmidt for J X = -F, right
 // preconditioned by P(a, a).  On return X holds the correction.
@@ -317,14 +335,24 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
 {
     const size_t mn = (size_t)P->geom.m * P->geom.n, len = 2 * mn;
     const int R = o->restart;
-    const size_t ldh = (size_t)R + 1;
+    const int ldh = R + 1;
     double *host = pinned_scratch();
     if (!host) {
         set_hip_error("hipHostMalloc", hipErrorOutOfMemory);
         return MCA_ERR_HIP;
     }
-    std::vector<double> Hc((size_t)(R + 1) * R), gvec(R + 1), y(R);
-    std::vector<Givens> rot(R);
+    // host snapshots of the control block, one slot per Arnoldi step
+    int *snap = reinterpret_cast<int *>(host + 256);
+    hipEvent_t done[2] = {nullptr, nullptr};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int i = 0; i < 2; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } guard{done};
+    for (auto &e : done) MCA_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
     double beta = fnorm;
     const double abs_tol = o->gmres_tol * fnorm;
@@ -333,87 +361,65 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
     // v_0 = -F / ||F||
     MCA_TRY(launch_scale(w.F, -1.0 / beta, w.V, len, s));
     for (;;) {
-        std::fill(gvec.begin(), gvec.end(), 0.0);
-        gvec[0] = beta;
-        int k = 0;
-        bool breakdown = false;
-        for (int j = 0; j < R; ++j) {
+        MCA_TRY(launch_cycle_init(w.ctl, w.g, R, beta, s));
+        const int jmax = std::min(R, o->max_krylov - its);
+        int last = -1;
+        for (int j = 0; j < jmax; ++j) {
+            const int slot = j & 1;
             double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
             double *wv = w.V + (size_t)(j + 1) * len;
-            mca_status st =
-                precond_run(P, o->precond, a, a, vj, vj + mn, zj, zj + mn, w.pw, s, tm);
+            const int *skip = w.ctl;
+            mca_status st = precond_run(P, o->precond, a, a, vj, vj + mn, zj, zj + mn, w.pw, s,
+                                        tm, slot, skip);
             if (st != MCA_OK) return st;
-            MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s));
-            MCA_TRY(launch_jacobian(P, w.D, zj, zj + mn, wv, wv + mn, s));
-            MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1));
+            // w = J z_j, fused with the partial sums of <w, v_0>
+            MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
+            MCA_TRY(launch_jacobian(P, w.D, zj, zj + mn, wv, wv + mn, s, w.V, w.pa, skip));
+            MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1, slot));
             // modified Gram-Schmidt: h_ij = <w, v_i>, w -= h_ij v_i, i = 0..j
             double *hcol = w.H + (size_t)j * ldh;
-            MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s));
-            MCA_TRY(launch_dot_partials(wv, w.V, len, w.pa, s));
+            MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s, slot));
             double *pin = w.pa, *pout = w.pb;
             for (int i = 0; i <= j; ++i) {
                 const double *vnext = (i < j) ? w.V + (size_t)(i + 1) * len : nullptr;
                 MCA_TRY(launch_mgs_step(wv, w.V + (size_t)i * len, vnext, len, pin, pout,
-                                        hcol + i, s));
+                                        hcol + i, s, skip));
                 std::swap(pin, pout);
             }
-            MCA_TRY(launch_normalize(wv, len, pin, hcol + j + 1, s));
-            MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 3));
-            MCA_TRY(hipMemcpyAsync(host, hcol, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-            MCA_TRY(hipStreamSynchronize(s));
-            MCA_TRY(tm->collect());
-            double *h = &Hc[(size_t)j * ldh];
-            for (int i = 0; i <= j + 1; ++i) {
-                h[i] = host[i];
-                if (!std::isfinite(h[i])) return MCA_ERR_NONFINITE;
+            MCA_TRY(launch_normalize(wv, len, pin, hcol + j + 1, s, skip));
+            MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 2, slot));
+            MCA_TRY(launch_givens(w.H, ldh, j, w.g, w.cs, w.sn, abs_tol, w.ctl, w.resid, s));
+            MCA_TRY(hipMemcpyAsync(snap + 4 * j, w.ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+            MCA_TRY(hipEventRecord(done[slot], s));
+            last = j;
+            if (j > 0) {
+                // step j runs on the GPU while the host reads step j-1's outcome
+                MCA_TRY(hipEventSynchronize(done[slot ^ 1]));
+                const int *c = snap + 4 * (j - 1);
+                MCA_TRY(tm->collect(slot ^ 1, c[1] == j));
+                if (c[0]) break;
             }
-            // apply the previous rotations, then annihilate h[j+1]
-            for (int i = 0; i < j; ++i) {
-                const double t = rot[i].c * h[i] + rot[i].s * h[i + 1];
-                h[i + 1] = -rot[i].s * h[i] + rot[i].c * h[i + 1];
-                h[i] = t;
-            }
-            const double hn = h[j + 1];
-            const double r = std::hypot(h[j], hn);
-            if (r == 0.0) {
-                breakdown = true;
-                k = j;
-                break;
-            }
-            rot[j].c = h[j] / r;
-            rot[j].s = hn / r;
-            h[j] = r;
-            h[j + 1] = 0.0;
-            gvec[j + 1] = -rot[j].s * gvec[j];
-            gvec[j] = rot[j].c * gvec[j];
-            ++its;
-            k = j + 1;
-            if (std::fabs(gvec[j + 1]) <= abs_tol) {
-                converged = true;
-                break;
-            }
-            if (hn == 0.0) {   // exact invariant subspace: the residual above is final
-                breakdown = true;
-                break;
-            }
-            if (its >= o->max_krylov) break;
         }
+        if (last >= 0) {
+            MCA_TRY(hipEventSynchronize(done[last & 1]));
+            MCA_TRY(tm->collect(last & 1, snap[4 * last + 1] == last + 1));
+        }
+        const int *c = (last >= 0) ? snap + 4 * last : nullptr;
+        const int k = c ? c[1] : 0;
+        const int reason = c ? c[2] : CYCLE_RUNNING;
+        if (reason == CYCLE_NONFINITE) return MCA_ERR_NONFINITE;
+        its += k;
         if (k > 0) {
-            // y = R^{-1} g  (upper triangular, column-major in Hc)
-            for (int i = k - 1; i >= 0; --i) {
-                double t = gvec[i];
-                for (int c2 = i + 1; c2 < k; ++c2) t -= Hc[(size_t)c2 * ldh + i] * y[c2];
-                y[i] = t / Hc[(size_t)i * ldh + i];
-            }
-            for (int i = 0; i < k; ++i) host[i] = y[i];
-            MCA_TRY(hipMemcpyAsync(w.coef, host, k * sizeof(double), hipMemcpyHostToDevice, s));
-            MCA_TRY(launch_update(w.Z, len, w.coef, k, len, w.X, first ? 0 : 1, s));
+            MCA_TRY(launch_backsolve(w.H, ldh, w.g, w.ctl, w.coef, s));
+            // the number of completed steps is ctl[1]
+            MCA_TRY(launch_update(w.Z, len, w.coef, 0, w.ctl + 1, len, w.X, first ? 0 : 1, s));
             first = false;
         } else if (first) {
             MCA_TRY(launch_fill(w.X, 0.0, len, s));
             first = false;
         }
-        if (converged || its >= o->max_krylov || breakdown) break;
+        converged = reason == CYCLE_CONVERGED;
+        if (converged || its >= o->max_krylov || reason == CYCLE_BREAKDOWN || k == 0) break;
         // restart from the true residual  r = -F - J X
         ++restarts;
         MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s));

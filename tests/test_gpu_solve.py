@@ -78,6 +78,35 @@ def test_solve_shapes(m, n, form):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("restart", [1, 2, 3])
+def test_solve_with_restarts(restart):
+    """Short restart lengths force several GMRES cycles per Newton step."""
+    say(f"solve 20x24 restart={restart}")
+    cb = synth.crossbar(20, 24, seed=21)
+    vt, vb, status, st = gpu_solve(cb, restart=restart, max_krylov=2000)
+    assert status == B.MCA_OK
+    assert st.restarts > 0
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in)
+    err = rel_err(vt, vb, rt, rb)
+    say(f"  newton {st.newton_iters} krylov {st.krylov_iters} restarts {st.restarts} err {err:.2e}")
+    assert err <= TOL
+
+
+def test_first_newton_step_is_the_linear_solve():
+    """From V = 0 the first Newton step is J(0)^{-1} Y: GMRES at tolerance 1e-10
+    must reproduce the oracle's direct solve of that system."""
+    n = 48
+    cb = synth.crossbar(n, n, seed=0)
+    ft, fb, d = oracle.residual(cb.geom, cb.g_dev, cb.v_in, np.zeros((n, n)), np.zeros((n, n)))
+    xt, xb = oracle.jacobian_solve(cb.geom, d, -ft, -fb, method="band")
+    for form in (B.MCA_PRECOND_LITERAL, B.MCA_PRECOND_PERMODE):
+        vt, vb, status, st = gpu_solve(cb, max_newton=1, gmres_tol=1e-10, precond=form)
+        assert status == B.MCA_ERR_NOT_CONVERGED and st.backtracks == 0
+        err = rel_err(vt, vb, xt, xb)
+        say(f"  first step form={form} err {err:.2e}")
+        assert err <= 1e-8
+
+
 def test_solve_1024_seed0():
     """The headline 1024 x 1024 crossbar (~2.1M unknowns) in the benchmark's
     configuration, against the oracle's Newton-CG steady state."""
@@ -91,6 +120,7 @@ def test_solve_1024_seed0():
     err = rel_err(vt, vb, rt, rb)
     say(f"  err vs oracle {err:.2e}")
     assert err <= TOL
+    assert st.newton_iters <= 4 and st.krylov_iters <= 40
     # Kirchhoff: source current in = termination currents out
     g = cb.geom
     i_in = np.sum(g.g_src * (cb.v_in - vt[:, 0]))
@@ -156,6 +186,8 @@ def test_not_converged_keeps_iterate_and_stats():
     assert status == B.MCA_ERR_NOT_CONVERGED
     assert st.newton_iters == 1 and st.krylov_iters >= 1
     assert 0 < st.rel_residual < 1e-2 and np.abs(vt).max() > 0.1
+    # the first step is exact up to the GMRES tolerance, so Newton is quadratic
+    assert st.rel_residual < 1e-3
 
 
 def test_nonfinite_input_reported():
