@@ -43,6 +43,24 @@ def parse():
     return p.parse_args()
 
 
+def gemm_traffic():
+    """HBM bytes of one FP64 transform launch at 1024^3, from the committed rocprofv3
+    counter summary, or None when the GEMM source changed since it was taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "solve_fp64_1024x1024.md")
+    src = os.path.join(ROOT, "paper_2109_07929_amd", "csrc", "gemm.hip")
+    try:
+        text = open(prof).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in text.splitlines()
+                if l.startswith(("gemm_traffic_bytes_per_launch:", "gemm_source_sha256:")))
+    if vals.get("gemm_source_sha256", "").strip() != digest:
+        return None
+    return int(vals["gemm_traffic_bytes_per_launch"])
+
+
 def cpu_baseline(cb):
     """The CPU oracle (plain FP64 C, one thread) on the same crossbar: one full
     Newton solve with CG linear steps (the oracle's large-size method)."""
@@ -118,7 +136,7 @@ def main():
     # roofline of the dominant kernel: the FP64 eigenbasis GEMMs
     roofline = None
     if not args.no_timing and klaunch[B.MCA_KCLASS_GEMM] > 0:
-        flops_per_launch = 2.0 * m * n * (m if True else n)   # 2 M N K, K = m (= n here)
+        flops_per_launch = 2.0 * m * n * m   # 2 M N K with M = N = K = size
         if form == B.MCA_PRECOND_PERMODE:
             flops_per_launch *= 2.0                            # two layers per launch
         avg_ms = kms[B.MCA_KCLASS_GEMM] / klaunch[B.MCA_KCLASS_GEMM]
@@ -126,7 +144,9 @@ def main():
         roofline = {"bound": "mfma", "kernel": "k_gemm_tn_f64 (eigenbasis transform)",
                     "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
-                    "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2),
+                    "traffic": gemm_traffic() if (m == 1024 and form == B.MCA_PRECOND_LITERAL) else None,
+                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
+                    "avg_launch_us": round(avg_ms * 1e3, 2),
                     "flops_per_launch": flops_per_launch}
     breakdown = {}
     if not args.no_timing:
