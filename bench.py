@@ -32,7 +32,10 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--size", type=int, default=1024, help="crossbar is size x size")
     p.add_argument("--seed", type=int, default=0)
-    p.add_argument("--precond", choices=["literal", "permode"], default="literal")
+    p.add_argument("--precond", choices=["literal", "permode"], default=None,
+                   help="default: literal for fp64, permode otherwise")
+    p.add_argument("--precision", choices=["fp64", "fp32", "bf16x3", "bf16"], default="fp64",
+                   help="arithmetic of the preconditioner's eigenbasis transforms")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-timing", action="store_true",
                    help="do not time kernel classes with HIP events (no roofline object)")
@@ -97,9 +100,13 @@ def main():
     plan = Plan(cb.geom, device=dev)
     setup_ms = 1e3 * (time.perf_counter() - t0)
 
+    prec = {"fp64": B.MCA_PREC_FP64, "fp32": B.MCA_PREC_FP32, "bf16x3": B.MCA_PREC_BF16X3,
+            "bf16": B.MCA_PREC_BF16}[args.precision]
+    if args.precond is None:
+        args.precond = "literal" if prec == B.MCA_PREC_FP64 else "permode"
     form = B.MCA_PRECOND_LITERAL if args.precond == "literal" else B.MCA_PRECOND_PERMODE
     flags = 0 if args.no_timing else B.MCA_FLAG_TIMING
-    opts = B.options(precond=form, flags=flags)
+    opts = B.options(precond=form, precision=prec, flags=flags)
     v_t = torch.zeros((m, n), dtype=torch.float64, device=dev)
     v_b = torch.zeros_like(v_t)
     ws = plan.workspace(opts)
@@ -135,7 +142,7 @@ def main():
 
     # roofline of the dominant kernel: the FP64 eigenbasis GEMMs
     roofline = None
-    if not args.no_timing and klaunch[B.MCA_KCLASS_GEMM] > 0:
+    if not args.no_timing and klaunch[B.MCA_KCLASS_GEMM] > 0 and prec == B.MCA_PREC_FP64:
         flops_per_launch = 2.0 * m * n * m   # 2 M N K with M = N = K = size
         if form == B.MCA_PRECOND_PERMODE:
             flops_per_launch *= 2.0                            # two layers per launch
@@ -155,6 +162,9 @@ def main():
             breakdown[nm] = {"ms_per_solve": round(kms[c] / args.steps, 4),
                              "launches_per_solve": int(klaunch[c] // args.steps)}
 
+    kind = ("plain FP64 Newton-FGMRES(30)" if prec == B.MCA_PREC_FP64 else
+            f"Newton-FGMRES(30) with a {args.precision} preconditioner")
+    workload = f"{kind}, {m}x{n} crossbar ({2 * m * n} unknowns), seed {args.seed}"
     out = {
         "metric": "MCA solves/s at 1024x1024, 1e-8 rel residual: plain FP64 vs batched+warm+mixed",
         "value": round(value, 3),
@@ -166,10 +176,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == B.MCA_PREC_FP64 else f"f64 (preconditioner {args.precision})",
         "data": "synthetic",
-        "config": {"workload": f"plain FP64 Newton-FGMRES(30), {m}x{n} crossbar "
-                               f"({2 * m * n} unknowns), seed {args.seed}",
+        "config": {"workload": workload,
                    "precond": args.precond, "newton_tol": opts.newton_tol,
                    "gmres_tol": opts.gmres_tol, "setup_ms": round(setup_ms, 1),
                    "newton_iters": newton[-1], "krylov_iters": krylov[-1],

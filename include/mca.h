@@ -54,10 +54,14 @@ typedef int32_t mca_status;
 
 /* Arithmetic of the preconditioner's eigenbasis transforms.  The Newton
  * residual, the Jacobian products, the Arnoldi orthogonalisation and the
- * Hessenberg least squares are FP64 in every mode.                          */
+ * Hessenberg least squares are FP64 in every mode; flexible GMRES absorbs the
+ * rounding of a reduced-precision preconditioner.  Reduced precisions need
+ * MCA_PRECOND_PERMODE (the literal order loses log10(lambda_max / a1) digits,
+ * too many for them).                                                        */
 #define MCA_PREC_FP64      0
-#define MCA_PREC_FP32      1   /* FP32 transforms (flexible GMRES absorbs the error)      */
+#define MCA_PREC_FP32      1   /* FP32 operands, FP32 MFMA                                 */
 #define MCA_PREC_BF16X3    2   /* split-BF16 (hi+lo) operands, 3 MFMA products, FP32 acc  */
+#define MCA_PREC_BF16      3   /* BF16 operands (hi only), FP32 accumulation               */
 
 /* How P^{-1} r is evaluated (both give P^{-1} of eq. (P) in exact arithmetic). */
 #define MCA_PRECOND_LITERAL  0 /* the paper's order: w = r_b - D B^{-1} r_t, z_t = M^{-1} w,
@@ -153,7 +157,8 @@ void       mca_plan_destroy(mca_plan *plan);
  * Host memory only; needs no GPU.  Errors: MCA_ERR_INVALID_ARG.             */
 mca_status mca_plan_host_eigen(const mca_plan *plan, int32_t layer, double *lambda, double *q);
 
-/* Device bytes the plan needs (Q_m, Q_m^T, Q_n, Q_n^T and the eigenvalues). */
+/* Device bytes the plan needs (Q_m, Q_m^T, Q_n, Q_n^T in FP64 and FP32, and
+ * the eigenvalues).                                                          */
 size_t     mca_plan_device_bytes(const mca_plan *plan);
 
 /* Copy the plan's data into `dev_buf` (caller-owned device memory of at least
@@ -197,6 +202,7 @@ mca_status mca_jacobian_apply(const mca_plan *plan, const double *d,
  * eigenbases: M^{-1} w <-> Q_m [(Q_m^T W Q_n) ./ mu] Q_n^T with
  *   mu_pq = lb_p lt_q / a1 + lb_p + (a2 / a1) lt_q.
  * ws: device workspace of mca_precond_workspace_bytes(plan, form, precision).
+ * precision other than MCA_PREC_FP64 requires form MCA_PRECOND_PERMODE.
  * r_* and z_* must not overlap.  Asynchronous on stream.
  * Errors: MCA_ERR_INVALID_ARG, MCA_ERR_WORKSPACE, MCA_ERR_HIP.               */
 mca_status mca_precond_apply(const mca_plan *plan, int32_t form, int32_t precision,

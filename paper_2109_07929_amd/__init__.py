@@ -10,7 +10,7 @@ from __future__ import annotations
 
 from . import binding, synth
 from .binding import (MCA_DEVICE_LINEAR, MCA_DEVICE_SINH, MCA_FLAG_INITIAL_GUESS,
-                      MCA_PREC_BF16X3, MCA_PREC_FP32, MCA_PREC_FP64, MCA_PRECOND_LITERAL,
+                      MCA_PREC_BF16, MCA_PREC_BF16X3, MCA_PREC_FP32, MCA_PREC_FP64, MCA_PRECOND_LITERAL,
                       MCA_PRECOND_NONE, MCA_PRECOND_PERMODE, MCAError, mca_geometry,
                       mca_options, mca_stats, options)
 

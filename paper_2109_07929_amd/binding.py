@@ -30,6 +30,7 @@ MCA_DEVICE_LINEAR = 1
 MCA_PREC_FP64 = 0
 MCA_PREC_FP32 = 1
 MCA_PREC_BF16X3 = 2
+MCA_PREC_BF16 = 3
 MCA_PRECOND_LITERAL = 0
 MCA_PRECOND_PERMODE = 1
 MCA_PRECOND_NONE = 2

@@ -25,9 +25,7 @@ struct DevPlan {
     const double *Qm, *QmT;   // m x m: Qm[i*m + p] = entry i of eigenvector p of G_bot
     const double *Qn, *QnT;   // n x n: Qn[j*n + q] = entry j of eigenvector q of G_top
     const double *lb, *lt;    // eigenvalues of G_bot (m) and G_top (n), ascending
-    const float *Qm32, *QmT32, *Qn32, *QnT32;           // FP32 copies
-    const uint16_t *QmH, *QmL, *QmTH, *QmTL;            // split-BF16 hi / lo parts
-    const uint16_t *QnH, *QnL, *QnTH, *QnTL;
+    const float *Qm32, *QmT32, *Qn32, *QnT32;   // FP32 copies (reduced-precision modes)
 };
 
 }  // namespace mca
@@ -101,6 +99,20 @@ struct GemmArgs {
 };
 hipError_t launch_gemm_f64(const GemmArgs &a, int epi, hipStream_t s);
 extern int gemm_variant;   // kernel variant (tuning only; 0 = default)
+
+// Per-mode preconditioner in reduced precision (gemm_lp.hip): four NT products
+// on FP32 / BF16 MFMA with the per-mode 2x2 solve in the second one.
+struct LowPrecChain {
+    int m, n;
+    double a1, a2;
+    const int *skip;
+    const float *QnT, *QmT, *Qm, *Qn;   // FP32 eigenbases
+    const double *lt, *lb;              // eigenvalues of G_top, G_bot
+    const double *rt, *rb;              // input r (FP64)
+    float *u_t, *u_b, *w_t, *w_b;       // FP32 intermediates, m*n each
+    double *zt, *zb;                    // output z (FP64)
+};
+hipError_t launch_precond_lowprec(int precision, const LowPrecChain &c, hipStream_t s);
 
 // Krylov kernels over vectors of even length len (= 2mn), 16-byte aligned.
 // partial dot products x.y -> partials[reduce_blocks(len)] (any length)

@@ -72,10 +72,12 @@ mca_status validate_options(const mca_options *o)
     if (o->max_newton < 1 || o->max_newton > MCA_MAX_NEWTON) return MCA_ERR_INVALID_ARG;
     if (o->max_krylov < 1) return MCA_ERR_INVALID_ARG;
     if (o->precision != MCA_PREC_FP64 && o->precision != MCA_PREC_FP32 &&
-        o->precision != MCA_PREC_BF16X3)
+        o->precision != MCA_PREC_BF16X3 && o->precision != MCA_PREC_BF16)
         return MCA_ERR_INVALID_ARG;
     if (o->precond != MCA_PRECOND_LITERAL && o->precond != MCA_PRECOND_PERMODE &&
         o->precond != MCA_PRECOND_NONE)
+        return MCA_ERR_INVALID_ARG;
+    if (o->precision != MCA_PREC_FP64 && o->precond == MCA_PRECOND_LITERAL)
         return MCA_ERR_INVALID_ARG;
     if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING)) return MCA_ERR_INVALID_ARG;
     return MCA_OK;
@@ -100,6 +102,7 @@ void wire_tridiag(const Wire &w, std::vector<double> &diag, std::vector<double> 
 // Layout of the plan's device block.
 struct PlanLayout {
     double *Qm, *QmT, *Qn, *QnT, *lb, *lt;
+    float *Qm32, *QmT32, *Qn32, *QnT32;
     size_t bytes;
 };
 
@@ -114,20 +117,30 @@ PlanLayout plan_layout(const mca_plan *P, void *base)
     L.QnT = c.take<double>(n * n);
     L.lb = c.take<double>(m);
     L.lt = c.take<double>(n);
+    L.Qm32 = c.take<float>(m * m);
+    L.QmT32 = c.take<float>(m * m);
+    L.Qn32 = c.take<float>(n * n);
+    L.QnT32 = c.take<float>(n * n);
     L.bytes = c.size();
     return L;
 }
 
-// Workspace of the preconditioner: up to four m x n FP64 buffers.
+// Workspace of the preconditioner: up to four m x n FP64 buffers, or four
+// m x n FP32 buffers in the reduced-precision modes.
 struct PrecondWs {
     double *b0t, *b0b, *b1t, *b1b;
+    float *f[4];
 };
 
-PrecondWs precond_layout(const mca_plan *P, Carver &c, int form)
+PrecondWs precond_layout(const mca_plan *P, Carver &c, int form, int precision = MCA_PREC_FP64)
 {
     const size_t mn = (size_t)P->geom.m * P->geom.n;
     PrecondWs w{};
     if (form == MCA_PRECOND_NONE) return w;
+    if (precision != MCA_PREC_FP64) {
+        for (auto &f : w.f) f = c.take<float>(mn);
+        return w;
+    }
     w.b0t = c.take<double>(mn);
     w.b1t = c.take<double>(mn);
     if (form == MCA_PRECOND_PERMODE) {
@@ -182,7 +195,7 @@ SolveWs solve_layout(const mca_plan *P, const mca_options *o, void *base)
     w.sn = c.take<double>(R);
     w.resid = c.take<double>(R);
     w.ctl = c.take<int>(4);
-    w.pw = precond_layout(P, c, o->precond);
+    w.pw = precond_layout(P, c, o->precond, o->precision);
     w.bytes = c.size();
     return w;
 }
@@ -271,13 +284,31 @@ struct Timing {
 };
 
 // z = P^{-1} r (eq. (P)) in the chosen evaluation form.
-mca_status precond_run(const mca_plan *P, int form, double a1, double a2, const double *rt,
-                       const double *rb, double *zt, double *zb, const PrecondWs &w,
-                       hipStream_t s, Timing *tm = nullptr, int slot = 0,
+mca_status precond_run(const mca_plan *P, int form, int precision, double a1, double a2,
+                       const double *rt, const double *rb, double *zt, double *zb,
+                       const PrecondWs &w, hipStream_t s, Timing *tm = nullptr, int slot = 0,
                        const int *skip = nullptr)
 {
     Timing off;
     if (!tm) tm = &off;
+    if (form != MCA_PRECOND_NONE && precision != MCA_PREC_FP64) {
+        const DevPlan &d = P->dev;
+        LowPrecChain c{};
+        c.m = P->geom.m;
+        c.n = P->geom.n;
+        c.a1 = a1;
+        c.a2 = a2;
+        c.skip = skip;
+        c.QnT = d.QnT32; c.QmT = d.QmT32; c.Qm = d.Qm32; c.Qn = d.Qn32;
+        c.lt = d.lt; c.lb = d.lb;
+        c.rt = rt; c.rb = rb;
+        c.u_t = w.f[0]; c.u_b = w.f[1]; c.w_t = w.f[2]; c.w_b = w.f[3];
+        c.zt = zt; c.zb = zb;
+        MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
+        MCA_TRY(launch_precond_lowprec(precision, c, s));
+        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 4, slot));
+        return MCA_OK;
+    }
     const int m = P->geom.m, n = P->geom.n;
     const size_t mn = (size_t)m * n;
     const DevPlan &d = P->dev;
@@ -369,8 +400,8 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
             double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
             double *wv = w.V + (size_t)(j + 1) * len;
             const int *skip = w.ctl;
-            mca_status st = precond_run(P, o->precond, a, a, vj, vj + mn, zj, zj + mn, w.pw, s,
-                                        tm, slot, skip);
+            mca_status st = precond_run(P, o->precond, o->precision, a, a, vj, vj + mn, zj,
+                                        zj + mn, w.pw, s, tm, slot, skip);
             if (st != MCA_OK) return st;
             // w = J z_j, fused with the partial sums of <w, v_0>
             MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
@@ -574,6 +605,14 @@ mca_status mca_plan_upload(mca_plan *P, void *dev_buf, size_t bytes, void *strea
         }
     std::memcpy(H.lb, P->lb.data(), m * sizeof(double));
     std::memcpy(H.lt, P->lt.data(), n * sizeof(double));
+    for (size_t k = 0; k < m * m; ++k) {
+        H.Qm32[k] = (float)H.Qm[k];
+        H.QmT32[k] = (float)H.QmT[k];
+    }
+    for (size_t k = 0; k < n * n; ++k) {
+        H.Qn32[k] = (float)H.Qn[k];
+        H.QnT32[k] = (float)H.QnT[k];
+    }
     MCA_TRY(hipMemcpyAsync(dev_buf, img.data(), P->dev_bytes, hipMemcpyHostToDevice, s));
     MCA_TRY(hipStreamSynchronize(s));
     PlanLayout L = plan_layout(P, dev_buf);
@@ -585,6 +624,10 @@ mca_status mca_plan_upload(mca_plan *P, void *dev_buf, size_t bytes, void *strea
     P->dev.QnT = L.QnT;
     P->dev.lb = L.lb;
     P->dev.lt = L.lt;
+    P->dev.Qm32 = L.Qm32;
+    P->dev.QmT32 = L.QmT32;
+    P->dev.Qn32 = L.Qn32;
+    P->dev.QnT32 = L.QnT32;
     return MCA_OK;
 }
 
@@ -601,9 +644,8 @@ size_t mca_workspace_bytes(const mca_plan *P, const mca_options *opts)
 size_t mca_precond_workspace_bytes(const mca_plan *P, int32_t form, int32_t precision)
 {
     if (!P) return 0;
-    (void)precision;
     Carver c(nullptr);
-    precond_layout(P, c, form);
+    precond_layout(P, c, form, precision);
     return c.size() > 0 ? c.size() : kAlign;
 }
 
@@ -634,15 +676,19 @@ mca_status mca_precond_apply(const mca_plan *P, int32_t form, int32_t precision,
     if (!P || !r_t || !r_b || !z_t || !z_b) return MCA_ERR_INVALID_ARG;
     if (form != MCA_PRECOND_LITERAL && form != MCA_PRECOND_PERMODE && form != MCA_PRECOND_NONE)
         return MCA_ERR_INVALID_ARG;
-    if (precision != MCA_PREC_FP64) return MCA_ERR_INVALID_ARG;
+    if (precision != MCA_PREC_FP64 && precision != MCA_PREC_FP32 &&
+        precision != MCA_PREC_BF16X3 && precision != MCA_PREC_BF16)
+        return MCA_ERR_INVALID_ARG;
+    if (precision != MCA_PREC_FP64 && form == MCA_PRECOND_LITERAL) return MCA_ERR_INVALID_ARG;
     if (!(std::isfinite(a1) && a1 > 0.0 && std::isfinite(a2) && a2 > 0.0))
         return MCA_ERR_INVALID_ARG;
     if (!plan_ready(P)) return MCA_ERR_WORKSPACE;
     if (form != MCA_PRECOND_NONE && (!ws || ws_bytes < mca_precond_workspace_bytes(P, form, precision)))
         return MCA_ERR_WORKSPACE;
     Carver c(ws);
-    PrecondWs w = precond_layout(P, c, form);
-    return precond_run(P, form, a1, a2, r_t, r_b, z_t, z_b, w, static_cast<hipStream_t>(stream));
+    PrecondWs w = precond_layout(P, c, form, precision);
+    return precond_run(P, form, precision, a1, a2, r_t, r_b, z_t, z_b, w,
+                       static_cast<hipStream_t>(stream));
 }
 
 mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in, double *v_t,
@@ -656,7 +702,6 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     else mca_options_default(&o);
     mca_status st = validate_options(&o);
     if (st != MCA_OK) return st;
-    if (o.precision != MCA_PREC_FP64) return MCA_ERR_INVALID_ARG;
     if (!plan_ready(P)) return MCA_ERR_WORKSPACE;
     SolveWs w = solve_layout(P, &o, ws);
     if (!ws || ws_bytes < w.bytes) return MCA_ERR_WORKSPACE;

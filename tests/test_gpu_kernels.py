@@ -156,3 +156,65 @@ def test_errors_and_validation():
         assert e.value.status == B.MCA_ERR_WORKSPACE
     finally:
         B.mca_plan_destroy(h)
+
+
+LOWPREC = [(B.MCA_PREC_FP32, 1e-4), (B.MCA_PREC_BF16X3, 1e-3), (B.MCA_PREC_BF16, 3e-2)]
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (33, 65), (64, 64), (130, 70)])
+@pytest.mark.parametrize("prec,tol", LOWPREC)
+def test_precond_lowprec_parity(m, n, prec, tol):
+    """Reduced-precision per-mode P^{-1} r against the oracle's direct solve.
+
+    Bound: FP32 transforms carry ~sqrt(K) 2^-24 relative rounding per product and
+    four products chain; split-BF16 keeps ~16 bits per operand; plain BF16 8 bits.
+    The bounds below leave a factor >= 10 over those estimates at these sizes."""
+    a1, a2 = 2.2e-5, 3e-5
+    say(f"precond lowprec {m}x{n} prec={prec}")
+    geom = synth.Geometry(m, n)
+    rt, rb = synth.vector(m, n, seed=m * 13 + n)
+    zt, zb = oracle.precond_apply(geom, a1, a2, rt, rb)
+    plan = Plan(geom)
+    gzt, gzb = plan.precond_apply(a1, a2, dev(rt), dev(rb), form=B.MCA_PRECOND_PERMODE,
+                                  precision=prec)
+    scale = max(np.abs(zt).max(), np.abs(zb).max())
+    err = max(np.abs(host(gzt) - zt).max(), np.abs(host(gzb) - zb).max()) / scale
+    say(f"  rel err {err:.3e} (tol {tol:.0e})")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [(B.MCA_PREC_FP32, 1e-2), (B.MCA_PREC_BF16X3, 5e-2),
+                                      (B.MCA_PREC_BF16, 10.0)])
+def test_precond_lowprec_residual_at_1024(prec, tol):
+    """||P z - r|| / ||r|| of the reduced-precision preconditioner at 1024 x 1024,
+    with P z from the oracle's Jacobian product at uniform slope (P(a,a) = J).
+
+    This is what flexible GMRES sees.  The inverse transform rounds the large
+    low-mode components (|x_hat| up to ||r|| / det_min ~ 1e5 ||r||) at the
+    operand precision, and P maps that error back with its largest eigenvalues,
+    so the residual is ~ eps_op x 1e5 x (a few): about 1e-3 in FP32, 1e-2 in
+    split-BF16, and above 1 in plain BF16 (a weak preconditioner at this size)."""
+    m = n = 1024
+    a = 2.2e-5
+    say(f"precond lowprec 1024^2 prec={prec}")
+    geom = synth.Geometry(m, n)
+    rt, rb = synth.vector(m, n, seed=5)
+    plan = Plan(geom)
+    gzt, gzb = plan.precond_apply(a, a, dev(rt), dev(rb), form=B.MCA_PRECOND_PERMODE,
+                                  precision=prec)
+    zt, zb = host(gzt), host(gzb)
+    pt, pb = oracle.jacobian_apply(geom, np.full((m, n), a), zt, zb)
+    rel = np.sqrt(np.sum((pt - rt) ** 2) + np.sum((pb - rb) ** 2)) / np.sqrt(
+        np.sum(rt ** 2) + np.sum(rb ** 2))
+    say(f"  ||Pz - r||/||r|| = {rel:.3e}")
+    assert rel <= tol
+
+
+def test_lowprec_needs_permode():
+    m, n = 8, 8
+    plan = Plan(synth.Geometry(m, n))
+    rt, rb = synth.vector(m, n, seed=2)
+    with pytest.raises(B.MCAError) as e:
+        plan.precond_apply(1e-5, 1e-5, dev(rt), dev(rb), form=B.MCA_PRECOND_LITERAL,
+                           precision=B.MCA_PREC_FP32)
+    assert e.value.status == B.MCA_ERR_INVALID_ARG

@@ -208,3 +208,32 @@ def test_workspace_too_small_rejected():
     status, _ = B.mca_solve(plan.handle, 16, 16, dev(cb.g_dev), dev(cb.v_in), vt, vb,
                             B.options(), small, check=False)
     assert status == B.MCA_ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("prec", [B.MCA_PREC_FP32, B.MCA_PREC_BF16X3, B.MCA_PREC_BF16])
+@pytest.mark.parametrize("m,n", [(32, 32), (70, 130)])
+def test_mixed_precision_solve_same_answer(prec, m, n):
+    """Reduced-precision preconditioner inside flexible GMRES: the Newton residual,
+    Arnoldi and least squares stay FP64, so the voltages meet the FP64 bar."""
+    say(f"mixed solve {m}x{n} prec={prec}")
+    cb = synth.crossbar(m, n, seed=7)
+    vt, vb, status, st = gpu_solve(cb, precond=B.MCA_PRECOND_PERMODE, precision=prec)
+    assert status == B.MCA_OK
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in)
+    err = rel_err(vt, vb, rt, rb)
+    say(f"  newton {st.newton_iters} krylov {list(st.krylov_history[:st.newton_iters])} err {err:.2e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("prec", [B.MCA_PREC_FP32, B.MCA_PREC_BF16X3, B.MCA_PREC_BF16])
+def test_mixed_precision_solve_1024(prec):
+    say(f"mixed solve 1024x1024 prec={prec}")
+    cb = synth.crossbar(1024, 1024, seed=0)
+    vt, vb, status, st = gpu_solve(cb, precond=B.MCA_PRECOND_PERMODE, precision=prec)
+    assert status == B.MCA_OK
+    say(f"  newton {st.newton_iters} krylov {list(st.krylov_history[:st.newton_iters])} "
+        f"relres {st.rel_residual:.2e}")
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="cg")
+    err = rel_err(vt, vb, rt, rb)
+    say(f"  err vs oracle {err:.2e}")
+    assert err <= TOL
