@@ -226,6 +226,57 @@ mca_status mca_solve(const mca_plan *plan, const double *g_dev, const double *v_
                      double *v_t, double *v_b, const mca_options *opts,
                      void *ws, size_t ws_bytes, mca_stats *stats, void *stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many crossbars, each with its own geometry (sizes may differ), solved
+ * together: every Newton / GMRES step of every crossbar runs in the same
+ * kernel launches (the Monte-Carlo use of Section IV, where many crossbars
+ * with varied devices and wires are simulated).  Each crossbar follows the
+ * same method and stopping rules as mca_solve; one that has converged or
+ * failed drops out of the launches while the others go on.
+ *
+ * Concatenated arrays: crossbar b's m_b x n_b arrays (g_dev, v_t, v_b) start
+ * at element cross_offsets[b] = sum_{c<b} m_c n_c of one device array, its
+ * drives v_in at element row_offsets[b] = sum_{c<b} m_c (see
+ * mca_batch_offsets).  Batches support form MCA_PRECOND_PERMODE with
+ * precision MCA_PREC_FP32, MCA_PREC_BF16X3 or MCA_PREC_BF16.               */
+typedef struct mca_batch mca_batch;
+
+/* Validate count geometries and build every crossbar's eigen-decompositions
+ * (host threads).  *out receives a host object freed by mca_batch_destroy.
+ * Errors: MCA_ERR_INVALID_ARG (count < 1, NULL pointer or a bad geometry). */
+mca_status mca_batch_create(int32_t count, const mca_geometry *geoms, mca_batch **out);
+void       mca_batch_destroy(mca_batch *batch);
+
+/* Offsets of the concatenated arrays (host arrays of count + 1 entries each,
+ * either may be NULL); the last entry is the total length.                */
+mca_status mca_batch_offsets(const mca_batch *batch, int64_t *cross_offsets,
+                             int64_t *row_offsets);
+
+/* Device bytes of the batch's set-up data (eigenbases in FP32 and bfloat16
+ * hi/lo planes, eigenvalues, launch tables), and their upload into
+ * caller-owned device memory (256-byte aligned, kept until the last solve).
+ * Synchronises stream.  Errors: MCA_ERR_INVALID_ARG, MCA_ERR_WORKSPACE,
+ * MCA_ERR_HIP.                                                             */
+size_t     mca_batch_device_bytes(const mca_batch *batch);
+mca_status mca_batch_upload(mca_batch *batch, void *dev_buf, size_t bytes, void *stream);
+
+/* Device workspace of mca_solve_batched with opts (NULL = PERMODE, BF16X3,
+ * other fields as mca_options_default); 0 when opts are not supported.    */
+size_t     mca_batch_workspace_bytes(const mca_batch *batch, const mca_options *opts);
+
+/* Steady state of every crossbar of the batch (as mca_solve, per crossbar).
+ * g_dev, v_in, v_t, v_b: concatenated device arrays (see above); v_t/v_b
+ * carry the initial guesses with MCA_FLAG_INITIAL_GUESS.  stats: host array
+ * of count records (may be NULL).  MCA_FLAG_TIMING is accepted and ignored.
+ * Returns MCA_OK when every crossbar converged, else the status of the first
+ * crossbar that did not (the per-crossbar outcome is in the residual
+ * history of stats).  Synchronises stream.
+ * Errors: MCA_ERR_INVALID_ARG, MCA_ERR_WORKSPACE (too small, or batch not
+ * uploaded), MCA_ERR_NONFINITE, MCA_ERR_NOT_CONVERGED, MCA_ERR_HIP.       */
+mca_status mca_solve_batched(const mca_batch *batch, const double *g_dev, const double *v_in,
+                             double *v_t, double *v_b, const mca_options *opts,
+                             void *ws, size_t ws_bytes, mca_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,7 @@ from .binding import (MCA_DEVICE_LINEAR, MCA_DEVICE_SINH, MCA_FLAG_INITIAL_GUESS
                       MCA_PRECOND_NONE, MCA_PRECOND_PERMODE, MCAError, mca_geometry,
                       mca_options, mca_stats, options)
 
-__all__ = ["Plan", "binding", "synth", "options", "MCAError", "mca_geometry", "mca_options",
+__all__ = ["Plan", "Batch", "binding", "synth", "options", "MCAError", "mca_geometry", "mca_options",
            "mca_stats"]
 
 
@@ -98,4 +98,79 @@ class Plan:
         ws = self.workspace(opts)
         status, stats = binding.mca_solve(self.handle, self.m, self.n, g_dev, v_in, v_t, v_b,
                                           opts, ws, check=check)
+        return v_t, v_b, status, stats
+
+
+class Batch:
+    """Many crossbars (sizes may differ) solved together on the current GPU.
+
+    Arrays are concatenated float64 GPU tensors: crossbar b's m x n arrays at
+    ``cross[b]:cross[b+1]``, its drives at ``rows[b]:rows[b+1]``.
+    """
+
+    def __init__(self, geoms, device="cuda"):
+        import torch
+        self.geoms = list(geoms)
+        self.count = len(self.geoms)
+        self.device = torch.device(device)
+        self.handle = binding.mca_batch_create([binding.geometry_from(g) for g in self.geoms])
+        self.cross, self.rows = binding.mca_batch_offsets(self.handle, self.count)
+        nbytes = binding.mca_batch_device_bytes(self.handle)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        binding.mca_batch_upload(self.handle, self.buf)
+        self._ws = None
+        self._ws_key = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                binding.mca_batch_destroy(h)
+            except Exception:   # interpreter shutdown: the library may be gone
+                pass
+            self.handle = None
+
+    @property
+    def total(self):
+        return int(self.cross[-1])
+
+    def concat(self, arrays):
+        """One contiguous float64 GPU tensor from per-crossbar arrays."""
+        import torch
+        return torch.cat([torch.as_tensor(a, dtype=torch.float64).reshape(-1) for a in arrays]).to(
+            self.device).contiguous()
+
+    def split(self, flat):
+        """Per-crossbar (m, n) views of a concatenated array."""
+        return [flat[int(self.cross[b]):int(self.cross[b + 1])].view(self.geoms[b].m, self.geoms[b].n)
+                for b in range(self.count)]
+
+    def workspace(self, opts):
+        import torch
+        nbytes = binding.mca_batch_workspace_bytes(self.handle, opts)
+        if nbytes == 0:
+            raise MCAError(binding.MCA_ERR_INVALID_ARG, "mca_batch_workspace_bytes")
+        if self._ws is None or self._ws_key != nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._ws_key = nbytes
+        return self._ws
+
+    def solve(self, g_dev, v_in, opts=None, guess=None, out=None, check=True):
+        """(v_t, v_b, status, [stats]) over the concatenated arrays."""
+        import torch
+        if opts is None:
+            opts = options(precond=MCA_PRECOND_PERMODE, precision=MCA_PREC_BF16X3)
+        if out is None:
+            v_t = torch.zeros(self.total, dtype=torch.float64, device=self.device)
+            v_b = torch.zeros(self.total, dtype=torch.float64, device=self.device)
+        else:
+            v_t, v_b = out
+        if guess is not None:
+            v_t.copy_(guess[0])
+            v_b.copy_(guess[1])
+            opts.flags |= MCA_FLAG_INITIAL_GUESS
+        ws = self.workspace(opts)
+        status, stats = binding.mca_solve_batched(self.handle, self.count, self.total,
+                                                  int(self.rows[-1]), g_dev, v_in, v_t, v_b,
+                                                  opts, ws, check=check)
         return v_t, v_b, status, stats

@@ -51,6 +51,8 @@ ABI_SYMBOLS = (
     "mca_plan_device_bytes", "mca_plan_upload", "mca_workspace_bytes",
     "mca_precond_workspace_bytes", "mca_residual", "mca_jacobian_apply",
     "mca_precond_apply", "mca_solve",
+    "mca_batch_create", "mca_batch_destroy", "mca_batch_offsets", "mca_batch_device_bytes",
+    "mca_batch_upload", "mca_batch_workspace_bytes", "mca_solve_batched",
 )
 
 
@@ -131,6 +133,21 @@ def lib():
     L.mca_solve.argtypes = [vp, vp, vp, vp, vp, C.POINTER(mca_options), vp, sz,
                             C.POINTER(mca_stats), vp]
     L.mca_solve.restype = i32
+    L.mca_batch_create.argtypes = [i32, C.POINTER(mca_geometry), PP]
+    L.mca_batch_create.restype = i32
+    L.mca_batch_destroy.argtypes = [vp]
+    L.mca_batch_destroy.restype = None
+    L.mca_batch_offsets.argtypes = [vp, vp, vp]
+    L.mca_batch_offsets.restype = i32
+    L.mca_batch_device_bytes.argtypes = [vp]
+    L.mca_batch_device_bytes.restype = sz
+    L.mca_batch_upload.argtypes = [vp, vp, sz, vp]
+    L.mca_batch_upload.restype = i32
+    L.mca_batch_workspace_bytes.argtypes = [vp, C.POINTER(mca_options)]
+    L.mca_batch_workspace_bytes.restype = sz
+    L.mca_solve_batched.argtypes = [vp, vp, vp, vp, vp, C.POINTER(mca_options), vp, sz,
+                                    C.POINTER(mca_stats), vp]
+    L.mca_solve_batched.restype = i32
     _lib = L
     return L
 
@@ -282,3 +299,51 @@ def mca_solve(plan, m, n, g_dev, v_in, v_t, v_b, opts: mca_options | None, ws, s
     if check:
         _check(status, "mca_solve")
     return status, st
+
+
+# ---------------------------------------------------------------- batches
+def mca_batch_create(geoms) -> C.c_void_p:
+    arr = (mca_geometry * len(geoms))(*geoms)
+    out = C.c_void_p()
+    _check(lib().mca_batch_create(len(geoms), arr, C.byref(out)), "mca_batch_create")
+    return out
+
+
+def mca_batch_destroy(batch) -> None:
+    lib().mca_batch_destroy(batch)
+
+
+def mca_batch_offsets(batch, count: int):
+    """(cross_offsets, row_offsets): int64 arrays of count + 1 entries."""
+    cross = np.zeros(count + 1, dtype=np.int64)
+    rows = np.zeros(count + 1, dtype=np.int64)
+    _check(lib().mca_batch_offsets(batch, cross.ctypes.data_as(C.c_void_p),
+                                   rows.ctypes.data_as(C.c_void_p)), "mca_batch_offsets")
+    return cross, rows
+
+
+def mca_batch_device_bytes(batch) -> int:
+    return int(lib().mca_batch_device_bytes(batch))
+
+
+def mca_batch_upload(batch, dev_buf, stream=None) -> None:
+    p, nbytes = _buf(dev_buf, "dev_buf")
+    _check(lib().mca_batch_upload(batch, p, nbytes, _stream(stream)), "mca_batch_upload")
+
+
+def mca_batch_workspace_bytes(batch, opts: mca_options | None = None) -> int:
+    return int(lib().mca_batch_workspace_bytes(batch, C.byref(opts) if opts is not None else None))
+
+
+def mca_solve_batched(batch, count, total, rows, g_dev, v_in, v_t, v_b, opts, ws, stream=None,
+                      check: bool = True):
+    """Returns (status, [mca_stats] * count); total = sum m n, rows = sum m."""
+    wp, wbytes = _buf(ws, "ws")
+    st = (mca_stats * count)()
+    status = lib().mca_solve_batched(batch, _ptr(g_dev, total, "g_dev"), _ptr(v_in, rows, "v_in"),
+                                     _ptr(v_t, total, "v_t"), _ptr(v_b, total, "v_b"),
+                                     C.byref(opts) if opts is not None else None, wp, wbytes,
+                                     st, _stream(stream))
+    if check:
+        _check(status, "mca_solve_batched")
+    return status, list(st)

@@ -1,0 +1,1206 @@
+// batch.hip -- many crossbars of different sizes solved together (Monte-Carlo
+// device variation): every Newton / flexible-GMRES step of every crossbar runs
+// in the same kernel launches.
+//
+// Layout: crossbar b's m*n arrays start at element ox_b = sum_{c<b} m_c n_c of
+// the concatenated arrays; its Krylov vectors (top layer then bottom layer,
+// 2 m n values) start at 2 ox_b of each batch-wide vector; its drives at
+// orow_b = sum_{c<b} m_c.  Streaming kernels run over a block table: block t
+// covers crosspoints [c*CH, (c+1)*CH) of crossbar table[t].x (c = table[t].y),
+// so per-block partial sums of one crossbar are contiguous and every block of
+// that crossbar reduces them in the same fixed order.
+//
+// Control lives on the device: one state record per crossbar (Newton status,
+// tolerances, line-search step, GMRES cycle flags), updated by one-thread-per-
+// crossbar kernels; kernels skip crossbars whose flag says so.  The host only
+// reads counters (crossbars still active, still in a GMRES cycle, still in the
+// line search) to decide how many launches to enqueue.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "device_common.h"
+
+namespace mca {
+namespace {
+
+using dev::block_sum;
+using dev::TPB;
+using dev::wire_apply;
+
+constexpr int CH = 2048;   // crosspoints per block of the streaming kernels
+
+struct BInst {             // device descriptor of one crossbar
+    int m, n, linear, blk0, nblk, pad;
+    Wire top, bot;
+    double v0, g_src;
+    long long ox, orow;
+};
+
+struct BState {            // device control record of one crossbar
+    double ynorm, fnorm, dsum, a, beta, abs_tol, step, fn_trial, ds_trial;
+    int active;            // Newton still iterating
+    int status;            // final mca_status
+    int newton, krylov, backtracks, restarts;
+    int gm_todo;           // in the current Newton step's GMRES solve
+    int restart;           // the GMRES cycle ended unconverged: restart
+    int first;             // next X update overwrites (first cycle of the step)
+    int upd;               // columns of the last cycle to add into X
+    int kry_step;          // GMRES iterations in this Newton step
+    int ls_todo, accept, halvings;
+};
+constexpr int kStateInts = sizeof(BState) / sizeof(int);
+static_assert(sizeof(BState) % sizeof(double) == 0, "state record");
+
+__device__ __forceinline__ bool on(const int *flag, int b)
+{
+    return flag == nullptr || flag[(size_t)b * kStateInts] != 0;
+}
+
+// crossbar b, crosspoint range of block t; false when the block has nothing to do
+__device__ __forceinline__ bool block_range(const BInst *__restrict__ I, const int2 *__restrict__ bt,
+                                            const int *flag, int &b, int &k0, int &k1)
+{
+    const int2 e = bt[blockIdx.x];
+    b = e.x;
+    const int mn = I[b].m * I[b].n;
+    k0 = e.y * CH;
+    k1 = min(k0 + CH, mn);
+    return on(flag, b);
+}
+
+// Sum of crossbar b's per-block partials (component c of nc), fixed order.
+__device__ __forceinline__ double inst_sum(const BInst &I, const double *__restrict__ p, int nc, int c)
+{
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < I.nblk; t += TPB) v[0] += p[(size_t)(I.blk0 + t) * nc + c];
+    block_sum<1>(v);
+    return v[0];
+}
+
+// --------------------------------------------------------------- streaming
+__global__ __launch_bounds__(TPB) void bk_residual(
+    const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *flag,
+    const double *__restrict__ g_dev, const double *__restrict__ v_in,
+    const double *__restrict__ V, double *__restrict__ F, double *__restrict__ D,
+    double *__restrict__ part)
+{
+    int b, k0, k1;
+    if (!block_range(I, bt, flag, b, k0, k1)) return;
+    const BInst in = I[b];
+    const int m = in.m, n = in.n;
+    const size_t mn = (size_t)m * n;
+    const double *vt = V + 2 * in.ox, *vb = vt + mn;
+    double *ft = F + 2 * in.ox, *fb = ft + mn;
+    double acc[2] = {0.0, 0.0};
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+        const int i = k / n, j = k - i * n;
+        const double t = vt[k], bv = vb[k];
+        double st = (j > 0) ? in.top.g * (t - vt[k - 1]) : in.top.end0 * (t - v_in[in.orow + i]);
+        st += (j + 1 < n) ? in.top.g * (t - vt[k + 1]) : in.top.end1 * t;
+        const double sb = wire_apply(in.bot, i, bv, (i > 0) ? vb[k - n] : 0.0,
+                                     (i + 1 < m) ? vb[k + n] : 0.0);
+        const double u = t - bv, g = g_dev[in.ox + k];
+        double cur, slope;
+        if (in.linear) {
+            cur = g * u;
+            slope = g;
+        } else {
+            const double x = u / in.v0;
+            cur = g * in.v0 * sinh(x);
+            slope = g * cosh(x);
+        }
+        const double f1 = st + cur, f2 = sb - cur;
+        ft[k] = f1;
+        fb[k] = f2;
+        D[in.ox + k] = slope;
+        acc[0] += f1 * f1 + f2 * f2;
+        acc[1] += slope;
+    }
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) {
+        part[2 * (size_t)blockIdx.x] = acc[0];
+        part[2 * (size_t)blockIdx.x + 1] = acc[1];
+    }
+}
+
+// J x at crosspoint k of a crossbar (eq. (J)): (top row, bottom row)
+__device__ __forceinline__ void jac_point(const BInst &in, const double *__restrict__ xt,
+                                          const double *__restrict__ xb, double d, int k,
+                                          double &y1, double &y2)
+{
+    const int m = in.m, n = in.n;
+    const int i = k / n, j = k - i * n;
+    const double t = xt[k], bv = xb[k];
+    const double st = wire_apply(in.top, j, t, (j > 0) ? xt[k - 1] : 0.0,
+                                 (j + 1 < n) ? xt[k + 1] : 0.0);
+    const double sb = wire_apply(in.bot, i, bv, (i > 0) ? xb[k - n] : 0.0,
+                                 (i + 1 < m) ? xb[k + n] : 0.0);
+    const double c = d * (t - bv);
+    y1 = st + c;
+    y2 = sb - c;
+}
+
+// y = J x per crossbar; with v0, per-block partials of <y, v0>.
+__global__ __launch_bounds__(TPB) void bk_jacobian(
+    const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *__restrict__ ctl,
+    const double *__restrict__ D, const double *__restrict__ X, double *__restrict__ Y,
+    const double *__restrict__ v0, double *__restrict__ part)
+{
+    int b, k0, k1;
+    if (!block_range(I, bt, nullptr, b, k0, k1)) return;
+    if (ctl[4 * b]) return;
+    const BInst in = I[b];
+    const size_t mn = (size_t)in.m * in.n;
+    const double *xt = X + 2 * in.ox, *xb = xt + mn;
+    double *yt = Y + 2 * in.ox, *yb = yt + mn;
+    const double *d = D + in.ox;
+    double acc[1] = {0.0};
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+        double y1, y2;
+        jac_point(in, xt, xb, d[k], k, y1, y2);
+        yt[k] = y1;
+        yb[k] = y2;
+        acc[0] += y1 * v0[2 * in.ox + k] + y2 * v0[2 * in.ox + mn + k];
+    }
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// GMRES restart of the flagged crossbars: r = -(F + J X) into R, with
+// per-block partials of ||r||^2.
+__global__ __launch_bounds__(TPB) void bk_restart_residual(
+    const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *flag,
+    const double *__restrict__ D, const double *__restrict__ X, const double *__restrict__ F,
+    double *__restrict__ Rv, double *__restrict__ part)
+{
+    int b, k0, k1;
+    if (!block_range(I, bt, flag, b, k0, k1)) return;
+    const BInst in = I[b];
+    const size_t mn = (size_t)in.m * in.n, base = 2 * in.ox;
+    const double *xt = X + base, *xb = xt + mn;
+    const double *d = D + in.ox;
+    double acc[1] = {0.0};
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+        double y1, y2;
+        jac_point(in, xt, xb, d[k], k, y1, y2);
+        const double r1 = -(F[base + k] + y1), r2 = -(F[base + mn + k] + y2);
+        Rv[base + k] = r1;
+        Rv[base + mn + k] = r2;
+        acc[0] += r1 * r1 + r2 * r2;
+    }
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// One MGS step of every running crossbar: h = <w, v_prev> (from pin),
+// w -= h v_prev, partial <w, v_next> (or ||w||^2).  H is per crossbar,
+// column-major with leading dimension ldh; h goes to H_b[col][row].
+__global__ __launch_bounds__(TPB) void bk_mgs_step(
+    const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *__restrict__ ctl,
+    double *__restrict__ W, const double *__restrict__ Vp, const double *__restrict__ Vn,
+    const double *__restrict__ pin, double *__restrict__ pout, double *__restrict__ H, int ldh,
+    int hsize, int col, int row)
+{
+    int b, k0, k1;
+    if (!block_range(I, bt, nullptr, b, k0, k1)) return;
+    if (ctl[4 * b]) return;
+    const BInst in = I[b];
+    const size_t mn = (size_t)in.m * in.n, base = 2 * in.ox;
+    const double h = inst_sum(in, pin, 1, 0);
+    if (k0 == 0 && threadIdx.x == 0) H[(size_t)b * hsize + (size_t)col * ldh + row] = h;
+    double acc[1] = {0.0};
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            const size_t e = base + l * mn + k;
+            const double x = W[e] - h * Vp[e];
+            W[e] = x;
+            acc[0] += x * (Vn ? Vn[e] : x);
+        }
+    }
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) pout[blockIdx.x] = acc[0];
+}
+
+__global__ __launch_bounds__(TPB) void bk_normalize(
+    const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *__restrict__ ctl,
+    double *__restrict__ W, const double *__restrict__ pin, double *__restrict__ H, int ldh,
+    int hsize, int col, int row)
+{
+    int b, k0, k1;
+    if (!block_range(I, bt, nullptr, b, k0, k1)) return;
+    if (ctl[4 * b]) return;
+    const BInst in = I[b];
+    const size_t mn = (size_t)in.m * in.n, base = 2 * in.ox;
+    const double nrm = sqrt(inst_sum(in, pin, 1, 0));
+    if (k0 == 0 && threadIdx.x == 0) H[(size_t)b * hsize + (size_t)col * ldh + row] = nrm;
+    if (!(nrm > 0.0)) return;
+    const double inv = 1.0 / nrm;
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+        W[base + k] *= inv;
+        W[base + mn + k] *= inv;
+    }
+}
+
+// dst = alpha_b * src (+ beta * src2), per crossbar scalars from the state
+// record (field offset in doubles), for crossbars whose flag is set.
+__global__ __launch_bounds__(TPB) void bk_axpy(
+    const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *flag,
+    const BState *__restrict__ S, int mode, const double *__restrict__ x,
+    const double *__restrict__ y, double *__restrict__ out)
+{
+    int b, k0, k1;
+    if (!block_range(I, bt, flag, b, k0, k1)) return;
+    const BInst in = I[b];
+    const size_t mn = (size_t)in.m * in.n, base = 2 * in.ox;
+    const BState s = S[b];
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            const size_t e = base + l * mn + k;
+            double v;
+            switch (mode) {
+            case 0: v = -x[e] / s.beta; break;            // v0 = -F / beta
+            case 1: v = x[e] + s.step * y[e]; break;       // trial = V + step X
+            case 2: v = -(x[e] + y[e]); break;             // r = -(F + J X)
+            case 3: v = x[e] / s.beta; break;              // v0 = r / beta
+            default: v = x[e]; break;                      // copy
+            }
+            out[e] = v;
+        }
+    }
+}
+
+// D copy for accepted crossbars (m n values per crossbar)
+__global__ __launch_bounds__(TPB) void bk_copy_cross(
+    const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *flag,
+    const double *__restrict__ src, double *__restrict__ dst)
+{
+    int b, k0, k1;
+    if (!block_range(I, bt, flag, b, k0, k1)) return;
+    const size_t ox = I[b].ox;
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) dst[ox + k] = src[ox + k];
+}
+
+// X (+)= sum_{i < upd_b} y_b[i] Z_i for crossbars with upd_b > 0 or first_b set
+__global__ __launch_bounds__(TPB) void bk_update(
+    const BInst *__restrict__ I, const int2 *__restrict__ bt, const BState *__restrict__ S,
+    const double *__restrict__ Z, size_t zstride, const double *__restrict__ Y, int R,
+    double *__restrict__ X)
+{
+    int b, k0, k1;
+    if (!block_range(I, bt, nullptr, b, k0, k1)) return;
+    const int k = S[b].upd;
+    const int overwrite = S[b].first;   // first cycle of a Newton step (k = 0 writes zeros)
+    if (k <= 0 && !overwrite) return;
+    const BInst in = I[b];
+    const size_t mn = (size_t)in.m * in.n, base = 2 * in.ox;
+    const double *y = Y + (size_t)b * R;
+    for (int kk = k0 + threadIdx.x; kk < k1; kk += TPB) {
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            const size_t e = base + l * mn + kk;
+            double s = overwrite ? 0.0 : X[e];
+            for (int v = 0; v < k; ++v) s += y[v] * Z[(size_t)v * zstride + e];
+            X[e] = s;
+        }
+    }
+}
+
+// scatter the iterate into the caller's v_t / v_b, or gather a guess from them
+__global__ __launch_bounds__(TPB) void bk_user_io(const BInst *__restrict__ I,
+                                                  const int2 *__restrict__ bt,
+                                                  const BState *__restrict__ S, double *V,
+                                                  double *vt, double *vb, int to_user)
+{
+    int b, k0, k1;
+    if (!block_range(I, bt, nullptr, b, k0, k1)) return;
+    const BInst in = I[b];
+    const size_t mn = (size_t)in.m * in.n;
+    const bool zero = to_user && S[b].ynorm == 0.0;
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+        if (to_user) {
+            vt[in.ox + k] = zero ? 0.0 : V[2 * in.ox + k];
+            vb[in.ox + k] = zero ? 0.0 : V[2 * in.ox + mn + k];
+        } else {
+            V[2 * in.ox + k] = vt[in.ox + k];
+            V[2 * in.ox + mn + k] = vb[in.ox + k];
+        }
+    }
+}
+
+// ------------------------------------------------------- per-crossbar sums
+// One block per crossbar: sums of its block partials into state fields.
+// what: 0 = (fnorm, dsum) from residual partials, 1 = (fn_trial, ds_trial),
+//       2 = beta from <r, r> partials.
+__global__ __launch_bounds__(TPB) void bk_inst_norms(const BInst *__restrict__ I, int count,
+                                                     const int *flag,
+                                                     const double *__restrict__ part, int what,
+                                                     BState *__restrict__ S)
+{
+    const int b = blockIdx.x;
+    if (b >= count || !on(flag, b)) return;
+    const BInst in = I[b];
+    if (what == 2) {
+        const double s = inst_sum(in, part, 1, 0);
+        if (threadIdx.x == 0) S[b].beta = sqrt(s);
+        return;
+    }
+    const double f2 = inst_sum(in, part, 2, 0);
+    const double ds = inst_sum(in, part, 2, 1);
+    if (threadIdx.x == 0) {
+        if (what == 0) {
+            S[b].fnorm = sqrt(f2);
+            S[b].dsum = ds;
+        } else {
+            S[b].fn_trial = sqrt(f2);
+            S[b].ds_trial = ds;
+        }
+    }
+}
+
+// ||Y_b|| = g_src ||v_in_b||; state initialisation
+__global__ __launch_bounds__(TPB) void bk_init(const BInst *__restrict__ I, int count,
+                                               const double *__restrict__ v_in,
+                                               BState *__restrict__ S)
+{
+    const int b = blockIdx.x;
+    if (b >= count) return;
+    const BInst in = I[b];
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < in.m; i += TPB) {
+        const double x = v_in[in.orow + i];
+        v[0] += x * x;
+    }
+    block_sum<1>(v);
+    if (threadIdx.x == 0) {
+        BState s{};
+        s.ynorm = in.g_src * sqrt(v[0]);
+        if (!isfinite(s.ynorm)) {
+            s.status = MCA_ERR_NONFINITE;
+        } else if (s.ynorm == 0.0) {
+            s.status = MCA_OK;   // no drive: V = 0 solves F = 0 exactly
+        } else {
+            s.active = 1;
+            s.status = MCA_ERR_NOT_CONVERGED;
+        }
+        S[b] = s;
+    }
+}
+
+// Newton step k begins: convergence test, history, GMRES set-up.
+__global__ void bk_newton_begin(const BInst *__restrict__ I, int count, BState *__restrict__ S,
+                                int k, int max_newton, double tol, double gtol,
+                                double *__restrict__ rhist, int *__restrict__ counter)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    int act = 0;
+    if (b < count) {
+        BState &s = S[b];
+        if (s.active) {
+            const double rel = s.ynorm > 0.0 ? s.fnorm / s.ynorm : 0.0;
+            rhist[(size_t)b * (MCA_MAX_NEWTON + 1) + k] = rel;
+            if (!isfinite(s.fnorm) || !isfinite(s.dsum)) {
+                s.active = 0;
+                s.status = MCA_ERR_NONFINITE;
+            } else if (s.fnorm <= tol * s.ynorm) {
+                s.active = 0;
+                s.status = MCA_OK;
+            } else if (k >= max_newton) {
+                s.active = 0;
+                s.status = MCA_ERR_NOT_CONVERGED;
+            } else {
+                s.a = s.dsum / ((double)I[b].m * I[b].n);
+                s.beta = s.fnorm;
+                s.abs_tol = gtol * s.fnorm;
+                s.gm_todo = 1;
+                s.first = 1;
+                s.kry_step = 0;
+                s.restart = 0;
+                s.upd = 0;
+            }
+        }
+        act = s.active;
+    }
+    // count in a fixed order: one block of up to 1024 threads per launch
+    __shared__ int sh[1024];
+    sh[threadIdx.x] = act;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int t = 0; t < (int)blockDim.x; ++t) c += sh[t];
+        counter[blockIdx.x] = c;
+    }
+}
+
+// sum of per-block counters (one thread)
+__global__ void bk_sum_counters(const int *__restrict__ c, int n, int *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int s = 0;
+    for (int i = 0; i < n; ++i) s += c[i];
+    out[0] = s;
+}
+
+// GMRES cycle start for crossbars in their Newton step's GMRES solve
+__global__ void bk_cycle_init(int count, BState *__restrict__ S, int *__restrict__ ctl,
+                              double *__restrict__ g, int R, int max_krylov)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    BState &s = S[b];
+    s.restart = 0;
+    const bool run = s.gm_todo && s.kry_step < max_krylov;
+    ctl[4 * b + 0] = run ? 0 : 1;
+    ctl[4 * b + 1] = 0;
+    ctl[4 * b + 2] = CYCLE_RUNNING;
+    ctl[4 * b + 3] = run ? (max_krylov - s.kry_step) : 0;   // iterations allowed
+    double *gb = g + (size_t)b * (R + 1);
+    for (int i = 0; i <= R; ++i) gb[i] = (i == 0) ? s.beta : 0.0;
+}
+
+// Givens rotations of Hessenberg column j, per running crossbar.
+__global__ void bk_givens(int count, const BState *__restrict__ S, double *__restrict__ H,
+                          int ldh, int hsize, int j, double *__restrict__ g,
+                          double *__restrict__ cs, double *__restrict__ sn, int R,
+                          int *__restrict__ ctl, int *__restrict__ counter)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    int running = 0;
+    if (b < count && !ctl[4 * b]) {
+        int *c = ctl + 4 * b;
+        double *h = H + (size_t)b * hsize + (size_t)j * ldh;
+        double *gb = g + (size_t)b * (R + 1), *cb = cs + (size_t)b * R, *sb = sn + (size_t)b * R;
+        bool bad = false;
+        for (int i = 0; i <= j + 1; ++i) bad = bad || !isfinite(h[i]);
+        if (bad) {
+            c[0] = 1;
+            c[2] = CYCLE_NONFINITE;
+        } else {
+            for (int i = 0; i < j; ++i) {
+                const double t = cb[i] * h[i] + sb[i] * h[i + 1];
+                h[i + 1] = -sb[i] * h[i] + cb[i] * h[i + 1];
+                h[i] = t;
+            }
+            const double hn = h[j + 1];
+            const double r = hypot(h[j], hn);
+            if (r == 0.0) {
+                c[0] = 1;
+                c[2] = CYCLE_BREAKDOWN;
+            } else {
+                cb[j] = h[j] / r;
+                sb[j] = hn / r;
+                h[j] = r;
+                h[j + 1] = 0.0;
+                gb[j + 1] = -sb[j] * gb[j];
+                gb[j] = cb[j] * gb[j];
+                c[1] = j + 1;
+                if (fabs(gb[j + 1]) <= S[b].abs_tol) {
+                    c[0] = 1;
+                    c[2] = CYCLE_CONVERGED;
+                } else if (j + 1 >= c[3]) {
+                    c[0] = 1;   // iteration budget of this Newton step spent
+                }
+            }
+        }
+        running = c[0] ? 0 : 1;
+    }
+    __shared__ int sh[1024];
+    sh[threadIdx.x] = running;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int t = 0; t < (int)blockDim.x; ++t) s += sh[t];
+        counter[blockIdx.x] = s;
+    }
+}
+
+// End of a GMRES cycle: least squares, bookkeeping, restart decision.
+__global__ void bk_cycle_end(int count, BState *__restrict__ S, const double *__restrict__ H,
+                             int ldh, int hsize, const double *__restrict__ g, int R,
+                             const int *__restrict__ ctl, double *__restrict__ Y, int max_krylov,
+                             int *__restrict__ counter)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    int again = 0;
+    if (b < count) {
+        BState &s = S[b];
+        s.upd = 0;
+        if (s.gm_todo) {
+            const int *c = ctl + 4 * b;
+            const int k = c[1];
+            const double *Hb = H + (size_t)b * hsize;
+            const double *gb = g + (size_t)b * (R + 1);
+            double *y = Y + (size_t)b * R;
+            for (int i = k - 1; i >= 0; --i) {
+                double t = gb[i];
+                for (int cc = i + 1; cc < k; ++cc) t -= Hb[(size_t)cc * ldh + i] * y[cc];
+                y[i] = t / Hb[(size_t)i * ldh + i];
+            }
+            s.upd = k;
+            s.kry_step += k;
+            s.krylov += k;
+            if (c[2] == CYCLE_NONFINITE) {
+                s.gm_todo = 0;
+                s.active = 0;
+                s.status = MCA_ERR_NONFINITE;
+                s.upd = 0;
+                s.first = 0;
+            } else if (c[2] == CYCLE_CONVERGED || c[2] == CYCLE_BREAKDOWN || k == 0 ||
+                       s.kry_step >= max_krylov) {
+                s.gm_todo = 0;
+            } else {
+                s.restart = 1;
+                s.restarts += 1;
+                again = 1;
+            }
+        }
+    }
+    __shared__ int sh[1024];
+    sh[threadIdx.x] = again;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) t += sh[i];
+        counter[blockIdx.x] = t;
+    }
+}
+
+// after the X update of a cycle: later cycles of the Newton step accumulate
+__global__ void bk_after_update(int count, BState *__restrict__ S)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    S[b].first = 0;
+    S[b].upd = 0;
+}
+
+// restart: with beta = ||r|| of the new residual, stop (converged or not
+// finite) or keep the restart flag for the scaling v_0 = r / beta
+__global__ void bk_restart_check(int count, BState *__restrict__ S)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    BState &s = S[b];
+    if (!s.restart) return;
+    if (!isfinite(s.beta)) {
+        s.gm_todo = 0;
+        s.active = 0;
+        s.status = MCA_ERR_NONFINITE;
+        s.restart = 0;
+    } else if (s.beta <= s.abs_tol) {
+        s.gm_todo = 0;
+        s.restart = 0;
+    }
+}
+
+__global__ void bk_ls_init(int count, BState *__restrict__ S, int *__restrict__ khist, int k)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    BState &s = S[b];
+    s.ls_todo = s.active;
+    s.step = 1.0;
+    s.halvings = 0;
+    s.accept = 0;
+    if (s.active) khist[(size_t)b * MCA_MAX_NEWTON + k] = s.kry_step;
+}
+
+// damped update: accept when ||F(V + s X)|| <= (1 - 1e-4 s) ||F(V)||
+__global__ void bk_ls_check(int count, BState *__restrict__ S, int *__restrict__ counter)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    int todo = 0;
+    if (b < count) {
+        BState &s = S[b];
+        if (s.ls_todo) {
+            const bool fin = isfinite(s.fn_trial) && isfinite(s.ds_trial);
+            if (fin && s.fn_trial <= (1.0 - 1e-4 * s.step) * s.fnorm) {
+                s.ls_todo = 0;
+                s.accept = 1;
+            } else if (s.halvings >= 30) {
+                s.ls_todo = 0;
+                s.accept = fin && s.fn_trial < s.fnorm;
+            } else {
+                s.step *= 0.5;
+                s.halvings += 1;
+                s.backtracks += 1;
+            }
+        }
+        todo = s.ls_todo;
+    }
+    __shared__ int sh[1024];
+    sh[threadIdx.x] = todo;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) t += sh[i];
+        counter[blockIdx.x] = t;
+    }
+}
+
+__global__ void bk_ls_finish(int count, BState *__restrict__ S)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    BState &s = S[b];
+    if (!s.active) return;
+    if (s.accept) {
+        s.fnorm = s.fn_trial;
+        s.dsum = s.ds_trial;
+        s.newton += 1;
+    } else {
+        // no decrease: the rounding floor (accepted below 1e-12 ||Y||) or a failure
+        s.active = 0;
+        s.status = (s.fnorm <= 1e-12 * s.ynorm) ? MCA_OK : MCA_ERR_NOT_CONVERGED;
+    }
+}
+
+int cblocks(int count) { return (count + 1023) / 1024; }
+
+}  // namespace
+}  // namespace mca
+
+// ====================================================================== host
+struct mca_batch {
+    std::vector<mca_geometry> geoms;
+    std::vector<mca_plan *> plans;          // host eigen data per crossbar
+    std::vector<long long> ox, orow;        // offsets (count + 1 entries)
+    std::vector<int2> btab;                 // block table
+    std::vector<mca::BInst> inst;
+    size_t len = 0;                         // sum 2 m n
+    size_t dev_bytes = 0;
+    void *dev_buf = nullptr;
+    // device pointers (inside dev_buf)
+    mca::BInst *d_inst = nullptr;
+    int2 *d_btab = nullptr;
+    mca::LpDesc *d_desc[2][4] = {};         // [fp32 | bf16][step]
+    int4 *d_tiles[4] = {};
+    int ntiles[4] = {};
+};
+
+namespace mca {
+namespace {
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct BCarver {
+    char *base;
+    size_t off = 0;
+    explicit BCarver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count)
+    {
+        off = align256(off);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t size() const { return align256(off); }
+};
+
+// device block of a batch: descriptors, tables and every crossbar's eigenbases
+struct BatchLayout {
+    BInst *inst;
+    int2 *btab;
+    LpDesc *desc[2][4];
+    int4 *tiles[4];
+    std::vector<float *> q32[4];                  // per crossbar: QnT, QmT, Qm, Qn
+    std::vector<uint16_t *> qh[4], ql[4];
+    std::vector<double *> lt, lb;
+    size_t bytes;
+};
+
+const int kLp = 64;   // tile edge of the reduced-precision products
+
+BatchLayout batch_layout(const mca_batch *B, void *base)
+{
+    BCarver c(base);
+    BatchLayout L;
+    const size_t cnt = B->geoms.size();
+    L.inst = c.take<BInst>(cnt);
+    L.btab = c.take<int2>(B->btab.size());
+    for (auto &p : L.desc)
+        for (auto &d : p) d = c.take<LpDesc>(cnt);
+    for (int s = 0; s < 4; ++s) L.tiles[s] = c.take<int4>(B->ntiles[s]);
+    for (int s = 0; s < 4; ++s) {
+        L.q32[s].resize(cnt);
+        L.qh[s].resize(cnt);
+        L.ql[s].resize(cnt);
+    }
+    L.lt.resize(cnt);
+    L.lb.resize(cnt);
+    for (size_t b = 0; b < cnt; ++b) {
+        const size_t m = B->geoms[b].m, n = B->geoms[b].n;
+        const size_t sz[4] = {n * n, m * m, m * m, n * n};   // QnT, QmT, Qm, Qn
+        for (int s = 0; s < 4; ++s) {
+            L.q32[s][b] = c.take<float>(sz[s]);
+            L.qh[s][b] = c.take<uint16_t>(sz[s]);
+            L.ql[s][b] = c.take<uint16_t>(sz[s]);
+        }
+        L.lt[b] = c.take<double>(n);
+        L.lb[b] = c.take<double>(m);
+    }
+    L.bytes = c.size();
+    return L;
+}
+
+struct BatchWs {
+    double *V, *Z, *X, *Vc, *T, *F, *Ft, *D, *Dt;
+    double *pa, *pb;
+    double *H, *g, *cs, *sn, *Y;
+    int *ctl, *counter;
+    BState *S;
+    double *rhist;
+    int *khist;
+    LpPlanes x, u, w;
+    size_t bytes;
+};
+
+BatchWs batch_ws(const mca_batch *B, const mca_options *o, void *base)
+{
+    const size_t cnt = B->geoms.size(), len = B->len, R = o->restart;
+    const size_t nblk = B->btab.size();
+    BCarver c(base);
+    BatchWs w;
+    w.V = c.take<double>((R + 1) * len);
+    w.Z = c.take<double>(R * len);
+    w.X = c.take<double>(len);
+    w.Vc = c.take<double>(len);
+    w.T = c.take<double>(len);
+    w.F = c.take<double>(len);
+    w.Ft = c.take<double>(len);
+    w.D = c.take<double>(len / 2);
+    w.Dt = c.take<double>(len / 2);
+    w.pa = c.take<double>(2 * nblk);
+    w.pb = c.take<double>(2 * nblk);
+    w.H = c.take<double>(cnt * (R + 1) * R);
+    w.g = c.take<double>(cnt * (R + 1));
+    w.cs = c.take<double>(cnt * R);
+    w.sn = c.take<double>(cnt * R);
+    w.Y = c.take<double>(cnt * R);
+    w.ctl = c.take<int>(4 * cnt);
+    w.counter = c.take<int>(cblocks((int)cnt) + 8);
+    w.S = c.take<BState>(cnt);
+    w.rhist = c.take<double>(cnt * (MCA_MAX_NEWTON + 1));
+    w.khist = c.take<int>(cnt * MCA_MAX_NEWTON);
+    for (LpPlanes *p : {&w.x, &w.u, &w.w}) {
+        if (o->precision == MCA_PREC_FP32) {
+            p->p[0] = c.take<float>(len);
+            p->p[1] = nullptr;
+        } else {
+            p->p[0] = c.take<uint16_t>(len);
+            p->p[1] = c.take<uint16_t>(len);
+        }
+    }
+    w.bytes = c.size();
+    return w;
+}
+
+#define MCA_BTRY(expr)                  \
+    do {                                \
+        hipError_t e_ = (expr);         \
+        if (e_ != hipSuccess) {         \
+            set_hip_error(#expr, e_);   \
+            return MCA_ERR_HIP;         \
+        }                               \
+    } while (0)
+
+mca_status batch_options_ok(const mca_options *o)
+{
+    if (!(o->newton_tol >= 0.0) || !(o->gmres_tol > 0.0) || !(o->gmres_tol < 1.0))
+        return MCA_ERR_INVALID_ARG;
+    if (o->restart < 1 || o->restart > MCA_MAX_RESTART) return MCA_ERR_INVALID_ARG;
+    if (o->max_newton < 1 || o->max_newton > MCA_MAX_NEWTON) return MCA_ERR_INVALID_ARG;
+    if (o->max_krylov < 1) return MCA_ERR_INVALID_ARG;
+    if (o->precond != MCA_PRECOND_PERMODE) return MCA_ERR_INVALID_ARG;
+    if (o->precision != MCA_PREC_FP32 && o->precision != MCA_PREC_BF16X3 &&
+        o->precision != MCA_PREC_BF16)
+        return MCA_ERR_INVALID_ARG;
+    if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING)) return MCA_ERR_INVALID_ARG;
+    return MCA_OK;
+}
+
+}  // namespace
+}  // namespace mca
+
+using namespace mca;
+
+extern "C" {
+
+mca_status mca_batch_create(int32_t count, const mca_geometry *geoms, mca_batch **out)
+{
+    if (!out || count < 1 || !geoms) return MCA_ERR_INVALID_ARG;
+    *out = nullptr;
+    mca_batch *B = new (std::nothrow) mca_batch();
+    if (!B) return MCA_ERR_INVALID_ARG;
+    B->geoms.assign(geoms, geoms + count);
+    B->plans.assign(count, nullptr);
+    // eigen set-up of every crossbar's two wires, spread over host threads
+    std::vector<mca_status> st(count, MCA_OK);
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nt; ++t)
+        pool.emplace_back([&, t]() {
+            for (int b = (int)t; b < count; b += (int)nt) st[b] = mca_plan_create(&geoms[b], &B->plans[b]);
+        });
+    for (auto &th : pool) th.join();
+    for (int b = 0; b < count; ++b)
+        if (st[b] != MCA_OK) {
+            mca_batch_destroy(B);
+            return st[b];
+        }
+    B->ox.assign(count + 1, 0);
+    B->orow.assign(count + 1, 0);
+    for (int b = 0; b < count; ++b) {
+        B->ox[b + 1] = B->ox[b] + (long long)geoms[b].m * geoms[b].n;
+        B->orow[b + 1] = B->orow[b] + geoms[b].m;
+    }
+    B->len = 2 * (size_t)B->ox[count];
+    B->inst.resize(count);
+    for (int b = 0; b < count; ++b) {
+        const mca_plan *P = B->plans[b];
+        BInst &I = B->inst[b];
+        I.m = geoms[b].m;
+        I.n = geoms[b].n;
+        I.linear = geoms[b].device_model == MCA_DEVICE_LINEAR;
+        I.top = P->top;
+        I.bot = P->bot;
+        I.v0 = geoms[b].v0;
+        I.g_src = geoms[b].g_src;
+        I.ox = B->ox[b];
+        I.orow = B->orow[b];
+        I.blk0 = (int)B->btab.size();
+        const int nb = (int)((((size_t)I.m * I.n) + CH - 1) / CH);
+        I.nblk = nb;
+        for (int c = 0; c < nb; ++c) B->btab.push_back(int2{b, c});
+    }
+    // tiles of the four products: steps 1, 2 are n x m, steps 3, 4 are m x n
+    for (int s = 0; s < 4; ++s) {
+        int t = 0;
+        for (int b = 0; b < count; ++b) {
+            const int M = (s < 2) ? geoms[b].n : geoms[b].m, N = (s < 2) ? geoms[b].m : geoms[b].n;
+            t += ((M + kLp - 1) / kLp) * ((N + kLp - 1) / kLp);
+        }
+        B->ntiles[s] = t;
+    }
+    B->dev_bytes = batch_layout(B, nullptr).bytes;
+    *out = B;
+    return MCA_OK;
+}
+
+void mca_batch_destroy(mca_batch *B)
+{
+    if (!B) return;
+    for (mca_plan *p : B->plans) mca_plan_destroy(p);
+    delete B;
+}
+
+mca_status mca_batch_offsets(const mca_batch *B, int64_t *cross_offsets, int64_t *row_offsets)
+{
+    if (!B) return MCA_ERR_INVALID_ARG;
+    for (size_t b = 0; b < B->ox.size(); ++b) {
+        if (cross_offsets) cross_offsets[b] = B->ox[b];
+        if (row_offsets) row_offsets[b] = B->orow[b];
+    }
+    return MCA_OK;
+}
+
+size_t mca_batch_device_bytes(const mca_batch *B) { return B ? B->dev_bytes : 0; }
+
+mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *stream)
+{
+    if (!B || !dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) & 255)) return MCA_ERR_INVALID_ARG;
+    if (bytes < B->dev_bytes) return MCA_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t cnt = B->geoms.size();
+    std::vector<char> img(B->dev_bytes);
+    BatchLayout H = batch_layout(B, img.data());   // host image, same offsets
+    BatchLayout D = batch_layout(B, dev_buf);      // device addresses
+    std::memcpy(H.inst, B->inst.data(), cnt * sizeof(BInst));
+    std::memcpy(H.btab, B->btab.data(), B->btab.size() * sizeof(int2));
+    std::vector<double> tmp;
+    for (size_t b = 0; b < cnt; ++b) {
+        const mca_plan *P = B->plans[b];
+        const size_t m = P->geom.m, n = P->geom.n;
+        // QnT, QmT, Qm, Qn in FP64 from the host eigenvectors
+        for (int q = 0; q < 4; ++q) {
+            const size_t L = (q == 0 || q == 3) ? n : m;
+            const std::vector<double> &src = (q == 0 || q == 3) ? P->Qn : P->Qm;
+            const bool tr = (q == 0 || q == 1);
+            tmp.resize(L * L);
+            for (size_t i = 0; i < L; ++i)
+                for (size_t j = 0; j < L; ++j) tmp[i * L + j] = tr ? src[j * L + i] : src[i * L + j];
+            split_host(tmp.data(), L * L, MCA_PREC_FP32, H.q32[q][b], nullptr);
+            split_host(tmp.data(), L * L, MCA_PREC_BF16X3, H.qh[q][b], H.ql[q][b]);
+        }
+        std::memcpy(H.lt[b], P->lt.data(), n * sizeof(double));
+        std::memcpy(H.lb[b], P->lb.data(), m * sizeof(double));
+        // descriptors of the four products
+        const int Ms[4] = {(int)n, (int)n, (int)m, (int)m}, Ns[4] = {(int)m, (int)m, (int)n, (int)n};
+        const int Ks[4] = {(int)n, (int)m, (int)m, (int)n};
+        for (int f = 0; f < 2; ++f)
+            for (int st = 0; st < 4; ++st) {
+                LpDesc d{};
+                d.M = Ms[st];
+                d.N = Ns[st];
+                d.K = Ks[st];
+                d.inst = (int)b;
+                if (f == 0) {
+                    d.Q[0] = D.q32[st][b];
+                    d.Q[1] = nullptr;
+                } else {
+                    d.Q[0] = D.qh[st][b];
+                    d.Q[1] = D.ql[st][b];
+                }
+                d.off_data = d.off_out = 2 * (size_t)B->ox[b];
+                d.mn = m * n;
+                d.lam_row = (st < 2) ? D.lt[b] : nullptr;
+                d.lam_col = (st < 2) ? D.lb[b] : nullptr;
+                // data rows are m*n-offset slices: aligned when 2 ox and mn are multiples of 8
+                d.vec = (d.K % 8 == 0) && ((2 * (size_t)B->ox[b]) % 8 == 0) && (d.mn % 8 == 0);
+                H.desc[f][st][b] = d;
+            }
+    }
+    for (int st = 0; st < 4; ++st) {
+        int t = 0;
+        for (size_t b = 0; b < cnt; ++b) {
+            const int M = H.desc[0][st][b].M, N = H.desc[0][st][b].N;
+            for (int i = 0; i < (M + kLp - 1) / kLp; ++i)
+                for (int j = 0; j < (N + kLp - 1) / kLp; ++j) H.tiles[st][t++] = int4{(int)b, i * kLp, j * kLp, 0};
+        }
+    }
+    MCA_BTRY(hipMemcpyAsync(dev_buf, img.data(), B->dev_bytes, hipMemcpyHostToDevice, s));
+    MCA_BTRY(hipStreamSynchronize(s));
+    B->dev_buf = dev_buf;
+    B->d_inst = D.inst;
+    B->d_btab = D.btab;
+    for (int f = 0; f < 2; ++f)
+        for (int st = 0; st < 4; ++st) B->d_desc[f][st] = D.desc[f][st];
+    for (int st = 0; st < 4; ++st) B->d_tiles[st] = D.tiles[st];
+    return MCA_OK;
+}
+
+size_t mca_batch_workspace_bytes(const mca_batch *B, const mca_options *opts)
+{
+    if (!B) return 0;
+    mca_options o;
+    if (opts) o = *opts;
+    else {
+        mca_options_default(&o);
+        o.precond = MCA_PRECOND_PERMODE;
+        o.precision = MCA_PREC_BF16X3;
+    }
+    if (batch_options_ok(&o) != MCA_OK) return 0;
+    return batch_ws(B, &o, nullptr).bytes;
+}
+
+mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const double *v_in,
+                             double *v_t, double *v_b, const mca_options *opts, void *ws,
+                             size_t ws_bytes, mca_stats *stats, void *stream)
+{
+    if (!B || !g_dev || !v_in || !v_t || !v_b) return MCA_ERR_INVALID_ARG;
+    const int cnt = (int)B->geoms.size();
+    if (stats) std::memset(stats, 0, sizeof(mca_stats) * cnt);
+    mca_options o;
+    if (opts) o = *opts;
+    else {
+        mca_options_default(&o);
+        o.precond = MCA_PRECOND_PERMODE;
+        o.precision = MCA_PREC_BF16X3;
+    }
+    mca_status st = batch_options_ok(&o);
+    if (st != MCA_OK) return st;
+    if (!B->dev_buf) return MCA_ERR_WORKSPACE;
+    BatchWs w = batch_ws(B, &o, ws);
+    if (!ws || ws_bytes < w.bytes) return MCA_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int R = o.restart, ldh = R + 1, hsize = (R + 1) * R;
+    const size_t len = B->len;
+    const int nblk = (int)B->btab.size();
+    const dim3 gridB(nblk), blk(TPB);
+    const int cb = cblocks(cnt), ct = std::min(cnt, 1024);
+    const int *actf = &w.S[0].active, *lsf = &w.S[0].ls_todo, *rsf = &w.S[0].restart;
+    const int *accf = &w.S[0].accept;
+    int *host = nullptr;
+    MCA_BTRY(hipHostMalloc((void **)&host, 4096 * sizeof(int), hipHostMallocDefault));
+    struct HostFree {
+        int *p;
+        ~HostFree() { (void)hipHostFree(p); }
+    } hf{host};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    struct EvFree {
+        hipEvent_t *e;
+        ~EvFree()
+        {
+            for (int i = 0; i < 2; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } ef{ev};
+    for (auto &e : ev) MCA_BTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+
+    // read the sum of the per-block counters written by the last control kernel
+    auto count_now = [&](int *out) -> mca_status {
+        hipLaunchKernelGGL(bk_sum_counters, dim3(1), dim3(64), 0, s, w.counter, cb, w.counter + cb);
+        MCA_BTRY(hipGetLastError());
+        MCA_BTRY(hipMemcpyAsync(host, w.counter + cb, sizeof(int), hipMemcpyDeviceToHost, s));
+        MCA_BTRY(hipStreamSynchronize(s));
+        *out = host[0];
+        return MCA_OK;
+    };
+
+    GroupedChain gc{};
+    const int f = (o.precision == MCA_PREC_FP32) ? 0 : 1;
+    for (int q = 0; q < 4; ++q) {
+        gc.descs[q] = B->d_desc[f][q];
+        gc.tiles[q] = B->d_tiles[q];
+        gc.ntiles[q] = B->ntiles[q];
+    }
+    gc.len = len;
+    gc.x = w.x;
+    gc.u = w.u;
+    gc.w = w.w;
+    gc.a_inst = &w.S[0].a;
+    gc.a_stride = (int)(sizeof(BState) / sizeof(double));
+    gc.ctl = w.ctl;
+
+    // initial state and iterate
+    hipLaunchKernelGGL(bk_init, dim3(cnt), blk, 0, s, B->d_inst, cnt, v_in, w.S);
+    if (o.flags & MCA_FLAG_INITIAL_GUESS)
+        hipLaunchKernelGGL(bk_user_io, gridB, blk, 0, s, B->d_inst, B->d_btab, w.S, w.Vc, v_t, v_b,
+                           0);
+    else
+        MCA_BTRY(launch_fill(w.Vc, 0.0, len, s));
+    hipLaunchKernelGGL(bk_residual, gridB, blk, 0, s, B->d_inst, B->d_btab, (const int *)nullptr, g_dev,
+                       v_in, w.Vc, w.F, w.D, w.pa);
+    hipLaunchKernelGGL(bk_inst_norms, dim3(cnt), blk, 0, s, B->d_inst, cnt, (const int *)nullptr,
+                       w.pa, 0, w.S);
+    MCA_BTRY(hipGetLastError());
+
+    for (int k = 0; k <= o.max_newton; ++k) {
+        hipLaunchKernelGGL(bk_newton_begin, dim3(cb), dim3(ct), 0, s, B->d_inst, cnt, w.S, k,
+                           o.max_newton, o.newton_tol, o.gmres_tol, w.rhist, w.counter);
+        int active = 0;
+        if ((st = count_now(&active)) != MCA_OK) return st;
+        if (active == 0) break;
+        // flexible GMRES for every active crossbar: v_0 = -F / beta
+        hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, actf, w.S, 0, w.F,
+                           (const double *)nullptr, w.V);
+        for (;;) {
+            hipLaunchKernelGGL(bk_cycle_init, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.ctl, w.g, R,
+                               o.max_krylov);
+            int last = -1;
+            for (int j = 0; j < R; ++j) {
+                double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
+                double *wv = w.V + (size_t)(j + 1) * len;
+                gc.r = vj;
+                gc.z = zj;
+                MCA_BTRY(launch_precond_lowprec_grouped(o.precision, gc, s));
+                hipLaunchKernelGGL(bk_jacobian, gridB, blk, 0, s, B->d_inst, B->d_btab, w.ctl,
+                                   w.D, zj, wv, w.V, w.pa);
+                double *pin = w.pa, *pout = w.pb;
+                for (int i = 0; i <= j; ++i) {
+                    const double *vn = (i < j) ? w.V + (size_t)(i + 1) * len : nullptr;
+                    hipLaunchKernelGGL(bk_mgs_step, gridB, blk, 0, s, B->d_inst, B->d_btab, w.ctl,
+                                       wv, w.V + (size_t)i * len, vn, pin, pout, w.H, ldh, hsize,
+                                       j, i);
+                    std::swap(pin, pout);
+                }
+                hipLaunchKernelGGL(bk_normalize, gridB, blk, 0, s, B->d_inst, B->d_btab, w.ctl, wv,
+                                   pin, w.H, ldh, hsize, j, j + 1);
+                hipLaunchKernelGGL(bk_givens, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.H, ldh, hsize, j,
+                                   w.g, w.cs, w.sn, R, w.ctl, w.counter);
+                hipLaunchKernelGGL(bk_sum_counters, dim3(1), dim3(64), 0, s, w.counter, cb,
+                                   w.counter + cb + 1);
+                MCA_BTRY(hipGetLastError());
+                MCA_BTRY(hipMemcpyAsync(host + 16 + j, w.counter + cb + 1, sizeof(int),
+                                        hipMemcpyDeviceToHost, s));
+                MCA_BTRY(hipEventRecord(ev[j & 1], s));
+                last = j;
+                if (j > 0) {
+                    MCA_BTRY(hipEventSynchronize(ev[(j - 1) & 1]));
+                    if (host[16 + j - 1] == 0) break;   // every crossbar's cycle has stopped
+                }
+            }
+            if (last >= 0) MCA_BTRY(hipEventSynchronize(ev[last & 1]));
+            hipLaunchKernelGGL(bk_cycle_end, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.H, ldh, hsize, w.g,
+                               R, w.ctl, w.Y, o.max_krylov, w.counter);
+            hipLaunchKernelGGL(bk_update, gridB, blk, 0, s, B->d_inst, B->d_btab, w.S, w.Z, len, w.Y,
+                               R, w.X);
+            hipLaunchKernelGGL(bk_after_update, dim3(cb), dim3(ct), 0, s, cnt, w.S);
+            int again = 0;
+            if ((st = count_now(&again)) != MCA_OK) return st;
+            if (again == 0) break;
+            // restart from the true residual r = -F - J X for the crossbars that need it
+            hipLaunchKernelGGL(bk_restart_residual, gridB, blk, 0, s, B->d_inst, B->d_btab, rsf,
+                               w.D, w.X, w.F, w.V, w.pb);
+            hipLaunchKernelGGL(bk_inst_norms, dim3(cnt), blk, 0, s, B->d_inst, cnt, rsf, w.pb, 2,
+                               w.S);
+            hipLaunchKernelGGL(bk_restart_check, dim3(cb), dim3(ct), 0, s, cnt, w.S);
+            hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, rsf, w.S, 3, w.V,
+                               (const double *)nullptr, w.V);
+            MCA_BTRY(hipGetLastError());
+        }
+        // damped update with a per-crossbar line search
+        hipLaunchKernelGGL(bk_ls_init, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.khist, k);
+        for (int round = 0; round < 32; ++round) {
+            hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, lsf, w.S, 1, w.Vc,
+                               w.X, w.T);
+            hipLaunchKernelGGL(bk_residual, gridB, blk, 0, s, B->d_inst, B->d_btab, lsf, g_dev,
+                               v_in, w.T, w.Ft, w.Dt, w.pa);
+            hipLaunchKernelGGL(bk_inst_norms, dim3(cnt), blk, 0, s, B->d_inst, cnt, lsf, w.pa, 1,
+                               w.S);
+            hipLaunchKernelGGL(bk_ls_check, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.counter);
+            int todo = 0;
+            if ((st = count_now(&todo)) != MCA_OK) return st;
+            if (todo == 0) break;
+        }
+        // accepted crossbars move to the trial point
+        hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, accf, w.S, 4, w.T,
+                           (const double *)nullptr, w.Vc);
+        hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, accf, w.S, 4, w.Ft,
+                           (const double *)nullptr, w.F);
+        hipLaunchKernelGGL(bk_copy_cross, gridB, blk, 0, s, B->d_inst, B->d_btab, accf, w.Dt, w.D);
+        hipLaunchKernelGGL(bk_ls_finish, dim3(cb), dim3(ct), 0, s, cnt, w.S);
+        MCA_BTRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(bk_user_io, gridB, blk, 0, s, B->d_inst, B->d_btab, w.S, w.Vc, v_t, v_b, 1);
+    MCA_BTRY(hipGetLastError());
+    // per-crossbar results
+    std::vector<BState> S(cnt);
+    std::vector<double> rh((size_t)cnt * (MCA_MAX_NEWTON + 1));
+    std::vector<int> kh((size_t)cnt * MCA_MAX_NEWTON);
+    MCA_BTRY(hipMemcpyAsync(S.data(), w.S, cnt * sizeof(BState), hipMemcpyDeviceToHost, s));
+    MCA_BTRY(hipMemcpyAsync(rh.data(), w.rhist, rh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    MCA_BTRY(hipMemcpyAsync(kh.data(), w.khist, kh.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    MCA_BTRY(hipStreamSynchronize(s));
+    mca_status result = MCA_OK;
+    for (int b = 0; b < cnt; ++b) {
+        const BState &x = S[b];
+        int status = x.status;
+        if (x.active) status = MCA_ERR_NOT_CONVERGED;
+        if (status != MCA_OK && result == MCA_OK) result = status;
+        if (stats) {
+            mca_stats &t = stats[b];
+            t.newton_iters = x.newton;
+            t.krylov_iters = x.krylov;
+            t.backtracks = x.backtracks;
+            t.restarts = x.restarts;
+            t.rel_residual = x.ynorm > 0 ? x.fnorm / x.ynorm : 0.0;
+            t.a_last = x.a;
+            for (int i = 0; i <= std::min(x.newton, MCA_MAX_NEWTON); ++i)
+                t.residual_history[i] = rh[(size_t)b * (MCA_MAX_NEWTON + 1) + i];
+            for (int i = 0; i < std::min(x.newton, MCA_MAX_NEWTON); ++i)
+                t.krylov_history[i] = kh[(size_t)b * MCA_MAX_NEWTON + i];
+        }
+    }
+    return result;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// device_common.h -- small device helpers shared by the kernel files.
+#pragma once
+
+#include "mca_internal.h"
+
+namespace mca {
+namespace dev {
+
+constexpr int TPB = 256;   // threads per block of the streaming kernels
+
+// Product of one wire matrix (eq. (G) with end terminations) with x at node k
+// of the wire, in branch-current form:
+//   sum over the node's segments of g (x_k - x_neighbour)
+//   + end conductance * x_k at the wire's first / last node.
+__device__ __forceinline__ double wire_apply(const Wire w, int k, double xk, double xm, double xp)
+{
+    double s = (k > 0) ? w.g * (xk - xm) : w.end0 * xk;
+    s += (k + 1 < w.len) ? w.g * (xk - xp) : w.end1 * xk;
+    return s;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over a TPB-thread block in a fixed order; the result is valid in every thread.
+template <int NC>
+__device__ __forceinline__ void block_sum(double (&v)[NC])
+{
+    __shared__ double sh[NC][TPB / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double w = wave_sum(v[c]);
+        if (lane == 0) sh[c][wave] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < TPB / 64; ++w) s += sh[c][w];
+        v[c] = s;
+    }
+    __syncthreads();
+}
+
+// Sum of nb per-block partials p[0..nb), identical in every block (fixed order).
+__device__ __forceinline__ double sum_partials(const double *__restrict__ p, int nb)
+{
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nb; b += TPB) v[0] += p[b];
+    block_sum<1>(v);
+    return v[0];
+}
+
+}  // namespace dev
+}  // namespace mca

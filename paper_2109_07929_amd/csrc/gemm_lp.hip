@@ -5,19 +5,24 @@
 // row-major with K contiguous (A: M x K, B: N x K).  The per-mode
 // preconditioner (the block formula of eq. (block) applied per Kronecker
 // eigenmode) then becomes four such products without any transpose:
-//   U^T   = Q_n^T . X^T      A = Q_n^T,  B = X      (contract over j)
-//   W^T   = U^T . Q_m        A = U^T,    B = Q_m^T  (contract over i), + 2x2 solve
+//   U^T   = Q_n^T . X^T      A = Q_n^T,  B = X       (contract over j)
+//   W^T   = U^T . Q_m        A = U^T,    B = Q_m^T   (contract over i), + 2x2 solve
 //   Y     = Q_m . X^hat      A = Q_m,    B = X^hat^T (contract over p)
-//   Z     = Y . Q_n^T        A = Y,      B = Q_n    (contract over q)
-// (X is the m x n input, hats mark the eigenbasis.)  Operands are converted
-// to FP32 while they are staged into LDS; in the BF16 modes each value is
-// also split into hi + lo bfloat16 halves (v = hi + lo to ~16 bits), and the
-// product uses hi.hi (BF16) or hi.hi + hi.lo + lo.hi (BF16X3), accumulated in
-// FP32 by v_mfma_f32_16x16x32_bf16.  The FP32 mode uses v_mfma_f32_16x16x4f32.
+//   Z     = Y . Q_n^T        A = Y,      B = Q_n     (contract over q)
+// (X is the m x n input, hats mark the eigenbasis.)
+//
+// Operands live in global memory in the format the MFMA consumes, so staging
+// into LDS is a plain 16-byte copy: FP32 arrays for the FP32 mode
+// (v_mfma_f32_16x16x4f32), or bfloat16 hi + lo planes (v = hi + lo to ~16
+// bits) for the BF16 modes (v_mfma_f32_16x16x32_bf16: hi.hi for BF16,
+// hi.hi + hi.lo + lo.hi for BF16X3, always accumulated in FP32).  The
+// eigenbases are converted once in the plan, the FP64 input r by a split
+// kernel, and every intermediate by the epilogue of the product that makes it.
 //
 // Tiling: 64 x 64 output tile per 256-thread workgroup (four waves of 32 x 32,
-// 2 x 2 MFMA tiles each), K staged through LDS in double-buffered 32-deep
-// slices.  One operand may have two batches (the two layers) sharing the other.
+// 2 x 2 MFMA tiles each); K staged through LDS in double-buffered 64-deep
+// slices with two slices of global loads in flight.  One operand may have two
+// batches (the two layers) that share the other operand.
 #include <hip/hip_bf16.h>
 
 #include "mca_internal.h"
@@ -27,137 +32,153 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
-constexpr int LBM = 64, LBN = 64, LBK = 32, LTPB = 256;
-constexpr int FPITCH = LBK + 4;     // FP32 LDS row pitch (floats): 16 rows hit distinct banks
-constexpr int HPITCH = LBK + 8;     // BF16 LDS row pitch (bf16): 16-byte reads stay conflict-free
-
-template <typename T>
-__device__ __forceinline__ float to_f32(T v) { return (float)v; }
-
-// Round-to-nearest-even split of an FP32 value into bfloat16 hi + lo.
-__device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo)
-{
-    hi = (__bf16)v;
-    lo = (__bf16)(v - (float)hi);
-}
+constexpr int LBM = 64, LBK = 64, LTPB = 256;
 
 template <int MODE>
-struct LdsTile;
-
+struct Fmt {   // BF16 modes: two bf16 planes, 8 values per 16-byte chunk
+    static constexpr int kPlanes = (MODE == MCA_PREC_BF16X3) ? 2 : 1;
+    static constexpr int kPerChunk = 8;
+    static constexpr int kPitch = LBK + 8;                 // bf16 per LDS row
+    using elem = __bf16;
+};
 template <>
-struct LdsTile<MCA_PREC_FP32> {
-    float v[LBM][FPITCH];
+struct Fmt<MCA_PREC_FP32> {
+    static constexpr int kPlanes = 1;
+    static constexpr int kPerChunk = 4;
+    static constexpr int kPitch = LBK + 4;                 // floats per LDS row
+    using elem = float;
+};
+
+// One operand: planes[0] (hi or FP32 values) and planes[1] (lo), row stride K.
+struct Operand {
+    const void *p[2];
 };
 
 template <int MODE>
-struct LdsTile {   // BF16 modes
-    __bf16 hi[LBM][HPITCH];
-    __bf16 lo[LBM][HPITCH];
+struct Tile {
+    typename Fmt<MODE>::elem v[Fmt<MODE>::kPlanes][LBM][Fmt<MODE>::kPitch];
 };
 
-template <typename T, int NBT>
-struct Ptrs {
-    const T *p[NBT];
-};
-
-// One operand slice (64 rows x 32 k) in registers: thread t holds row t/4,
-// k = 8 (t%4) .. +7.
-struct Slice {
-    float v[8];
-};
-
-template <typename T>
-__device__ __forceinline__ void load_slice(const T *__restrict__ base, int rows, int K, int r0,
-                                           int k0, bool fast, Slice &s)
+// Chunks of one 64 x 64 operand slice per plane, per thread.
+template <int MODE>
+constexpr int chunks_per_thread()
 {
-    const int t = threadIdx.x;
-    const int r = r0 + (t >> 2), kk = k0 + (t & 3) * 8;
-    if (fast) {
-        const T *p = base + (size_t)r * K + kk;
+    return LBM * LBK / Fmt<MODE>::kPerChunk / LTPB;
+}
+
+template <int MODE>
+struct Regs {
+    u4 c[Fmt<MODE>::kPlanes][chunks_per_thread<MODE>()];
+};
+
+template <int MODE>
+__device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int r0, int k0,
+                                        bool fast, Regs<MODE> &g)
+{
+    constexpr int PC = Fmt<MODE>::kPerChunk, CPR = LBK / PC, CPT = chunks_per_thread<MODE>();
+    using E = typename Fmt<MODE>::elem;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) s.v[e] = to_f32(p[e]);
-    } else {
-        const int rc = min(r, rows - 1);
+    for (int pl = 0; pl < Fmt<MODE>::kPlanes; ++pl) {
+        const E *base = static_cast<const E *>(op.p[pl]);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = kk + e;
-            const float x = to_f32(base[(size_t)rc * K + min(k, K - 1)]);
-            s.v[e] = (r < rows && k < K) ? x : 0.0f;
+        for (int c = 0; c < CPT; ++c) {
+            const int id = threadIdx.x + c * LTPB;
+            const int r = r0 + id / CPR, k = k0 + (id % CPR) * PC;
+            if (fast) {
+                g.c[pl][c] = *reinterpret_cast<const u4 *>(base + (size_t)r * K + k);
+            } else {
+                // clamped element loads; out-of-range elements become zero
+                union {
+                    u4 v;
+                    E e[PC];
+                } u;
+                const size_t rc = (size_t)min(r, rows - 1);
+#pragma unroll
+                for (int e = 0; e < PC; ++e) {
+                    const E x = base[rc * K + min(k + e, K - 1)];
+                    u.e[e] = (r < rows && k + e < K) ? x : (E)0.0f;
+                }
+                g.c[pl][c] = u.v;
+            }
         }
     }
 }
 
 template <int MODE>
-__device__ __forceinline__ void stash_slice(LdsTile<MODE> &L, const Slice &s)
+__device__ __forceinline__ void stash_op(Tile<MODE> &t, const Regs<MODE> &g)
 {
-    const int t = threadIdx.x;
-    const int r = t >> 2, k = (t & 3) * 8;
-    if constexpr (MODE == MCA_PREC_FP32) {
+    constexpr int PC = Fmt<MODE>::kPerChunk, CPR = LBK / PC, CPT = chunks_per_thread<MODE>();
 #pragma unroll
-        for (int e = 0; e < 8; ++e) L.v[r][k + e] = s.v[e];
-    } else {
-        bf8 h, l;
+    for (int pl = 0; pl < Fmt<MODE>::kPlanes; ++pl)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            __bf16 a, b;
-            split_bf16(s.v[e], a, b);
-            h[e] = a;
-            l[e] = b;
+        for (int c = 0; c < CPT; ++c) {
+            const int id = threadIdx.x + c * LTPB;
+            *reinterpret_cast<u4 *>(&t.v[pl][id / CPR][(id % CPR) * PC]) = g.c[pl][c];
         }
-        *reinterpret_cast<bf8 *>(&L.hi[r][k]) = h;
-        if constexpr (MODE == MCA_PREC_BF16X3) *reinterpret_cast<bf8 *>(&L.lo[r][k]) = l;
-    }
 }
 
-// Arguments: A (M x K) and B (N x K), K contiguous; NB batches of A when
-// a_batched, else of B; output O (M x N) row-major, FP32 or FP64.
+// O = A B^T.  NB batches of A (A_BATCHED) or of B, sharing the other operand.
+// Output formats: OUT_F32, OUT_BF2 (hi/lo planes), OUT_BF1 (hi plane), OUT_F64.
+enum { OUT_F32 = 0, OUT_BF2 = 1, OUT_F64 = 2, OUT_BF1 = 3 };
+
 struct LpArgs {
     int M, N, K;
-    const void *A[2];
-    const void *B[2];
-    void *O[2];
+    Operand A[2], B[2];
+    void *O[2][2];                     // [batch][plane]
     const double *lam_row, *lam_col;   // PERMODE: eigenvalues along rows (lt) / cols (lb)
     double a1, a2;
+    int vec;                           // all operands 16-byte aligned with K % 8 == 0
     const int *skip;
 };
 
-template <int MODE, int NB, bool A_BATCHED, typename TA, typename TB, typename TO, int EPI>
-__global__ __launch_bounds__(LTPB) void k_gemm_nt_lp(LpArgs a)
+template <typename T>
+__device__ __forceinline__ void put(const LpArgs &a, int b, size_t o, T v, int out)
 {
-    __shared__ LdsTile<MODE> As[2][A_BATCHED ? NB : 1];
-    __shared__ LdsTile<MODE> Bs[2][A_BATCHED ? 1 : NB];
-    if (a.skip && *a.skip) return;
-    constexpr int NA = A_BATCHED ? NB : 1, NBB = A_BATCHED ? 1 : NB;
+    if (out == OUT_F64) {
+        static_cast<double *>(a.O[b][0])[o] = (double)v;
+    } else if (out == OUT_F32) {
+        static_cast<float *>(a.O[b][0])[o] = (float)v;
+    } else {
+        const float f = (float)v;
+        const __bf16 hi = (__bf16)f;
+        static_cast<__bf16 *>(a.O[b][0])[o] = hi;
+        if (out == OUT_BF2) static_cast<__bf16 *>(a.O[b][1])[o] = (__bf16)(f - (float)hi);
+    }
+}
 
+constexpr int DEPTH = 2;   // K slices in flight (deeper rings measured no faster)
+
+// One 64 x 64 output tile at (m0, n0) of O = A B^T.
+template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI>
+__device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
+{
+    constexpr int NA = A_BATCHED ? NB : 1, NBB = A_BATCHED ? 1 : NB;
+    __shared__ Tile<MODE> As[2][NA];
+    __shared__ Tile<MODE> Bs[2][NBB];
     const int M = a.M, N = a.N, K = a.K;
-    const int tiles_n = (N + LBN - 1) / LBN;
-    // XCD-aware order: every XCD owns a contiguous run of tiles
-    int t = blockIdx.x;
-    const int nwg = gridDim.x;
-    if (nwg % 8 == 0) t = (t % 8) * (nwg / 8) + t / 8;
-    const int m0 = (t / tiles_n) * LBM, n0 = (t % tiles_n) * LBN;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const bool fast_m = (m0 + LBM <= M) && (K % 8 == 0);
-    const bool fast_n = (n0 + LBN <= N) && (K % 8 == 0);
+    const bool fast_m = a.vec && (m0 + LBM <= M);
+    const bool fast_n = a.vec && (n0 + LBM <= N);
 
-    Slice sa[NA], sb[NBB];
-    auto load = [&](int k0) {
+    struct Stage {
+        Regs<MODE> ra[NA], rb[NBB];
+    };
+    auto load = [&](Stage &st, int k0) {
         const bool kin = k0 + LBK <= K;
 #pragma unroll
-        for (int b = 0; b < NA; ++b)
-            load_slice(static_cast<const TA *>(a.A[b]), M, K, m0, k0, fast_m && kin, sa[b]);
+        for (int b = 0; b < NA; ++b) load_op<MODE>(a.A[b], M, K, m0, k0, fast_m && kin, st.ra[b]);
 #pragma unroll
-        for (int b = 0; b < NBB; ++b)
-            load_slice(static_cast<const TB *>(a.B[b]), N, K, n0, k0, fast_n && kin, sb[b]);
+        for (int b = 0; b < NBB; ++b) load_op<MODE>(a.B[b], N, K, n0, k0, fast_n && kin, st.rb[b]);
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](const Stage &st, int buf) {
 #pragma unroll
-        for (int b = 0; b < NA; ++b) stash_slice<MODE>(As[buf][b], sa[b]);
+        for (int b = 0; b < NA; ++b) stash_op<MODE>(As[buf][b], st.ra[b]);
 #pragma unroll
-        for (int b = 0; b < NBB; ++b) stash_slice<MODE>(Bs[buf][b], sb[b]);
+        for (int b = 0; b < NBB; ++b) stash_op<MODE>(Bs[buf][b], st.rb[b]);
     };
 
     f4 acc[NB][2][2];
@@ -171,8 +192,8 @@ __global__ __launch_bounds__(LTPB) void k_gemm_nt_lp(LpArgs a)
     auto compute = [&](int buf) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const LdsTile<MODE> &TA_ = As[buf][A_BATCHED ? b : 0];
-            const LdsTile<MODE> &TB_ = Bs[buf][A_BATCHED ? 0 : b];
+            const Tile<MODE> &TA_ = As[buf][A_BATCHED ? b : 0];
+            const Tile<MODE> &TB_ = Bs[buf][A_BATCHED ? 0 : b];
             if constexpr (MODE == MCA_PREC_FP32) {
                 // A fragment: row l%16, k l/16; B fragment: k l/16, column l%16
 #pragma unroll
@@ -180,9 +201,9 @@ __global__ __launch_bounds__(LTPB) void k_gemm_nt_lp(LpArgs a)
                     const int kk = k4 * 4 + (lane >> 4);
                     float fa[2], fb[2];
 #pragma unroll
-                    for (int i = 0; i < 2; ++i) fa[i] = TA_.v[wm + i * 16 + (lane & 15)][kk];
+                    for (int i = 0; i < 2; ++i) fa[i] = TA_.v[0][wm + i * 16 + (lane & 15)][kk];
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) fb[j] = TB_.v[wn + j * 16 + (lane & 15)][kk];
+                    for (int j = 0; j < 2; ++j) fb[j] = TB_.v[0][wn + j * 16 + (lane & 15)][kk];
 #pragma unroll
                     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -192,43 +213,59 @@ __global__ __launch_bounds__(LTPB) void k_gemm_nt_lp(LpArgs a)
                 }
             } else {
                 // A fragment: row l%16, k 8(l/16)..+7; B fragment: column l%16, same k
-                const int kk = (lane >> 4) * 8;
-                bf8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    ah[i] = *reinterpret_cast<const bf8 *>(&TA_.hi[wm + i * 16 + (lane & 15)][kk]);
-                    bh[i] = *reinterpret_cast<const bf8 *>(&TB_.hi[wn + i * 16 + (lane & 15)][kk]);
-                    if constexpr (MODE == MCA_PREC_BF16X3) {
-                        al[i] = *reinterpret_cast<const bf8 *>(&TA_.lo[wm + i * 16 + (lane & 15)][kk]);
-                        bl[i] = *reinterpret_cast<const bf8 *>(&TB_.lo[wn + i * 16 + (lane & 15)][kk]);
-                    }
-                }
+                for (int k32 = 0; k32 < LBK / 32; ++k32) {
+                    const int kk = k32 * 32 + (lane >> 4) * 8;
+                    bf8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
+                    for (int i = 0; i < 2; ++i) {
+                        ah[i] = *reinterpret_cast<const bf8 *>(&TA_.v[0][wm + i * 16 + (lane & 15)][kk]);
+                        bh[i] = *reinterpret_cast<const bf8 *>(&TB_.v[0][wn + i * 16 + (lane & 15)][kk]);
                         if constexpr (MODE == MCA_PREC_BF16X3) {
-                            acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j],
-                                                                                   acc[b][i][j], 0, 0, 0);
-                            acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j],
-                                                                                   acc[b][i][j], 0, 0, 0);
+                            al[i] = *reinterpret_cast<const bf8 *>(&TA_.v[1][wm + i * 16 + (lane & 15)][kk]);
+                            bl[i] = *reinterpret_cast<const bf8 *>(&TB_.v[1][wn + i * 16 + (lane & 15)][kk]);
                         }
-                        acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j],
-                                                                               acc[b][i][j], 0, 0, 0);
                     }
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            if constexpr (MODE == MCA_PREC_BF16X3) {
+                                acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    al[i], bh[j], acc[b][i][j], 0, 0, 0);
+                                acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    ah[i], bl[j], acc[b][i][j], 0, 0, 0);
+                            }
+                            acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                ah[i], bh[j], acc[b][i][j], 0, 0, 0);
+                        }
+                }
             }
         }
     };
 
+    // DEPTH K slices in flight: a ring of register stages; the loop is unrolled
+    // by DEPTH so that the stages rotate by name.  At step k the stage that
+    // held slice k (already in LDS) receives slice k + DEPTH, slice k is
+    // multiplied, and slice k + 1 moves from registers into the other LDS buffer.
     const int nk = (K + LBK - 1) / LBK;
-    load(0);
-    stash(0);
+    Stage st[DEPTH];
+#pragma unroll
+    for (int u = 0; u < DEPTH; ++u)
+        if (u < nk) load(st[u], u * LBK);
+    stash(st[0], 0);
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        if (kt + 1 < nk) load((kt + 1) * LBK);
-        compute(kt & 1);
-        if (kt + 1 < nk) stash((kt + 1) & 1);
-        __syncthreads();
+    for (int kb = 0; kb < nk; kb += DEPTH) {
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) {
+            const int k = kb + u;
+            if (k < nk) {   // uniform
+                if (k + DEPTH < nk) load(st[u], (k + DEPTH) * LBK);
+                compute(k & 1);
+                if (k + 1 < nk) stash(st[(u + 1) % DEPTH], (k + 1) & 1);
+                __syncthreads();
+            }
+        }
     }
 
     // accumulator element r of lane l: row 4 (l/16) + r, column l%16
@@ -247,55 +284,214 @@ __global__ __launch_bounds__(LTPB) void k_gemm_nt_lp(LpArgs a)
                     const double lt = a.lam_row[row], lb = a.lam_col[col];
                     const double det = lt * lb + a.a2 * lt + a.a1 * lb;
                     const double rt = acc[0][i][j][r], rb = acc[NB - 1][i][j][r];
-                    static_cast<TO *>(a.O[0])[o] = (TO)(((lb + a.a2) * rt + a.a1 * rb) / det);
-                    static_cast<TO *>(a.O[1])[o] = (TO)((a.a2 * rt + (lt + a.a1) * rb) / det);
+                    put(a, 0, o, ((lb + a.a2) * rt + a.a1 * rb) / det, OUT);
+                    put(a, 1, o, (a.a2 * rt + (lt + a.a1) * rb) / det, OUT);
                 } else {
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) static_cast<TO *>(a.O[b])[o] = (TO)acc[b][i][j][r];
+                    for (int b = 0; b < NB; ++b) put(a, b, o, acc[b][i][j][r], OUT);
                 }
             }
 }
 
+// XCD-aware order: every XCD owns a contiguous run of workgroup ids.
+__device__ __forceinline__ int xcd_order(int bid, int nwg)
+{
+    return (nwg % 8 == 0) ? (bid % 8) * (nwg / 8) + bid / 8 : bid;
+}
+
+template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI>
+__global__ __launch_bounds__(LTPB) void k_gemm_nt_lp(LpArgs a)
+{
+    if (a.skip && *a.skip) return;
+    const int t = xcd_order(blockIdx.x, gridDim.x);
+    const int tiles_n = (a.N + LBM - 1) / LBM;
+    gemm_nt_tile<MODE, NB, A_BATCHED, OUT, EPI>(a, (t / tiles_n) * LBM, (t % tiles_n) * LBM);
+}
+
+// Grouped launch over many crossbars: tile t of the table names an instance's
+// product (descriptor) and the tile's origin.  The data operand and the output
+// of every instance sit at an element offset from the launch's base planes;
+// the eigenbasis operand is the instance's own.
+template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI>
+__global__ __launch_bounds__(LTPB) void k_gemm_nt_lp_grouped(GroupedLp g)
+{
+    const int t = xcd_order(blockIdx.x, gridDim.x);
+    const int4 tile = g.tiles[t];
+    const LpDesc &d = g.descs[tile.x];
+    if (g.ctl && g.ctl[4 * d.inst]) return;   // this crossbar's GMRES cycle has converged
+    LpArgs a{};
+    a.M = d.M;
+    a.N = d.N;
+    a.K = d.K;
+    const size_t es = g.data_elem_bytes, os = g.out_elem_bytes;
+    for (int b = 0; b < 2; ++b) {
+        Operand data;
+        for (int pl = 0; pl < 2; ++pl)
+            data.p[pl] = g.data[pl] ? static_cast<const char *>(g.data[pl]) + (d.off_data + b * d.mn) * es
+                                    : nullptr;
+        if (A_BATCHED) a.A[b] = data;
+        else a.B[b] = data;
+        for (int pl = 0; pl < 2; ++pl)
+            a.O[b][pl] = g.out[pl] ? static_cast<char *>(g.out[pl]) + (d.off_out + b * d.mn) * os
+                                   : nullptr;
+    }
+    Operand q;
+    q.p[0] = d.Q[0];
+    q.p[1] = d.Q[1];
+    if (A_BATCHED) a.B[0] = q;
+    else a.A[0] = q;
+    a.lam_row = d.lam_row;
+    a.lam_col = d.lam_col;
+    if (g.a_inst) a.a1 = a.a2 = g.a_inst[d.inst * g.a_stride];
+    a.vec = d.vec;
+    gemm_nt_tile<MODE, NB, A_BATCHED, OUT, EPI>(a, tile.y, tile.z);
+}
+
+// FP64 -> the operand format of MODE (FP32, or bf16 hi/lo planes), two arrays.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_split(const double *__restrict__ x0,
+                                               const double *__restrict__ x1, size_t len,
+                                               void *o00, void *o01, void *o10, void *o11,
+                                               const int *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    const int nb = x1 ? 2 : 1;
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < len; k += (size_t)gridDim.x * 256) {
+        for (int b = 0; b < nb; ++b) {
+            const float f = (float)(b == 0 ? x0[k] : x1[k]);
+            if constexpr (MODE == MCA_PREC_FP32) {
+                static_cast<float *>(b == 0 ? o00 : o10)[k] = f;
+            } else {
+                const __bf16 hi = (__bf16)f;
+                static_cast<__bf16 *>(b == 0 ? o00 : o10)[k] = hi;
+                if constexpr (MODE == MCA_PREC_BF16X3)
+                    static_cast<__bf16 *>(b == 0 ? o01 : o11)[k] = (__bf16)(f - (float)hi);
+            }
+        }
+    }
+}
+
+bool aligned16(const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 template <int MODE>
 hipError_t chain(const LowPrecChain &c, hipStream_t s)
 {
+    constexpr int OUT = (MODE == MCA_PREC_FP32) ? OUT_F32 : (MODE == MCA_PREC_BF16X3) ? OUT_BF2 : OUT_BF1;
     const int m = c.m, n = c.n;
+    const size_t mn = (size_t)m * n;
+    auto tiles = [](int M, int N) { return ((M + LBM - 1) / LBM) * ((N + LBM - 1) / LBM); };
+    auto op = [](const LpPlanes &p) {
+        Operand o;
+        o.p[0] = p.p[0];
+        o.p[1] = p.p[1];
+        return o;
+    };
+    auto vec_ok = [&](const LpArgs &g) {
+        bool ok = (g.K % 8 == 0);
+        for (int b = 0; b < 2; ++b)
+            for (int pl = 0; pl < 2; ++pl) ok = ok && aligned16(g.A[b].p[pl]) && aligned16(g.B[b].p[pl]);
+        return ok ? 1 : 0;
+    };
+    // 0. r (FP64) -> operand format
+    {
+        const int blocks = (int)std::min<size_t>((mn + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_split<MODE>, dim3(blocks), dim3(256), 0, s, c.rt, c.rb, mn,
+                           c.x[0].p[0], c.x[0].p[1], c.x[1].p[0], c.x[1].p[1], c.skip);
+    }
     LpArgs g{};
-    g.skip = c.skip;
-    g.a1 = c.a1;
-    g.a2 = c.a2;
-    auto tiles = [](int M, int N) { return ((M + LBM - 1) / LBM) * ((N + LBN - 1) / LBN); };
     // 1. U^T (n x m) = Q_n^T . X^T     A = QnT (n x n), B = X (m x n), both layers of X
+    g.skip = c.skip;
     g.M = n; g.N = m; g.K = n;
-    g.A[0] = c.QnT; g.B[0] = c.rt; g.B[1] = c.rb; g.O[0] = c.u_t; g.O[1] = c.u_b;
-    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, false, float, double, float, EPI_STORE>),
-                       dim3(tiles(n, m)), dim3(LTPB), 0, s, g);
+    g.A[0] = op(c.QnT); g.B[0] = op(c.x[0]); g.B[1] = op(c.x[1]);
+    for (int b = 0; b < 2; ++b) { g.O[b][0] = c.u[b].p[0]; g.O[b][1] = c.u[b].p[1]; }
+    g.vec = vec_ok(g);
+    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, false, OUT, EPI_STORE>), dim3(tiles(n, m)),
+                       dim3(LTPB), 0, s, g);
     // 2. W^T (n x m) = U^T . Q_m      A = U^T (n x m), B = QmT (m x m); per-mode solve
     g = LpArgs{};
     g.skip = c.skip; g.a1 = c.a1; g.a2 = c.a2;
     g.M = n; g.N = m; g.K = m;
-    g.A[0] = c.u_t; g.A[1] = c.u_b; g.B[0] = c.QmT; g.O[0] = c.w_t; g.O[1] = c.w_b;
+    g.A[0] = op(c.u[0]); g.A[1] = op(c.u[1]); g.B[0] = op(c.QmT);
+    for (int b = 0; b < 2; ++b) { g.O[b][0] = c.w[b].p[0]; g.O[b][1] = c.w[b].p[1]; }
     g.lam_row = c.lt; g.lam_col = c.lb;
-    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, true, float, float, float, EPI_PERMODE>),
-                       dim3(tiles(n, m)), dim3(LTPB), 0, s, g);
+    g.vec = vec_ok(g);
+    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, true, OUT, EPI_PERMODE>), dim3(tiles(n, m)),
+                       dim3(LTPB), 0, s, g);
     // 3. Y (m x n) = Q_m . X^hat      A = Qm (m x m), B = X^hat^T (n x m)
     g = LpArgs{};
     g.skip = c.skip;
     g.M = m; g.N = n; g.K = m;
-    g.A[0] = c.Qm; g.B[0] = c.w_t; g.B[1] = c.w_b; g.O[0] = c.u_t; g.O[1] = c.u_b;
-    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, false, float, float, float, EPI_STORE>),
-                       dim3(tiles(m, n)), dim3(LTPB), 0, s, g);
+    g.A[0] = op(c.Qm); g.B[0] = op(c.w[0]); g.B[1] = op(c.w[1]);
+    for (int b = 0; b < 2; ++b) { g.O[b][0] = c.u[b].p[0]; g.O[b][1] = c.u[b].p[1]; }
+    g.vec = vec_ok(g);
+    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, false, OUT, EPI_STORE>), dim3(tiles(m, n)),
+                       dim3(LTPB), 0, s, g);
     // 4. Z (m x n) = Y . Q_n^T         A = Y (m x n), B = Qn (n x n); FP64 out
     g = LpArgs{};
     g.skip = c.skip;
     g.M = m; g.N = n; g.K = n;
-    g.A[0] = c.u_t; g.A[1] = c.u_b; g.B[0] = c.Qn; g.O[0] = c.zt; g.O[1] = c.zb;
-    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, true, float, float, double, EPI_STORE>),
-                       dim3(tiles(m, n)), dim3(LTPB), 0, s, g);
+    g.A[0] = op(c.u[0]); g.A[1] = op(c.u[1]); g.B[0] = op(c.Qn);
+    g.O[0][0] = c.zt; g.O[1][0] = c.zb;
+    g.vec = vec_ok(g);
+    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, true, OUT_F64, EPI_STORE>), dim3(tiles(m, n)),
+                       dim3(LTPB), 0, s, g);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t chain_grouped(const GroupedChain &c, hipStream_t s)
+{
+    constexpr int OUT = (MODE == MCA_PREC_FP32) ? OUT_F32 : (MODE == MCA_PREC_BF16X3) ? OUT_BF2 : OUT_BF1;
+    const size_t es = (MODE == MCA_PREC_FP32) ? 4 : 2;
+    {
+        const int blocks = (int)std::min<size_t>((c.len + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_split<MODE>, dim3(blocks), dim3(256), 0, s, c.r, nullptr, c.len,
+                           c.x.p[0], c.x.p[1], nullptr, nullptr, nullptr);
+    }
+    GroupedLp g{};
+    g.a_inst = c.a_inst;
+    g.a_stride = c.a_stride;
+    g.ctl = c.ctl;
+    g.data_elem_bytes = es;
+    g.out_elem_bytes = es;
+    auto set = [&](int step, const LpPlanes &in, const LpPlanes &out) {
+        g.descs = c.descs[step];
+        g.tiles = c.tiles[step];
+        g.data[0] = in.p[0];
+        g.data[1] = in.p[1];
+        g.out[0] = out.p[0];
+        g.out[1] = out.p[1];
+    };
+    set(0, c.x, c.u);
+    hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, 2, false, OUT, EPI_STORE>), dim3(c.ntiles[0]),
+                       dim3(LTPB), 0, s, g);
+    set(1, c.u, c.w);
+    hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, 2, true, OUT, EPI_PERMODE>), dim3(c.ntiles[1]),
+                       dim3(LTPB), 0, s, g);
+    set(2, c.w, c.u);
+    hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, 2, false, OUT, EPI_STORE>), dim3(c.ntiles[2]),
+                       dim3(LTPB), 0, s, g);
+    LpPlanes z;
+    z.p[0] = c.z;
+    z.p[1] = nullptr;
+    set(3, c.u, z);
+    g.out_elem_bytes = 8;
+    hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, 2, true, OUT_F64, EPI_STORE>),
+                       dim3(c.ntiles[3]), dim3(LTPB), 0, s, g);
     return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t launch_precond_lowprec_grouped(int precision, const GroupedChain &c, hipStream_t s)
+{
+    switch (precision) {
+    case MCA_PREC_FP32: return chain_grouped<MCA_PREC_FP32>(c, s);
+    case MCA_PREC_BF16: return chain_grouped<MCA_PREC_BF16>(c, s);
+    case MCA_PREC_BF16X3: return chain_grouped<MCA_PREC_BF16X3>(c, s);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_precond_lowprec(int precision, const LowPrecChain &c, hipStream_t s)
 {
@@ -304,6 +500,21 @@ hipError_t launch_precond_lowprec(int precision, const LowPrecChain &c, hipStrea
     case MCA_PREC_BF16: return chain<MCA_PREC_BF16>(c, s);
     case MCA_PREC_BF16X3: return chain<MCA_PREC_BF16X3>(c, s);
     default: return hipErrorInvalidValue;
+    }
+}
+
+// FP64 eigenbasis -> FP32 values or bf16 hi/lo (host, at plan upload).
+void split_host(const double *src, size_t count, int precision, void *p0, void *p1)
+{
+    for (size_t k = 0; k < count; ++k) {
+        const float f = (float)src[k];
+        if (precision == MCA_PREC_FP32) {
+            static_cast<float *>(p0)[k] = f;
+        } else {
+            const __bf16 hi = (__bf16)f;
+            static_cast<__bf16 *>(p0)[k] = hi;
+            static_cast<__bf16 *>(p1)[k] = (__bf16)(f - (float)hi);
+        }
     }
 }
 

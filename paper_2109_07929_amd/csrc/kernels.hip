@@ -5,63 +5,20 @@
 // vector of the coupled system is the top array followed by the bottom array
 // (length 2mn, the paper's stacking [V_t; V_b] of eq. (F)).
 //
-// Wire stencils are written in branch-current form: the product of a wire
-// matrix (eq. (G), with terminations at both wire ends) with x at node k is
-//   sum over the node's segments of g (x_k - x_neighbour)
-//   + end conductance * x_k at the wire's first / last node,
-// which equals the tridiagonal product exactly in real arithmetic and keeps
-// the residual's rounding proportional to the branch currents.
-#include "mca_internal.h"
+// Wire stencils are written in branch-current form (dev::wire_apply), which
+// equals the tridiagonal product exactly in real arithmetic and keeps the
+// residual's rounding proportional to the branch currents.
+#include "device_common.h"
 
 namespace mca {
 namespace {
 
-constexpr int TPB = 256;
+using dev::block_sum;
+using dev::sum_partials;
+using dev::TPB;
+using dev::wire_apply;
+
 constexpr int kMaxReduceBlocks = 1024;
-
-__device__ __forceinline__ double wire_apply(const Wire w, int k, double xk, double xm, double xp)
-{
-    double s = (k > 0) ? w.g * (xk - xm) : w.end0 * xk;
-    s += (k + 1 < w.len) ? w.g * (xk - xp) : w.end1 * xk;
-    return s;
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Sum over the block in a fixed order; the result is valid in every thread.
-template <int NC>
-__device__ __forceinline__ void block_sum(double (&v)[NC])
-{
-    __shared__ double sh[NC][TPB / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        double w = wave_sum(v[c]);
-        if (lane == 0) sh[c][wave] = w;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < TPB / 64; ++w) s += sh[c][w];
-        v[c] = s;
-    }
-    __syncthreads();
-}
-
-// Sum of nb per-block partials, identical in every block (fixed order).
-__device__ __forceinline__ double sum_partials(const double *__restrict__ p, int nb)
-{
-    double v[1] = {0.0};
-    for (int b = threadIdx.x; b < nb; b += TPB) v[0] += p[b];
-    block_sum<1>(v);
-    return v[0];
-}
 
 // --------------------------------------------------------------- residual
 // F_t = G_t V_t + I - Y_t, F_b = G_b V_b - I (eqs. (MNA)/(F)); D = dI/du.

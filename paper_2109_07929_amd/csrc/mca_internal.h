@@ -25,7 +25,9 @@ struct DevPlan {
     const double *Qm, *QmT;   // m x m: Qm[i*m + p] = entry i of eigenvector p of G_bot
     const double *Qn, *QnT;   // n x n: Qn[j*n + q] = entry j of eigenvector q of G_top
     const double *lb, *lt;    // eigenvalues of G_bot (m) and G_top (n), ascending
-    const float *Qm32, *QmT32, *Qn32, *QnT32;   // FP32 copies (reduced-precision modes)
+    // reduced-precision copies: FP32, and bfloat16 hi / lo planes (v = hi + lo)
+    const float *Qm32, *QmT32, *Qn32, *QnT32;
+    const void *QmH, *QmL, *QmTH, *QmTL, *QnH, *QnL, *QnTH, *QnTL;
 };
 
 }  // namespace mca
@@ -102,17 +104,60 @@ extern int gemm_variant;   // kernel variant (tuning only; 0 = default)
 
 // Per-mode preconditioner in reduced precision (gemm_lp.hip): four NT products
 // on FP32 / BF16 MFMA with the per-mode 2x2 solve in the second one.
+// An operand in its MFMA format: FP32 values in p[0], or bfloat16 hi (p[0]) and
+// lo (p[1]) planes.
+struct LpPlanes {
+    void *p[2];
+};
 struct LowPrecChain {
     int m, n;
     double a1, a2;
     const int *skip;
-    const float *QnT, *QmT, *Qm, *Qn;   // FP32 eigenbases
+    LpPlanes QnT, QmT, Qm, Qn;          // eigenbases
     const double *lt, *lb;              // eigenvalues of G_top, G_bot
     const double *rt, *rb;              // input r (FP64)
-    float *u_t, *u_b, *w_t, *w_b;       // FP32 intermediates, m*n each
+    LpPlanes x[2], u[2], w[2];          // workspace: split r and two intermediates, m*n each
     double *zt, *zb;                    // output z (FP64)
 };
 hipError_t launch_precond_lowprec(int precision, const LowPrecChain &c, hipStream_t s);
+
+// Grouped form over a batch of crossbars (batch.hip): one crossbar's product
+// in a grouped launch.  Data operands and outputs of every crossbar sit at an
+// element offset from the launch's base planes (layer 1 at + mn).
+struct LpDesc {
+    int M, N, K, inst;
+    const void *Q[2];                   // the crossbar's eigenbasis operand (planes)
+    size_t off_data, off_out, mn;
+    const double *lam_row, *lam_col;    // eigenvalues along output rows / columns
+    int vec;                            // 16-byte aligned rows, K % 8 == 0
+};
+struct GroupedLp {
+    const LpDesc *descs;
+    const int4 *tiles;                  // (descriptor, m0, n0, unused)
+    const void *data[2];
+    void *out[2];
+    size_t data_elem_bytes, out_elem_bytes;
+    const double *a_inst;               // per-crossbar a1 = a2, stride a_stride doubles
+    int a_stride;
+    const int *ctl;                     // per-crossbar control blocks (4 ints), stop flag first
+};
+// The four products of the per-mode chain over a batch, after splitting the
+// whole Krylov vector r (len doubles) into operand planes x.
+struct GroupedChain {
+    const LpDesc *descs[4];
+    const int4 *tiles[4];
+    int ntiles[4];
+    const double *r;
+    size_t len;
+    LpPlanes x, u, w;
+    double *z;
+    const double *a_inst;
+    int a_stride;
+    const int *ctl;
+};
+hipError_t launch_precond_lowprec_grouped(int precision, const GroupedChain &c, hipStream_t s);
+// host: FP64 -> FP32 (p0) or bfloat16 hi (p0) + lo (p1)
+void split_host(const double *src, size_t count, int precision, void *p0, void *p1);
 
 // Krylov kernels over vectors of even length len (= 2mn), 16-byte aligned.
 // partial dot products x.y -> partials[reduce_blocks(len)] (any length)

@@ -103,6 +103,7 @@ void wire_tridiag(const Wire &w, std::vector<double> &diag, std::vector<double> 
 struct PlanLayout {
     double *Qm, *QmT, *Qn, *QnT, *lb, *lt;
     float *Qm32, *QmT32, *Qn32, *QnT32;
+    uint16_t *QmH, *QmL, *QmTH, *QmTL, *QnH, *QnL, *QnTH, *QnTL;   // bfloat16 planes
     size_t bytes;
 };
 
@@ -121,15 +122,24 @@ PlanLayout plan_layout(const mca_plan *P, void *base)
     L.QmT32 = c.take<float>(m * m);
     L.Qn32 = c.take<float>(n * n);
     L.QnT32 = c.take<float>(n * n);
+    L.QmH = c.take<uint16_t>(m * m);
+    L.QmL = c.take<uint16_t>(m * m);
+    L.QmTH = c.take<uint16_t>(m * m);
+    L.QmTL = c.take<uint16_t>(m * m);
+    L.QnH = c.take<uint16_t>(n * n);
+    L.QnL = c.take<uint16_t>(n * n);
+    L.QnTH = c.take<uint16_t>(n * n);
+    L.QnTL = c.take<uint16_t>(n * n);
     L.bytes = c.size();
     return L;
 }
 
-// Workspace of the preconditioner: up to four m x n FP64 buffers, or four
-// m x n FP32 buffers in the reduced-precision modes.
+// Workspace of the preconditioner: up to four m x n FP64 buffers, or six
+// m x n operands of 4 bytes per value (FP32, or two bfloat16 planes) in the
+// reduced-precision modes.
 struct PrecondWs {
     double *b0t, *b0b, *b1t, *b1b;
-    float *f[4];
+    LpPlanes lp[6];
 };
 
 PrecondWs precond_layout(const mca_plan *P, Carver &c, int form, int precision = MCA_PREC_FP64)
@@ -138,7 +148,15 @@ PrecondWs precond_layout(const mca_plan *P, Carver &c, int form, int precision =
     PrecondWs w{};
     if (form == MCA_PRECOND_NONE) return w;
     if (precision != MCA_PREC_FP64) {
-        for (auto &f : w.f) f = c.take<float>(mn);
+        for (auto &op : w.lp) {
+            if (precision == MCA_PREC_FP32) {
+                op.p[0] = c.take<float>(mn);
+                op.p[1] = nullptr;
+            } else {
+                op.p[0] = c.take<uint16_t>(mn);
+                op.p[1] = c.take<uint16_t>(mn);
+            }
+        }
         return w;
     }
     w.b0t = c.take<double>(mn);
@@ -299,14 +317,30 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
         c.a1 = a1;
         c.a2 = a2;
         c.skip = skip;
-        c.QnT = d.QnT32; c.QmT = d.QmT32; c.Qm = d.Qm32; c.Qn = d.Qn32;
+        auto planes = [](const void *a, const void *b) {
+            LpPlanes p;
+            p.p[0] = const_cast<void *>(a);
+            p.p[1] = const_cast<void *>(b);
+            return p;
+        };
+        if (precision == MCA_PREC_FP32) {
+            c.QnT = planes(d.QnT32, nullptr); c.QmT = planes(d.QmT32, nullptr);
+            c.Qm = planes(d.Qm32, nullptr); c.Qn = planes(d.Qn32, nullptr);
+        } else {
+            c.QnT = planes(d.QnTH, d.QnTL); c.QmT = planes(d.QmTH, d.QmTL);
+            c.Qm = planes(d.QmH, d.QmL); c.Qn = planes(d.QnH, d.QnL);
+        }
         c.lt = d.lt; c.lb = d.lb;
         c.rt = rt; c.rb = rb;
-        c.u_t = w.f[0]; c.u_b = w.f[1]; c.w_t = w.f[2]; c.w_b = w.f[3];
+        for (int b = 0; b < 2; ++b) {
+            c.x[b] = w.lp[b];
+            c.u[b] = w.lp[2 + b];
+            c.w[b] = w.lp[4 + b];
+        }
         c.zt = zt; c.zb = zb;
         MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
         MCA_TRY(launch_precond_lowprec(precision, c, s));
-        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 4, slot));
+        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 5, slot));   // operand split + 4 products
         return MCA_OK;
     }
     const int m = P->geom.m, n = P->geom.n;
@@ -605,14 +639,14 @@ mca_status mca_plan_upload(mca_plan *P, void *dev_buf, size_t bytes, void *strea
         }
     std::memcpy(H.lb, P->lb.data(), m * sizeof(double));
     std::memcpy(H.lt, P->lt.data(), n * sizeof(double));
-    for (size_t k = 0; k < m * m; ++k) {
-        H.Qm32[k] = (float)H.Qm[k];
-        H.QmT32[k] = (float)H.QmT[k];
-    }
-    for (size_t k = 0; k < n * n; ++k) {
-        H.Qn32[k] = (float)H.Qn[k];
-        H.QnT32[k] = (float)H.QnT[k];
-    }
+    split_host(H.Qm, m * m, MCA_PREC_FP32, H.Qm32, nullptr);
+    split_host(H.QmT, m * m, MCA_PREC_FP32, H.QmT32, nullptr);
+    split_host(H.Qn, n * n, MCA_PREC_FP32, H.Qn32, nullptr);
+    split_host(H.QnT, n * n, MCA_PREC_FP32, H.QnT32, nullptr);
+    split_host(H.Qm, m * m, MCA_PREC_BF16X3, H.QmH, H.QmL);
+    split_host(H.QmT, m * m, MCA_PREC_BF16X3, H.QmTH, H.QmTL);
+    split_host(H.Qn, n * n, MCA_PREC_BF16X3, H.QnH, H.QnL);
+    split_host(H.QnT, n * n, MCA_PREC_BF16X3, H.QnTH, H.QnTL);
     MCA_TRY(hipMemcpyAsync(dev_buf, img.data(), P->dev_bytes, hipMemcpyHostToDevice, s));
     MCA_TRY(hipStreamSynchronize(s));
     PlanLayout L = plan_layout(P, dev_buf);
@@ -628,6 +662,8 @@ mca_status mca_plan_upload(mca_plan *P, void *dev_buf, size_t bytes, void *strea
     P->dev.QmT32 = L.QmT32;
     P->dev.Qn32 = L.Qn32;
     P->dev.QnT32 = L.QnT32;
+    P->dev.QmH = L.QmH; P->dev.QmL = L.QmL; P->dev.QmTH = L.QmTH; P->dev.QmTL = L.QmTL;
+    P->dev.QnH = L.QnH; P->dev.QnL = L.QnL; P->dev.QnTH = L.QnTH; P->dev.QnTL = L.QnTL;
     return MCA_OK;
 }
 

@@ -1,0 +1,159 @@
+"""Parity of mca_solve_batched (many crossbars of different sizes in the same
+launches) with the CPU oracle, crossbar by crossbar, and with mca_solve.
+
+The bar is the solver's: every crossbar's voltages match the oracle's steady
+state to 1e-8 relative error (max over both layers of |V - V_ref| / max |V_ref|).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2109_07929_amd import Batch, Plan, synth
+from paper_2109_07929_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+PRECS = [B.MCA_PREC_FP32, B.MCA_PREC_BF16X3, B.MCA_PREC_BF16]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_err(gt, gb, rt, rb):
+    scale = max(np.abs(rt).max(), np.abs(rb).max())
+    return max(np.abs(gt - rt).max(), np.abs(gb - rb).max()) / scale
+
+
+def batch_solve(cbs, check=False, **opt):
+    bt = Batch([c.geom for c in cbs])
+    g = bt.concat([c.g_dev for c in cbs])
+    v = bt.concat([c.v_in for c in cbs])
+    kw = dict(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3)
+    kw.update(opt)
+    vt, vb, status, stats = bt.solve(g, v, B.options(**kw), check=check)
+    torch.cuda.synchronize()
+    return bt, [t.cpu().numpy() for t in bt.split(vt)], [t.cpu().numpy() for t in bt.split(vb)], \
+        status, stats
+
+
+def ragged_batch(seed=3):
+    # sizes off the 64-tile grid and odd products (unaligned offsets in the batch)
+    return synth.mc_batch(7, seed=seed, sizes=(5, 20, 33, 64, 72))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_ragged_vs_oracle(prec):
+    cbs = ragged_batch()
+    say(f"batch ragged prec={prec}: " + " ".join(f"{c.geom.m}x{c.geom.n}" for c in cbs))
+    bt, vts, vbs, status, stats = batch_solve(cbs, precision=prec)
+    assert status == B.MCA_OK
+    for b, c in enumerate(cbs):
+        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="band")
+        err = rel_err(vts[b], vbs[b], rt, rb)
+        st = stats[b]
+        say(f"  {c.geom.m}x{c.geom.n}: newton {st.newton_iters} krylov "
+            f"{list(st.krylov_history[:st.newton_iters])} relres {st.rel_residual:.1e} err {err:.1e}")
+        assert st.rel_residual <= 1e-10
+        assert err <= TOL
+
+
+def test_batch_matches_single_solves():
+    """Each crossbar of a batch follows mca_solve's iteration (same options)."""
+    cbs = synth.mc_batch(3, seed=11, sizes=(48, 64, 96))
+    _, vts, vbs, status, stats = batch_solve(cbs, precision=B.MCA_PREC_FP32)
+    assert status == B.MCA_OK
+    for b, c in enumerate(cbs):
+        plan = Plan(c.geom)
+        o = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_FP32)
+        g = torch.from_numpy(c.g_dev).cuda()
+        v = torch.from_numpy(c.v_in).cuda()
+        vt, vb, s1, st1 = plan.solve(g, v, o)
+        torch.cuda.synchronize()
+        err = rel_err(vts[b], vbs[b], vt.cpu().numpy(), vb.cpu().numpy())
+        say(f"  {c.geom.m}x{c.geom.n}: batch newton {stats[b].newton_iters} single "
+            f"{st1.newton_iters}; krylov {stats[b].krylov_iters} vs {st1.krylov_iters}; diff {err:.1e}")
+        assert stats[b].newton_iters == st1.newton_iters
+        assert abs(stats[b].krylov_iters - st1.krylov_iters) <= 2
+        assert err <= TOL
+
+
+@pytest.mark.parametrize("restart", [1, 3])
+def test_batch_restarts(restart):
+    cbs = ragged_batch(seed=5)
+    say(f"batch restart={restart}")
+    _, vts, vbs, status, stats = batch_solve(cbs, restart=restart, max_krylov=600)
+    assert status == B.MCA_OK
+    assert sum(s.restarts for s in stats) > 0
+    for b, c in enumerate(cbs):
+        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="band")
+        assert rel_err(vts[b], vbs[b], rt, rb) <= TOL
+
+
+def test_batch_mixed_outcomes():
+    """A non-finite crossbar and a zero-drive crossbar do not disturb the others."""
+    cbs = synth.mc_batch(4, seed=2, sizes=(16, 40))
+    cbs[1].g_dev[3, 2] = np.nan
+    cbs[2].v_in[:] = 0.0
+    _, vts, vbs, status, stats = batch_solve(cbs)
+    assert status == B.MCA_ERR_NONFINITE
+    assert np.all(vts[2] == 0.0) and np.all(vbs[2] == 0.0)
+    for b in (0, 3):
+        c = cbs[b]
+        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="band")
+        assert rel_err(vts[b], vbs[b], rt, rb) <= TOL
+
+
+def test_batch_initial_guess_at_solution():
+    cbs = ragged_batch(seed=8)
+    bt, vts, vbs, status, stats = batch_solve(cbs)
+    assert status == B.MCA_OK
+    g = bt.concat([c.g_dev for c in cbs])
+    v = bt.concat([c.v_in for c in cbs])
+    guess = (bt.concat(vts), bt.concat(vbs))
+    o = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3)
+    vt, vb, status, stats = bt.solve(g, v, o, guess=guess)
+    assert status == B.MCA_OK
+    assert all(s.newton_iters == 0 for s in stats)
+    torch.cuda.synchronize()
+    assert torch.equal(vt, guess[0]) and torch.equal(vb, guess[1])
+
+
+def test_batch_of_one_and_unsupported_options():
+    c = synth.crossbar(24, 20, seed=4)
+    _, vts, vbs, status, stats = batch_solve([c])
+    assert status == B.MCA_OK
+    rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="band")
+    assert rel_err(vts[0], vbs[0], rt, rb) <= TOL
+    bt = Batch([c.geom])
+    g = bt.concat([c.g_dev])
+    v = bt.concat([c.v_in])
+    with pytest.raises(B.MCAError):
+        bt.solve(g, v, B.options())          # FP64 / literal: single-crossbar only
+
+
+def test_batch_monte_carlo_256():
+    """The Monte-Carlo workload: 256 crossbars with m, n drawn from {64, ..., 512}.
+    Every crossbar's final residual is recomputed by the oracle on the host; four
+    sampled crossbars are compared with the oracle's steady state."""
+    cbs = synth.mc_batch(256, seed=0)
+    say(f"batch MC 256: {sum(c.geom.m * c.geom.n for c in cbs)} crosspoints")
+    bt, vts, vbs, status, stats = batch_solve(cbs)
+    assert status == B.MCA_OK
+    worst = 0.0
+    for b, c in enumerate(cbs):
+        ft, fb = oracle.residual(c.geom, c.g_dev, c.v_in, vts[b], vbs[b])[:2]
+        rel = np.sqrt((ft ** 2).sum() + (fb ** 2).sum()) / oracle.source_norm(c.geom, c.v_in)
+        worst = max(worst, rel)
+    say(f"  worst oracle residual {worst:.2e}; newton "
+        f"{min(s.newton_iters for s in stats)}..{max(s.newton_iters for s in stats)}")
+    assert worst <= 2e-10
+    for b in (0, 1, 100, 255):
+        c = cbs[b]
+        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="cg")
+        err = rel_err(vts[b], vbs[b], rt, rb)
+        say(f"  sample {b} {c.geom.m}x{c.geom.n}: err {err:.1e}")
+        assert err <= TOL

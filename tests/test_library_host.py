@@ -130,3 +130,38 @@ def test_eigen_1024_orthogonal():
     T = _tri(1024, geo.g_top, geo.g_src, geo.g_top_end)
     assert np.abs(Q.T @ Q - np.eye(1024)).max() < 2e-14
     assert np.abs(T @ Q - Q * lam).max() < 1e-14
+
+
+def test_batch_host_setup():
+    """mca_batch_create: offsets of the concatenated arrays, per-crossbar eigen data,
+    option validation of the batched solve (host only)."""
+    geoms = [B.geometry(3, 5), B.geometry(64, 17, g_top=0.3), B.geometry(1, 1)]
+    h = B.mca_batch_create(geoms)
+    try:
+        cross, rows = B.mca_batch_offsets(h, 3)
+        assert list(cross) == [0, 15, 15 + 64 * 17, 15 + 64 * 17 + 1]
+        assert list(rows) == [0, 3, 67, 68]
+        assert B.mca_batch_device_bytes(h) > 0
+        ok = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3)
+        n_ok = B.mca_batch_workspace_bytes(h, ok)
+        assert n_ok > 0 and n_ok % 256 == 0
+        assert B.mca_batch_workspace_bytes(h, None) == n_ok
+        # FP64 and the literal form are single-crossbar only
+        assert B.mca_batch_workspace_bytes(h, B.options()) == 0
+        assert B.mca_batch_workspace_bytes(
+            h, B.options(precond=B.MCA_PRECOND_LITERAL, precision=B.MCA_PREC_FP32)) == 0
+        assert B.mca_batch_workspace_bytes(h, B.options(
+            precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_FP32, restart=0)) == 0
+        # larger restart -> more Krylov storage
+        big = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3, restart=40)
+        assert B.mca_batch_workspace_bytes(h, big) > n_ok
+    finally:
+        B.mca_batch_destroy(h)
+
+
+def test_batch_create_rejects_bad_geometry():
+    with pytest.raises(B.MCAError) as e:
+        B.mca_batch_create([B.geometry(4, 4), B.geometry(0, 4)])
+    assert e.value.status == B.MCA_ERR_INVALID_ARG
+    with pytest.raises(B.MCAError):
+        B.mca_batch_create([])
