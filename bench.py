@@ -7,6 +7,13 @@ Newton tolerance 1e-10 (||F|| / ||Y||) with GMRES(30) tolerance 1e-8, inputs
 already resident in HBM.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 1024]
+
+With --mc COUNT a step is instead one batched solve (mca_solve_batched) of
+COUNT Monte-Carlo crossbars of uneven sizes (m, n drawn from {64, ..., 512},
+16-level weights with lognormal device variation, wire conductance drawn per
+crossbar); with --batch COUNT, of COUNT standard size x size crossbars (seeds
+seed .. seed + COUNT - 1).  Both are timed beside a loop of per-crossbar
+mca_solve calls with the same options.
 """
 
 from __future__ import annotations
@@ -39,6 +46,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-timing", action="store_true",
                    help="do not time kernel classes with HIP events (no roofline object)")
+    p.add_argument("--mc", type=int, default=0,
+                   help="batched Monte-Carlo workload of this many crossbars instead")
+    p.add_argument("--batch", type=int, default=0,
+                   help="batched solve of this many size x size crossbars instead")
+    p.add_argument("--no-loop", action="store_true",
+                   help="with --mc / --batch: skip the per-crossbar loop comparison")
     p.add_argument("--copy-calib", action="store_true",
                    help="after the timed solves, copy a 256 MiB float64 array device-to-device "
                         "three times: a kernel of known traffic that calibrates the "
@@ -77,12 +90,117 @@ def cpu_baseline(cb):
                       f"to the FP64 floor), single thread, {dt:.2f} s"}
 
 
+def bench_batched(args):
+    """Batched workloads: one step = one mca_solve_batched of all the crossbars."""
+    import numpy as np
+    import torch
+
+    from paper_2109_07929_amd import Batch, Plan, synth
+    from paper_2109_07929_amd import binding as B
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    prec = {"fp32": B.MCA_PREC_FP32, "bf16x3": B.MCA_PREC_BF16X3, "bf16": B.MCA_PREC_BF16}.get(
+        args.precision, B.MCA_PREC_BF16X3)
+    pname = {B.MCA_PREC_FP32: "fp32", B.MCA_PREC_BF16X3: "bf16x3", B.MCA_PREC_BF16: "bf16"}[prec]
+    if args.mc:
+        cbs = synth.mc_batch(args.mc, seed=args.seed)
+        what = (f"batched Monte-Carlo, {args.mc} crossbars with m, n in {{64..512}}")
+    else:
+        cbs = [synth.crossbar(args.size, args.size, seed=args.seed + i) for i in range(args.batch)]
+        what = f"batched, {args.batch} crossbars of {args.size}x{args.size}"
+    count = len(cbs)
+    t0 = time.perf_counter()
+    bt = Batch([c.geom for c in cbs], device=dev)
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+    g = bt.concat([c.g_dev for c in cbs])
+    v = bt.concat([c.v_in for c in cbs])
+    vt = torch.zeros(bt.total, dtype=torch.float64, device=dev)
+    vb = torch.zeros_like(vt)
+    opts = B.options(precond=B.MCA_PRECOND_PERMODE, precision=prec)
+    ws = bt.workspace(opts)
+    stream = torch.cuda.current_stream()
+    rows = int(bt.rows[-1])
+
+    def step():
+        return B.mca_solve_batched(bt.handle, bt.count, bt.total, rows, g, v, vt, vb, opts, ws,
+                                   stream)[1]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"# warmup done ({args.warmup} batched solves)", file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        stats = step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    value = count * 1e3 / ms_per_step
+    newton = [s.newton_iters for s in stats]
+    krylov = [s.krylov_iters for s in stats]
+    print(f"# batched: {ms_per_step:.2f} ms per batch", file=sys.stderr, flush=True)
+
+    loop = None
+    if not args.no_loop:
+        # the same crossbars one mca_solve call after another, same options
+        plans = [Plan(c.geom, device=dev) for c in cbs]
+        data = [(torch.from_numpy(c.g_dev).to(dev), torch.from_numpy(c.v_in).to(dev),
+                 torch.zeros((c.geom.m, c.geom.n), dtype=torch.float64, device=dev),
+                 torch.zeros((c.geom.m, c.geom.n), dtype=torch.float64, device=dev)) for c in cbs]
+        wss = [p.workspace(opts) for p in plans]
+
+        def loop_step():
+            for p, (gg, vv, ot, ob), w in zip(plans, data, wss):
+                B.mca_solve(p.handle, p.m, p.n, gg, vv, ot, ob, opts, w, stream)
+
+        loop_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(1, min(3, args.steps))
+        for _ in range(reps):
+            loop_step()
+        torch.cuda.synchronize()
+        loop_ms = 1e3 * (time.perf_counter() - t0) / reps
+        loop = {"ms_per_batch": round(loop_ms, 3), "solves_per_s": round(count * 1e3 / loop_ms, 2),
+                "speedup_of_batched": round(loop_ms / ms_per_step, 3)}
+        print(f"# loop: {loop_ms:.2f} ms per batch", file=sys.stderr, flush=True)
+
+    sizes = [c.geom.m * c.geom.n for c in cbs]
+    out = {
+        "metric": "MCA solves/s at 1024x1024, 1e-8 rel residual: plain FP64 vs batched+warm+mixed",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"f64 (preconditioner {pname})",
+        "data": "synthetic",
+        "config": {"workload": f"{what} ({sum(sizes)} crosspoints), seed {args.seed}, "
+                               f"Newton-FGMRES(30) with a {pname} per-mode preconditioner",
+                   "newton_tol": opts.newton_tol, "gmres_tol": opts.gmres_tol,
+                   "setup_ms": round(setup_ms, 1),
+                   "newton_iters": [min(newton), max(newton)],
+                   "krylov_iters": [min(krylov), max(krylov)]},
+        "per_crossbar_loop": loop,
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this solver has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.mc or args.batch:
+        return bench_batched(args)
     import numpy as np
     import torch
 
