@@ -62,6 +62,12 @@ def _load():
     lib.orc_jacobian_solve_band.argtypes = [G, _P, _P, _P, _P, _P]
     lib.orc_jacobian_solve_cg.argtypes = [G, _P, _P, _P, _P, _P, d, C.c_int]
     lib.orc_solve.argtypes = [G, _P, _P, _P, _P, d, C.c_int, C.c_int, _P]
+    lib.orc_mhat_inverse_apply.argtypes = [G, d, d, _P, _P]
+    lib.orc_mhat_inverse_apply.restype = None
+    lib.orc_precond_apply_approx.argtypes = [G, d, d, _P, _P, _P, _P]
+    lib.orc_precond_apply_approx.restype = None
+    lib.orc_jacobi_apply.argtypes = [G, _P, _P, _P, _P, _P]
+    lib.orc_jacobi_apply.restype = None
     _lib = lib
     return lib
 
@@ -138,6 +144,28 @@ def precond_apply(geom, a1: float, a2: float, r_t, r_b, method: str = "auto"):
     rc = fn(C.byref(_geom(geom)), float(a1), float(a2), _f64(r_t), _f64(r_b), zt, zb)
     if rc != 0:
         raise RuntimeError(f"oracle precond_apply failed ({rc})")
+    return zt, zb
+
+
+def mhat_inverse_apply(geom, a1: float, a2: float, w):
+    """Mhat^{-1} w of eqs. (Mhat), (M-1hat), (2matrix4): G2hat^{-1} W G1^{-1}."""
+    out = np.zeros((geom.m, geom.n))
+    _load().orc_mhat_inverse_apply(C.byref(_geom(geom)), float(a1), float(a2), _f64(w), out)
+    return out
+
+
+def precond_apply_approx(geom, a1: float, a2: float, r_t, r_b):
+    """(z_t, z_b) = eq. (block) with the paper's approximation M ~ Mhat."""
+    zt, zb = np.zeros((geom.m, geom.n)), np.zeros((geom.m, geom.n))
+    _load().orc_precond_apply_approx(C.byref(_geom(geom)), float(a1), float(a2), _f64(r_t),
+                                     _f64(r_b), zt, zb)
+    return zt, zb
+
+
+def jacobi_apply(geom, d, r_t, r_b):
+    """(z_t, z_b) = r ./ diag(J(d)): the point-Jacobi baseline."""
+    zt, zb = np.zeros((geom.m, geom.n)), np.zeros((geom.m, geom.n))
+    _load().orc_jacobi_apply(C.byref(_geom(geom)), _f64(d), _f64(r_t), _f64(r_b), zt, zb)
     return zt, zb
 
 

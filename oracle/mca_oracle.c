@@ -16,6 +16,9 @@
  *     that the perpendicular natural indexing gives (Section III-A);
  *   - the preconditioner solve z = P^{-1} r with P from eq. (P), by a direct
  *     method on the assembled P (dense LU, or band Cholesky of a symmetrised P);
+ *   - the paper's approximate preconditioner (M ~ Mhat, eqs. (Mhat) to
+ *     (2matrix4)) in the paper's order with tridiagonal solves, and the
+ *     point-Jacobi preconditioner as a baseline;
  *   - the steady state F(V) = 0 by Newton's method (eq. (Newton3)) whose
  *     linear steps are direct band-Cholesky solves of J (oracle A), or
  *     preconditioned CG with exact wire-line block solves (oracle B, for sizes
@@ -586,4 +589,98 @@ int orc_solve(const orc_geom *G, const double *g_dev, const double *v_in,
     }
     free(f); free(d); free(dv); free(nt); free(nf); free(nd);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The paper's approximate preconditioner (Section III-B, eqs. (diagM) to
+ * (2matrix4)).  The Schur complement M of eq. (M) is -a2 I + (G2 (x) G1)/a1
+ * with G1 = G_top + a1 I (eq. (G1), n x n) and G2 = G_bot + a2 I (eq. (G2),
+ * m x m).  Dropping the -a2 I term (small against the wire conductance,
+ * eq. (condition)) gives M ~ Mhat = G2hat (x) G1 with G2hat = G2 / a1
+ * (eq. (Mhat); the off-diagonal of eq. (G2hat) is read as -g/a1), whose
+ * inverse is G2hat^{-1} (x) G1^{-1} (eq. (M-1hat)).  With the row-major
+ * vec of an m x n array, (A (x) B) vec(X) = vec(A X B^T), so eq. (2matrix4)
+ * reads  Mhat^{-1} w  <->  G2hat^{-1} W G1^{-1}: one tridiagonal solve with
+ * G2hat down every column of W and one with G1 along every row.            */
+
+/* Tridiagonal solve T x = b by Gaussian elimination without pivoting (the
+ * Thomas algorithm; T is diagonally dominant here).  diag has len entries,
+ * off len-1 (symmetric T).  x and b may alias; `stride` steps between the
+ * entries of b / x.                                                         */
+static void tridiag_solve(int len, const double *diag, const double *off,
+                          const double *b, double *x, size_t stride)
+{
+    double *cp = malloc(sizeof(double) * len), *dp = malloc(sizeof(double) * len);
+    cp[0] = (len > 1) ? off[0] / diag[0] : 0.0;
+    dp[0] = b[0] / diag[0];
+    for (int k = 1; k < len; ++k) {
+        double den = diag[k] - off[k - 1] * cp[k - 1];
+        cp[k] = (k + 1 < len) ? off[k] / den : 0.0;
+        dp[k] = (b[k * stride] - off[k - 1] * dp[k - 1]) / den;
+    }
+    x[(size_t)(len - 1) * stride] = dp[len - 1];
+    for (int k = len - 2; k >= 0; --k)
+        x[k * stride] = dp[k] - cp[k] * x[(size_t)(k + 1) * stride];
+    free(cp); free(dp);
+}
+
+/* out = Mhat^{-1} w (eqs. (M-1hat), (2matrix4)); w, out m x n row-major. */
+void orc_mhat_inverse_apply(const orc_geom *G, double a1, double a2,
+                            const double *w, double *out)
+{
+    int m = G->m, n = G->n;
+    double *g1d = malloc(sizeof(double) * n), *g1o = malloc(sizeof(double) * (n + 1));
+    double *g2d = malloc(sizeof(double) * m), *g2o = malloc(sizeof(double) * (m + 1));
+    /* G1 = G_top + a1 I (eq. (G1)); G2hat = (G_bot + a2 I) / a1 (eqs. (G2), (G2hat)) */
+    top_wire(G, g1d, g1o);
+    for (int j = 0; j < n; ++j) g1d[j] += a1;
+    bot_wire(G, g2d, g2o);
+    for (int i = 0; i < m; ++i) g2d[i] = (g2d[i] + a2) / a1;
+    for (int i = 0; i + 1 < m; ++i) g2o[i] /= a1;
+    memcpy(out, w, sizeof(double) * (size_t)m * n);
+    /* G2hat^{-1} W: one solve down each column j */
+    for (int j = 0; j < n; ++j) tridiag_solve(m, g2d, g2o, out + j, out + j, (size_t)n);
+    /* (G2hat^{-1} W) G1^{-1}: one solve along each row i (G1 symmetric) */
+    for (int i = 0; i < m; ++i)
+        tridiag_solve(n, g1d, g1o, out + (size_t)i * n, out + (size_t)i * n, 1);
+    free(g1d); free(g1o); free(g2d); free(g2o);
+}
+
+/* z = Phat^{-1} r: the block-inversion formula of eq. (block) with M replaced
+ * by Mhat, in the paper's order:
+ *   w   = r_b + (G_b + a2 I) r_t / a1       (-D B^{-1} r_t + r_b, B = -a1 I)
+ *   z_t = Mhat^{-1} w
+ *   z_b = ((G_t + a1 I) z_t - r_t) / a1     (B^{-1} (r_t - A z_t))          */
+void orc_precond_apply_approx(const orc_geom *G, double a1, double a2,
+                              const double *rt, const double *rb,
+                              double *zt, double *zb)
+{
+    size_t mn = (size_t)G->m * G->n;
+    double *gt = malloc(sizeof(double) * mn), *gb = malloc(sizeof(double) * mn);
+    double *w = malloc(sizeof(double) * mn);
+    apply_layers(G, rt, rt, gt, gb);   /* gb = G_b r_t (gt unused) */
+    for (size_t q = 0; q < mn; ++q) w[q] = rb[q] + (gb[q] + a2 * rt[q]) / a1;
+    orc_mhat_inverse_apply(G, a1, a2, w, zt);
+    apply_layers(G, zt, zt, gt, gb);   /* gt = G_t z_t */
+    for (size_t q = 0; q < mn; ++q) zb[q] = (gt[q] + a1 * zt[q] - rt[q]) / a1;
+    free(gt); free(gb); free(w);
+}
+
+/* Jacobi (point-diagonal) preconditioner of J, a baseline: z = r ./ diag(J)
+ * with diag(J) = diag(G_t) + D on the top layer, diag(G_b) + D below.      */
+void orc_jacobi_apply(const orc_geom *G, const double *d, const double *rt,
+                      const double *rb, double *zt, double *zb)
+{
+    int m = G->m, n = G->n;
+    double *td = malloc(sizeof(double) * n), *to = malloc(sizeof(double) * (n + 1));
+    double *bd = malloc(sizeof(double) * m), *bo = malloc(sizeof(double) * (m + 1));
+    top_wire(G, td, to);
+    bot_wire(G, bd, bo);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j) {
+            size_t q = (size_t)i * n + j;
+            zt[q] = rt[q] / (td[j] + d[q]);
+            zb[q] = rb[q] / (bd[i] + d[q]);
+        }
+    free(td); free(to); free(bd); free(bo);
 }

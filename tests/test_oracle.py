@@ -377,6 +377,86 @@ def test_row_major_kronecker_vec_identity():
     np.testing.assert_allclose(np.kron(A, B) @ X.ravel(), (A @ X @ B.T).ravel(), rtol=1e-13)
 
 
+# ------------------------------------ the paper's approximation M ~ Mhat
+
+def _wire_dense(length, g, e0, e1):
+    A = np.zeros((length, length))
+    for k in range(length - 1):
+        A[k, k] += g
+        A[k + 1, k + 1] += g
+        A[k, k + 1] -= g
+        A[k + 1, k] -= g
+    A[0, 0] += e0
+    A[-1, -1] += e1
+    return A
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 4), (3, 1), (3, 4), (5, 3)])
+def test_mhat_inverse_is_kron_of_tridiagonal_inverses(m, n):
+    """eqs. (Mhat), (G2hat), (M-1hat): Mhat = G2hat (x) G1 with G2hat = (G_bot + a2 I)/a1
+    and G1 = G_top + a1 I; its inverse applied through eq. (2matrix4) equals a dense
+    numpy solve with the assembled Kronecker product."""
+    geom = _geom(m, n)
+    a1, a2 = 3e-3, 5e-4
+    G1 = _wire_dense(n, geom.g_top, geom.g_src, geom.g_top_end) + a1 * np.eye(n)
+    G2hat = (_wire_dense(m, geom.g_bot, geom.g_bot_end0, geom.g_bot_end1) + a2 * np.eye(m)) / a1
+    w = np.random.default_rng(4).standard_normal((m, n))
+    ref = np.linalg.solve(np.kron(G2hat, G1), w.ravel()).reshape(m, n)
+    out = oracle.mhat_inverse_apply(geom, a1, a2, w)
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (2, 5), (4, 3), (6, 6)])
+def test_approx_precond_equals_exact_when_a2_is_zero(m, n):
+    """Mhat drops only the -a2 I term of eq. (M): with a2 = 0 the approximate
+    preconditioner is exactly P^{-1} (dense LU of the assembled eq. (P))."""
+    geom = _geom(m, n)
+    a1 = 0.02
+    rng = np.random.default_rng(9)
+    rt, rb = rng.standard_normal((m, n)), rng.standard_normal((m, n))
+    P = _kron_P(geom, a1, 0.0)
+    z = np.linalg.solve(P, np.concatenate([rt.ravel(), rb.ravel()]))
+    zt, zb = oracle.precond_apply_approx(geom, a1, 0.0, rt, rb)
+    np.testing.assert_allclose(np.concatenate([zt.ravel(), zb.ravel()]), z, rtol=0,
+                               atol=1e-11 * np.abs(z).max())
+
+
+@pytest.mark.parametrize("m,n", [(3, 4), (5, 3), (6, 6)])
+@pytest.mark.parametrize("a", [2e-5, 1e-2])
+def test_approx_precond_inverts_P_without_its_lower_coupling(m, n, a):
+    """The Schur complement of [[G_t + a1 I, -a1 I], [0, G_b + a2 I]] is exactly
+    (G_b + a2 I)(G_t + a1 I)/a1 = Mhat, so eq. (block) with Mhat inverts P with its
+    -a2 I block removed.  Also: it differs from P^{-1} by O(a2)."""
+    geom = _geom(m, n)
+    a1 = a2 = a
+    rng = np.random.default_rng(5)
+    rt, rb = rng.standard_normal((m, n)), rng.standard_normal((m, n))
+    Phat = _kron_P(geom, a1, a2)
+    mn = m * n
+    Phat[mn:, :mn] = 0.0
+    zt, zb = oracle.precond_apply_approx(geom, a1, a2, rt, rb)
+    z = np.concatenate([zt.ravel(), zb.ravel()])
+    r = np.concatenate([rt.ravel(), rb.ravel()])
+    # the paper's order divides by a1: about log10(lambda_max / a1) digits are lost
+    lam_max = 4 * max(geom.g_top, geom.g_bot) + 1.0          # >= ||Phat||
+    tol = 64 * 2.2e-16 * (lam_max / a1) * lam_max * np.abs(z).max()
+    np.testing.assert_allclose(Phat @ z, r, rtol=0, atol=tol)
+    ze = np.linalg.solve(_kron_P(geom, a1, a2), r)
+    assert np.abs(z - ze).max() <= 0.5 * np.abs(ze).max()   # a different operator, but close
+    assert not np.allclose(z, ze, rtol=1e-12, atol=0)
+
+
+def test_jacobi_matches_dense_diagonal():
+    geom = _geom(4, 5)
+    rng = np.random.default_rng(6)
+    d = rng.uniform(1e-6, 1e-4, (4, 5))
+    rt, rb = rng.standard_normal((4, 5)), rng.standard_normal((4, 5))
+    diag = np.diag(oracle.dense_jacobian(geom, d))
+    zt, zb = oracle.jacobi_apply(geom, d, rt, rb)
+    np.testing.assert_allclose(np.concatenate([zt.ravel(), zb.ravel()]),
+                               np.concatenate([rt.ravel(), rb.ravel()]) / diag, rtol=1e-15)
+
+
 def test_golden_32x32_seed0_unchanged():
     """The stored oracle steady state (tests/golden/make_golden.py) still holds."""
     import json
