@@ -39,8 +39,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--size", type=int, default=1024, help="crossbar is size x size")
     p.add_argument("--seed", type=int, default=0)
-    p.add_argument("--precond", choices=["literal", "permode"], default=None,
-                   help="default: literal for fp64, permode otherwise")
+    p.add_argument("--precond", choices=["literal", "permode", "approx", "jacobi", "none"],
+                   default=None, help="default: literal for fp64, permode otherwise")
     p.add_argument("--precision", choices=["fp64", "fp32", "bf16x3", "bf16"], default="fp64",
                    help="arithmetic of the preconditioner's eigenbasis transforms")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -222,7 +222,9 @@ def main():
             "bf16": B.MCA_PREC_BF16}[args.precision]
     if args.precond is None:
         args.precond = "literal" if prec == B.MCA_PREC_FP64 else "permode"
-    form = B.MCA_PRECOND_LITERAL if args.precond == "literal" else B.MCA_PRECOND_PERMODE
+    form = {"literal": B.MCA_PRECOND_LITERAL, "permode": B.MCA_PRECOND_PERMODE,
+            "approx": B.MCA_PRECOND_APPROX, "jacobi": B.MCA_PRECOND_JACOBI,
+            "none": B.MCA_PRECOND_NONE}[args.precond]
     flags = 0 if args.no_timing else B.MCA_FLAG_TIMING
     opts = B.options(precond=form, precision=prec, flags=flags)
     v_t = torch.zeros((m, n), dtype=torch.float64, device=dev)
@@ -260,7 +262,19 @@ def main():
 
     # roofline of the dominant kernel: the FP64 eigenbasis GEMMs
     roofline = None
-    if not args.no_timing and klaunch[B.MCA_KCLASS_GEMM] > 0 and prec == B.MCA_PREC_FP64:
+    if not args.no_timing and klaunch[B.MCA_KCLASS_GEMM] > 0 and form == B.MCA_PRECOND_APPROX:
+        # two PCR line-solve launches per application: columns read r_b and write z_b
+        # (16 B per crosspoint), rows read r_t, z_b and write z_t (24 B)
+        bytes_per_launch = 20.0 * m * n
+        avg_ms = kms[B.MCA_KCLASS_GEMM] / klaunch[B.MCA_KCLASS_GEMM]
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": "k_pcr_solve (tridiagonal line solves)",
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "avg_launch_us": round(avg_ms * 1e3, 2),
+                    "bytes_per_launch": bytes_per_launch}
+    elif not args.no_timing and klaunch[B.MCA_KCLASS_GEMM] > 0 and prec == B.MCA_PREC_FP64 and \
+            form in (B.MCA_PRECOND_LITERAL, B.MCA_PRECOND_PERMODE):
         flops_per_launch = 2.0 * m * n * m   # 2 M N K with M = N = K = size
         if form == B.MCA_PRECOND_PERMODE:
             flops_per_launch *= 2.0                            # two layers per launch
@@ -282,6 +296,8 @@ def main():
 
     kind = ("plain FP64 Newton-FGMRES(30)" if prec == B.MCA_PREC_FP64 else
             f"Newton-FGMRES(30) with a {args.precision} preconditioner")
+    if form in (B.MCA_PRECOND_APPROX, B.MCA_PRECOND_JACOBI, B.MCA_PRECOND_NONE):
+        kind = f"FP64 Newton-FGMRES(30), {args.precond} preconditioner"
     workload = f"{kind}, {m}x{n} crossbar ({2 * m * n} unknowns), seed {args.seed}"
     out = {
         "metric": "MCA solves/s at 1024x1024, 1e-8 rel residual: plain FP64 vs batched+warm+mixed",

@@ -63,11 +63,17 @@ typedef int32_t mca_status;
 #define MCA_PREC_BF16X3    2   /* split-BF16 (hi+lo) operands, 3 MFMA products, FP32 acc  */
 #define MCA_PREC_BF16      3   /* BF16 operands (hi only), FP32 accumulation               */
 
-/* How P^{-1} r is evaluated (both give P^{-1} of eq. (P) in exact arithmetic). */
+/* How the preconditioner is applied.  LITERAL and PERMODE both give P^{-1} of
+ * eq. (P) in exact arithmetic; APPROX is the paper's approximation (it inverts
+ * P with its -a2 I block dropped, which is what M ~ Mhat amounts to); JACOBI
+ * and NONE are baselines.                                                   */
 #define MCA_PRECOND_LITERAL  0 /* the paper's order: w = r_b - D B^{-1} r_t, z_t = M^{-1} w,
                                   z_b = B^{-1}(r_t - A z_t)  (eqs. (block), (M))            */
 #define MCA_PRECOND_PERMODE  1 /* the same 2x2 block formula applied per Kronecker eigenmode */
 #define MCA_PRECOND_NONE     2 /* z = r (unpreconditioned GMRES, for comparison)            */
+#define MCA_PRECOND_APPROX   3 /* the paper's approximation M ~ Mhat = G2hat (x) G1 (eq. (Mhat)),
+                                  applied by tridiagonal solves; FP64 only, m, n <= 8192 */
+#define MCA_PRECOND_JACOBI   4 /* point-Jacobi z = r ./ diag(J), a baseline (mca_solve only) */
 
 #define MCA_FLAG_INITIAL_GUESS 1  /* mca_solve starts from v_t/v_b instead of V = 0       */
 #define MCA_FLAG_TIMING        2  /* mca_solve times its kernel classes with HIP events     */

@@ -34,6 +34,8 @@ MCA_PREC_BF16 = 3
 MCA_PRECOND_LITERAL = 0
 MCA_PRECOND_PERMODE = 1
 MCA_PRECOND_NONE = 2
+MCA_PRECOND_APPROX = 3
+MCA_PRECOND_JACOBI = 4
 MCA_FLAG_INITIAL_GUESS = 1
 MCA_FLAG_TIMING = 2
 MCA_KCLASS_GEMM = 0

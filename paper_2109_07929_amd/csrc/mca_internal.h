@@ -159,6 +159,27 @@ hipError_t launch_precond_lowprec_grouped(int precision, const GroupedChain &c, 
 // host: FP64 -> FP32 (p0) or bfloat16 hi (p0) + lo (p1)
 void split_host(const double *src, size_t count, int precision, void *p0, void *p1);
 
+// The paper's approximate preconditioner (tridiag.hip): batched tridiagonal
+// solves with (wire + shift I) by parallel cyclic reduction.  PcrTables holds
+// one shifted wire's multipliers; lines of up to kPcrMaxLen elements.
+constexpr int kPcrMaxLen = 8192;
+struct PcrTables {
+    int len, levels;
+    double *alpha, *gamma, *invb;   // levels x len, levels x len, len
+    double *work;                   // 6 x len set-up scratch
+};
+size_t pcr_table_doubles(int len);
+PcrTables pcr_carve(double *base, int len);
+hipError_t launch_pcr_setup(const Wire &w, double shift, const PcrTables &t, hipStream_t s);
+// out = T^{-1} (in + in2_scale * in2) along `lines` lines; rows: lines are
+// contiguous (elem_stride 1), else consecutive lines are adjacent (line_stride 1)
+hipError_t launch_pcr_solve(const PcrTables &t, int lines, bool rows, size_t line_stride,
+                            size_t elem_stride, const double *in, const double *in2,
+                            double in2_scale, double *out, const int *skip, hipStream_t s);
+// z = r ./ diag(J(D))
+hipError_t launch_jacobi(const mca_plan *P, const double *D, const double *rt, const double *rb,
+                         double *zt, double *zb, const int *skip, hipStream_t s);
+
 // Krylov kernels over vectors of even length len (= 2mn), 16-byte aligned.
 // partial dot products x.y -> partials[reduce_blocks(len)] (any length)
 hipError_t launch_dot_partials(const double *x, const double *y, size_t len,

@@ -74,14 +74,18 @@ mca_status validate_options(const mca_options *o)
     if (o->precision != MCA_PREC_FP64 && o->precision != MCA_PREC_FP32 &&
         o->precision != MCA_PREC_BF16X3 && o->precision != MCA_PREC_BF16)
         return MCA_ERR_INVALID_ARG;
-    if (o->precond != MCA_PRECOND_LITERAL && o->precond != MCA_PRECOND_PERMODE &&
-        o->precond != MCA_PRECOND_NONE)
+    if (o->precond < MCA_PRECOND_LITERAL || o->precond > MCA_PRECOND_JACOBI)
         return MCA_ERR_INVALID_ARG;
-    if (o->precision != MCA_PREC_FP64 && o->precond == MCA_PRECOND_LITERAL)
+    // reduced precision applies to the eigenbasis transforms of the per-mode form only
+    if (o->precision != MCA_PREC_FP64 && o->precond != MCA_PRECOND_PERMODE &&
+        o->precond != MCA_PRECOND_NONE)
         return MCA_ERR_INVALID_ARG;
     if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING)) return MCA_ERR_INVALID_ARG;
     return MCA_OK;
 }
+
+// The approximate form holds whole wires in LDS.
+bool approx_fits(const mca_plan *P) { return P->geom.m <= kPcrMaxLen && P->geom.n <= kPcrMaxLen; }
 
 // Wire matrix of eq. (G) with the two end terminations (see mca.h).
 Wire make_wire(int len, double g, double end0, double end1) { return Wire{g, end0, end1, len}; }
@@ -140,13 +144,19 @@ PlanLayout plan_layout(const mca_plan *P, void *base)
 struct PrecondWs {
     double *b0t, *b0b, *b1t, *b1b;
     LpPlanes lp[6];
+    PcrTables g1, g2;   // approximate form: G_top + a1 I (len n), G_bot + a2 I (len m)
 };
 
 PrecondWs precond_layout(const mca_plan *P, Carver &c, int form, int precision = MCA_PREC_FP64)
 {
     const size_t mn = (size_t)P->geom.m * P->geom.n;
     PrecondWs w{};
-    if (form == MCA_PRECOND_NONE) return w;
+    if (form == MCA_PRECOND_NONE || form == MCA_PRECOND_JACOBI) return w;
+    if (form == MCA_PRECOND_APPROX) {
+        w.g1 = pcr_carve(c.take<double>(pcr_table_doubles(P->geom.n)), P->geom.n);
+        w.g2 = pcr_carve(c.take<double>(pcr_table_doubles(P->geom.m)), P->geom.m);
+        return w;
+    }
     if (precision != MCA_PREC_FP64) {
         for (auto &op : w.lp) {
             if (precision == MCA_PREC_FP32) {
@@ -302,13 +312,41 @@ struct Timing {
 };
 
 // z = P^{-1} r (eq. (P)) in the chosen evaluation form.
+// Per-shift set-up of the approximate form (the PCR multipliers of
+// G_top + a1 I and G_bot + a2 I); nothing for the other forms.
+mca_status precond_setup(const mca_plan *P, int form, double a1, double a2, const PrecondWs &w,
+                         hipStream_t s)
+{
+    if (form != MCA_PRECOND_APPROX) return MCA_OK;
+    MCA_TRY(launch_pcr_setup(P->top, a1, w.g1, s));
+    MCA_TRY(launch_pcr_setup(P->bot, a2, w.g2, s));
+    return MCA_OK;
+}
+
 mca_status precond_run(const mca_plan *P, int form, int precision, double a1, double a2,
                        const double *rt, const double *rb, double *zt, double *zb,
                        const PrecondWs &w, hipStream_t s, Timing *tm = nullptr, int slot = 0,
-                       const int *skip = nullptr)
+                       const int *skip = nullptr, const double *D = nullptr)
 {
     Timing off;
     if (!tm) tm = &off;
+    if (form == MCA_PRECOND_APPROX) {
+        // the paper's M ~ Mhat (eqs. (Mhat)-(2matrix4)) as a block back-substitution:
+        // z_b = (G_b + a2 I)^{-1} r_b down the columns, then
+        // z_t = (G_t + a1 I)^{-1} (r_t + a1 z_b) along the rows
+        const int m = P->geom.m, n = P->geom.n;
+        MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
+        MCA_TRY(launch_pcr_solve(w.g2, n, false, 1, (size_t)n, rb, nullptr, 0.0, zb, skip, s));
+        MCA_TRY(launch_pcr_solve(w.g1, m, true, (size_t)n, 1, rt, zb, a1, zt, skip, s));
+        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 2, slot));
+        return MCA_OK;
+    }
+    if (form == MCA_PRECOND_JACOBI) {
+        MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
+        MCA_TRY(launch_jacobi(P, D, rt, rb, zt, zb, skip, s));
+        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 1, slot));
+        return MCA_OK;
+    }
     if (form != MCA_PRECOND_NONE && precision != MCA_PREC_FP64) {
         const DevPlan &d = P->dev;
         LowPrecChain c{};
@@ -425,6 +463,10 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
     bool converged = false, first = true;
     // v_0 = -F / ||F||
     MCA_TRY(launch_scale(w.F, -1.0 / beta, w.V, len, s));
+    {
+        const mca_status st = precond_setup(P, o->precond, a, a, w.pw, s);
+        if (st != MCA_OK) return st;
+    }
     for (;;) {
         MCA_TRY(launch_cycle_init(w.ctl, w.g, R, beta, s));
         const int jmax = std::min(R, o->max_krylov - its);
@@ -435,7 +477,7 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
             double *wv = w.V + (size_t)(j + 1) * len;
             const int *skip = w.ctl;
             mca_status st = precond_run(P, o->precond, o->precision, a, a, vj, vj + mn, zj,
-                                        zj + mn, w.pw, s, tm, slot, skip);
+                                        zj + mn, w.pw, s, tm, slot, skip, w.D);
             if (st != MCA_OK) return st;
             // w = J z_j, fused with the partial sums of <w, v_0>
             MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
@@ -674,6 +716,7 @@ size_t mca_workspace_bytes(const mca_plan *P, const mca_options *opts)
     if (opts) o = *opts;
     else mca_options_default(&o);
     if (validate_options(&o) != MCA_OK) return 0;
+    if (o.precond == MCA_PRECOND_APPROX && !approx_fits(P)) return 0;
     return solve_layout(P, &o, nullptr).bytes;
 }
 
@@ -710,12 +753,15 @@ mca_status mca_precond_apply(const mca_plan *P, int32_t form, int32_t precision,
                              double *z_b, void *ws, size_t ws_bytes, void *stream)
 {
     if (!P || !r_t || !r_b || !z_t || !z_b) return MCA_ERR_INVALID_ARG;
-    if (form != MCA_PRECOND_LITERAL && form != MCA_PRECOND_PERMODE && form != MCA_PRECOND_NONE)
+    if (form != MCA_PRECOND_LITERAL && form != MCA_PRECOND_PERMODE && form != MCA_PRECOND_NONE &&
+        form != MCA_PRECOND_APPROX)
         return MCA_ERR_INVALID_ARG;
     if (precision != MCA_PREC_FP64 && precision != MCA_PREC_FP32 &&
         precision != MCA_PREC_BF16X3 && precision != MCA_PREC_BF16)
         return MCA_ERR_INVALID_ARG;
-    if (precision != MCA_PREC_FP64 && form == MCA_PRECOND_LITERAL) return MCA_ERR_INVALID_ARG;
+    if (precision != MCA_PREC_FP64 && form != MCA_PRECOND_PERMODE && form != MCA_PRECOND_NONE)
+        return MCA_ERR_INVALID_ARG;
+    if (form == MCA_PRECOND_APPROX && !approx_fits(P)) return MCA_ERR_INVALID_ARG;
     if (!(std::isfinite(a1) && a1 > 0.0 && std::isfinite(a2) && a2 > 0.0))
         return MCA_ERR_INVALID_ARG;
     if (!plan_ready(P)) return MCA_ERR_WORKSPACE;
@@ -723,6 +769,8 @@ mca_status mca_precond_apply(const mca_plan *P, int32_t form, int32_t precision,
         return MCA_ERR_WORKSPACE;
     Carver c(ws);
     PrecondWs w = precond_layout(P, c, form, precision);
+    const mca_status st = precond_setup(P, form, a1, a2, w, static_cast<hipStream_t>(stream));
+    if (st != MCA_OK) return st;
     return precond_run(P, form, precision, a1, a2, r_t, r_b, z_t, z_b, w,
                        static_cast<hipStream_t>(stream));
 }
@@ -738,6 +786,7 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     else mca_options_default(&o);
     mca_status st = validate_options(&o);
     if (st != MCA_OK) return st;
+    if (o.precond == MCA_PRECOND_APPROX && !approx_fits(P)) return MCA_ERR_INVALID_ARG;
     if (!plan_ready(P)) return MCA_ERR_WORKSPACE;
     SolveWs w = solve_layout(P, &o, ws);
     if (!ws || ws_bytes < w.bytes) return MCA_ERR_WORKSPACE;

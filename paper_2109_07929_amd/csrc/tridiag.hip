@@ -1,0 +1,253 @@
+// tridiag.hip -- the paper's approximate preconditioner on the GPU: batched
+// tridiagonal solves with the shifted wire matrices, by parallel cyclic
+// reduction (PCR), and the point-Jacobi baseline.
+//
+// Approximating the Schur complement M of eq. (M) by Mhat = G2hat (x) G1
+// (eq. (Mhat)) is the same as dropping P's -a2 I block: the Schur complement
+// of [[G_t + a1 I, -a1 I], [0, G_b + a2 I]] is (G_b + a2 I)(G_t + a1 I)/a1 =
+// Mhat exactly.  So the paper's evaluation (eqs. (block), (2matrix4)) equals
+// the block back-substitution
+//     z_b = (G_b + a2 I)^{-1} r_b                 (G2 = G_bot + a2 I down every column)
+//     z_t = (G_t + a1 I)^{-1} (r_t + a1 z_b)      (G1 = G_top + a1 I along every row)
+// which never divides a difference by a1.  Each line solve is PCR held in
+// LDS: level l (stride s = 2^l) replaces equation k by itself plus
+// alpha_k * (equation k - s) + gamma_k * (equation k + s), eliminating the
+// couplings to k -+ s; after ceil(log2 len) levels every equation is
+// diagonal.  The multipliers depend only on the matrix, so they are built
+// once per shift (once per Newton step) and every right-hand side is then
+// log2(len) LDS sweeps of two FMAs per element.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace mca {
+namespace {
+
+using dev::TPB;
+
+constexpr int kLds = kPcrMaxLen;            // doubles of one workgroup's lines
+constexpr int kEpt = kLds / TPB;            // elements per thread
+
+// diagonal / couplings of (wire + shift I) at level 0
+__global__ __launch_bounds__(TPB) void k_pcr_init(Wire w, double shift, double *__restrict__ a,
+                                                  double *__restrict__ b, double *__restrict__ c)
+{
+    const int len = w.len;
+    for (int k = blockIdx.x * TPB + threadIdx.x; k < len; k += gridDim.x * TPB) {
+        b[k] = ((k > 0) ? w.g : w.end0) + ((k + 1 < len) ? w.g : w.end1) + shift;
+        a[k] = (k > 0) ? -w.g : 0.0;
+        c[k] = (k + 1 < len) ? -w.g : 0.0;
+    }
+}
+
+// one PCR level of the matrix (a, b, c) with stride s -> (a2, b2, c2) and the
+// level's multipliers
+__global__ __launch_bounds__(TPB) void k_pcr_level(int len, int s, const double *__restrict__ a,
+                                                   const double *__restrict__ b,
+                                                   const double *__restrict__ c,
+                                                   double *__restrict__ a2, double *__restrict__ b2,
+                                                   double *__restrict__ c2,
+                                                   double *__restrict__ alpha,
+                                                   double *__restrict__ gamma)
+{
+    for (int k = blockIdx.x * TPB + threadIdx.x; k < len; k += gridDim.x * TPB) {
+        const bool lo = k - s >= 0, hi = k + s < len;
+        const double al = lo ? -a[k] / b[k - s] : 0.0;
+        const double ga = hi ? -c[k] / b[k + s] : 0.0;
+        a2[k] = lo ? al * a[k - s] : 0.0;
+        c2[k] = hi ? ga * c[k + s] : 0.0;
+        b2[k] = b[k] + (lo ? al * c[k - s] : 0.0) + (hi ? ga * a[k + s] : 0.0);
+        alpha[k] = al;
+        gamma[k] = ga;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_pcr_final(int len, const double *__restrict__ b,
+                                                   double *__restrict__ invb)
+{
+    for (int k = blockIdx.x * TPB + threadIdx.x; k < len; k += gridDim.x * TPB) invb[k] = 1.0 / b[k];
+}
+
+// Solve T x = in (+ in2_scale * in2) for `lines` lines of length len.
+// Element k of line l sits at l * line_stride + k * elem_stride.  A workgroup
+// holds lpw consecutive lines in LDS, ordered as in memory: line-major when the
+// lines are contiguous (rows), element-major when consecutive lines are
+// adjacent in memory (columns), so loads and stores stay coalesced.
+struct PcrSolveArgs {
+    int len, levels, lines, lpw, rows;
+    size_t line_stride, elem_stride;
+    const double *alpha, *gamma, *invb;   // levels x len, levels x len, len
+    const double *in, *in2;
+    double in2_scale;
+    double *out;
+    const int *skip;
+};
+
+__global__ __launch_bounds__(TPB) void k_pcr_solve(PcrSolveArgs p)
+{
+    if (p.skip && *p.skip) return;
+    __shared__ double d[kLds];
+    const int len = p.len, lpw = p.lpw, E = len * lpw;
+    const int line0 = blockIdx.x * lpw;
+    const int kst = p.rows ? 1 : lpw;      // LDS distance between elements k and k + 1
+    auto coords = [&](int e, int &k, int &l) {
+        if (p.rows) {
+            l = e / len;
+            k = e - l * len;
+        } else {
+            k = e / lpw;
+            l = e - k * lpw;
+        }
+    };
+    for (int e = threadIdx.x; e < E; e += TPB) {
+        int k, l;
+        coords(e, k, l);
+        double v = 0.0;
+        if (line0 + l < p.lines) {
+            const size_t g = (size_t)(line0 + l) * p.line_stride + (size_t)k * p.elem_stride;
+            v = p.in[g];
+            if (p.in2) v += p.in2_scale * p.in2[g];
+        }
+        d[e] = v;
+    }
+    __syncthreads();
+    int s = 1;
+    for (int lev = 0; lev < p.levels; ++lev, s <<= 1) {
+        const double *al = p.alpha + (size_t)lev * len, *ga = p.gamma + (size_t)lev * len;
+        double nd[kEpt];
+#pragma unroll
+        for (int r = 0; r < kEpt; ++r) {
+            const int e = threadIdx.x + r * TPB;
+            if (e < E) {
+                int k, l;
+                coords(e, k, l);
+                double v = d[e];
+                if (k - s >= 0) v += al[k] * d[e - s * kst];
+                if (k + s < len) v += ga[k] * d[e + s * kst];
+                nd[r] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kEpt; ++r) {
+            const int e = threadIdx.x + r * TPB;
+            if (e < E) d[e] = nd[r];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < E; e += TPB) {
+        int k, l;
+        coords(e, k, l);
+        if (line0 + l < p.lines)
+            p.out[(size_t)(line0 + l) * p.line_stride + (size_t)k * p.elem_stride] = d[e] * p.invb[k];
+    }
+}
+
+// Jacobi: z = r ./ diag(J), diag(J) = wire diagonal + D on each layer
+__global__ __launch_bounds__(TPB) void k_jacobi(int m, int n, Wire top, Wire bot,
+                                                const double *__restrict__ D,
+                                                const double *__restrict__ rt,
+                                                const double *__restrict__ rb,
+                                                double *__restrict__ zt, double *__restrict__ zb,
+                                                const int *skip)
+{
+    if (skip && *skip) return;
+    const size_t mn = (size_t)m * n;
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
+        const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
+        const double dt = ((j > 0) ? top.g : top.end0) + ((j + 1 < n) ? top.g : top.end1);
+        const double db = ((i > 0) ? bot.g : bot.end0) + ((i + 1 < m) ? bot.g : bot.end1);
+        zt[k] = rt[k] / (dt + D[k]);
+        zb[k] = rb[k] / (db + D[k]);
+    }
+}
+
+int pcr_levels(int len)
+{
+    int l = 0;
+    while ((1 << l) < len) ++l;
+    return l;
+}
+
+int grid_for(size_t count) { return (int)std::max<size_t>(1, std::min<size_t>((count + TPB - 1) / TPB, 1024)); }
+
+// lines per workgroup: as many as fit in LDS, but keep >= ~512 workgroups
+int lines_per_wg(int len, int lines)
+{
+    int lpw = 1;
+    while (2 * lpw * len <= kLds && 2 * lpw <= std::max(1, lines / 512)) lpw *= 2;
+    return lpw;
+}
+
+}  // namespace
+
+size_t pcr_table_doubles(int len)
+{
+    return (size_t)(2 * pcr_levels(len) + 1 + 6) * len;
+}
+
+PcrTables pcr_carve(double *base, int len)
+{
+    PcrTables t{};
+    t.len = len;
+    t.levels = pcr_levels(len);
+    t.alpha = base;
+    t.gamma = base + (size_t)t.levels * len;
+    t.invb = base + (size_t)2 * t.levels * len;
+    t.work = t.invb + len;
+    return t;
+}
+
+hipError_t launch_pcr_setup(const Wire &w, double shift, const PcrTables &t, hipStream_t s)
+{
+    const int len = t.len, grid = grid_for(len);
+    double *a = t.work, *b = a + len, *c = b + len, *a2 = c + len, *b2 = a2 + len, *c2 = b2 + len;
+    hipLaunchKernelGGL(k_pcr_init, dim3(grid), dim3(TPB), 0, s, w, shift, a, b, c);
+    for (int lev = 0, st = 1; lev < t.levels; ++lev, st <<= 1) {
+        hipLaunchKernelGGL(k_pcr_level, dim3(grid), dim3(TPB), 0, s, len, st, a, b, c, a2, b2, c2,
+                           t.alpha + (size_t)lev * len, t.gamma + (size_t)lev * len);
+        std::swap(a, a2);
+        std::swap(b, b2);
+        std::swap(c, c2);
+    }
+    hipLaunchKernelGGL(k_pcr_final, dim3(grid), dim3(TPB), 0, s, len, b, t.invb);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcr_solve(const PcrTables &t, int lines, bool rows, size_t line_stride,
+                            size_t elem_stride, const double *in, const double *in2,
+                            double in2_scale, double *out, const int *skip, hipStream_t s)
+{
+    if (t.len > kPcrMaxLen || t.len < 1) return hipErrorInvalidValue;
+    PcrSolveArgs p{};
+    p.len = t.len;
+    p.levels = t.levels;
+    p.lines = lines;
+    p.lpw = lines_per_wg(t.len, lines);
+    p.rows = rows ? 1 : 0;
+    p.line_stride = line_stride;
+    p.elem_stride = elem_stride;
+    p.alpha = t.alpha;
+    p.gamma = t.gamma;
+    p.invb = t.invb;
+    p.in = in;
+    p.in2 = in2;
+    p.in2_scale = in2_scale;
+    p.out = out;
+    p.skip = skip;
+    hipLaunchKernelGGL(k_pcr_solve, dim3((lines + p.lpw - 1) / p.lpw), dim3(TPB), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi(const mca_plan *P, const double *D, const double *rt, const double *rb,
+                         double *zt, double *zb, const int *skip, hipStream_t s)
+{
+    const size_t mn = (size_t)P->geom.m * P->geom.n;
+    hipLaunchKernelGGL(k_jacobi, dim3(grid_for(mn)), dim3(TPB), 0, s, P->geom.m, P->geom.n,
+                       P->top, P->bot, D, rt, rb, zt, zb, skip);
+    return hipGetLastError();
+}
+
+}  // namespace mca

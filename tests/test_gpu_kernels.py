@@ -136,6 +136,63 @@ def test_precond_inverts_P_at_1024(form):
     assert err <= (1e-9 if form == B.MCA_PRECOND_PERMODE else 1e-5)
 
 
+APPROX_SHAPES = SHAPES + [(300, 77), (3, 8192), (8192, 3)]
+
+
+@pytest.mark.parametrize("m,n", APPROX_SHAPES)
+@pytest.mark.parametrize("a1,a2", [(2.2e-5, 2.2e-5), (3e-4, 4e-5)])
+def test_precond_approx_parity(m, n, a1, a2):
+    """The paper's approximation M ~ Mhat: GPU block back-substitution by PCR
+    against the oracle's literal order (eq. (block) with Mhat^{-1} by eq. (2matrix4))."""
+    say(f"precond approx {m}x{n} a=({a1},{a2})")
+    geom = synth.Geometry(m, n)
+    rt, rb = synth.vector(m, n, seed=m * 7 + n)
+    zt, zb = oracle.precond_apply_approx(geom, a1, a2, rt, rb)
+    plan = _plan_with_eigs(geom)
+    gzt, gzb = plan.precond_apply(a1, a2, dev(rt), dev(rb), form=B.MCA_PRECOND_APPROX)
+    scale = max(np.abs(zt).max(), np.abs(zb).max())
+    # the oracle's order divides by a1 (the GPU's does not): its rounding sets the bar
+    tol = max(1e-11, _literal_tol(plan, a1))
+    err = max(np.abs(host(gzt) - zt).max(), np.abs(host(gzb) - zb).max()) / scale
+    say(f"  rel err {err:.3e} (tol {tol:.1e})")
+    assert err <= tol
+
+
+def test_precond_approx_inverts_P_without_lower_coupling_at_1024():
+    """Full size: the approximate z solves [[G_t + a1 I, -a1 I], [0, G_b + a2 I]] z = r
+    (P with its -a2 I block dropped), checked with the oracle's Jacobian product at
+    uniform slope a (P(a, a) = J):  P z + [0; a z_t] = r."""
+    m = n = 1024
+    a = 2.2e-5
+    geom = synth.Geometry(m, n)
+    rt, rb = synth.vector(m, n, seed=6)
+    plan = Plan(geom)
+    gzt, gzb = plan.precond_apply(a, a, dev(rt), dev(rb), form=B.MCA_PRECOND_APPROX)
+    zt, zb = host(gzt), host(gzb)
+    pt, pb = oracle.jacobian_apply(geom, np.full((m, n), a), zt, zb)
+    pb = pb + a * zt
+    rel = np.sqrt(np.sum((pt - rt) ** 2) + np.sum((pb - rb) ** 2)) / np.sqrt(
+        np.sum(rt ** 2) + np.sum(rb ** 2))
+    # backward-stable solves: ||Phat z - r|| <= c eps ||Phat|| ||z||, ||Phat|| <= 2
+    zr = np.sqrt(np.sum(zt ** 2) + np.sum(zb ** 2)) / np.sqrt(np.sum(rt ** 2) + np.sum(rb ** 2))
+    bound = 64 * 2.2e-16 * 2.0 * zr
+    say(f"  ||Phat z - r||/||r|| = {rel:.3e} (bound {bound:.1e})")
+    assert rel <= bound
+    ot, ob = oracle.precond_apply_approx(geom, a, a, rt, rb)
+    scale = max(np.abs(ot).max(), np.abs(ob).max())
+    err = max(np.abs(zt - ot).max(), np.abs(zb - ob).max()) / scale
+    say(f"  max rel err vs oracle {err:.3e}")
+    assert err <= max(1e-11, 2.2e-16 * 64 * 2.0 / a)
+
+
+def test_precond_jacobi_only_in_the_solver():
+    m, n = 6, 5
+    rt, rb = synth.vector(m, n, seed=2)
+    plan = Plan(synth.Geometry(m, n))
+    with pytest.raises(B.MCAError):
+        plan.precond_apply(1e-5, 1e-5, dev(rt), dev(rb), form=B.MCA_PRECOND_JACOBI)
+
+
 def test_errors_and_validation():
     m, n = 8, 8
     plan = Plan(synth.Geometry(m, n))

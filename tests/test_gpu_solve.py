@@ -237,3 +237,29 @@ def test_mixed_precision_solve_1024(prec):
     err = rel_err(vt, vb, rt, rb)
     say(f"  err vs oracle {err:.2e}")
     assert err <= TOL
+
+
+@pytest.mark.parametrize("m,n", [(5, 3), (32, 32), (17, 45), (96, 64)])
+@pytest.mark.parametrize("form", [B.MCA_PRECOND_APPROX, B.MCA_PRECOND_JACOBI])
+def test_solve_approx_and_jacobi_forms(m, n, form):
+    """Other preconditioners change the iteration, not the steady state."""
+    say(f"solve {m}x{n} form={form}")
+    cb = synth.crossbar(m, n, seed=3)
+    vt, vb, status, st = gpu_solve(cb, precond=form, max_krylov=20000)
+    say(f"  status {status} newton {st.newton_iters} krylov "
+        f"{list(st.krylov_history[:st.newton_iters])} restarts {st.restarts}")
+    assert status == B.MCA_OK
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="band")
+    assert rel_err(vt, vb, rt, rb) <= TOL
+
+
+def test_solve_approx_1024():
+    say("solve 1024x1024 approx")
+    cb = synth.crossbar(1024, 1024, seed=0)
+    vt, vb, status, st = gpu_solve(cb, precond=B.MCA_PRECOND_APPROX)
+    say(f"  newton {st.newton_iters} krylov {list(st.krylov_history[:st.newton_iters])}")
+    assert status == B.MCA_OK
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="cg")
+    err = rel_err(vt, vb, rt, rb)
+    say(f"  err vs oracle {err:.2e}")
+    assert err <= TOL

@@ -165,3 +165,18 @@ def test_batch_create_rejects_bad_geometry():
     assert e.value.status == B.MCA_ERR_INVALID_ARG
     with pytest.raises(B.MCAError):
         B.mca_batch_create([])
+
+
+def test_approx_and_jacobi_forms_validation():
+    """The approximate (paper's Mhat) and Jacobi forms are FP64-only."""
+    P = B.mca_plan_create(B.geometry(8, 8))
+    try:
+        for form in (B.MCA_PRECOND_APPROX, B.MCA_PRECOND_JACOBI):
+            assert B.mca_workspace_bytes(P, B.options(precond=form)) > 0
+            assert B.mca_workspace_bytes(P, B.options(precond=form,
+                                                      precision=B.MCA_PREC_FP32)) == 0
+        assert B.mca_workspace_bytes(P, B.options(precond=5)) == 0
+        # the approximate form needs its multiplier tables; Jacobi no workspace
+        assert B.mca_precond_workspace_bytes(P, B.MCA_PRECOND_APPROX) > 0
+    finally:
+        B.mca_plan_destroy(P)
