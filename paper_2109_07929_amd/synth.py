@@ -111,3 +111,20 @@ def mc_batch(count: int, seed: int = 0, sizes=tuple(range(64, 513, 64)),
         geom = Geometry(m, n, g_top=gw, g_bot=gw, g_src=gw)
         out.append(Crossbar(geom, np.ascontiguousarray(g_dev), v_in, seed * 100003 + k))
     return out
+
+
+# ------------------------------------------------------- warm-start network
+CNN_LAYERS = [(3, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 2)]
+
+
+def cnn_init(seed: int = 0) -> np.ndarray:
+    """Packed initial parameters of the warm-start network (float32): per layer
+    w[dy][dx][ci][co] ~ N(0, 2 / (9 ci)) (He), then b[co] = 0; the last layer's
+    weights are scaled by 0.1."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, (ci, co) in enumerate(CNN_LAYERS):
+        std = np.sqrt(2.0 / (9 * ci)) * (0.1 if k == len(CNN_LAYERS) - 1 else 1.0)
+        out.append(rng.standard_normal(9 * ci * co) * std)
+        out.append(np.zeros(co))
+    return np.concatenate(out).astype(np.float32)
