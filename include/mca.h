@@ -77,6 +77,8 @@ typedef int32_t mca_status;
 
 #define MCA_FLAG_INITIAL_GUESS 1  /* mca_solve starts from v_t/v_b instead of V = 0       */
 #define MCA_FLAG_TIMING        2  /* mca_solve times its kernel classes with HIP events     */
+#define MCA_FLAG_GUESS_FALLBACK 4 /* with INITIAL_GUESS: a guess whose residual is not below
+                                     that of V = 0 (||F(0)|| = ||Y||) is dropped for V = 0  */
 
 /* Kernel classes timed under MCA_FLAG_TIMING (mca_stats.kernel_ms / kernel_launches). */
 #define MCA_KCLASS_GEMM      0    /* eigenbasis transforms of the preconditioner          */
@@ -137,6 +139,7 @@ typedef struct mca_stats {
      * the number of kernel launches in those groups.                             */
     double  kernel_ms[MCA_NUM_KCLASS];
     int32_t kernel_launches[MCA_NUM_KCLASS];
+    int32_t start;                        /* 1: started from the caller's guess, 0: V = 0 */
 } mca_stats;
 
 typedef struct mca_plan mca_plan;
@@ -282,6 +285,50 @@ size_t     mca_batch_workspace_bytes(const mca_batch *batch, const mca_options *
 mca_status mca_solve_batched(const mca_batch *batch, const double *g_dev, const double *v_in,
                              double *v_t, double *v_b, const mca_options *opts,
                              void *ws, size_t ws_bytes, mca_stats *stats, void *stream);
+
+/* ------------------------------------------------------- warm-start network
+ * A 6-layer 3x3 CNN predicts a crossbar's steady state from its inputs, to
+ * start mca_solve (MCA_FLAG_INITIAL_GUESS) nearer to the solution than V = 0
+ * (Newton's method, eq. (Newton3), converges from the guess; the guess only
+ * changes the iteration count).  It corrects a mean-field guess: the paper's
+ * approximate preconditioner (eq. (block) with M ~ Mhat) applied to the drive
+ * vector Y at a1 = a2 = a = mean(g_dev); as Y_b = 0 that guess is
+ * V0_t[i][j] = v_in[i] phi[j], V0_b = 0 with phi = g_src (G_top + a I)^{-1} e_0.
+ * Per crosspoint (i, j) the input channels are log10(g_dev) + 5,
+ * v_in[i]/0.15 - 1, (g_top - 0.5)/0.3 and v_in[i] (1 - phi[j]) / 0.1; five 3x3
+ * convolutions with 32 channels and ReLU, then a linear 3x3 convolution to
+ * (y_t, y_b); V_t = V0_t - 0.01 y_t, V_b = 0.01 y_b.  Zero "same" padding.
+ * Arithmetic: bfloat16 weights and activations on MFMA, FP32 accumulation,
+ * FP32 master parameters and Adam state.
+ *
+ * params: device FP32 vector of mca_cnn_param_count() values: per layer
+ * w[dy][dx][ci][co] (row-major; ci = 4, 32, 32, 32, 32, 32; co = 32, 32, 32,
+ * 32, 32, 2) followed by b[co].  A batch is `batch` crossbars of one size
+ * m x n, described by a host array geoms[batch] (equal m, n; only g_top,
+ * g_src and g_top_end are used); g_dev, v_t, v_b hold batch*m*n doubles
+ * (crossbar after crossbar), v_in batch*m.  Arrays are device pointers; the
+ * calls synchronise stream once (to upload the small wire table) and then
+ * enqueue the rest asynchronously.                                          */
+int64_t    mca_cnn_param_count(void);
+/* device workspace (bytes) for a batch of m x n crossbars; 0 for bad sizes */
+size_t     mca_cnn_workspace_bytes(int32_t batch, int32_t m, int32_t n);
+/* predicted v_t, v_b.  Errors: MCA_ERR_INVALID_ARG, MCA_ERR_WORKSPACE, MCA_ERR_HIP. */
+mca_status mca_cnn_predict(const float *params, int32_t batch, const mca_geometry *geoms,
+                           const double *g_dev, const double *v_in, double *v_t, double *v_b,
+                           void *ws, size_t ws_bytes, void *stream);
+/* Training loss against solved voltages v_t, v_b: the mean over the batch of
+ * (y - y_target)^2 over every crosspoint and both outputs, y_target from the
+ * voltage map above; grad (device, param_count floats) receives its
+ * gradient, loss (device, 1 float) its value.  Same errors as predict.      */
+mca_status mca_cnn_gradient(const float *params, int32_t batch, const mca_geometry *geoms,
+                            const double *g_dev, const double *v_in, const double *v_t,
+                            const double *v_b, float *grad, float *loss, void *ws,
+                            size_t ws_bytes, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step >= 1)
+ * on params with moment vectors adam_m, adam_v (device, param_count floats,
+ * zero before step 1).  Errors: MCA_ERR_INVALID_ARG, MCA_ERR_HIP.          */
+mca_status mca_cnn_adam(float *params, const float *grad, float *adam_m, float *adam_v,
+                        int32_t step, float lr, void *stream);
 
 #ifdef __cplusplus
 }

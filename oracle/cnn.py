@@ -5,15 +5,20 @@ CPU baseline may import this module; the HIP library never uses it and the two
 share no code.
 
 The network predicts the crossbar's steady state from its inputs, to start
-Newton's method (eq. (Newton3)) closer to the solution than V = 0:
+Newton's method (eq. (Newton3)) closer to the solution than V = 0.  It
+corrects a mean-field guess: the paper's approximate preconditioner (eq.
+(block) with M ~ Mhat) applied to the drive vector Y at a1 = a2 = mean(g_dev).
+With Y_b = 0 that guess is V0_t[i, j] = v_in[i] phi[j], V0_b = 0, where
+phi = g_src (G_top + a I)^{-1} e_0 is the decay profile along one top wire.
   * input channels per crosspoint (i, j):
         f0 = log10(g_dev[i, j]) + 5             (device conductance, ~[-1, 1])
         f1 = v_in[i] / 0.15 - 1                 (the row's drive, ~[-1, 1])
-        f2 = (g_wire - 0.5) / 0.3               (the wire conductance, ~[-1, 1])
+        f2 = (g_top - 0.5) / 0.3                (the wire conductance, ~[-1, 1])
+        f3 = v_in[i] (1 - phi[j]) / 0.1         (the mean-field IR drop)
   * six 3x3 convolutions (cross-correlation, zero "same" padding), 32
     channels, ReLU after the first five, a linear last layer with 2 outputs;
   * outputs (y_t, y_b) parameterise the voltages as
-        V_t = v_in[i] - 0.1 y_t,    V_b = 0.1 y_b;
+        V_t = v_in[i] phi[j] - 0.01 y_t,    V_b = 0.01 y_b;
   * training loss: the mean of (y - y_target)^2 over crosspoints and both
     outputs; optimiser Adam (Kingma & Ba) with bias correction.
 
@@ -26,32 +31,60 @@ from __future__ import annotations
 import numpy as np
 
 CH = 32
-LAYERS = [(3, CH, True), (CH, CH, True), (CH, CH, True), (CH, CH, True), (CH, CH, True),
+LAYERS = [(4, CH, True), (CH, CH, True), (CH, CH, True), (CH, CH, True), (CH, CH, True),
           (CH, 2, False)]
-V_SCALE = 0.1
+V_SCALE = 0.01
 
 
-def features(g_dev, v_in, g_wire):
-    """(m, n, 3) input channels of one crossbar."""
+def wire_profile(geom, g_dev):
+    """phi = g_src (G_top + a I)^{-1} e_0 with a = mean(g_dev): the top wire
+    matrix with terminations (eq. (G)), shifted as G1 of eq. (G1)."""
+    n = geom.n
+    a = float(np.mean(g_dev))
+    T = np.zeros((n, n))
+    for k in range(n - 1):                  # one segment between k and k + 1
+        T[k, k] += geom.g_top
+        T[k + 1, k + 1] += geom.g_top
+        T[k, k + 1] -= geom.g_top
+        T[k + 1, k] -= geom.g_top
+    T[0, 0] += geom.g_src
+    T[-1, -1] += geom.g_top_end
+    rhs = np.zeros(n)
+    rhs[0] = geom.g_src
+    return np.linalg.solve(T + a * np.eye(n), rhs)
+
+
+def features(geom, g_dev, v_in):
+    """(m, n, 4) input channels of one crossbar."""
     g_dev = np.asarray(g_dev, dtype=np.float64)
+    v_in = np.asarray(v_in, dtype=np.float64)
     m, n = g_dev.shape
-    f = np.empty((m, n, 3))
+    phi = wire_profile(geom, g_dev)
+    f = np.empty((m, n, 4))
     f[..., 0] = np.log10(g_dev) + 5.0
-    f[..., 1] = (np.asarray(v_in, dtype=np.float64) / 0.15 - 1.0)[:, None]
-    f[..., 2] = (float(g_wire) - 0.5) / 0.3
+    f[..., 1] = (v_in / 0.15 - 1.0)[:, None]
+    f[..., 2] = (float(geom.g_top) - 0.5) / 0.3
+    f[..., 3] = v_in[:, None] * (1.0 - phi[None, :]) / 0.1
     return f
 
 
-def targets(v_in, v_t, v_b):
+def base_guess(geom, g_dev, v_in):
+    """The mean-field guess (V0_t, V0_b)."""
+    phi = wire_profile(geom, g_dev)
+    v_in = np.asarray(v_in, dtype=np.float64)
+    return v_in[:, None] * phi[None, :], np.zeros((geom.m, geom.n))
+
+
+def targets(geom, g_dev, v_in, v_t, v_b):
     """(m, n, 2) training targets of a solved crossbar."""
-    v_in = np.asarray(v_in, dtype=np.float64)
-    return np.stack([(v_in[:, None] - v_t) / V_SCALE, np.asarray(v_b) / V_SCALE], axis=-1)
+    b_t, _ = base_guess(geom, g_dev, v_in)
+    return np.stack([(b_t - v_t) / V_SCALE, np.asarray(v_b) / V_SCALE], axis=-1)
 
 
-def voltages(v_in, y):
+def voltages(geom, g_dev, v_in, y):
     """(V_t, V_b) from the network's outputs y (m, n, 2)."""
-    v_in = np.asarray(v_in, dtype=np.float64)
-    return v_in[:, None] - V_SCALE * y[..., 0], V_SCALE * y[..., 1]
+    b_t, _ = base_guess(geom, g_dev, v_in)
+    return b_t - V_SCALE * y[..., 0], V_SCALE * y[..., 1]
 
 
 def conv3x3(x, w, b):
@@ -67,7 +100,7 @@ def conv3x3(x, w, b):
 
 
 def forward(params, x):
-    """Activations [x, a1, ..., a5, y] of one crossbar's features x (m, n, 3)."""
+    """Activations [x, a1, ..., a5, y] of one crossbar's features x (m, n, 4)."""
     acts = [np.asarray(x, dtype=np.float64)]
     for (w, b), (_, _, relu) in zip(params, LAYERS):
         z = conv3x3(acts[-1], w, b)

@@ -94,6 +94,7 @@ class Plan:
         if guess is not None:
             v_t.copy_(guess[0])
             v_b.copy_(guess[1])
+            opts = mca_options.from_buffer_copy(opts)
             opts.flags |= MCA_FLAG_INITIAL_GUESS
         ws = self.workspace(opts)
         status, stats = binding.mca_solve(self.handle, self.m, self.n, g_dev, v_in, v_t, v_b,
@@ -155,8 +156,9 @@ class Batch:
             self._ws_key = nbytes
         return self._ws
 
-    def solve(self, g_dev, v_in, opts=None, guess=None, out=None, check=True):
-        """(v_t, v_b, status, [stats]) over the concatenated arrays."""
+    def solve(self, g_dev, v_in, opts=None, guess=None, out=None, check=True, ws=None):
+        """(v_t, v_b, status, [stats]) over the concatenated arrays.  ws: optional
+        workspace tensor (at least mca_batch_workspace_bytes) shared between batches."""
         import torch
         if opts is None:
             opts = options(precond=MCA_PRECOND_PERMODE, precision=MCA_PREC_BF16X3)
@@ -168,8 +170,10 @@ class Batch:
         if guess is not None:
             v_t.copy_(guess[0])
             v_b.copy_(guess[1])
+            opts = mca_options.from_buffer_copy(opts)
             opts.flags |= MCA_FLAG_INITIAL_GUESS
-        ws = self.workspace(opts)
+        if ws is None:
+            ws = self.workspace(opts)
         status, stats = binding.mca_solve_batched(self.handle, self.count, self.total,
                                                   int(self.rows[-1]), g_dev, v_in, v_t, v_b,
                                                   opts, ws, check=check)

@@ -38,6 +38,7 @@ MCA_PRECOND_APPROX = 3
 MCA_PRECOND_JACOBI = 4
 MCA_FLAG_INITIAL_GUESS = 1
 MCA_FLAG_TIMING = 2
+MCA_FLAG_GUESS_FALLBACK = 4
 MCA_KCLASS_GEMM = 0
 MCA_KCLASS_JACOBIAN = 1
 MCA_KCLASS_ORTHO = 2
@@ -55,6 +56,8 @@ ABI_SYMBOLS = (
     "mca_precond_apply", "mca_solve",
     "mca_batch_create", "mca_batch_destroy", "mca_batch_offsets", "mca_batch_device_bytes",
     "mca_batch_upload", "mca_batch_workspace_bytes", "mca_solve_batched",
+    "mca_cnn_param_count", "mca_cnn_workspace_bytes", "mca_cnn_predict", "mca_cnn_gradient",
+    "mca_cnn_adam",
 )
 
 
@@ -78,7 +81,7 @@ class mca_stats(C.Structure):
                 ("residual_history", C.c_double * (MCA_MAX_NEWTON + 1)),
                 ("krylov_history", C.c_int32 * MCA_MAX_NEWTON),
                 ("kernel_ms", C.c_double * MCA_NUM_KCLASS),
-                ("kernel_launches", C.c_int32 * MCA_NUM_KCLASS)]
+                ("kernel_launches", C.c_int32 * MCA_NUM_KCLASS), ("start", C.c_int32)]
 
     def history(self):
         k = self.newton_iters
@@ -150,6 +153,17 @@ def lib():
     L.mca_solve_batched.argtypes = [vp, vp, vp, vp, vp, C.POINTER(mca_options), vp, sz,
                                     C.POINTER(mca_stats), vp]
     L.mca_solve_batched.restype = i32
+    L.mca_cnn_param_count.argtypes = []
+    L.mca_cnn_param_count.restype = C.c_int64
+    L.mca_cnn_workspace_bytes.argtypes = [i32, i32, i32]
+    L.mca_cnn_workspace_bytes.restype = sz
+    L.mca_cnn_predict.argtypes = [vp, i32, C.POINTER(mca_geometry), vp, vp, vp, vp, vp, sz, vp]
+    L.mca_cnn_predict.restype = i32
+    L.mca_cnn_gradient.argtypes = [vp, i32, C.POINTER(mca_geometry), vp, vp, vp, vp, vp, vp, vp,
+                                   sz, vp]
+    L.mca_cnn_gradient.restype = i32
+    L.mca_cnn_adam.argtypes = [vp, vp, vp, vp, i32, C.c_float, vp]
+    L.mca_cnn_adam.restype = i32
     _lib = L
     return L
 
@@ -349,3 +363,55 @@ def mca_solve_batched(batch, count, total, rows, g_dev, v_in, v_t, v_b, opts, ws
     if check:
         _check(status, "mca_solve_batched")
     return status, list(st)
+
+
+# ------------------------------------------------------- warm-start network
+def _f32(t, numel, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or \
+            not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{what}: expected a contiguous float32 GPU tensor of {numel} values")
+    return C.c_void_p(t.data_ptr())
+
+
+def mca_cnn_param_count() -> int:
+    return int(lib().mca_cnn_param_count())
+
+
+def mca_cnn_workspace_bytes(batch, m, n) -> int:
+    return int(lib().mca_cnn_workspace_bytes(int(batch), int(m), int(n)))
+
+
+def _geoms(geoms):
+    geoms = [g if isinstance(g, mca_geometry) else geometry_from(g) for g in geoms]
+    return (mca_geometry * len(geoms))(*geoms), len(geoms), geoms[0].m, geoms[0].n
+
+
+def mca_cnn_predict(params, geoms, g_dev, v_in, v_t, v_b, ws, stream=None):
+    """geoms: one geometry (mca_geometry or synth.Geometry) per crossbar of the batch."""
+    arr, batch, m, n = _geoms(geoms)
+    P = batch * m * n
+    wp, wbytes = _buf(ws, "ws")
+    _check(lib().mca_cnn_predict(_f32(params, mca_cnn_param_count(), "params"), batch, arr,
+                                 _ptr(g_dev, P, "g_dev"), _ptr(v_in, batch * m, "v_in"),
+                                 _ptr(v_t, P, "v_t"), _ptr(v_b, P, "v_b"), wp, wbytes,
+                                 _stream(stream)), "mca_cnn_predict")
+
+
+def mca_cnn_gradient(params, geoms, g_dev, v_in, v_t, v_b, grad, loss, ws, stream=None):
+    arr, batch, m, n = _geoms(geoms)
+    P = batch * m * n
+    wp, wbytes = _buf(ws, "ws")
+    npar = mca_cnn_param_count()
+    _check(lib().mca_cnn_gradient(_f32(params, npar, "params"), batch, arr,
+                                  _ptr(g_dev, P, "g_dev"), _ptr(v_in, batch * m, "v_in"),
+                                  _ptr(v_t, P, "v_t"), _ptr(v_b, P, "v_b"),
+                                  _f32(grad, npar, "grad"), _f32(loss, 1, "loss"), wp, wbytes,
+                                  _stream(stream)), "mca_cnn_gradient")
+
+
+def mca_cnn_adam(params, grad, adam_m, adam_v, step, lr, stream=None):
+    npar = mca_cnn_param_count()
+    _check(lib().mca_cnn_adam(_f32(params, npar, "params"), _f32(grad, npar, "grad"),
+                              _f32(adam_m, npar, "adam_m"), _f32(adam_v, npar, "adam_v"),
+                              int(step), float(lr), _stream(stream)), "mca_cnn_adam")

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmca.so")
-SOURCES = ["kernels.hip", "gemm.hip", "gemm_lp.hip", "batch.hip", "tridiag.hip", "eigen.cpp", "solver.cpp"]
+SOURCES = ["kernels.hip", "gemm.hip", "gemm_lp.hip", "batch.hip", "tridiag.hip", "cnn.hip", "eigen.cpp", "solver.cpp"]
 ARCH = "gfx950"
 
 # Packed-FP32 instructions are kept out of every code object; -O3 would emit

@@ -20,7 +20,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -53,6 +55,8 @@ struct BState {            // device control record of one crossbar
     int upd;               // columns of the last cycle to add into X
     int kry_step;          // GMRES iterations in this Newton step
     int ls_todo, accept, halvings;
+    int guess;             // started from the caller's guess
+    int reject;            // the guess is dropped for V = 0
 };
 constexpr int kStateInts = sizeof(BState) / sizeof(int);
 static_assert(sizeof(BState) % sizeof(double) == 0, "state record");
@@ -270,6 +274,7 @@ __global__ __launch_bounds__(TPB) void bk_axpy(
             case 1: v = x[e] + s.step * y[e]; break;       // trial = V + step X
             case 2: v = -(x[e] + y[e]); break;             // r = -(F + J X)
             case 3: v = x[e] / s.beta; break;              // v0 = r / beta
+            case 5: v = 0.0; break;                        // start from V = 0
             default: v = x[e]; break;                      // copy
             }
             out[e] = v;
@@ -600,6 +605,20 @@ __global__ void bk_restart_check(int count, BState *__restrict__ S)
     }
 }
 
+// guesses no better than V = 0 (whose residual is ||Y||) are dropped
+__global__ void bk_check_guess(int count, BState *__restrict__ S, int fallback)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    BState &s = S[b];
+    s.guess = 1;
+    s.reject = 0;
+    if (fallback && s.active && !(s.fnorm < s.ynorm && isfinite(s.dsum))) {
+        s.reject = 1;
+        s.guess = 0;
+    }
+}
+
 __global__ void bk_ls_init(int count, BState *__restrict__ S, int *__restrict__ khist, int k)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -670,7 +689,8 @@ int cblocks(int count) { return (count + 1023) / 1024; }
 // ====================================================================== host
 struct mca_batch {
     std::vector<mca_geometry> geoms;
-    std::vector<mca_plan *> plans;          // host eigen data per crossbar
+    std::vector<mca_plan *> plans;          // host eigen data per distinct geometry
+    std::vector<int> pidx;                  // plan of each crossbar
     std::vector<long long> ox, orow;        // offsets (count + 1 entries)
     std::vector<int2> btab;                 // block table
     std::vector<mca::BInst> inst;
@@ -705,13 +725,14 @@ struct BCarver {
     size_t size() const { return align256(off); }
 };
 
-// device block of a batch: descriptors, tables and every crossbar's eigenbases
+// device block of a batch: descriptors, tables and the eigenbases of every
+// distinct geometry (crossbars that share a geometry share them)
 struct BatchLayout {
     BInst *inst;
     int2 *btab;
     LpDesc *desc[2][4];
     int4 *tiles[4];
-    std::vector<float *> q32[4];                  // per crossbar: QnT, QmT, Qm, Qn
+    std::vector<float *> q32[4];                  // per plan: QnT, QmT, Qm, Qn
     std::vector<uint16_t *> qh[4], ql[4];
     std::vector<double *> lt, lb;
     size_t bytes;
@@ -729,15 +750,16 @@ BatchLayout batch_layout(const mca_batch *B, void *base)
     for (auto &p : L.desc)
         for (auto &d : p) d = c.take<LpDesc>(cnt);
     for (int s = 0; s < 4; ++s) L.tiles[s] = c.take<int4>(B->ntiles[s]);
+    const size_t np = B->plans.size();
     for (int s = 0; s < 4; ++s) {
-        L.q32[s].resize(cnt);
-        L.qh[s].resize(cnt);
-        L.ql[s].resize(cnt);
+        L.q32[s].resize(np);
+        L.qh[s].resize(np);
+        L.ql[s].resize(np);
     }
-    L.lt.resize(cnt);
-    L.lb.resize(cnt);
-    for (size_t b = 0; b < cnt; ++b) {
-        const size_t m = B->geoms[b].m, n = B->geoms[b].n;
+    L.lt.resize(np);
+    L.lb.resize(np);
+    for (size_t b = 0; b < np; ++b) {
+        const size_t m = B->plans[b]->geom.m, n = B->plans[b]->geom.n;
         const size_t sz[4] = {n * n, m * m, m * m, n * n};   // QnT, QmT, Qm, Qn
         for (int s = 0; s < 4; ++s) {
             L.q32[s][b] = c.take<float>(sz[s]);
@@ -823,7 +845,8 @@ mca_status batch_options_ok(const mca_options *o)
     if (o->precision != MCA_PREC_FP32 && o->precision != MCA_PREC_BF16X3 &&
         o->precision != MCA_PREC_BF16)
         return MCA_ERR_INVALID_ARG;
-    if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING)) return MCA_ERR_INVALID_ARG;
+    if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING | MCA_FLAG_GUESS_FALLBACK))
+        return MCA_ERR_INVALID_ARG;
     return MCA_OK;
 }
 
@@ -841,20 +864,37 @@ mca_status mca_batch_create(int32_t count, const mca_geometry *geoms, mca_batch 
     mca_batch *B = new (std::nothrow) mca_batch();
     if (!B) return MCA_ERR_INVALID_ARG;
     B->geoms.assign(geoms, geoms + count);
-    B->plans.assign(count, nullptr);
-    // eigen set-up of every crossbar's two wires, spread over host threads
-    std::vector<mca_status> st(count, MCA_OK);
+    // one plan per distinct geometry (bitwise equal records share it)
+    std::vector<int> first;                  // a crossbar of each distinct geometry
+    {
+        std::map<std::string, int> seen;
+        B->pidx.resize(count);
+        for (int b = 0; b < count; ++b) {
+            const std::string key(reinterpret_cast<const char *>(&geoms[b]), sizeof(mca_geometry));
+            auto it = seen.find(key);
+            if (it == seen.end()) {
+                it = seen.emplace(key, (int)first.size()).first;
+                first.push_back(b);
+            }
+            B->pidx[b] = it->second;
+        }
+    }
+    const int np = (int)first.size();
+    B->plans.assign(np, nullptr);
+    // eigen set-up of the two wires of every distinct geometry, spread over host threads
+    std::vector<mca_status> st(np, MCA_OK);
     const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
     for (unsigned t = 0; t < nt; ++t)
         pool.emplace_back([&, t]() {
-            for (int b = (int)t; b < count; b += (int)nt) st[b] = mca_plan_create(&geoms[b], &B->plans[b]);
+            for (int u = (int)t; u < np; u += (int)nt)
+                st[u] = mca_plan_create(&geoms[first[u]], &B->plans[u]);
         });
     for (auto &th : pool) th.join();
-    for (int b = 0; b < count; ++b)
-        if (st[b] != MCA_OK) {
+    for (int u = 0; u < np; ++u)
+        if (st[u] != MCA_OK) {
             mca_batch_destroy(B);
-            return st[b];
+            return st[u];
         }
     B->ox.assign(count + 1, 0);
     B->orow.assign(count + 1, 0);
@@ -865,7 +905,7 @@ mca_status mca_batch_create(int32_t count, const mca_geometry *geoms, mca_batch 
     B->len = 2 * (size_t)B->ox[count];
     B->inst.resize(count);
     for (int b = 0; b < count; ++b) {
-        const mca_plan *P = B->plans[b];
+        const mca_plan *P = B->plans[B->pidx[b]];
         BInst &I = B->inst[b];
         I.m = geoms[b].m;
         I.n = geoms[b].n;
@@ -926,8 +966,8 @@ mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *str
     std::memcpy(H.inst, B->inst.data(), cnt * sizeof(BInst));
     std::memcpy(H.btab, B->btab.data(), B->btab.size() * sizeof(int2));
     std::vector<double> tmp;
-    for (size_t b = 0; b < cnt; ++b) {
-        const mca_plan *P = B->plans[b];
+    for (size_t u = 0; u < B->plans.size(); ++u) {
+        const mca_plan *P = B->plans[u];
         const size_t m = P->geom.m, n = P->geom.n;
         // QnT, QmT, Qm, Qn in FP64 from the host eigenvectors
         for (int q = 0; q < 4; ++q) {
@@ -937,11 +977,15 @@ mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *str
             tmp.resize(L * L);
             for (size_t i = 0; i < L; ++i)
                 for (size_t j = 0; j < L; ++j) tmp[i * L + j] = tr ? src[j * L + i] : src[i * L + j];
-            split_host(tmp.data(), L * L, MCA_PREC_FP32, H.q32[q][b], nullptr);
-            split_host(tmp.data(), L * L, MCA_PREC_BF16X3, H.qh[q][b], H.ql[q][b]);
+            split_host(tmp.data(), L * L, MCA_PREC_FP32, H.q32[q][u], nullptr);
+            split_host(tmp.data(), L * L, MCA_PREC_BF16X3, H.qh[q][u], H.ql[q][u]);
         }
-        std::memcpy(H.lt[b], P->lt.data(), n * sizeof(double));
-        std::memcpy(H.lb[b], P->lb.data(), m * sizeof(double));
+        std::memcpy(H.lt[u], P->lt.data(), n * sizeof(double));
+        std::memcpy(H.lb[u], P->lb.data(), m * sizeof(double));
+    }
+    for (size_t b = 0; b < cnt; ++b) {
+        const int u = B->pidx[b];
+        const size_t m = B->geoms[b].m, n = B->geoms[b].n;
         // descriptors of the four products
         const int Ms[4] = {(int)n, (int)n, (int)m, (int)m}, Ns[4] = {(int)m, (int)m, (int)n, (int)n};
         const int Ks[4] = {(int)n, (int)m, (int)m, (int)n};
@@ -953,16 +997,16 @@ mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *str
                 d.K = Ks[st];
                 d.inst = (int)b;
                 if (f == 0) {
-                    d.Q[0] = D.q32[st][b];
+                    d.Q[0] = D.q32[st][u];
                     d.Q[1] = nullptr;
                 } else {
-                    d.Q[0] = D.qh[st][b];
-                    d.Q[1] = D.ql[st][b];
+                    d.Q[0] = D.qh[st][u];
+                    d.Q[1] = D.ql[st][u];
                 }
                 d.off_data = d.off_out = 2 * (size_t)B->ox[b];
                 d.mn = m * n;
-                d.lam_row = (st < 2) ? D.lt[b] : nullptr;
-                d.lam_col = (st < 2) ? D.lb[b] : nullptr;
+                d.lam_row = (st < 2) ? D.lt[u] : nullptr;
+                d.lam_col = (st < 2) ? D.lb[u] : nullptr;
                 // data rows are m*n-offset slices: aligned when 2 ox and mn are multiples of 8
                 d.vec = (d.K % 8 == 0) && ((2 * (size_t)B->ox[b]) % 8 == 0) && (d.mn % 8 == 0);
                 H.desc[f][st][b] = d;
@@ -1081,6 +1125,16 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
                        v_in, w.Vc, w.F, w.D, w.pa);
     hipLaunchKernelGGL(bk_inst_norms, dim3(cnt), blk, 0, s, B->d_inst, cnt, (const int *)nullptr,
                        w.pa, 0, w.S);
+    if (o.flags & MCA_FLAG_INITIAL_GUESS) {
+        const int *rjf = &w.S[0].reject;
+        hipLaunchKernelGGL(bk_check_guess, dim3(cb), dim3(ct), 0, s, cnt, w.S,
+                           (o.flags & MCA_FLAG_GUESS_FALLBACK) ? 1 : 0);
+        hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, rjf, w.S, 5,
+                           (const double *)nullptr, (const double *)nullptr, w.Vc);
+        hipLaunchKernelGGL(bk_residual, gridB, blk, 0, s, B->d_inst, B->d_btab, rjf, g_dev, v_in,
+                           w.Vc, w.F, w.D, w.pa);
+        hipLaunchKernelGGL(bk_inst_norms, dim3(cnt), blk, 0, s, B->d_inst, cnt, rjf, w.pa, 0, w.S);
+    }
     MCA_BTRY(hipGetLastError());
 
     for (int k = 0; k <= o.max_newton; ++k) {
@@ -1194,6 +1248,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
             t.restarts = x.restarts;
             t.rel_residual = x.ynorm > 0 ? x.fnorm / x.ynorm : 0.0;
             t.a_last = x.a;
+            t.start = x.guess;
             for (int i = 0; i <= std::min(x.newton, MCA_MAX_NEWTON); ++i)
                 t.residual_history[i] = rh[(size_t)b * (MCA_MAX_NEWTON + 1) + i];
             for (int i = 0; i < std::min(x.newton, MCA_MAX_NEWTON); ++i)

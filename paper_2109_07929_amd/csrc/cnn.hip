@@ -1,0 +1,727 @@
+// cnn.hip -- the warm-start network: a 6-layer 3x3 CNN that predicts the
+// crossbar's steady state from its inputs, so that Newton's method (eq.
+// (Newton3)) starts near the solution.  BF16 operands on MFMA with FP32
+// accumulation for inference and training (forward, backward, Adam).
+//
+// The network corrects a mean-field guess: the paper's approximate
+// preconditioner (eq. (block) with M ~ Mhat) applied to the drive vector Y at
+// a1 = a2 = a = mean(g_dev), which for Y_b = 0 is V0_t[i][j] = v_in[i] phi[j],
+// V0_b = 0 with phi = g_src (G_top + a I)^{-1} e_0 (one tridiagonal solve per
+// crossbar).  It carries what a 13 x 13 receptive field cannot see: the IR
+// drop accumulated along a whole wire.
+// Channels per crosspoint: f0 = log10(g_dev) + 5, f1 = v_in[i]/0.15 - 1,
+// f2 = (g_top - 0.5)/0.3, f3 = v_in[i] (1 - phi[j]) / 0.1; five 3x3
+// convolutions with 32 channels and ReLU, a linear 3x3 convolution to 2
+// outputs (y_t, y_b); V_t = v_in[i] phi[j] - 0.01 y_t, V_b = 0.01 y_b.  Zero
+// "same" padding.  Loss: mean (y - y_target)^2.
+//
+// Every activation is an NHWC bfloat16 tensor with 32 channels (64 bytes per
+// crosspoint; the 3 input channels and the 2 output gradients are zero-padded
+// to 32), so one MFMA convolution kernel serves every layer:
+//   out^T[co][p] = sum_tap sum_ci W[tap][co][ci] in[p + off(tap)][ci]
+// as v_mfma_f32_16x16x32_bf16 with A = weights (rows = output channels, K =
+// 32 input channels of one tap) and B = 16 crosspoints of an LDS-staged input
+// tile, so each lane ends with 4 consecutive channels of one crosspoint (one
+// 8-byte store).  The input gradient of a layer is the same kernel with the
+// taps mirrored and the channel roles swapped, its epilogue applying the ReLU
+// mask of the layer below.  Weight gradients contract over crosspoints:
+// dW[tap][ci][co] = sum_p in[p + off(tap)][ci] dZ[p][co], MFMA with K = 32
+// crosspoints of channel-major LDS tiles, per-workgroup partials reduced in a
+// fixed order.
+#include <hip/hip_bf16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mca_internal.h"
+
+namespace mca {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+constexpr int NC = 32;             // channels of every internal tensor
+constexpr int NL = 6;              // layers
+constexpr int TAPS = 9;
+constexpr int WSZ = TAPS * NC * NC;
+constexpr int CT = 256;            // threads per workgroup
+constexpr int TR = 8, TC = 64;     // convolution tile: rows x columns of crosspoints
+constexpr int PIX = 40;            // LDS pitch of one crosspoint (bf16)
+constexpr int WR = 4;              // weight-gradient tile rows (x TC columns)
+constexpr int HP = TC + 2 + 6;     // LDS pitch of one halo row (bf16), channel-major tiles
+constexpr int WGRAD_GRID = 512;
+constexpr double V_SCALE = 0.01;
+
+constexpr int kCi[NL] = {4, NC, NC, NC, NC, NC};
+constexpr int kCo[NL] = {NC, NC, NC, NC, NC, 2};
+
+__host__ __device__ constexpr int layer_offset(int l)
+{
+    int off = 0;
+    for (int k = 0; k < l; ++k) off += TAPS * kCi[k] * kCo[k] + kCo[k];
+    return off;
+}
+constexpr int kParams = layer_offset(NL);
+
+enum { EPI_RELU = 0, EPI_MASK = 1, EPI_OUT2 = 2 };
+
+struct ConvArgs {
+    int B, m, n, tiles_i, tiles_j;
+    const __bf16 *in;       // NHWC, 32 channels
+    const __bf16 *W;        // [tap][out channel][in channel]
+    const float *bias;      // 32 (EPI_RELU, EPI_OUT2)
+    const __bf16 *mask;     // EPI_MASK: NHWC activation of the layer below
+    __bf16 *out;            // NHWC (EPI_RELU, EPI_MASK)
+    float *outf;            // EPI_OUT2: 2 values per crosspoint
+};
+
+template <int EPI>
+__global__ __launch_bounds__(CT) void k_conv(ConvArgs a)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sIn[(TR + 2) * (TC + 2) * PIX];
+    const int tiles_per_img = a.tiles_i * a.tiles_j;
+    const int b = blockIdx.x / tiles_per_img;
+    const int t = blockIdx.x - b * tiles_per_img;
+    const int i0 = (t / a.tiles_j) * TR, j0 = (t % a.tiles_j) * TC;
+    const int m = a.m, n = a.n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // input tile with a one-crosspoint halo; zeros outside the array
+    constexpr int HPX = (TR + 2) * (TC + 2);
+    for (int q = threadIdx.x; q < HPX * 4; q += CT) {
+        const int px = q >> 2, part = q & 3;
+        const int hr = px / (TC + 2), hc = px - hr * (TC + 2);
+        const int i = i0 + hr - 1, j = j0 + hc - 1;
+        u4 v = {0u, 0u, 0u, 0u};
+        if (i >= 0 && i < m && j >= 0 && j < n)
+            v = *reinterpret_cast<const u4 *>(a.in + (((size_t)b * m + i) * n + j) * NC + part * 8);
+        *reinterpret_cast<u4 *>(&sIn[px * PIX + part * 8]) = v;
+    }
+    // weights: A fragments (row = output channel lane%16, K = 8 input channels)
+    bf8 wa[TAPS][2];
+#pragma unroll
+    for (int tap = 0; tap < TAPS; ++tap)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            wa[tap][u] = *reinterpret_cast<const bf8 *>(
+                a.W + ((size_t)tap * NC + u * 16 + (lane & 15)) * NC + (lane >> 4) * 8);
+    __syncthreads();
+
+    f4 acc[2][4][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) acc[r][c][u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < TAPS; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int hr = wave * 2 + r + dy, hc = c * 16 + (lane & 15) + dx;
+                const bf8 bv = *reinterpret_cast<const bf8 *>(
+                    &sIn[(hr * (TC + 2) + hc) * PIX + (lane >> 4) * 8]);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    acc[r][c][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[tap][u], bv,
+                                                                           acc[r][c][u], 0, 0, 0);
+            }
+    }
+
+    // lane holds output channels u*16 + 4(lane/16) + e of crosspoint column lane%16
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = i0 + wave * 2 + r, j = j0 + c * 16 + (lane & 15);
+            if (i >= m || j >= n) continue;
+            const size_t p = ((size_t)b * m + i) * n + j;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int co = u * 16 + (lane >> 4) * 4;
+                const f4 v = acc[r][c][u];
+                if constexpr (EPI == EPI_OUT2) {
+                    if (u == 0 && (lane >> 4) == 0) {
+                        a.outf[2 * p] = v[0] + a.bias[0];
+                        a.outf[2 * p + 1] = v[1] + a.bias[1];
+                    }
+                } else {
+                    bf4 o;
+                    if constexpr (EPI == EPI_RELU) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) o[e] = (__bf16)fmaxf(v[e] + a.bias[co + e], 0.f);
+                    } else {
+                        const bf4 mk = *reinterpret_cast<const bf4 *>(a.mask + p * NC + co);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            o[e] = (__bf16)(((float)mk[e] > 0.f) ? v[e] : 0.f);
+                    }
+                    *reinterpret_cast<bf4 *>(a.out + p * NC + co) = o;
+                }
+            }
+        }
+}
+
+struct WgradArgs {
+    int B, m, n, tiles_i, tiles_j, ntiles;
+    const __bf16 *in;       // layer input (NHWC, 32 channels)
+    const __bf16 *dz;       // gradient at the layer output (NHWC, 32 channels)
+    float *part;            // per workgroup: 9 x 32 x 32 weight sums, then 32 bias sums
+};
+
+__global__ __launch_bounds__(CT) void k_conv_wgrad(WgradArgs a)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sA[NC * (WR + 2) * HP];
+    __shared__ __attribute__((aligned(16))) __bf16 sD[NC * WR * TC];
+    __shared__ float sB[8][NC];
+    __shared__ float red[NC * NC];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = a.m, n = a.n;
+    f4 acc[TAPS][2][2];
+#pragma unroll
+    for (int tap = 0; tap < TAPS; ++tap)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) acc[tap][s][u] = f4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;   // bias gradient: channel threadIdx % 32, pixels of segment threadIdx / 32
+    const int tiles_per_img = a.tiles_i * a.tiles_j;
+
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int b = tile / tiles_per_img;
+        const int t = tile - b * tiles_per_img;
+        const int i0 = (t / a.tiles_j) * WR, j0 = (t % a.tiles_j) * TC;
+        __syncthreads();   // the previous tile's LDS reads are done
+        // input with halo, channel-major: sA[c][hr][hc]
+        for (int q = threadIdx.x; q < (WR + 2) * (TC + 2) * 4; q += CT) {
+            const int px = q >> 2, part = q & 3;
+            const int hr = px / (TC + 2), hc = px - hr * (TC + 2);
+            const int i = i0 + hr - 1, j = j0 + hc - 1;
+            bf8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
+            if (i >= 0 && i < m && j >= 0 && j < n)
+                v = *reinterpret_cast<const bf8 *>(a.in + (((size_t)b * m + i) * n + j) * NC + part * 8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sA[((part * 8 + e) * (WR + 2) + hr) * HP + hc] = v[e];
+        }
+        // output gradient, channel-major: sD[c][r][col]
+        for (int q = threadIdx.x; q < WR * TC * 4; q += CT) {
+            const int px = q >> 2, part = q & 3;
+            const int r = px / TC, col = px - r * TC;
+            const int i = i0 + r, j = j0 + col;
+            bf8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
+            if (i < m && j < n)
+                v = *reinterpret_cast<const bf8 *>(a.dz + (((size_t)b * m + i) * n + j) * NC + part * 8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sD[((part * 8 + e) * WR + r) * TC + col] = v[e];
+        }
+        __syncthreads();
+        {
+            const int c = threadIdx.x & 31, seg = threadIdx.x >> 5;   // 8 segments of 32 pixels
+            for (int k = 0; k < WR * TC / 8; ++k) {
+                const int px = seg * (WR * TC / 8) + k;
+                bsum += (float)sD[(c * WR + px / TC) * TC + px % TC];
+            }
+        }
+        // wave w: row w of the tile, two K-blocks of 32 crosspoints
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = wave;
+            bf8 bd[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                bd[u] = *reinterpret_cast<const bf8 *>(
+                    &sD[((u * 16 + (lane & 15)) * WR + r) * TC + h * 32 + (lane >> 4) * 8]);
+#pragma unroll
+            for (int tap = 0; tap < TAPS; ++tap) {
+                const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const __bf16 *src =
+                        &sA[((s * 16 + (lane & 15)) * (WR + 2) + r + dy) * HP + h * 32 + (lane >> 4) * 8 + dx];
+                    bf8 av;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) av[e] = src[e];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        acc[tap][s][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bd[u],
+                                                                                 acc[tap][s][u], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // partial sums of this workgroup: lane holds dW rows (input channels)
+    // s*16 + 4(lane/16) + e, column (output channel) u*16 + lane%16; the four
+    // waves hold different crosspoints and are summed in wave order, tap by tap
+    float *out = a.part + (size_t)blockIdx.x * (WSZ + NC);
+#pragma unroll
+    for (int tap = 0; tap < TAPS; ++tap) {
+        for (int w = 0; w < 4; ++w) {
+            __syncthreads();
+            if (wave == w) {
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int ci = s * 16 + (lane >> 4) * 4 + e, co = u * 16 + (lane & 15);
+                            const float v = acc[tap][s][u][e];
+                            red[ci * NC + co] = (w == 0) ? v : red[ci * NC + co] + v;
+                        }
+            }
+        }
+        __syncthreads();
+        for (int o = threadIdx.x; o < NC * NC; o += CT) out[tap * NC * NC + o] = red[o];
+    }
+    sB[threadIdx.x >> 5][threadIdx.x & 31] = bsum;
+    __syncthreads();
+    if (threadIdx.x < NC) {
+        float s = 0.f;
+        for (int g = 0; g < 8; ++g) s += sB[g][threadIdx.x];
+        out[WSZ + threadIdx.x] = s;
+    }
+}
+
+// sum of the workgroup partials (fixed order) into the packed gradient of layer l
+__global__ __launch_bounds__(CT) void k_wgrad_reduce(const float *__restrict__ part, int nparts,
+                                                     int layer, float *__restrict__ grad)
+{
+    const int ci_n = kCi[layer], co_n = kCo[layer];
+    const int nw = TAPS * ci_n * co_n;
+    float *g = grad + layer_offset(layer);
+    for (int q = blockIdx.x * CT + threadIdx.x; q < nw + co_n; q += gridDim.x * CT) {
+        int src;
+        if (q < nw) {
+            const int tap = q / (ci_n * co_n), rem = q - tap * ci_n * co_n;
+            const int ci = rem / co_n, co = rem - ci * co_n;
+            src = (tap * NC + ci) * NC + co;
+        } else {
+            src = WSZ + (q - nw);
+        }
+        float s = 0.f;
+        for (int k = 0; k < nparts; ++k) s += part[(size_t)k * (WSZ + NC) + src];
+        g[q] = s;
+    }
+}
+
+// master FP32 parameters -> bf16 forward weights [tap][co][ci], mirrored
+// backward weights [tap'][ci][co] = w[8 - tap'][ci][co], FP32 biases; zero padded
+__global__ __launch_bounds__(CT) void k_pack(const float *__restrict__ params, __bf16 *__restrict__ Wf,
+                                             __bf16 *__restrict__ Wb, float *__restrict__ bias)
+{
+    for (int q = blockIdx.x * CT + threadIdx.x; q < NL * (WSZ + NC); q += gridDim.x * CT) {
+        const int l = q / (WSZ + NC), rem = q - l * (WSZ + NC);
+        const float *w = params + layer_offset(l);
+        const int ci_n = kCi[l], co_n = kCo[l];
+        if (rem < WSZ) {
+            const int tap = rem / (NC * NC), r2 = rem - tap * NC * NC;
+            const int x = r2 / NC, y = r2 - x * NC;
+            // Wf[tap][co = x][ci = y]
+            Wf[(size_t)l * WSZ + rem] =
+                (__bf16)((x < co_n && y < ci_n) ? w[(tap * ci_n + y) * co_n + x] : 0.f);
+            // Wb[tap][ci = x][co = y] = w[8 - tap][x][y]
+            Wb[(size_t)l * WSZ + rem] =
+                (__bf16)((x < ci_n && y < co_n) ? w[((8 - tap) * ci_n + x) * co_n + y] : 0.f);
+        } else {
+            const int c = rem - WSZ;
+            bias[l * NC + c] = (c < co_n) ? w[TAPS * ci_n * co_n + c] : 0.f;
+        }
+    }
+}
+
+// Per crossbar (one workgroup each): a = mean(g_dev) (fixed-order block sum),
+// then phi = g_src (G_top + a I)^{-1} e_0 by Gaussian elimination on the
+// tridiagonal top-wire matrix (one thread; diagonally dominant, no pivoting).
+// wires[b] = (g_top, g_src, g_top_end); cp is n doubles of scratch per crossbar.
+__global__ __launch_bounds__(CT) void k_meanfield(int m, int n, const double *__restrict__ g_dev,
+                                                  const double *__restrict__ wires,
+                                                  double *__restrict__ phi, double *__restrict__ cp)
+{
+    const int b = blockIdx.x;
+    const size_t mn = (size_t)m * n;
+    double acc = 0.0;
+    for (size_t k = threadIdx.x; k < mn; k += CT) acc += g_dev[(size_t)b * mn + k];
+    __shared__ double sh[CT / 64];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double sum = 0.0;
+    for (int w = 0; w < CT / 64; ++w) sum += sh[w];
+    const double a = sum / (double)mn;
+    const double g = wires[3 * b], gsrc = wires[3 * b + 1], gend = wires[3 * b + 2];
+    double *ph = phi + (size_t)b * n, *c = cp + (size_t)b * n;
+    // forward elimination: diag_k = g (neighbours) + end terms + a, off = -g
+    for (int k = 0; k < n; ++k) {
+        const double diag = ((k > 0) ? g : gsrc) + ((k + 1 < n) ? g : gend) + a;
+        const double rhs = (k == 0) ? gsrc : 0.0;
+        const double den = (k > 0) ? diag + g * c[k - 1] : diag;   // diag - (-g) c'[k-1]
+        c[k] = (k + 1 < n) ? -g / den : 0.0;
+        ph[k] = (k > 0) ? (rhs + g * ph[k - 1]) / den : rhs / den;
+    }
+    for (int k = n - 2; k >= 0; --k) ph[k] -= c[k] * ph[k + 1];
+}
+
+// input channels (zero-padded to 32)
+__global__ __launch_bounds__(CT) void k_features(int B, int m, int n, const double *__restrict__ g_dev,
+                                                 const double *__restrict__ v_in,
+                                                 const double *__restrict__ wires,
+                                                 const double *__restrict__ phi,
+                                                 __bf16 *__restrict__ x)
+{
+    const size_t P = (size_t)B * m * n;
+    for (size_t p = (size_t)blockIdx.x * CT + threadIdx.x; p < P; p += (size_t)gridDim.x * CT) {
+        const size_t row = p / n;                // b * m + i
+        const int b = (int)(row / m);
+        const int j = (int)(p - row * n);
+        const double vin = v_in[row];
+        bf8 v0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v0[e] = (__bf16)0.f;
+        v0[0] = (__bf16)(float)(log10(g_dev[p]) + 5.0);
+        v0[1] = (__bf16)(float)(vin / 0.15 - 1.0);
+        v0[2] = (__bf16)(float)((wires[3 * b] - 0.5) / 0.3);
+        v0[3] = (__bf16)(float)(vin * (1.0 - phi[(size_t)b * n + j]) / 0.1);
+        bf8 z;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.f;
+        bf8 *o = reinterpret_cast<bf8 *>(x + p * NC);
+        o[0] = v0;
+        o[1] = z;
+        o[2] = z;
+        o[3] = z;
+    }
+}
+
+// y (2 per crosspoint) -> voltages
+__global__ __launch_bounds__(CT) void k_voltages(int B, int m, int n, const float *__restrict__ y,
+                                                 const double *__restrict__ v_in,
+                                                 const double *__restrict__ phi,
+                                                 double *__restrict__ vt, double *__restrict__ vb)
+{
+    const size_t P = (size_t)B * m * n;
+    for (size_t p = (size_t)blockIdx.x * CT + threadIdx.x; p < P; p += (size_t)gridDim.x * CT) {
+        const size_t row = p / n;
+        const size_t b = row / m, j = p - row * n;
+        vt[p] = v_in[row] * phi[b * n + j] - V_SCALE * (double)y[2 * p];
+        vb[p] = V_SCALE * (double)y[2 * p + 1];
+    }
+}
+
+// loss partials and dL/dy (zero-padded to 32 channels)
+__global__ __launch_bounds__(CT) void k_loss(int B, int m, int n, const float *__restrict__ y,
+                                             const double *__restrict__ v_in,
+                                             const double *__restrict__ phi,
+                                             const double *__restrict__ vt,
+                                             const double *__restrict__ vb, __bf16 *__restrict__ dy,
+                                             float *__restrict__ part)
+{
+    const size_t P = (size_t)B * m * n;
+    const float scale = (float)(2.0 / (2.0 * (double)P));
+    float acc = 0.f;
+    for (size_t p = (size_t)blockIdx.x * CT + threadIdx.x; p < P; p += (size_t)gridDim.x * CT) {
+        const size_t row = p / n;
+        const size_t bb = row / m, j = p - row * n;
+        const float t0 = (float)((v_in[row] * phi[bb * n + j] - vt[p]) / V_SCALE);
+        const float t1 = (float)(vb[p] / V_SCALE);
+        const float d0 = y[2 * p] - t0, d1 = y[2 * p + 1] - t1;
+        acc += d0 * d0 + d1 * d1;
+        bf8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
+        v[0] = (__bf16)(scale * d0);
+        v[1] = (__bf16)(scale * d1);
+        bf8 z;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.f;
+        bf8 *o = reinterpret_cast<bf8 *>(dy + p * NC);
+        o[0] = v;
+        o[1] = z;
+        o[2] = z;
+        o[3] = z;
+    }
+    __shared__ float sh[CT / 64];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int w = 0; w < CT / 64; ++w) s += sh[w];
+        part[blockIdx.x] = s;
+    }
+}
+
+__global__ void k_loss_final(const float *__restrict__ part, int nb, size_t count,
+                             float *__restrict__ loss)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += part[k];
+    loss[0] = (float)(s / (2.0 * (double)count));
+}
+
+__global__ __launch_bounds__(CT) void k_adam(float *__restrict__ p, const float *__restrict__ g,
+                                             float *__restrict__ m, float *__restrict__ v, int count,
+                                             float lr, float c1, float c2)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    for (int q = blockIdx.x * CT + threadIdx.x; q < count; q += gridDim.x * CT) {
+        const float gg = g[q];
+        const float mm = b1 * m[q] + (1.f - b1) * gg;
+        const float vv = b2 * v[q] + (1.f - b2) * gg * gg;
+        m[q] = mm;
+        v[q] = vv;
+        p[q] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    }
+}
+
+constexpr int kLossBlocks = 1024;
+
+size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct CnnWs {
+    __bf16 *Wf, *Wb;
+    float *bias;
+    double *wires, *phi, *cp;   // per crossbar: (g_top, g_src, g_top_end), profile, scratch
+    __bf16 *act[NL];     // act[0] = features, act[l] = output of layer l (l = 1..5)
+    float *y;
+    __bf16 *dy, *dz[2];
+    float *part, *lpart;
+    size_t bytes;
+};
+
+CnnWs cnn_ws(int B, int m, int n, void *base)
+{
+    char *p = static_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = al256(off);
+        char *r = p ? p + off : nullptr;
+        off += bytes;
+        return r;
+    };
+    const size_t P = (size_t)B * m * n;
+    CnnWs w{};
+    w.Wf = reinterpret_cast<__bf16 *>(take((size_t)NL * WSZ * 2));
+    w.Wb = reinterpret_cast<__bf16 *>(take((size_t)NL * WSZ * 2));
+    w.bias = reinterpret_cast<float *>(take((size_t)NL * NC * 4));
+    w.wires = reinterpret_cast<double *>(take((size_t)B * 3 * 8));
+    w.phi = reinterpret_cast<double *>(take((size_t)B * n * 8));
+    w.cp = reinterpret_cast<double *>(take((size_t)B * n * 8));
+    for (int l = 0; l < NL; ++l) w.act[l] = reinterpret_cast<__bf16 *>(take(P * NC * 2));
+    w.y = reinterpret_cast<float *>(take(P * 2 * 4));
+    w.dy = reinterpret_cast<__bf16 *>(take(P * NC * 2));
+    w.dz[0] = reinterpret_cast<__bf16 *>(take(P * NC * 2));
+    w.dz[1] = reinterpret_cast<__bf16 *>(take(P * NC * 2));
+    w.part = reinterpret_cast<float *>(take((size_t)WGRAD_GRID * (WSZ + NC) * 4));
+    w.lpart = reinterpret_cast<float *>(take(kLossBlocks * 4));
+    w.bytes = al256(off);
+    return w;
+}
+
+int ew_grid(size_t count) { return (int)std::max<size_t>(1, std::min<size_t>((count + CT - 1) / CT, 4096)); }
+
+hipError_t conv(int epi, int B, int m, int n, const __bf16 *in, const __bf16 *W, const float *bias,
+                const __bf16 *mask, __bf16 *out, float *outf, hipStream_t s)
+{
+    ConvArgs a{};
+    a.B = B;
+    a.m = m;
+    a.n = n;
+    a.tiles_i = (m + TR - 1) / TR;
+    a.tiles_j = (n + TC - 1) / TC;
+    a.in = in;
+    a.W = W;
+    a.bias = bias;
+    a.mask = mask;
+    a.out = out;
+    a.outf = outf;
+    const dim3 grid((unsigned)((size_t)B * a.tiles_i * a.tiles_j));
+    switch (epi) {
+    case EPI_RELU: hipLaunchKernelGGL(k_conv<EPI_RELU>, grid, dim3(CT), 0, s, a); break;
+    case EPI_MASK: hipLaunchKernelGGL(k_conv<EPI_MASK>, grid, dim3(CT), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_conv<EPI_OUT2>, grid, dim3(CT), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t wgrad(int layer, int B, int m, int n, const __bf16 *in, const __bf16 *dz, float *part,
+                 float *grad, hipStream_t s)
+{
+    WgradArgs a{};
+    a.B = B;
+    a.m = m;
+    a.n = n;
+    a.tiles_i = (m + WR - 1) / WR;
+    a.tiles_j = (n + TC - 1) / TC;
+    a.ntiles = B * a.tiles_i * a.tiles_j;
+    a.in = in;
+    a.dz = dz;
+    a.part = part;
+    const int grid = std::min(a.ntiles, WGRAD_GRID);
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(grid), dim3(CT), 0, s, a);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(8), dim3(CT), 0, s, part, grid, layer, grad);
+    return hipGetLastError();
+}
+
+// forward pass: features, packed weights, five ReLU layers, the output layer
+// the per-crossbar wire table -> device (synchronises s: the host table is local)
+hipError_t upload_wires(const mca_geometry *geoms, int B, const CnnWs &w, hipStream_t s)
+{
+    std::vector<double> tab(3 * (size_t)B);
+    for (int b = 0; b < B; ++b) {
+        tab[3 * b] = geoms[b].g_top;
+        tab[3 * b + 1] = geoms[b].g_src;
+        tab[3 * b + 2] = geoms[b].g_top_end;
+    }
+    hipError_t e = hipMemcpyAsync(w.wires, tab.data(), tab.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+}
+
+hipError_t forward(const float *params, int B, int m, int n, const double *g_dev,
+                   const double *v_in, const CnnWs &w, hipStream_t s)
+{
+    const size_t P = (size_t)B * m * n;
+    hipLaunchKernelGGL(k_pack, dim3(ew_grid(NL * (WSZ + NC))), dim3(CT), 0, s, params, w.Wf, w.Wb,
+                       w.bias);
+    hipLaunchKernelGGL(k_meanfield, dim3(B), dim3(CT), 0, s, m, n, g_dev, w.wires, w.phi, w.cp);
+    hipLaunchKernelGGL(k_features, dim3(ew_grid(P)), dim3(CT), 0, s, B, m, n, g_dev, v_in, w.wires,
+                       w.phi, w.act[0]);
+    hipError_t e = hipGetLastError();
+    for (int l = 0; l < NL - 1 && e == hipSuccess; ++l)
+        e = conv(EPI_RELU, B, m, n, w.act[l], w.Wf + (size_t)l * WSZ, w.bias + l * NC, nullptr,
+                 w.act[l + 1], nullptr, s);
+    if (e == hipSuccess)
+        e = conv(EPI_OUT2, B, m, n, w.act[NL - 1], w.Wf + (size_t)(NL - 1) * WSZ,
+                 w.bias + (NL - 1) * NC, nullptr, nullptr, w.y, s);
+    return e;
+}
+
+bool dims_ok(int B, int m, int n) { return B >= 1 && m >= 1 && n >= 1; }
+
+// every crossbar of a network batch has the batch's size and a valid top wire
+bool geoms_ok(const mca_geometry *geoms, int B)
+{
+    if (!geoms || B < 1) return false;
+    for (int b = 0; b < B; ++b) {
+        const mca_geometry &g = geoms[b];
+        if (g.m != geoms[0].m || g.n != geoms[0].n || g.m < 1 || g.n < 1) return false;
+        if (!(g.g_top > 0.0) || !(g.g_src >= 0.0) || !(g.g_top_end >= 0.0) ||
+            !(g.g_src + g.g_top_end > 0.0) || !std::isfinite(g.g_top) || !std::isfinite(g.g_src) ||
+            !std::isfinite(g.g_top_end))
+            return false;
+    }
+    return true;
+}
+
+}  // namespace
+}  // namespace mca
+
+using namespace mca;
+
+extern "C" {
+
+int64_t mca_cnn_param_count(void) { return kParams; }
+
+size_t mca_cnn_workspace_bytes(int32_t batch, int32_t m, int32_t n)
+{
+    if (!dims_ok(batch, m, n)) return 0;
+    return cnn_ws(batch, m, n, nullptr).bytes;
+}
+
+mca_status mca_cnn_predict(const float *params, int32_t batch, const mca_geometry *geoms,
+                           const double *g_dev, const double *v_in, double *v_t, double *v_b,
+                           void *ws, size_t ws_bytes, void *stream)
+{
+    if (!params || !g_dev || !v_in || !v_t || !v_b || !geoms_ok(geoms, batch))
+        return MCA_ERR_INVALID_ARG;
+    const int m = geoms[0].m, n = geoms[0].n;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return MCA_ERR_WORKSPACE;
+    const CnnWs w = cnn_ws(batch, m, n, ws);
+    if (ws_bytes < w.bytes) return MCA_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = upload_wires(geoms, batch, w, s);
+    if (e == hipSuccess) e = forward(params, batch, m, n, g_dev, v_in, w, s);
+    if (e == hipSuccess) {
+        const size_t P = (size_t)batch * m * n;
+        hipLaunchKernelGGL(k_voltages, dim3(ew_grid(P)), dim3(CT), 0, s, batch, m, n, w.y, v_in,
+                           w.phi, v_t, v_b);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        set_hip_error("mca_cnn_predict", e);
+        return MCA_ERR_HIP;
+    }
+    return MCA_OK;
+}
+
+mca_status mca_cnn_gradient(const float *params, int32_t batch, const mca_geometry *geoms,
+                            const double *g_dev, const double *v_in, const double *v_t,
+                            const double *v_b, float *grad, float *loss, void *ws,
+                            size_t ws_bytes, void *stream)
+{
+    if (!params || !g_dev || !v_in || !v_t || !v_b || !grad || !loss || !geoms_ok(geoms, batch))
+        return MCA_ERR_INVALID_ARG;
+    const int m = geoms[0].m, n = geoms[0].n;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return MCA_ERR_WORKSPACE;
+    const CnnWs w = cnn_ws(batch, m, n, ws);
+    if (ws_bytes < w.bytes) return MCA_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t P = (size_t)batch * m * n;
+    hipError_t e = upload_wires(geoms, batch, w, s);
+    if (e == hipSuccess) e = forward(params, batch, m, n, g_dev, v_in, w, s);
+    if (e == hipSuccess) {
+        const int nb = std::min(ew_grid(P), kLossBlocks);
+        hipLaunchKernelGGL(k_loss, dim3(nb), dim3(CT), 0, s, batch, m, n, w.y, v_in, w.phi, v_t,
+                           v_b, w.dy, w.lpart);
+        hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, w.lpart, nb, P, loss);
+        e = hipGetLastError();
+    }
+    // backward: layer l's weight gradient from its input act[l] and output gradient,
+    // then the gradient at act[l] through the mirrored weights and act[l]'s ReLU mask
+    const __bf16 *dout = w.dy;
+    for (int l = NL - 1; l >= 0 && e == hipSuccess; --l) {
+        e = wgrad(l, batch, m, n, w.act[l], dout, w.part, grad, s);
+        if (e != hipSuccess || l == 0) break;
+        __bf16 *din = w.dz[l & 1];
+        e = conv(EPI_MASK, batch, m, n, dout, w.Wb + (size_t)l * WSZ, nullptr, w.act[l], din,
+                 nullptr, s);
+        dout = din;
+    }
+    if (e != hipSuccess) {
+        set_hip_error("mca_cnn_gradient", e);
+        return MCA_ERR_HIP;
+    }
+    return MCA_OK;
+}
+
+mca_status mca_cnn_adam(float *params, const float *grad, float *adam_m, float *adam_v,
+                        int32_t step, float lr, void *stream)
+{
+    if (!params || !grad || !adam_m || !adam_v || step < 1 || !(lr > 0.f)) return MCA_ERR_INVALID_ARG;
+    const float c1 = 1.f - std::pow(0.9f, (float)step), c2 = 1.f - std::pow(0.999f, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(ew_grid(kParams)), dim3(CT), 0, static_cast<hipStream_t>(stream),
+                       params, grad, adam_m, adam_v, (int)kParams, lr, c1, c2);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_hip_error("mca_cnn_adam", e);
+        return MCA_ERR_HIP;
+    }
+    return MCA_OK;
+}
+
+}  // extern "C"

@@ -80,7 +80,8 @@ mca_status validate_options(const mca_options *o)
     if (o->precision != MCA_PREC_FP64 && o->precond != MCA_PRECOND_PERMODE &&
         o->precond != MCA_PRECOND_NONE)
         return MCA_ERR_INVALID_ARG;
-    if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING)) return MCA_ERR_INVALID_ARG;
+    if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING | MCA_FLAG_GUESS_FALLBACK))
+        return MCA_ERR_INVALID_ARG;
     return MCA_OK;
 }
 
@@ -825,6 +826,14 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     SolveWs wk = w;
     st = residual_norms(P, g_dev, v_in, Vc, Vc + mn, F, D, wk, s, &tm, &fnorm, &dsum);
     if (st == MCA_ERR_HIP) return st;
+    int from_guess = (o.flags & MCA_FLAG_INITIAL_GUESS) ? 1 : 0;
+    if (from_guess && (o.flags & MCA_FLAG_GUESS_FALLBACK) && !(st == MCA_OK && fnorm < ynorm)) {
+        // the guess is no better than V = 0, whose residual is ||Y||: start from 0
+        MCA_TRY(launch_fill(Vc, 0.0, len, s));
+        st = residual_norms(P, g_dev, v_in, Vc, Vc + mn, F, D, wk, s, &tm, &fnorm, &dsum);
+        if (st == MCA_ERR_HIP) return st;
+        from_guess = 0;
+    }
 
     mca_status result = (st == MCA_OK) ? MCA_ERR_NOT_CONVERGED : st;
     int k = 0, total_its = 0, backtracks = 0, restarts = 0;
@@ -884,6 +893,7 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
         stats->restarts = restarts;
         stats->rel_residual = fnorm / ynorm;
         stats->a_last = a;
+        stats->start = from_guess;
         for (int c = 0; c < MCA_NUM_KCLASS; ++c) {
             stats->kernel_ms[c] = tm.ms[c];
             stats->kernel_launches[c] = tm.launches[c];

@@ -114,7 +114,7 @@ def mc_batch(count: int, seed: int = 0, sizes=tuple(range(64, 513, 64)),
 
 
 # ------------------------------------------------------- warm-start network
-CNN_LAYERS = [(3, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 2)]
+CNN_LAYERS = [(4, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 2)]
 
 
 def cnn_init(seed: int = 0) -> np.ndarray:
@@ -128,3 +128,35 @@ def cnn_init(seed: int = 0) -> np.ndarray:
         out.append(rng.standard_normal(9 * ci * co) * std)
         out.append(np.zeros(co))
     return np.concatenate(out).astype(np.float32)
+
+
+# ------------------------------------------ warm-start training / evaluation
+# Crossbars of one size with the Monte-Carlo distributions above (16-level
+# weights with lognormal variation, drives U[0, 0.3]), drawn on the GPU with
+# torch's seeded generator so that tens of thousands of 512 x 512 crossbars
+# need no host work.  The wire conductance takes one of WIRE_LEVELS values
+# spread evenly over [0.2, 0.8] S (equal shares), so that the crossbars of
+# one level share a geometry and the solver's set-up for it.
+WIRE_LEVELS = 64
+
+
+def wire_level(k: int) -> float:
+    return 0.2 + 0.6 * (k + 0.5) / WIRE_LEVELS
+
+
+def level_geometry(m: int, n: int, k: int) -> Geometry:
+    gw = wire_level(k)
+    return Geometry(m, n, g_top=gw, g_bot=gw, g_src=gw)
+
+
+def mc_device_batch(count: int, m: int, n: int, seed: int, device="cuda", sigma: float = 0.3):
+    """(g_dev (count, m, n), v_in (count, m)) as float64 device tensors; draw
+    order: weight levels, variation, drives."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    q = torch.randint(0, 16, (count, m, n), generator=gen, device=device).to(torch.float64)
+    z = torch.randn((count, m, n), generator=gen, device=device, dtype=torch.float64)
+    g_dev = 1e-6 * torch.pow(100.0, q / 15.0) * torch.exp(sigma * z)
+    v_in = 0.3 * torch.rand((count, m), generator=gen, device=device, dtype=torch.float64)
+    return g_dev.contiguous(), v_in.contiguous()

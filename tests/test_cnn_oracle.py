@@ -48,7 +48,7 @@ def _small_net(seed):
 
 
 def test_param_packing():
-    assert cnn.param_count() == 3 * 9 * 32 + 32 + 4 * (32 * 9 * 32 + 32) + 32 * 9 * 2 + 2
+    assert cnn.param_count() == 4 * 9 * 32 + 32 + 4 * (32 * 9 * 32 + 32) + 32 * 9 * 2 + 2
     flat = synth.cnn_init(3)
     assert flat.size == cnn.param_count()
     np.testing.assert_array_equal(cnn.pack(cnn.unpack(flat)), flat.astype(np.float64))
@@ -60,7 +60,9 @@ def test_gradients_match_finite_differences():
     xs, ts = [], []
     for shape in ((5, 4), (3, 6)):
         g = 10 ** rng.uniform(-6, -4, shape)
-        xs.append(cnn.features(g, rng.uniform(0, 0.3, shape[0]), rng.uniform(0.2, 0.8)))
+        w = rng.uniform(0.2, 0.8)
+        geom = synth.Geometry(shape[0], shape[1], g_top=w, g_bot=w, g_src=w)
+        xs.append(cnn.features(geom, g, rng.uniform(0, 0.3, shape[0])))
         ts.append(rng.standard_normal(shape + (2,)))
 
     def total_loss(ps):
@@ -104,15 +106,37 @@ def test_adam_first_step_is_lr_times_sign():
 
 def test_voltage_parameterisation_round_trip():
     rng = np.random.default_rng(3)
+    geom = synth.Geometry(4, 5)
+    g = 10 ** rng.uniform(-6, -4, (4, 5))
     v_in = rng.uniform(0, 0.3, 4)
     vt, vb = rng.uniform(0, 0.3, (4, 5)), rng.uniform(0, 0.05, (4, 5))
-    rt, rb = cnn.voltages(v_in, cnn.targets(v_in, vt, vb))
+    rt, rb = cnn.voltages(geom, g, v_in, cnn.targets(geom, g, v_in, vt, vb))
     np.testing.assert_allclose(rt, vt, atol=1e-15)
     np.testing.assert_allclose(rb, vb, atol=1e-15)
 
 
 def test_features_definition():
-    f = cnn.features(np.array([[1e-6, 1e-4]]), np.array([0.3]), 0.8)
+    geom = synth.Geometry(1, 2, g_top=0.8, g_bot=0.8, g_src=0.8)
+    f = cnn.features(geom, np.array([[1e-6, 1e-4]]), np.array([0.3]))
     np.testing.assert_allclose(f[0, :, 0], [-1.0, 1.0])
     np.testing.assert_allclose(f[0, :, 1], [1.0, 1.0])
     np.testing.assert_allclose(f[0, :, 2], [1.0, 1.0])
+
+
+@pytest.mark.parametrize("m,n", [(3, 5), (6, 4), (1, 7)])
+def test_mean_field_guess_is_the_approximate_preconditioner_applied_to_Y(m, n):
+    """V0 = v_in[i] phi[j] equals the oracle's approximate preconditioner (eq.
+    (block) with Mhat, the paper's order) applied to Y at a1 = a2 = mean(g_dev)."""
+    import oracle
+    rng = np.random.default_rng(m * n)
+    geom = synth.Geometry(m, n, g_top=0.5, g_bot=0.5, g_src=0.5)
+    g = 10 ** rng.uniform(-6, -4, (m, n))
+    v_in = rng.uniform(0, 0.3, m)
+    a = float(np.mean(g))
+    yt = np.zeros((m, n))
+    yt[:, 0] = geom.g_src * v_in
+    zt, zb = oracle.precond_apply_approx(geom, a, a, yt, np.zeros((m, n)))
+    bt, bb = cnn.base_guess(geom, g, v_in)
+    # the literal order divides by a: its rounding sets the tolerance
+    np.testing.assert_allclose(bt, zt, rtol=0, atol=1e-9 * np.abs(zt).max())
+    np.testing.assert_allclose(bb, zb, rtol=0, atol=1e-9 * np.abs(zt).max())

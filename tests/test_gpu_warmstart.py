@@ -1,0 +1,72 @@
+"""The learned warm start: the guess fallback of both solvers, and what the
+trained network (paper_2109_07929_amd/warmstart_512.npy, made by
+`python -m paper_2109_07929_amd.warmstart train`) gains on held-out 512 x 512
+crossbars.  A warm start may only change iteration counts: the voltages match
+the cold solve to the solver's bar."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2109_07929_amd import Batch, Plan, synth, warmstart
+from paper_2109_07929_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_guess_fallback_single_solve():
+    cb = synth.crossbar(40, 30, seed=2)
+    plan = Plan(cb.geom)
+    g = torch.from_numpy(cb.g_dev).cuda()
+    v = torch.from_numpy(cb.v_in).cuda()
+    vt0, vb0, s0, st0 = plan.solve(g, v, B.options())
+    bad = (torch.full_like(vt0, 5.0), torch.full_like(vb0, -5.0))
+    o = B.options(flags=B.MCA_FLAG_GUESS_FALLBACK)
+    vt1, vb1, s1, st1 = plan.solve(g, v, o, guess=bad)
+    assert s1 == B.MCA_OK and st1.start == 0 and st1.newton_iters == st0.newton_iters
+    assert torch.equal(vt1, vt0) and torch.equal(vb1, vb0)
+    vt2, vb2, s2, st2 = plan.solve(g, v, o, guess=(vt0.clone(), vb0.clone()))
+    assert s2 == B.MCA_OK and st2.start == 1 and st2.newton_iters == 0
+
+
+def test_guess_fallback_batched():
+    cbs = synth.mc_batch(4, seed=4, sizes=(24, 40))
+    bt = Batch([c.geom for c in cbs])
+    g = bt.concat([c.g_dev for c in cbs])
+    v = bt.concat([c.v_in for c in cbs])
+    o = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3)
+    vt0, vb0, s0, st0 = bt.solve(g, v, o)
+    assert s0 == B.MCA_OK
+    # crossbars 0, 2 get a useless guess, 1, 3 their solution
+    gt, gb = vt0.clone(), vb0.clone()
+    for b in (0, 2):
+        gt[int(bt.cross[b]):int(bt.cross[b + 1])] = 7.0
+    ow = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3,
+                   flags=B.MCA_FLAG_GUESS_FALLBACK)
+    vt1, vb1, s1, st1 = bt.solve(g, v, ow, guess=(gt, gb))
+    assert s1 == B.MCA_OK
+    assert [s.start for s in st1] == [0, 1, 0, 1]
+    assert [s.newton_iters for s in st1] == [st0[0].newton_iters, 0, st0[2].newton_iters, 0]
+    scale = float(torch.maximum(vt0.abs().max(), vb0.abs().max()))
+    assert float((vt1 - vt0).abs().max()) <= 1e-12 * scale
+
+
+@pytest.mark.skipif(not os.path.exists(warmstart.DEFAULT_PARAMS), reason="no trained network")
+def test_trained_network_gains_on_held_out_crossbars():
+    params = warmstart.load_params()
+    res = warmstart.evaluate(params, count=64, size=512, seed=424242)
+    s = warmstart.summary(res)
+    say(f"  {s}")
+    # both solves stop at ||F|| <= 1e-10 ||Y||: the same residual tolerance
+    assert s["max_relres_warm"] <= 1e-10
+    assert s["max_rel_dv_warm_vs_cold"] <= 1e-6
+    assert s["guess_used_fraction"] >= 0.9
+    assert s["newton_warm"] < s["newton_cold"]
+    assert s["krylov_warm"] < s["krylov_cold"]

@@ -180,3 +180,18 @@ def test_approx_and_jacobi_forms_validation():
         assert B.mca_precond_workspace_bytes(P, B.MCA_PRECOND_APPROX) > 0
     finally:
         B.mca_plan_destroy(P)
+
+
+def test_batch_shares_set_up_of_equal_geometries():
+    """Crossbars with the same geometry share one eigen set-up and one copy of the
+    device eigenbases."""
+    same = B.mca_batch_create([B.geometry(40, 30)] * 3)
+    diff = B.mca_batch_create([B.geometry(40, 30, g_top=0.3 + 0.1 * k) for k in range(3)])
+    one = B.mca_batch_create([B.geometry(40, 30)])
+    try:
+        per_plan = B.mca_batch_device_bytes(diff) - B.mca_batch_device_bytes(same)
+        assert per_plan > 2 * 4 * (40 * 40 + 30 * 30)       # two plans' FP32 + bf16 planes
+        assert B.mca_batch_device_bytes(same) - B.mca_batch_device_bytes(one) < 8192
+    finally:
+        for h in (same, diff, one):
+            B.mca_batch_destroy(h)
