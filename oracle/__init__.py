@@ -68,6 +68,8 @@ def _load():
     lib.orc_precond_apply_approx.restype = None
     lib.orc_jacobi_apply.argtypes = [G, _P, _P, _P, _P, _P]
     lib.orc_jacobi_apply.restype = None
+    lib.orc_sweep_guess.argtypes = [G, _P, _P, _P, _P]
+    lib.orc_sweep_guess.restype = None
     _lib = lib
     return lib
 
@@ -167,6 +169,13 @@ def jacobi_apply(geom, d, r_t, r_b):
     zt, zb = np.zeros((geom.m, geom.n)), np.zeros((geom.m, geom.n))
     _load().orc_jacobi_apply(C.byref(_geom(geom)), _f64(d), _f64(r_t), _f64(r_b), zt, zb)
     return zt, zb
+
+
+def sweep_guess(geom, g_dev, v_in):
+    """(V_t, V_b) of one block Gauss-Seidel sweep on J(0) V = Y."""
+    vt, vb = np.zeros((geom.m, geom.n)), np.zeros((geom.m, geom.n))
+    _load().orc_sweep_guess(C.byref(_geom(geom)), _f64(g_dev), _f64(v_in), vt, vb)
+    return vt, vb
 
 
 def jacobian_solve(geom, d, b_t, b_b, method: str = "band", rel_tol: float = 1e-13):

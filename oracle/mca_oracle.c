@@ -684,3 +684,58 @@ void orc_jacobi_apply(const orc_geom *G, const double *d, const double *rt,
         }
     free(td); free(to); free(bd); free(bo);
 }
+
+/* ------------------------------------------------------------------------ */
+/* One block Gauss-Seidel sweep on the linearisation at V = 0, a cheap start
+ * for Newton's method: J(0) = [[G_t + D, -D], [-D, G_b + D]] with D = g_dev
+ * (the device slope at u = 0 for both device models), right-hand side Y.
+ *   V_t = (G_t + D)^{-1} Y_t              (one tridiagonal solve per row)
+ *   V_b = (G_b + D)^{-1} (D V_t)          (one per column; Y_b = 0)
+ * Written as the Thomas algorithm per wire with the device conductances on
+ * the diagonal.                                                              */
+static void tridiag_solve_var(int len, const double *diag, const double *off,
+                              const double *b, double *x, size_t stride)
+{
+    double *cp = malloc(sizeof(double) * len), *dp = malloc(sizeof(double) * len);
+    cp[0] = (len > 1) ? off[0] / diag[0] : 0.0;
+    dp[0] = b[0] / diag[0];
+    for (int k = 1; k < len; ++k) {
+        double den = diag[k * stride] - off[k - 1] * cp[k - 1];
+        cp[k] = (k + 1 < len) ? off[k] / den : 0.0;
+        dp[k] = (b[k * stride] - off[k - 1] * dp[k - 1]) / den;
+    }
+    x[(size_t)(len - 1) * stride] = dp[len - 1];
+    for (int k = len - 2; k >= 0; --k)
+        x[k * stride] = dp[k] - cp[k] * x[(size_t)(k + 1) * stride];
+    free(cp); free(dp);
+}
+
+void orc_sweep_guess(const orc_geom *G, const double *g_dev, const double *v_in,
+                     double *vt, double *vb)
+{
+    int m = G->m, n = G->n;
+    size_t mn = (size_t)m * n;
+    double *td = malloc(sizeof(double) * n), *to = malloc(sizeof(double) * (n + 1));
+    double *bd = malloc(sizeof(double) * m), *bo = malloc(sizeof(double) * (m + 1));
+    double *dg = malloc(sizeof(double) * mn), *rhs = malloc(sizeof(double) * mn);
+    top_wire(G, td, to);
+    bot_wire(G, bd, bo);
+    /* rows: (G_top + diag(g_dev[i, :])) v = Y_t[i, :] */
+    for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < n; ++j) {
+            size_t q = (size_t)i * n + j;
+            dg[q] = td[j] + g_dev[q];
+            rhs[q] = (j == 0) ? G->g_src * v_in[i] : 0.0;
+        }
+        tridiag_solve_var(n, dg + (size_t)i * n, to, rhs + (size_t)i * n, vt + (size_t)i * n, 1);
+    }
+    /* columns: (G_bot + diag(g_dev[:, j])) v = g_dev[:, j] * V_t[:, j] */
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j) {
+            size_t q = (size_t)i * n + j;
+            dg[q] = bd[i] + g_dev[q];
+            rhs[q] = g_dev[q] * vt[q];
+        }
+    for (int j = 0; j < n; ++j) tridiag_solve_var(m, dg + j, bo, rhs + j, vb + j, (size_t)n);
+    free(td); free(to); free(bd); free(bo); free(dg); free(rhs);
+}

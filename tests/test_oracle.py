@@ -457,6 +457,25 @@ def test_jacobi_matches_dense_diagonal():
                                np.concatenate([rt.ravel(), rb.ravel()]) / diag, rtol=1e-15)
 
 
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 5), (4, 1), (3, 4), (5, 6)])
+def test_sweep_guess_is_one_block_gauss_seidel_step(m, n):
+    """V_t = A11^{-1} Y_t, V_b = A22^{-1}(D V_t) with the diagonal blocks of the
+    dense J(D = g_dev) (the linearisation at V = 0) and numpy's dense solver."""
+    geom = _geom(m, n)
+    rng = np.random.default_rng(m + 7 * n)
+    g = 10 ** rng.uniform(-3, -1, (m, n))       # strong devices: every term matters
+    v_in = rng.uniform(0, 0.3, m)
+    J = oracle.dense_jacobian(geom, g)
+    mn = m * n
+    yt = np.zeros((m, n))
+    yt[:, 0] = geom.g_src * v_in
+    vt = np.linalg.solve(J[:mn, :mn], yt.ravel())
+    vb = np.linalg.solve(J[mn:, mn:], g.ravel() * vt)
+    st, sb = oracle.sweep_guess(geom, g, v_in)
+    np.testing.assert_allclose(st.ravel(), vt, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(sb.ravel(), vb, rtol=1e-12, atol=1e-15)
+
+
 def test_golden_32x32_seed0_unchanged():
     """The stored oracle steady state (tests/golden/make_golden.py) still holds."""
     import json
