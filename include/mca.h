@@ -77,8 +77,13 @@ typedef int32_t mca_status;
 
 #define MCA_FLAG_INITIAL_GUESS 1  /* mca_solve starts from v_t/v_b instead of V = 0       */
 #define MCA_FLAG_TIMING        2  /* mca_solve times its kernel classes with HIP events     */
-#define MCA_FLAG_GUESS_FALLBACK 4 /* with INITIAL_GUESS: a guess whose residual is not below
-                                     that of V = 0 (||F(0)|| = ||Y||) is dropped for V = 0  */
+#define MCA_FLAG_GUESS_FALLBACK 4 /* with a guess: a guess whose residual is not below that
+                                     of V = 0 (||F(0)|| = ||Y||) is dropped for V = 0       */
+#define MCA_FLAG_SWEEP_START   8  /* start from one block Gauss-Seidel sweep on the
+                                     linearisation at V = 0, J(0) V = Y:
+                                     V_t = (G_t + D)^{-1} Y_t, V_b = (G_b + D)^{-1} D V_t,
+                                     D = g_dev (tridiagonal solves along every wire);
+                                     not with INITIAL_GUESS; m, n <= 2048                  */
 
 /* Kernel classes timed under MCA_FLAG_TIMING (mca_stats.kernel_ms / kernel_launches). */
 #define MCA_KCLASS_GEMM      0    /* eigenbasis transforms of the preconditioner          */

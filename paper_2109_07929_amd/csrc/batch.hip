@@ -845,7 +845,10 @@ mca_status batch_options_ok(const mca_options *o)
     if (o->precision != MCA_PREC_FP32 && o->precision != MCA_PREC_BF16X3 &&
         o->precision != MCA_PREC_BF16)
         return MCA_ERR_INVALID_ARG;
-    if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING | MCA_FLAG_GUESS_FALLBACK))
+    if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING | MCA_FLAG_GUESS_FALLBACK |
+                     MCA_FLAG_SWEEP_START))
+        return MCA_ERR_INVALID_ARG;
+    if ((o->flags & MCA_FLAG_INITIAL_GUESS) && (o->flags & MCA_FLAG_SWEEP_START))
         return MCA_ERR_INVALID_ARG;
     return MCA_OK;
 }
@@ -1116,7 +1119,19 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
 
     // initial state and iterate
     hipLaunchKernelGGL(bk_init, dim3(cnt), blk, 0, s, B->d_inst, cnt, v_in, w.S);
-    if (o.flags & MCA_FLAG_INITIAL_GUESS)
+    if (o.flags & MCA_FLAG_SWEEP_START) {
+        for (int b = 0; b < cnt; ++b) {
+            const BInst &in = B->inst[b];
+            if (in.m > kSweepMaxLen || in.n > kSweepMaxLen) return MCA_ERR_INVALID_ARG;
+        }
+        for (int b = 0; b < cnt; ++b) {
+            const BInst &in = B->inst[b];
+            const size_t mn = (size_t)in.m * in.n;
+            double *vt = w.Vc + 2 * in.ox;
+            MCA_BTRY(launch_sweep_guess(in.top, in.bot, in.m, in.n, in.g_src, g_dev + in.ox,
+                                        v_in + in.orow, vt, vt + mn, s));
+        }
+    } else if (o.flags & MCA_FLAG_INITIAL_GUESS)
         hipLaunchKernelGGL(bk_user_io, gridB, blk, 0, s, B->d_inst, B->d_btab, w.S, w.Vc, v_t, v_b,
                            0);
     else
@@ -1125,7 +1140,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
                        v_in, w.Vc, w.F, w.D, w.pa);
     hipLaunchKernelGGL(bk_inst_norms, dim3(cnt), blk, 0, s, B->d_inst, cnt, (const int *)nullptr,
                        w.pa, 0, w.S);
-    if (o.flags & MCA_FLAG_INITIAL_GUESS) {
+    if (o.flags & (MCA_FLAG_INITIAL_GUESS | MCA_FLAG_SWEEP_START)) {
         const int *rjf = &w.S[0].reject;
         hipLaunchKernelGGL(bk_check_guess, dim3(cb), dim3(ct), 0, s, cnt, w.S,
                            (o.flags & MCA_FLAG_GUESS_FALLBACK) ? 1 : 0);

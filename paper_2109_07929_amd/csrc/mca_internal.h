@@ -176,6 +176,13 @@ hipError_t launch_pcr_setup(const Wire &w, double shift, const PcrTables &t, hip
 hipError_t launch_pcr_solve(const PcrTables &t, int lines, bool rows, size_t line_stride,
                             size_t elem_stride, const double *in, const double *in2,
                             double in2_scale, double *out, const int *skip, hipStream_t s);
+// One block Gauss-Seidel sweep on the linearisation at V = 0 (a start for
+// Newton's method): V_t = (G_t + D)^{-1} Y_t, V_b = (G_b + D)^{-1} D V_t with
+// D = g_dev, by per-wire tridiagonal solves (lines of up to kSweepMaxLen).
+constexpr int kSweepMaxLen = 2048;
+hipError_t launch_sweep_guess(const Wire &top, const Wire &bot, int m, int n, double g_src,
+                              const double *g_dev, const double *v_in, double *vt, double *vb,
+                              hipStream_t s);
 // z = r ./ diag(J(D))
 hipError_t launch_jacobi(const mca_plan *P, const double *D, const double *rt, const double *rb,
                          double *zt, double *zb, const int *skip, hipStream_t s);

@@ -80,7 +80,10 @@ mca_status validate_options(const mca_options *o)
     if (o->precision != MCA_PREC_FP64 && o->precond != MCA_PRECOND_PERMODE &&
         o->precond != MCA_PRECOND_NONE)
         return MCA_ERR_INVALID_ARG;
-    if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING | MCA_FLAG_GUESS_FALLBACK))
+    if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING | MCA_FLAG_GUESS_FALLBACK |
+                     MCA_FLAG_SWEEP_START))
+        return MCA_ERR_INVALID_ARG;
+    if ((o->flags & MCA_FLAG_INITIAL_GUESS) && (o->flags & MCA_FLAG_SWEEP_START))
         return MCA_ERR_INVALID_ARG;
     return MCA_OK;
 }
@@ -788,6 +791,9 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     mca_status st = validate_options(&o);
     if (st != MCA_OK) return st;
     if (o.precond == MCA_PRECOND_APPROX && !approx_fits(P)) return MCA_ERR_INVALID_ARG;
+    if ((o.flags & MCA_FLAG_SWEEP_START) &&
+        (P->geom.m > kSweepMaxLen || P->geom.n > kSweepMaxLen))
+        return MCA_ERR_INVALID_ARG;
     if (!plan_ready(P)) return MCA_ERR_WORKSPACE;
     SolveWs w = solve_layout(P, &o, ws);
     if (!ws || ws_bytes < w.bytes) return MCA_ERR_WORKSPACE;
@@ -817,6 +823,9 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     if (o.flags & MCA_FLAG_INITIAL_GUESS) {
         MCA_TRY(hipMemcpyAsync(Vc, v_t, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
         MCA_TRY(hipMemcpyAsync(Vc + mn, v_b, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else if (o.flags & MCA_FLAG_SWEEP_START) {
+        MCA_TRY(launch_sweep_guess(P->top, P->bot, P->geom.m, P->geom.n, P->geom.g_src, g_dev,
+                                   v_in, Vc, Vc + mn, s));
     } else {
         MCA_TRY(launch_fill(Vc, 0.0, len, s));
     }
@@ -826,7 +835,7 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     SolveWs wk = w;
     st = residual_norms(P, g_dev, v_in, Vc, Vc + mn, F, D, wk, s, &tm, &fnorm, &dsum);
     if (st == MCA_ERR_HIP) return st;
-    int from_guess = (o.flags & MCA_FLAG_INITIAL_GUESS) ? 1 : 0;
+    int from_guess = (o.flags & (MCA_FLAG_INITIAL_GUESS | MCA_FLAG_SWEEP_START)) ? 1 : 0;
     if (from_guess && (o.flags & MCA_FLAG_GUESS_FALLBACK) && !(st == MCA_OK && fnorm < ynorm)) {
         // the guess is no better than V = 0, whose residual is ||Y||: start from 0
         MCA_TRY(launch_fill(Vc, 0.0, len, s));

@@ -164,6 +164,107 @@ __global__ __launch_bounds__(TPB) void k_jacobi(int m, int n, Wire top, Wire bot
     }
 }
 
+// Tridiagonal solves whose diagonal varies along every line: (wire + diag(shunt))
+// x = rhs, by PCR with the coefficients (a, b, c) reduced level by level in
+// LDS next to the right-hand side (no shared tables: every line differs).
+// rhs_k = [k == 0] r0_scale r0[line] + shunt_k rhs1_k (either part optional).
+constexpr int kVarMax = 2048;   // elements per workgroup: four LDS arrays of doubles
+constexpr int kVarEpt = kVarMax / TPB;
+
+struct LineSolveArgs {
+    int len, levels, lines, lpw, rows;
+    size_t line_stride, elem_stride;
+    Wire w;
+    const double *shunt, *r0, *rhs1;
+    double r0_scale;
+    double *out;
+};
+
+__global__ __launch_bounds__(TPB) void k_line_solve(LineSolveArgs p)
+{
+    __shared__ double sa[kVarMax], sb[kVarMax], sc[kVarMax], sd[kVarMax];
+    const int len = p.len, lpw = p.lpw, E = len * lpw;
+    const int line0 = blockIdx.x * lpw;
+    const int kst = p.rows ? 1 : lpw;
+    auto coords = [&](int e, int &k, int &l) {
+        if (p.rows) {
+            l = e / len;
+            k = e - l * len;
+        } else {
+            k = e / lpw;
+            l = e - k * lpw;
+        }
+    };
+    for (int e = threadIdx.x; e < E; e += TPB) {
+        int k, l;
+        coords(e, k, l);
+        double a = 0.0, b = 1.0, c = 0.0, d = 0.0;
+        if (line0 + l < p.lines) {
+            const size_t g = (size_t)(line0 + l) * p.line_stride + (size_t)k * p.elem_stride;
+            const double sh = p.shunt[g];
+            b = ((k > 0) ? p.w.g : p.w.end0) + ((k + 1 < len) ? p.w.g : p.w.end1) + sh;
+            a = (k > 0) ? -p.w.g : 0.0;
+            c = (k + 1 < len) ? -p.w.g : 0.0;
+            if (k == 0 && p.r0) d = p.r0_scale * p.r0[line0 + l];
+            if (p.rhs1) d += sh * p.rhs1[g];
+        }
+        sa[e] = a;
+        sb[e] = b;
+        sc[e] = c;
+        sd[e] = d;
+    }
+    __syncthreads();
+    int s = 1;
+    for (int lev = 0; lev < p.levels; ++lev, s <<= 1) {
+        double na[kVarEpt], nb[kVarEpt], nc[kVarEpt], nd[kVarEpt];
+#pragma unroll
+        for (int r = 0; r < kVarEpt; ++r) {
+            const int e = threadIdx.x + r * TPB;
+            if (e < E) {
+                int k, l;
+                coords(e, k, l);
+                double a2 = 0.0, c2 = 0.0, b2 = sb[e], d2 = sd[e];
+                if (k - s >= 0) {
+                    const int q = e - s * kst;
+                    const double al = -sa[e] / sb[q];
+                    a2 = al * sa[q];
+                    b2 += al * sc[q];
+                    d2 += al * sd[q];
+                }
+                if (k + s < len) {
+                    const int q = e + s * kst;
+                    const double ga = -sc[e] / sb[q];
+                    c2 = ga * sc[q];
+                    b2 += ga * sa[q];
+                    d2 += ga * sd[q];
+                }
+                na[r] = a2;
+                nb[r] = b2;
+                nc[r] = c2;
+                nd[r] = d2;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kVarEpt; ++r) {
+            const int e = threadIdx.x + r * TPB;
+            if (e < E) {
+                sa[e] = na[r];
+                sb[e] = nb[r];
+                sc[e] = nc[r];
+                sd[e] = nd[r];
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < E; e += TPB) {
+        int k, l;
+        coords(e, k, l);
+        if (line0 + l < p.lines)
+            p.out[(size_t)(line0 + l) * p.line_stride + (size_t)k * p.elem_stride] = sd[e] / sb[e];
+    }
+}
+
 int pcr_levels(int len)
 {
     int l = 0;
@@ -174,11 +275,34 @@ int pcr_levels(int len)
 int grid_for(size_t count) { return (int)std::max<size_t>(1, std::min<size_t>((count + TPB - 1) / TPB, 1024)); }
 
 // lines per workgroup: as many as fit in LDS, but keep >= ~512 workgroups
-int lines_per_wg(int len, int lines)
+int lines_per_wg(int len, int lines, int cap = kLds)
 {
     int lpw = 1;
-    while (2 * lpw * len <= kLds && 2 * lpw <= std::max(1, lines / 512)) lpw *= 2;
+    while (2 * lpw * len <= cap && 2 * lpw <= std::max(1, lines / 512)) lpw *= 2;
     return lpw;
+}
+
+hipError_t line_solve(const Wire &w, int lines, int len, bool rows, size_t line_stride,
+                      size_t elem_stride, const double *shunt, const double *r0, double r0_scale,
+                      const double *rhs1, double *out, hipStream_t s)
+{
+    if (len < 1 || len > kVarMax || lines < 1) return hipErrorInvalidValue;
+    LineSolveArgs p{};
+    p.len = len;
+    p.levels = pcr_levels(len);
+    p.lines = lines;
+    p.lpw = lines_per_wg(len, lines, kVarMax);
+    p.rows = rows ? 1 : 0;
+    p.line_stride = line_stride;
+    p.elem_stride = elem_stride;
+    p.w = w;
+    p.shunt = shunt;
+    p.r0 = r0;
+    p.rhs1 = rhs1;
+    p.r0_scale = r0_scale;
+    p.out = out;
+    hipLaunchKernelGGL(k_line_solve, dim3((lines + p.lpw - 1) / p.lpw), dim3(TPB), 0, s, p);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -239,6 +363,18 @@ hipError_t launch_pcr_solve(const PcrTables &t, int lines, bool rows, size_t lin
     p.skip = skip;
     hipLaunchKernelGGL(k_pcr_solve, dim3((lines + p.lpw - 1) / p.lpw), dim3(TPB), 0, s, p);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_guess(const Wire &top, const Wire &bot, int m, int n, double g_src,
+                              const double *g_dev, const double *v_in, double *vt, double *vb,
+                              hipStream_t s)
+{
+    // rows: (G_top + diag(g_dev[i, :])) V_t[i, :] = Y_t[i, :], Y_t[i, 0] = g_src v_in[i]
+    hipError_t e = line_solve(top, m, n, true, (size_t)n, 1, g_dev, v_in, g_src, nullptr, vt, s);
+    // columns: (G_bot + diag(g_dev[:, j])) V_b[:, j] = g_dev[:, j] V_t[:, j]
+    if (e == hipSuccess)
+        e = line_solve(bot, n, m, false, 1, (size_t)n, g_dev, nullptr, 0.0, vt, vb, s);
+    return e;
 }
 
 hipError_t launch_jacobi(const mca_plan *P, const double *D, const double *rt, const double *rb,

@@ -70,3 +70,49 @@ def test_trained_network_gains_on_held_out_crossbars():
     assert s["guess_used_fraction"] >= 0.9
     assert s["newton_warm"] < s["newton_cold"]
     assert s["krylov_warm"] < s["krylov_cold"]
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (40, 70), (300, 129)])
+def test_sweep_start_single(m, n):
+    """MCA_FLAG_SWEEP_START: the residual of the starting point equals that of the
+    oracle's block Gauss-Seidel sweep, and the solve reaches the oracle's state."""
+    cb = synth.crossbar(m, n, seed=m + n)
+    plan = Plan(cb.geom)
+    g = torch.from_numpy(cb.g_dev).cuda()
+    v = torch.from_numpy(cb.v_in).cuda()
+    vt, vb, s, st = plan.solve(g, v, B.options(flags=B.MCA_FLAG_SWEEP_START))
+    assert s == B.MCA_OK and st.start == 1
+    gt, gb = oracle.sweep_guess(cb.geom, cb.g_dev, cb.v_in)
+    ft, fb, _ = oracle.residual(cb.geom, cb.g_dev, cb.v_in, gt, gb)
+    r0 = np.sqrt((ft ** 2).sum() + (fb ** 2).sum()) / oracle.source_norm(cb.geom, cb.v_in)
+    say(f"  {m}x{n}: start residual gpu {st.residual_history[0]:.6e} oracle {r0:.6e}, "
+        f"newton {st.newton_iters}")
+    assert abs(st.residual_history[0] - r0) <= 1e-6 * r0 + 1e-15
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="band" if m * n < 5000 else "cg")
+    scale = max(np.abs(rt).max(), np.abs(rb).max())
+    err = max(np.abs(vt.cpu().numpy() - rt).max(), np.abs(vb.cpu().numpy() - rb).max()) / scale
+    assert err <= 1e-8
+    with pytest.raises(B.MCAError):
+        plan.solve(g, v, B.options(flags=B.MCA_FLAG_SWEEP_START), guess=(vt, vb))
+
+
+def test_sweep_start_batched_saves_a_newton_step():
+    cbs = synth.mc_batch(6, seed=9, sizes=(64, 128, 256))
+    bt = Batch([c.geom for c in cbs])
+    g = bt.concat([c.g_dev for c in cbs])
+    v = bt.concat([c.v_in for c in cbs])
+    o = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3)
+    _, _, s0, st0 = bt.solve(g, v, o)
+    ow = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3,
+                   flags=B.MCA_FLAG_SWEEP_START | B.MCA_FLAG_GUESS_FALLBACK)
+    vt, vb, s1, st1 = bt.solve(g, v, ow)
+    assert s0 == B.MCA_OK and s1 == B.MCA_OK
+    for b, c in enumerate(cbs):
+        gt, gb = oracle.sweep_guess(c.geom, c.g_dev, c.v_in)
+        ft, fb, _ = oracle.residual(c.geom, c.g_dev, c.v_in, gt, gb)
+        r0 = np.sqrt((ft ** 2).sum() + (fb ** 2).sum()) / oracle.source_norm(c.geom, c.v_in)
+        assert st1[b].start == 1
+        assert abs(st1[b].residual_history[0] - r0) <= 1e-6 * r0
+        assert st1[b].rel_residual <= 1e-10
+    say(f"  newton cold {[s.newton_iters for s in st0]} sweep {[s.newton_iters for s in st1]}")
+    assert sum(s.newton_iters for s in st1) < sum(s.newton_iters for s in st0)
