@@ -52,6 +52,10 @@ def parse():
                    help="batched solve of this many size x size crossbars instead")
     p.add_argument("--no-loop", action="store_true",
                    help="with --mc / --batch: skip the per-crossbar loop comparison")
+    p.add_argument("--no-compare", action="store_true",
+                   help="skip the batched + warm-started + mixed-precision comparison")
+    p.add_argument("--compare-batch", type=int, default=8,
+                   help="crossbars per batch of the comparison forms")
     p.add_argument("--copy-calib", action="store_true",
                    help="after the timed solves, copy a 256 MiB float64 array device-to-device "
                         "three times: a kernel of known traffic that calibrates the "
@@ -193,6 +197,73 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def compare_forms(args, dev):
+    """The metric's other side at the same size and tolerance: batches of
+    args.compare_batch crossbars (seeds seed .. seed + count - 1) solved by
+    mca_solve_batched with the split-BF16 per-mode preconditioner, from V = 0,
+    from the sweep start, and from the warm-start network's guess (prediction
+    time included), each with the guess fallback."""
+    import torch
+
+    from paper_2109_07929_amd import Batch, synth, warmstart
+    from paper_2109_07929_amd import binding as B
+
+    count, m = args.compare_batch, args.size
+    cbs = [synth.crossbar(m, m, seed=args.seed + i) for i in range(count)]
+    bt = Batch([c.geom for c in cbs], device=dev)
+    g = bt.concat([c.g_dev for c in cbs])
+    v = bt.concat([c.v_in for c in cbs])
+    vt = torch.zeros(bt.total, dtype=torch.float64, device=dev)
+    vb = torch.zeros_like(vt)
+    base = dict(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3)
+    ws = bt.workspace(B.options(**base))
+    stream = torch.cuda.current_stream()
+    rows = int(bt.rows[-1])
+    params = None
+    if os.path.exists(warmstart.DEFAULT_PARAMS):
+        params = warmstart.load_params(device=dev)
+        cws = torch.empty(B.mca_cnn_workspace_bytes(count, m, m), dtype=torch.uint8, device=dev)
+        g3, v2 = g.view(count, m, m), v.view(count, m)
+        pt = torch.empty((count, m, m), dtype=torch.float64, device=dev)
+        pb = torch.empty_like(pt)
+
+    def run(form):
+        if form == "cnn":
+            B.mca_cnn_predict(params, [c.geom for c in cbs], g3, v2, pt, pb, cws, stream)
+            vt.copy_(pt.view(-1))
+            vb.copy_(pb.view(-1))
+            flags = B.MCA_FLAG_INITIAL_GUESS | B.MCA_FLAG_GUESS_FALLBACK
+        else:
+            flags = B.MCA_FLAG_SWEEP_START | B.MCA_FLAG_GUESS_FALLBACK if form == "sweep" else 0
+        o = B.options(flags=flags, **base)
+        return B.mca_solve_batched(bt.handle, count, bt.total, rows, g, v, vt, vb, o, ws,
+                                   stream, check=False)
+
+    out = {"batch": count, "precision": "bf16x3 (per-mode)", "forms": {}}
+    for form in ("zero", "sweep", "cnn"):
+        if form == "cnn" and params is None:
+            continue
+        for _ in range(max(1, args.warmup)):
+            run(form)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            status, stats = run(form)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        out["forms"][form] = {
+            "solves_per_s": round(count * 1e3 / ms, 2), "ms_per_batch": round(ms, 3),
+            "status": B.status_string(status),
+            "newton_iters": sum(s.newton_iters for s in stats) / count,
+            "krylov_iters": sum(s.krylov_iters for s in stats) / count,
+            "guess_used": sum(s.start for s in stats) / count,
+            "max_rel_residual": max(s.rel_residual for s in stats)}
+        print(f"# {form}: {ms:.2f} ms per batch of {count}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -320,6 +391,12 @@ def main():
         "roofline": roofline,
         "kernel_breakdown": breakdown,
     }
+    if not args.no_compare:
+        cmp = compare_forms(args, dev)
+        best = max(f["solves_per_s"] for f in cmp["forms"].values())
+        cmp["best_solves_per_s"] = best
+        cmp["speedup_vs_plain_fp64"] = round(best / value, 3)
+        out["batched_warm_mixed"] = cmp
     if args.copy_calib:
         src = torch.rand(32 << 20, dtype=torch.float64, device=dev)   # 256 MiB
         dst = torch.empty_like(src)

@@ -85,63 +85,118 @@ struct PcrSolveArgs {
     const int *skip;
 };
 
+// EPT elements per thread (E = len * lpw <= EPT * TPB); LDS sized to E at
+// launch.  Each thread's (k, line) pairs are fixed for the whole solve.  With
+// MAXLEV > 0 every level's multipliers of the thread's elements are loaded into
+// registers before the first level (one memory latency instead of one per
+// level); otherwise the next level's are loaded while the current one runs.
+template <int EPT, int MAXLEV>
 __global__ __launch_bounds__(TPB) void k_pcr_solve(PcrSolveArgs p)
 {
     if (p.skip && *p.skip) return;
-    __shared__ double d[kLds];
+    extern __shared__ double d[];
     const int len = p.len, lpw = p.lpw, E = len * lpw;
     const int line0 = blockIdx.x * lpw;
     const int kst = p.rows ? 1 : lpw;      // LDS distance between elements k and k + 1
-    auto coords = [&](int e, int &k, int &l) {
-        if (p.rows) {
-            l = e / len;
-            k = e - l * len;
-        } else {
-            k = e / lpw;
-            l = e - k * lpw;
+    int kk[EPT];
+    bool valid[EPT];
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+        const int e = threadIdx.x + r * TPB;
+        int k = 0, l = 0;
+        if (e < E) {
+            if (p.rows) {
+                l = e / len;
+                k = e - l * len;
+            } else {
+                k = e / lpw;
+                l = e - k * lpw;
+            }
         }
-    };
-    for (int e = threadIdx.x; e < E; e += TPB) {
-        int k, l;
-        coords(e, k, l);
+        kk[r] = k;
+        valid[r] = e < E && line0 + l < p.lines;
         double v = 0.0;
-        if (line0 + l < p.lines) {
+        if (valid[r]) {
             const size_t g = (size_t)(line0 + l) * p.line_stride + (size_t)k * p.elem_stride;
             v = p.in[g];
             if (p.in2) v += p.in2_scale * p.in2[g];
         }
-        d[e] = v;
+        if (e < E) d[e] = v;
+    }
+    constexpr int NL = MAXLEV > 0 ? MAXLEV : 1;
+    double al[NL][EPT], ga[NL][EPT];
+    if constexpr (MAXLEV > 0) {
+#pragma unroll
+        for (int lev = 0; lev < MAXLEV; ++lev)
+#pragma unroll
+            for (int r = 0; r < EPT; ++r) {
+                const bool on = lev < p.levels;
+                al[lev][r] = on ? p.alpha[(size_t)lev * len + kk[r]] : 0.0;
+                ga[lev][r] = on ? p.gamma[(size_t)lev * len + kk[r]] : 0.0;
+            }
+    } else {
+#pragma unroll
+        for (int r = 0; r < EPT; ++r) {
+            al[0][r] = (p.levels > 0) ? p.alpha[kk[r]] : 0.0;
+            ga[0][r] = (p.levels > 0) ? p.gamma[kk[r]] : 0.0;
+        }
     }
     __syncthreads();
-    int s = 1;
-    for (int lev = 0; lev < p.levels; ++lev, s <<= 1) {
-        const double *al = p.alpha + (size_t)lev * len, *ga = p.gamma + (size_t)lev * len;
-        double nd[kEpt];
+    auto level = [&](int lev, int s, const double *a, const double *g) {
+        double nd[EPT];
 #pragma unroll
-        for (int r = 0; r < kEpt; ++r) {
+        for (int r = 0; r < EPT; ++r) {
             const int e = threadIdx.x + r * TPB;
             if (e < E) {
-                int k, l;
-                coords(e, k, l);
+                const int k = kk[r];
                 double v = d[e];
-                if (k - s >= 0) v += al[k] * d[e - s * kst];
-                if (k + s < len) v += ga[k] * d[e + s * kst];
+                if (k - s >= 0) v += a[r] * d[e - s * kst];
+                if (k + s < len) v += g[r] * d[e + s * kst];
                 nd[r] = v;
+            }
+        }
+        if constexpr (MAXLEV == 0) {
+            if (lev + 1 < p.levels) {
+                const double *an = p.alpha + (size_t)(lev + 1) * len;
+                const double *gn = p.gamma + (size_t)(lev + 1) * len;
+#pragma unroll
+                for (int r = 0; r < EPT; ++r) {
+                    al[0][r] = an[kk[r]];
+                    ga[0][r] = gn[kk[r]];
+                }
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kEpt; ++r) {
+        for (int r = 0; r < EPT; ++r) {
             const int e = threadIdx.x + r * TPB;
             if (e < E) d[e] = nd[r];
         }
         __syncthreads();
+    };
+    if constexpr (MAXLEV > 0) {
+#pragma unroll
+        for (int lev = 0; lev < MAXLEV; ++lev)
+            if (lev < p.levels) level(lev, 1 << lev, al[lev], ga[lev]);
+    } else {
+        for (int lev = 0; lev < p.levels; ++lev) {
+            double a0[EPT], g0[EPT];
+#pragma unroll
+            for (int r = 0; r < EPT; ++r) {
+                a0[r] = al[0][r];
+                g0[r] = ga[0][r];
+            }
+            level(lev, 1 << lev, a0, g0);
+        }
     }
-    for (int e = threadIdx.x; e < E; e += TPB) {
-        int k, l;
-        coords(e, k, l);
-        if (line0 + l < p.lines)
-            p.out[(size_t)(line0 + l) * p.line_stride + (size_t)k * p.elem_stride] = d[e] * p.invb[k];
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+        const int e = threadIdx.x + r * TPB;
+        if (valid[r]) {
+            const int l = p.rows ? e / len : e - kk[r] * lpw;
+            p.out[(size_t)(line0 + l) * p.line_stride + (size_t)kk[r] * p.elem_stride] =
+                d[e] * p.invb[kk[r]];
+        }
     }
 }
 
@@ -275,6 +330,8 @@ int pcr_levels(int len)
 int grid_for(size_t count) { return (int)std::max<size_t>(1, std::min<size_t>((count + TPB - 1) / TPB, 1024)); }
 
 // lines per workgroup: as many as fit in LDS, but keep >= ~512 workgroups
+// lines per workgroup: as many as fit in `cap` elements while keeping about
+// 512 workgroups or more (measured best at 1024 x 1024)
 int lines_per_wg(int len, int lines, int cap = kLds)
 {
     int lpw = 1;
@@ -361,7 +418,13 @@ hipError_t launch_pcr_solve(const PcrTables &t, int lines, bool rows, size_t lin
     p.in2_scale = in2_scale;
     p.out = out;
     p.skip = skip;
-    hipLaunchKernelGGL(k_pcr_solve, dim3((lines + p.lpw - 1) / p.lpw), dim3(TPB), 0, s, p);
+    const size_t lds = (size_t)t.len * p.lpw * sizeof(double);
+    const dim3 grid((lines + p.lpw - 1) / p.lpw);
+    // (loading every level's multipliers up front, MAXLEV > 0, measured slower)
+    if (t.len * p.lpw <= 8 * TPB)
+        hipLaunchKernelGGL((k_pcr_solve<8, 0>), grid, dim3(TPB), lds, s, p);
+    else
+        hipLaunchKernelGGL((k_pcr_solve<kEpt, 0>), grid, dim3(TPB), lds, s, p);
     return hipGetLastError();
 }
 
