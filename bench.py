@@ -64,21 +64,25 @@ def parse():
 
 
 def gemm_traffic():
-    """HBM bytes of one FP64 transform launch at 1024^3, from the committed rocprofv3
-    counter summary, or None when the GEMM source changed since it was taken."""
+    """HBM bytes of one preconditioner application's FP64 transforms at 1024^2,
+    from the committed rocprofv3 counter summary, or None when the kernels
+    changed since it was taken."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "solve_fp64_1024x1024.md")
-    src = os.path.join(ROOT, "paper_2109_07929_amd", "csrc", "gemm.hip")
+    h = hashlib.sha256()
     try:
         text = open(prof).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        for f in ("gemm.hip", "kernels.hip"):
+            h.update(open(os.path.join(ROOT, "paper_2109_07929_amd", "csrc", f), "rb").read())
     except OSError:
         return None
+    digest = h.hexdigest()
     vals = dict(l.split(": ", 1) for l in text.splitlines()
-                if l.startswith(("gemm_traffic_bytes_per_launch:", "gemm_source_sha256:")))
-    if vals.get("gemm_source_sha256", "").strip() != digest:
+                if l.startswith(("transform_traffic_bytes_per_application:",
+                                 "transform_source_sha256:")))
+    if vals.get("transform_source_sha256", "").strip() != digest:
         return None
-    return int(vals["gemm_traffic_bytes_per_launch"])
+    return int(vals["transform_traffic_bytes_per_application"])
 
 
 def cpu_baseline(cb):
@@ -346,18 +350,33 @@ def main():
                     "bytes_per_launch": bytes_per_launch}
     elif not args.no_timing and klaunch[B.MCA_KCLASS_GEMM] > 0 and prec == B.MCA_PREC_FP64 and \
             form in (B.MCA_PRECOND_LITERAL, B.MCA_PRECOND_PERMODE):
-        flops_per_launch = 2.0 * m * n * m   # 2 M N K with M = N = K = size
+        # unit: one preconditioner application = all its FP64 transform launches.
+        # Literal form: Q_m side 2 n m^2 flops each way, Q_n side 2 m n^2 each way; with
+        # a persymmetric G_bot (equal bottom terminations, m even) the Q_m side is two
+        # half-size products (n m^2 each way) plus the unfold pass; the per-mode form
+        # transforms both layers (twice the literal flops).
+        g = cb.geom
+        persym = (form == B.MCA_PRECOND_LITERAL and m % 2 == 0 and g.g_bot_end0 == g.g_bot_end1)
+        qm = (1.0 if persym else 2.0) * n * m * m
+        flops_app = 2 * qm + 2 * (2.0 * m * n * n)
+        launches_app = 5 if persym else 4
         if form == B.MCA_PRECOND_PERMODE:
-            flops_per_launch *= 2.0                            # two layers per launch
-        avg_ms = kms[B.MCA_KCLASS_GEMM] / klaunch[B.MCA_KCLASS_GEMM]
-        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        roofline = {"bound": "mfma", "kernel": "k_gemm_tn_f64 (eigenbasis transform)",
+            flops_app *= 2.0
+        napps = klaunch[B.MCA_KCLASS_GEMM] / launches_app
+        t_app_ms = kms[B.MCA_KCLASS_GEMM] / napps
+        achieved = flops_app / (t_app_ms * 1e-3) / 1e12
+        traffic = gemm_traffic() if (m == 1024 and persym) else None
+        roofline = {"bound": "mfma",
+                    "kernel": "FP64 eigenbasis transforms of one preconditioner application "
+                              "(k_gemm_tn_f64 launches" + (" + k_unfold)" if persym else ")"),
                     "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
-                    "traffic": gemm_traffic() if (m == 1024 and form == B.MCA_PRECOND_LITERAL) else None,
-                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
-                    "avg_launch_us": round(avg_ms * 1e3, 2),
-                    "flops_per_launch": flops_per_launch}
+                    "traffic": traffic,
+                    "traffic_unit": "HBM bytes per application (rocprofv3 FETCH_SIZE x2 + "
+                                    "WRITE_SIZE summed over its launches)",
+                    "avg_application_us": round(t_app_ms * 1e3, 2),
+                    "launches_per_application": launches_app,
+                    "flops_per_application": flops_app}
     breakdown = {}
     if not args.no_timing:
         names = ["gemm", "jacobian", "ortho", "residual"]

@@ -66,6 +66,17 @@ struct Stage {
 template <int NB, int EPI, int BK, int WAVES, bool UPFRONT>
 __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
 {
+    // a pair launch: the second half of the grid computes the second product
+    int bid = blockIdx.x, nwg = gridDim.x;
+    if (NB == 1 && a.pair) {
+        nwg >>= 1;
+        if (bid >= nwg) {
+            bid -= nwg;
+            a.L0 = a.L1;
+            a.R = a.R1;
+            a.O0 = a.O1;
+        }
+    }
     constexpr int NT = 64 * WAVES;
     constexpr int RP = NT / 16;          // slice rows staged per pass
     constexpr int H = BK / RP;           // passes per slice
@@ -79,12 +90,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
     const int M = a.M, N = a.N, K = a.K;
     const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
     int tm, tn;
-    tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    tile_of(bid, nwg, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave / (BN / WCOLS)) * 32, wn = (wave % (BN / WCOLS)) * WCOLS;
-    const double *Lb[2] = {a.L0, a.L1};
+    const double *Lb[2] = {a.L0, NB > 1 ? a.L1 : a.L0};
 
     // Interior tiles with 16-byte aligned rows (a.vec) use unconditional
     // 16-byte loads; edge tiles clamp every address into the array and zero
@@ -237,7 +248,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
                 const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
                 const int col = n0 + wn + j * 16 + (lane & 15);
                 if (row >= M || col >= N) continue;
-                const size_t o = (size_t)row * N + col;
+                const size_t ldo = a.ldo ? (size_t)a.ldo : (size_t)N;
+                const size_t o = (size_t)row * ldo + col;
                 if constexpr (EPI == EPI_STORE) {
 #pragma unroll
                     for (int b = 0; b < NB; ++b) (b == 0 ? a.O0 : a.O1)[o] = acc[b][i][j][r];
@@ -286,9 +298,14 @@ hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
     GemmArgs a = in;
     auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
     a.vec = (a.M % 2 == 0) && (a.N % 2 == 0) && al16(a.L0) && al16(a.R) &&
-            (a.L1 == nullptr || al16(a.L1));
-    const int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
-    const bool dual = a.L1 != nullptr;
+            (a.L1 == nullptr || al16(a.L1)) && (!a.pair || al16(a.R1)) &&
+            (a.ldo == 0 || a.ldo % 2 == 0);
+    int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+    const bool dual = a.L1 != nullptr && !a.pair;
+    if (a.pair) {
+        if (!a.L1 || !a.R1 || !a.O1 || epi != EPI_STORE) return hipErrorInvalidValue;
+        tiles *= 2;
+    }
     if (epi == EPI_PERMODE && !dual) return hipErrorInvalidValue;
     if (dual) {
         if (epi == EPI_PERMODE) launch_variant<2, EPI_PERMODE>(a, tiles, s);
@@ -297,6 +314,7 @@ hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
     } else {
         if (epi == EPI_DIV_MU) launch_variant<1, EPI_DIV_MU>(a, tiles, s);
         else if (epi == EPI_STORE) launch_variant<1, EPI_STORE>(a, tiles, s);
+
         else return hipErrorInvalidValue;
     }
     return hipGetLastError();

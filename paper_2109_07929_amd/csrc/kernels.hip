@@ -130,6 +130,46 @@ __global__ __launch_bounds__(TPB) void k_precond_pre(
     }
 }
 
+// w = r_b + ((G_b + a2 I) r_t) / a1 at rows i and m-1-i, folded: P = sum, Q = difference
+__global__ __launch_bounds__(TPB) void k_precond_pre_fold(
+    int m, int n, Wire bot, double inv_a1, double a2,
+    const double *__restrict__ rt, const double *__restrict__ rb, double *__restrict__ f,
+    const int *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    const int h = m / 2;
+    const size_t hn = (size_t)h * n;
+    auto w_at = [&](int i, int j) {
+        const size_t k = (size_t)i * n + j;
+        const double r = rt[k];
+        const double s = wire_apply(bot, i, r, (i > 0) ? rt[k - n] : 0.0,
+                                    (i + 1 < m) ? rt[k + n] : 0.0);
+        return rb[k] + (s + a2 * r) * inv_a1;
+    };
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < hn; k += (size_t)gridDim.x * TPB) {
+        const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
+        const double w0 = w_at(i, j), w1 = w_at(m - 1 - i, j);
+        f[k] = w0 + w1;
+        f[hn + k] = w0 - w1;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_unfold(const double *__restrict__ ys,
+                                                const double *__restrict__ ya, int n, int h,
+                                                double *__restrict__ xt, const int *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    const size_t nh = (size_t)n * h;
+    const int m = 2 * h;
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < nh; k += (size_t)gridDim.x * TPB) {
+        const size_t j = k / h;
+        const int i = (int)(k - j * h);
+        const double s = ys[k], a = ya[k];
+        xt[j * m + i] = s + a;
+        xt[j * m + (m - 1 - i)] = s - a;
+    }
+}
+
 __global__ __launch_bounds__(TPB) void k_precond_post(
     int m, int n, Wire top, double a1, double inv_a1,
     const double *__restrict__ zt, const double *__restrict__ rt, double *__restrict__ zb,
@@ -385,6 +425,23 @@ hipError_t launch_precond_pre(const mca_plan *P, double a1, double a2, const dou
     const int m = P->geom.m, n = P->geom.n;
     hipLaunchKernelGGL(k_precond_pre, dim3(elementwise_blocks((size_t)m * n)), dim3(TPB), 0, s,
                        m, n, P->bot, 1.0 / a1, a2, rt, rb, w, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_pre_fold(const mca_plan *P, double a1, double a2, const double *rt,
+                                   const double *rb, double *f, hipStream_t s, const int *skip)
+{
+    const int m = P->geom.m, n = P->geom.n;
+    hipLaunchKernelGGL(k_precond_pre_fold, dim3(elementwise_blocks((size_t)(m / 2) * n)), dim3(TPB),
+                       0, s, m, n, P->bot, 1.0 / a1, a2, rt, rb, f, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_unfold(const double *ys, const double *ya, int n, int h, double *xt,
+                         hipStream_t s, const int *skip)
+{
+    hipLaunchKernelGGL(k_unfold, dim3(elementwise_blocks((size_t)n * h)), dim3(TPB), 0, s, ys, ya,
+                       n, h, xt, skip);
     return hipGetLastError();
 }
 

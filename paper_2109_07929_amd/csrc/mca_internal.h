@@ -28,6 +28,12 @@ struct DevPlan {
     // reduced-precision copies: FP32, and bfloat16 hi / lo planes (v = hi + lo)
     const float *Qm32, *QmT32, *Qn32, *QnT32;
     const void *QmH, *QmL, *QmTH, *QmTL, *QnH, *QnL, *QnTH, *QnTL;
+    // persymmetric G_bot (equal end terminations, m even): its eigenvectors are
+    // [u; J u]/sqrt2 (symmetric) or [u; -J u]/sqrt2 (antisymmetric), u of length
+    // h = m/2.  Us, Ua (h x h) hold u/sqrt2 column-wise, UsT, UaT their
+    // transposes; lbp = (lambda_sym, lambda_anti), the mode order of the folded
+    // transforms.  Null when G_bot is not persymmetric.
+    const double *Us, *UsT, *Ua, *UaT, *lbp;
 };
 
 }  // namespace mca
@@ -37,6 +43,8 @@ struct mca_plan {
     mca::Wire top, bot;
     std::vector<double> lb, lt;      // host eigenvalues
     std::vector<double> Qm, Qn;      // host eigenvectors (row-major, columns are vectors)
+    bool persym = false;             // G_bot persymmetric with m even: folded transforms
+    std::vector<double> Us, Ua, ls, la;   // halves (h x h, u / sqrt2) and their eigenvalues
     size_t dev_bytes = 0;
     void *dev_buf = nullptr;         // caller-owned, set by mca_plan_upload
     mca::DevPlan dev{};
@@ -77,6 +85,16 @@ hipError_t launch_jacobian(const mca_plan *P, const double *d, const double *xt,
 hipError_t launch_precond_pre(const mca_plan *P, double a1, double a2, const double *rt,
                               const double *rb, double *w, hipStream_t s,
                               const int *skip = nullptr);
+// Folded first step for a persymmetric G_bot (m = 2h): with w as above,
+// P[i] = w[i] + w[m-1-i] into f[0, h*n), Q[i] = w[i] - w[m-1-i] into f[h*n, m*n).
+hipError_t launch_precond_pre_fold(const mca_plan *P, double a1, double a2, const double *rt,
+                                   const double *rb, double *f, hipStream_t s,
+                                   const int *skip = nullptr);
+// Unfold the inverse Q_m transform of a persymmetric G_bot: from the symmetric and
+// antisymmetric halves Ys, Ya (n x h each), X^T[j][i] = Ys + Ya and
+// X^T[j][m-1-i] = Ys - Ya (X^T n x m, m = 2h).
+hipError_t launch_unfold(const double *ys, const double *ya, int n, int h, double *xt,
+                         hipStream_t s, const int *skip = nullptr);
 // z_b = ((G_t + a1 I) z_t - r_t) / a1          (last step of the literal form)
 hipError_t launch_precond_post(const mca_plan *P, double a1, const double *zt,
                                const double *rt, double *zb, hipStream_t s,
@@ -89,6 +107,8 @@ enum GemmEpi { EPI_STORE = 0, EPI_DIV_MU = 1, EPI_PERMODE = 2 };
 //   L: K x M row-major (ld = M), R: K x N row-major (ld = N), O: M x N row-major.
 //   EPI_DIV_MU : O[p][q] = acc / (lb[p] lt[q] / a1 + lb[p] + (a2/a1) lt[q])
 //   EPI_PERMODE: (O0, O1) = 2x2 per-mode solve of (acc0, acc1)      (needs 2 batches)
+// O's row stride is ldo (0: N).  pair: two independent single-batch products in
+// one launch, the second with L1, R1, O1 (the same sizes and epilogue).
 struct GemmArgs {
     int M, N, K;
     const double *L0, *L1;     // L1 may be null (single batch)
@@ -98,6 +118,9 @@ struct GemmArgs {
     double a1, a2;
     int vec;                   // set by the launcher: rows are 16-byte aligned
     const int *skip;           // optional: return at once when *skip != 0
+    int ldo;                   // output row stride (0: N)
+    int pair;                  // second independent product (L1, R1, O1) in the same launch
+    const double *R1;
 };
 hipError_t launch_gemm_f64(const GemmArgs &a, int epi, hipStream_t s);
 extern int gemm_variant;   // kernel variant (tuning only; 0 = default)

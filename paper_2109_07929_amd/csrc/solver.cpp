@@ -112,6 +112,7 @@ struct PlanLayout {
     double *Qm, *QmT, *Qn, *QnT, *lb, *lt;
     float *Qm32, *QmT32, *Qn32, *QnT32;
     uint16_t *QmH, *QmL, *QmTH, *QmTL, *QnH, *QnL, *QnTH, *QnTL;   // bfloat16 planes
+    double *Us, *UsT, *Ua, *UaT, *lbp;                               // persymmetric halves
     size_t bytes;
 };
 
@@ -138,6 +139,15 @@ PlanLayout plan_layout(const mca_plan *P, void *base)
     L.QnL = c.take<uint16_t>(n * n);
     L.QnTH = c.take<uint16_t>(n * n);
     L.QnTL = c.take<uint16_t>(n * n);
+    L.Us = L.UsT = L.Ua = L.UaT = L.lbp = nullptr;
+    if (P->persym) {
+        const size_t h = m / 2;
+        L.Us = c.take<double>(h * h);
+        L.UsT = c.take<double>(h * h);
+        L.Ua = c.take<double>(h * h);
+        L.UaT = c.take<double>(h * h);
+        L.lbp = c.take<double>(m);
+    }
     L.bytes = c.size();
     return L;
 }
@@ -156,6 +166,12 @@ PrecondWs precond_layout(const mca_plan *P, Carver &c, int form, int precision =
     const size_t mn = (size_t)P->geom.m * P->geom.n;
     PrecondWs w{};
     if (form == MCA_PRECOND_NONE || form == MCA_PRECOND_JACOBI) return w;
+    if (form == MCA_PRECOND_LITERAL && precision == MCA_PREC_FP64 && P->persym) {
+        w.b0t = c.take<double>(mn);
+        w.b1t = c.take<double>(mn);
+        w.b0b = c.take<double>(mn);   // the symmetric half of the inverse Q_m transform
+        return w;
+    }
     if (form == MCA_PRECOND_APPROX) {
         w.g1 = pcr_carve(c.take<double>(pcr_table_doubles(P->geom.n)), P->geom.n);
         w.g2 = pcr_carve(c.take<double>(pcr_table_doubles(P->geom.m)), P->geom.m);
@@ -399,6 +415,40 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
     g.a1 = a1;
     g.a2 = a2;
     g.skip = skip;
+    if (form == MCA_PRECOND_LITERAL && P->persym) {
+        // G_bot persymmetric (m = 2h): every Q_m transform splits into a symmetric and
+        // an antisymmetric half of h modes each, half the work of the full transform.
+        const int h = m / 2;
+        const size_t hn = (size_t)h * n;
+        // P = w_top + J w_bot, Q = w_top - J w_bot with w = r_b + (G_b + a2 I) r_t / a1
+        MCA_TRY(launch_precond_pre_fold(P, a1, a2, rt, rb, w.b0t, s, skip));
+        MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
+        // W_hat^T = [P^T U_s | Q^T U_a]   (n x m, modes: symmetric, antisymmetric; one launch)
+        g.M = n; g.N = h; g.K = h; g.ldo = m; g.pair = 1;
+        g.L0 = w.b0t; g.R = d.Us; g.O0 = w.b1t;
+        g.L1 = w.b0t + hn; g.R1 = d.Ua; g.O1 = w.b1t + h;
+        MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
+        g.pair = 0; g.ldo = 0; g.L1 = nullptr; g.R1 = nullptr; g.O1 = nullptr;
+        // X_hat = (W_hat Q_n) ./ mu        (m x n, rows in that mode order)
+        g.M = m; g.N = n; g.K = n; g.lb = d.lbp;
+        g.L0 = w.b1t; g.R = d.Qn; g.O0 = w.b0t;
+        MCA_TRY(launch_gemm_f64(g, EPI_DIV_MU, s));
+        g.lb = d.lb;
+        // Y_s = X_hat_s^T U_s^T, Y_a = X_hat_a^T U_a^T   (n x h each; one launch)
+        g.M = n; g.N = h; g.K = h; g.pair = 1;
+        g.L0 = w.b0t; g.R = d.UsT; g.O0 = w.b0b;
+        g.L1 = w.b0t + hn; g.R1 = d.UaT; g.O1 = w.b0b + hn;
+        MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
+        g.pair = 0; g.L1 = nullptr; g.R1 = nullptr; g.O1 = nullptr;
+        // X^T = [Y_s + Y_a | mirrored (Y_s - Y_a)]        (n x m)
+        MCA_TRY(launch_unfold(w.b0b, w.b0b + hn, n, h, w.b1t, s, skip));
+        // z_t = X Q_n^T                                   (m x n)
+        g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.R = d.QnT; g.O0 = zt;
+        MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
+        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 5, slot));
+        MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s, skip));
+        return MCA_OK;
+    }
     if (form == MCA_PRECOND_LITERAL) {
         // w = r_b + (G_b + a2 I) r_t / a1
         MCA_TRY(launch_precond_pre(P, a1, a2, rt, rb, w.b0t, s, skip));
@@ -644,6 +694,24 @@ mca_status mca_plan_create(const mca_geometry *geom, mca_plan **out)
     P->Qm.resize((size_t)m * m);
     wire_tridiag(P->bot, diag, off);
     tridiag_eigen(m, diag.data(), off.data(), P->lb.data(), P->Qm.data());
+    // persymmetric G_bot: the symmetric / antisymmetric eigenvectors [u; +-J u]/sqrt2
+    // come from two h x h problems, the last diagonal entry shifted by -+ the
+    // coupling of the two middle nodes
+    P->persym = (m >= 2) && (m % 2 == 0) && (geom->g_bot_end0 == geom->g_bot_end1);
+    if (P->persym) {
+        const int h = m / 2;
+        std::vector<double> dh(diag.begin(), diag.begin() + h), oh(off.begin(), off.begin() + (h - 1));
+        const double cpl = off[h - 1];
+        const double r2 = 1.0 / std::sqrt(2.0);
+        for (int sign = 0; sign < 2; ++sign) {
+            std::vector<double> dd = dh, lam(h), Q((size_t)h * h);
+            dd[h - 1] += (sign == 0) ? cpl : -cpl;
+            tridiag_eigen(h, dd.data(), oh.data(), lam.data(), Q.data());
+            for (double &x : Q) x *= r2;
+            (sign == 0 ? P->Us : P->Ua) = Q;
+            (sign == 0 ? P->ls : P->la) = lam;
+        }
+    }
     P->dev_bytes = plan_layout(P, nullptr).bytes;
     *out = P;
     return MCA_OK;
@@ -693,6 +761,18 @@ mca_status mca_plan_upload(mca_plan *P, void *dev_buf, size_t bytes, void *strea
     split_host(H.QmT, m * m, MCA_PREC_BF16X3, H.QmTH, H.QmTL);
     split_host(H.Qn, n * n, MCA_PREC_BF16X3, H.QnH, H.QnL);
     split_host(H.QnT, n * n, MCA_PREC_BF16X3, H.QnTH, H.QnTL);
+    if (P->persym) {
+        const size_t h = m / 2;
+        for (size_t i = 0; i < h; ++i)
+            for (size_t k = 0; k < h; ++k) {
+                H.Us[i * h + k] = P->Us[i * h + k];
+                H.UsT[k * h + i] = P->Us[i * h + k];
+                H.Ua[i * h + k] = P->Ua[i * h + k];
+                H.UaT[k * h + i] = P->Ua[i * h + k];
+            }
+        std::memcpy(H.lbp, P->ls.data(), h * sizeof(double));
+        std::memcpy(H.lbp + h, P->la.data(), h * sizeof(double));
+    }
     MCA_TRY(hipMemcpyAsync(dev_buf, img.data(), P->dev_bytes, hipMemcpyHostToDevice, s));
     MCA_TRY(hipStreamSynchronize(s));
     PlanLayout L = plan_layout(P, dev_buf);
@@ -710,6 +790,8 @@ mca_status mca_plan_upload(mca_plan *P, void *dev_buf, size_t bytes, void *strea
     P->dev.QnT32 = L.QnT32;
     P->dev.QmH = L.QmH; P->dev.QmL = L.QmL; P->dev.QmTH = L.QmTH; P->dev.QmTL = L.QmTL;
     P->dev.QnH = L.QnH; P->dev.QnL = L.QnL; P->dev.QnTH = L.QnTH; P->dev.QnTL = L.QnTL;
+    P->dev.Us = L.Us; P->dev.UsT = L.UsT; P->dev.Ua = L.Ua; P->dev.UaT = L.UaT;
+    P->dev.lbp = L.lbp;
     return MCA_OK;
 }
 

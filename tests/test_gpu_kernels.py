@@ -102,6 +102,26 @@ def test_precond_parity(m, n, form, a1, a2):
     assert err <= tol
 
 
+@pytest.mark.parametrize("m,n,ends", [(64, 48, (0.1, 0.1)), (64, 48, (0.1, 0.07)),
+                                      (2, 5, (0.1, 0.1)), (130, 70, (0.2, 0.2)),
+                                      (7, 9, (0.1, 0.1))])
+def test_precond_literal_persymmetric_fold(m, n, ends):
+    """Equal bottom terminations with m even take the folded Q_m transforms
+    (symmetric / antisymmetric eigenvector halves); unequal ends or odd m the
+    full ones.  Both must match the oracle."""
+    a1 = a2 = 2.2e-5
+    geom = synth.Geometry(m, n, g_bot_end0=ends[0], g_bot_end1=ends[1])
+    rt, rb = synth.vector(m, n, seed=m + 3 * n)
+    zt, zb = oracle.precond_apply(geom, a1, a2, rt, rb)
+    plan = _plan_with_eigs(geom)
+    gzt, gzb = plan.precond_apply(a1, a2, dev(rt), dev(rb), form=B.MCA_PRECOND_LITERAL)
+    scale = max(np.abs(zt).max(), np.abs(zb).max())
+    err = max(np.abs(host(gzt) - zt).max(), np.abs(host(gzb) - zb).max()) / scale
+    tol = max(1e-11, _literal_tol(plan, a1))
+    say(f"  {m}x{n} ends {ends}: rel err {err:.2e} (tol {tol:.1e})")
+    assert err <= tol
+
+
 def test_precond_none_is_identity():
     m, n = 9, 11
     rt, rb = synth.vector(m, n, seed=1)
