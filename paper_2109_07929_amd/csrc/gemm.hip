@@ -28,7 +28,13 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, PAD = 2;
+constexpr int BM = 64, BN = 64, PAD = 0;
+
+// LDS column of element (k, c) of a staged slice: odd K rows swap their
+// 16-double halves, so the four K rows that one MFMA fragment read touches
+// (16 lanes each) fall on distinct banks in every 32-lane pass (rows are 64
+// doubles = 128 dwords, a multiple of the 64 banks).
+__device__ __forceinline__ int swz(int k, int c) { return c ^ ((k & 1) << 4); }
 constexpr int kXcds = 8;      // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kGroupM = 4;    // tile rows per group of the tile order
 
@@ -152,11 +158,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
         for (int h = 0; h < H; ++h) {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                double2 *d = reinterpret_cast<double2 *>(&Ls[buf][b][lr + RP * h][lc]);
+                const int row = lr + RP * h;
+                double2 *d = reinterpret_cast<double2 *>(&Ls[buf][b][row][swz(row, lc)]);
                 d[0] = st.l[b][h][0];
                 d[1] = st.l[b][h][1];
             }
-            double2 *d = reinterpret_cast<double2 *>(&Rs[buf][lr + RP * h][lc]);
+            const int row = lr + RP * h;
+            double2 *d = reinterpret_cast<double2 *>(&Rs[buf][row][swz(row, lc)]);
             d[0] = st.r[h][0];
             d[1] = st.r[h][1];
         }
@@ -179,9 +187,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) af[slot][b][i] = Ls[buf][b][kr][wm + i * 16 + (lane & 15)];
+            for (int b = 0; b < NB; ++b)
+                af[slot][b][i] = Ls[buf][b][kr][swz(kr, wm + i * 16 + (lane & 15))];
 #pragma unroll
-        for (int j = 0; j < WJ; ++j) bf[slot][j] = Rs[buf][kr][wn + j * 16 + (lane & 15)];
+        for (int j = 0; j < WJ; ++j) bf[slot][j] = Rs[buf][kr][swz(kr, wn + j * 16 + (lane & 15))];
     };
     auto mfmas = [&](int slot) {
 #pragma unroll
