@@ -263,3 +263,34 @@ def test_solve_approx_1024():
     err = rel_err(vt, vb, rt, rb)
     say(f"  err vs oracle {err:.2e}")
     assert err <= TOL
+
+
+@pytest.mark.slow
+def test_solve_2048_fp64_and_mixed_precision():
+    """The 2048 x 2048 crossbar (8.4M unknowns): the plain FP64 solve and the
+    FP32 / split-BF16 / BF16 preconditioners against the oracle's steady state
+    (CG Newton), with iteration counts and times beside the FP64 solve."""
+    m = n = 2048
+    cb = synth.crossbar(m, n, seed=0)
+    say("solve 2048x2048: oracle (CG Newton) ...")
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="cg")
+    plan = Plan(cb.geom)
+    g, v = dev(cb.g_dev), dev(cb.v_in)
+    for form, prec in ((B.MCA_PRECOND_LITERAL, B.MCA_PREC_FP64),
+                       (B.MCA_PRECOND_PERMODE, B.MCA_PREC_FP32),
+                       (B.MCA_PRECOND_PERMODE, B.MCA_PREC_BF16X3),
+                       (B.MCA_PRECOND_PERMODE, B.MCA_PREC_BF16)):
+        o = B.options(precond=form, precision=prec)
+        plan.solve(g, v, o)                       # warm-up (first launch of each kernel)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        vt, vb, status, st = plan.solve(g, v, o)
+        ev1.record()
+        torch.cuda.synchronize()
+        err = rel_err(host(vt), host(vb), rt, rb)
+        say(f"  precision {prec}: {ev0.elapsed_time(ev1):.1f} ms, newton {st.newton_iters} krylov "
+            f"{list(st.krylov_history[:st.newton_iters])}, rel residual {st.rel_residual:.1e}, "
+            f"max rel voltage error {err:.2e}")
+        assert status == B.MCA_OK
+        assert err <= TOL
