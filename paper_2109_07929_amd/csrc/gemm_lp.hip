@@ -35,19 +35,22 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int LBM = 64, LBK = 64, LTPB = 256;
+#ifndef MCA_LP_PAD
+#define MCA_LP_PAD 8
+#endif
 
 template <int MODE>
 struct Fmt {   // BF16 modes: two bf16 planes, 8 values per 16-byte chunk
     static constexpr int kPlanes = (MODE == MCA_PREC_BF16X3) ? 2 : 1;
     static constexpr int kPerChunk = 8;
-    static constexpr int kPitch = LBK + 8;                 // bf16 per LDS row
+    static constexpr int kPad = MCA_LP_PAD;                // bf16 of LDS row padding
     using elem = __bf16;
 };
 template <>
 struct Fmt<MCA_PREC_FP32> {
     static constexpr int kPlanes = 1;
     static constexpr int kPerChunk = 4;
-    static constexpr int kPitch = LBK + 4;                 // floats per LDS row
+    static constexpr int kPad = 4;
     using elem = float;
 };
 
@@ -56,28 +59,30 @@ struct Operand {
     const void *p[2];
 };
 
-template <int MODE>
+// One operand slice in LDS: ROWS rows (tile edge) x KS values of K (+ padding).
+template <int MODE, int ROWS, int KS>
 struct Tile {
-    typename Fmt<MODE>::elem v[Fmt<MODE>::kPlanes][LBM][Fmt<MODE>::kPitch];
+    typename Fmt<MODE>::elem v[Fmt<MODE>::kPlanes][ROWS][KS + Fmt<MODE>::kPad];
 };
 
-// Chunks of one 64 x 64 operand slice per plane, per thread.
-template <int MODE>
+// 16-byte chunks of one ROWS x KS operand slice per plane, per thread.
+template <int MODE, int ROWS, int KS>
 constexpr int chunks_per_thread()
 {
-    return LBM * LBK / Fmt<MODE>::kPerChunk / LTPB;
+    return ROWS * KS / Fmt<MODE>::kPerChunk / LTPB;
 }
 
-template <int MODE>
+template <int MODE, int ROWS, int KS>
 struct Regs {
-    u4 c[Fmt<MODE>::kPlanes][chunks_per_thread<MODE>()];
+    u4 c[Fmt<MODE>::kPlanes][chunks_per_thread<MODE, ROWS, KS>()];
 };
 
-template <int MODE>
+template <int MODE, int ROWS, int KS>
 __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int r0, int k0,
-                                        bool fast, Regs<MODE> &g)
+                                        bool fast, Regs<MODE, ROWS, KS> &g)
 {
-    constexpr int PC = Fmt<MODE>::kPerChunk, CPR = LBK / PC, CPT = chunks_per_thread<MODE>();
+    constexpr int PC = Fmt<MODE>::kPerChunk, CPR = KS / PC;
+    constexpr int CPT = chunks_per_thread<MODE, ROWS, KS>();
     using E = typename Fmt<MODE>::elem;
 #pragma unroll
     for (int pl = 0; pl < Fmt<MODE>::kPlanes; ++pl) {
@@ -106,10 +111,11 @@ __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int 
     }
 }
 
-template <int MODE>
-__device__ __forceinline__ void stash_op(Tile<MODE> &t, const Regs<MODE> &g)
+template <int MODE, int ROWS, int KS>
+__device__ __forceinline__ void stash_op(Tile<MODE, ROWS, KS> &t, const Regs<MODE, ROWS, KS> &g)
 {
-    constexpr int PC = Fmt<MODE>::kPerChunk, CPR = LBK / PC, CPT = chunks_per_thread<MODE>();
+    constexpr int PC = Fmt<MODE>::kPerChunk, CPR = KS / PC;
+    constexpr int CPT = chunks_per_thread<MODE, ROWS, KS>();
 #pragma unroll
     for (int pl = 0; pl < Fmt<MODE>::kPlanes; ++pl)
 #pragma unroll
@@ -150,75 +156,81 @@ __device__ __forceinline__ void put(const LpArgs &a, int b, size_t o, T v, int o
 
 constexpr int DEPTH = 2;   // K slices in flight (deeper rings measured no faster)
 
-// One 64 x 64 output tile at (m0, n0) of O = A B^T.
-template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI>
+// One TS x TS output tile at (m0, n0) of O = A B^T: four waves of (TS/2)^2,
+// F x F MFMA tiles of 16 x 16 each; K staged in slices of KS.
+template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI, int TS, int KS>
 __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 {
     constexpr int NA = A_BATCHED ? NB : 1, NBB = A_BATCHED ? 1 : NB;
-    __shared__ Tile<MODE> As[2][NA];
-    __shared__ Tile<MODE> Bs[2][NBB];
+    constexpr int WT = TS / 2, F = WT / 16;
+    using TileT = Tile<MODE, TS, KS>;
+    using RegsT = Regs<MODE, TS, KS>;
+    __shared__ TileT As[2][NA];
+    __shared__ TileT Bs[2][NBB];
     const int M = a.M, N = a.N, K = a.K;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const bool fast_m = a.vec && (m0 + LBM <= M);
-    const bool fast_n = a.vec && (n0 + LBM <= N);
+    const int wm = (wave >> 1) * WT, wn = (wave & 1) * WT;
+    const bool fast_m = a.vec && (m0 + TS <= M);
+    const bool fast_n = a.vec && (n0 + TS <= N);
 
     struct Stage {
-        Regs<MODE> ra[NA], rb[NBB];
+        RegsT ra[NA], rb[NBB];
     };
     auto load = [&](Stage &st, int k0) {
-        const bool kin = k0 + LBK <= K;
+        const bool kin = k0 + KS <= K;
 #pragma unroll
-        for (int b = 0; b < NA; ++b) load_op<MODE>(a.A[b], M, K, m0, k0, fast_m && kin, st.ra[b]);
+        for (int b = 0; b < NA; ++b)
+            load_op<MODE, TS, KS>(a.A[b], M, K, m0, k0, fast_m && kin, st.ra[b]);
 #pragma unroll
-        for (int b = 0; b < NBB; ++b) load_op<MODE>(a.B[b], N, K, n0, k0, fast_n && kin, st.rb[b]);
+        for (int b = 0; b < NBB; ++b)
+            load_op<MODE, TS, KS>(a.B[b], N, K, n0, k0, fast_n && kin, st.rb[b]);
     };
     auto stash = [&](const Stage &st, int buf) {
 #pragma unroll
-        for (int b = 0; b < NA; ++b) stash_op<MODE>(As[buf][b], st.ra[b]);
+        for (int b = 0; b < NA; ++b) stash_op<MODE, TS, KS>(As[buf][b], st.ra[b]);
 #pragma unroll
-        for (int b = 0; b < NBB; ++b) stash_op<MODE>(Bs[buf][b], st.rb[b]);
+        for (int b = 0; b < NBB; ++b) stash_op<MODE, TS, KS>(Bs[buf][b], st.rb[b]);
     };
 
-    f4 acc[NB][2][2];
+    f4 acc[NB][F][F];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < F; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[b][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < F; ++j) acc[b][i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
     auto compute = [&](int buf) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const Tile<MODE> &TA_ = As[buf][A_BATCHED ? b : 0];
-            const Tile<MODE> &TB_ = Bs[buf][A_BATCHED ? 0 : b];
+            const TileT &TA_ = As[buf][A_BATCHED ? b : 0];
+            const TileT &TB_ = Bs[buf][A_BATCHED ? 0 : b];
             if constexpr (MODE == MCA_PREC_FP32) {
                 // A fragment: row l%16, k l/16; B fragment: k l/16, column l%16
 #pragma unroll
-                for (int k4 = 0; k4 < LBK / 4; ++k4) {
+                for (int k4 = 0; k4 < KS / 4; ++k4) {
                     const int kk = k4 * 4 + (lane >> 4);
-                    float fa[2], fb[2];
+                    float fa[F], fb[F];
 #pragma unroll
-                    for (int i = 0; i < 2; ++i) fa[i] = TA_.v[0][wm + i * 16 + (lane & 15)][kk];
+                    for (int i = 0; i < F; ++i) fa[i] = TA_.v[0][wm + i * 16 + (lane & 15)][kk];
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) fb[j] = TB_.v[0][wn + j * 16 + (lane & 15)][kk];
+                    for (int j = 0; j < F; ++j) fb[j] = TB_.v[0][wn + j * 16 + (lane & 15)][kk];
 #pragma unroll
-                    for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < F; ++i)
 #pragma unroll
-                        for (int j = 0; j < 2; ++j)
+                        for (int j = 0; j < F; ++j)
                             acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j],
                                                                                 acc[b][i][j], 0, 0, 0);
                 }
             } else {
                 // A fragment: row l%16, k 8(l/16)..+7; B fragment: column l%16, same k
 #pragma unroll
-                for (int k32 = 0; k32 < LBK / 32; ++k32) {
+                for (int k32 = 0; k32 < KS / 32; ++k32) {
                     const int kk = k32 * 32 + (lane >> 4) * 8;
-                    bf8 ah[2], al[2], bh[2], bl[2];
+                    bf8 ah[F], al[F], bh[F], bl[F];
 #pragma unroll
-                    for (int i = 0; i < 2; ++i) {
+                    for (int i = 0; i < F; ++i) {
                         ah[i] = *reinterpret_cast<const bf8 *>(&TA_.v[0][wm + i * 16 + (lane & 15)][kk]);
                         bh[i] = *reinterpret_cast<const bf8 *>(&TB_.v[0][wn + i * 16 + (lane & 15)][kk]);
                         if constexpr (MODE == MCA_PREC_BF16X3) {
@@ -227,9 +239,9 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
                         }
                     }
 #pragma unroll
-                    for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < F; ++i)
 #pragma unroll
-                        for (int j = 0; j < 2; ++j) {
+                        for (int j = 0; j < F; ++j) {
                             if constexpr (MODE == MCA_PREC_BF16X3) {
                                 acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                                     al[i], bh[j], acc[b][i][j], 0, 0, 0);
@@ -248,11 +260,11 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
     // by DEPTH so that the stages rotate by name.  At step k the stage that
     // held slice k (already in LDS) receives slice k + DEPTH, slice k is
     // multiplied, and slice k + 1 moves from registers into the other LDS buffer.
-    const int nk = (K + LBK - 1) / LBK;
+    const int nk = (K + KS - 1) / KS;
     Stage st[DEPTH];
 #pragma unroll
     for (int u = 0; u < DEPTH; ++u)
-        if (u < nk) load(st[u], u * LBK);
+        if (u < nk) load(st[u], u * KS);
     stash(st[0], 0);
     __syncthreads();
     for (int kb = 0; kb < nk; kb += DEPTH) {
@@ -260,7 +272,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
         for (int u = 0; u < DEPTH; ++u) {
             const int k = kb + u;
             if (k < nk) {   // uniform
-                if (k + DEPTH < nk) load(st[u], (k + DEPTH) * LBK);
+                if (k + DEPTH < nk) load(st[u], (k + DEPTH) * KS);
                 compute(k & 1);
                 if (k + 1 < nk) stash(st[(u + 1) % DEPTH], (k + 1) & 1);
                 __syncthreads();
@@ -270,9 +282,9 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 
     // accumulator element r of lane l: row 4 (l/16) + r, column l%16
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < F; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < F; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
@@ -299,13 +311,13 @@ __device__ __forceinline__ int xcd_order(int bid, int nwg)
     return (nwg % 8 == 0) ? (bid % 8) * (nwg / 8) + bid / 8 : bid;
 }
 
-template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI>
+template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI, int TS, int KS>
 __global__ __launch_bounds__(LTPB) void k_gemm_nt_lp(LpArgs a)
 {
     if (a.skip && *a.skip) return;
     const int t = xcd_order(blockIdx.x, gridDim.x);
-    const int tiles_n = (a.N + LBM - 1) / LBM;
-    gemm_nt_tile<MODE, NB, A_BATCHED, OUT, EPI>(a, (t / tiles_n) * LBM, (t % tiles_n) * LBM);
+    const int tiles_n = (a.N + TS - 1) / TS;
+    gemm_nt_tile<MODE, NB, A_BATCHED, OUT, EPI, TS, KS>(a, (t / tiles_n) * TS, (t % tiles_n) * TS);
 }
 
 // Grouped launch over many crossbars: tile t of the table names an instance's
@@ -344,7 +356,7 @@ __global__ __launch_bounds__(LTPB) void k_gemm_nt_lp_grouped(GroupedLp g)
     a.lam_col = d.lam_col;
     if (g.a_inst) a.a1 = a.a2 = g.a_inst[d.inst * g.a_stride];
     a.vec = d.vec;
-    gemm_nt_tile<MODE, NB, A_BATCHED, OUT, EPI>(a, tile.y, tile.z);
+    gemm_nt_tile<MODE, NB, A_BATCHED, OUT, EPI, LBM, LBK>(a, tile.y, tile.z);
 }
 
 // FP64 -> the operand format of MODE (FP32, or bf16 hi/lo planes), two arrays.
@@ -373,13 +385,27 @@ __global__ __launch_bounds__(256) void k_split(const double *__restrict__ x0,
 
 bool aligned16(const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// 128 x 128 tiles (K slices of 32) when they still give 256 or more workgroups:
+// four times the operand reuse of 64 x 64 tiles; else 64 x 64 (K slices of 64).
+template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI>
+void launch_nt(const LpArgs &g, hipStream_t s)
+{
+    const long big = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
+    if (big >= 256)
+        hipLaunchKernelGGL((k_gemm_nt_lp<MODE, NB, A_BATCHED, OUT, EPI, 128, 32>), dim3((int)big),
+                           dim3(LTPB), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gemm_nt_lp<MODE, NB, A_BATCHED, OUT, EPI, LBM, LBK>),
+                           dim3(((g.M + LBM - 1) / LBM) * ((g.N + LBM - 1) / LBM)), dim3(LTPB), 0, s,
+                           g);
+}
+
 template <int MODE>
 hipError_t chain(const LowPrecChain &c, hipStream_t s)
 {
     constexpr int OUT = (MODE == MCA_PREC_FP32) ? OUT_F32 : (MODE == MCA_PREC_BF16X3) ? OUT_BF2 : OUT_BF1;
     const int m = c.m, n = c.n;
     const size_t mn = (size_t)m * n;
-    auto tiles = [](int M, int N) { return ((M + LBM - 1) / LBM) * ((N + LBM - 1) / LBM); };
     auto op = [](const LpPlanes &p) {
         Operand o;
         o.p[0] = p.p[0];
@@ -405,8 +431,7 @@ hipError_t chain(const LowPrecChain &c, hipStream_t s)
     g.A[0] = op(c.QnT); g.B[0] = op(c.x[0]); g.B[1] = op(c.x[1]);
     for (int b = 0; b < 2; ++b) { g.O[b][0] = c.u[b].p[0]; g.O[b][1] = c.u[b].p[1]; }
     g.vec = vec_ok(g);
-    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, false, OUT, EPI_STORE>), dim3(tiles(n, m)),
-                       dim3(LTPB), 0, s, g);
+    launch_nt<MODE, 2, false, OUT, EPI_STORE>(g, s);
     // 2. W^T (n x m) = U^T . Q_m      A = U^T (n x m), B = QmT (m x m); per-mode solve
     g = LpArgs{};
     g.skip = c.skip; g.a1 = c.a1; g.a2 = c.a2;
@@ -415,8 +440,7 @@ hipError_t chain(const LowPrecChain &c, hipStream_t s)
     for (int b = 0; b < 2; ++b) { g.O[b][0] = c.w[b].p[0]; g.O[b][1] = c.w[b].p[1]; }
     g.lam_row = c.lt; g.lam_col = c.lb;
     g.vec = vec_ok(g);
-    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, true, OUT, EPI_PERMODE>), dim3(tiles(n, m)),
-                       dim3(LTPB), 0, s, g);
+    launch_nt<MODE, 2, true, OUT, EPI_PERMODE>(g, s);
     // 3. Y (m x n) = Q_m . X^hat      A = Qm (m x m), B = X^hat^T (n x m)
     g = LpArgs{};
     g.skip = c.skip;
@@ -424,8 +448,7 @@ hipError_t chain(const LowPrecChain &c, hipStream_t s)
     g.A[0] = op(c.Qm); g.B[0] = op(c.w[0]); g.B[1] = op(c.w[1]);
     for (int b = 0; b < 2; ++b) { g.O[b][0] = c.u[b].p[0]; g.O[b][1] = c.u[b].p[1]; }
     g.vec = vec_ok(g);
-    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, false, OUT, EPI_STORE>), dim3(tiles(m, n)),
-                       dim3(LTPB), 0, s, g);
+    launch_nt<MODE, 2, false, OUT, EPI_STORE>(g, s);
     // 4. Z (m x n) = Y . Q_n^T         A = Y (m x n), B = Qn (n x n); FP64 out
     g = LpArgs{};
     g.skip = c.skip;
@@ -433,8 +456,7 @@ hipError_t chain(const LowPrecChain &c, hipStream_t s)
     g.A[0] = op(c.u[0]); g.A[1] = op(c.u[1]); g.B[0] = op(c.Qn);
     g.O[0][0] = c.zt; g.O[1][0] = c.zb;
     g.vec = vec_ok(g);
-    hipLaunchKernelGGL((k_gemm_nt_lp<MODE, 2, true, OUT_F64, EPI_STORE>), dim3(tiles(m, n)),
-                       dim3(LTPB), 0, s, g);
+    launch_nt<MODE, 2, true, OUT_F64, EPI_STORE>(g, s);
     return hipGetLastError();
 }
 

@@ -260,6 +260,27 @@ def test_precond_lowprec_parity(m, n, prec, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("prec,tol", [(B.MCA_PREC_FP32, 1e-3), (B.MCA_PREC_BF16X3, 1e-2)])
+def test_precond_lowprec_large_tiles(prec, tol):
+    """Products of 2048-class sizes take the 128 x 128 tiles; a ragged size (not a
+    multiple of 128) against the FP64 per-mode path (itself oracle-checked above).
+    An indexing slip gives errors of order one; rounding stays far below the bound."""
+    m, n = 2112, 2080
+    a1, a2 = 2.2e-5, 3e-5
+    say(f"precond lowprec large tiles {m}x{n} prec={prec}")
+    geom = synth.Geometry(m, n)
+    rt, rb = synth.vector(m, n, seed=11)
+    plan = Plan(geom)
+    ft, fb = plan.precond_apply(a1, a2, dev(rt), dev(rb), form=B.MCA_PRECOND_PERMODE)
+    gt, gb = plan.precond_apply(a1, a2, dev(rt), dev(rb), form=B.MCA_PRECOND_PERMODE,
+                                precision=prec)
+    zt, zb = host(ft), host(fb)
+    scale = max(np.abs(zt).max(), np.abs(zb).max())
+    err = max(np.abs(host(gt) - zt).max(), np.abs(host(gb) - zb).max()) / scale
+    say(f"  rel err vs FP64 {err:.3e} (tol {tol:.0e})")
+    assert err <= tol
+
+
 @pytest.mark.parametrize("prec,tol", [(B.MCA_PREC_FP32, 1e-2), (B.MCA_PREC_BF16X3, 5e-2),
                                       (B.MCA_PREC_BF16, 10.0)])
 def test_precond_lowprec_residual_at_1024(prec, tol):
