@@ -157,3 +157,18 @@ def test_batch_monte_carlo_256():
         err = rel_err(vts[b], vbs[b], rt, rb)
         say(f"  sample {b} {c.geom.m}x{c.geom.n}: err {err:.1e}")
         assert err <= TOL
+
+
+def test_batch_more_than_1024_crossbars():
+    """Over 1024 crossbars the per-crossbar control kernels run in several blocks
+    (counters summed across them): every crossbar still converges, each matches
+    its own residual check, and a sample matches the oracle."""
+    cbs = synth.mc_batch(1100, seed=21, sizes=(4, 6, 8, 12))
+    say(f"batch of {len(cbs)}")
+    bt, vts, vbs, status, stats = batch_solve(cbs)
+    assert status == B.MCA_OK
+    assert all(s.rel_residual <= 1e-10 for s in stats)
+    for b in (0, 511, 1023, 1024, 1099):
+        c = cbs[b]
+        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="band")
+        assert rel_err(vts[b], vbs[b], rt, rb) <= TOL
