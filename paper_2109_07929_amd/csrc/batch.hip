@@ -703,6 +703,7 @@ struct mca_batch {
     mca::LpDesc *d_desc[2][4] = {};         // [fp32 | bf16][step]
     int4 *d_tiles[4] = {};
     int ntiles[4] = {};
+    int tile = 64;                          // tile edge of the grouped products
 };
 
 namespace mca {
@@ -738,7 +739,18 @@ struct BatchLayout {
     size_t bytes;
 };
 
-const int kLp = 64;   // tile edge of the reduced-precision products
+// Tile edge of a batch's grouped products: 128 (four times the operand reuse)
+// when every crossbar's sides are at least 256 and the batch still gives 256 or
+// more 128-tiles per product; else 64.
+int choose_tile(const std::vector<mca_geometry> &geoms)
+{
+    long t128 = 0;
+    for (const mca_geometry &g : geoms) {
+        if (g.m < 256 || g.n < 256) return 64;
+        t128 += (long)((g.m + 127) / 128) * ((g.n + 127) / 128);
+    }
+    return t128 >= 256 ? 128 : 64;
+}
 
 BatchLayout batch_layout(const mca_batch *B, void *base)
 {
@@ -925,11 +937,13 @@ mca_status mca_batch_create(int32_t count, const mca_geometry *geoms, mca_batch 
         for (int c = 0; c < nb; ++c) B->btab.push_back(int2{b, c});
     }
     // tiles of the four products: steps 1, 2 are n x m, steps 3, 4 are m x n
+    B->tile = choose_tile(B->geoms);
+    const int T = B->tile;
     for (int s = 0; s < 4; ++s) {
         int t = 0;
         for (int b = 0; b < count; ++b) {
             const int M = (s < 2) ? geoms[b].n : geoms[b].m, N = (s < 2) ? geoms[b].m : geoms[b].n;
-            t += ((M + kLp - 1) / kLp) * ((N + kLp - 1) / kLp);
+            t += ((M + T - 1) / T) * ((N + T - 1) / T);
         }
         B->ntiles[s] = t;
     }
@@ -1019,8 +1033,9 @@ mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *str
         int t = 0;
         for (size_t b = 0; b < cnt; ++b) {
             const int M = H.desc[0][st][b].M, N = H.desc[0][st][b].N;
-            for (int i = 0; i < (M + kLp - 1) / kLp; ++i)
-                for (int j = 0; j < (N + kLp - 1) / kLp; ++j) H.tiles[st][t++] = int4{(int)b, i * kLp, j * kLp, 0};
+            const int T = B->tile;
+            for (int i = 0; i < (M + T - 1) / T; ++i)
+                for (int j = 0; j < (N + T - 1) / T; ++j) H.tiles[st][t++] = int4{(int)b, i * T, j * T, 0};
         }
     }
     MCA_BTRY(hipMemcpyAsync(dev_buf, img.data(), B->dev_bytes, hipMemcpyHostToDevice, s));
@@ -1110,6 +1125,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         gc.ntiles[q] = B->ntiles[q];
     }
     gc.len = len;
+    gc.tile = B->tile;
     gc.x = w.x;
     gc.u = w.u;
     gc.w = w.w;

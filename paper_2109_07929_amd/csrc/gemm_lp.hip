@@ -324,7 +324,7 @@ __global__ __launch_bounds__(LTPB) void k_gemm_nt_lp(LpArgs a)
 // product (descriptor) and the tile's origin.  The data operand and the output
 // of every instance sit at an element offset from the launch's base planes;
 // the eigenbasis operand is the instance's own.
-template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI>
+template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI, int TS, int KS>
 __global__ __launch_bounds__(LTPB) void k_gemm_nt_lp_grouped(GroupedLp g)
 {
     const int t = xcd_order(blockIdx.x, gridDim.x);
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(LTPB) void k_gemm_nt_lp_grouped(GroupedLp g)
     a.lam_col = d.lam_col;
     if (g.a_inst) a.a1 = a.a2 = g.a_inst[d.inst * g.a_stride];
     a.vec = d.vec;
-    gemm_nt_tile<MODE, NB, A_BATCHED, OUT, EPI, LBM, LBK>(a, tile.y, tile.z);
+    gemm_nt_tile<MODE, NB, A_BATCHED, OUT, EPI, TS, KS>(a, tile.y, tile.z);
 }
 
 // FP64 -> the operand format of MODE (FP32, or bf16 hi/lo planes), two arrays.
@@ -460,6 +460,17 @@ hipError_t chain(const LowPrecChain &c, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI>
+void launch_grouped(const GroupedLp &g, int ntiles, int tile, hipStream_t s)
+{
+    if (tile == 128)
+        hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, NB, A_BATCHED, OUT, EPI, 128, 32>),
+                           dim3(ntiles), dim3(LTPB), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, NB, A_BATCHED, OUT, EPI, LBM, LBK>),
+                           dim3(ntiles), dim3(LTPB), 0, s, g);
+}
+
 template <int MODE>
 hipError_t chain_grouped(const GroupedChain &c, hipStream_t s)
 {
@@ -485,21 +496,17 @@ hipError_t chain_grouped(const GroupedChain &c, hipStream_t s)
         g.out[1] = out.p[1];
     };
     set(0, c.x, c.u);
-    hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, 2, false, OUT, EPI_STORE>), dim3(c.ntiles[0]),
-                       dim3(LTPB), 0, s, g);
+    launch_grouped<MODE, 2, false, OUT, EPI_STORE>(g, c.ntiles[0], c.tile, s);
     set(1, c.u, c.w);
-    hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, 2, true, OUT, EPI_PERMODE>), dim3(c.ntiles[1]),
-                       dim3(LTPB), 0, s, g);
+    launch_grouped<MODE, 2, true, OUT, EPI_PERMODE>(g, c.ntiles[1], c.tile, s);
     set(2, c.w, c.u);
-    hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, 2, false, OUT, EPI_STORE>), dim3(c.ntiles[2]),
-                       dim3(LTPB), 0, s, g);
+    launch_grouped<MODE, 2, false, OUT, EPI_STORE>(g, c.ntiles[2], c.tile, s);
     LpPlanes z;
     z.p[0] = c.z;
     z.p[1] = nullptr;
     set(3, c.u, z);
     g.out_elem_bytes = 8;
-    hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, 2, true, OUT_F64, EPI_STORE>),
-                       dim3(c.ntiles[3]), dim3(LTPB), 0, s, g);
+    launch_grouped<MODE, 2, true, OUT_F64, EPI_STORE>(g, c.ntiles[3], c.tile, s);
     return hipGetLastError();
 }
 

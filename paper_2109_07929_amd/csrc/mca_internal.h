@@ -170,6 +170,7 @@ struct GroupedChain {
     const LpDesc *descs[4];
     const int4 *tiles[4];
     int ntiles[4];
+    int tile;                           // tile edge of the tables: 64 or 128
     const double *r;
     size_t len;
     LpPlanes x, u, w;

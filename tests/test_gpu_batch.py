@@ -172,3 +172,17 @@ def test_batch_more_than_1024_crossbars():
         c = cbs[b]
         rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="band")
         assert rel_err(vts[b], vbs[b], rt, rb) <= TOL
+
+
+def test_batch_large_crossbars_use_large_tiles():
+    """Batches whose crossbars all have sides >= 256 run the grouped products on
+    128 x 128 tiles; ragged sizes (not multiples of 128) against the oracle."""
+    cbs = [synth.crossbar(300, 520, seed=s) for s in range(4)]
+    bt, vts, vbs, status, stats = batch_solve(cbs)
+    assert status == B.MCA_OK
+    for b, c in enumerate(cbs):
+        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="cg")
+        err = rel_err(vts[b], vbs[b], rt, rb)
+        say(f"  {c.geom.m}x{c.geom.n}: newton {stats[b].newton_iters} krylov "
+            f"{stats[b].krylov_iters} err {err:.1e}")
+        assert err <= TOL
