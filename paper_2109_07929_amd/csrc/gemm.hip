@@ -280,26 +280,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
 
 }  // namespace
 
-int gemm_variant = 0;
-
+// 8 waves (two per SIMD), 32-deep K slices, fragments double-buffered: the
+// fastest of the measured shapes (4 waves of 32 x 32; fragments read up front;
+// 64-deep slices) at 1024^3 and 2048^3.
 template <int NB, int EPI>
 static void launch_variant(const GemmArgs &a, int tiles, hipStream_t s)
 {
-    switch (gemm_variant) {
-    case 1:   // 4 waves, fragments double-buffered
-        hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, 32, 4, false>), dim3(tiles), dim3(256), 0, s, a);
-        break;
-    case 3:   // 8 waves, fragments up front
-        hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, 32, 8, true>), dim3(tiles), dim3(512), 0, s, a);
-        break;
-    case 4:   // 8 waves, 64-deep K slices for one batch
-        hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, (NB == 1 ? 64 : 32), 8, false>), dim3(tiles),
-                           dim3(512), 0, s, a);
-        break;
-    default:  // 8 waves (two per SIMD), fragments double-buffered
-        hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, 32, 8, false>), dim3(tiles), dim3(512), 0, s, a);
-        break;
-    }
+    hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, 32, 8, false>), dim3(tiles), dim3(512), 0, s, a);
 }
 
 hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)

@@ -123,7 +123,6 @@ struct GemmArgs {
     const double *R1;
 };
 hipError_t launch_gemm_f64(const GemmArgs &a, int epi, hipStream_t s);
-extern int gemm_variant;   // kernel variant (tuning only; 0 = default)
 
 // Per-mode preconditioner in reduced precision (gemm_lp.hip): four NT products
 // on FP32 / BF16 MFMA with the per-mode 2x2 solve in the second one.

@@ -86,11 +86,9 @@ struct PcrSolveArgs {
 };
 
 // EPT elements per thread (E = len * lpw <= EPT * TPB); LDS sized to E at
-// launch.  Each thread's (k, line) pairs are fixed for the whole solve.  With
-// MAXLEV > 0 every level's multipliers of the thread's elements are loaded into
-// registers before the first level (one memory latency instead of one per
-// level); otherwise the next level's are loaded while the current one runs.
-template <int EPT, int MAXLEV>
+// launch.  Each thread's (k, line) pairs are fixed for the whole solve, and the
+// next level's multipliers are loaded while the current level is applied.
+template <int EPT>
 __global__ __launch_bounds__(TPB) void k_pcr_solve(PcrSolveArgs p)
 {
     if (p.skip && *p.skip) return;
@@ -123,26 +121,15 @@ __global__ __launch_bounds__(TPB) void k_pcr_solve(PcrSolveArgs p)
         }
         if (e < E) d[e] = v;
     }
-    constexpr int NL = MAXLEV > 0 ? MAXLEV : 1;
-    double al[NL][EPT], ga[NL][EPT];
-    if constexpr (MAXLEV > 0) {
+    double al[EPT], ga[EPT];
 #pragma unroll
-        for (int lev = 0; lev < MAXLEV; ++lev)
-#pragma unroll
-            for (int r = 0; r < EPT; ++r) {
-                const bool on = lev < p.levels;
-                al[lev][r] = on ? p.alpha[(size_t)lev * len + kk[r]] : 0.0;
-                ga[lev][r] = on ? p.gamma[(size_t)lev * len + kk[r]] : 0.0;
-            }
-    } else {
-#pragma unroll
-        for (int r = 0; r < EPT; ++r) {
-            al[0][r] = (p.levels > 0) ? p.alpha[kk[r]] : 0.0;
-            ga[0][r] = (p.levels > 0) ? p.gamma[kk[r]] : 0.0;
-        }
+    for (int r = 0; r < EPT; ++r) {
+        al[r] = (p.levels > 0) ? p.alpha[kk[r]] : 0.0;
+        ga[r] = (p.levels > 0) ? p.gamma[kk[r]] : 0.0;
     }
     __syncthreads();
-    auto level = [&](int lev, int s, const double *a, const double *g) {
+    int s = 1;
+    for (int lev = 0; lev < p.levels; ++lev, s <<= 1) {
         double nd[EPT];
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
@@ -150,20 +137,18 @@ __global__ __launch_bounds__(TPB) void k_pcr_solve(PcrSolveArgs p)
             if (e < E) {
                 const int k = kk[r];
                 double v = d[e];
-                if (k - s >= 0) v += a[r] * d[e - s * kst];
-                if (k + s < len) v += g[r] * d[e + s * kst];
+                if (k - s >= 0) v += al[r] * d[e - s * kst];
+                if (k + s < len) v += ga[r] * d[e + s * kst];
                 nd[r] = v;
             }
         }
-        if constexpr (MAXLEV == 0) {
-            if (lev + 1 < p.levels) {
-                const double *an = p.alpha + (size_t)(lev + 1) * len;
-                const double *gn = p.gamma + (size_t)(lev + 1) * len;
+        if (lev + 1 < p.levels) {
+            const double *an = p.alpha + (size_t)(lev + 1) * len;
+            const double *gn = p.gamma + (size_t)(lev + 1) * len;
 #pragma unroll
-                for (int r = 0; r < EPT; ++r) {
-                    al[0][r] = an[kk[r]];
-                    ga[0][r] = gn[kk[r]];
-                }
+            for (int r = 0; r < EPT; ++r) {
+                al[r] = an[kk[r]];
+                ga[r] = gn[kk[r]];
             }
         }
         __syncthreads();
@@ -173,21 +158,6 @@ __global__ __launch_bounds__(TPB) void k_pcr_solve(PcrSolveArgs p)
             if (e < E) d[e] = nd[r];
         }
         __syncthreads();
-    };
-    if constexpr (MAXLEV > 0) {
-#pragma unroll
-        for (int lev = 0; lev < MAXLEV; ++lev)
-            if (lev < p.levels) level(lev, 1 << lev, al[lev], ga[lev]);
-    } else {
-        for (int lev = 0; lev < p.levels; ++lev) {
-            double a0[EPT], g0[EPT];
-#pragma unroll
-            for (int r = 0; r < EPT; ++r) {
-                a0[r] = al[0][r];
-                g0[r] = ga[0][r];
-            }
-            level(lev, 1 << lev, a0, g0);
-        }
     }
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
@@ -420,11 +390,11 @@ hipError_t launch_pcr_solve(const PcrTables &t, int lines, bool rows, size_t lin
     p.skip = skip;
     const size_t lds = (size_t)t.len * p.lpw * sizeof(double);
     const dim3 grid((lines + p.lpw - 1) / p.lpw);
-    // (loading every level's multipliers up front, MAXLEV > 0, measured slower)
+    // (loading every level's multipliers up front measured slower)
     if (t.len * p.lpw <= 8 * TPB)
-        hipLaunchKernelGGL((k_pcr_solve<8, 0>), grid, dim3(TPB), lds, s, p);
+        hipLaunchKernelGGL(k_pcr_solve<8>, grid, dim3(TPB), lds, s, p);
     else
-        hipLaunchKernelGGL((k_pcr_solve<kEpt, 0>), grid, dim3(TPB), lds, s, p);
+        hipLaunchKernelGGL(k_pcr_solve<kEpt>, grid, dim3(TPB), lds, s, p);
     return hipGetLastError();
 }
 
