@@ -50,6 +50,12 @@ def parse():
                    help="batched Monte-Carlo workload of this many crossbars instead")
     p.add_argument("--batch", type=int, default=0,
                    help="batched solve of this many size x size crossbars instead")
+    p.add_argument("--mgs-passes", action="store_true",
+                   help="orthogonalise with one pass per basis vector (MCA_FLAG_MGS_PASSES) "
+                        "instead of the two-pass compact WY form")
+    p.add_argument("--graph", action="store_true",
+                   help="with --mc / --batch: replay the Arnoldi steps as captured HIP graphs "
+                        "(the eager launches are timed beside them)")
     p.add_argument("--no-loop", action="store_true",
                    help="with --mc / --batch: skip the per-crossbar loop comparison")
     p.add_argument("--no-compare", action="store_true",
@@ -83,6 +89,42 @@ def gemm_traffic():
     if vals.get("transform_source_sha256", "").strip() != digest:
         return None
     return int(vals["transform_traffic_bytes_per_application"])
+
+
+def krylov_hbm(st, mn, opts, kms, steps):
+    """HBM roofline of the Krylov part of a solve (the Jacobian products and the
+    Arnoldi orthogonalisation), from the timed kernel classes of the last solve's
+    iteration counts.  Algorithmic bytes per crosspoint at Arnoldi step j: the
+    matvec 40 (read x, D; write y) plus MGS 16 (j + 1) + 32 (read the basis once,
+    read and write w).  Kernel bytes: what the kernels must move, which reads the
+    basis twice in the two-pass form (projections, then update), and once per
+    projection pass in the one-pass-per-vector form."""
+    from paper_2109_07929_amd import binding as B
+    R = opts.restart
+    two_pass = not (opts.flags & B.MCA_FLAG_MGS_PASSES) and R <= 32
+    alg = kern = 0.0
+    for k in st.krylov_history[:st.newton_iters]:
+        while k > 0:
+            c = min(R, k)
+            for j in range(c):
+                alg += 40 + 16 * (j + 1) + 32
+                if two_pass:
+                    kern += (40 + 16 * (j + 1)) + (32 + 16 * (j + 1))
+                else:
+                    # Jacobian with <y, v_0> (56), j + 1 fused MGS passes (64, the last
+                    # without the next projection 48), normalisation (32)
+                    kern += 56 + 64 * j + 48 + 32
+            k -= c
+    ms = (kms[B.MCA_KCLASS_JACOBIAN] + kms[B.MCA_KCLASS_ORTHO]) / steps
+    if ms <= 0:
+        return None
+    a = alg * mn / (ms * 1e-3) / 1e9
+    kb = kern * mn / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "form": "two-pass MGS (compact WY)" if two_pass else "MGS, one pass per vector",
+            "ms_per_solve": round(ms, 4), "algorithmic_bytes_per_solve": alg * mn,
+            "achieved_algorithmic": round(a, 1), "kernel_bytes_per_solve": kern * mn,
+            "achieved_kernel": round(kb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac_algorithmic": round(a / HBM_PEAK_GBS, 4), "frac_kernel": round(kb / HBM_PEAK_GBS, 4)}
 
 
 def cpu_baseline(cb):
@@ -125,27 +167,34 @@ def bench_batched(args):
     v = bt.concat([c.v_in for c in cbs])
     vt = torch.zeros(bt.total, dtype=torch.float64, device=dev)
     vb = torch.zeros_like(vt)
-    opts = B.options(precond=B.MCA_PRECOND_PERMODE, precision=prec)
+    opts = B.options(precond=B.MCA_PRECOND_PERMODE, precision=prec,
+                     flags=B.MCA_FLAG_GRAPH if args.graph else 0)
     ws = bt.workspace(opts)
     stream = torch.cuda.current_stream()
     rows = int(bt.rows[-1])
 
-    def step():
-        return B.mca_solve_batched(bt.handle, bt.count, bt.total, rows, g, v, vt, vb, opts, ws,
-                                   stream)[1]
+    def timed(o):
+        def step():
+            return B.mca_solve_batched(bt.handle, bt.count, bt.total, rows, g, v, vt, vb, o, ws,
+                                       stream)[1]
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            st = step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / args.steps, st
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print(f"# warmup done ({args.warmup} batched solves)", file=sys.stderr, flush=True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        stats = step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    ms_per_step, stats = timed(opts)
     value = count * 1e3 / ms_per_step
+    eager = None
+    if args.graph:
+        ems, _ = timed(B.options(precond=B.MCA_PRECOND_PERMODE, precision=prec))
+        eager = {"ms_per_batch": round(ems, 3), "solves_per_s": round(count * 1e3 / ems, 2)}
+        print(f"# eager launches: {ems:.2f} ms per batch", file=sys.stderr, flush=True)
     newton = [s.newton_iters for s in stats]
     krylov = [s.krylov_iters for s in stats]
     print(f"# batched: {ms_per_step:.2f} ms per batch", file=sys.stderr, flush=True)
@@ -192,10 +241,11 @@ def bench_batched(args):
         "config": {"workload": f"{what} ({sum(sizes)} crosspoints), seed {args.seed}, "
                                f"Newton-FGMRES(30) with a {pname} per-mode preconditioner",
                    "newton_tol": opts.newton_tol, "gmres_tol": opts.gmres_tol,
-                   "setup_ms": round(setup_ms, 1),
+                   "setup_ms": round(setup_ms, 1), "graph": bool(args.graph),
                    "newton_iters": [min(newton), max(newton)],
                    "krylov_iters": [min(krylov), max(krylov)]},
         "per_crossbar_loop": loop,
+        "eager_launches": eager,
         "roofline": None,
     }
     print(json.dumps(out), flush=True)
@@ -301,6 +351,8 @@ def main():
             "approx": B.MCA_PRECOND_APPROX, "jacobi": B.MCA_PRECOND_JACOBI,
             "none": B.MCA_PRECOND_NONE}[args.precond]
     flags = 0 if args.no_timing else B.MCA_FLAG_TIMING
+    if args.mgs_passes:
+        flags |= B.MCA_FLAG_MGS_PASSES
     opts = B.options(precond=form, precision=prec, flags=flags)
     v_t = torch.zeros((m, n), dtype=torch.float64, device=dev)
     v_b = torch.zeros_like(v_t)
@@ -324,6 +376,7 @@ def main():
     ev0.record(stream)
     for _ in range(args.steps):
         st = step()
+        st_last = st
         kms += np.array(st.kernel_ms[:])
         klaunch += np.array(st.kernel_launches[:])
         newton.append(st.newton_iters)
@@ -383,6 +436,9 @@ def main():
         for c, nm in enumerate(names):
             breakdown[nm] = {"ms_per_solve": round(kms[c] / args.steps, 4),
                              "launches_per_solve": int(klaunch[c] // args.steps)}
+    kry_hbm = None
+    if not args.no_timing and kms[B.MCA_KCLASS_JACOBIAN] > 0:
+        kry_hbm = krylov_hbm(st_last, m * n, opts, kms, args.steps)
 
     kind = ("plain FP64 Newton-FGMRES(30)" if prec == B.MCA_PREC_FP64 else
             f"Newton-FGMRES(30) with a {args.precision} preconditioner")
@@ -408,6 +464,7 @@ def main():
                    "newton_iters": newton[-1], "krylov_iters": krylov[-1],
                    "wall_s": round(wall, 3)},
         "roofline": roofline,
+        "krylov_hbm": kry_hbm,
         "kernel_breakdown": breakdown,
     }
     if not args.no_compare:

@@ -84,6 +84,15 @@ typedef int32_t mca_status;
                                      V_t = (G_t + D)^{-1} Y_t, V_b = (G_b + D)^{-1} D V_t,
                                      D = g_dev (tridiagonal solves along every wire);
                                      not with INITIAL_GUESS; m, n <= 2048                  */
+#define MCA_FLAG_GRAPH        16  /* mca_solve_batched only: each Arnoldi step is captured
+                                     once into a HIP graph kept in the batch and replayed
+                                     by later cycles and solves with the same workspace,
+                                     precision and restart length                       */
+#define MCA_FLAG_MGS_PASSES   32  /* Arnoldi orthogonalisation in one pass over the
+                                     vector per basis vector (modified Gram-Schmidt as
+                                     written) instead of the default two passes per step
+                                     (the same projections in compact WY form, restart
+                                     <= 32); the two give the same h up to rounding     */
 
 /* Kernel classes timed under MCA_FLAG_TIMING (mca_stats.kernel_ms / kernel_launches). */
 #define MCA_KCLASS_GEMM      0    /* eigenbasis transforms of the preconditioner          */
@@ -282,6 +291,9 @@ size_t     mca_batch_workspace_bytes(const mca_batch *batch, const mca_options *
  * g_dev, v_in, v_t, v_b: concatenated device arrays (see above); v_t/v_b
  * carry the initial guesses with MCA_FLAG_INITIAL_GUESS.  stats: host array
  * of count records (may be NULL).  MCA_FLAG_TIMING is accepted and ignored.
+ * The batch keeps pinned host counters and, with MCA_FLAG_GRAPH, the captured
+ * Arnoldi steps (dropped when the workspace address, precision, restart
+ * length or uploaded block change): calls on one batch must not overlap.
  * Returns MCA_OK when every crossbar converged, else the status of the first
  * crossbar that did not (the per-crossbar outcome is in the residual
  * history of stats).  Synchronises stream.

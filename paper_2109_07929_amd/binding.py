@@ -40,6 +40,8 @@ MCA_FLAG_INITIAL_GUESS = 1
 MCA_FLAG_TIMING = 2
 MCA_FLAG_GUESS_FALLBACK = 4
 MCA_FLAG_SWEEP_START = 8
+MCA_FLAG_GRAPH = 16
+MCA_FLAG_MGS_PASSES = 32
 MCA_KCLASS_GEMM = 0
 MCA_KCLASS_JACOBIAN = 1
 MCA_KCLASS_ORTHO = 2

@@ -232,6 +232,152 @@ __global__ __launch_bounds__(TPB) void bk_mgs_step(
     if (threadIdx.x == 0) pout[blockIdx.x] = acc[0];
 }
 
+// Two-pass Gram-Schmidt of Arnoldi step j for every crossbar in its cycle
+// (modified Gram-Schmidt in compact WY form, as in mca_solve): the basis is
+// unnormalised (slot q holds u_q, v_q = sig_q u_q), the first kernel forms
+// w = sig_j J z~_j with the projections on the basis, the second w -= V h
+// with the products of the new vector with the basis.  After each pass a
+// kernel with one block per crossbar reduces that crossbar's partials and
+// does its small dense work.  Partials of crossbar b, value q, its block t:
+//   p[(blk0 * NVAL) + q * nblk + t]   (NVAL = kGsMaxV or kGsMaxV + 1).
+struct BGs {
+    const BInst *I;
+    const int2 *bt;
+    int *ctl;                   // per crossbar: stop flag first (stride 4)
+    const double *D;
+    const double *Z;            // slot j of Z: the preconditioned u_j
+    double *W;                  // slot j + 1 of V
+    const double *V;            // slot 0 of V
+    size_t len;                 // slot stride
+    double *sig;                // per crossbar R + 1 scales
+    double *L;                  // per crossbar (R + 1)^2, row-major
+    double *H;                  // per crossbar hsize, column-major ld ldh
+    int R, ldh, hsize, j;
+    double *p1, *p2;
+    double *g, *cs, *sn;        // Givens state, per crossbar
+    const BState *S;
+    int *run;                   // per crossbar: 1 while its cycle runs
+};
+
+template <int MAXV>
+__global__ __launch_bounds__(TPB) void bk_jacobian_proj(BGs a)
+{
+    int b, k0, k1;
+    if (!block_range(a.I, a.bt, nullptr, b, k0, k1)) return;
+    if (a.ctl[4 * b]) return;
+    const BInst in = a.I[b];
+    const int j = a.j, nv = j + 1, R1 = a.R + 1;
+    const size_t mn = (size_t)in.m * in.n, base = 2 * in.ox;
+    const double *zt = a.Z + base, *zb = zt + mn;
+    const double *d = a.D + in.ox;
+    const double *sg = a.sig + (size_t)b * R1;
+    const double sj = sg[j];
+    double acc[MAXV];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) acc[q] = 0.0;
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+        double y1, y2;
+        jac_point(in, zt, zb, d[k], k, y1, y2);
+        y1 *= sj;
+        y2 *= sj;
+        a.W[base + k] = y1;
+        a.W[base + mn + k] = y2;
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+            if (q < nv)
+                acc[q] += y1 * a.V[q * a.len + base + k] + y2 * a.V[q * a.len + base + mn + k];
+    }
+    block_sum<MAXV>(acc);
+    const int t = blockIdx.x - in.blk0;
+    double *p = a.p1 + (size_t)in.blk0 * kGsMaxV;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+            if (q < nv) p[(size_t)q * in.nblk + t] = acc[q];
+    }
+}
+
+// One block per crossbar: s_q = sig_q <w, u_q> from the crossbar's partials,
+// then (I + L) h = s by forward substitution; h to the crossbar's H column j.
+__global__ __launch_bounds__(TPB) void bk_gs_coef(BGs a)
+{
+    const int b = blockIdx.x;
+    if (a.ctl[4 * b]) return;
+    const BInst in = a.I[b];
+    const int j = a.j, nv = j + 1, R1 = a.R + 1;
+    const double *p = a.p1 + (size_t)in.blk0 * kGsMaxV;
+    const double *sg = a.sig + (size_t)b * R1;
+    __shared__ double sv[kGsMaxV];
+    __shared__ double Ls[kGsMaxV][kGsMaxV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = wave; q < nv; q += TPB / 64) {
+        double x = 0.0;
+        for (int u = lane; u < in.nblk; u += 64) x += p[(size_t)q * in.nblk + u];
+        x = dev::wave_sum(x);
+        if (lane == 0) sv[q] = sg[q] * x;
+    }
+    const double *Lb = a.L + (size_t)b * R1 * R1;
+    for (int e = threadIdx.x; e < nv * kGsMaxV; e += TPB) {
+        const int r = e / kGsMaxV, k = e - r * kGsMaxV;
+        if (k < r) Ls[r][k] = Lb[(size_t)r * R1 + k];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    double *hcol = a.H + (size_t)b * a.hsize + (size_t)j * a.ldh;
+    double h = 0.0;     // lane k holds h_k
+    for (int r = 0; r <= j; ++r) {
+        double x = (lane < r) ? Ls[r][lane] * h : 0.0;
+        x = dev::wave_sum(x);
+        const double hr = sv[r] - x;
+        if (lane == r) h = hr;
+        if (lane == 0) hcol[r] = hr;
+    }
+}
+
+template <int MAXV>
+__global__ __launch_bounds__(TPB) void bk_gs_update(BGs a)
+{
+    int b, k0, k1;
+    if (!block_range(a.I, a.bt, nullptr, b, k0, k1)) return;
+    if (a.ctl[4 * b]) return;
+    const BInst in = a.I[b];
+    const int j = a.j, nv = j + 1, R1 = a.R + 1;
+    const size_t mn = (size_t)in.m * in.n, base = 2 * in.ox;
+    double *sg = a.sig + (size_t)b * R1;
+    double *hcol = a.H + (size_t)b * a.hsize + (size_t)j * a.ldh;
+    double c[MAXV], acc[MAXV + 1];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) c[q] = (q < nv) ? hcol[q] * sg[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q <= MAXV; ++q) acc[q] = 0.0;
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            const size_t e = base + l * mn + k;
+            double vq[MAXV];
+            double x = a.W[e];
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q) {
+                vq[q] = (q < nv) ? a.V[q * a.len + e] : 0.0;
+                x -= c[q] * vq[q];
+            }
+            a.W[e] = x;
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q) acc[q] += x * vq[q];
+            acc[MAXV] += x * x;
+        }
+    }
+    block_sum<MAXV + 1>(acc);
+    const int t = blockIdx.x - in.blk0;
+    double *p = a.p2 + (size_t)in.blk0 * (kGsMaxV + 1);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+            if (q < nv) p[(size_t)q * in.nblk + t] = acc[q];
+        p[(size_t)nv * in.nblk + t] = acc[MAXV];
+    }
+}
+
 __global__ __launch_bounds__(TPB) void bk_normalize(
     const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *__restrict__ ctl,
     double *__restrict__ W, const double *__restrict__ pin, double *__restrict__ H, int ldh,
@@ -445,20 +591,26 @@ __global__ void bk_newton_begin(const BInst *__restrict__ I, int count, BState *
 }
 
 // sum of per-block counters (one thread)
-__global__ void bk_sum_counters(const int *__restrict__ c, int n, int *__restrict__ out)
+// out[0] = sum of c[0..n); with host_out (the device address of pinned host
+// memory) also written through to the host.
+__global__ void bk_sum_counters(const int *__restrict__ c, int n, int *__restrict__ out,
+                                int *__restrict__ host_out)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int s = 0;
     for (int i = 0; i < n; ++i) s += c[i];
     out[0] = s;
+    if (host_out) __hip_atomic_store(host_out, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // GMRES cycle start for crossbars in their Newton step's GMRES solve
 __global__ void bk_cycle_init(int count, BState *__restrict__ S, int *__restrict__ ctl,
-                              double *__restrict__ g, int R, int max_krylov)
+                              double *__restrict__ g, int R, int max_krylov,
+                              double *__restrict__ sig)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= count) return;
+    if (sig) sig[(size_t)b * (R + 1)] = 1.0;     // v_0 is stored normalised
     BState &s = S[b];
     s.restart = 0;
     const bool run = s.gm_todo && s.kry_step < max_krylov;
@@ -471,51 +623,58 @@ __global__ void bk_cycle_init(int count, BState *__restrict__ S, int *__restrict
 }
 
 // Givens rotations of Hessenberg column j, per running crossbar.
+// Givens update of crossbar b's Hessenberg column j (one thread); returns 1
+// while the crossbar's cycle keeps running.
+__device__ int batch_givens(int b, const BState *__restrict__ S, double *__restrict__ H, int ldh,
+                            int hsize, int j, double *__restrict__ g, double *__restrict__ cs,
+                            double *__restrict__ sn, int R, int *__restrict__ ctl)
+{
+    int *c = ctl + 4 * b;
+    if (c[0]) return 0;
+    double *h = H + (size_t)b * hsize + (size_t)j * ldh;
+    double *gb = g + (size_t)b * (R + 1), *cb = cs + (size_t)b * R, *sb = sn + (size_t)b * R;
+    bool bad = false;
+    for (int i = 0; i <= j + 1; ++i) bad = bad || !isfinite(h[i]);
+    if (bad) {
+        c[0] = 1;
+        c[2] = CYCLE_NONFINITE;
+    } else {
+        for (int i = 0; i < j; ++i) {
+            const double t = cb[i] * h[i] + sb[i] * h[i + 1];
+            h[i + 1] = -sb[i] * h[i] + cb[i] * h[i + 1];
+            h[i] = t;
+        }
+        const double hn = h[j + 1];
+        const double r = hypot(h[j], hn);
+        if (r == 0.0) {
+            c[0] = 1;
+            c[2] = CYCLE_BREAKDOWN;
+        } else {
+            cb[j] = h[j] / r;
+            sb[j] = hn / r;
+            h[j] = r;
+            h[j + 1] = 0.0;
+            gb[j + 1] = -sb[j] * gb[j];
+            gb[j] = cb[j] * gb[j];
+            c[1] = j + 1;
+            if (fabs(gb[j + 1]) <= S[b].abs_tol) {
+                c[0] = 1;
+                c[2] = CYCLE_CONVERGED;
+            } else if (j + 1 >= c[3]) {
+                c[0] = 1;   // iteration budget of this Newton step spent
+            }
+        }
+    }
+    return c[0] ? 0 : 1;
+}
+
 __global__ void bk_givens(int count, const BState *__restrict__ S, double *__restrict__ H,
                           int ldh, int hsize, int j, double *__restrict__ g,
                           double *__restrict__ cs, double *__restrict__ sn, int R,
                           int *__restrict__ ctl, int *__restrict__ counter)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    int running = 0;
-    if (b < count && !ctl[4 * b]) {
-        int *c = ctl + 4 * b;
-        double *h = H + (size_t)b * hsize + (size_t)j * ldh;
-        double *gb = g + (size_t)b * (R + 1), *cb = cs + (size_t)b * R, *sb = sn + (size_t)b * R;
-        bool bad = false;
-        for (int i = 0; i <= j + 1; ++i) bad = bad || !isfinite(h[i]);
-        if (bad) {
-            c[0] = 1;
-            c[2] = CYCLE_NONFINITE;
-        } else {
-            for (int i = 0; i < j; ++i) {
-                const double t = cb[i] * h[i] + sb[i] * h[i + 1];
-                h[i + 1] = -sb[i] * h[i] + cb[i] * h[i + 1];
-                h[i] = t;
-            }
-            const double hn = h[j + 1];
-            const double r = hypot(h[j], hn);
-            if (r == 0.0) {
-                c[0] = 1;
-                c[2] = CYCLE_BREAKDOWN;
-            } else {
-                cb[j] = h[j] / r;
-                sb[j] = hn / r;
-                h[j] = r;
-                h[j + 1] = 0.0;
-                gb[j + 1] = -sb[j] * gb[j];
-                gb[j] = cb[j] * gb[j];
-                c[1] = j + 1;
-                if (fabs(gb[j + 1]) <= S[b].abs_tol) {
-                    c[0] = 1;
-                    c[2] = CYCLE_CONVERGED;
-                } else if (j + 1 >= c[3]) {
-                    c[0] = 1;   // iteration budget of this Newton step spent
-                }
-            }
-        }
-        running = c[0] ? 0 : 1;
-    }
+    const int running = (b < count) ? batch_givens(b, S, H, ldh, hsize, j, g, cs, sn, R, ctl) : 0;
     __shared__ int sh[1024];
     sh[threadIdx.x] = running;
     __syncthreads();
@@ -526,11 +685,47 @@ __global__ void bk_givens(int count, const BState *__restrict__ S, double *__res
     }
 }
 
+// One block per crossbar after the second pass: ||x|| and <x, u_q> from the
+// partials give H[j+1][j], sig_{j+1} and row j + 1 of L; then the crossbar's
+// Givens update.  run[b] = 1 while its cycle keeps running.
+__global__ __launch_bounds__(TPB) void bk_gs_finish(BGs a)
+{
+    const int b = blockIdx.x;
+    if (a.ctl[4 * b]) {
+        if (threadIdx.x == 0) a.run[b] = 0;
+        return;
+    }
+    const BInst in = a.I[b];
+    const int j = a.j, nv = j + 1, R1 = a.R + 1;
+    const double *p = a.p2 + (size_t)in.blk0 * (kGsMaxV + 1);
+    double *sg = a.sig + (size_t)b * R1;
+    __shared__ double sv[kGsMaxV + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = wave; q <= nv; q += TPB / 64) {
+        double x = 0.0;
+        for (int u = lane; u < in.nblk; u += 64) x += p[(size_t)q * in.nblk + u];
+        x = dev::wave_sum(x);
+        if (lane == 0) sv[q] = x;
+    }
+    __syncthreads();
+    const double nrm = sqrt(sv[nv]);
+    const double inv = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+    // row j + 1 of L: <v_{j+1}, v_q> = sig_q <x, u_q> / ||x||
+    if (threadIdx.x < nv)
+        a.L[(size_t)b * R1 * R1 + (size_t)(j + 1) * R1 + threadIdx.x] =
+            sv[threadIdx.x] * sg[threadIdx.x] * inv;
+    if (threadIdx.x == 0) {
+        sg[j + 1] = inv;
+        a.H[(size_t)b * a.hsize + (size_t)j * a.ldh + j + 1] = nrm;
+        a.run[b] = batch_givens(b, a.S, a.H, a.ldh, a.hsize, j, a.g, a.cs, a.sn, a.R, a.ctl);
+    }
+}
+
 // End of a GMRES cycle: least squares, bookkeeping, restart decision.
 __global__ void bk_cycle_end(int count, BState *__restrict__ S, const double *__restrict__ H,
                              int ldh, int hsize, const double *__restrict__ g, int R,
                              const int *__restrict__ ctl, double *__restrict__ Y, int max_krylov,
-                             int *__restrict__ counter)
+                             int *__restrict__ counter, const double *__restrict__ sig)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     int again = 0;
@@ -548,6 +743,8 @@ __global__ void bk_cycle_end(int count, BState *__restrict__ S, const double *__
                 for (int cc = i + 1; cc < k; ++cc) t -= Hb[(size_t)cc * ldh + i] * y[cc];
                 y[i] = t / Hb[(size_t)i * ldh + i];
             }
+            if (sig)   // an unnormalised basis: the update takes y_i sig_i
+                for (int i = 0; i < k; ++i) y[i] *= sig[(size_t)b * (R + 1) + i];
             s.upd = k;
             s.kry_step += k;
             s.krylov += k;
@@ -684,6 +881,34 @@ __global__ void bk_ls_finish(int count, BState *__restrict__ S)
 int cblocks(int count) { return (count + 1023) / 1024; }
 
 }  // namespace
+
+// Arnoldi steps captured as HIP graphs (MCA_FLAG_GRAPH): one executable graph
+// per step index j (step j runs j + 1 projection passes), built on first use
+// and replayed by later cycles and later solves.  The kernels' pointers
+// depend on the workspace address, the precision, the restart length and the
+// uploaded batch block, so a change of any of them drops the cache.
+struct StepGraphs {
+    void *ws = nullptr;
+    const void *dev = nullptr;
+    int precision = -1, restart = 0;
+    hipStream_t cap = nullptr;          // private stream that the steps are captured on
+    std::vector<hipGraphExec_t> exec;
+    void clear()
+    {
+        for (hipGraphExec_t &e : exec)
+            if (e) (void)hipGraphExecDestroy(e);
+        exec.clear();
+        ws = nullptr;
+        dev = nullptr;
+    }
+    void release()
+    {
+        clear();
+        if (cap) (void)hipStreamDestroy(cap);
+        cap = nullptr;
+    }
+};
+
 }  // namespace mca
 
 // ====================================================================== host
@@ -704,6 +929,10 @@ struct mca_batch {
     int4 *d_tiles[4] = {};
     int ntiles[4] = {};
     int tile = 64;                          // tile edge of the grouped products
+    // state kept between solves: pinned counters read back by the host, and
+    // the captured Arnoldi steps (calls on one batch must not overlap)
+    mutable int *host = nullptr;
+    mutable mca::StepGraphs graphs;
 };
 
 namespace mca {
@@ -788,6 +1017,8 @@ BatchLayout batch_layout(const mca_batch *B, void *base)
 struct BatchWs {
     double *V, *Z, *X, *Vc, *T, *F, *Ft, *D, *Dt;
     double *pa, *pb;
+    double *pg1, *pg2, *sig, *Lg;   // two-pass Gram-Schmidt
+    int *run;
     double *H, *g, *cs, *sn, *Y;
     int *ctl, *counter;
     BState *S;
@@ -814,6 +1045,11 @@ BatchWs batch_ws(const mca_batch *B, const mca_options *o, void *base)
     w.Dt = c.take<double>(len / 2);
     w.pa = c.take<double>(2 * nblk);
     w.pb = c.take<double>(2 * nblk);
+    w.pg1 = c.take<double>(nblk * kGsMaxV);
+    w.pg2 = c.take<double>(nblk * (kGsMaxV + 1));
+    w.sig = c.take<double>(cnt * (R + 1));
+    w.Lg = c.take<double>(cnt * (R + 1) * (R + 1));
+    w.run = c.take<int>(cnt);
     w.H = c.take<double>(cnt * (R + 1) * R);
     w.g = c.take<double>(cnt * (R + 1));
     w.cs = c.take<double>(cnt * R);
@@ -858,7 +1094,7 @@ mca_status batch_options_ok(const mca_options *o)
         o->precision != MCA_PREC_BF16)
         return MCA_ERR_INVALID_ARG;
     if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING | MCA_FLAG_GUESS_FALLBACK |
-                     MCA_FLAG_SWEEP_START))
+                     MCA_FLAG_SWEEP_START | MCA_FLAG_GRAPH | MCA_FLAG_MGS_PASSES))
         return MCA_ERR_INVALID_ARG;
     if ((o->flags & MCA_FLAG_INITIAL_GUESS) && (o->flags & MCA_FLAG_SWEEP_START))
         return MCA_ERR_INVALID_ARG;
@@ -956,6 +1192,8 @@ void mca_batch_destroy(mca_batch *B)
 {
     if (!B) return;
     for (mca_plan *p : B->plans) mca_plan_destroy(p);
+    B->graphs.release();
+    if (B->host) (void)hipHostFree(B->host);
     delete B;
 }
 
@@ -977,6 +1215,7 @@ mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *str
     if (bytes < B->dev_bytes) return MCA_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t cnt = B->geoms.size();
+    B->graphs.clear();
     std::vector<char> img(B->dev_bytes);
     BatchLayout H = batch_layout(B, img.data());   // host image, same offsets
     BatchLayout D = batch_layout(B, dev_buf);      // device addresses
@@ -1090,12 +1329,21 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     const int cb = cblocks(cnt), ct = std::min(cnt, 1024);
     const int *actf = &w.S[0].active, *lsf = &w.S[0].ls_todo, *rsf = &w.S[0].restart;
     const int *accf = &w.S[0].accept;
-    int *host = nullptr;
-    MCA_BTRY(hipHostMalloc((void **)&host, 4096 * sizeof(int), hipHostMallocDefault));
-    struct HostFree {
-        int *p;
-        ~HostFree() { (void)hipHostFree(p); }
-    } hf{host};
+    if (!B->host) MCA_BTRY(hipHostMalloc((void **)&B->host, 4096 * sizeof(int), hipHostMallocDefault));
+    int *host = B->host, *host_dev = nullptr;
+    MCA_BTRY(hipHostGetDevicePointer((void **)&host_dev, host, 0));
+    const bool graph = (o.flags & MCA_FLAG_GRAPH) != 0;
+    StepGraphs &G = B->graphs;
+    if (graph) {
+        if (G.ws != ws || G.dev != B->dev_buf || G.precision != o.precision || G.restart != R)
+            G.clear();
+        if (!G.cap) MCA_BTRY(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+        G.ws = ws;
+        G.dev = B->dev_buf;
+        G.precision = o.precision;
+        G.restart = R;
+        G.exec.resize(R, nullptr);
+    }
     hipEvent_t ev[2] = {nullptr, nullptr};
     struct EvFree {
         hipEvent_t *e;
@@ -1109,7 +1357,8 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
 
     // read the sum of the per-block counters written by the last control kernel
     auto count_now = [&](int *out) -> mca_status {
-        hipLaunchKernelGGL(bk_sum_counters, dim3(1), dim3(64), 0, s, w.counter, cb, w.counter + cb);
+        hipLaunchKernelGGL(bk_sum_counters, dim3(1), dim3(64), 0, s, w.counter, cb, w.counter + cb,
+                           (int *)nullptr);
         MCA_BTRY(hipGetLastError());
         MCA_BTRY(hipMemcpyAsync(host, w.counter + cb, sizeof(int), hipMemcpyDeviceToHost, s));
         MCA_BTRY(hipStreamSynchronize(s));
@@ -1132,6 +1381,77 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     gc.a_inst = &w.S[0].a;
     gc.a_stride = (int)(sizeof(BState) / sizeof(double));
     gc.ctl = w.ctl;
+
+    const bool two_pass = !(o.flags & MCA_FLAG_MGS_PASSES) && R <= kGsMaxV;
+    BGs gs{};
+    gs.I = B->d_inst;
+    gs.bt = B->d_btab;
+    gs.ctl = w.ctl;
+    gs.D = w.D;
+    gs.V = w.V;
+    gs.len = len;
+    gs.sig = w.sig;
+    gs.L = w.Lg;
+    gs.H = w.H;
+    gs.R = R;
+    gs.ldh = ldh;
+    gs.hsize = hsize;
+    gs.p1 = w.pg1;
+    gs.p2 = w.pg2;
+    gs.g = w.g;
+    gs.cs = w.cs;
+    gs.sn = w.sn;
+    gs.S = w.S;
+    gs.run = w.run;
+    // Arnoldi step j of every crossbar still in its cycle: preconditioner,
+    // Jacobian product fused with <w, v_0>, the projection passes, the
+    // normalisation, the Givens update, and the count of running cycles
+    // written to host[16 + j]
+    auto enqueue_step = [&](int j, hipStream_t q) -> hipError_t {
+        double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
+        double *wv = w.V + (size_t)(j + 1) * len;
+        GroupedChain c = gc;
+        c.r = vj;
+        c.z = zj;
+        hipError_t e = launch_precond_lowprec_grouped(o.precision, c, q);
+        if (e != hipSuccess) return e;
+        if (two_pass) {
+            BGs a = gs;
+            a.Z = zj;
+            a.W = wv;
+            a.j = j;
+            const int nv = j + 1;
+            if (nv <= 4) hipLaunchKernelGGL(bk_jacobian_proj<4>, gridB, blk, 0, q, a);
+            else if (nv <= 8) hipLaunchKernelGGL(bk_jacobian_proj<8>, gridB, blk, 0, q, a);
+            else if (nv <= 16) hipLaunchKernelGGL(bk_jacobian_proj<16>, gridB, blk, 0, q, a);
+            else hipLaunchKernelGGL(bk_jacobian_proj<32>, gridB, blk, 0, q, a);
+            hipLaunchKernelGGL(bk_gs_coef, dim3(cnt), blk, 0, q, a);
+            if (nv <= 4) hipLaunchKernelGGL(bk_gs_update<4>, gridB, blk, 0, q, a);
+            else if (nv <= 8) hipLaunchKernelGGL(bk_gs_update<8>, gridB, blk, 0, q, a);
+            else if (nv <= 16) hipLaunchKernelGGL(bk_gs_update<16>, gridB, blk, 0, q, a);
+            else hipLaunchKernelGGL(bk_gs_update<32>, gridB, blk, 0, q, a);
+            hipLaunchKernelGGL(bk_gs_finish, dim3(cnt), blk, 0, q, a);
+            hipLaunchKernelGGL(bk_sum_counters, dim3(1), dim3(64), 0, q, w.run, cnt,
+                               w.counter + cb + 1, host_dev + 16 + j);
+        } else {
+            hipLaunchKernelGGL(bk_jacobian, gridB, blk, 0, q, B->d_inst, B->d_btab, w.ctl, w.D, zj,
+                               wv, w.V, w.pa);
+            double *pin = w.pa, *pout = w.pb;
+            for (int i = 0; i <= j; ++i) {
+                const double *vn = (i < j) ? w.V + (size_t)(i + 1) * len : nullptr;
+                hipLaunchKernelGGL(bk_mgs_step, gridB, blk, 0, q, B->d_inst, B->d_btab, w.ctl, wv,
+                                   w.V + (size_t)i * len, vn, pin, pout, w.H, ldh, hsize, j, i);
+                std::swap(pin, pout);
+            }
+            hipLaunchKernelGGL(bk_normalize, gridB, blk, 0, q, B->d_inst, B->d_btab, w.ctl, wv, pin,
+                               w.H, ldh, hsize, j, j + 1);
+            hipLaunchKernelGGL(bk_givens, dim3(cb), dim3(ct), 0, q, cnt, w.S, w.H, ldh, hsize, j,
+                               w.g, w.cs, w.sn, R, w.ctl, w.counter);
+            hipLaunchKernelGGL(bk_sum_counters, dim3(1), dim3(64), 0, q, w.counter, cb,
+                               w.counter + cb + 1, host_dev + 16 + j);
+        }
+        return hipGetLastError();
+    };
 
     // initial state and iterate
     hipLaunchKernelGGL(bk_init, dim3(cnt), blk, 0, s, B->d_inst, cnt, v_in, w.S);
@@ -1179,33 +1499,32 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
                            (const double *)nullptr, w.V);
         for (;;) {
             hipLaunchKernelGGL(bk_cycle_init, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.ctl, w.g, R,
-                               o.max_krylov);
+                               o.max_krylov, two_pass ? w.sig : nullptr);
             int last = -1;
             for (int j = 0; j < R; ++j) {
-                double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
-                double *wv = w.V + (size_t)(j + 1) * len;
-                gc.r = vj;
-                gc.z = zj;
-                MCA_BTRY(launch_precond_lowprec_grouped(o.precision, gc, s));
-                hipLaunchKernelGGL(bk_jacobian, gridB, blk, 0, s, B->d_inst, B->d_btab, w.ctl,
-                                   w.D, zj, wv, w.V, w.pa);
-                double *pin = w.pa, *pout = w.pb;
-                for (int i = 0; i <= j; ++i) {
-                    const double *vn = (i < j) ? w.V + (size_t)(i + 1) * len : nullptr;
-                    hipLaunchKernelGGL(bk_mgs_step, gridB, blk, 0, s, B->d_inst, B->d_btab, w.ctl,
-                                       wv, w.V + (size_t)i * len, vn, pin, pout, w.H, ldh, hsize,
-                                       j, i);
-                    std::swap(pin, pout);
+                if (graph) {
+                    hipGraphExec_t &ex = G.exec[j];
+                    if (!ex) {
+                        MCA_BTRY(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+                        const hipError_t e1 = enqueue_step(j, G.cap);
+                        hipGraph_t gph = nullptr;
+                        const hipError_t e2 = hipStreamEndCapture(G.cap, &gph);
+                        hipError_t e3 = hipErrorInvalidValue;
+                        if (e1 == hipSuccess && e2 == hipSuccess && gph)
+                            e3 = hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0);
+                        if (gph) (void)hipGraphDestroy(gph);
+                        if (e3 != hipSuccess) {
+                            ex = nullptr;
+                            const hipError_t e = (e1 != hipSuccess) ? e1 : (e2 != hipSuccess) ? e2 : e3;
+                            set_hip_error("capture of an Arnoldi step", e);
+                            (void)hipGetLastError();
+                            return MCA_ERR_HIP;
+                        }
+                    }
+                    MCA_BTRY(hipGraphLaunch(ex, s));
+                } else {
+                    MCA_BTRY(enqueue_step(j, s));
                 }
-                hipLaunchKernelGGL(bk_normalize, gridB, blk, 0, s, B->d_inst, B->d_btab, w.ctl, wv,
-                                   pin, w.H, ldh, hsize, j, j + 1);
-                hipLaunchKernelGGL(bk_givens, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.H, ldh, hsize, j,
-                                   w.g, w.cs, w.sn, R, w.ctl, w.counter);
-                hipLaunchKernelGGL(bk_sum_counters, dim3(1), dim3(64), 0, s, w.counter, cb,
-                                   w.counter + cb + 1);
-                MCA_BTRY(hipGetLastError());
-                MCA_BTRY(hipMemcpyAsync(host + 16 + j, w.counter + cb + 1, sizeof(int),
-                                        hipMemcpyDeviceToHost, s));
                 MCA_BTRY(hipEventRecord(ev[j & 1], s));
                 last = j;
                 if (j > 0) {
@@ -1215,7 +1534,8 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
             }
             if (last >= 0) MCA_BTRY(hipEventSynchronize(ev[last & 1]));
             hipLaunchKernelGGL(bk_cycle_end, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.H, ldh, hsize, w.g,
-                               R, w.ctl, w.Y, o.max_krylov, w.counter);
+                               R, w.ctl, w.Y, o.max_krylov, w.counter,
+                               two_pass ? (const double *)w.sig : nullptr);
             hipLaunchKernelGGL(bk_update, gridB, blk, 0, s, B->d_inst, B->d_btab, w.S, w.Z, len, w.Y,
                                R, w.X);
             hipLaunchKernelGGL(bk_after_update, dim3(cb), dim3(ct), 0, s, cnt, w.S);

@@ -256,63 +256,278 @@ __global__ __launch_bounds__(TPB) void k_normalize(
     }
 }
 
+// ----------------------------- two-pass Gram-Schmidt (MGS, compact WY form)
+// Modified Gram-Schmidt applies the elementary projections I - v_k v_k^T,
+// k = 0..j, one after another.  Their product equals I - V T V^T with
+// T^{-1} = I + L, L the strictly lower triangle of V^T V (for unit v_k), and
+// MGS's coefficients are h = T (V^T w).  So one pass over the basis gives the
+// projections s = V^T w, a forward substitution (I + L) h = s gives MGS's h,
+// and a second pass forms w - V h.  L grows by one row per step: the second
+// pass also leaves the products of the new vector with the basis.
+//
+// The basis is kept unnormalised: slot q holds u_q with v_q = sig_q u_q
+// (sig_q = 1 / ||u_q||, sig_0 = 1).  The preconditioner is linear, so it is
+// applied to u_j, and the Jacobian product is scaled by sig_j instead;
+// the least-squares coefficients take the factors sig_j before the update.
+//
+// The two streaming passes leave per-block partials (value q at
+// partials[q * kGsBlocks + block]); a one-block kernel after each sums them
+// in a fixed order and does the small dense work of the step.
+
+// Sums of nval values' partials (kGsBlocks = 1024 each, value q at
+// p[q * 1024 + block]) by a block of 1024 threads: thread t loads partial t of
+// every value at once, then a fixed-order tree; out[q] in LDS.
+__device__ __forceinline__ void sum_partials_1024(const double *__restrict__ p, int nval,
+                                                  double *out)
+{
+    static_assert(kGsBlocks == 1024, "one thread per partial");
+    __shared__ double red[kGsMaxV + 1][16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double v[kGsMaxV + 1];
+#pragma unroll
+    for (int q = 0; q <= kGsMaxV; ++q) v[q] = (q < nval) ? p[(size_t)q * kGsBlocks + t] : 0.0;
+#pragma unroll
+    for (int q = 0; q <= kGsMaxV; ++q) {
+        if (q < nval) {
+            const double x = dev::wave_sum(v[q]);
+            if (lane == 0) red[q][wave] = x;
+        }
+    }
+    __syncthreads();
+    if (t < nval) {
+        double x = 0.0;
+        for (int w = 0; w < 16; ++w) x += red[t][w];
+        out[t] = x;
+    }
+    __syncthreads();
+}
+
+// Copy of the cycle control block (stop flag, steps done, reason) to the
+// host's pinned snapshot slot, written through to memory.
+__device__ __forceinline__ void write_snapshot(int *snap, const int *ctl)
+{
+    for (int i = 0; i < 4; ++i)
+        __hip_atomic_store(snap + i, ctl[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Givens update of Hessenberg column j: apply rotations 0..j-1, then the
+// rotation that zeroes h[j+1]; update g and stop the cycle when
+// |g[j+1]| <= abs_tol (the GMRES residual).  Every thread of the block calls
+// it (the column and the rotations are staged in LDS by all of them); thread
+// 0 does the arithmetic.  hlast: the value of h[j+1].
+__device__ void givens_block(double *__restrict__ H, int ldh, int j, double hlast,
+                             double *__restrict__ g, double *__restrict__ cs,
+                             double *__restrict__ sn, double abs_tol, int *__restrict__ ctl,
+                             double *__restrict__ resid)
+{
+    __shared__ double hs[MCA_MAX_RESTART + 1], cz[MCA_MAX_RESTART], sz[MCA_MAX_RESTART];
+    double *h = H + (size_t)j * ldh;
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        hs[i] = h[i];
+        if (i < j) {
+            cz[i] = cs[i];
+            sz[i] = sn[i];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double hj1 = hlast;
+    bool bad = !isfinite(hj1);
+    for (int i = 0; i <= j; ++i) bad = bad || !isfinite(hs[i]);
+    if (bad) {
+        ctl[0] = 1;
+        ctl[2] = CYCLE_NONFINITE;
+        return;
+    }
+    for (int i = 0; i < j; ++i) {   // rotation i mixes rows i and i + 1 <= j
+        const double t = cz[i] * hs[i] + sz[i] * hs[i + 1];
+        hs[i + 1] = -sz[i] * hs[i] + cz[i] * hs[i + 1];
+        hs[i] = t;
+    }
+    for (int i = 0; i < j; ++i) h[i] = hs[i];
+    const double r = hypot(hs[j], hj1);
+    if (r == 0.0) {
+        h[j] = hs[j];
+        h[j + 1] = hj1;
+        ctl[0] = 1;
+        ctl[2] = CYCLE_BREAKDOWN;
+        return;
+    }
+    const double c = hs[j] / r, sv = hj1 / r;
+    cs[j] = c;
+    sn[j] = sv;
+    h[j] = r;
+    h[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sv * gj;
+    g[j] = c * gj;
+    ctl[1] = j + 1;
+    resid[j] = fabs(sv * gj);
+    if (fabs(sv * gj) <= abs_tol) {   // includes hj1 == 0 (invariant subspace)
+        ctl[0] = 1;
+        ctl[2] = CYCLE_CONVERGED;
+    }
+}
+
+// w = sig_j J z~_j (eq. (J); z~_j the preconditioned u_j) with the partials of
+// <w, u_q>, q <= j.
+template <int MAXV>
+__global__ __launch_bounds__(TPB) void k_jacobian_proj(GsStep a)
+{
+    if (*a.ctl) return;
+    const int m = a.m, n = a.n, j = a.j, nv = j + 1;
+    const size_t mn = (size_t)m * n;
+    const double sj = a.sig[j];
+    double acc[MAXV];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) acc[q] = 0.0;
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
+        const int i = (int)(k / n), jj = (int)(k - (size_t)i * n);
+        const double t = a.zt[k], b = a.zb[k];
+        const double st = wire_apply(a.top, jj, t, (jj > 0) ? a.zt[k - 1] : 0.0,
+                                     (jj + 1 < n) ? a.zt[k + 1] : 0.0);
+        const double sb = wire_apply(a.bot, i, b, (i > 0) ? a.zb[k - n] : 0.0,
+                                     (i + 1 < m) ? a.zb[k + n] : 0.0);
+        const double c = a.d[k] * (t - b);
+        const double y1 = sj * (st + c), y2 = sj * (sb - c);
+        a.w[k] = y1;
+        a.w[mn + k] = y2;
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+            if (q < nv) acc[q] += y1 * a.V[q * a.ldv + k] + y2 * a.V[q * a.ldv + mn + k];
+    }
+    block_sum<MAXV>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+            if (q < nv) a.p1[(size_t)q * gridDim.x + blockIdx.x] = acc[q];
+    }
+}
+
+// One block of 1024 threads: s_q = sig_q <w, u_q> from the partials, then
+// (I + L) h = s by forward substitution with rows 0..j of L; h to H column j.
+__global__ __launch_bounds__(1024) void k_gs_coef(GsStep a)
+{
+    if (*a.ctl) return;
+    const int j = a.j, nv = j + 1;
+    __shared__ double sv[kGsMaxV + 1];
+    __shared__ double Ls[kGsMaxV][kGsMaxV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e = threadIdx.x; e < nv * kGsMaxV; e += 1024) {
+        const int r = e / kGsMaxV, k = e - r * kGsMaxV;
+        if (k < r) Ls[r][k] = a.L[(size_t)r * a.ldl + k];
+    }
+    sum_partials_1024(a.p1, nv, sv);
+    if (wave != 0) return;
+    if (lane < nv) sv[lane] *= a.sig[lane];   // s_q = sig_q <w, u_q>
+    double h = 0.0;     // lane k holds h_k
+    for (int r = 0; r <= j; ++r) {
+        // h_r = s_r - sum_{k < r} L[r][k] h_k
+        double t = (lane < r) ? Ls[r][lane] * h : 0.0;
+        t = dev::wave_sum(t);
+        const double hr = sv[r] - t;
+        if (lane == r) h = hr;
+        if (lane == 0) a.hcol[r] = hr;
+    }
+}
+
+// Second pass: x = w - sum_q h_q sig_q u_q (q <= j, in order) stored as u_{j+1},
+// with the partials of <x, u_q> (values 0..j) and ||x||^2 (value j + 1).
+template <int MAXV>
+__global__ __launch_bounds__(TPB) void k_gs_update(GsStep a)
+{
+    if (*a.ctl) return;
+    const int j = a.j, nv = j + 1;
+    double c[MAXV], acc[MAXV + 1];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) c[q] = (q < nv) ? a.hcol[q] * a.sig[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q <= MAXV; ++q) acc[q] = 0.0;
+    // pairs of elements (the vector length 2mn and the slot stride are even)
+    double2 *w2 = reinterpret_cast<double2 *>(a.w);
+    const double2 *V2 = reinterpret_cast<const double2 *>(a.V);
+    const size_t len2 = (size_t)a.m * a.n, ldv2 = a.ldv / 2;
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len2; k += (size_t)gridDim.x * TPB) {
+        double2 vq[MAXV];
+        double2 x = w2[k];
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q) {
+            vq[q] = (q < nv) ? V2[q * ldv2 + k] : double2{0.0, 0.0};
+            x.x -= c[q] * vq[q].x;
+            x.y -= c[q] * vq[q].y;
+        }
+        w2[k] = x;
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q) acc[q] += x.x * vq[q].x + x.y * vq[q].y;
+        acc[MAXV] += x.x * x.x + x.y * x.y;
+    }
+    block_sum<MAXV + 1>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+            if (q < nv) a.p2[(size_t)q * gridDim.x + blockIdx.x] = acc[q];
+        a.p2[(size_t)nv * gridDim.x + blockIdx.x] = acc[MAXV];
+    }
+}
+
+// One block of 1024 threads: ||x|| and <x, u_q> from the partials give
+// H[j+1][j] = ||x||, sig_{j+1} and row j + 1 of L; then the Givens update of
+// column j.
+__global__ __launch_bounds__(1024) void k_gs_finish(GsStep a)
+{
+    if (*a.ctl) {   // a stopped cycle: the snapshot only
+        if (threadIdx.x == 0) write_snapshot(a.snap, a.ctl);
+        return;
+    }
+    const int j = a.j, nv = j + 1;
+    __shared__ double sv[kGsMaxV + 1];
+    sum_partials_1024(a.p2, nv + 1, sv);
+    const double nrm = sqrt(sv[nv]);
+    const double inv = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+    // row j + 1 of L: <v_{j+1}, v_q> = sig_q <x, u_q> / ||x||
+    if (threadIdx.x < nv)
+        a.L[(size_t)(j + 1) * a.ldl + threadIdx.x] = sv[threadIdx.x] * a.sig[threadIdx.x] * inv;
+    if (threadIdx.x == 0) a.sig[j + 1] = inv;
+    givens_block(a.H, a.ldh, j, nrm, a.g, a.cs, a.sn, a.abs_tol, a.ctl, a.resid);
+    if (threadIdx.x == 0) write_snapshot(a.snap, a.ctl);
+}
+
 // ------------------------------------------- least squares on the device
 // Control block of one GMRES cycle: ctl[0] stop flag (read by every kernel
 // of later Arnoldi steps), ctl[1] iterations completed, ctl[2] reason.
 // ls: g[R+1] (rotated right-hand side), cs[R], sn[R] (Givens rotations).
-__global__ void k_cycle_init(int *__restrict__ ctl, double *__restrict__ g, int R, double beta)
+__global__ void k_cycle_init(int *__restrict__ ctl, double *__restrict__ g, int R, double beta,
+                             double *__restrict__ sig)
 {
     for (int i = threadIdx.x; i <= R; i += blockDim.x) g[i] = (i == 0) ? beta : 0.0;
     if (threadIdx.x == 0) {
         ctl[0] = 0;
         ctl[1] = 0;
         ctl[2] = CYCLE_RUNNING;
+        if (sig) sig[0] = 1.0;
     }
 }
 
-// Hessenberg column j: apply rotations 0..j-1, then the rotation that zeroes
-// h[j+1]; update g and stop when |g[j+1]| <= abs_tol (the GMRES residual).
+// One Givens update of Hessenberg column j (givens_block), then the snapshot.
 __global__ void k_givens(double *__restrict__ H, int ldh, int j, double *__restrict__ g,
                          double *__restrict__ cs, double *__restrict__ sn, double abs_tol,
-                         int *__restrict__ ctl, double *__restrict__ resid)
+                         int *__restrict__ ctl, double *__restrict__ resid, int *__restrict__ snap)
 {
-    if (threadIdx.x != 0 || ctl[0]) return;
-    double *h = H + (size_t)j * ldh;
-    for (int i = 0; i <= j + 1; ++i)
-        if (!isfinite(h[i])) {
-            ctl[0] = 1;
-            ctl[2] = CYCLE_NONFINITE;
-            return;
-        }
-    for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
-        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
-        h[i] = t;
-    }
-    const double hn = h[j + 1];
-    const double r = hypot(h[j], hn);
-    if (r == 0.0) {
-        ctl[0] = 1;
-        ctl[2] = CYCLE_BREAKDOWN;
+    if (ctl[0]) {
+        if (threadIdx.x == 0) write_snapshot(snap, ctl);
         return;
     }
-    cs[j] = h[j] / r;
-    sn[j] = hn / r;
-    h[j] = r;
-    h[j + 1] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    ctl[1] = j + 1;
-    resid[j] = fabs(g[j + 1]);
-    if (fabs(g[j + 1]) <= abs_tol) {   // includes hn == 0 (invariant subspace)
-        ctl[0] = 1;
-        ctl[2] = CYCLE_CONVERGED;
-    }
+    const double hlast = H[(size_t)j * ldh + j + 1];
+    givens_block(H, ldh, j, hlast, g, cs, sn, abs_tol, ctl, resid);
+    if (threadIdx.x == 0) write_snapshot(snap, ctl);
 }
 
 // y = R^{-1} g over the ctl[1] completed columns (upper triangular R in H).
+// With sig (an unnormalised basis, v_i = sig_i u_i) y_i is then scaled by
+// sig_i: the update sums y_i sig_i times the preconditioned u_i.
 __global__ void k_backsolve(const double *__restrict__ H, int ldh, const double *__restrict__ g,
-                            const int *__restrict__ ctl, double *__restrict__ y)
+                            const int *__restrict__ ctl, double *__restrict__ y,
+                            const double *__restrict__ sig)
 {
     if (threadIdx.x != 0) return;
     const int k = ctl[1];
@@ -321,6 +536,8 @@ __global__ void k_backsolve(const double *__restrict__ H, int ldh, const double 
         for (int c = i + 1; c < k; ++c) t -= H[(size_t)c * ldh + i] * y[c];
         y[i] = t / H[(size_t)i * ldh + i];
     }
+    if (sig)
+        for (int i = 0; i < k; ++i) y[i] *= sig[i];
 }
 
 __global__ __launch_bounds__(TPB) void k_scale(const double *__restrict__ x, double alpha,
@@ -481,24 +698,46 @@ hipError_t launch_normalize(double *w, size_t len, const double *partials_in, do
     return hipGetLastError();
 }
 
-hipError_t launch_cycle_init(int *ctl, double *g, int R, double beta, hipStream_t s)
+hipError_t launch_gs_step(const GsStep &g, int pass, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, s, ctl, g, R, beta);
+    const int nv = g.j + 1;
+    if (g.j < 0 || nv > kGsMaxV || g.j + 1 >= g.ldl || g.j + 1 >= g.ldh) return hipErrorInvalidValue;
+    const dim3 grid(kGsBlocks), b(TPB);
+    if (pass == 0) {
+        if (nv <= 4) hipLaunchKernelGGL(k_jacobian_proj<4>, grid, b, 0, s, g);
+        else if (nv <= 8) hipLaunchKernelGGL(k_jacobian_proj<8>, grid, b, 0, s, g);
+        else if (nv <= 16) hipLaunchKernelGGL(k_jacobian_proj<16>, grid, b, 0, s, g);
+        else hipLaunchKernelGGL(k_jacobian_proj<32>, grid, b, 0, s, g);
+    } else {
+        hipLaunchKernelGGL(k_gs_coef, dim3(1), dim3(1024), 0, s, g);
+        if (nv <= 4) hipLaunchKernelGGL(k_gs_update<4>, grid, b, 0, s, g);
+        else if (nv <= 8) hipLaunchKernelGGL(k_gs_update<8>, grid, b, 0, s, g);
+        else if (nv <= 16) hipLaunchKernelGGL(k_gs_update<16>, grid, b, 0, s, g);
+        else hipLaunchKernelGGL(k_gs_update<32>, grid, b, 0, s, g);
+        hipLaunchKernelGGL(k_gs_finish, dim3(1), dim3(1024), 0, s, g);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cycle_init(int *ctl, double *g, int R, double beta, hipStream_t s,
+                             double *sig)
+{
+    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, s, ctl, g, R, beta, sig);
     return hipGetLastError();
 }
 
 hipError_t launch_givens(double *H, int ldh, int j, double *g, double *cs, double *sn,
-                         double abs_tol, int *ctl, double *resid, hipStream_t s)
+                         double abs_tol, int *ctl, double *resid, int *snap, hipStream_t s)
 {
     hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, H, ldh, j, g, cs, sn, abs_tol, ctl,
-                       resid);
+                       resid, snap);
     return hipGetLastError();
 }
 
 hipError_t launch_backsolve(const double *H, int ldh, const double *g, const int *ctl,
-                            double *y, hipStream_t s)
+                            double *y, hipStream_t s, const double *sig)
 {
-    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, H, ldh, g, ctl, y);
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, H, ldh, g, ctl, y, sig);
     return hipGetLastError();
 }
 

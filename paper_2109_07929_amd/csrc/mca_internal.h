@@ -223,14 +223,48 @@ hipError_t launch_mgs_step(double *w, const double *v_prev, const double *v_next
 hipError_t launch_normalize(double *w, size_t len, const double *partials_in, double *h_out,
                             hipStream_t s, const int *skip = nullptr);
 
+// One Arnoldi step j in two passes (modified Gram-Schmidt in compact WY form,
+// see kernels.hip) over an unnormalised basis V (slot q holds u_q, v_q =
+// sig_q u_q).  Pass 0: w = sig_j J z~_j with the projections on the basis.
+// Pass 1: MGS's coefficients (one block), w -= V h with the products of the
+// new vector with the basis, then ||w||, the next row of L and the Givens
+// update of column j (one block).  j + 1 <= kGsMaxV.
+constexpr int kGsMaxV = 32;
+constexpr int kGsBlocks = 1024;
+struct GsStep {
+    int m, n, j;
+    Wire top, bot;
+    const double *d;              // device slopes D (m x n)
+    const double *zt, *zb;        // preconditioned u_j (top, bottom layer)
+    double *w;                    // slot j + 1 of V: the new vector (length 2mn)
+    const double *V;              // slot 0 of V
+    size_t ldv;                   // slot stride (2mn)
+    double *sig;                  // sig_q (R + 1)
+    double *L;                    // strictly lower V^T V, row-major, ld ldl
+    int ldl;
+    double *H;                    // Hessenberg, column-major, ld ldh
+    int ldh;
+    double *hcol;                 // H column j
+    double *p1, *p2;              // partials: kGsMaxV and kGsMaxV + 1 values x kGsBlocks
+    double *g, *cs, *sn, *resid;  // Givens state of the cycle
+    double abs_tol;
+    int *ctl;                     // cycle control block (stop flag first)
+    int *snap;                    // device address of the host's snapshot slot of step j
+};
+// pass 0: the Jacobian product with the projections; pass 1: the update
+hipError_t launch_gs_step(const GsStep &g, int pass, hipStream_t s);
+
 // Device-side least squares of one GMRES cycle (see k_givens).
 enum CycleReason { CYCLE_RUNNING = 0, CYCLE_CONVERGED = 1, CYCLE_BREAKDOWN = 2,
                    CYCLE_NONFINITE = 3 };
-hipError_t launch_cycle_init(int *ctl, double *g, int R, double beta, hipStream_t s);
+// sig (may be null): sig[0] = 1 (v_0 is stored normalised)
+hipError_t launch_cycle_init(int *ctl, double *g, int R, double beta, hipStream_t s,
+                             double *sig = nullptr);
+// ... then ctl[0..3] written to snap (pinned host memory, device address)
 hipError_t launch_givens(double *H, int ldh, int j, double *g, double *cs, double *sn,
-                         double abs_tol, int *ctl, double *resid, hipStream_t s);
+                         double abs_tol, int *ctl, double *resid, int *snap, hipStream_t s);
 hipError_t launch_backsolve(const double *H, int ldh, const double *g, const int *ctl,
-                            double *y, hipStream_t s);
+                            double *y, hipStream_t s, const double *sig = nullptr);
 
 // y = alpha * x
 hipError_t launch_scale(const double *x, double alpha, double *y, size_t len, hipStream_t s);

@@ -81,7 +81,7 @@ mca_status validate_options(const mca_options *o)
         o->precond != MCA_PRECOND_NONE)
         return MCA_ERR_INVALID_ARG;
     if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING | MCA_FLAG_GUESS_FALLBACK |
-                     MCA_FLAG_SWEEP_START))
+                     MCA_FLAG_SWEEP_START | MCA_FLAG_MGS_PASSES))
         return MCA_ERR_INVALID_ARG;
     if ((o->flags & MCA_FLAG_INITIAL_GUESS) && (o->flags & MCA_FLAG_SWEEP_START))
         return MCA_ERR_INVALID_ARG;
@@ -208,6 +208,9 @@ struct SolveWs {
     double *D, *Dn;   // device slopes at Vc / Vn
     double *tmp;      // J X for restarts
     double *pa, *pb;  // per-block partial sums (ping-pong)
+    double *pg1, *pg2;  // two-pass Gram-Schmidt partials (projections; update pass)
+    double *Lg;       // strictly lower V^T V, row-major, ld = restart + 1
+    double *sig;      // basis scales sig_q = 1 / ||u_q|| (two-pass form)
     double *H;        // Hessenberg, column-major, ld = restart + 1
     double *coef;     // least-squares solution y
     double *scal;     // reduced scalars
@@ -235,6 +238,10 @@ SolveWs solve_layout(const mca_plan *P, const mca_options *o, void *base)
     w.tmp = c.take<double>(len);
     w.pa = c.take<double>(4 * 1024);
     w.pb = c.take<double>(4 * 1024);
+    w.pg1 = c.take<double>((size_t)kGsMaxV * kGsBlocks);
+    w.pg2 = c.take<double>((size_t)(kGsMaxV + 1) * kGsBlocks);
+    w.Lg = c.take<double>((R + 1) * (R + 1));
+    w.sig = c.take<double>(R + 1);
     w.H = c.take<double>((R + 1) * R);
     w.coef = c.take<double>(R);
     w.scal = c.take<double>(8);
@@ -485,7 +492,9 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
 }
 
 // Flexible GMRES(restart) with modified Gram-Schmidt for J X = -F, right
-// preconditioned by P(a, a).  On return X holds the correction.
+// preconditioned by P(a, a).  On return X holds the correction.  Gram-Schmidt
+// runs in two passes per Arnoldi step (compact WY form) when restart <= 32 and
+// MCA_FLAG_MGS_PASSES is not set, else in one pass per basis vector.
 mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, double fnorm,
                   double a, hipStream_t s, Timing *tm, int *its_out, int *restarts_out,
                   bool *conv_out)
@@ -493,13 +502,17 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
     const size_t mn = (size_t)P->geom.m * P->geom.n, len = 2 * mn;
     const int R = o->restart;
     const int ldh = R + 1;
+    const bool two_pass = !(o->flags & MCA_FLAG_MGS_PASSES) && R <= kGsMaxV;
     double *host = pinned_scratch();
     if (!host) {
         set_hip_error("hipHostMalloc", hipErrorOutOfMemory);
         return MCA_ERR_HIP;
     }
-    // host snapshots of the control block, one slot per Arnoldi step
+    // host snapshots of the control block, one slot per Arnoldi step, written
+    // by the step's last kernel
     int *snap = reinterpret_cast<int *>(host + 256);
+    int *snap_dev = nullptr;
+    MCA_TRY(hipHostGetDevicePointer((void **)&snap_dev, snap, 0));
     hipEvent_t done[2] = {nullptr, nullptr};
     struct EvGuard {
         hipEvent_t *e;
@@ -513,6 +526,27 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
 
     double beta = fnorm;
     const double abs_tol = o->gmres_tol * fnorm;
+    GsStep gs{};
+    gs.m = P->geom.m;
+    gs.n = P->geom.n;
+    gs.top = P->top;
+    gs.bot = P->bot;
+    gs.d = w.D;
+    gs.V = w.V;
+    gs.ldv = len;
+    gs.sig = w.sig;
+    gs.L = w.Lg;
+    gs.ldl = R + 1;
+    gs.H = w.H;
+    gs.ldh = ldh;
+    gs.p1 = w.pg1;
+    gs.p2 = w.pg2;
+    gs.g = w.g;
+    gs.cs = w.cs;
+    gs.sn = w.sn;
+    gs.resid = w.resid;
+    gs.abs_tol = abs_tol;
+    gs.ctl = w.ctl;
     int its = 0, restarts = 0;
     bool converged = false, first = true;
     // v_0 = -F / ||F||
@@ -522,7 +556,7 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
         if (st != MCA_OK) return st;
     }
     for (;;) {
-        MCA_TRY(launch_cycle_init(w.ctl, w.g, R, beta, s));
+        MCA_TRY(launch_cycle_init(w.ctl, w.g, R, beta, s, two_pass ? w.sig : nullptr));
         const int jmax = std::min(R, o->max_krylov - its);
         int last = -1;
         for (int j = 0; j < jmax; ++j) {
@@ -533,24 +567,42 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
             mca_status st = precond_run(P, o->precond, o->precision, a, a, vj, vj + mn, zj,
                                         zj + mn, w.pw, s, tm, slot, skip, w.D);
             if (st != MCA_OK) return st;
-            // w = J z_j, fused with the partial sums of <w, v_0>
-            MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
-            MCA_TRY(launch_jacobian(P, w.D, zj, zj + mn, wv, wv + mn, s, w.V, w.pa, skip));
-            MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1, slot));
-            // modified Gram-Schmidt: h_ij = <w, v_i>, w -= h_ij v_i, i = 0..j
             double *hcol = w.H + (size_t)j * ldh;
-            MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s, slot));
-            double *pin = w.pa, *pout = w.pb;
-            for (int i = 0; i <= j; ++i) {
-                const double *vnext = (i < j) ? w.V + (size_t)(i + 1) * len : nullptr;
-                MCA_TRY(launch_mgs_step(wv, w.V + (size_t)i * len, vnext, len, pin, pout,
-                                        hcol + i, s, skip));
-                std::swap(pin, pout);
+            if (two_pass) {
+                // w = sig_j J z~_j fused with the projections on the basis and
+                // MGS's coefficients, then w -= V h with the Givens update
+                gs.j = j;
+                gs.zt = zj;
+                gs.zb = zj + mn;
+                gs.w = wv;
+                gs.hcol = hcol;
+                gs.snap = snap_dev + 4 * j;
+                MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
+                MCA_TRY(launch_gs_step(gs, 0, s));
+                MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1, slot));
+                MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s, slot));
+                MCA_TRY(launch_gs_step(gs, 1, s));
+                MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, 3, slot));
+            } else {
+                // w = J z_j, fused with the partial sums of <w, v_0>
+                MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
+                MCA_TRY(launch_jacobian(P, w.D, zj, zj + mn, wv, wv + mn, s, w.V, w.pa, skip));
+                MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1, slot));
+                // modified Gram-Schmidt, one pass per basis vector:
+                // h_ij = <w, v_i>, w -= h_ij v_i, i = 0..j
+                MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s, slot));
+                double *pin = w.pa, *pout = w.pb;
+                for (int i = 0; i <= j; ++i) {
+                    const double *vnext = (i < j) ? w.V + (size_t)(i + 1) * len : nullptr;
+                    MCA_TRY(launch_mgs_step(wv, w.V + (size_t)i * len, vnext, len, pin, pout,
+                                            hcol + i, s, skip));
+                    std::swap(pin, pout);
+                }
+                MCA_TRY(launch_normalize(wv, len, pin, hcol + j + 1, s, skip));
+                MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 2, slot));
+                MCA_TRY(launch_givens(w.H, ldh, j, w.g, w.cs, w.sn, abs_tol, w.ctl, w.resid,
+                                      snap_dev + 4 * j, s));
             }
-            MCA_TRY(launch_normalize(wv, len, pin, hcol + j + 1, s, skip));
-            MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 2, slot));
-            MCA_TRY(launch_givens(w.H, ldh, j, w.g, w.cs, w.sn, abs_tol, w.ctl, w.resid, s));
-            MCA_TRY(hipMemcpyAsync(snap + 4 * j, w.ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
             MCA_TRY(hipEventRecord(done[slot], s));
             last = j;
             if (j > 0) {
@@ -571,7 +623,8 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
         if (reason == CYCLE_NONFINITE) return MCA_ERR_NONFINITE;
         its += k;
         if (k > 0) {
-            MCA_TRY(launch_backsolve(w.H, ldh, w.g, w.ctl, w.coef, s));
+            MCA_TRY(launch_backsolve(w.H, ldh, w.g, w.ctl, w.coef, s,
+                                     two_pass ? w.sig : nullptr));
             // the number of completed steps is ctl[1]
             MCA_TRY(launch_update(w.Z, len, w.coef, 0, w.ctl + 1, len, w.X, first ? 0 : 1, s));
             first = false;

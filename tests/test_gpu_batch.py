@@ -186,3 +186,78 @@ def test_batch_large_crossbars_use_large_tiles():
         say(f"  {c.geom.m}x{c.geom.n}: newton {stats[b].newton_iters} krylov "
             f"{stats[b].krylov_iters} err {err:.1e}")
         assert err <= TOL
+
+
+def test_batch_graph_replays_match_eager():
+    """Arnoldi steps captured as HIP graphs (MCA_FLAG_GRAPH) reproduce the eager
+    launches bit for bit: at capture, on replays in later cycles (restart 5) and
+    later solves, with eager solves and other inputs in between, and after a
+    change of workspace (which drops the captured steps)."""
+    cbs = ragged_batch(seed=5)
+    bt = Batch([c.geom for c in cbs])
+    kw = dict(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3, restart=5)
+    eager = B.options(**kw)
+    graph = B.options(flags=B.MCA_FLAG_GRAPH, **kw)
+    ws = bt.workspace(eager)
+    ws2 = bt.workspace(eager)
+    inputs = {
+        "a": (bt.concat([c.g_dev for c in cbs]), bt.concat([c.v_in for c in cbs])),
+        "b": (bt.concat([c.g_dev[::-1].copy() for c in cbs]),
+              bt.concat([0.5 * c.v_in for c in cbs])),
+    }
+
+    def run(key, opts, w):
+        g, v = inputs[key]
+        vt, vb, status, stats = bt.solve(g, v, opts, ws=w)
+        torch.cuda.synchronize()
+        return (vt.cpu().numpy(), vb.cpu().numpy(), status,
+                [(s.newton_iters, s.krylov_iters, s.restarts) for s in stats])
+
+    ref = {k: run(k, eager, ws) for k in inputs}
+    for k, r in ref.items():
+        say(f"graph batch eager {k}: status {r[2]} iterations {r[3]}")
+        assert r[2] == B.MCA_OK
+    assert any(it[2] > 0 for it in ref["a"][3]), "restart 5 should restart some crossbar"
+    for i, (k, w) in enumerate([("a", ws), ("b", ws), ("a", ws), ("b", ws2), ("a", ws2)]):
+        if i == 2:
+            run("b", eager, ws)          # eager work between the replays
+        got = run(k, graph, w)
+        say(f"graph replay {i} ({k}): status {got[2]} iterations {got[3]}")
+        assert got[2] == ref[k][2]
+        assert got[3] == ref[k][3]
+        assert np.array_equal(got[0], ref[k][0]) and np.array_equal(got[1], ref[k][1])
+
+
+def test_single_solve_rejects_graph_flag():
+    c = synth.crossbar(16, 16, seed=0)
+    plan = Plan(c.geom)
+    o = B.options(flags=B.MCA_FLAG_GRAPH)
+    with pytest.raises(Exception):
+        plan.solve(torch.from_numpy(c.g_dev).cuda(), torch.from_numpy(c.v_in).cuda(), o)
+
+
+@pytest.mark.parametrize("restart", [5, 30])
+def test_batch_two_pass_gram_schmidt_matches_one_pass_per_vector(restart):
+    """The batched solver's default orthogonalisation (modified Gram-Schmidt in
+    compact WY form, two passes per step, per-crossbar reductions by each
+    crossbar's last block) against MGS with one pass per basis vector: same
+    Newton counts, GMRES counts within one per Newton step, and both within the
+    bar of the oracle's steady state."""
+    cbs = ragged_batch(seed=9)
+    runs = {}
+    for name, flags in (("two-pass", 0), ("per-vector", B.MCA_FLAG_MGS_PASSES)):
+        _, vts, vbs, status, stats = batch_solve(cbs, restart=restart, flags=flags)
+        assert status == B.MCA_OK
+        runs[name] = (vts, vbs, stats)
+    for b, c in enumerate(cbs):
+        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="band")
+        sa, sb = runs["two-pass"][2][b], runs["per-vector"][2][b]
+        ka = list(sa.krylov_history[:sa.newton_iters])
+        kb = list(sb.krylov_history[:sb.newton_iters])
+        ea = rel_err(runs["two-pass"][0][b], runs["two-pass"][1][b], rt, rb)
+        eb = rel_err(runs["per-vector"][0][b], runs["per-vector"][1][b], rt, rb)
+        say(f"  {c.geom.m}x{c.geom.n} restart {restart}: two-pass {ka} err {ea:.1e}, "
+            f"per-vector {kb} err {eb:.1e}")
+        assert sa.newton_iters == sb.newton_iters
+        assert all(abs(x - y) <= 1 for x, y in zip(ka, kb))
+        assert ea <= TOL and eb <= TOL

@@ -78,6 +78,33 @@ def test_solve_shapes(m, n, form):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("m,n,restart", [(32, 32, 30), (70, 130, 30), (64, 48, 4), (96, 64, 32),
+                                          (48, 48, 40)])
+def test_two_pass_gram_schmidt_matches_one_pass_per_vector(m, n, restart):
+    """The default Arnoldi orthogonalisation (modified Gram-Schmidt in compact WY
+    form, two passes per step) and MGS with one pass per basis vector
+    (MCA_FLAG_MGS_PASSES) give the same coefficients up to rounding: the same
+    Newton and GMRES counts (one GMRES step of slack per Newton step) and both
+    steady states within the bar of the oracle's.  restart 40 exceeds the
+    two-pass limit (32), so both runs take the one-pass form there."""
+    cb = synth.crossbar(m, n, seed=4)
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="band")
+    runs = {}
+    for name, flags in (("two-pass", 0), ("per-vector", B.MCA_FLAG_MGS_PASSES)):
+        vt, vb, status, st = gpu_solve(cb, restart=restart, flags=flags)
+        assert status == B.MCA_OK
+        err = rel_err(vt, vb, rt, rb)
+        kh = list(st.krylov_history[:st.newton_iters])
+        say(f"  {m}x{n} restart {restart} {name}: newton {st.newton_iters} krylov {kh} "
+            f"restarts {st.restarts} err {err:.2e}")
+        assert err <= TOL
+        runs[name] = (st.newton_iters, kh, vt, vb)
+    a, b = runs["two-pass"], runs["per-vector"]
+    assert a[0] == b[0]
+    assert all(abs(x - y) <= 1 for x, y in zip(a[1], b[1]))
+    assert rel_err(a[2], a[3], b[2], b[3]) <= 1e-10
+
+
 @pytest.mark.parametrize("restart", [1, 2, 3])
 def test_solve_with_restarts(restart):
     """Short restart lengths force several GMRES cycles per Newton step."""
