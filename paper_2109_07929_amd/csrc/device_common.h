@@ -25,11 +25,11 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum over a TPB-thread block in a fixed order; the result is valid in every thread.
-template <int NC>
+// Sum over an NT-thread block in a fixed order; the result is valid in every thread.
+template <int NC, int NT = TPB>
 __device__ __forceinline__ void block_sum(double (&v)[NC])
 {
-    __shared__ double sh[NC][TPB / 64];
+    __shared__ double sh[NC][NT / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -41,10 +41,31 @@ __device__ __forceinline__ void block_sum(double (&v)[NC])
     for (int c = 0; c < NC; ++c) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < TPB / 64; ++w) s += sh[c][w];
+        for (int w = 0; w < NT / 64; ++w) s += sh[c][w];
         v[c] = s;
     }
     __syncthreads();
+}
+
+// Block sums of the first nc of NC per-thread values, in a fixed order, stored
+// by threads 0..nc-1: out[c * stride] = sum over the NT-thread block of v[c].
+template <int NC, int NT>
+__device__ __forceinline__ void block_store_sums(const double (&v)[NC], int nc, double *out,
+                                                 size_t stride)
+{
+    __shared__ double sh[NC][NT / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const double w = wave_sum(v[c]);
+        if (lane == 0) sh[c][wave] = w;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += sh[threadIdx.x][w];
+        out[threadIdx.x * stride] = s;
+    }
 }
 
 // Sum of nb per-block partials p[0..nb), identical in every block (fixed order).

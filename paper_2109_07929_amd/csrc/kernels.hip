@@ -271,21 +271,22 @@ __global__ __launch_bounds__(TPB) void k_normalize(
 // the least-squares coefficients take the factors sig_j before the update.
 //
 // The two streaming passes leave per-block partials (value q at
-// partials[q * kGsBlocks + block]); a one-block kernel after each sums them
-// in a fixed order and does the small dense work of the step.
+// partials[q * gridDim.x + block]).  The update pass's blocks each sum the
+// first pass's partials themselves (kProjBlocks of them per value); a
+// one-block kernel after the update pass sums its partials and does the rest
+// of the step's small dense work.
 
-// Sums of nval values' partials (kGsBlocks = 1024 each, value q at
-// p[q * 1024 + block]) by a block of 1024 threads: thread t loads partial t of
-// every value at once, then a fixed-order tree; out[q] in LDS.
-__device__ __forceinline__ void sum_partials_1024(const double *__restrict__ p, int nval,
+// Sums of nval values' partials (nb <= 1024 each, value q at p[q * nb +
+// block]) by a block of 1024 threads: thread t loads partial t of every
+// value at once, then a fixed-order tree; out[q] in LDS.
+__device__ __forceinline__ void sum_partials_1024(const double *__restrict__ p, int nval, int nb,
                                                   double *out)
 {
-    static_assert(kGsBlocks == 1024, "one thread per partial");
     __shared__ double red[kGsMaxV + 1][16];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double v[kGsMaxV + 1];
 #pragma unroll
-    for (int q = 0; q <= kGsMaxV; ++q) v[q] = (q < nval) ? p[(size_t)q * kGsBlocks + t] : 0.0;
+    for (int q = 0; q <= kGsMaxV; ++q) v[q] = (q < nval && t < nb) ? p[(size_t)q * nb + t] : 0.0;
 #pragma unroll
     for (int q = 0; q <= kGsMaxV; ++q) {
         if (q < nval) {
@@ -303,11 +304,11 @@ __device__ __forceinline__ void sum_partials_1024(const double *__restrict__ p, 
 }
 
 // Copy of the cycle control block (stop flag, steps done, reason) to the
-// host's pinned snapshot slot, written through to memory.
+// host's pinned snapshot slot (16-byte aligned); the host reads it after the
+// kernel has completed.
 __device__ __forceinline__ void write_snapshot(int *snap, const int *ctl)
 {
-    for (int i = 0; i < 4; ++i)
-        __hip_atomic_store(snap + i, ctl[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    *reinterpret_cast<int4 *>(snap) = int4{ctl[0], ctl[1], ctl[2], ctl[3]};
 }
 
 // Givens update of Hessenberg column j: apply rotations 0..j-1, then the
@@ -371,8 +372,8 @@ __device__ void givens_block(double *__restrict__ H, int ldh, int j, double hlas
 
 // w = sig_j J z~_j (eq. (J); z~_j the preconditioned u_j) with the partials of
 // <w, u_q>, q <= j.
-template <int MAXV>
-__global__ __launch_bounds__(TPB) void k_jacobian_proj(GsStep a)
+template <int MAXV, int NT>
+__global__ __launch_bounds__(NT) void k_jacobian_proj(GsStep a)
 {
     if (*a.ctl) return;
     const int m = a.m, n = a.n, j = a.j, nv = j + 1;
@@ -381,7 +382,8 @@ __global__ __launch_bounds__(TPB) void k_jacobian_proj(GsStep a)
     double acc[MAXV];
 #pragma unroll
     for (int q = 0; q < MAXV; ++q) acc[q] = 0.0;
-    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
+#pragma unroll 1
+    for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < mn; k += (size_t)gridDim.x * NT) {
         const int i = (int)(k / n), jj = (int)(k - (size_t)i * n);
         const double t = a.zt[k], b = a.zb[k];
         const double st = wire_apply(a.top, jj, t, (jj > 0) ? a.zt[k - 1] : 0.0,
@@ -396,15 +398,11 @@ __global__ __launch_bounds__(TPB) void k_jacobian_proj(GsStep a)
         for (int q = 0; q < MAXV; ++q)
             if (q < nv) acc[q] += y1 * a.V[q * a.ldv + k] + y2 * a.V[q * a.ldv + mn + k];
     }
-    block_sum<MAXV>(acc);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < MAXV; ++q)
-            if (q < nv) a.p1[(size_t)q * gridDim.x + blockIdx.x] = acc[q];
-    }
+    dev::block_store_sums<MAXV, NT>(acc, nv, a.p1 + blockIdx.x, gridDim.x);
 }
 
-// One block of 1024 threads: s_q = sig_q <w, u_q> from the partials, then
+// Longer bases (j + 1 > kGsFusedMaxV): one block of 1024 threads forms
+// s_q = sig_q <w, u_q> from the first pass's kGsBlocks partials, then
 // (I + L) h = s by forward substitution with rows 0..j of L; h to H column j.
 __global__ __launch_bounds__(1024) void k_gs_coef(GsStep a)
 {
@@ -417,7 +415,7 @@ __global__ __launch_bounds__(1024) void k_gs_coef(GsStep a)
         const int r = e / kGsMaxV, k = e - r * kGsMaxV;
         if (k < r) Ls[r][k] = a.L[(size_t)r * a.ldl + k];
     }
-    sum_partials_1024(a.p1, nv, sv);
+    sum_partials_1024(a.p1, nv, kGsBlocks, sv);
     if (wave != 0) return;
     if (lane < nv) sv[lane] *= a.sig[lane];   // s_q = sig_q <w, u_q>
     double h = 0.0;     // lane k holds h_k
@@ -431,23 +429,65 @@ __global__ __launch_bounds__(1024) void k_gs_coef(GsStep a)
     }
 }
 
-// Second pass: x = w - sum_q h_q sig_q u_q (q <= j, in order) stored as u_{j+1},
-// with the partials of <x, u_q> (values 0..j) and ||x||^2 (value j + 1).
-template <int MAXV>
-__global__ __launch_bounds__(TPB) void k_gs_update(GsStep a)
+// Second pass.  With PRO (j + 1 <= kGsFusedMaxV) every block first forms
+// MGS's coefficients itself: s_q = sig_q <w, u_q> from the first pass's
+// kProjBlocks partials (the same fixed order in every block), then
+// (I + L) h = s by forward substitution with rows 0..j of L; block 0 stores h
+// in H column j.  Without PRO, k_gs_coef has stored h.  Then
+// x = w - sum_q h_q sig_q u_q (q <= j, in order) is stored as u_{j+1}, with
+// the partials of <x, u_q> (values 0..j) and ||x||^2 (value j + 1).
+template <int MAXV, bool PRO, int NT>
+__global__ __launch_bounds__(NT) void k_gs_update(GsStep a)
 {
     if (*a.ctl) return;
     const int j = a.j, nv = j + 1;
+    __shared__ double hsh[kGsMaxV];
+    if constexpr (!PRO) {
+        for (int q = threadIdx.x; q < nv; q += NT) hsh[q] = a.hcol[q];
+        __syncthreads();
+    } else {
+        __shared__ double sv[kGsMaxV];
+        __shared__ double Ls[kGsMaxV][kGsMaxV];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int q = wave; q < nv; q += NT / 64) {
+            double x = 0.0;
+#pragma unroll
+            for (int u = 0; u < kProjBlocks / 64; ++u) x += a.p1[(size_t)q * kProjBlocks + lane + 64 * u];
+            x = dev::wave_sum(x);
+            if (lane == 0) sv[q] = a.sig[q] * x;
+        }
+        for (int e = threadIdx.x; e < nv * kGsMaxV; e += NT) {
+            const int r = e / kGsMaxV, k = e - r * kGsMaxV;
+            if (k < r) Ls[r][k] = a.L[(size_t)r * a.ldl + k];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double h = 0.0;     // lane k holds h_k
+            for (int r = 0; r <= j; ++r) {
+                // h_r = s_r - sum_{k < r} L[r][k] h_k
+                double t = (lane < r) ? Ls[r][lane] * h : 0.0;
+                t = dev::wave_sum(t);
+                const double hr = sv[r] - t;
+                if (lane == r) h = hr;
+                if (lane == 0) {
+                    hsh[r] = hr;
+                    if (blockIdx.x == 0) a.hcol[r] = hr;
+                }
+            }
+        }
+        __syncthreads();
+    }
     double c[MAXV], acc[MAXV + 1];
 #pragma unroll
-    for (int q = 0; q < MAXV; ++q) c[q] = (q < nv) ? a.hcol[q] * a.sig[q] : 0.0;
+    for (int q = 0; q < MAXV; ++q) c[q] = (q < nv) ? hsh[q] * a.sig[q] : 0.0;
 #pragma unroll
     for (int q = 0; q <= MAXV; ++q) acc[q] = 0.0;
     // pairs of elements (the vector length 2mn and the slot stride are even)
     double2 *w2 = reinterpret_cast<double2 *>(a.w);
     const double2 *V2 = reinterpret_cast<const double2 *>(a.V);
     const size_t len2 = (size_t)a.m * a.n, ldv2 = a.ldv / 2;
-    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len2; k += (size_t)gridDim.x * TPB) {
+#pragma unroll 1
+    for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < len2; k += (size_t)gridDim.x * NT) {
         double2 vq[MAXV];
         double2 x = w2[k];
 #pragma unroll
@@ -461,12 +501,24 @@ __global__ __launch_bounds__(TPB) void k_gs_update(GsStep a)
         for (int q = 0; q < MAXV; ++q) acc[q] += x.x * vq[q].x + x.y * vq[q].y;
         acc[MAXV] += x.x * x.x + x.y * x.y;
     }
-    block_sum<MAXV + 1>(acc);
-    if (threadIdx.x == 0) {
+    // block sums of <x, u_q> (q < nv) and ||x||^2 as values 0..nv
+    __shared__ double sh[MAXV + 1][NT / 64];
+    {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-        for (int q = 0; q < MAXV; ++q)
-            if (q < nv) a.p2[(size_t)q * gridDim.x + blockIdx.x] = acc[q];
-        a.p2[(size_t)nv * gridDim.x + blockIdx.x] = acc[MAXV];
+        for (int q = 0; q <= MAXV; ++q) {
+            if (q < nv || q == MAXV) {
+                const double t = dev::wave_sum(acc[q]);
+                if (lane == 0) sh[q][wave] = t;
+            }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= nv) {
+        const int q = ((int)threadIdx.x < nv) ? (int)threadIdx.x : MAXV;
+        double t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t += sh[q][w];
+        a.p2[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -481,7 +533,7 @@ __global__ __launch_bounds__(1024) void k_gs_finish(GsStep a)
     }
     const int j = a.j, nv = j + 1;
     __shared__ double sv[kGsMaxV + 1];
-    sum_partials_1024(a.p2, nv + 1, sv);
+    sum_partials_1024(a.p2, nv + 1, (nv <= kGsFusedMaxV) ? kProjBlocks : kGsBlocks, sv);
     const double nrm = sqrt(sv[nv]);
     const double inv = (nrm > 0.0) ? 1.0 / nrm : 0.0;
     // row j + 1 of L: <v_{j+1}, v_q> = sig_q <x, u_q> / ||x||
@@ -702,18 +754,25 @@ hipError_t launch_gs_step(const GsStep &g, int pass, hipStream_t s)
 {
     const int nv = g.j + 1;
     if (g.j < 0 || nv > kGsMaxV || g.j + 1 >= g.ldl || g.j + 1 >= g.ldh) return hipErrorInvalidValue;
+    const bool fused = nv <= kGsFusedMaxV;
     const dim3 grid(kGsBlocks), b(TPB);
     if (pass == 0) {
-        if (nv <= 4) hipLaunchKernelGGL(k_jacobian_proj<4>, grid, b, 0, s, g);
-        else if (nv <= 8) hipLaunchKernelGGL(k_jacobian_proj<8>, grid, b, 0, s, g);
-        else if (nv <= 16) hipLaunchKernelGGL(k_jacobian_proj<16>, grid, b, 0, s, g);
-        else hipLaunchKernelGGL(k_jacobian_proj<32>, grid, b, 0, s, g);
+        // short bases: kProjBlocks blocks of 1024 threads, whose partials every
+        // update block sums; longer ones: kGsBlocks blocks of TPB threads
+        const dim3 pg(kProjBlocks), pb(1024);
+        if (nv <= 4) hipLaunchKernelGGL((k_jacobian_proj<4, 1024>), pg, pb, 0, s, g);
+        else if (nv <= 8) hipLaunchKernelGGL((k_jacobian_proj<8, 1024>), pg, pb, 0, s, g);
+        else if (nv <= 16) hipLaunchKernelGGL((k_jacobian_proj<16, TPB>), grid, b, 0, s, g);
+        else hipLaunchKernelGGL((k_jacobian_proj<32, TPB>), grid, b, 0, s, g);
     } else {
-        hipLaunchKernelGGL(k_gs_coef, dim3(1), dim3(1024), 0, s, g);
-        if (nv <= 4) hipLaunchKernelGGL(k_gs_update<4>, grid, b, 0, s, g);
-        else if (nv <= 8) hipLaunchKernelGGL(k_gs_update<8>, grid, b, 0, s, g);
-        else if (nv <= 16) hipLaunchKernelGGL(k_gs_update<16>, grid, b, 0, s, g);
-        else hipLaunchKernelGGL(k_gs_update<32>, grid, b, 0, s, g);
+        static_assert(kGsFusedMaxV == 8, "variants below");
+        // short bases: kProjBlocks blocks of 1024 threads (each forms h itself)
+        const dim3 pg(kProjBlocks), pb(1024);
+        if (!fused) hipLaunchKernelGGL(k_gs_coef, dim3(1), dim3(1024), 0, s, g);
+        if (nv <= 4) hipLaunchKernelGGL((k_gs_update<4, true, 1024>), pg, pb, 0, s, g);
+        else if (nv <= 8) hipLaunchKernelGGL((k_gs_update<8, true, 1024>), pg, pb, 0, s, g);
+        else if (nv <= 16) hipLaunchKernelGGL((k_gs_update<16, false, TPB>), grid, b, 0, s, g);
+        else hipLaunchKernelGGL((k_gs_update<32, false, TPB>), grid, b, 0, s, g);
         hipLaunchKernelGGL(k_gs_finish, dim3(1), dim3(1024), 0, s, g);
     }
     return hipGetLastError();

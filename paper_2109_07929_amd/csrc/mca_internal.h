@@ -226,11 +226,13 @@ hipError_t launch_normalize(double *w, size_t len, const double *partials_in, do
 // One Arnoldi step j in two passes (modified Gram-Schmidt in compact WY form,
 // see kernels.hip) over an unnormalised basis V (slot q holds u_q, v_q =
 // sig_q u_q).  Pass 0: w = sig_j J z~_j with the projections on the basis.
-// Pass 1: MGS's coefficients (one block), w -= V h with the products of the
-// new vector with the basis, then ||w||, the next row of L and the Givens
-// update of column j (one block).  j + 1 <= kGsMaxV.
+// Pass 1: MGS's coefficients and w -= V h with the products of the new
+// vector with the basis, then ||w||, the next row of L and the Givens update
+// of column j (one block).  j + 1 <= kGsMaxV.
 constexpr int kGsMaxV = 32;
-constexpr int kGsBlocks = 1024;
+constexpr int kGsBlocks = 1024;     // blocks of the update pass (and of longer first passes)
+constexpr int kProjBlocks = 256;    // blocks of short first passes (every update block sums them)
+constexpr int kGsFusedMaxV = 8;     // basis sizes whose coefficients the update blocks form
 struct GsStep {
     int m, n, j;
     Wire top, bot;
