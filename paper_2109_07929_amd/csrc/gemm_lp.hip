@@ -460,10 +460,16 @@ hipError_t chain(const LowPrecChain &c, hipStream_t s)
     return hipGetLastError();
 }
 
+// Tile edge 128 (K slices of 32); 64 with K slices of 64, or of 32 when the
+// launch has at least two tiles per CU: the shallower slices halve the LDS
+// and the registers of a workgroup, so that two share a CU.
 template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI>
 void launch_grouped(const GroupedLp &g, int ntiles, int tile, hipStream_t s)
 {
-    if (tile == 128)
+    if (tile == 64 && ntiles >= 512)
+        hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, NB, A_BATCHED, OUT, EPI, 64, 32>),
+                           dim3(ntiles), dim3(LTPB), 0, s, g);
+    else if (tile == 128)
         hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, NB, A_BATCHED, OUT, EPI, 128, 32>),
                            dim3(ntiles), dim3(LTPB), 0, s, g);
     else

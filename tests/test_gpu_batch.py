@@ -261,3 +261,23 @@ def test_batch_two_pass_gram_schmidt_matches_one_pass_per_vector(restart):
         assert sa.newton_iters == sb.newton_iters
         assert all(abs(x - y) <= 1 for x, y in zip(ka, kb))
         assert ea <= TOL and eb <= TOL
+
+
+def test_batch_many_ragged_crossbars_shallow_slices():
+    """Enough ragged crossbars that the grouped products run two tiles per CU
+    (64 x 64 tiles with 32-deep K slices, 512 or more tiles per product): every
+    crossbar converges, and a sample matches the oracle's steady state."""
+    cbs = synth.mc_batch(420, seed=21, sizes=(20, 33, 64, 72, 100))
+    tiles = sum(-(-c.geom.m // 64) * -(-c.geom.n // 64) for c in cbs)
+    say(f"ragged batch of {len(cbs)} crossbars, {tiles} tiles per product")
+    assert tiles >= 512
+    bt, vts, vbs, status, stats = batch_solve(cbs)
+    assert status == B.MCA_OK
+    assert max(s.rel_residual for s in stats) <= 1e-10
+    for b in range(0, len(cbs), 21):
+        c = cbs[b]
+        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="band")
+        err = rel_err(vts[b], vbs[b], rt, rb)
+        say(f"  {c.geom.m}x{c.geom.n}: newton {stats[b].newton_iters} krylov "
+            f"{stats[b].krylov_iters} err {err:.1e}")
+        assert err <= TOL
