@@ -98,7 +98,9 @@ def krylov_hbm(st, mn, opts, kms, steps):
     matvec 40 (read x, D; write y) plus MGS 16 (j + 1) + 32 (read the basis once,
     read and write w).  Kernel bytes: what the kernels must move, which reads the
     basis twice in the two-pass form (projections, then update), and once per
-    projection pass in the one-pass-per-vector form."""
+    projection pass in the one-pass-per-vector form.  The time is that of the
+    Jacobian and orthogonalisation classes (HIP events around the streaming
+    passes; the one-block Givens kernels are outside them)."""
     from paper_2109_07929_amd import binding as B
     R = opts.restart
     two_pass = not (opts.flags & B.MCA_FLAG_MGS_PASSES) and R <= 32

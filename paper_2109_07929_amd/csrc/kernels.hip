@@ -764,7 +764,7 @@ hipError_t launch_gs_step(const GsStep &g, int pass, hipStream_t s)
         else if (nv <= 8) hipLaunchKernelGGL((k_jacobian_proj<8, 1024>), pg, pb, 0, s, g);
         else if (nv <= 16) hipLaunchKernelGGL((k_jacobian_proj<16, TPB>), grid, b, 0, s, g);
         else hipLaunchKernelGGL((k_jacobian_proj<32, TPB>), grid, b, 0, s, g);
-    } else {
+    } else if (pass == 1) {
         static_assert(kGsFusedMaxV == 8, "variants below");
         // short bases: kProjBlocks blocks of 1024 threads (each forms h itself)
         const dim3 pg(kProjBlocks), pb(1024);
@@ -773,6 +773,7 @@ hipError_t launch_gs_step(const GsStep &g, int pass, hipStream_t s)
         else if (nv <= 8) hipLaunchKernelGGL((k_gs_update<8, true, 1024>), pg, pb, 0, s, g);
         else if (nv <= 16) hipLaunchKernelGGL((k_gs_update<16, false, TPB>), grid, b, 0, s, g);
         else hipLaunchKernelGGL((k_gs_update<32, false, TPB>), grid, b, 0, s, g);
+    } else {
         hipLaunchKernelGGL(k_gs_finish, dim3(1), dim3(1024), 0, s, g);
     }
     return hipGetLastError();

@@ -253,7 +253,8 @@ struct GsStep {
     int *ctl;                     // cycle control block (stop flag first)
     int *snap;                    // device address of the host's snapshot slot of step j
 };
-// pass 0: the Jacobian product with the projections; pass 1: the update
+// pass 0: the Jacobian product with the projections; pass 1: the update;
+// pass 2: ||w||, sig_{j+1}, row j + 1 of L, the Givens update and the snapshot
 hipError_t launch_gs_step(const GsStep &g, int pass, hipStream_t s);
 
 // Device-side least squares of one GMRES cycle (see k_givens).

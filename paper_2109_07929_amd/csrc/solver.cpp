@@ -582,7 +582,8 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
                 MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1, slot));
                 MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s, slot));
                 MCA_TRY(launch_gs_step(gs, 1, s));
-                MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 1 <= kGsFusedMaxV ? 2 : 3, slot));
+                MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 1 <= kGsFusedMaxV ? 1 : 2, slot));
+                MCA_TRY(launch_gs_step(gs, 2, s));
             } else {
                 // w = J z_j, fused with the partial sums of <w, v_0>
                 MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
