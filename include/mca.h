@@ -154,6 +154,11 @@ typedef struct mca_stats {
     double  kernel_ms[MCA_NUM_KCLASS];
     int32_t kernel_launches[MCA_NUM_KCLASS];
     int32_t start;                        /* 1: started from the caller's guess, 0: V = 0 */
+    double  err_bound;                    /* certified ||V - V*||_2 <= err_bound: F is the
+                                             gradient of a strongly convex energy (J(V) >=
+                                             blkdiag(G_t, G_b) since dI/du >= 0), so the error
+                                             is at most ||F(V)||_2 / min(lambda_min(G_top),
+                                             lambda_min(G_bot))                             */
 } mca_stats;
 
 typedef struct mca_plan mca_plan;
@@ -161,6 +166,9 @@ typedef struct mca_plan mca_plan;
 void        mca_options_default(mca_options *opts);
 const char *mca_status_string(mca_status s);
 const char *mca_last_error(void);     /* thread-local text of the last MCA_ERR_HIP */
+/* sizeof of the ABI's structs, so that a binding can check its layout:
+ * which 0 = mca_geometry, 1 = mca_options, 2 = mca_stats; 0 for other values. */
+size_t      mca_abi_struct_size(int32_t which);
 
 /* Validate `geom` and build the preconditioner's geometry data on the host:
  * the eigen-decompositions G_top = Q_n diag(lt) Q_n^T (n x n) and

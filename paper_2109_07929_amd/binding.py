@@ -52,7 +52,7 @@ MCA_MAX_NEWTON = 64
 
 # every entry point include/mca.h declares
 ABI_SYMBOLS = (
-    "mca_options_default", "mca_status_string", "mca_last_error",
+    "mca_options_default", "mca_status_string", "mca_last_error", "mca_abi_struct_size",
     "mca_plan_create", "mca_plan_destroy", "mca_plan_host_eigen",
     "mca_plan_device_bytes", "mca_plan_upload", "mca_workspace_bytes",
     "mca_precond_workspace_bytes", "mca_residual", "mca_jacobian_apply",
@@ -84,7 +84,8 @@ class mca_stats(C.Structure):
                 ("residual_history", C.c_double * (MCA_MAX_NEWTON + 1)),
                 ("krylov_history", C.c_int32 * MCA_MAX_NEWTON),
                 ("kernel_ms", C.c_double * MCA_NUM_KCLASS),
-                ("kernel_launches", C.c_int32 * MCA_NUM_KCLASS), ("start", C.c_int32)]
+                ("kernel_launches", C.c_int32 * MCA_NUM_KCLASS), ("start", C.c_int32),
+                ("err_bound", C.c_double)]
 
     def history(self):
         k = self.newton_iters
@@ -118,6 +119,12 @@ def lib():
     L.mca_status_string.restype = C.c_char_p
     L.mca_last_error.argtypes = []
     L.mca_last_error.restype = C.c_char_p
+    L.mca_abi_struct_size.argtypes = [C.c_int32]
+    L.mca_abi_struct_size.restype = C.c_size_t
+    for which, st in enumerate((mca_geometry, mca_options, mca_stats)):
+        if L.mca_abi_struct_size(which) != C.sizeof(st):
+            raise ImportError(f"{LIB_PATH}: {st.__name__} is {L.mca_abi_struct_size(which)} bytes "
+                              f"in the library and {C.sizeof(st)} in the binding")
     L.mca_plan_create.argtypes = [C.POINTER(mca_geometry), PP]
     L.mca_plan_create.restype = i32
     L.mca_plan_destroy.argtypes = [vp]

@@ -1600,6 +1600,8 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
             t.rel_residual = x.ynorm > 0 ? x.fnorm / x.ynorm : 0.0;
             t.a_last = x.a;
             t.start = x.guess;
+            const mca_plan *P = B->plans[B->pidx[b]];
+            t.err_bound = x.fnorm / std::min(P->lt[0], P->lb[0]);
             for (int i = 0; i <= std::min(x.newton, MCA_MAX_NEWTON); ++i)
                 t.residual_history[i] = rh[(size_t)b * (MCA_MAX_NEWTON + 1) + i];
             for (int i = 0; i < std::min(x.newton, MCA_MAX_NEWTON); ++i)

@@ -727,6 +727,16 @@ const char *mca_status_string(mca_status s)
 
 const char *mca_last_error(void) { return g_last_error.c_str(); }
 
+size_t mca_abi_struct_size(int32_t which)
+{
+    switch (which) {
+    case 0: return sizeof(mca_geometry);
+    case 1: return sizeof(mca_options);
+    case 2: return sizeof(mca_stats);
+    default: return 0;
+    }
+}
+
 mca_status mca_plan_create(const mca_geometry *geom, mca_plan **out)
 {
     if (!out) return MCA_ERR_INVALID_ARG;
@@ -1039,6 +1049,7 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
         stats->rel_residual = fnorm / ynorm;
         stats->a_last = a;
         stats->start = from_guess;
+        stats->err_bound = fnorm / std::min(P->lt[0], P->lb[0]);
         for (int c = 0; c < MCA_NUM_KCLASS; ++c) {
             stats->kernel_ms[c] = tm.ms[c];
             stats->kernel_launches[c] = tm.launches[c];

@@ -59,6 +59,9 @@ def test_batch_ragged_vs_oracle(prec):
             f"{list(st.krylov_history[:st.newton_iters])} relres {st.rel_residual:.1e} err {err:.1e}")
         assert st.rel_residual <= 1e-10
         assert err <= TOL
+        # certified bound on the 2-norm error
+        e2 = np.sqrt(np.sum((vts[b] - rt) ** 2) + np.sum((vbs[b] - rb) ** 2))
+        assert e2 <= st.err_bound * (1 + 1e-6) + 1e-13 * np.abs(rt).max()
 
 
 def test_batch_matches_single_solves():

@@ -65,6 +65,21 @@ def test_solve_32x32_seed0(form):
         assert abs(vt[i, j] - t) <= TOL * ref["max_vt"]
 
 
+@pytest.mark.parametrize("m,n,tol", [(32, 32, 1e-10), (70, 130, 1e-10), (48, 40, 1e-5)])
+def test_certified_error_bound(m, n, tol):
+    """stats.err_bound = ||F(V)||_2 / min(lambda_min(G_top), lambda_min(G_bot)) bounds the
+    2-norm error against the oracle's steady state (a loose Newton tolerance leaves a
+    visible error)."""
+    cb = synth.crossbar(m, n, seed=2)
+    vt, vb, status, st = gpu_solve(cb, newton_tol=tol)
+    assert status == B.MCA_OK
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="band")
+    err = np.sqrt(np.sum((vt - rt) ** 2) + np.sum((vb - rb) ** 2))
+    say(f"  {m}x{n} tol {tol:g}: error {err:.2e} bound {st.err_bound:.2e}")
+    assert np.isfinite(st.err_bound) and 0.0 <= st.err_bound
+    assert err <= st.err_bound * (1 + 1e-6) + 1e-13 * np.abs(rt).max()
+
+
 @pytest.mark.parametrize("m,n", [(1, 1), (1, 9), (9, 1), (5, 3), (17, 33), (64, 48), (70, 130)])
 @pytest.mark.parametrize("form", [B.MCA_PRECOND_LITERAL, B.MCA_PRECOND_PERMODE])
 def test_solve_shapes(m, n, form):

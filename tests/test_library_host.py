@@ -29,6 +29,13 @@ def test_header_symbols_are_exported():
         assert hasattr(lib, name), name
 
 
+def test_struct_layouts_match_the_library():
+    lib = B.lib()
+    for which, st in enumerate((B.mca_geometry, B.mca_options, B.mca_stats)):
+        assert lib.mca_abi_struct_size(which) == C.sizeof(st), st.__name__
+    assert lib.mca_abi_struct_size(3) == 0
+
+
 def test_status_strings():
     assert B.status_string(B.MCA_OK) == "ok"
     assert "converged" in B.status_string(B.MCA_ERR_NOT_CONVERGED)
