@@ -129,6 +129,24 @@ def krylov_hbm(st, mn, opts, kms, steps):
             "frac_algorithmic": round(a / HBM_PEAK_GBS, 4), "frac_kernel": round(kb / HBM_PEAK_GBS, 4)}
 
 
+def hbm_copy(out, roofline, kry_hbm, ev0, ev1, stream, dev):
+    import torch
+    big = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    big2 = torch.empty_like(big)
+    for _ in range(2):
+        big2.copy_(big)
+    ev0.record(stream)
+    for _ in range(5):
+        big2.copy_(big)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    out["hbm_copy_GBs"] = round(2 * big.numel() * 8 * 5 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 1)
+    if roofline is not None and roofline.get("unit") == "GB/s":
+        roofline["frac_of_copy"] = round(roofline["achieved"] / out["hbm_copy_GBs"], 4)
+    if kry_hbm is not None:
+        kry_hbm["frac_kernel_of_copy"] = round(kry_hbm["achieved_kernel"] / out["hbm_copy_GBs"], 4)
+
+
 def cpu_baseline(cb):
     """The CPU oracle (plain FP64 C, one thread) on the same crossbar: one full
     Newton solve with CG linear steps (the oracle's large-size method)."""
@@ -475,6 +493,10 @@ def main():
         cmp["best_solves_per_s"] = best
         cmp["speedup_vs_plain_fp64"] = round(best / value, 3)
         out["batched_warm_mixed"] = cmp
+    # measured HBM ceiling: a 1 GiB device-to-device copy (read + write bytes / time);
+    # not in counter runs, whose calibration copy is the only one
+    if not args.copy_calib:
+        hbm_copy(out, roofline, kry_hbm, ev0, ev1, stream, dev)
     if args.copy_calib:
         src = torch.rand(32 << 20, dtype=torch.float64, device=dev)   # 256 MiB
         dst = torch.empty_like(src)
