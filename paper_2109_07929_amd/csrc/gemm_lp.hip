@@ -77,6 +77,16 @@ struct Regs {
     u4 c[Fmt<MODE>::kPlanes][chunks_per_thread<MODE, ROWS, KS>()];
 };
 
+// Operand planes are device (global) memory; loads through these pointers
+// are global loads, which the wait counters track apart from LDS traffic (a
+// generic pointer would give flat loads, whose waits also hold every LDS
+// access behind them).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *global_ptr(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
 template <int MODE, int ROWS, int KS>
 __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int r0, int k0,
                                         bool fast, Regs<MODE, ROWS, KS> &g)
@@ -86,13 +96,14 @@ __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int 
     using E = typename Fmt<MODE>::elem;
 #pragma unroll
     for (int pl = 0; pl < Fmt<MODE>::kPlanes; ++pl) {
-        const E *base = static_cast<const E *>(op.p[pl]);
+        const auto *base = global_ptr(static_cast<const E *>(op.p[pl]));
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int id = threadIdx.x + c * LTPB;
             const int r = r0 + id / CPR, k = k0 + (id % CPR) * PC;
             if (fast) {
-                g.c[pl][c] = *reinterpret_cast<const u4 *>(base + (size_t)r * K + k);
+                g.c[pl][c] = *reinterpret_cast<const __attribute__((address_space(1))) u4 *>(
+                    base + (size_t)r * K + k);
             } else {
                 // clamped element loads; out-of-range elements become zero
                 union {
@@ -186,6 +197,13 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
         for (int b = 0; b < NBB; ++b)
             load_op<MODE, TS, KS>(a.B[b], N, K, n0, k0, fast_n && kin, st.rb[b]);
     };
+    // interior tiles with K a whole number of slices: unconditional 16-byte loads
+    auto load_fast = [&](Stage &st, int k0) {
+#pragma unroll
+        for (int b = 0; b < NA; ++b) load_op<MODE, TS, KS>(a.A[b], M, K, m0, k0, true, st.ra[b]);
+#pragma unroll
+        for (int b = 0; b < NBB; ++b) load_op<MODE, TS, KS>(a.B[b], N, K, n0, k0, true, st.rb[b]);
+    };
     auto stash = [&](const Stage &st, int buf) {
 #pragma unroll
         for (int b = 0; b < NA; ++b) stash_op<MODE, TS, KS>(As[buf][b], st.ra[b]);
@@ -262,12 +280,34 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
     // multiplied, and slice k + 1 moves from registers into the other LDS buffer.
     const int nk = (K + KS - 1) / KS;
     Stage st[DEPTH];
+    int kb = 0;
+    if (fast_m && fast_n && K % KS == 0 && nk >= DEPTH) {
+        // the same ring with the loads' conditions lifted out of the steady
+        // state, so that no branch sits between a load and the wait before
+        // its LDS store and the wait covers only that stage
 #pragma unroll
-    for (int u = 0; u < DEPTH; ++u)
-        if (u < nk) load(st[u], u * KS);
-    stash(st[0], 0);
-    __syncthreads();
-    for (int kb = 0; kb < nk; kb += DEPTH) {
+        for (int u = 0; u < DEPTH; ++u) load_fast(st[u], u * KS);
+        stash(st[0], 0);
+        __syncthreads();
+        for (; kb + 2 * DEPTH < nk + 1; kb += DEPTH) {
+#pragma unroll
+            for (int u = 0; u < DEPTH; ++u) {
+                const int k = kb + u;   // k + DEPTH < nk throughout
+                load_fast(st[u], (k + DEPTH) * KS);
+                __builtin_amdgcn_sched_barrier(0);   // issue the loads before the MFMAs
+                compute(k & 1);
+                stash(st[(u + 1) % DEPTH], (k + 1) & 1);
+                __syncthreads();
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u)
+            if (u < nk) load(st[u], u * KS);
+        stash(st[0], 0);
+        __syncthreads();
+    }
+    for (; kb < nk; kb += DEPTH) {
 #pragma unroll
         for (int u = 0; u < DEPTH; ++u) {
             const int k = kb + u;
@@ -293,7 +333,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
                 const size_t o = (size_t)row * N + col;
                 if constexpr (EPI == EPI_PERMODE) {
                     // mode (p, q) = (col, row): [[lt + a1, -a1], [-a2, lb + a2]] x = r
-                    const double lt = a.lam_row[row], lb = a.lam_col[col];
+                    const double lt = global_ptr(a.lam_row)[row], lb = global_ptr(a.lam_col)[col];
                     const double det = lt * lb + a.a2 * lt + a.a1 * lb;
                     const double rt = acc[0][i][j][r], rb = acc[NB - 1][i][j][r];
                     put(a, 0, o, ((lb + a.a2) * rt + a.a1 * rb) / det, OUT);
