@@ -266,6 +266,8 @@ def bench_batched(args):
                    "krylov_iters": [min(krylov), max(krylov)]},
         "per_crossbar_loop": loop,
         "eager_launches": eager,
+        # with the batch's host set-up (eigen-decompositions, upload) counted once
+        "solves_per_s_with_setup": round(count * 1e3 / (ms_per_step + setup_ms), 2),
         "roofline": None,
     }
     print(json.dumps(out), flush=True)
