@@ -254,6 +254,11 @@ struct BGs {
     double *H;                  // per crossbar hsize, column-major ld ldh
     int R, ldh, hsize, j;
     double *p1, *p2;
+    // with xp[0] set, the update pass also writes the new vector in the
+    // preconditioner's operand format (FP32, or bfloat16 hi [+ lo]), the
+    // conversion the next step's chain would otherwise make of it
+    void *xp[2];
+    int prec;
     double *g, *cs, *sn;        // Givens state, per crossbar
     const BState *S;
     int *run;                   // per crossbar: 1 while its cycle runs
@@ -362,6 +367,17 @@ __global__ __launch_bounds__(TPB) void bk_gs_update(BGs a)
                 x -= c[q] * vq[q];
             }
             a.W[e] = x;
+            if (a.xp[0]) {   // as k_split: FP64 -> FP32 -> bfloat16 hi, lo = rest
+                const float f = (float)x;
+                if (a.prec == MCA_PREC_FP32) {
+                    static_cast<float *>(a.xp[0])[e] = f;
+                } else {
+                    const __bf16 hi = (__bf16)f;
+                    static_cast<__bf16 *>(a.xp[0])[e] = hi;
+                    if (a.prec == MCA_PREC_BF16X3)
+                        static_cast<__bf16 *>(a.xp[1])[e] = (__bf16)(f - (float)hi);
+                }
+            }
 #pragma unroll
             for (int q = 0; q < MAXV; ++q) acc[q] += x * vq[q];
             acc[MAXV] += x * x;
@@ -1403,6 +1419,9 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     gs.sn = w.sn;
     gs.S = w.S;
     gs.run = w.run;
+    gs.xp[0] = w.x.p[0];
+    gs.xp[1] = w.x.p[1];
+    gs.prec = o.precision;
     // Arnoldi step j of every crossbar still in its cycle: preconditioner,
     // Jacobian product fused with <w, v_0>, the projection passes, the
     // normalisation, the Givens update, and the count of running cycles
@@ -1413,6 +1432,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         GroupedChain c = gc;
         c.r = vj;
         c.z = zj;
+        c.r_split = (two_pass && j > 0) ? 1 : 0;   // the previous update pass converted v_j
         hipError_t e = launch_precond_lowprec_grouped(o.precision, c, q);
         if (e != hipSuccess) return e;
         if (two_pass) {

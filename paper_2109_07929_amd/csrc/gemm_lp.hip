@@ -459,7 +459,7 @@ hipError_t chain(const LowPrecChain &c, hipStream_t s)
         return ok ? 1 : 0;
     };
     // 0. r (FP64) -> operand format
-    {
+    if (!c.r_split) {
         const int blocks = (int)std::min<size_t>((mn + 255) / 256, 4096);
         hipLaunchKernelGGL(k_split<MODE>, dim3(blocks), dim3(256), 0, s, c.rt, c.rb, mn,
                            c.x[0].p[0], c.x[0].p[1], c.x[1].p[0], c.x[1].p[1], c.skip);
@@ -522,7 +522,7 @@ hipError_t chain_grouped(const GroupedChain &c, hipStream_t s)
 {
     constexpr int OUT = (MODE == MCA_PREC_FP32) ? OUT_F32 : (MODE == MCA_PREC_BF16X3) ? OUT_BF2 : OUT_BF1;
     const size_t es = (MODE == MCA_PREC_FP32) ? 4 : 2;
-    {
+    if (!c.r_split) {
         const int blocks = (int)std::min<size_t>((c.len + 255) / 256, 8192);
         hipLaunchKernelGGL(k_split<MODE>, dim3(blocks), dim3(256), 0, s, c.r, nullptr, c.len,
                            c.x.p[0], c.x.p[1], nullptr, nullptr, nullptr);

@@ -497,6 +497,24 @@ __global__ __launch_bounds__(NT) void k_gs_update(GsStep a)
             x.y -= c[q] * vq[q].y;
         }
         w2[k] = x;
+        if (a.xp[0][0]) {   // as k_split: FP64 -> FP32 -> bfloat16 hi, lo = rest
+            const size_t mn = (size_t)a.m * a.n;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                size_t e = 2 * k + h;
+                const int layer = e < mn ? 0 : 1;
+                e -= layer * mn;
+                const float f = (float)(h ? x.y : x.x);
+                if (a.prec == MCA_PREC_FP32) {
+                    static_cast<float *>(a.xp[layer][0])[e] = f;
+                } else {
+                    const __bf16 hi = (__bf16)f;
+                    static_cast<__bf16 *>(a.xp[layer][0])[e] = hi;
+                    if (a.prec == MCA_PREC_BF16X3)
+                        static_cast<__bf16 *>(a.xp[layer][1])[e] = (__bf16)(f - (float)hi);
+                }
+            }
+        }
 #pragma unroll
         for (int q = 0; q < MAXV; ++q) acc[q] += x.x * vq[q].x + x.y * vq[q].y;
         acc[MAXV] += x.x * x.x + x.y * x.y;

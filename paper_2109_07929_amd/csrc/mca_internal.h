@@ -138,6 +138,7 @@ struct LowPrecChain {
     LpPlanes QnT, QmT, Qm, Qn;          // eigenbases
     const double *lt, *lb;              // eigenvalues of G_top, G_bot
     const double *rt, *rb;              // input r (FP64)
+    int r_split;                        // x already holds r in operand format
     LpPlanes x[2], u[2], w[2];          // workspace: split r and two intermediates, m*n each
     double *zt, *zb;                    // output z (FP64)
 };
@@ -172,6 +173,7 @@ struct GroupedChain {
     int tile;                           // tile edge of the tables: 64 or 128
     const double *r;
     size_t len;
+    int r_split;                        // x already holds r in operand format
     LpPlanes x, u, w;
     double *z;
     const double *a_inst;
@@ -252,6 +254,11 @@ struct GsStep {
     double abs_tol;
     int *ctl;                     // cycle control block (stop flag first)
     int *snap;                    // device address of the host's snapshot slot of step j
+    // with xp[0][0] set, the update pass also writes the new vector in the
+    // reduced-precision preconditioner's operand format (per layer: FP32, or
+    // bfloat16 hi [+ lo]), the conversion the next step's chain would make
+    void *xp[2][2];
+    int prec;
 };
 // pass 0: the Jacobian product with the projections; pass 1: the update;
 // pass 2: ||w||, sig_{j+1}, row j + 1 of L, the Givens update and the snapshot

@@ -353,7 +353,7 @@ mca_status precond_setup(const mca_plan *P, int form, double a1, double a2, cons
 mca_status precond_run(const mca_plan *P, int form, int precision, double a1, double a2,
                        const double *rt, const double *rb, double *zt, double *zb,
                        const PrecondWs &w, hipStream_t s, Timing *tm = nullptr, int slot = 0,
-                       const int *skip = nullptr, const double *D = nullptr)
+                       const int *skip = nullptr, const double *D = nullptr, bool r_split = false)
 {
     Timing off;
     if (!tm) tm = &off;
@@ -397,6 +397,7 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
         }
         c.lt = d.lt; c.lb = d.lb;
         c.rt = rt; c.rb = rb;
+        c.r_split = r_split ? 1 : 0;
         for (int b = 0; b < 2; ++b) {
             c.x[b] = w.lp[b];
             c.u[b] = w.lp[2 + b];
@@ -405,7 +406,7 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
         c.zt = zt; c.zb = zb;
         MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
         MCA_TRY(launch_precond_lowprec(precision, c, s));
-        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 5, slot));   // operand split + 4 products
+        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, r_split ? 4 : 5, slot));   // operand split + 4 products
         return MCA_OK;
     }
     const int m = P->geom.m, n = P->geom.n;
@@ -547,6 +548,15 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
     gs.resid = w.resid;
     gs.abs_tol = abs_tol;
     gs.ctl = w.ctl;
+    // the reduced-precision per-mode chain: the update pass converts the new
+    // vector into the chain's operand planes itself
+    const bool lp_fused = two_pass && o->precond == MCA_PRECOND_PERMODE &&
+                          o->precision != MCA_PREC_FP64;
+    if (lp_fused) {
+        for (int b = 0; b < 2; ++b)
+            for (int pl = 0; pl < 2; ++pl) gs.xp[b][pl] = w.pw.lp[b].p[pl];
+        gs.prec = o->precision;
+    }
     int its = 0, restarts = 0;
     bool converged = false, first = true;
     // v_0 = -F / ||F||
@@ -564,8 +574,10 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
             double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
             double *wv = w.V + (size_t)(j + 1) * len;
             const int *skip = w.ctl;
+            // (the previous step's update pass left v_j in operand format)
             mca_status st = precond_run(P, o->precond, o->precision, a, a, vj, vj + mn, zj,
-                                        zj + mn, w.pw, s, tm, slot, skip, w.D);
+                                        zj + mn, w.pw, s, tm, slot, skip, w.D,
+                                        lp_fused && j > 0);
             if (st != MCA_OK) return st;
             double *hcol = w.H + (size_t)j * ldh;
             if (two_pass) {
