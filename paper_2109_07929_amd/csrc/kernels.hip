@@ -542,24 +542,95 @@ __global__ __launch_bounds__(NT) void k_gs_update(GsStep a)
 
 // One block of 1024 threads: ||x|| and <x, u_q> from the partials give
 // H[j+1][j] = ||x||, sig_{j+1} and row j + 1 of L; then the Givens update of
-// column j.
+// column j and the snapshot.  Every load the block needs (the stop flag, the
+// partials, Hessenberg column j, the rotations, g[j], the scales) is issued
+// before any of them is used: the kernel is a chain of dependent steps, and
+// that keeps it to one memory round trip before the arithmetic.
 __global__ __launch_bounds__(1024) void k_gs_finish(GsStep a)
 {
-    if (*a.ctl) {   // a stopped cycle: the snapshot only
-        if (threadIdx.x == 0) write_snapshot(a.snap, a.ctl);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int j = a.j, nv = j + 1;
+    const int nb = (nv <= kGsFusedMaxV) ? kProjBlocks : kGsBlocks;
+    const int stop = a.ctl[0];
+    double v[kGsMaxV + 1];
+#pragma unroll
+    for (int q = 0; q <= kGsMaxV; ++q) v[q] = (q <= nv && t < nb) ? a.p2[(size_t)q * nb + t] : 0.0;
+    __shared__ double hs[MCA_MAX_RESTART + 1], cz[MCA_MAX_RESTART], sz[MCA_MAX_RESTART];
+    __shared__ double sgs[kGsMaxV + 1], gj;
+    if (t <= j) {
+        hs[t] = a.hcol[t];
+        sgs[t] = a.sig[t];
+        if (t < j) {
+            cz[t] = a.cs[t];
+            sz[t] = a.sn[t];
+        }
+    }
+    if (t == 0) gj = a.g[j];
+    if (stop) {   // a stopped cycle: the snapshot only
+        if (t == 0) write_snapshot(a.snap, a.ctl);
         return;
     }
-    const int j = a.j, nv = j + 1;
+    // fixed-order sums of the partials: waves, then the 16 wave sums
+    __shared__ double red[kGsMaxV + 1][16];
     __shared__ double sv[kGsMaxV + 1];
-    sum_partials_1024(a.p2, nv + 1, (nv <= kGsFusedMaxV) ? kProjBlocks : kGsBlocks, sv);
+#pragma unroll
+    for (int q = 0; q <= kGsMaxV; ++q) {
+        if (q <= nv) {
+            const double x = dev::wave_sum(v[q]);
+            if (lane == 0) red[q][wave] = x;
+        }
+    }
+    __syncthreads();
+    if (t <= nv) {
+        double x = 0.0;
+        for (int w = 0; w < 16; ++w) x += red[t][w];
+        sv[t] = x;
+    }
+    __syncthreads();
     const double nrm = sqrt(sv[nv]);
     const double inv = (nrm > 0.0) ? 1.0 / nrm : 0.0;
     // row j + 1 of L: <v_{j+1}, v_q> = sig_q <x, u_q> / ||x||
-    if (threadIdx.x < nv)
-        a.L[(size_t)(j + 1) * a.ldl + threadIdx.x] = sv[threadIdx.x] * a.sig[threadIdx.x] * inv;
-    if (threadIdx.x == 0) a.sig[j + 1] = inv;
-    givens_block(a.H, a.ldh, j, nrm, a.g, a.cs, a.sn, a.abs_tol, a.ctl, a.resid);
-    if (threadIdx.x == 0) write_snapshot(a.snap, a.ctl);
+    if (t < nv) a.L[(size_t)(j + 1) * a.ldl + t] = sv[t] * sgs[t] * inv;
+    if (t != 0) return;
+    a.sig[j + 1] = inv;
+    // Givens update of column j (hs: h[0..j], h[j+1] = nrm)
+    int *ctl = a.ctl;
+    double *h = a.hcol;
+    bool bad = !isfinite(nrm);
+    for (int i = 0; i <= j; ++i) bad = bad || !isfinite(hs[i]);
+    if (bad) {
+        ctl[0] = 1;
+        ctl[2] = CYCLE_NONFINITE;
+    } else {
+        for (int i = 0; i < j; ++i) {   // rotation i mixes rows i and i + 1 <= j
+            const double u = cz[i] * hs[i] + sz[i] * hs[i + 1];
+            hs[i + 1] = -sz[i] * hs[i] + cz[i] * hs[i + 1];
+            hs[i] = u;
+        }
+        for (int i = 0; i < j; ++i) h[i] = hs[i];
+        const double r = hypot(hs[j], nrm);
+        if (r == 0.0) {
+            h[j] = hs[j];
+            h[j + 1] = nrm;
+            ctl[0] = 1;
+            ctl[2] = CYCLE_BREAKDOWN;
+        } else {
+            const double c = hs[j] / r, sn = nrm / r;
+            a.cs[j] = c;
+            a.sn[j] = sn;
+            h[j] = r;
+            h[j + 1] = 0.0;
+            a.g[j + 1] = -sn * gj;
+            a.g[j] = c * gj;
+            ctl[1] = j + 1;
+            a.resid[j] = fabs(sn * gj);
+            if (fabs(sn * gj) <= a.abs_tol) {   // includes nrm == 0 (invariant subspace)
+                ctl[0] = 1;
+                ctl[2] = CYCLE_CONVERGED;
+            }
+        }
+    }
+    write_snapshot(a.snap, ctl);
 }
 
 // ------------------------------------------- least squares on the device
