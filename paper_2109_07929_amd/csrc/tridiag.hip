@@ -28,7 +28,6 @@ namespace {
 using dev::TPB;
 
 constexpr int kLds = kPcrMaxLen;            // doubles of one workgroup's lines
-constexpr int kEpt = kLds / TPB;            // elements per thread
 
 // diagonal / couplings of (wire + shift I) at level 0
 __global__ __launch_bounds__(TPB) void k_pcr_init(Wire w, double shift, double *__restrict__ a,
@@ -70,6 +69,13 @@ __global__ __launch_bounds__(TPB) void k_pcr_final(int len, const double *__rest
     for (int k = blockIdx.x * TPB + threadIdx.x; k < len; k += gridDim.x * TPB) invb[k] = 1.0 / b[k];
 }
 
+// Workgroup ids are dispatched round-robin over the 8 XCDs; this order gives
+// every XCD a contiguous run of ids.
+__device__ __forceinline__ int xcd_order(int bid, int nwg)
+{
+    return (nwg % 8 == 0) ? (bid % 8) * (nwg / 8) + bid / 8 : bid;
+}
+
 // Solve T x = in (+ in2_scale * in2) for `lines` lines of length len.
 // Element k of line l sits at l * line_stride + k * elem_stride.  A workgroup
 // holds lpw consecutive lines in LDS, ordered as in memory: line-major when the
@@ -85,22 +91,23 @@ struct PcrSolveArgs {
     const int *skip;
 };
 
-// EPT elements per thread (E = len * lpw <= EPT * TPB); LDS sized to E at
-// launch.  Each thread's (k, line) pairs are fixed for the whole solve, and the
+// NT threads of EPT elements each (E = len * lpw <= EPT * NT); LDS sized to E
+// at launch.  Workgroups are taken in XCD order, so the lpw-line groups that
+// share cache lines (adjacent columns) are solved on one XCD (one L2).  Each thread's (k, line) pairs are fixed for the whole solve, and the
 // next level's multipliers are loaded while the current level is applied.
-template <int EPT>
-__global__ __launch_bounds__(TPB) void k_pcr_solve(PcrSolveArgs p)
+template <int EPT, int NT>
+__global__ __launch_bounds__(NT) void k_pcr_solve(PcrSolveArgs p)
 {
     if (p.skip && *p.skip) return;
     extern __shared__ double d[];
     const int len = p.len, lpw = p.lpw, E = len * lpw;
-    const int line0 = blockIdx.x * lpw;
+    const int line0 = xcd_order(blockIdx.x, gridDim.x) * lpw;
     const int kst = p.rows ? 1 : lpw;      // LDS distance between elements k and k + 1
     int kk[EPT];
     bool valid[EPT];
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
-        const int e = threadIdx.x + r * TPB;
+        const int e = threadIdx.x + r * NT;
         int k = 0, l = 0;
         if (e < E) {
             if (p.rows) {
@@ -133,7 +140,7 @@ __global__ __launch_bounds__(TPB) void k_pcr_solve(PcrSolveArgs p)
         double nd[EPT];
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
-            const int e = threadIdx.x + r * TPB;
+            const int e = threadIdx.x + r * NT;
             if (e < E) {
                 const int k = kk[r];
                 double v = d[e];
@@ -154,14 +161,14 @@ __global__ __launch_bounds__(TPB) void k_pcr_solve(PcrSolveArgs p)
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < EPT; ++r) {
-            const int e = threadIdx.x + r * TPB;
+            const int e = threadIdx.x + r * NT;
             if (e < E) d[e] = nd[r];
         }
         __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < EPT; ++r) {
-        const int e = threadIdx.x + r * TPB;
+        const int e = threadIdx.x + r * NT;
         if (valid[r]) {
             const int l = p.rows ? e / len : e - kk[r] * lpw;
             p.out[(size_t)(line0 + l) * p.line_stride + (size_t)kk[r] * p.elem_stride] =
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(TPB) void k_line_solve(LineSolveArgs p)
 {
     __shared__ double sa[kVarMax], sb[kVarMax], sc[kVarMax], sd[kVarMax];
     const int len = p.len, lpw = p.lpw, E = len * lpw;
-    const int line0 = blockIdx.x * lpw;
+    const int line0 = xcd_order(blockIdx.x, gridDim.x) * lpw;
     const int kst = p.rows ? 1 : lpw;
     auto coords = [&](int e, int &k, int &l) {
         if (p.rows) {
@@ -390,11 +397,15 @@ hipError_t launch_pcr_solve(const PcrTables &t, int lines, bool rows, size_t lin
     p.skip = skip;
     const size_t lds = (size_t)t.len * p.lpw * sizeof(double);
     const dim3 grid((lines + p.lpw - 1) / p.lpw);
-    // (loading every level's multipliers up front measured slower)
-    if (t.len * p.lpw <= 8 * TPB)
-        hipLaunchKernelGGL(k_pcr_solve<8>, grid, dim3(TPB), lds, s, p);
+    // (loading every level's multipliers up front measured slower; so did
+    // 32 elements per thread, which spills)
+    const int E = t.len * p.lpw;
+    if (E <= 8 * TPB)
+        hipLaunchKernelGGL((k_pcr_solve<8, TPB>), grid, dim3(TPB), lds, s, p);
+    else if (E <= 8 * 512)
+        hipLaunchKernelGGL((k_pcr_solve<8, 512>), grid, dim3(512), lds, s, p);
     else
-        hipLaunchKernelGGL(k_pcr_solve<kEpt>, grid, dim3(TPB), lds, s, p);
+        hipLaunchKernelGGL((k_pcr_solve<8, 1024>), grid, dim3(1024), lds, s, p);
     return hipGetLastError();
 }
 

@@ -156,7 +156,7 @@ def test_precond_inverts_P_at_1024(form):
     assert err <= (1e-9 if form == B.MCA_PRECOND_PERMODE else 1e-5)
 
 
-APPROX_SHAPES = SHAPES + [(300, 77), (3, 8192), (8192, 3)]
+APPROX_SHAPES = SHAPES + [(300, 77), (40, 3000), (3, 8192), (8192, 3)]
 
 
 @pytest.mark.parametrize("m,n", APPROX_SHAPES)
