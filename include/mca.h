@@ -93,6 +93,13 @@ typedef int32_t mca_status;
                                      written) instead of the default two passes per step
                                      (the same projections in compact WY form, restart
                                      <= 32); the two give the same h up to rounding     */
+#define MCA_FLAG_TIMING_SAMPLED 64 /* mca_solve times only the preconditioner class
+                                     (MCA_KCLASS_GEMM), on every 4th application: a timed
+                                     event between dependent kernels leaves the GPU idle for
+                                     a few microseconds, so timing every group slows the
+                                     solve; kernel_ms / kernel_launches of the sampled
+                                     groups is the average launch time (MCA_FLAG_TIMING,
+                                     if also set, times every group)                  */
 
 /* Kernel classes timed under MCA_FLAG_TIMING (mca_stats.kernel_ms / kernel_launches). */
 #define MCA_KCLASS_GEMM      0    /* eigenbasis transforms of the preconditioner          */
@@ -150,7 +157,8 @@ typedef struct mca_stats {
     int32_t krylov_history[MCA_MAX_NEWTON];       /* GMRES iterations of each step       */
     /* MCA_FLAG_TIMING only (zero otherwise): GPU time of each kernel class between
      * HIP events recorded on the solve's stream around each group of launches, and
-     * the number of kernel launches in those groups.                             */
+     * the number of kernel launches in those groups (MCA_FLAG_TIMING_SAMPLED: the
+     * sampled preconditioner groups only).                                       */
     double  kernel_ms[MCA_NUM_KCLASS];
     int32_t kernel_launches[MCA_NUM_KCLASS];
     int32_t start;                        /* 1: started from the caller's guess, 0: V = 0 */
@@ -298,7 +306,8 @@ size_t     mca_batch_workspace_bytes(const mca_batch *batch, const mca_options *
 /* Steady state of every crossbar of the batch (as mca_solve, per crossbar).
  * g_dev, v_in, v_t, v_b: concatenated device arrays (see above); v_t/v_b
  * carry the initial guesses with MCA_FLAG_INITIAL_GUESS.  stats: host array
- * of count records (may be NULL).  MCA_FLAG_TIMING is accepted and ignored.
+ * of count records (may be NULL).  MCA_FLAG_TIMING and MCA_FLAG_TIMING_SAMPLED
+ * are accepted and ignored.
  * The batch keeps pinned host counters and, with MCA_FLAG_GRAPH, the captured
  * Arnoldi steps (dropped when the workspace address, precision, restart
  * length or uploaded block change): calls on one batch must not overlap.

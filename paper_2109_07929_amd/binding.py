@@ -42,6 +42,7 @@ MCA_FLAG_GUESS_FALLBACK = 4
 MCA_FLAG_SWEEP_START = 8
 MCA_FLAG_GRAPH = 16
 MCA_FLAG_MGS_PASSES = 32
+MCA_FLAG_TIMING_SAMPLED = 64
 MCA_KCLASS_GEMM = 0
 MCA_KCLASS_JACOBIAN = 1
 MCA_KCLASS_ORTHO = 2

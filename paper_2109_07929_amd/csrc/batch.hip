@@ -1110,7 +1110,8 @@ mca_status batch_options_ok(const mca_options *o)
         o->precision != MCA_PREC_BF16)
         return MCA_ERR_INVALID_ARG;
     if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING | MCA_FLAG_GUESS_FALLBACK |
-                     MCA_FLAG_SWEEP_START | MCA_FLAG_GRAPH | MCA_FLAG_MGS_PASSES))
+                     MCA_FLAG_SWEEP_START | MCA_FLAG_GRAPH | MCA_FLAG_MGS_PASSES |
+                     MCA_FLAG_TIMING_SAMPLED))
         return MCA_ERR_INVALID_ARG;
     if ((o->flags & MCA_FLAG_INITIAL_GUESS) && (o->flags & MCA_FLAG_SWEEP_START))
         return MCA_ERR_INVALID_ARG;

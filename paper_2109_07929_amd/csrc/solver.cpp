@@ -81,7 +81,7 @@ mca_status validate_options(const mca_options *o)
         o->precond != MCA_PRECOND_NONE)
         return MCA_ERR_INVALID_ARG;
     if (o->flags & ~(MCA_FLAG_INITIAL_GUESS | MCA_FLAG_TIMING | MCA_FLAG_GUESS_FALLBACK |
-                     MCA_FLAG_SWEEP_START | MCA_FLAG_MGS_PASSES))
+                     MCA_FLAG_SWEEP_START | MCA_FLAG_MGS_PASSES | MCA_FLAG_TIMING_SAMPLED))
         return MCA_ERR_INVALID_ARG;
     if ((o->flags & MCA_FLAG_INITIAL_GUESS) && (o->flags & MCA_FLAG_SWEEP_START))
         return MCA_ERR_INVALID_ARG;
@@ -283,17 +283,22 @@ bool plan_ready(const mca_plan *P) { return P && P->dev_buf != nullptr; }
 // launches.  Two slots alternate between consecutive Arnoldi steps (the host
 // runs one step ahead); a slot is collected once its step has completed, and
 // counted only if the step ran (a step skipped after convergence is not).
+// Sampled mode: only the preconditioner class, every kSampleStride-th group.
 struct Timing {
     static constexpr int kSlots = 2;
-    bool on = false;
+    static constexpr int kSampleStride = 4;
+    bool on = false, sampled = false;
+    unsigned gemm_groups = 0;
     hipEvent_t ev[kSlots][MCA_NUM_KCLASS][2] = {};
+    bool active[kSlots][MCA_NUM_KCLASS] = {};
     int pending[kSlots][MCA_NUM_KCLASS] = {};
     double ms[MCA_NUM_KCLASS] = {};
     int launches[MCA_NUM_KCLASS] = {};
 
-    hipError_t init()
+    hipError_t init(bool sample = false)
     {
         on = true;
+        sampled = sample;
         for (auto &sl : ev)
             for (auto &c : sl)
                 for (auto &e : c) {
@@ -311,11 +316,17 @@ struct Timing {
     }
     hipError_t begin(int c, hipStream_t s, int slot = 0)
     {
-        return on ? hipEventRecord(ev[slot][c][0], s) : hipSuccess;
+        if (!on) return hipSuccess;
+        bool take = true;
+        if (sampled)
+            take = c == MCA_KCLASS_GEMM && gemm_groups++ % kSampleStride == 0;
+        active[slot][c] = take;
+        return take ? hipEventRecord(ev[slot][c][0], s) : hipSuccess;
     }
     hipError_t end(int c, hipStream_t s, int nlaunch, int slot = 0)
     {
-        if (!on) return hipSuccess;
+        if (!on || !active[slot][c]) return hipSuccess;
+        active[slot][c] = false;
         pending[slot][c] = nlaunch;
         return hipEventRecord(ev[slot][c][1], s);
     }
@@ -988,7 +999,8 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
         MCA_TRY(launch_fill(Vc, 0.0, len, s));
     }
     Timing tm;
-    if (o.flags & MCA_FLAG_TIMING) MCA_TRY(tm.init());
+    if (o.flags & (MCA_FLAG_TIMING | MCA_FLAG_TIMING_SAMPLED))
+        MCA_TRY(tm.init(!(o.flags & MCA_FLAG_TIMING)));
     double fnorm = 0.0, dsum = 0.0;
     SolveWs wk = w;
     st = residual_norms(P, g_dev, v_in, Vc, Vc + mn, F, D, wk, s, &tm, &fnorm, &dsum);

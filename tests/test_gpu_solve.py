@@ -134,6 +134,39 @@ def test_solve_with_restarts(restart):
     assert err <= TOL
 
 
+def test_kernel_timing_changes_nothing():
+    """MCA_FLAG_TIMING and MCA_FLAG_TIMING_SAMPLED leave the solve bit-identical;
+    the first reports every class with a plausible time, the second only the
+    preconditioner groups of every 4th application."""
+    cb = synth.crossbar(96, 80, seed=4)
+    a = gpu_solve(cb)
+    b = gpu_solve(cb, flags=B.MCA_FLAG_TIMING)
+    assert a[2] == b[2] == B.MCA_OK
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    st = b[3]
+    assert list(a[3].kernel_ms) == [0.0] * B.MCA_NUM_KCLASS
+    its = st.krylov_iters
+    say(f"  ms {list(st.kernel_ms)} launches {list(st.kernel_launches)} its {its}")
+    # one preconditioner application (4 or 5 transform launches) and one Jacobian
+    # pass per GMRES iteration, a residual per Newton step
+    assert st.kernel_launches[B.MCA_KCLASS_GEMM] in (4 * its, 5 * its)
+    assert st.kernel_launches[B.MCA_KCLASS_JACOBIAN] >= its
+    assert st.kernel_launches[B.MCA_KCLASS_RESIDUAL] >= st.newton_iters
+    for c in range(B.MCA_NUM_KCLASS):
+        assert 0.0 < st.kernel_ms[c] < 1e3
+    # sampled: only the preconditioner groups of every 4th application
+    c = gpu_solve(cb, flags=B.MCA_FLAG_TIMING_SAMPLED)
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    sc = c[3]
+    per_app = st.kernel_launches[B.MCA_KCLASS_GEMM] // its
+    apps = sc.kernel_launches[B.MCA_KCLASS_GEMM] // per_app
+    assert sc.kernel_launches[B.MCA_KCLASS_GEMM] == apps * per_app
+    assert its // 4 - 1 <= apps <= (its + 3) // 4 + st.newton_iters
+    assert sc.kernel_ms[B.MCA_KCLASS_GEMM] > 0.0
+    for k in (B.MCA_KCLASS_JACOBIAN, B.MCA_KCLASS_ORTHO, B.MCA_KCLASS_RESIDUAL):
+        assert sc.kernel_ms[k] == 0.0 and sc.kernel_launches[k] == 0
+
+
 def test_first_newton_step_is_the_linear_solve():
     """From V = 0 the first Newton step is J(0)^{-1} Y: GMRES at tolerance 1e-10
     must reproduce the oracle's direct solve of that system."""
