@@ -65,6 +65,44 @@ struct Stage {
     double2 r[H][2];
 };
 
+// Epilogue: accumulator element r of lane l is row l/16 + 4r, column l%16 of
+// its 16 x 16 tile (the f64 16x16x4 layout, checked on gfx950).
+template <int NB, int EPI, int WJ>
+__device__ __forceinline__ void store_tile(const GemmArgs &a, const d4 (&acc)[NB][2][WJ], int m0,
+                                           int n0, int wm, int wn, int lane)
+{
+    const int M = a.M, N = a.N;
+    const double inv_a1 = (EPI != EPI_STORE) ? 1.0 / a.a1 : 0.0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < WJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+                const int col = n0 + wn + j * 16 + (lane & 15);
+                if (row >= M || col >= N) continue;
+                const size_t ldo = a.ldo ? (size_t)a.ldo : (size_t)N;
+                const size_t o = (size_t)row * ldo + col;
+                if constexpr (EPI == EPI_STORE) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) (b == 0 ? a.O0 : a.O1)[o] = acc[b][i][j][r];
+                } else if constexpr (EPI == EPI_DIV_MU) {
+                    // eigenvalue of M (eq. (M)) for mode (row, col), summed without cancellation
+                    const double lb = a.lb[row], lt = a.lt[col];
+                    const double mu = lb * lt * inv_a1 + lb + a.a2 * inv_a1 * lt;
+                    a.O0[o] = acc[0][i][j][r] / mu;
+                } else {
+                    // per-mode block solve [[lt + a1, -a1], [-a2, lb + a2]] x = r
+                    const double lb = a.lb[row], lt = a.lt[col];
+                    const double det = lt * lb + a.a2 * lt + a.a1 * lb;
+                    const double rt = acc[0][i][j][r], rb = acc[NB - 1][i][j][r];
+                    a.O0[o] = ((lb + a.a2) * rt + a.a1 * rb) / det;
+                    a.O1[o] = (a.a2 * rt + (lt + a.a1) * rb) / det;
+                }
+            }
+}
+
 // WAVES = 4: 2 x 2 waves of 32 x 32 (2 x 2 MFMA tiles each), one wave per SIMD.
 // WAVES = 8: 2 x 4 waves of 32 x 16 (2 x 1 MFMA tiles each), two waves per
 // SIMD, so that one wave's LDS reads overlap the other's MFMAs.
@@ -245,37 +283,119 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
     }
     if (kt < nk) compute(kt & 1);
 
-    // epilogue: accumulator element r of lane l is row l/16 + 4r, column l%16
-    // (the f64 16x16x4 layout, checked on gfx950)
-    const double inv_a1 = (EPI != EPI_STORE) ? 1.0 / a.a1 : 0.0;
+    store_tile<NB, EPI, WJ>(a, acc, m0, n0, wm, wn, lane);
+}
+
+// Direct-to-LDS variant for whole tiles (M, N multiples of 64, K a multiple of
+// 128, 16-byte aligned rows, one batch): every K slice moves from global memory
+// into LDS by global_load_lds_dwordx4 (16 bytes per lane, 1 KB per wave
+// instruction, no register staging), four slices deep in four LDS buffers of
+// 32 KB.  A wave's instruction fills two consecutive slice rows in LDS order;
+// each lane picks the global columns that land in the swizzled layout of
+// swz().  One barrier per slice: after it, the buffer computed one slice
+// earlier is free and takes the slice three ahead.
+struct DmaSlice {
+    double l[32][64];
+    double r[32][64];
+};
+
+template <int EPI>
+__global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
+{
+    int bid = blockIdx.x, nwg = gridDim.x;
+    if (a.pair) {
+        nwg >>= 1;
+        if (bid >= nwg) {
+            bid -= nwg;
+            a.L0 = a.L1;
+            a.R = a.R1;
+            a.O0 = a.O1;
+        }
+    }
+    // four distinct objects, so that the compiler's wait for LDS DMA before a
+    // read of one buffer does not count the loads still filling the others
+    __shared__ DmaSlice S0, S1, S2, S3;
+    if (a.skip && *a.skip) return;   // uniform: a converged GMRES cycle
+
+    const int M = a.M, N = a.N, K = a.K;
+    int tm, tn;
+    tile_of(bid, nwg, M / BM, N / BN, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave / 4) * 32, wn = (wave % 4) * 16;
+
+    // wave w fills slice rows 4w .. 4w + 3, two per instruction
+    const int prow = 4 * wave;
+    const double *lsrc[2], *rsrc[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int t = 0; t < 2; ++t) {
+        const int row = prow + 2 * t + (lane >> 5);
+        const int col = (2 * (lane & 31)) ^ ((row & 1) << 4);   // swz() is an involution
+        lsrc[t] = a.L0 + (size_t)row * M + m0 + col;
+        rsrc[t] = a.R + (size_t)row * N + n0 + col;
+    }
+    const size_t lstep = (size_t)32 * M, rstep = (size_t)32 * N;
+    typedef const void __attribute__((address_space(1))) *gptr;
+    typedef void __attribute__((address_space(3))) *lptr;
+    auto issue = [&](DmaSlice &S, int kt) {
 #pragma unroll
-        for (int j = 0; j < WJ; ++j)
+        for (int t = 0; t < 2; ++t) {
+            __builtin_amdgcn_global_load_lds((gptr)(lsrc[t] + kt * lstep),
+                                             (lptr)&S.l[prow + 2 * t][0], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((gptr)(rsrc[t] + kt * rstep),
+                                             (lptr)&S.r[prow + 2 * t][0], 16, 0, 0);
+        }
+    };
+
+    d4 acc[1][2][1];
+    acc[0][0][0] = d4{0.0, 0.0, 0.0, 0.0};
+    acc[0][1][0] = d4{0.0, 0.0, 0.0, 0.0};
+    double af[2][2], bf[2];
+    auto frag = [&](const DmaSlice &S, int k4, int slot) {
+        const int kr = k4 * 4 + (lane >> 4);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
-                const int col = n0 + wn + j * 16 + (lane & 15);
-                if (row >= M || col >= N) continue;
-                const size_t ldo = a.ldo ? (size_t)a.ldo : (size_t)N;
-                const size_t o = (size_t)row * ldo + col;
-                if constexpr (EPI == EPI_STORE) {
+        for (int i = 0; i < 2; ++i) af[slot][i] = S.l[kr][swz(kr, wm + i * 16 + (lane & 15))];
+        bf[slot] = S.r[kr][swz(kr, wn + (lane & 15))];
+    };
+    auto compute = [&](const DmaSlice &S) {
+        frag(S, 0, 0);
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) (b == 0 ? a.O0 : a.O1)[o] = acc[b][i][j][r];
-                } else if constexpr (EPI == EPI_DIV_MU) {
-                    // eigenvalue of M (eq. (M)) for mode (row, col), summed without cancellation
-                    const double lb = a.lb[row], lt = a.lt[col];
-                    const double mu = lb * lt * inv_a1 + lb + a.a2 * inv_a1 * lt;
-                    a.O0[o] = acc[0][i][j][r] / mu;
-                } else {
-                    // per-mode block solve [[lt + a1, -a1], [-a2, lb + a2]] x = r
-                    const double lb = a.lb[row], lt = a.lt[col];
-                    const double det = lt * lb + a.a2 * lt + a.a1 * lb;
-                    const double rt = acc[0][i][j][r], rb = acc[NB - 1][i][j][r];
-                    a.O0[o] = ((lb + a.a2) * rt + a.a1 * rb) / det;
-                    a.O1[o] = (a.a2 * rt + (lt + a.a1) * rb) / det;
-                }
-            }
+        for (int k4 = 0; k4 < 8; ++k4) {
+            if (k4 + 1 < 8) frag(S, k4 + 1, (k4 + 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                acc[0][i][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[k4 & 1][i], bf[k4 & 1],
+                                                                    acc[0][i][0], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    // s_waitcnt immediates (gfx9 encoding, expcnt and lgkmcnt left at their maxima)
+    constexpr int kWaitVm8 = 0xF70 | 8, kWaitVm0 = 0xF70;
+    const int nk = K / 32;
+    const int last = nk - 1;
+    auto step = [&](const DmaSlice &cur, DmaSlice &nxt, int kt) {
+        // slice kt is this wave's oldest DMA: two younger slices (8 loads) may
+        // still be in flight; the barrier then publishes every wave's part
+        __builtin_amdgcn_s_waitcnt(kWaitVm8);
+        asm volatile("s_barrier" ::: "memory");
+        // past the end the last slice is loaded again (in bounds, never read),
+        // which keeps the count of loads in flight the same at every step
+        issue(nxt, min(kt + 3, last));
+        compute(cur);
+    };
+    issue(S0, 0);
+    issue(S1, 1);
+    issue(S2, 2);
+    for (int kt = 0; kt < nk; kt += 4) {
+        step(S0, S3, kt);
+        step(S1, S0, kt + 1);
+        step(S2, S1, kt + 2);
+        step(S3, S2, kt + 3);
+    }
+    // no LDS DMA may outlive the workgroup
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    store_tile<1, EPI, 1>(a, acc, m0, n0, wm, wn, lane);
 }
 
 }  // namespace
@@ -303,6 +423,19 @@ hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
         tiles *= 2;
     }
     if (epi == EPI_PERMODE && !dual) return hipErrorInvalidValue;
+    // whole tiles, K in 128-deep steps, at most one tile per CU: the
+    // direct-to-LDS kernel (its 128 KB of LDS hold one workgroup per CU; with
+    // more tiles the register-staged kernel, two workgroups per CU, is faster:
+    // 2048^2 transforms at 77% vs 72% of the FP64 matrix peak)
+    const bool dma = !dual && a.vec && a.M % BM == 0 && a.N % BN == 0 && a.K % 128 == 0 &&
+                     a.K >= 128 && epi != EPI_PERMODE && tiles <= 256;
+    if (dma) {
+        if (epi == EPI_DIV_MU)
+            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_DIV_MU>), dim3(tiles), dim3(512), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_STORE>), dim3(tiles), dim3(512), 0, s, a);
+        return hipGetLastError();
+    }
     if (dual) {
         if (epi == EPI_PERMODE) launch_variant<2, EPI_PERMODE>(a, tiles, s);
         else if (epi == EPI_STORE) launch_variant<2, EPI_STORE>(a, tiles, s);

@@ -25,7 +25,8 @@ from paper_2109_07929_amd import binding as B
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(1, 1), (1, 7), (6, 1), (5, 3), (16, 24), (33, 65), (64, 64), (100, 130), (130, 70)]
+SHAPES = [(1, 1), (1, 7), (6, 1), (5, 3), (16, 24), (33, 65), (64, 64), (100, 130), (130, 70),
+          (256, 128)]
 
 
 def dev(a):
@@ -104,7 +105,7 @@ def test_precond_parity(m, n, form, a1, a2):
 
 @pytest.mark.parametrize("m,n,ends", [(64, 48, (0.1, 0.1)), (64, 48, (0.1, 0.07)),
                                       (2, 5, (0.1, 0.1)), (130, 70, (0.2, 0.2)),
-                                      (7, 9, (0.1, 0.1))])
+                                      (7, 9, (0.1, 0.1)), (128, 256, (0.1, 0.07))])
 def test_precond_literal_persymmetric_fold(m, n, ends):
     """Equal bottom terminations with m even take the folded Q_m transforms
     (symmetric / antisymmetric eigenvector halves); unequal ends or odd m the
