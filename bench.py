@@ -419,6 +419,26 @@ def main():
     ms_per_step = total_ms / args.steps
     value = 1e3 / ms_per_step
 
+    # per-class breakdown: a pass after the timed region with every group timed
+    breakdown, kry_hbm = {}, None
+    if not args.no_timing:
+        nfull = 2
+        fms = np.zeros(B.MCA_NUM_KCLASS)
+        flaunch = np.zeros(B.MCA_NUM_KCLASS, dtype=np.int64)
+        its_full = 0
+        for _ in range(nfull):
+            st_full = step(opts_full)
+            its_full += st_full.krylov_iters
+            fms += np.array(st_full.kernel_ms[:])
+            flaunch += np.array(st_full.kernel_launches[:])
+        torch.cuda.synchronize()
+        names = ["gemm", "jacobian", "ortho", "residual"]
+        breakdown["timed"] = f"{nfull} solves after the timed region, every kernel group timed"
+        for c, nm in enumerate(names):
+            breakdown[nm] = {"ms_per_solve": round(fms[c] / nfull, 4),
+                             "launches_per_solve": int(flaunch[c] // nfull)}
+        if fms[B.MCA_KCLASS_JACOBIAN] > 0:
+            kry_hbm = krylov_hbm(st_full, m * n, opts_full, fms, nfull)
     # roofline of the dominant kernel: the FP64 eigenbasis GEMMs
     roofline = None
     if not args.no_timing and klaunch[B.MCA_KCLASS_GEMM] > 0 and form == B.MCA_PRECOND_APPROX:
@@ -443,7 +463,10 @@ def main():
         persym = (form == B.MCA_PRECOND_LITERAL and m % 2 == 0 and g.g_bot_end0 == g.g_bot_end1)
         qm = (1.0 if persym else 2.0) * n * m * m
         flops_app = 2 * qm + 2 * (2.0 * m * n * n)
-        launches_app = 5 if persym else 4
+        # transform launches per application, from the pass with every group timed
+        # (one application per GMRES iteration): 4 products, plus the unfold pass
+        # when it is not fused into the last product
+        launches_app = int(round(flaunch[B.MCA_KCLASS_GEMM] / max(its_full, 1)))
         if form == B.MCA_PRECOND_PERMODE:
             flops_app *= 2.0
         napps = klaunch[B.MCA_KCLASS_GEMM] / launches_app
@@ -452,7 +475,7 @@ def main():
         traffic = gemm_traffic() if (m == 1024 and persym) else None
         roofline = {"bound": "mfma",
                     "kernel": "FP64 eigenbasis transforms of one preconditioner application "
-                              "(k_gemm_tn_f64 launches" + (" + k_unfold)" if persym else ")"),
+                              "(k_gemm_tn_f64 launches" + (", the unfold fused or in k_unfold)" if persym else ")"),
                     "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
                     "traffic": traffic,
@@ -465,24 +488,6 @@ def main():
         roofline["timed_groups"] = ("every 4th preconditioner application of the timed solves"
                                     if not args.full_timing else
                                     "every preconditioner application of the timed solves")
-    # per-class breakdown: a pass after the timed region with every group timed
-    breakdown, kry_hbm = {}, None
-    if not args.no_timing:
-        nfull = 2
-        fms = np.zeros(B.MCA_NUM_KCLASS)
-        flaunch = np.zeros(B.MCA_NUM_KCLASS, dtype=np.int64)
-        for _ in range(nfull):
-            st_full = step(opts_full)
-            fms += np.array(st_full.kernel_ms[:])
-            flaunch += np.array(st_full.kernel_launches[:])
-        torch.cuda.synchronize()
-        names = ["gemm", "jacobian", "ortho", "residual"]
-        breakdown["timed"] = f"{nfull} solves after the timed region, every kernel group timed"
-        for c, nm in enumerate(names):
-            breakdown[nm] = {"ms_per_solve": round(fms[c] / nfull, 4),
-                             "launches_per_solve": int(flaunch[c] // nfull)}
-        if fms[B.MCA_KCLASS_JACOBIAN] > 0:
-            kry_hbm = krylov_hbm(st_full, m * n, opts_full, fms, nfull)
 
     kind = ("plain FP64 Newton-FGMRES(30)" if prec == B.MCA_PREC_FP64 else
             f"Newton-FGMRES(30) with a {args.precision} preconditioner")

@@ -294,6 +294,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
 // each lane picks the global columns that land in the swizzled layout of
 // swz().  One barrier per slice: after it, the buffer computed one slice
 // earlier is free and takes the slice three ahead.
+// EPI_UNFOLD: the tile is 32 rows p of A = Y_s^T R (LDS columns 0..31 of the L
+// slice, from Y_s) over the same 32 rows of B = Y_a^T R (columns 32..63, from
+// Y_a); the waves holding B pass it through LDS to the waves holding A, which
+// store A + B to row p and A - B to row M-1-p.
 struct DmaSlice {
     double l[32][64];
     double r[32][64];
@@ -317,12 +321,14 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
     __shared__ DmaSlice S0, S1, S2, S3;
     if (a.skip && *a.skip) return;   // uniform: a converged GMRES cycle
 
+    constexpr bool UNF = EPI == EPI_UNFOLD;
     const int M = a.M, N = a.N, K = a.K;
     int tm, tn;
-    tile_of(bid, nwg, M / BM, N / BN, tm, tn);
-    const int m0 = tm * BM, n0 = tn * BN;
+    tile_of(bid, nwg, M / BM, N / BN, tm, tn);   // (UNF: M/2 rows in tiles of 32)
+    const int m0 = tm * (UNF ? BM / 2 : BM), n0 = tn * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave / 4) * 32, wn = (wave % 4) * 16;
+    const size_t ldl = UNF ? (size_t)(M / 2) : (size_t)M;
 
     // wave w fills slice rows 4w .. 4w + 3, two per instruction
     const int prow = 4 * wave;
@@ -331,10 +337,13 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
     for (int t = 0; t < 2; ++t) {
         const int row = prow + 2 * t + (lane >> 5);
         const int col = (2 * (lane & 31)) ^ ((row & 1) << 4);   // swz() is an involution
-        lsrc[t] = a.L0 + (size_t)row * M + m0 + col;
+        if (UNF)
+            lsrc[t] = (col < 32 ? a.L0 : a.L1) + (size_t)row * ldl + m0 + (col & 31);
+        else
+            lsrc[t] = a.L0 + (size_t)row * ldl + m0 + col;
         rsrc[t] = a.R + (size_t)row * N + n0 + col;
     }
-    const size_t lstep = (size_t)32 * M, rstep = (size_t)32 * N;
+    const size_t lstep = 32 * ldl, rstep = (size_t)32 * N;
     typedef const void __attribute__((address_space(1))) *gptr;
     typedef void __attribute__((address_space(3))) *lptr;
     auto issue = [&](DmaSlice &S, int kt) {
@@ -395,7 +404,31 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
     }
     // no LDS DMA may outlive the workgroup
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    store_tile<1, EPI, 1>(a, acc, m0, n0, wm, wn, lane);
+    if constexpr (UNF) {
+        // every wave's DMA has landed (S0 is free); B goes through S0.l
+        asm volatile("s_barrier" ::: "memory");
+        const int c = wn + (lane & 15);
+        if (wm == 32) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) S0.l[i * 16 + (lane >> 4) + 4 * r][c] = acc[0][i][0][r];
+        }
+        asm volatile("s_barrier" ::: "memory");
+        if (wm == 0) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int p = m0 + i * 16 + (lane >> 4) + 4 * r;
+                    const double A = acc[0][i][0][r], Bv = S0.l[p - m0][c];
+                    a.O0[(size_t)p * N + n0 + c] = A + Bv;
+                    a.O0[(size_t)(M - 1 - p) * N + n0 + c] = A - Bv;
+                }
+        }
+    } else {
+        store_tile<1, EPI, 1>(a, acc, m0, n0, wm, wn, lane);
+    }
 }
 
 }  // namespace
@@ -407,6 +440,13 @@ template <int NB, int EPI>
 static void launch_variant(const GemmArgs &a, int tiles, hipStream_t s)
 {
     hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, 32, 8, false>), dim3(tiles), dim3(512), 0, s, a);
+}
+
+bool gemm_unfold_fits(int M, int N, int K)
+{
+    // the direct-to-LDS kernel's conditions, with M/2 rows in 32-row tiles
+    return M > 0 && N > 0 && M % BM == 0 && N % BN == 0 && K % 128 == 0 && K >= 128 &&
+           (M / BM) * (N / BN) <= 256;
 }
 
 hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
@@ -423,10 +463,16 @@ hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
         tiles *= 2;
     }
     if (epi == EPI_PERMODE && !dual) return hipErrorInvalidValue;
+    if (epi == EPI_UNFOLD) {
+        if (!gemm_unfold_fits(a.M, a.N, a.K) || !a.vec || !a.L1 || a.pair || a.ldo)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_UNFOLD>), dim3(tiles), dim3(512), 0, s, a);
+        return hipGetLastError();
+    }
     // whole tiles, K in 128-deep steps, at most one tile per CU: the
     // direct-to-LDS kernel (its 128 KB of LDS hold one workgroup per CU; with
     // more tiles the register-staged kernel, two workgroups per CU, is faster:
-    // 2048^2 transforms at 77% vs 72% of the FP64 matrix peak)
+    // 2048^2 transforms at 80% vs 72% of the FP64 matrix peak)
     const bool dma = !dual && a.vec && a.M % BM == 0 && a.N % BN == 0 && a.K % 128 == 0 &&
                      a.K >= 128 && epi != EPI_PERMODE && tiles <= 256;
     if (dma) {

@@ -101,12 +101,17 @@ hipError_t launch_precond_post(const mca_plan *P, double a1, const double *zt,
                                const int *skip = nullptr);
 
 // GEMM epilogues
-enum GemmEpi { EPI_STORE = 0, EPI_DIV_MU = 1, EPI_PERMODE = 2 };
+enum GemmEpi { EPI_STORE = 0, EPI_DIV_MU = 1, EPI_PERMODE = 2, EPI_UNFOLD = 3 };
 
 // O = L^T R (one or two batches sharing R), FP64 MFMA.
 //   L: K x M row-major (ld = M), R: K x N row-major (ld = N), O: M x N row-major.
 //   EPI_DIV_MU : O[p][q] = acc / (lb[p] lt[q] / a1 + lb[p] + (a2/a1) lt[q])
 //   EPI_PERMODE: (O0, O1) = 2x2 per-mode solve of (acc0, acc1)      (needs 2 batches)
+//   EPI_UNFOLD : L0 = Y_s, L1 = Y_a (K x M/2 each, ld = M/2) stand for
+//                L = [Y_s + Y_a | column-mirrored (Y_s - Y_a)], so that O rows p and
+//                M-1-p are A_p + B_p and A_p - B_p with A = Y_s^T R, B = Y_a^T R
+//                (the persymmetric unfold fused into the product); only when
+//                gemm_unfold_fits(M, N, K)
 // O's row stride is ldo (0: N).  pair: two independent single-batch products in
 // one launch, the second with L1, R1, O1 (the same sizes and epilogue).
 struct GemmArgs {
@@ -123,6 +128,7 @@ struct GemmArgs {
     const double *R1;
 };
 hipError_t launch_gemm_f64(const GemmArgs &a, int epi, hipStream_t s);
+bool gemm_unfold_fits(int M, int N, int K);
 
 // Per-mode preconditioner in reduced precision (gemm_lp.hip): four NT products
 // on FP32 / BF16 MFMA with the per-mode 2x2 solve in the second one.

@@ -459,12 +459,22 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
         g.L1 = w.b0t + hn; g.R1 = d.UaT; g.O1 = w.b0b + hn;
         MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
         g.pair = 0; g.L1 = nullptr; g.R1 = nullptr; g.O1 = nullptr;
-        // X^T = [Y_s + Y_a | mirrored (Y_s - Y_a)]        (n x m)
-        MCA_TRY(launch_unfold(w.b0b, w.b0b + hn, n, h, w.b1t, s, skip));
-        // z_t = X Q_n^T                                   (m x n)
-        g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.R = d.QnT; g.O0 = zt;
-        MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
-        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 5, slot));
+        int nl = 4;
+        if (gemm_unfold_fits(m, n, n)) {
+            // z_t = X Q_n^T with X^T = [Y_s + Y_a | mirrored (Y_s - Y_a)] formed
+            // inside the product: rows i and m-1-i from the same tile
+            g.M = m; g.N = n; g.K = n; g.L0 = w.b0b; g.L1 = w.b0b + hn; g.R = d.QnT; g.O0 = zt;
+            MCA_TRY(launch_gemm_f64(g, EPI_UNFOLD, s));
+            g.L1 = nullptr;
+        } else {
+            // X^T = [Y_s + Y_a | mirrored (Y_s - Y_a)]        (n x m)
+            MCA_TRY(launch_unfold(w.b0b, w.b0b + hn, n, h, w.b1t, s, skip));
+            // z_t = X Q_n^T                                   (m x n)
+            g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.R = d.QnT; g.O0 = zt;
+            MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
+            nl = 5;
+        }
+        MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, nl, slot));
         MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s, skip));
         return MCA_OK;
     }
