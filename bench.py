@@ -130,7 +130,11 @@ def krylov_hbm(st, mn, opts, kms, steps):
             "ms_per_solve": round(ms, 4), "algorithmic_bytes_per_solve": alg * mn,
             "achieved_algorithmic": round(a, 1), "kernel_bytes_per_solve": kern * mn,
             "achieved_kernel": round(kb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac_algorithmic": round(a / HBM_PEAK_GBS, 4), "frac_kernel": round(kb / HBM_PEAK_GBS, 4)}
+            "frac_algorithmic": round(a / HBM_PEAK_GBS, 4), "frac_kernel": round(kb / HBM_PEAK_GBS, 4),
+            "timing": "HIP-event brackets around each Jacobian and orthogonalisation group; each "
+                      "bracket also holds the few microseconds a timed event leaves the GPU idle, so "
+                      "these rates sit below the kernels' own (rocprofv3 durations per Arnoldi step "
+                      "in profiles/solve_fp64_1024x1024.md)"}
 
 
 def hbm_copy(out, roofline, kry_hbm, ev0, ev1, stream, dev):
