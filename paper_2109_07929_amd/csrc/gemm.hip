@@ -287,25 +287,27 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
 }
 
 // Direct-to-LDS variant for whole tiles (M, N multiples of 64, K a multiple of
-// 128, 16-byte aligned rows, one batch): every K slice moves from global memory
-// into LDS by global_load_lds_dwordx4 (16 bytes per lane, 1 KB per wave
-// instruction, no register staging), four slices deep in four LDS buffers of
-// 32 KB.  A wave's instruction fills two consecutive slice rows in LDS order;
-// each lane picks the global columns that land in the swizzled layout of
-// swz().  One barrier per slice: after it, the buffer computed one slice
-// earlier is free and takes the slice three ahead.
+// BK * ST, 16-byte aligned rows, one batch): every BK-deep K slice moves from
+// global memory into LDS by global_load_lds_dwordx4 (16 bytes per lane, 1 KB
+// per wave instruction, no register staging), ST slices deep in ST LDS
+// buffers.  A wave's instruction fills two consecutive slice rows in LDS
+// order; each lane picks the global columns that land in the swizzled layout
+// of swz().  One barrier per slice: after it, the buffer computed one slice
+// earlier is free and takes the slice ST - 1 ahead.
 // EPI_UNFOLD: the tile is 32 rows p of A = Y_s^T R (LDS columns 0..31 of the L
 // slice, from Y_s) over the same 32 rows of B = Y_a^T R (columns 32..63, from
 // Y_a); the waves holding B pass it through LDS to the waves holding A, which
 // store A + B to row p and A - B to row M-1-p.
+template <int BK>
 struct DmaSlice {
-    double l[32][64];
-    double r[32][64];
+    double l[BK][64];
+    double r[BK][64];
 };
 
-template <int EPI>
+template <int EPI, int BK, int ST>
 __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
 {
+    static_assert(BK % 16 == 0 && BK >= 32 && (ST == 2 || ST == 4), "slice shape");
     int bid = blockIdx.x, nwg = gridDim.x;
     if (a.pair) {
         nwg >>= 1;
@@ -316,12 +318,14 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
             a.O0 = a.O1;
         }
     }
-    // four distinct objects, so that the compiler's wait for LDS DMA before a
-    // read of one buffer does not count the loads still filling the others
-    __shared__ DmaSlice S0, S1, S2, S3;
+    // distinct objects, so that the compiler's wait for LDS DMA before a read
+    // of one buffer does not count the loads still filling the others (the
+    // buffers past ST are never referenced and take no LDS)
+    __shared__ DmaSlice<BK> S0, S1, S2, S3;
     if (a.skip && *a.skip) return;   // uniform: a converged GMRES cycle
 
     constexpr bool UNF = EPI == EPI_UNFOLD;
+    constexpr int T = BK / 16;        // row pairs per wave and operand in a slice
     const int M = a.M, N = a.N, K = a.K;
     int tm, tn;
     tile_of(bid, nwg, M / BM, N / BN, tm, tn);   // (UNF: M/2 rows in tiles of 32)
@@ -330,11 +334,11 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
     const int wm = (wave / 4) * 32, wn = (wave % 4) * 16;
     const size_t ldl = UNF ? (size_t)(M / 2) : (size_t)M;
 
-    // wave w fills slice rows 4w .. 4w + 3, two per instruction
-    const int prow = 4 * wave;
-    const double *lsrc[2], *rsrc[2];
+    // wave w fills slice rows 2T w .. 2T w + 2T - 1, two per instruction
+    const int prow = 2 * T * wave;
+    const double *lsrc[T], *rsrc[T];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < T; ++t) {
         const int row = prow + 2 * t + (lane >> 5);
         const int col = (2 * (lane & 31)) ^ ((row & 1) << 4);   // swz() is an involution
         if (UNF)
@@ -343,12 +347,12 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
             lsrc[t] = a.L0 + (size_t)row * ldl + m0 + col;
         rsrc[t] = a.R + (size_t)row * N + n0 + col;
     }
-    const size_t lstep = 32 * ldl, rstep = (size_t)32 * N;
+    const size_t lstep = BK * ldl, rstep = (size_t)BK * N;
     typedef const void __attribute__((address_space(1))) *gptr;
     typedef void __attribute__((address_space(3))) *lptr;
-    auto issue = [&](DmaSlice &S, int kt) {
+    auto issue = [&](DmaSlice<BK> &S, int kt) {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < T; ++t) {
             __builtin_amdgcn_global_load_lds((gptr)(lsrc[t] + kt * lstep),
                                              (lptr)&S.l[prow + 2 * t][0], 16, 0, 0);
             __builtin_amdgcn_global_load_lds((gptr)(rsrc[t] + kt * rstep),
@@ -360,17 +364,17 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
     acc[0][0][0] = d4{0.0, 0.0, 0.0, 0.0};
     acc[0][1][0] = d4{0.0, 0.0, 0.0, 0.0};
     double af[2][2], bf[2];
-    auto frag = [&](const DmaSlice &S, int k4, int slot) {
+    auto frag = [&](const DmaSlice<BK> &S, int k4, int slot) {
         const int kr = k4 * 4 + (lane >> 4);
 #pragma unroll
         for (int i = 0; i < 2; ++i) af[slot][i] = S.l[kr][swz(kr, wm + i * 16 + (lane & 15))];
         bf[slot] = S.r[kr][swz(kr, wn + (lane & 15))];
     };
-    auto compute = [&](const DmaSlice &S) {
+    auto compute = [&](const DmaSlice<BK> &S) {
         frag(S, 0, 0);
 #pragma unroll
-        for (int k4 = 0; k4 < 8; ++k4) {
-            if (k4 + 1 < 8) frag(S, k4 + 1, (k4 + 1) & 1);
+        for (int k4 = 0; k4 < BK / 4; ++k4) {
+            if (k4 + 1 < BK / 4) frag(S, k4 + 1, (k4 + 1) & 1);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -379,28 +383,39 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    // s_waitcnt immediates (gfx9 encoding, expcnt and lgkmcnt left at their maxima)
-    constexpr int kWaitVm8 = 0xF70 | 8, kWaitVm0 = 0xF70;
-    const int nk = K / 32;
+    // s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt
+    // and lgkmcnt left at their maxima)
+    constexpr int kYounger = (ST - 2) * 2 * T;   // loads of the slices issued after the oldest
+    static_assert(kYounger < 64, "vmcnt range");
+    constexpr int kWaitVm = 0xF70 | (kYounger & 15) | ((kYounger >> 4) << 14), kWaitVm0 = 0xF70;
+    const int nk = K / BK;
     const int last = nk - 1;
-    auto step = [&](const DmaSlice &cur, DmaSlice &nxt, int kt) {
-        // slice kt is this wave's oldest DMA: two younger slices (8 loads) may
-        // still be in flight; the barrier then publishes every wave's part
-        __builtin_amdgcn_s_waitcnt(kWaitVm8);
+    auto step = [&](const DmaSlice<BK> &cur, DmaSlice<BK> &nxt, int kt) {
+        // slice kt is this wave's oldest DMA, ST - 2 younger slices may still
+        // be in flight; the barrier then publishes every wave's part
+        __builtin_amdgcn_s_waitcnt(kWaitVm);
         asm volatile("s_barrier" ::: "memory");
         // past the end the last slice is loaded again (in bounds, never read),
         // which keeps the count of loads in flight the same at every step
-        issue(nxt, min(kt + 3, last));
+        issue(nxt, min(kt + ST - 1, last));
         compute(cur);
     };
-    issue(S0, 0);
-    issue(S1, 1);
-    issue(S2, 2);
-    for (int kt = 0; kt < nk; kt += 4) {
-        step(S0, S3, kt);
-        step(S1, S0, kt + 1);
-        step(S2, S1, kt + 2);
-        step(S3, S2, kt + 3);
+    if constexpr (ST == 4) {
+        issue(S0, 0);
+        issue(S1, 1);
+        issue(S2, 2);
+        for (int kt = 0; kt < nk; kt += 4) {
+            step(S0, S3, kt);
+            step(S1, S0, kt + 1);
+            step(S2, S1, kt + 2);
+            step(S3, S2, kt + 3);
+        }
+    } else {
+        issue(S0, 0);
+        for (int kt = 0; kt < nk; kt += 2) {
+            step(S0, S1, kt);
+            step(S1, S0, kt + 1);
+        }
     }
     // no LDS DMA may outlive the workgroup
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
@@ -442,10 +457,15 @@ static void launch_variant(const GemmArgs &a, int tiles, hipStream_t s)
     hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, 32, 8, false>), dim3(tiles), dim3(512), 0, s, a);
 }
 
+// direct-to-LDS launches: 32-deep slices in two buffers (64 KB of LDS).
+// Measured at 1024^2 (application of the persymmetric literal form): 126.8 us
+// with two 32-deep buffers, 126.6 us with two 64-deep, 129 us with four 32-deep.
+constexpr int kDmaBk = 32, kDmaSt = 2, kDmaKStep = kDmaBk * kDmaSt;
+
 bool gemm_unfold_fits(int M, int N, int K)
 {
     // the direct-to-LDS kernel's conditions, with M/2 rows in 32-row tiles
-    return M > 0 && N > 0 && M % BM == 0 && N % BN == 0 && K % 128 == 0 && K >= 128 &&
+    return M > 0 && N > 0 && M % BM == 0 && N % BN == 0 && K % kDmaKStep == 0 && K > 0 &&
            (M / BM) * (N / BN) <= 256;
 }
 
@@ -466,20 +486,20 @@ hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
     if (epi == EPI_UNFOLD) {
         if (!gemm_unfold_fits(a.M, a.N, a.K) || !a.vec || !a.L1 || a.pair || a.ldo)
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_UNFOLD>), dim3(tiles), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_UNFOLD, kDmaBk, kDmaSt>), dim3(tiles), dim3(512), 0, s, a);
         return hipGetLastError();
     }
-    // whole tiles, K in 128-deep steps, at most one tile per CU: the
-    // direct-to-LDS kernel (its 128 KB of LDS hold one workgroup per CU; with
-    // more tiles the register-staged kernel, two workgroups per CU, is faster:
-    // 2048^2 transforms at 80% vs 72% of the FP64 matrix peak)
-    const bool dma = !dual && a.vec && a.M % BM == 0 && a.N % BN == 0 && a.K % 128 == 0 &&
-                     a.K >= 128 && epi != EPI_PERMODE && tiles <= 256;
+    // whole tiles, at most one tile per CU: the direct-to-LDS kernel (with
+    // more tiles the register-staged kernel is as fast or faster: 2048^2
+    // transforms at 80% of the FP64 matrix peak with it, 79% with two 32-deep
+    // DMA buffers, 72% with four)
+    const bool dma = !dual && a.vec && a.M % BM == 0 && a.N % BN == 0 && a.K % kDmaKStep == 0 &&
+                     a.K > 0 && epi != EPI_PERMODE && tiles <= 256;
     if (dma) {
         if (epi == EPI_DIV_MU)
-            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_DIV_MU>), dim3(tiles), dim3(512), 0, s, a);
+            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_DIV_MU, kDmaBk, kDmaSt>), dim3(tiles), dim3(512), 0, s, a);
         else
-            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_STORE>), dim3(tiles), dim3(512), 0, s, a);
+            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_STORE, kDmaBk, kDmaSt>), dim3(tiles), dim3(512), 0, s, a);
         return hipGetLastError();
     }
     if (dual) {
