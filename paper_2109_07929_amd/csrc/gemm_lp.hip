@@ -35,6 +35,15 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int LBM = 64, LBK = 64, LTPB = 256;
+// Waves of a 128 x 128 tile's workgroup: eight (two per SIMD, 64 x 32 each), so
+// that one wave's LDS reads and barrier waits overlap the other's MFMAs; 64 x 64
+// tiles keep four waves of 32 x 32.
+constexpr int kWaves128 = 8;
+template <int TS>
+constexpr int lp_threads()
+{
+    return TS == 128 ? 64 * kWaves128 : LTPB;
+}
 #ifndef MCA_LP_PAD
 #define MCA_LP_PAD 8
 #endif
@@ -65,16 +74,17 @@ struct Tile {
     typename Fmt<MODE>::elem v[Fmt<MODE>::kPlanes][ROWS][KS + Fmt<MODE>::kPad];
 };
 
-// 16-byte chunks of one ROWS x KS operand slice per plane, per thread.
-template <int MODE, int ROWS, int KS>
+// 16-byte chunks of one ROWS x KS operand slice per plane, per thread of NT.
+template <int MODE, int ROWS, int KS, int NT>
 constexpr int chunks_per_thread()
 {
-    return ROWS * KS / Fmt<MODE>::kPerChunk / LTPB;
+    static_assert(ROWS * KS / Fmt<MODE>::kPerChunk % NT == 0, "chunks per thread");
+    return ROWS * KS / Fmt<MODE>::kPerChunk / NT;
 }
 
-template <int MODE, int ROWS, int KS>
+template <int MODE, int ROWS, int KS, int NT>
 struct Regs {
-    u4 c[Fmt<MODE>::kPlanes][chunks_per_thread<MODE, ROWS, KS>()];
+    u4 c[Fmt<MODE>::kPlanes][chunks_per_thread<MODE, ROWS, KS, NT>()];
 };
 
 // Operand planes are device (global) memory; loads through these pointers
@@ -87,19 +97,19 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T *global_ptr
     return (const __attribute__((address_space(1))) T *)p;
 }
 
-template <int MODE, int ROWS, int KS>
+template <int MODE, int ROWS, int KS, int NT>
 __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int r0, int k0,
-                                        bool fast, Regs<MODE, ROWS, KS> &g)
+                                        bool fast, Regs<MODE, ROWS, KS, NT> &g)
 {
     constexpr int PC = Fmt<MODE>::kPerChunk, CPR = KS / PC;
-    constexpr int CPT = chunks_per_thread<MODE, ROWS, KS>();
+    constexpr int CPT = chunks_per_thread<MODE, ROWS, KS, NT>();
     using E = typename Fmt<MODE>::elem;
 #pragma unroll
     for (int pl = 0; pl < Fmt<MODE>::kPlanes; ++pl) {
         const auto *base = global_ptr(static_cast<const E *>(op.p[pl]));
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int id = threadIdx.x + c * LTPB;
+            const int id = threadIdx.x + c * NT;
             const int r = r0 + id / CPR, k = k0 + (id % CPR) * PC;
             if (fast) {
                 g.c[pl][c] = *reinterpret_cast<const __attribute__((address_space(1))) u4 *>(
@@ -122,16 +132,16 @@ __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int 
     }
 }
 
-template <int MODE, int ROWS, int KS>
-__device__ __forceinline__ void stash_op(Tile<MODE, ROWS, KS> &t, const Regs<MODE, ROWS, KS> &g)
+template <int MODE, int ROWS, int KS, int NT>
+__device__ __forceinline__ void stash_op(Tile<MODE, ROWS, KS> &t, const Regs<MODE, ROWS, KS, NT> &g)
 {
     constexpr int PC = Fmt<MODE>::kPerChunk, CPR = KS / PC;
-    constexpr int CPT = chunks_per_thread<MODE, ROWS, KS>();
+    constexpr int CPT = chunks_per_thread<MODE, ROWS, KS, NT>();
 #pragma unroll
     for (int pl = 0; pl < Fmt<MODE>::kPlanes; ++pl)
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int id = threadIdx.x + c * LTPB;
+            const int id = threadIdx.x + c * NT;
             *reinterpret_cast<u4 *>(&t.v[pl][id / CPR][(id % CPR) * PC]) = g.c[pl][c];
         }
 }
@@ -167,21 +177,24 @@ __device__ __forceinline__ void put(const LpArgs &a, int b, size_t o, T v, int o
 
 constexpr int DEPTH = 2;   // K slices in flight (deeper rings measured no faster)
 
-// One TS x TS output tile at (m0, n0) of O = A B^T: four waves of (TS/2)^2,
-// F x F MFMA tiles of 16 x 16 each; K staged in slices of KS.
+// One TS x TS output tile at (m0, n0) of O = A B^T: four waves of (TS/2)^2 or
+// eight of (TS/2) x (TS/4), FI x FJ MFMA tiles of 16 x 16 each; K staged in
+// slices of KS.
 template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI, int TS, int KS>
 __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 {
     constexpr int NA = A_BATCHED ? NB : 1, NBB = A_BATCHED ? 1 : NB;
-    constexpr int WT = TS / 2, F = WT / 16;
+    constexpr int NT = lp_threads<TS>(), WAVES = NT / 64;
+    constexpr int WTM = TS / 2, WTN = (WAVES == 8) ? TS / 4 : TS / 2;
+    constexpr int FI = WTM / 16, FJ = WTN / 16;
     using TileT = Tile<MODE, TS, KS>;
-    using RegsT = Regs<MODE, TS, KS>;
+    using RegsT = Regs<MODE, TS, KS, NT>;
     __shared__ TileT As[2][NA];
     __shared__ TileT Bs[2][NBB];
     const int M = a.M, N = a.N, K = a.K;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * WT, wn = (wave & 1) * WT;
+    const int wm = (wave / (TS / WTN)) * WTM, wn = (wave % (TS / WTN)) * WTN;
     const bool fast_m = a.vec && (m0 + TS <= M);
     const bool fast_n = a.vec && (n0 + TS <= N);
 
@@ -192,32 +205,32 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
         const bool kin = k0 + KS <= K;
 #pragma unroll
         for (int b = 0; b < NA; ++b)
-            load_op<MODE, TS, KS>(a.A[b], M, K, m0, k0, fast_m && kin, st.ra[b]);
+            load_op<MODE, TS, KS, NT>(a.A[b], M, K, m0, k0, fast_m && kin, st.ra[b]);
 #pragma unroll
         for (int b = 0; b < NBB; ++b)
-            load_op<MODE, TS, KS>(a.B[b], N, K, n0, k0, fast_n && kin, st.rb[b]);
+            load_op<MODE, TS, KS, NT>(a.B[b], N, K, n0, k0, fast_n && kin, st.rb[b]);
     };
     // interior tiles with K a whole number of slices: unconditional 16-byte loads
     auto load_fast = [&](Stage &st, int k0) {
 #pragma unroll
-        for (int b = 0; b < NA; ++b) load_op<MODE, TS, KS>(a.A[b], M, K, m0, k0, true, st.ra[b]);
+        for (int b = 0; b < NA; ++b) load_op<MODE, TS, KS, NT>(a.A[b], M, K, m0, k0, true, st.ra[b]);
 #pragma unroll
-        for (int b = 0; b < NBB; ++b) load_op<MODE, TS, KS>(a.B[b], N, K, n0, k0, true, st.rb[b]);
+        for (int b = 0; b < NBB; ++b) load_op<MODE, TS, KS, NT>(a.B[b], N, K, n0, k0, true, st.rb[b]);
     };
     auto stash = [&](const Stage &st, int buf) {
 #pragma unroll
-        for (int b = 0; b < NA; ++b) stash_op<MODE, TS, KS>(As[buf][b], st.ra[b]);
+        for (int b = 0; b < NA; ++b) stash_op<MODE, TS, KS, NT>(As[buf][b], st.ra[b]);
 #pragma unroll
-        for (int b = 0; b < NBB; ++b) stash_op<MODE, TS, KS>(Bs[buf][b], st.rb[b]);
+        for (int b = 0; b < NBB; ++b) stash_op<MODE, TS, KS, NT>(Bs[buf][b], st.rb[b]);
     };
 
-    f4 acc[NB][F][F];
+    f4 acc[NB][FI][FJ];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int i = 0; i < F; ++i)
+        for (int i = 0; i < FI; ++i)
 #pragma unroll
-            for (int j = 0; j < F; ++j) acc[b][i][j] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < FJ; ++j) acc[b][i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
     auto compute = [&](int buf) {
 #pragma unroll
@@ -229,15 +242,15 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 #pragma unroll
                 for (int k4 = 0; k4 < KS / 4; ++k4) {
                     const int kk = k4 * 4 + (lane >> 4);
-                    float fa[F], fb[F];
+                    float fa[FI], fb[FJ];
 #pragma unroll
-                    for (int i = 0; i < F; ++i) fa[i] = TA_.v[0][wm + i * 16 + (lane & 15)][kk];
+                    for (int i = 0; i < FI; ++i) fa[i] = TA_.v[0][wm + i * 16 + (lane & 15)][kk];
 #pragma unroll
-                    for (int j = 0; j < F; ++j) fb[j] = TB_.v[0][wn + j * 16 + (lane & 15)][kk];
+                    for (int j = 0; j < FJ; ++j) fb[j] = TB_.v[0][wn + j * 16 + (lane & 15)][kk];
 #pragma unroll
-                    for (int i = 0; i < F; ++i)
+                    for (int i = 0; i < FI; ++i)
 #pragma unroll
-                        for (int j = 0; j < F; ++j)
+                        for (int j = 0; j < FJ; ++j)
                             acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j],
                                                                                 acc[b][i][j], 0, 0, 0);
                 }
@@ -246,20 +259,23 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 #pragma unroll
                 for (int k32 = 0; k32 < KS / 32; ++k32) {
                     const int kk = k32 * 32 + (lane >> 4) * 8;
-                    bf8 ah[F], al[F], bh[F], bl[F];
+                    bf8 ah[FI], al[FI], bh[FJ], bl[FJ];
 #pragma unroll
-                    for (int i = 0; i < F; ++i) {
+                    for (int i = 0; i < FI; ++i) {
                         ah[i] = *reinterpret_cast<const bf8 *>(&TA_.v[0][wm + i * 16 + (lane & 15)][kk]);
-                        bh[i] = *reinterpret_cast<const bf8 *>(&TB_.v[0][wn + i * 16 + (lane & 15)][kk]);
-                        if constexpr (MODE == MCA_PREC_BF16X3) {
+                        if constexpr (MODE == MCA_PREC_BF16X3)
                             al[i] = *reinterpret_cast<const bf8 *>(&TA_.v[1][wm + i * 16 + (lane & 15)][kk]);
-                            bl[i] = *reinterpret_cast<const bf8 *>(&TB_.v[1][wn + i * 16 + (lane & 15)][kk]);
-                        }
                     }
 #pragma unroll
-                    for (int i = 0; i < F; ++i)
+                    for (int j = 0; j < FJ; ++j) {
+                        bh[j] = *reinterpret_cast<const bf8 *>(&TB_.v[0][wn + j * 16 + (lane & 15)][kk]);
+                        if constexpr (MODE == MCA_PREC_BF16X3)
+                            bl[j] = *reinterpret_cast<const bf8 *>(&TB_.v[1][wn + j * 16 + (lane & 15)][kk]);
+                    }
 #pragma unroll
-                        for (int j = 0; j < F; ++j) {
+                    for (int i = 0; i < FI; ++i)
+#pragma unroll
+                        for (int j = 0; j < FJ; ++j) {
                             if constexpr (MODE == MCA_PREC_BF16X3) {
                                 acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                                     al[i], bh[j], acc[b][i][j], 0, 0, 0);
@@ -322,9 +338,9 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 
     // accumulator element r of lane l: row 4 (l/16) + r, column l%16
 #pragma unroll
-    for (int i = 0; i < F; ++i)
+    for (int i = 0; i < FI; ++i)
 #pragma unroll
-        for (int j = 0; j < F; ++j)
+        for (int j = 0; j < FJ; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
@@ -352,7 +368,7 @@ __device__ __forceinline__ int xcd_order(int bid, int nwg)
 }
 
 template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI, int TS, int KS>
-__global__ __launch_bounds__(LTPB) void k_gemm_nt_lp(LpArgs a)
+__global__ __launch_bounds__(lp_threads<TS>()) void k_gemm_nt_lp(LpArgs a)
 {
     if (a.skip && *a.skip) return;
     const int t = xcd_order(blockIdx.x, gridDim.x);
@@ -365,7 +381,7 @@ __global__ __launch_bounds__(LTPB) void k_gemm_nt_lp(LpArgs a)
 // of every instance sit at an element offset from the launch's base planes;
 // the eigenbasis operand is the instance's own.
 template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI, int TS, int KS>
-__global__ __launch_bounds__(LTPB) void k_gemm_nt_lp_grouped(GroupedLp g)
+__global__ __launch_bounds__(lp_threads<TS>()) void k_gemm_nt_lp_grouped(GroupedLp g)
 {
     const int t = xcd_order(blockIdx.x, gridDim.x);
     const int4 tile = g.tiles[t];
@@ -433,7 +449,7 @@ void launch_nt(const LpArgs &g, hipStream_t s)
     const long big = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
     if (big >= 256)
         hipLaunchKernelGGL((k_gemm_nt_lp<MODE, NB, A_BATCHED, OUT, EPI, 128, 32>), dim3((int)big),
-                           dim3(LTPB), 0, s, g);
+                           dim3(lp_threads<128>()), 0, s, g);
     else
         hipLaunchKernelGGL((k_gemm_nt_lp<MODE, NB, A_BATCHED, OUT, EPI, LBM, LBK>),
                            dim3(((g.M + LBM - 1) / LBM) * ((g.N + LBM - 1) / LBM)), dim3(LTPB), 0, s,
@@ -511,7 +527,7 @@ void launch_grouped(const GroupedLp &g, int ntiles, int tile, hipStream_t s)
                            dim3(ntiles), dim3(LTPB), 0, s, g);
     else if (tile == 128)
         hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, NB, A_BATCHED, OUT, EPI, 128, 32>),
-                           dim3(ntiles), dim3(LTPB), 0, s, g);
+                           dim3(ntiles), dim3(lp_threads<128>()), 0, s, g);
     else
         hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, NB, A_BATCHED, OUT, EPI, LBM, LBK>),
                            dim3(ntiles), dim3(LTPB), 0, s, g);
