@@ -39,10 +39,11 @@ constexpr int LBM = 64, LBK = 64, LTPB = 256;
 // that one wave's LDS reads and barrier waits overlap the other's MFMAs; 64 x 64
 // tiles keep four waves of 32 x 32.
 constexpr int kWaves128 = 8;
-template <int TS>
+constexpr int kWaves64 = 4;   // 64 x 64 tiles, 64-deep slices (eight: no faster)
+template <int TS, int KS>
 constexpr int lp_threads()
 {
-    return TS == 128 ? 64 * kWaves128 : LTPB;
+    return TS == 128 ? 64 * kWaves128 : (TS == 64 && KS == 64) ? 64 * kWaves64 : LTPB;
 }
 #ifndef MCA_LP_PAD
 #define MCA_LP_PAD 8
@@ -184,7 +185,7 @@ template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI, int TS, int KS>
 __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 {
     constexpr int NA = A_BATCHED ? NB : 1, NBB = A_BATCHED ? 1 : NB;
-    constexpr int NT = lp_threads<TS>(), WAVES = NT / 64;
+    constexpr int NT = lp_threads<TS, KS>(), WAVES = NT / 64;
     constexpr int WTM = TS / 2, WTN = (WAVES == 8) ? TS / 4 : TS / 2;
     constexpr int FI = WTM / 16, FJ = WTN / 16;
     using TileT = Tile<MODE, TS, KS>;
@@ -368,7 +369,7 @@ __device__ __forceinline__ int xcd_order(int bid, int nwg)
 }
 
 template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI, int TS, int KS>
-__global__ __launch_bounds__(lp_threads<TS>()) void k_gemm_nt_lp(LpArgs a)
+__global__ __launch_bounds__((lp_threads<TS, KS>())) void k_gemm_nt_lp(LpArgs a)
 {
     if (a.skip && *a.skip) return;
     const int t = xcd_order(blockIdx.x, gridDim.x);
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(lp_threads<TS>()) void k_gemm_nt_lp(LpArgs a)
 // of every instance sit at an element offset from the launch's base planes;
 // the eigenbasis operand is the instance's own.
 template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI, int TS, int KS>
-__global__ __launch_bounds__(lp_threads<TS>()) void k_gemm_nt_lp_grouped(GroupedLp g)
+__global__ __launch_bounds__((lp_threads<TS, KS>())) void k_gemm_nt_lp_grouped(GroupedLp g)
 {
     const int t = xcd_order(blockIdx.x, gridDim.x);
     const int4 tile = g.tiles[t];
@@ -449,11 +450,11 @@ void launch_nt(const LpArgs &g, hipStream_t s)
     const long big = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
     if (big >= 256)
         hipLaunchKernelGGL((k_gemm_nt_lp<MODE, NB, A_BATCHED, OUT, EPI, 128, 32>), dim3((int)big),
-                           dim3(lp_threads<128>()), 0, s, g);
+                           dim3(lp_threads<128, 32>()), 0, s, g);
     else
         hipLaunchKernelGGL((k_gemm_nt_lp<MODE, NB, A_BATCHED, OUT, EPI, LBM, LBK>),
-                           dim3(((g.M + LBM - 1) / LBM) * ((g.N + LBM - 1) / LBM)), dim3(LTPB), 0, s,
-                           g);
+                           dim3(((g.M + LBM - 1) / LBM) * ((g.N + LBM - 1) / LBM)),
+                           dim3(lp_threads<LBM, LBK>()), 0, s, g);
 }
 
 template <int MODE>
@@ -519,18 +520,20 @@ hipError_t chain(const LowPrecChain &c, hipStream_t s)
 // Tile edge 128 (K slices of 32); 64 with K slices of 64, or of 32 when the
 // launch has at least two tiles per CU: the shallower slices halve the LDS
 // and the registers of a workgroup, so that two share a CU.
+constexpr int kSlice32Tiles = 512;
+
 template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI>
 void launch_grouped(const GroupedLp &g, int ntiles, int tile, hipStream_t s)
 {
-    if (tile == 64 && ntiles >= 512)
+    if (tile == 64 && ntiles >= kSlice32Tiles)
         hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, NB, A_BATCHED, OUT, EPI, 64, 32>),
-                           dim3(ntiles), dim3(LTPB), 0, s, g);
+                           dim3(ntiles), dim3(lp_threads<64, 32>()), 0, s, g);
     else if (tile == 128)
         hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, NB, A_BATCHED, OUT, EPI, 128, 32>),
-                           dim3(ntiles), dim3(lp_threads<128>()), 0, s, g);
+                           dim3(ntiles), dim3(lp_threads<128, 32>()), 0, s, g);
     else
         hipLaunchKernelGGL((k_gemm_nt_lp_grouped<MODE, NB, A_BATCHED, OUT, EPI, LBM, LBK>),
-                           dim3(ntiles), dim3(LTPB), 0, s, g);
+                           dim3(ntiles), dim3(lp_threads<LBM, LBK>()), 0, s, g);
 }
 
 template <int MODE>
