@@ -291,48 +291,151 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
         }
     };
 
-    // DEPTH K slices in flight: a ring of register stages; the loop is unrolled
-    // by DEPTH so that the stages rotate by name.  At step k the stage that
-    // held slice k (already in LDS) receives slice k + DEPTH, slice k is
-    // multiplied, and slice k + 1 moves from registers into the other LDS buffer.
-    const int nk = (K + KS - 1) / KS;
-    Stage st[DEPTH];
-    int kb = 0;
-    if (fast_m && fast_n && K % KS == 0 && nk >= DEPTH) {
-        // the same ring with the loads' conditions lifted out of the steady
-        // state, so that no branch sits between a load and the wait before
-        // its LDS store and the wait covers only that stage
+    bool done = false;
+    if constexpr (TS == 128 && KS == 32 && MODE != MCA_PREC_FP32 && NT == 512) {
+        // only in launches of at most one tile per CU (one 2048^2 split-BF16
+        // solve 16.3 -> 14.7 ms); with more, the register path measured faster
+        // (8 x 1024^2 batch 21.0 vs 21.3 ms)
+        if (fast_m && fast_n && K % KS == 0 && gridDim.x <= 256) {
+            // Interior tile: every slice goes from global memory straight into
+            // LDS (global_load_lds_dwordx4, 16 bytes per lane), two buffers.
+            // The slice layout drops the row padding: plane p, row r, 16-byte
+            // chunk c of the row's 32 values sits at byte p 8192 + 64 r +
+            // 16 (c ^ ((r >> 2) & 3)), so the 16 rows one fragment read
+            // touches per chunk fall on distinct banks.  Each step reads its
+            // fragments, then issues the next slice into the other buffer,
+            // then runs its MFMAs.
+            constexpr int PL = Fmt<MODE>::kPlanes;
+            constexpr int NI = (NA + NBB) * PL * 8;   // 1 KB instructions per slice
+            constexpr int NQ = NI / 8;                 // per wave
+            static_assert(NI % 8 == 0, "instructions per wave");
+            typedef const void __attribute__((address_space(1))) *gptr;
+            typedef void __attribute__((address_space(3))) *lptr;
+            auto tile_base = [&](int buf, int t) -> char * {
+                return t < NA ? reinterpret_cast<char *>(&As[buf][t])
+                              : reinterpret_cast<char *>(&Bs[buf][t - NA]);
+            };
+            const __bf16 *src[NQ];
+            int dst_t[NQ], dst_off[NQ];
 #pragma unroll
-        for (int u = 0; u < DEPTH; ++u) load_fast(st[u], u * KS);
-        stash(st[0], 0);
-        __syncthreads();
-        for (; kb + 2 * DEPTH < nk + 1; kb += DEPTH) {
+            for (int q = 0; q < NQ; ++q) {
+                const int idx = wave + 8 * q;
+                const int t = idx / (PL * 8), pl = (idx / 8) % PL, rb = idx % 8;
+                const int r = rb * 16 + (lane >> 2);
+                const int c = (lane & 3) ^ ((r >> 2) & 3);
+                // (selects over the few operands: indexing the argument copy
+                // with a per-wave value would move it to scratch memory)
+                const void *base = nullptr;
 #pragma unroll
-            for (int u = 0; u < DEPTH; ++u) {
-                const int k = kb + u;   // k + DEPTH < nk throughout
-                load_fast(st[u], (k + DEPTH) * KS);
-                __builtin_amdgcn_sched_barrier(0);   // issue the loads before the MFMAs
-                compute(k & 1);
-                stash(st[(u + 1) % DEPTH], (k + 1) & 1);
-                __syncthreads();
+                for (int u = 0; u < NA; ++u)
+                    if (t == u) base = pl ? a.A[u].p[PL - 1] : a.A[u].p[0];
+#pragma unroll
+                for (int u = 0; u < NBB; ++u)
+                    if (t == NA + u) base = pl ? a.B[u].p[PL - 1] : a.B[u].p[0];
+                const int r0 = t < NA ? m0 : n0;
+                src[q] = static_cast<const __bf16 *>(base) + (size_t)(r0 + r) * K + c * 8;
+                dst_t[q] = t;
+                dst_off[q] = pl * 8192 + rb * 1024;
             }
+            auto issue = [&](int buf, int k0) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    __builtin_amdgcn_global_load_lds((gptr)(src[q] + k0),
+                                                     (lptr)(tile_base(buf, dst_t[q]) + dst_off[q]),
+                                                     16, 0, 0);
+            };
+            auto frag = [&](int buf, int t, int pl, int row) -> bf8 {
+                const int c = (lane >> 4) ^ ((row >> 2) & 3);
+                return *reinterpret_cast<const bf8 *>(tile_base(buf, t) + pl * 8192 + row * 64 + c * 16);
+            };
+            const int nk = K / KS;
+            issue(0, 0);
+            for (int k = 0; k < nk; ++k) {
+                const int buf = k & 1;
+                // this wave's part of slice k has landed; the barrier publishes
+                // every wave's part and frees the other buffer
+                __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0)
+                asm volatile("s_barrier" ::: "memory");
+                bf8 fa[NA][PL][FI], fb[NBB][PL][FJ];
+#pragma unroll
+                for (int b = 0; b < NA; ++b)
+#pragma unroll
+                    for (int pl = 0; pl < PL; ++pl)
+#pragma unroll
+                        for (int i = 0; i < FI; ++i) fa[b][pl][i] = frag(buf, b, pl, wm + i * 16 + (lane & 15));
+#pragma unroll
+                for (int b = 0; b < NBB; ++b)
+#pragma unroll
+                    for (int pl = 0; pl < PL; ++pl)
+#pragma unroll
+                        for (int j = 0; j < FJ; ++j)
+                            fb[b][pl][j] = frag(buf, NA + b, pl, wn + j * 16 + (lane & 15));
+                if (k + 1 < nk) issue(buf ^ 1, (k + 1) * KS);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const int ba = A_BATCHED ? b : 0, bb = A_BATCHED ? 0 : b;
+#pragma unroll
+                    for (int i = 0; i < FI; ++i)
+#pragma unroll
+                        for (int j = 0; j < FJ; ++j) {
+                            if constexpr (MODE == MCA_PREC_BF16X3) {
+                                acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    fa[ba][1][i], fb[bb][0][j], acc[b][i][j], 0, 0, 0);
+                                acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    fa[ba][0][i], fb[bb][PL - 1][j], acc[b][i][j], 0, 0, 0);
+                            }
+                            acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                fa[ba][0][i], fb[bb][0][j], acc[b][i][j], 0, 0, 0);
+                        }
+                }
+            }
+            done = true;
         }
-    } else {
-#pragma unroll
-        for (int u = 0; u < DEPTH; ++u)
-            if (u < nk) load(st[u], u * KS);
-        stash(st[0], 0);
-        __syncthreads();
     }
-    for (; kb < nk; kb += DEPTH) {
-#pragma unroll
-        for (int u = 0; u < DEPTH; ++u) {
-            const int k = kb + u;
-            if (k < nk) {   // uniform
-                if (k + DEPTH < nk) load(st[u], (k + DEPTH) * KS);
-                compute(k & 1);
-                if (k + 1 < nk) stash(st[(u + 1) % DEPTH], (k + 1) & 1);
-                __syncthreads();
+    if (!done) {
+        // DEPTH K slices in flight: a ring of register stages; the loop is unrolled
+        // by DEPTH so that the stages rotate by name.  At step k the stage that
+        // held slice k (already in LDS) receives slice k + DEPTH, slice k is
+        // multiplied, and slice k + 1 moves from registers into the other LDS buffer.
+        const int nk = (K + KS - 1) / KS;
+        Stage st[DEPTH];
+        int kb = 0;
+        if (fast_m && fast_n && K % KS == 0 && nk >= DEPTH) {
+            // the same ring with the loads' conditions lifted out of the steady
+            // state, so that no branch sits between a load and the wait before
+            // its LDS store and the wait covers only that stage
+    #pragma unroll
+            for (int u = 0; u < DEPTH; ++u) load_fast(st[u], u * KS);
+            stash(st[0], 0);
+            __syncthreads();
+            for (; kb + 2 * DEPTH < nk + 1; kb += DEPTH) {
+    #pragma unroll
+                for (int u = 0; u < DEPTH; ++u) {
+                    const int k = kb + u;   // k + DEPTH < nk throughout
+                    load_fast(st[u], (k + DEPTH) * KS);
+                    __builtin_amdgcn_sched_barrier(0);   // issue the loads before the MFMAs
+                    compute(k & 1);
+                    stash(st[(u + 1) % DEPTH], (k + 1) & 1);
+                    __syncthreads();
+                }
+            }
+        } else {
+    #pragma unroll
+            for (int u = 0; u < DEPTH; ++u)
+                if (u < nk) load(st[u], u * KS);
+            stash(st[0], 0);
+            __syncthreads();
+        }
+        for (; kb < nk; kb += DEPTH) {
+    #pragma unroll
+            for (int u = 0; u < DEPTH; ++u) {
+                const int k = kb + u;
+                if (k < nk) {   // uniform
+                    if (k + DEPTH < nk) load(st[u], (k + DEPTH) * KS);
+                    compute(k & 1);
+                    if (k + 1 < nk) stash(st[(u + 1) % DEPTH], (k + 1) & 1);
+                    __syncthreads();
+                }
             }
         }
     }
