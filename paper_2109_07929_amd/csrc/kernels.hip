@@ -371,8 +371,11 @@ __device__ void givens_block(double *__restrict__ H, int ldh, int j, double hlas
 }
 
 // w = sig_j J z~_j (eq. (J); z~_j the preconditioned u_j) with the partials of
-// <w, u_q>, q <= j.
-template <int MAXV, int NT>
+// <w, u_q>, q <= j.  POST: z~_j's bottom half comes from its top half here
+// (the literal form's last step, eq. (block)): z_b = ((G_t + a1 I) z_t - r_t)
+// / a1 at the crosspoint, stored, and at the rows above and below for the
+// bottom wire's stencil, the same arithmetic as k_precond_post.
+template <int MAXV, int NT, bool POST>
 __global__ __launch_bounds__(NT) void k_jacobian_proj(GsStep a)
 {
     if (*a.ctl) return;
@@ -385,11 +388,27 @@ __global__ __launch_bounds__(NT) void k_jacobian_proj(GsStep a)
 #pragma unroll 1
     for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < mn; k += (size_t)gridDim.x * NT) {
         const int i = (int)(k / n), jj = (int)(k - (size_t)i * n);
-        const double t = a.zt[k], b = a.zb[k];
+        const double t = a.zt[k];
         const double st = wire_apply(a.top, jj, t, (jj > 0) ? a.zt[k - 1] : 0.0,
                                      (jj + 1 < n) ? a.zt[k + 1] : 0.0);
-        const double sb = wire_apply(a.bot, i, b, (i > 0) ? a.zb[k - n] : 0.0,
-                                     (i + 1 < m) ? a.zb[k + n] : 0.0);
+        double b, bm, bp;
+        if constexpr (POST) {
+            auto zb_at = [&](size_t kk) {
+                const double z = a.zt[kk];
+                const double s = wire_apply(a.top, jj, z, (jj > 0) ? a.zt[kk - 1] : 0.0,
+                                            (jj + 1 < n) ? a.zt[kk + 1] : 0.0);
+                return (s + a.post_a1 * z - a.post_rt[kk]) * a.post_inv_a1;
+            };
+            b = zb_at(k);
+            a.zb_store[k] = b;
+            bm = (i > 0) ? zb_at(k - n) : 0.0;
+            bp = (i + 1 < m) ? zb_at(k + n) : 0.0;
+        } else {
+            b = a.zb[k];
+            bm = (i > 0) ? a.zb[k - n] : 0.0;
+            bp = (i + 1 < m) ? a.zb[k + n] : 0.0;
+        }
+        const double sb = wire_apply(a.bot, i, b, bm, bp);
         const double c = a.d[k] * (t - b);
         const double y1 = sj * (st + c), y2 = sj * (sb - c);
         a.w[k] = y1;
@@ -849,10 +868,17 @@ hipError_t launch_gs_step(const GsStep &g, int pass, hipStream_t s)
         // short bases: kProjBlocks blocks of 1024 threads, whose partials every
         // update block sums; longer ones: kGsBlocks blocks of TPB threads
         const dim3 pg(kProjBlocks), pb(1024);
-        if (nv <= 4) hipLaunchKernelGGL((k_jacobian_proj<4, 1024>), pg, pb, 0, s, g);
-        else if (nv <= 8) hipLaunchKernelGGL((k_jacobian_proj<8, 1024>), pg, pb, 0, s, g);
-        else if (nv <= 16) hipLaunchKernelGGL((k_jacobian_proj<16, TPB>), grid, b, 0, s, g);
-        else hipLaunchKernelGGL((k_jacobian_proj<32, TPB>), grid, b, 0, s, g);
+        if (g.post_rt) {
+            if (nv <= 4) hipLaunchKernelGGL((k_jacobian_proj<4, 1024, true>), pg, pb, 0, s, g);
+            else if (nv <= 8) hipLaunchKernelGGL((k_jacobian_proj<8, 1024, true>), pg, pb, 0, s, g);
+            else if (nv <= 16) hipLaunchKernelGGL((k_jacobian_proj<16, TPB, true>), grid, b, 0, s, g);
+            else hipLaunchKernelGGL((k_jacobian_proj<32, TPB, true>), grid, b, 0, s, g);
+        } else {
+            if (nv <= 4) hipLaunchKernelGGL((k_jacobian_proj<4, 1024, false>), pg, pb, 0, s, g);
+            else if (nv <= 8) hipLaunchKernelGGL((k_jacobian_proj<8, 1024, false>), pg, pb, 0, s, g);
+            else if (nv <= 16) hipLaunchKernelGGL((k_jacobian_proj<16, TPB, false>), grid, b, 0, s, g);
+            else hipLaunchKernelGGL((k_jacobian_proj<32, TPB, false>), grid, b, 0, s, g);
+        }
     } else if (pass == 1) {
         static_assert(kGsFusedMaxV == 8, "variants below");
         // short bases: kProjBlocks blocks of 1024 threads (each forms h itself)

@@ -265,6 +265,12 @@ struct GsStep {
     // bfloat16 hi [+ lo]), the conversion the next step's chain would make
     void *xp[2][2];
     int prec;
+    // with post_rt set (literal form), pass 0 also forms the preconditioner's
+    // last step z_b = ((G_t + a1 I) z_t - r_t) / a1 from z_t, stores it at
+    // zb_store and uses it in place of zb
+    const double *post_rt;
+    double *zb_store;
+    double post_a1, post_inv_a1;
 };
 // pass 0: the Jacobian product with the projections; pass 1: the update;
 // pass 2: ||w||, sig_{j+1}, row j + 1 of L, the Givens update and the snapshot

@@ -364,7 +364,8 @@ mca_status precond_setup(const mca_plan *P, int form, double a1, double a2, cons
 mca_status precond_run(const mca_plan *P, int form, int precision, double a1, double a2,
                        const double *rt, const double *rb, double *zt, double *zb,
                        const PrecondWs &w, hipStream_t s, Timing *tm = nullptr, int slot = 0,
-                       const int *skip = nullptr, const double *D = nullptr, bool r_split = false)
+                       const int *skip = nullptr, const double *D = nullptr, bool r_split = false,
+                       bool defer_post = false)
 {
     Timing off;
     if (!tm) tm = &off;
@@ -475,7 +476,8 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
             nl = 5;
         }
         MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, nl, slot));
-        MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s, skip));
+        // (deferred: the caller's Jacobian pass forms z_b)
+        if (!defer_post) MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s, skip));
         return MCA_OK;
     }
     if (form == MCA_PRECOND_LITERAL) {
@@ -495,8 +497,8 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
         g.M = m; g.N = n; g.K = n; g.L0 = w.b1t; g.R = d.QnT; g.O0 = zt;
         MCA_TRY(launch_gemm_f64(g, EPI_STORE, s));
         MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 4, slot));
-        // z_b = ((G_t + a1 I) z_t - r_t) / a1
-        MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s, skip));
+        // z_b = ((G_t + a1 I) z_t - r_t) / a1 (deferred: the caller's Jacobian pass forms it)
+        if (!defer_post) MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s, skip));
         return MCA_OK;
     }
     // per-mode: transform both layers, solve each mode's 2x2 block, transform back
@@ -578,6 +580,13 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
             for (int pl = 0; pl < 2; ++pl) gs.xp[b][pl] = w.pw.lp[b].p[pl];
         gs.prec = o->precision;
     }
+    // the literal form's last step (z_b from z_t) runs inside the Jacobian pass
+    const bool post_fused = two_pass && o->precond == MCA_PRECOND_LITERAL &&
+                            o->precision == MCA_PREC_FP64;
+    if (post_fused) {
+        gs.post_a1 = a;
+        gs.post_inv_a1 = 1.0 / a;
+    }
     int its = 0, restarts = 0;
     bool converged = false, first = true;
     // v_0 = -F / ||F||
@@ -598,7 +607,7 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
             // (the previous step's update pass left v_j in operand format)
             mca_status st = precond_run(P, o->precond, o->precision, a, a, vj, vj + mn, zj,
                                         zj + mn, w.pw, s, tm, slot, skip, w.D,
-                                        lp_fused && j > 0);
+                                        lp_fused && j > 0, post_fused);
             if (st != MCA_OK) return st;
             double *hcol = w.H + (size_t)j * ldh;
             if (two_pass) {
@@ -607,6 +616,10 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
                 gs.j = j;
                 gs.zt = zj;
                 gs.zb = zj + mn;
+                if (post_fused) {
+                    gs.post_rt = vj;
+                    gs.zb_store = zj + mn;
+                }
                 gs.w = wv;
                 gs.hcol = hcol;
                 gs.snap = snap_dev + 4 * j;
