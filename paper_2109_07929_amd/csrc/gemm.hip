@@ -21,6 +21,8 @@
 // with two slices of global loads in flight.  A second batch (the bottom
 // layer) may share the same R tile: the per-mode 2x2 solve of the block
 // formula (eq. (block)) then runs in the epilogue on both accumulators.
+// Launches of at most one whole tile per CU take the direct-to-LDS variant
+// (k_gemm_tn_f64_dma), which can also fuse the persymmetric unfold.
 #include "mca_internal.h"
 
 namespace mca {
