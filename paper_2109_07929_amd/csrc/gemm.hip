@@ -306,10 +306,11 @@ struct DmaSlice {
     double r[BK][64];
 };
 
-template <int EPI, int BK, int ST>
-__global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
+template <int EPI, int BK, int ST, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64_dma(GemmArgs a)
 {
-    static_assert(BK % 16 == 0 && BK >= 32 && (ST == 2 || ST == 4), "slice shape");
+    static_assert(BK % (2 * WAVES) == 0 && BK >= 32 && (ST == 2 || ST == 4), "slice shape");
+    static_assert(WAVES == 4 || WAVES == 8, "2 x 2 waves of 32 x 32 or 2 x 4 of 32 x 16");
     int bid = blockIdx.x, nwg = gridDim.x;
     if (a.pair) {
         nwg >>= 1;
@@ -327,13 +328,14 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
     if (a.skip && *a.skip) return;   // uniform: a converged GMRES cycle
 
     constexpr bool UNF = EPI == EPI_UNFOLD;
-    constexpr int T = BK / 16;        // row pairs per wave and operand in a slice
+    constexpr int T = BK / (2 * WAVES);   // row pairs per wave and operand in a slice
+    constexpr int WJ = (WAVES == 4) ? 2 : 1, WCOLS = 16 * WJ;
     const int M = a.M, N = a.N, K = a.K;
     int tm, tn;
     tile_of(bid, nwg, M / BM, N / BN, tm, tn);   // (UNF: M/2 rows in tiles of 32)
     const int m0 = tm * (UNF ? BM / 2 : BM), n0 = tn * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave / 4) * 32, wn = (wave % 4) * 16;
+    const int wm = (wave / (BN / WCOLS)) * 32, wn = (wave % (BN / WCOLS)) * WCOLS;
     const size_t ldl = UNF ? (size_t)(M / 2) : (size_t)M;
 
     // wave w fills slice rows 2T w .. 2T w + 2T - 1, two per instruction
@@ -362,15 +364,18 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
         }
     };
 
-    d4 acc[1][2][1];
-    acc[0][0][0] = d4{0.0, 0.0, 0.0, 0.0};
-    acc[0][1][0] = d4{0.0, 0.0, 0.0, 0.0};
-    double af[2][2], bf[2];
+    d4 acc[1][2][WJ];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < WJ; ++j) acc[0][i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    double af[2][2], bf[2][WJ];
     auto frag = [&](const DmaSlice<BK> &S, int k4, int slot) {
         const int kr = k4 * 4 + (lane >> 4);
 #pragma unroll
         for (int i = 0; i < 2; ++i) af[slot][i] = S.l[kr][swz(kr, wm + i * 16 + (lane & 15))];
-        bf[slot] = S.r[kr][swz(kr, wn + (lane & 15))];
+#pragma unroll
+        for (int j = 0; j < WJ; ++j) bf[slot][j] = S.r[kr][swz(kr, wn + j * 16 + (lane & 15))];
     };
     auto compute = [&](const DmaSlice<BK> &S) {
         frag(S, 0, 0);
@@ -380,8 +385,10 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                acc[0][i][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[k4 & 1][i], bf[k4 & 1],
-                                                                    acc[0][i][0], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < WJ; ++j)
+                    acc[0][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[k4 & 1][i], bf[k4 & 1][j],
+                                                                        acc[0][i][j], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
         }
     };
@@ -424,27 +431,32 @@ __global__ __launch_bounds__(512) void k_gemm_tn_f64_dma(GemmArgs a)
     if constexpr (UNF) {
         // every wave's DMA has landed (S0 is free); B goes through S0.l
         asm volatile("s_barrier" ::: "memory");
-        const int c = wn + (lane & 15);
         if (wm == 32) {
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) S0.l[i * 16 + (lane >> 4) + 4 * r][c] = acc[0][i][0][r];
+                for (int j = 0; j < WJ; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        S0.l[i * 16 + (lane >> 4) + 4 * r][wn + j * 16 + (lane & 15)] = acc[0][i][j][r];
         }
         asm volatile("s_barrier" ::: "memory");
         if (wm == 0) {
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int p = m0 + i * 16 + (lane >> 4) + 4 * r;
-                    const double A = acc[0][i][0][r], Bv = S0.l[p - m0][c];
-                    a.O0[(size_t)p * N + n0 + c] = A + Bv;
-                    a.O0[(size_t)(M - 1 - p) * N + n0 + c] = A - Bv;
-                }
+                for (int j = 0; j < WJ; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int p = m0 + i * 16 + (lane >> 4) + 4 * r;
+                        const int c = wn + j * 16 + (lane & 15);
+                        const double A = acc[0][i][j][r], Bv = S0.l[p - m0][c];
+                        a.O0[(size_t)p * N + n0 + c] = A + Bv;
+                        a.O0[(size_t)(M - 1 - p) * N + n0 + c] = A - Bv;
+                    }
         }
     } else {
-        store_tile<1, EPI, 1>(a, acc, m0, n0, wm, wn, lane);
+        store_tile<1, EPI, WJ>(a, acc, m0, n0, wm, wn, lane);
     }
 }
 
@@ -459,10 +471,11 @@ static void launch_variant(const GemmArgs &a, int tiles, hipStream_t s)
     hipLaunchKernelGGL((k_gemm_tn_f64<NB, EPI, 32, 8, false>), dim3(tiles), dim3(512), 0, s, a);
 }
 
-// direct-to-LDS launches: 32-deep slices in two buffers (64 KB of LDS).
-// Measured at 1024^2 (application of the persymmetric literal form): 126.8 us
-// with two 32-deep buffers, 126.6 us with two 64-deep, 129 us with four 32-deep.
-constexpr int kDmaBk = 32, kDmaSt = 2, kDmaKStep = kDmaBk * kDmaSt;
+// direct-to-LDS launches: 32-deep slices in two buffers (64 KB of LDS), eight
+// waves.  Measured at 1024^2 (application of the persymmetric literal form):
+// 126.8 us with two 32-deep buffers, 126.6 us with two 64-deep, 129 us with
+// four 32-deep; four waves of 32 x 32: 134.9 us (32-deep), 139 us (64-deep).
+constexpr int kDmaBk = 32, kDmaSt = 2, kDmaKStep = kDmaBk * kDmaSt, kDmaWaves = 8;
 
 bool gemm_unfold_fits(int M, int N, int K)
 {
@@ -488,7 +501,7 @@ hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
     if (epi == EPI_UNFOLD) {
         if (!gemm_unfold_fits(a.M, a.N, a.K) || !a.vec || !a.L1 || a.pair || a.ldo)
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_UNFOLD, kDmaBk, kDmaSt>), dim3(tiles), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_UNFOLD, kDmaBk, kDmaSt, kDmaWaves>), dim3(tiles), dim3(64 * kDmaWaves), 0, s, a);
         return hipGetLastError();
     }
     // whole tiles, at most one tile per CU: the direct-to-LDS kernel (with
@@ -499,9 +512,9 @@ hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
                      a.K > 0 && epi != EPI_PERMODE && tiles <= 256;
     if (dma) {
         if (epi == EPI_DIV_MU)
-            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_DIV_MU, kDmaBk, kDmaSt>), dim3(tiles), dim3(512), 0, s, a);
+            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_DIV_MU, kDmaBk, kDmaSt, kDmaWaves>), dim3(tiles), dim3(64 * kDmaWaves), 0, s, a);
         else
-            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_STORE, kDmaBk, kDmaSt>), dim3(tiles), dim3(512), 0, s, a);
+            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_STORE, kDmaBk, kDmaSt, kDmaWaves>), dim3(tiles), dim3(64 * kDmaWaves), 0, s, a);
         return hipGetLastError();
     }
     if (dual) {
