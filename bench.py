@@ -108,6 +108,10 @@ def krylov_hbm(st, mn, opts, kms, steps):
     from paper_2109_07929_amd import binding as B
     R = opts.restart
     two_pass = not (opts.flags & B.MCA_FLAG_MGS_PASSES) and R <= 32
+    # literal FP64 form, two passes: the Jacobian pass also forms the preconditioner's
+    # last step z_b from z_t (reads r_t and writes z_b instead of reading z_b: +8 B)
+    post = (two_pass and opts.precond == B.MCA_PRECOND_LITERAL
+            and opts.precision == B.MCA_PREC_FP64)
     alg = kern = 0.0
     for k in st.krylov_history[:st.newton_iters]:
         while k > 0:
@@ -115,7 +119,7 @@ def krylov_hbm(st, mn, opts, kms, steps):
             for j in range(c):
                 alg += 40 + 16 * (j + 1) + 32
                 if two_pass:
-                    kern += (40 + 16 * (j + 1)) + (32 + 16 * (j + 1))
+                    kern += (40 + (8 if post else 0) + 16 * (j + 1)) + (32 + 16 * (j + 1))
                 else:
                     # Jacobian with <y, v_0> (56), j + 1 fused MGS passes (64, the last
                     # without the next projection 48), normalisation (32)

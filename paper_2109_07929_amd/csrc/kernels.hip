@@ -373,8 +373,12 @@ __device__ void givens_block(double *__restrict__ H, int ldh, int j, double hlas
 // w = sig_j J z~_j (eq. (J); z~_j the preconditioned u_j) with the partials of
 // <w, u_q>, q <= j.  POST: z~_j's bottom half comes from its top half here
 // (the literal form's last step, eq. (block)): z_b = ((G_t + a1 I) z_t - r_t)
-// / a1 at the crosspoint, stored, and at the rows above and below for the
-// bottom wire's stencil, the same arithmetic as k_precond_post.
+// / a1 with the arithmetic of k_precond_post, stored for the solution update.
+// The bottom wire's stencil needs z_b at the rows above and below, so a POST
+// thread walks a strip of kPostRows rows of one column and rolls z_t's row
+// triple and z_b down it (each z_b formed (kPostRows + 2) / kPostRows times).
+constexpr int kPostRows = 4;
+
 template <int MAXV, int NT, bool POST>
 __global__ __launch_bounds__(NT) void k_jacobian_proj(GsStep a)
 {
@@ -385,29 +389,9 @@ __global__ __launch_bounds__(NT) void k_jacobian_proj(GsStep a)
     double acc[MAXV];
 #pragma unroll
     for (int q = 0; q < MAXV; ++q) acc[q] = 0.0;
-#pragma unroll 1
-    for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < mn; k += (size_t)gridDim.x * NT) {
-        const int i = (int)(k / n), jj = (int)(k - (size_t)i * n);
-        const double t = a.zt[k];
-        const double st = wire_apply(a.top, jj, t, (jj > 0) ? a.zt[k - 1] : 0.0,
-                                     (jj + 1 < n) ? a.zt[k + 1] : 0.0);
-        double b, bm, bp;
-        if constexpr (POST) {
-            auto zb_at = [&](size_t kk) {
-                const double z = a.zt[kk];
-                const double s = wire_apply(a.top, jj, z, (jj > 0) ? a.zt[kk - 1] : 0.0,
-                                            (jj + 1 < n) ? a.zt[kk + 1] : 0.0);
-                return (s + a.post_a1 * z - a.post_rt[kk]) * a.post_inv_a1;
-            };
-            b = zb_at(k);
-            a.zb_store[k] = b;
-            bm = (i > 0) ? zb_at(k - n) : 0.0;
-            bp = (i + 1 < m) ? zb_at(k + n) : 0.0;
-        } else {
-            b = a.zb[k];
-            bm = (i > 0) ? a.zb[k - n] : 0.0;
-            bp = (i + 1 < m) ? a.zb[k + n] : 0.0;
-        }
+    // one crosspoint: t = z_t, st = top stencil of z_t, b / bm / bp = z_b here,
+    // one row up, one row down
+    auto point = [&](size_t k, int i, double t, double st, double b, double bm, double bp) {
         const double sb = wire_apply(a.bot, i, b, bm, bp);
         const double c = a.d[k] * (t - b);
         const double y1 = sj * (st + c), y2 = sj * (sb - c);
@@ -416,6 +400,59 @@ __global__ __launch_bounds__(NT) void k_jacobian_proj(GsStep a)
 #pragma unroll
         for (int q = 0; q < MAXV; ++q)
             if (q < nv) acc[q] += y1 * a.V[q * a.ldv + k] + y2 * a.V[q * a.ldv + mn + k];
+    };
+    if constexpr (POST) {
+        const int strips = (m + kPostRows - 1) / kPostRows;
+        const size_t units = (size_t)strips * n;
+#pragma unroll 1
+        for (size_t u = (size_t)blockIdx.x * NT + threadIdx.x; u < units; u += (size_t)gridDim.x * NT) {
+            const int sx = (int)(u / n), jj = (int)(u - (size_t)sx * n);
+            const int i0 = sx * kPostRows, i1 = min(i0 + kPostRows, m);
+            auto row = [&](int i, double &zl, double &zc, double &zr) {
+                const size_t kk = (size_t)i * n + jj;
+                zc = a.zt[kk];
+                zl = (jj > 0) ? a.zt[kk - 1] : 0.0;
+                zr = (jj + 1 < n) ? a.zt[kk + 1] : 0.0;
+            };
+            auto zb_of = [&](int i, double zl, double zc, double zr) {
+                const double s = wire_apply(a.top, jj, zc, zl, zr);
+                return (s + a.post_a1 * zc - a.post_rt[(size_t)i * n + jj]) * a.post_inv_a1;
+            };
+            double cl, cc, cr;
+            row(i0, cl, cc, cr);
+            double bc = zb_of(i0, cl, cc, cr), bprev = 0.0;
+            if (i0 > 0) {
+                double pl, pc, pr;
+                row(i0 - 1, pl, pc, pr);
+                bprev = zb_of(i0 - 1, pl, pc, pr);
+            }
+#pragma unroll 1
+            for (int i = i0; i < i1; ++i) {
+                double nl = 0.0, nc = 0.0, nr = 0.0, bnext = 0.0;
+                if (i + 1 < m) {
+                    row(i + 1, nl, nc, nr);
+                    bnext = zb_of(i + 1, nl, nc, nr);
+                }
+                const size_t k = (size_t)i * n + jj;
+                a.zb_store[k] = bc;
+                point(k, i, cc, wire_apply(a.top, jj, cc, cl, cr), bc, bprev, bnext);
+                bprev = bc;
+                bc = bnext;
+                cl = nl;
+                cc = nc;
+                cr = nr;
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < mn; k += (size_t)gridDim.x * NT) {
+            const int i = (int)(k / n), jj = (int)(k - (size_t)i * n);
+            const double t = a.zt[k];
+            const double st = wire_apply(a.top, jj, t, (jj > 0) ? a.zt[k - 1] : 0.0,
+                                         (jj + 1 < n) ? a.zt[k + 1] : 0.0);
+            point(k, i, t, st, a.zb[k], (i > 0) ? a.zb[k - n] : 0.0,
+                  (i + 1 < m) ? a.zb[k + n] : 0.0);
+        }
     }
     dev::block_store_sums<MAXV, NT>(acc, nv, a.p1 + blockIdx.x, gridDim.x);
 }
