@@ -32,6 +32,7 @@ namespace mca {
 namespace {
 
 using dev::block_sum;
+using dev::sinh_cosh;
 using dev::TPB;
 using dev::wire_apply;
 
@@ -115,9 +116,10 @@ __global__ __launch_bounds__(TPB) void bk_residual(
             cur = g * u;
             slope = g;
         } else {
-            const double x = u / in.v0;
-            cur = g * in.v0 * sinh(x);
-            slope = g * cosh(x);
+            double sh, ch;
+            sinh_cosh(u / in.v0, sh, ch);
+            cur = g * in.v0 * sh;
+            slope = g * ch;
         }
         const double f1 = st + cur, f2 = sb - cur;
         ft[k] = f1;

@@ -8,6 +8,16 @@ namespace dev {
 
 constexpr int TPB = 256;   // threads per block of the streaming kernels
 
+// sinh x and cosh x from one expm1 of |x|: with e = expm1(|x|) >= 0 and p = 1 + e,
+// sinh |x| = e (2 + e) / (2 p) = (e / 2)(1 + 1/p) and cosh x = (p + 1/p) / 2 (no
+// cancellation for small |x|, none in p for large |x|; a few ulps each).
+__device__ __forceinline__ void sinh_cosh(double x, double &sh, double &ch)
+{
+    const double e = expm1(fabs(x)), p = 1.0 + e, r = 1.0 / p;
+    sh = copysign(0.5 * e * (1.0 + r), x);
+    ch = 0.5 * (p + r);
+}
+
 // Product of one wire matrix (eq. (G) with end terminations) with x at node k
 // of the wire, in branch-current form:
 //   sum over the node's segments of g (x_k - x_neighbour)

@@ -15,6 +15,7 @@ namespace {
 
 using dev::block_sum;
 using dev::sum_partials;
+using dev::sinh_cosh;
 using dev::TPB;
 using dev::wire_apply;
 
@@ -46,9 +47,10 @@ __global__ __launch_bounds__(TPB) void k_residual(
             cur = g * u;
             slope = g;
         } else {
-            const double x = u / v0;
-            cur = g * v0 * sinh(x);
-            slope = g * cosh(x);
+            double sh, ch;
+            sinh_cosh(u / v0, sh, ch);
+            cur = g * v0 * sh;
+            slope = g * ch;
         }
         const double f1 = st + cur, f2 = sb - cur;
         ft[k] = f1;
