@@ -64,7 +64,7 @@ def parse():
                    help="with --mc / --batch: skip the per-crossbar loop comparison")
     p.add_argument("--no-compare", action="store_true",
                    help="skip the batched + warm-started + mixed-precision comparison")
-    p.add_argument("--compare-batch", type=int, default=8,
+    p.add_argument("--compare-batch", type=int, default=16,
                    help="crossbars per batch of the comparison forms")
     p.add_argument("--copy-calib", action="store_true",
                    help="after the timed solves, copy a 256 MiB float64 array device-to-device "
