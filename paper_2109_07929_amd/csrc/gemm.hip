@@ -133,11 +133,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
     __shared__ double Rs[2][BK][BN + PAD];
     if (a.skip && *a.skip) return;   // uniform: a converged GMRES cycle
 
+    // EPI_UNFOLD (whole tiles only): 32 rows of A = Y_s^T R over the same rows
+    // of B = Y_a^T R, as in the direct-to-LDS kernel
+    constexpr bool UNF = EPI == EPI_UNFOLD;
+    static_assert(!UNF || NB == 1, "one batch");
     const int M = a.M, N = a.N, K = a.K;
     const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
     int tm, tn;
     tile_of(bid, nwg, tiles_m, tiles_n, tm, tn);
-    const int m0 = tm * BM, n0 = tn * BN;
+    const int m0 = tm * (UNF ? BM / 2 : BM), n0 = tn * BN;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave / (BN / WCOLS)) * 32, wn = (wave % (BN / WCOLS)) * WCOLS;
@@ -156,7 +160,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
                 const size_t gk = (size_t)(k0 + lr + RP * h);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    const double2 *p = reinterpret_cast<const double2 *>(Lb[b] + gk * M + m0 + lc);
+                    const double2 *p = reinterpret_cast<const double2 *>(
+                        UNF ? (lc < 32 ? a.L0 : a.L1) + gk * (M / 2) + m0 + (lc & 31)
+                            : Lb[b] + gk * M + m0 + lc);
                     st.l[b][h][0] = p[0];
                     st.l[b][h][1] = p[1];
                 }
@@ -285,7 +291,37 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_tn_f64(GemmArgs a)
     }
     if (kt < nk) compute(kt & 1);
 
-    store_tile<NB, EPI, WJ>(a, acc, m0, n0, wm, wn, lane);
+    if constexpr (UNF) {
+        // B passes through the first L buffer once every wave is done with it
+        __syncthreads();
+        double(*X)[BM + PAD] = Ls[0][0];
+        if (wm == 32) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < WJ; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        X[i * 16 + (lane >> 4) + 4 * r][wn + j * 16 + (lane & 15)] = acc[0][i][j][r];
+        }
+        __syncthreads();
+        if (wm == 0) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < WJ; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int p = m0 + i * 16 + (lane >> 4) + 4 * r;
+                        const int c = wn + j * 16 + (lane & 15);
+                        const double A = acc[0][i][j][r], Bv = X[p - m0][c];
+                        a.O0[(size_t)p * N + n0 + c] = A + Bv;
+                        a.O0[(size_t)(M - 1 - p) * N + n0 + c] = A - Bv;
+                    }
+        }
+    } else {
+        store_tile<NB, EPI, WJ>(a, acc, m0, n0, wm, wn, lane);
+    }
 }
 
 // Direct-to-LDS variant for whole tiles (M, N multiples of 64, K a multiple of
@@ -479,9 +515,8 @@ constexpr int kDmaBk = 32, kDmaSt = 2, kDmaKStep = kDmaBk * kDmaSt, kDmaWaves = 
 
 bool gemm_unfold_fits(int M, int N, int K)
 {
-    // the direct-to-LDS kernel's conditions, with M/2 rows in 32-row tiles
-    return M > 0 && N > 0 && M % BM == 0 && N % BN == 0 && K % kDmaKStep == 0 && K > 0 &&
-           (M / BM) * (N / BN) <= 256;
+    // whole tiles (M/2 rows in 32-row tiles) and whole K slices of either kernel
+    return M > 0 && N > 0 && M % BM == 0 && N % BN == 0 && K % kDmaKStep == 0 && K > 0;
 }
 
 hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
@@ -501,7 +536,11 @@ hipError_t launch_gemm_f64(const GemmArgs &in, int epi, hipStream_t s)
     if (epi == EPI_UNFOLD) {
         if (!gemm_unfold_fits(a.M, a.N, a.K) || !a.vec || !a.L1 || a.pair || a.ldo)
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_UNFOLD, kDmaBk, kDmaSt, kDmaWaves>), dim3(tiles), dim3(64 * kDmaWaves), 0, s, a);
+        if (tiles <= 256)
+            hipLaunchKernelGGL((k_gemm_tn_f64_dma<EPI_UNFOLD, kDmaBk, kDmaSt, kDmaWaves>), dim3(tiles),
+                               dim3(64 * kDmaWaves), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_gemm_tn_f64<1, EPI_UNFOLD, 32, 8, false>), dim3(tiles), dim3(512), 0, s, a);
         return hipGetLastError();
     }
     // whole tiles, at most one tile per CU: the direct-to-LDS kernel (with

@@ -132,13 +132,16 @@ def test_precond_none_is_identity():
     np.testing.assert_array_equal(host(zb), rb)
 
 
-@pytest.mark.parametrize("form", [B.MCA_PRECOND_LITERAL, B.MCA_PRECOND_PERMODE])
-def test_precond_inverts_P_at_1024(form):
-    """Full size (1024 x 1024, the solver's launch shape): ||P z - r|| / ||r||,
-    with P z from the oracle's Jacobian product at uniform slope a (P(a,a) = J)."""
-    m = n = 1024
+@pytest.mark.parametrize("m,n,form", [(1024, 1024, B.MCA_PRECOND_LITERAL),
+                                      (1024, 1024, B.MCA_PRECOND_PERMODE),
+                                      (1152, 1024, B.MCA_PRECOND_LITERAL)])
+def test_precond_inverts_P_at_1024(m, n, form):
+    """Full size (1024 x 1024, the solver's launch shape; 1152 x 1024 puts the
+    literal form's last product over more than 256 tiles, the register-staged
+    kernel with the unfold fused): ||P z - r|| / ||r||, with P z from the
+    oracle's Jacobian product at uniform slope a (P(a,a) = J)."""
     a = 2.2e-5
-    say(f"precond 1024^2 form={form}")
+    say(f"precond {m}x{n} form={form}")
     geom = synth.Geometry(m, n)
     rt, rb = synth.vector(m, n, seed=5)
     plan = _plan_with_eigs(geom)
