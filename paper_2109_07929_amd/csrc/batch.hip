@@ -1240,23 +1240,39 @@ mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *str
     BatchLayout D = batch_layout(B, dev_buf);      // device addresses
     std::memcpy(H.inst, B->inst.data(), cnt * sizeof(BInst));
     std::memcpy(H.btab, B->btab.data(), B->btab.size() * sizeof(int2));
-    std::vector<double> tmp;
-    for (size_t u = 0; u < B->plans.size(); ++u) {
-        const mca_plan *P = B->plans[u];
-        const size_t m = P->geom.m, n = P->geom.n;
-        // QnT, QmT, Qm, Qn in FP64 from the host eigenvectors
-        for (int q = 0; q < 4; ++q) {
-            const size_t L = (q == 0 || q == 3) ? n : m;
-            const std::vector<double> &src = (q == 0 || q == 3) ? P->Qn : P->Qm;
-            const bool tr = (q == 0 || q == 1);
-            tmp.resize(L * L);
-            for (size_t i = 0; i < L; ++i)
-                for (size_t j = 0; j < L; ++j) tmp[i * L + j] = tr ? src[j * L + i] : src[i * L + j];
-            split_host(tmp.data(), L * L, MCA_PREC_FP32, H.q32[q][u], nullptr);
-            split_host(tmp.data(), L * L, MCA_PREC_BF16X3, H.qh[q][u], H.ql[q][u]);
+    // every plan's operand planes, spread over host threads (disjoint parts of the image)
+    const size_t np = B->plans.size();
+    auto convert = [&](size_t first, size_t stride) {
+        std::vector<double> tmp;
+        for (size_t u = first; u < np; u += stride) {
+            const mca_plan *P = B->plans[u];
+            const size_t m = P->geom.m, n = P->geom.n;
+            // QnT, QmT, Qm, Qn in FP64 from the host eigenvectors
+            for (int q = 0; q < 4; ++q) {
+                const size_t L = (q == 0 || q == 3) ? n : m;
+                const std::vector<double> &src = (q == 0 || q == 3) ? P->Qn : P->Qm;
+                const bool tr = (q == 0 || q == 1);
+                tmp.resize(L * L);
+                for (size_t i = 0; i < L; ++i)
+                    for (size_t j = 0; j < L; ++j) tmp[i * L + j] = tr ? src[j * L + i] : src[i * L + j];
+                split_host(tmp.data(), L * L, MCA_PREC_FP32, H.q32[q][u], nullptr);
+                split_host(tmp.data(), L * L, MCA_PREC_BF16X3, H.qh[q][u], H.ql[q][u]);
+            }
+            std::memcpy(H.lt[u], P->lt.data(), n * sizeof(double));
+            std::memcpy(H.lb[u], P->lb.data(), m * sizeof(double));
         }
-        std::memcpy(H.lt[u], P->lt.data(), n * sizeof(double));
-        std::memcpy(H.lb[u], P->lb.data(), m * sizeof(double));
+    };
+    {
+        const size_t nt = std::max<size_t>(1, std::min<size_t>({16, np, std::thread::hardware_concurrency()}));
+        std::vector<std::thread> pool;
+        size_t started = 0;
+        try {
+            for (; started + 1 < nt; ++started) pool.emplace_back(convert, started + 1, nt);
+        } catch (...) {   // fewer threads than asked: this thread takes the rest
+        }
+        convert(0, nt);
+        for (size_t t = started + 1; t < nt; ++t) convert(t, nt);
+        for (auto &th : pool) th.join();
     }
     for (size_t b = 0; b < cnt; ++b) {
         const int u = B->pidx[b];

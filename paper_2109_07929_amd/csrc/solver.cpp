@@ -14,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mca_internal.h"
@@ -795,18 +796,28 @@ mca_status mca_plan_create(const mca_geometry *geom, mca_plan **out)
     P->top = make_wire(geom->n, geom->g_top, geom->g_src, geom->g_top_end);
     P->bot = make_wire(geom->m, geom->g_bot, geom->g_bot_end0, geom->g_bot_end1);
     const int m = geom->m, n = geom->n;
-    std::vector<double> diag, off;
+    // the top wire's problem on a thread of its own, beside the bottom wire's
     P->lt.resize(n);
     P->Qn.resize((size_t)n * n);
-    wire_tridiag(P->top, diag, off);
-    tridiag_eigen(n, diag.data(), off.data(), P->lt.data(), P->Qn.data());
+    auto top_job = [P, n] {
+        std::vector<double> d, o;
+        wire_tridiag(P->top, d, o);
+        tridiag_eigen(n, d.data(), o.data(), P->lt.data(), P->Qn.data());
+    };
+    std::thread top_th;
+    try {
+        top_th = std::thread(top_job);
+    } catch (...) {   // no thread to be had: run it here
+        top_job();
+    }
+    std::vector<double> diag, off;
     P->lb.resize(m);
     P->Qm.resize((size_t)m * m);
     wire_tridiag(P->bot, diag, off);
-    tridiag_eigen(m, diag.data(), off.data(), P->lb.data(), P->Qm.data());
     // persymmetric G_bot: the symmetric / antisymmetric eigenvectors [u; +-J u]/sqrt2
     // come from two h x h problems, the last diagonal entry shifted by -+ the
-    // coupling of the two middle nodes
+    // coupling of the two middle nodes; the full basis Q_m is assembled from
+    // them (eigenvalues merged in ascending order)
     P->persym = (m >= 2) && (m % 2 == 0) && (geom->g_bot_end0 == geom->g_bot_end1);
     if (P->persym) {
         const int h = m / 2;
@@ -821,7 +832,22 @@ mca_status mca_plan_create(const mca_geometry *geom, mca_plan **out)
             (sign == 0 ? P->Us : P->Ua) = Q;
             (sign == 0 ? P->ls : P->la) = lam;
         }
+        int is = 0, ia = 0;
+        for (int col = 0; col < m; ++col) {
+            const bool sym = ia >= h || (is < h && P->ls[is] <= P->la[ia]);
+            const std::vector<double> &Q = sym ? P->Us : P->Ua;
+            const int s = sym ? is++ : ia++;
+            P->lb[col] = sym ? P->ls[s] : P->la[s];
+            for (int i = 0; i < h; ++i) {
+                const double v = Q[(size_t)i * h + s];
+                P->Qm[(size_t)i * m + col] = v;
+                P->Qm[(size_t)(m - 1 - i) * m + col] = sym ? v : -v;
+            }
+        }
+    } else {
+        tridiag_eigen(m, diag.data(), off.data(), P->lb.data(), P->Qm.data());
     }
+    if (top_th.joinable()) top_th.join();
     P->dev_bytes = plan_layout(P, nullptr).bytes;
     *out = P;
     return MCA_OK;
