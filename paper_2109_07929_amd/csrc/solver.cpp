@@ -719,11 +719,13 @@ mca_status residual_norms(const mca_plan *P, const double *g_dev, const double *
         set_hip_error("hipHostMalloc", hipErrorOutOfMemory);
         return MCA_ERR_HIP;
     }
+    double *host_dev = nullptr;   // the same pinned words, as the device sees them
+    MCA_TRY(hipHostGetDevicePointer((void **)&host_dev, host, 0));
     MCA_TRY(tm->begin(MCA_KCLASS_RESIDUAL, s));
     MCA_TRY(launch_residual(P, g_dev, v_in, vt, vb, F, F + mn, D, w.pa, s));
     MCA_TRY(tm->end(MCA_KCLASS_RESIDUAL, s, 1));
-    MCA_TRY(launch_reduce(w.pa, reduce_blocks(mn), 2, w.scal, s));
-    MCA_TRY(hipMemcpyAsync(host, w.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    // the one-block reduction stores ||F||^2 and sum D straight into host memory
+    MCA_TRY(launch_reduce(w.pa, reduce_blocks(mn), 2, host_dev, s));
     MCA_TRY(hipStreamSynchronize(s));
     MCA_TRY(tm->collect());
     *fnorm = std::sqrt(host[0]);
@@ -1024,9 +1026,10 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     }
 
     // ||Y|| = g_src ||v_in||
+    double *host_dev = nullptr;
+    MCA_TRY(hipHostGetDevicePointer((void **)&host_dev, host, 0));
     MCA_TRY(launch_dot_partials(v_in, v_in, P->geom.m, w.pa, s));
-    MCA_TRY(launch_reduce(w.pa, reduce_blocks(P->geom.m), 1, w.scal, s));
-    MCA_TRY(hipMemcpyAsync(host, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    MCA_TRY(launch_reduce(w.pa, reduce_blocks(P->geom.m), 1, host_dev, s));
     MCA_TRY(hipStreamSynchronize(s));
     const double ynorm = P->geom.g_src * std::sqrt(host[0]);
     if (!std::isfinite(ynorm)) return MCA_ERR_NONFINITE;
