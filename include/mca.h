@@ -184,7 +184,9 @@ size_t      mca_abi_struct_size(int32_t which);
  * writes P^{-1} through Kronecker products of these matrices (eqs. (M),
  * (M-1hat), (2matrix4)); their eigenbasis turns every Kronecker factor into a
  * diagonal, so a1, a2 only shift eigenvalues and nothing is refactorised per
- * Newton step.  *out receives a host object freed by mca_plan_destroy.
+ * Newton step.  *out receives a host object freed by mca_plan_destroy.  The
+ * two wires are decomposed on the calling thread and one extra host thread
+ * (joined before return; thread-safe for distinct plans).
  * Errors: MCA_ERR_INVALID_ARG (bad geometry or NULL out).                    */
 mca_status mca_plan_create(const mca_geometry *geom, mca_plan **out);
 void       mca_plan_destroy(mca_plan *plan);
