@@ -604,7 +604,9 @@ __global__ __launch_bounds__(NT) void k_gs_update(GsStep a)
 // partials, Hessenberg column j, the rotations, g[j], the scales) is issued
 // before any of them is used: the kernel is a chain of dependent steps, and
 // that keeps it to one memory round trip before the arithmetic.
-__global__ __launch_bounds__(1024) void k_gs_finish(GsStep a)
+// (the body runs in a block of 1024 threads, in k_gs_finish or as block 0 of
+// k_finish_fold)
+__device__ __forceinline__ void gs_finish_block(const GsStep &a)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int j = a.j, nv = j + 1;
@@ -689,6 +691,49 @@ __global__ __launch_bounds__(1024) void k_gs_finish(GsStep a)
         }
     }
     write_snapshot(a.snap, ctl);
+}
+
+__global__ __launch_bounds__(1024) void k_gs_finish(GsStep a) { gs_finish_block(a); }
+
+// The finish of Arnoldi step j - 1 (block 0, dispatched first) and the fold that starts step
+// j's literal preconditioner (the other blocks, as k_precond_pre_fold) in one
+// launch: the two are independent (the preconditioner is applied to the
+// unnormalised u_j, which needs no sigma), and the finish, a chain of
+// dependent steps in one workgroup, then no longer takes a launch of its own.
+// The fold blocks skip on the stop flag as it stands when they start (the
+// finish may set it meanwhile; the products after them read it again).
+struct FoldArgs {
+    int m, n;
+    Wire bot;
+    double inv_a1, a2;
+    const double *rt, *rb;
+    double *f;
+    const int *skip;
+};
+
+__global__ __launch_bounds__(1024) void k_finish_fold(GsStep g, FoldArgs a)
+{
+    if (blockIdx.x == 0) {
+        gs_finish_block(g);
+        return;
+    }
+    if (a.skip && *a.skip) return;
+    const int m = a.m, n = a.n, h = m / 2;
+    const size_t hn = (size_t)h * n;
+    auto w_at = [&](int i, int j) {
+        const size_t k = (size_t)i * n + j;
+        const double r = a.rt[k];
+        const double s = wire_apply(a.bot, i, r, (i > 0) ? a.rt[k - n] : 0.0,
+                                    (i + 1 < m) ? a.rt[k + n] : 0.0);
+        return a.rb[k] + (s + a.a2 * r) * a.inv_a1;
+    };
+    const size_t stride = (size_t)(gridDim.x - 1) * 1024;
+    for (size_t k = (size_t)(blockIdx.x - 1) * 1024 + threadIdx.x; k < hn; k += stride) {
+        const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
+        const double w0 = w_at(i, j), w1 = w_at(m - 1 - i, j);
+        a.f[k] = w0 + w1;
+        a.f[hn + k] = w0 - w1;
+    }
 }
 
 // ------------------------------------------- least squares on the device
@@ -841,6 +886,28 @@ hipError_t launch_precond_pre(const mca_plan *P, double a1, double a2, const dou
     const int m = P->geom.m, n = P->geom.n;
     hipLaunchKernelGGL(k_precond_pre, dim3(elementwise_blocks((size_t)m * n)), dim3(TPB), 0, s,
                        m, n, P->bot, 1.0 / a1, a2, rt, rb, w, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_fold(const GsStep &g, const mca_plan *P, double a1, double a2,
+                              const double *rt, const double *rb, double *f, hipStream_t s,
+                              const int *skip)
+{
+    const int nv = g.j + 1;
+    if (g.j < 0 || nv > kGsMaxV || g.j + 1 >= g.ldl || g.j + 1 >= g.ldh) return hipErrorInvalidValue;
+    FoldArgs a{};
+    a.m = P->geom.m;
+    a.n = P->geom.n;
+    a.bot = P->bot;
+    a.inv_a1 = 1.0 / a1;
+    a.a2 = a2;
+    a.rt = rt;
+    a.rb = rb;
+    a.f = f;
+    a.skip = skip;
+    const size_t hn = (size_t)(a.m / 2) * a.n;
+    const int fold = (int)std::max<size_t>(1, std::min<size_t>((hn + 1023) / 1024, 512));
+    hipLaunchKernelGGL(k_finish_fold, dim3(fold + 1), dim3(1024), 0, s, g, a);
     return hipGetLastError();
 }
 

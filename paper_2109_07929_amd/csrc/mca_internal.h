@@ -275,6 +275,12 @@ struct GsStep {
 // pass 0: the Jacobian product with the projections; pass 1: the update;
 // pass 2: ||w||, sig_{j+1}, row j + 1 of L, the Givens update and the snapshot
 hipError_t launch_gs_step(const GsStep &g, int pass, hipStream_t s);
+// pass 2 of step g.j together with the persymmetric literal form's first
+// stencil and fold of the next step's preconditioner input (as
+// launch_precond_pre_fold), in one launch
+hipError_t launch_finish_fold(const GsStep &g, const mca_plan *P, double a1, double a2,
+                              const double *rt, const double *rb, double *f, hipStream_t s,
+                              const int *skip);
 
 // Device-side least squares of one GMRES cycle (see k_givens).
 enum CycleReason { CYCLE_RUNNING = 0, CYCLE_CONVERGED = 1, CYCLE_BREAKDOWN = 2,

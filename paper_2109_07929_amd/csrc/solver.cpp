@@ -366,10 +366,19 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
                        const double *rt, const double *rb, double *zt, double *zb,
                        const PrecondWs &w, hipStream_t s, Timing *tm = nullptr, int slot = 0,
                        const int *skip = nullptr, const double *D = nullptr, bool r_split = false,
-                       bool defer_post = false)
+                       bool defer_post = false, const GsStep *fin = nullptr,
+                       hipEvent_t fin_done = nullptr)
 {
     Timing off;
     if (!tm) tm = &off;
+    // fin: the previous Arnoldi step's finish, launched with this application's
+    // first kernel where that is the persymmetric fold, else on its own first;
+    // fin_done is recorded right after it
+    if (fin && !(form == MCA_PRECOND_LITERAL && precision == MCA_PREC_FP64 && P->persym)) {
+        MCA_TRY(launch_gs_step(*fin, 2, s));
+        MCA_TRY(hipEventRecord(fin_done, s));
+        fin = nullptr;
+    }
     if (form == MCA_PRECOND_APPROX) {
         // the paper's M ~ Mhat (eqs. (Mhat)-(2matrix4)) as a block back-substitution:
         // z_b = (G_b + a2 I)^{-1} r_b down the columns, then
@@ -442,7 +451,12 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
         const int h = m / 2;
         const size_t hn = (size_t)h * n;
         // P = w_top + J w_bot, Q = w_top - J w_bot with w = r_b + (G_b + a2 I) r_t / a1
-        MCA_TRY(launch_precond_pre_fold(P, a1, a2, rt, rb, w.b0t, s, skip));
+        if (fin) {
+            MCA_TRY(launch_finish_fold(*fin, P, a1, a2, rt, rb, w.b0t, s, skip));
+            MCA_TRY(hipEventRecord(fin_done, s));
+        } else {
+            MCA_TRY(launch_precond_pre_fold(P, a1, a2, rt, rb, w.b0t, s, skip));
+        }
         MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
         // W_hat^T = [P^T U_s | Q^T U_a]   (n x m, modes: symmetric, antisymmetric; one launch)
         g.M = n; g.N = h; g.K = h; g.ldo = m; g.pair = 1;
@@ -584,6 +598,11 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
     // the literal form's last step (z_b from z_t) runs inside the Jacobian pass
     const bool post_fused = two_pass && o->precond == MCA_PRECOND_LITERAL &&
                             o->precision == MCA_PREC_FP64;
+    // persymmetric literal form: step j's finish shares a launch with step j + 1's
+    // first stencil (the finish of the cycle's last enqueued step runs alone)
+    const bool merge_fin = post_fused && P->persym;
+    GsStep fin{};
+    bool fin_pending = false;
     if (post_fused) {
         gs.post_a1 = a;
         gs.post_inv_a1 = 1.0 / a;
@@ -608,7 +627,9 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
             // (the previous step's update pass left v_j in operand format)
             mca_status st = precond_run(P, o->precond, o->precision, a, a, vj, vj + mn, zj,
                                         zj + mn, w.pw, s, tm, slot, skip, w.D,
-                                        lp_fused && j > 0, post_fused);
+                                        lp_fused && j > 0, post_fused,
+                                        fin_pending ? &fin : nullptr, done[slot ^ 1]);
+            fin_pending = false;
             if (st != MCA_OK) return st;
             double *hcol = w.H + (size_t)j * ldh;
             if (two_pass) {
@@ -630,7 +651,12 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
                 MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s, slot));
                 MCA_TRY(launch_gs_step(gs, 1, s));
                 MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 1 <= kGsFusedMaxV ? 1 : 2, slot));
-                MCA_TRY(launch_gs_step(gs, 2, s));
+                if (merge_fin) {
+                    fin = gs;
+                    fin_pending = true;
+                } else {
+                    MCA_TRY(launch_gs_step(gs, 2, s));
+                }
             } else {
                 // w = J z_j, fused with the partial sums of <w, v_0>
                 MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
@@ -651,7 +677,9 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
                 MCA_TRY(launch_givens(w.H, ldh, j, w.g, w.cs, w.sn, abs_tol, w.ctl, w.resid,
                                       snap_dev + 4 * j, s));
             }
-            MCA_TRY(hipEventRecord(done[slot], s));
+            // (with the finish pending, done[slot] is recorded after it, at the
+            // start of the next step or below)
+            if (!fin_pending) MCA_TRY(hipEventRecord(done[slot], s));
             last = j;
             if (j > 0) {
                 // step j runs on the GPU while the host reads step j-1's outcome
@@ -660,6 +688,11 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
                 MCA_TRY(tm->collect(slot ^ 1, c[1] == j));
                 if (c[0]) break;
             }
+        }
+        if (fin_pending) {   // the last enqueued step's finish, alone
+            MCA_TRY(launch_gs_step(fin, 2, s));
+            MCA_TRY(hipEventRecord(done[last & 1], s));
+            fin_pending = false;
         }
         if (last >= 0) {
             MCA_TRY(hipEventSynchronize(done[last & 1]));
