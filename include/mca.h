@@ -87,7 +87,7 @@ typedef int32_t mca_status;
 #define MCA_FLAG_GRAPH        16  /* mca_solve_batched only: each Arnoldi step is captured
                                      once into a HIP graph kept in the batch and replayed
                                      by later cycles and solves with the same workspace,
-                                     precision and restart length                       */
+                                     precision, restart length and Gram-Schmidt form    */
 #define MCA_FLAG_MGS_PASSES   32  /* Arnoldi orthogonalisation in one pass over the
                                      vector per basis vector (modified Gram-Schmidt as
                                      written) instead of the default two passes per step
@@ -301,6 +301,12 @@ mca_status mca_batch_offsets(const mca_batch *batch, int64_t *cross_offsets,
 size_t     mca_batch_device_bytes(const mca_batch *batch);
 mca_status mca_batch_upload(mca_batch *batch, void *dev_buf, size_t bytes, void *stream);
 
+/* Edge of the square output tiles (64 or 128) of the batch's grouped
+ * eigenbasis products, fixed at creation from the crossbar sizes: 128 when
+ * every crossbar's sides are at least 256 and the batch gives at least 256
+ * such tiles per product, else 64.  0 for a NULL batch.  Host only.        */
+int32_t    mca_batch_product_tile(const mca_batch *batch);
+
 /* Device workspace of mca_solve_batched with opts (NULL = PERMODE, BF16X3,
  * other fields as mca_options_default); 0 when opts are not supported.    */
 size_t     mca_batch_workspace_bytes(const mca_batch *batch, const mca_options *opts);
@@ -312,7 +318,8 @@ size_t     mca_batch_workspace_bytes(const mca_batch *batch, const mca_options *
  * are accepted and ignored.
  * The batch keeps pinned host counters and, with MCA_FLAG_GRAPH, the captured
  * Arnoldi steps (dropped when the workspace address, precision, restart
- * length or uploaded block change): calls on one batch must not overlap.
+ * length, Gram-Schmidt form or uploaded block change): calls on one batch
+ * must not overlap.
  * Returns MCA_OK when every crossbar converged, else the status of the first
  * crossbar that did not (the per-crossbar outcome is in the residual
  * history of stats).  Synchronises stream.

@@ -132,6 +132,11 @@ class Batch:
             self.handle = None
 
     @property
+    def product_tile(self):
+        """Tile edge (64 or 128) of the batch's grouped eigenbasis products."""
+        return binding.mca_batch_product_tile(self.handle)
+
+    @property
     def total(self):
         return int(self.cross[-1])
 

@@ -59,7 +59,7 @@ ABI_SYMBOLS = (
     "mca_precond_workspace_bytes", "mca_residual", "mca_jacobian_apply",
     "mca_precond_apply", "mca_solve",
     "mca_batch_create", "mca_batch_destroy", "mca_batch_offsets", "mca_batch_device_bytes",
-    "mca_batch_upload", "mca_batch_workspace_bytes", "mca_solve_batched",
+    "mca_batch_product_tile", "mca_batch_upload", "mca_batch_workspace_bytes", "mca_solve_batched",
     "mca_cnn_param_count", "mca_cnn_workspace_bytes", "mca_cnn_predict", "mca_cnn_gradient",
     "mca_cnn_adam",
 )
@@ -159,6 +159,8 @@ def lib():
     L.mca_batch_device_bytes.restype = sz
     L.mca_batch_upload.argtypes = [vp, vp, sz, vp]
     L.mca_batch_upload.restype = i32
+    L.mca_batch_product_tile.argtypes = [vp]
+    L.mca_batch_product_tile.restype = i32
     L.mca_batch_workspace_bytes.argtypes = [vp, C.POINTER(mca_options)]
     L.mca_batch_workspace_bytes.restype = sz
     L.mca_solve_batched.argtypes = [vp, vp, vp, vp, vp, C.POINTER(mca_options), vp, sz,
@@ -351,6 +353,10 @@ def mca_batch_offsets(batch, count: int):
 
 def mca_batch_device_bytes(batch) -> int:
     return int(lib().mca_batch_device_bytes(batch))
+
+
+def mca_batch_product_tile(batch) -> int:
+    return int(lib().mca_batch_product_tile(batch))
 
 
 def mca_batch_upload(batch, dev_buf, stream=None) -> None:

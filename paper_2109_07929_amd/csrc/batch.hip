@@ -909,6 +909,7 @@ struct StepGraphs {
     void *ws = nullptr;
     const void *dev = nullptr;
     int precision = -1, restart = 0;
+    int two_pass = -1;                  // Gram-Schmidt form the steps were captured with
     hipStream_t cap = nullptr;          // private stream that the steps are captured on
     std::vector<hipGraphExec_t> exec;
     void clear()
@@ -1228,6 +1229,8 @@ mca_status mca_batch_offsets(const mca_batch *B, int64_t *cross_offsets, int64_t
 
 size_t mca_batch_device_bytes(const mca_batch *B) { return B ? B->dev_bytes : 0; }
 
+int32_t mca_batch_product_tile(const mca_batch *B) { return B ? B->tile : 0; }
+
 mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *stream)
 {
     if (!B || !dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) & 255)) return MCA_ERR_INVALID_ARG;
@@ -1368,15 +1371,19 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     int *host = B->host, *host_dev = nullptr;
     MCA_BTRY(hipHostGetDevicePointer((void **)&host_dev, host, 0));
     const bool graph = (o.flags & MCA_FLAG_GRAPH) != 0;
+    // the Gram-Schmidt form decides which kernels an Arnoldi step holds
+    const bool two_pass = !(o.flags & MCA_FLAG_MGS_PASSES) && R <= kGsMaxV;
     StepGraphs &G = B->graphs;
     if (graph) {
-        if (G.ws != ws || G.dev != B->dev_buf || G.precision != o.precision || G.restart != R)
+        if (G.ws != ws || G.dev != B->dev_buf || G.precision != o.precision || G.restart != R ||
+            G.two_pass != (int)two_pass)
             G.clear();
         if (!G.cap) MCA_BTRY(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
         G.ws = ws;
         G.dev = B->dev_buf;
         G.precision = o.precision;
         G.restart = R;
+        G.two_pass = (int)two_pass;
         G.exec.resize(R, nullptr);
     }
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1417,7 +1424,6 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     gc.a_stride = (int)(sizeof(BState) / sizeof(double));
     gc.ctl = w.ctl;
 
-    const bool two_pass = !(o.flags & MCA_FLAG_MGS_PASSES) && R <= kGsMaxV;
     BGs gs{};
     gs.I = B->d_inst;
     gs.bt = B->d_btab;

@@ -256,17 +256,26 @@ SolveWs solve_layout(const mca_plan *P, const mca_options *o, void *base)
     return w;
 }
 
-// Small pinned host staging area for the scalars read back per iteration.
+// Small pinned host staging area for the scalars read back per iteration, one
+// per host thread, released when the thread ends.
+struct PinnedScratch {
+    double *buf = nullptr;
+    ~PinnedScratch()
+    {
+        if (buf) (void)hipHostFree(buf);
+    }
+};
+
 double *pinned_scratch()
 {
-    thread_local double *buf = nullptr;
-    if (!buf) {
+    thread_local PinnedScratch ps;
+    if (!ps.buf) {
         void *p = nullptr;
         if (hipHostMalloc(&p, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess)
             return nullptr;
-        buf = static_cast<double *>(p);
+        ps.buf = static_cast<double *>(p);
     }
-    return buf;
+    return ps.buf;
 }
 
 #define MCA_TRY(expr)                                   \

@@ -177,16 +177,55 @@ def test_batch_more_than_1024_crossbars():
         assert rel_err(vts[b], vbs[b], rt, rb) <= TOL
 
 
-def test_batch_large_crossbars_use_large_tiles():
-    """Batches whose crossbars all have sides >= 256 run the grouped products on
-    128 x 128 tiles; ragged sizes (not multiples of 128) against the oracle."""
-    cbs = [synth.crossbar(300, 520, seed=s) for s in range(4)]
+_CG_CACHE = {}
+
+
+def _oracle_cg(c, key):
+    """Oracle B's steady state of crossbar c, computed once per module."""
+    if key not in _CG_CACHE:
+        _CG_CACHE[key] = oracle.solve(c.geom, c.g_dev, c.v_in, method="cg")[:2]
+    return _CG_CACHE[key]
+
+
+@pytest.mark.parametrize("prec", [B.MCA_PREC_FP32, B.MCA_PREC_BF16X3])
+def test_batch_large_tiles_ragged(prec):
+    """18 crossbars of 300 x 520 give 18 x 15 = 270 tiles of 128 per product, so
+    the grouped products run 128 x 128 tiles (checked through the library's
+    tile query), with edge tiles cut at 300 = 2 x 128 + 44 and 520 = 4 x 128 + 8
+    and more than one tile per CU.  Every crossbar against the oracle."""
+    cbs = [synth.crossbar(300, 520, seed=s) for s in range(18)]
+    bt, vts, vbs, status, stats = batch_solve(cbs, precision=prec)
+    assert bt.product_tile == 128
+    assert status == B.MCA_OK
+    worst = 0.0
+    for b, c in enumerate(cbs):
+        rt, rb = _oracle_cg(c, ("300x520", b))
+        err = rel_err(vts[b], vbs[b], rt, rb)
+        worst = max(worst, err)
+        assert err <= TOL, (b, err)
+    say(f"  18 x 300x520 prec {prec}: newton {[s.newton_iters for s in stats[:4]]}..., "
+        f"worst err {worst:.1e}")
+
+
+@pytest.mark.parametrize("count", [4, 5])
+def test_batch_large_tiles_1024(count):
+    """1024 x 1024 crossbars on 128 x 128 tiles, split-BF16: 4 crossbars give
+    256 tiles per product (one per CU: slices go straight into LDS), 5 give 320
+    (register-staged slices, the path of larger batches).  Every crossbar's
+    residual is recomputed by the oracle; crossbars 0 and 1 are compared with
+    the oracle's steady state element by element."""
+    cbs = [synth.crossbar(1024, 1024, seed=s) for s in range(count)]
     bt, vts, vbs, status, stats = batch_solve(cbs)
+    assert bt.product_tile == 128
     assert status == B.MCA_OK
     for b, c in enumerate(cbs):
-        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="cg")
+        ft, fb = oracle.residual(c.geom, c.g_dev, c.v_in, vts[b], vbs[b])[:2]
+        rel = np.sqrt((ft ** 2).sum() + (fb ** 2).sum()) / oracle.source_norm(c.geom, c.v_in)
+        assert rel <= 1e-10, (b, rel)
+    for b in (0, 1):
+        rt, rb = _oracle_cg(cbs[b], ("1024", b))
         err = rel_err(vts[b], vbs[b], rt, rb)
-        say(f"  {c.geom.m}x{c.geom.n}: newton {stats[b].newton_iters} krylov "
+        say(f"  {count} x 1024^2 crossbar {b}: newton {stats[b].newton_iters} krylov "
             f"{stats[b].krylov_iters} err {err:.1e}")
         assert err <= TOL
 
@@ -229,6 +268,34 @@ def test_batch_graph_replays_match_eager():
         assert got[2] == ref[k][2]
         assert got[3] == ref[k][3]
         assert np.array_equal(got[0], ref[k][0]) and np.array_equal(got[1], ref[k][1])
+
+
+def test_batch_graph_follows_gram_schmidt_form():
+    """Captured Arnoldi steps depend on the Gram-Schmidt form: graph solves that
+    alternate between the two-pass form and one pass per basis vector on one
+    workspace each reproduce the eager solve of their own form bit for bit."""
+    cbs = ragged_batch(seed=5)
+    bt = Batch([c.geom for c in cbs])
+    g = bt.concat([c.g_dev for c in cbs])
+    v = bt.concat([c.v_in for c in cbs])
+    kw = dict(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3, restart=5)
+    ws = bt.workspace(B.options(**kw))
+    ref = {}
+    for name, flags in (("two-pass", 0), ("per-vector", B.MCA_FLAG_MGS_PASSES)):
+        vt, vb, status, stats = bt.solve(g, v, B.options(flags=flags, **kw), ws=ws)
+        torch.cuda.synchronize()
+        assert status == B.MCA_OK
+        ref[name] = (vt.cpu().numpy(), vb.cpu().numpy(), [s.krylov_iters for s in stats])
+    for name, flags in (("two-pass", 0), ("per-vector", B.MCA_FLAG_MGS_PASSES),
+                        ("two-pass", 0), ("per-vector", B.MCA_FLAG_MGS_PASSES)):
+        vt, vb, status, stats = bt.solve(g, v, B.options(flags=flags | B.MCA_FLAG_GRAPH, **kw),
+                                         ws=ws)
+        torch.cuda.synchronize()
+        say(f"graph {name}: status {status} krylov {[s.krylov_iters for s in stats]}")
+        assert status == B.MCA_OK
+        assert [s.krylov_iters for s in stats] == ref[name][2]
+        assert np.array_equal(vt.cpu().numpy(), ref[name][0])
+        assert np.array_equal(vb.cpu().numpy(), ref[name][1])
 
 
 def test_single_solve_rejects_graph_flag():

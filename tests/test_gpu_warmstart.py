@@ -72,17 +72,31 @@ def test_trained_network_gains_on_held_out_crossbars():
     assert s["krylov_warm"] < s["krylov_cold"]
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (40, 70), (300, 129)])
+# A Newton tolerance no start can miss: the solve returns its starting point.
+RETURN_START = 1e300
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (40, 70), (300, 129), (1024, 1024)])
 def test_sweep_start_single(m, n):
-    """MCA_FLAG_SWEEP_START: the residual of the starting point equals that of the
-    oracle's block Gauss-Seidel sweep, and the solve reaches the oracle's state."""
+    """MCA_FLAG_SWEEP_START: the starting voltages equal the oracle's block
+    Gauss-Seidel sweep element by element, and the solve from them reaches the
+    oracle's steady state."""
     cb = synth.crossbar(m, n, seed=m + n)
     plan = Plan(cb.geom)
     g = torch.from_numpy(cb.g_dev).cuda()
     v = torch.from_numpy(cb.v_in).cuda()
+    gt, gb = oracle.sweep_guess(cb.geom, cb.g_dev, cb.v_in)
+    st_t, st_b, s, st = plan.solve(g, v, B.options(flags=B.MCA_FLAG_SWEEP_START,
+                                                   newton_tol=RETURN_START))
+    assert s == B.MCA_OK and st.start == 1 and st.newton_iters == 0
+    scale = max(np.abs(gt).max(), np.abs(gb).max())
+    d0 = max(np.abs(st_t.cpu().numpy() - gt).max(), np.abs(st_b.cpu().numpy() - gb).max()) / scale
+    say(f"  {m}x{n}: sweep start vs oracle {d0:.1e}")
+    assert d0 <= 1e-12
+    if m * n > 300 * 129:
+        return
     vt, vb, s, st = plan.solve(g, v, B.options(flags=B.MCA_FLAG_SWEEP_START))
     assert s == B.MCA_OK and st.start == 1
-    gt, gb = oracle.sweep_guess(cb.geom, cb.g_dev, cb.v_in)
     ft, fb, _ = oracle.residual(cb.geom, cb.g_dev, cb.v_in, gt, gb)
     r0 = np.sqrt((ft ** 2).sum() + (fb ** 2).sum()) / oracle.source_norm(cb.geom, cb.v_in)
     say(f"  {m}x{n}: start residual gpu {st.residual_history[0]:.6e} oracle {r0:.6e}, "
@@ -103,12 +117,20 @@ def test_sweep_start_batched_saves_a_newton_step():
     v = bt.concat([c.v_in for c in cbs])
     o = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3)
     _, _, s0, st0 = bt.solve(g, v, o)
-    ow = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3,
-                   flags=B.MCA_FLAG_SWEEP_START | B.MCA_FLAG_GUESS_FALLBACK)
+    flags = B.MCA_FLAG_SWEEP_START | B.MCA_FLAG_GUESS_FALLBACK
+    ow = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3, flags=flags)
     vt, vb, s1, st1 = bt.solve(g, v, ow)
-    assert s0 == B.MCA_OK and s1 == B.MCA_OK
+    o_start = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3, flags=flags,
+                        newton_tol=RETURN_START)
+    pt, pb, s2, st2 = bt.solve(g, v, o_start)
+    assert s0 == B.MCA_OK and s1 == B.MCA_OK and s2 == B.MCA_OK
+    pts = [t.cpu().numpy() for t in bt.split(pt)]
+    pbs = [t.cpu().numpy() for t in bt.split(pb)]
     for b, c in enumerate(cbs):
         gt, gb = oracle.sweep_guess(c.geom, c.g_dev, c.v_in)
+        scale = max(np.abs(gt).max(), np.abs(gb).max())
+        assert st2[b].start == 1 and st2[b].newton_iters == 0
+        assert max(np.abs(pts[b] - gt).max(), np.abs(pbs[b] - gb).max()) <= 1e-12 * scale
         ft, fb, _ = oracle.residual(c.geom, c.g_dev, c.v_in, gt, gb)
         r0 = np.sqrt((ft ** 2).sum() + (fb ** 2).sum()) / oracle.source_norm(c.geom, c.v_in)
         assert st1[b].start == 1

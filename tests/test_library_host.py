@@ -202,3 +202,20 @@ def test_batch_shares_set_up_of_equal_geometries():
     finally:
         for h in (same, diff, one):
             B.mca_batch_destroy(h)
+
+
+@pytest.mark.parametrize("sizes,count,tile", [
+    ((1024, 1024), 4, 128),        # 4 x 64 tiles of 128: 256
+    ((300, 520), 4, 64),           # 4 x 15 = 60 tiles of 128: too few
+    ((300, 520), 18, 128),         # 18 x 15 = 270
+    ((255, 1024), 8, 64),          # a side below 256
+    ((64, 64), 300, 64),
+])
+def test_batch_product_tile_choice(sizes, count, tile):
+    """128 x 128 product tiles only when every side is >= 256 and a product has
+    at least 256 of them (host query, no GPU)."""
+    h = B.mca_batch_create([B.geometry(*sizes)] * count)
+    try:
+        assert B.mca_batch_product_tile(h) == tile
+    finally:
+        B.mca_batch_destroy(h)
