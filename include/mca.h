@@ -252,6 +252,30 @@ mca_status mca_precond_apply(const mca_plan *plan, int32_t form, int32_t precisi
                              double *z_t, double *z_b,
                              void *ws, size_t ws_bytes, void *stream);
 
+/* mca_precond_apply without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, forms, precisions,
+ * arithmetic and kernels as mca_precond_apply; the workspace is a fixed
+ * device array inside the library, MCA_NOALLOC_SCRATCH_BYTES (32 MiB) per
+ * GPU, held from the library's load until the process ends.  The call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ * The array's address on the current GPU is looked up on the first call on
+ * that GPU (hipGetSymbolAddress; better made outside graph capture).
+ * Limit: mca_precond_workspace_bytes(plan, form, precision) <=
+ * MCA_NOALLOC_SCRATCH_BYTES, which holds every form up to 1024 x 1024
+ * crosspoints (the FP64 per-mode form needs 32 mn bytes, the others at most
+ * 24 mn); larger calls return MCA_ERR_WORKSPACE before any launch.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (other streams or host threads) race
+ * and must be serialised by the caller.  Asynchronous on stream.
+ * Errors: those of mca_precond_apply, MCA_ERR_WORKSPACE for sizes beyond the
+ * limit, MCA_ERR_HIP if the array's address cannot be found.               */
+#define MCA_NOALLOC_SCRATCH_BYTES (32u << 20)
+mca_status mca_precond_apply_noalloc(const mca_plan *plan, int32_t form, int32_t precision,
+                                     double a1, double a2,
+                                     const double *r_t, const double *r_b,
+                                     double *z_t, double *z_b, void *stream);
+
 /* Steady state: v_t, v_b with F(v_t, v_b) = 0 (eq. (F)), by Newton's method
  * (eq. (Newton3)); each step solves J dV = -F with flexible GMRES(restart),
  * modified Gram-Schmidt Arnoldi, right-preconditioned by P (eq. (P)) with

@@ -57,7 +57,7 @@ ABI_SYMBOLS = (
     "mca_plan_create", "mca_plan_destroy", "mca_plan_host_eigen",
     "mca_plan_device_bytes", "mca_plan_upload", "mca_workspace_bytes",
     "mca_precond_workspace_bytes", "mca_residual", "mca_jacobian_apply",
-    "mca_precond_apply", "mca_solve",
+    "mca_precond_apply", "mca_precond_apply_noalloc", "mca_solve",
     "mca_batch_create", "mca_batch_destroy", "mca_batch_offsets", "mca_batch_device_bytes",
     "mca_batch_product_tile", "mca_batch_upload", "mca_batch_workspace_bytes", "mca_solve_batched",
     "mca_cnn_param_count", "mca_cnn_workspace_bytes", "mca_cnn_predict", "mca_cnn_gradient",
@@ -146,6 +146,8 @@ def lib():
     L.mca_jacobian_apply.restype = i32
     L.mca_precond_apply.argtypes = [vp, i32, i32, dbl, dbl, vp, vp, vp, vp, vp, sz, vp]
     L.mca_precond_apply.restype = i32
+    L.mca_precond_apply_noalloc.argtypes = [vp, i32, i32, dbl, dbl, vp, vp, vp, vp, vp]
+    L.mca_precond_apply_noalloc.restype = i32
     L.mca_solve.argtypes = [vp, vp, vp, vp, vp, C.POINTER(mca_options), vp, sz,
                             C.POINTER(mca_stats), vp]
     L.mca_solve.restype = i32
@@ -313,6 +315,18 @@ def mca_precond_apply(plan, m, n, form, precision, a1, a2, r_t, r_b, z_t, z_b, w
                                    _ptr(r_t, mn, "r_t"), _ptr(r_b, mn, "r_b"),
                                    _ptr(z_t, mn, "z_t"), _ptr(z_b, mn, "z_b"), wp, wbytes,
                                    _stream(stream)), "mca_precond_apply")
+
+
+MCA_NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def mca_precond_apply_noalloc(plan, m, n, form, precision, a1, a2, r_t, r_b, z_t, z_b,
+                              stream=None) -> None:
+    mn = m * n
+    _check(lib().mca_precond_apply_noalloc(plan, int(form), int(precision), float(a1), float(a2),
+                                           _ptr(r_t, mn, "r_t"), _ptr(r_b, mn, "r_b"),
+                                           _ptr(z_t, mn, "z_t"), _ptr(z_b, mn, "z_b"),
+                                           _stream(stream)), "mca_precond_apply_noalloc")
 
 
 def mca_solve(plan, m, n, g_dev, v_in, v_t, v_b, opts: mca_options | None, ws, stream=None,

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -776,6 +777,34 @@ mca_status residual_norms(const mca_plan *P, const double *g_dev, const double *
     return MCA_OK;
 }
 
+// Workspace of mca_precond_apply_noalloc: one array per GPU, held by the code
+// object for the life of the process.  Host code never passes `scratch` itself
+// to a kernel (its host-side name is not the device address): the address
+// comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocBytes = (size_t)MCA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch array (looked up on first use).
+mca_status noalloc_scratch(void **out)
+{
+    int dev = -1;
+    MCA_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return MCA_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        MCA_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return MCA_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MCA_OK;
+}
+
 }  // namespace
 
 void set_hip_error(const char *what, hipError_t e)
@@ -1039,6 +1068,19 @@ mca_status mca_precond_apply(const mca_plan *P, int32_t form, int32_t precision,
     if (st != MCA_OK) return st;
     return precond_run(P, form, precision, a1, a2, r_t, r_b, z_t, z_b, w,
                        static_cast<hipStream_t>(stream));
+}
+
+mca_status mca_precond_apply_noalloc(const mca_plan *P, int32_t form, int32_t precision,
+                                     double a1, double a2, const double *r_t, const double *r_b,
+                                     double *z_t, double *z_b, void *stream)
+{
+    if (!P) return MCA_ERR_INVALID_ARG;
+    if (mca_precond_workspace_bytes(P, form, precision) > kNoAllocBytes) return MCA_ERR_WORKSPACE;
+    void *ws = nullptr;
+    const mca_status st = noalloc_scratch(&ws);
+    if (st != MCA_OK) return st;
+    return mca_precond_apply(P, form, precision, a1, a2, r_t, r_b, z_t, z_b, ws, kNoAllocBytes,
+                             stream);
 }
 
 mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in, double *v_t,
