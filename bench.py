@@ -64,6 +64,8 @@ def parse():
                    help="with --mc / --batch: skip the per-crossbar loop comparison")
     p.add_argument("--no-compare", action="store_true",
                    help="skip the batched + warm-started + mixed-precision comparison")
+    p.add_argument("--no-extra-configs", action="store_true",
+                   help="skip the 2048^2 mixed-precision and 256-crossbar Monte-Carlo legs")
     p.add_argument("--compare-batch", type=int, default=16,
                    help="crossbars per batch of the comparison forms")
     p.add_argument("--copy-calib", action="store_true",
@@ -159,17 +161,53 @@ def hbm_copy(out, roofline, kry_hbm, ev0, ev1, stream, dev):
         kry_hbm["frac_kernel_of_copy"] = round(kry_hbm["achieved_kernel"] / out["hbm_copy_GBs"], 4)
 
 
-def cpu_baseline(cb):
-    """The CPU oracle (plain FP64 C, one thread) on the same crossbar: one full
-    Newton solve with CG linear steps (the oracle's large-size method)."""
-    import numpy as np  # noqa: F401
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_solve_seconds(m, n, seed):
+    """One oracle solve of the standard crossbar (run in a worker process)."""
     import oracle
+    from paper_2109_07929_amd import synth
+    cb = synth.crossbar(m, n, seed=seed)
     t0 = time.perf_counter()
     oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="cg")
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full {cb.geom.m}x{cb.geom.n} solve (Newton, CG linear steps, "
-                      f"to the FP64 floor), single thread, {dt:.2f} s"}
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(cb, workers=16):
+    """The CPU oracle (plain FP64 C, one thread per solve) on the same crossbar:
+    one full Newton solve with CG linear steps (the oracle's large-size method),
+    first alone, then as many independent solves side by side as there are
+    workers (the host's all-cores throughput; this box's share of host cores is
+    at most 16)."""
+    import multiprocessing as mp
+    m, n = cb.geom.m, cb.geom.n
+    t1 = _oracle_solve_seconds(m, n, 0)
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    k = max(1, min(workers, avail))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(k) as pool:
+        times = pool.starmap(_oracle_solve_seconds, [(m, n, s) for s in range(k)])
+    wall = time.perf_counter() - t0
+    return {"value": round(k / wall, 4), "unit": "solves/s", "cores": k, "kind": "oracle",
+            "sample": f"{k} independent {m}x{n} solves (Newton, CG linear steps, to the FP64 "
+                      f"floor; seeds 0..{k - 1}), one per worker process, side by side: "
+                      f"{wall:.2f} s wall (slowest solve {max(times):.2f} s)",
+            "single_thread": {"value": round(1.0 / t1, 4), "cores": 1,
+                              "sample": f"one {m}x{n} solve, seed 0: {t1:.2f} s"},
+            "cpu_model": _cpu_model(), "nproc": nproc, "cpus_available": avail}
 
 
 def bench_batched(args):
@@ -327,7 +365,15 @@ def compare_forms(args, dev):
         return B.mca_solve_batched(bt.handle, count, bt.total, rows, g, v, vt, vb, o, ws,
                                    stream, check=False)
 
-    out = {"batch": count, "precision": "bf16x3 (per-mode)", "forms": {}}
+    out = {"batch": count, "precision": "bf16x3 (per-mode)", "forms": {},
+           "form_notes": {
+               "zero": "batched + mixed, Newton from V = 0",
+               "sweep": "batched + mixed, Newton from one block Gauss-Seidel sweep on the "
+                        "linearisation at V = 0 (a non-learned start)",
+               "cnn": "batched + mixed + learned warm start: the network's guess (inference "
+                      "timed), with the guess fallback"}}
+    if params is not None:
+        out["network"] = warmstart.describe_params(warmstart.DEFAULT_PARAMS)
     for form in ("zero", "sweep", "cnn"):
         if form == "cnn" and params is None:
             continue
@@ -350,6 +396,144 @@ def compare_forms(args, dev):
             "max_rel_residual": max(s.rel_residual for s in stats)}
         print(f"# {form}: {ms:.2f} ms per batch of {count}", file=sys.stderr, flush=True)
     return out
+
+
+def leg_mixed_2048(args, dev, size=2048, reps=3):
+    """The mixed-precision workload: one size x size standard crossbar (seed
+    args.seed) solved with the FP64 literal preconditioner and with the
+    split-BF16 and FP32 per-mode ones inside the same FP64 Newton-FGMRES; times
+    (HIP events, `reps` solves after one warm-up each), iterations, and the
+    largest relative voltage difference from the FP64 solve."""
+    import torch
+
+    from paper_2109_07929_amd import Plan, synth
+    from paper_2109_07929_amd import binding as B
+
+    cb = synth.crossbar(size, size, seed=args.seed)
+    t0 = time.perf_counter()
+    plan = Plan(cb.geom, device=dev)
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+    g = torch.from_numpy(cb.g_dev).to(dev)
+    v = torch.from_numpy(cb.v_in).to(dev)
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"{size}x{size} crossbar ({2 * size * size} unknowns), seed {args.seed}",
+           "setup_ms": round(setup_ms, 1), "forms": {}}
+    ref = None
+    for name, form, prec in (("fp64 literal", B.MCA_PRECOND_LITERAL, B.MCA_PREC_FP64),
+                             ("bf16x3 per-mode", B.MCA_PRECOND_PERMODE, B.MCA_PREC_BF16X3),
+                             ("fp32 per-mode", B.MCA_PRECOND_PERMODE, B.MCA_PREC_FP32)):
+        o = B.options(precond=form, precision=prec)
+        ws = plan.workspace(o)
+        vt = torch.zeros((size, size), dtype=torch.float64, device=dev)
+        vb = torch.zeros_like(vt)
+        status, st = B.mca_solve(plan.handle, size, size, g, v, vt, vb, o, ws, stream, check=False)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            status, st = B.mca_solve(plan.handle, size, size, g, v, vt, vb, o, ws, stream,
+                                     check=False)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        rec = {"ms_per_solve": round(ms, 3), "solves_per_s": round(1e3 / ms, 2),
+               "status": B.status_string(status), "newton_iters": st.newton_iters,
+               "krylov_history": list(st.krylov_history[:st.newton_iters]),
+               "rel_residual": st.rel_residual}
+        if ref is None:
+            ref = (vt.clone(), vb.clone(), ms)
+        else:
+            scale = float(torch.maximum(ref[0].abs().max(), ref[1].abs().max()))
+            dv = float(torch.maximum((vt - ref[0]).abs().max(), (vb - ref[1]).abs().max()))
+            rec["max_rel_dv_vs_fp64"] = dv / scale
+            rec["speedup_vs_fp64"] = round(ref[2] / ms, 3)
+        out["forms"][name] = rec
+        print(f"# {size}^2 {name}: {ms:.2f} ms per solve", file=sys.stderr, flush=True)
+        del ws
+    return out
+
+
+def leg_monte_carlo(args, dev, count=256):
+    """The Monte-Carlo workload: `count` crossbars with m, n drawn from
+    {64, ..., 512} (seed args.seed), split-BF16 per-mode preconditioner, solved
+    by one mca_solve_batched per batch against a loop of mca_solve calls with
+    the same options; with and without the host set-up (eigen-decompositions
+    and uploads) counted."""
+    import torch
+
+    from paper_2109_07929_amd import Batch, Plan, synth
+    from paper_2109_07929_amd import binding as B
+
+    cbs = synth.mc_batch(count, seed=args.seed)
+    opts = B.options(precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    bt = Batch([c.geom for c in cbs], device=dev)
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+    g = bt.concat([c.g_dev for c in cbs])
+    v = bt.concat([c.v_in for c in cbs])
+    vt = torch.zeros(bt.total, dtype=torch.float64, device=dev)
+    vb = torch.zeros_like(vt)
+    ws = bt.workspace(opts)
+    rows = int(bt.rows[-1])
+
+    def step():
+        return B.mca_solve_batched(bt.handle, bt.count, bt.total, rows, g, v, vt, vb, opts, ws,
+                                   stream, check=False)
+
+    step()
+    torch.cuda.synchronize()
+    reps = max(3, min(args.steps, 10))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        status, stats = step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    print(f"# Monte-Carlo {count}: {ms:.2f} ms per batch", file=sys.stderr, flush=True)
+    del ws
+    torch.cuda.empty_cache()
+    # the loop: one plan and workspace per crossbar, one mca_solve after another
+    t0 = time.perf_counter()
+    plans = [Plan(c.geom, device=dev) for c in cbs]
+    loop_setup_ms = 1e3 * (time.perf_counter() - t0)
+    data = [(torch.from_numpy(c.g_dev).to(dev), torch.from_numpy(c.v_in).to(dev),
+             torch.zeros((c.geom.m, c.geom.n), dtype=torch.float64, device=dev),
+             torch.zeros((c.geom.m, c.geom.n), dtype=torch.float64, device=dev)) for c in cbs]
+    ws_max = max(B.mca_workspace_bytes(p.handle, opts) for p in plans)
+    wsl = torch.empty(ws_max, dtype=torch.uint8, device=dev)
+
+    def loop_step():
+        worst = B.MCA_OK
+        for p, (gg, vv, ot, ob) in zip(plans, data):
+            st, _ = B.mca_solve(p.handle, p.m, p.n, gg, vv, ot, ob, opts, wsl, stream,
+                                check=False)
+            worst = worst if st == B.MCA_OK else st
+        return worst
+
+    loop_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lreps = 2
+    for _ in range(lreps):
+        lstatus = loop_step()
+    torch.cuda.synchronize()
+    loop_ms = 1e3 * (time.perf_counter() - t0) / lreps
+    print(f"# Monte-Carlo {count} loop: {loop_ms:.2f} ms", file=sys.stderr, flush=True)
+    newton = [s.newton_iters for s in stats]
+    return {"workload": f"{count} crossbars, m, n in {{64, ..., 512}}, seed {args.seed} "
+                        f"({sum(c.geom.m * c.geom.n for c in cbs)} crosspoints), bf16x3 per-mode",
+            "batched": {"ms_per_batch": round(ms, 3), "solves_per_s": round(count * 1e3 / ms, 1),
+                        "status": B.status_string(status), "setup_ms": round(setup_ms, 1),
+                        "solves_per_s_with_setup": round(count * 1e3 / (ms + setup_ms), 1),
+                        "newton_iters": [min(newton), max(newton)]},
+            "loop": {"ms_per_batch": round(loop_ms, 3),
+                     "solves_per_s": round(count * 1e3 / loop_ms, 1),
+                     "status": B.status_string(lstatus), "setup_ms": round(loop_setup_ms, 1),
+                     "solves_per_s_with_setup": round(count * 1e3 / (loop_ms + loop_setup_ms), 1)},
+            "speedup_of_batched": round(loop_ms / ms, 2),
+            "speedup_of_batched_with_setup": round((loop_ms + loop_setup_ms) / (ms + setup_ms), 2)}
 
 
 def main():
@@ -469,6 +653,9 @@ def main():
         # transforms both layers (twice the literal flops).
         g = cb.geom
         persym = (form == B.MCA_PRECOND_LITERAL and m % 2 == 0 and g.g_bot_end0 == g.g_bot_end1)
+        # algorithmic flops (the method's unit): 4(m + n) per crosspoint for the literal
+        # form (two transforms each way), 8(m + n) per mode for the per-mode form
+        alg_app = (4.0 if form == B.MCA_PRECOND_LITERAL else 8.0) * (m + n) * m * n
         qm = (1.0 if persym else 2.0) * n * m * m
         flops_app = 2 * qm + 2 * (2.0 * m * n * n)
         # transform launches per application, from the pass with every group timed
@@ -479,7 +666,8 @@ def main():
             flops_app *= 2.0
         napps = klaunch[B.MCA_KCLASS_GEMM] / launches_app
         t_app_ms = kms[B.MCA_KCLASS_GEMM] / napps
-        achieved = flops_app / (t_app_ms * 1e-3) / 1e12
+        achieved = alg_app / (t_app_ms * 1e-3) / 1e12
+        executed = flops_app / (t_app_ms * 1e-3) / 1e12
         traffic = gemm_traffic() if (m == 1024 and persym) else None
         roofline = {"bound": "mfma",
                     "kernel": "FP64 eigenbasis transforms of one preconditioner application "
@@ -491,7 +679,12 @@ def main():
                                     "WRITE_SIZE summed over its launches)",
                     "avg_application_us": round(t_app_ms * 1e3, 2),
                     "launches_per_application": launches_app,
-                    "flops_per_application": flops_app}
+                    "flops_per_application": alg_app,
+                    "flops_unit": ("algorithmic: 4(m+n) per crosspoint for the literal form, "
+                                   "8(m+n) for the per-mode form"),
+                    "executed_flops_per_application": flops_app,
+                    "executed_achieved": round(executed, 3),
+                    "executed_frac": round(executed / FP64_MFMA_PEAK_TFLOPS, 4)}
     if roofline is not None:
         roofline["timed_groups"] = ("every 4th preconditioner application of the timed solves"
                                     if not args.full_timing else
@@ -526,10 +719,26 @@ def main():
     }
     if not args.no_compare:
         cmp = compare_forms(args, dev)
-        best = max(f["solves_per_s"] for f in cmp["forms"].values())
-        cmp["best_solves_per_s"] = best
-        cmp["speedup_vs_plain_fp64"] = round(best / value, 3)
+        for f in cmp["forms"].values():
+            f["speedup_vs_plain_fp64"] = (round(f["solves_per_s"] / value, 3)
+                                          if f["status"] == "ok" else None)
+        # the metric's "batched + warm + mixed" side is the learned warm start
+        warm = cmp["forms"].get("cnn")
+        cmp["warm_form"] = "cnn" if warm is not None else None
+        cmp["speedup_vs_plain_fp64"] = warm["speedup_vs_plain_fp64"] if warm else None
+        ok = {k: f for k, f in cmp["forms"].items() if f["status"] == "ok"}
+        if ok:
+            best = max(ok, key=lambda k: ok[k]["solves_per_s"])
+            cmp["fastest_form"] = best
+            cmp["fastest_speedup_vs_plain_fp64"] = ok[best]["speedup_vs_plain_fp64"]
         out["batched_warm_mixed"] = cmp
+        del cmp
+        torch.cuda.empty_cache()
+    if not args.no_extra_configs and m == 1024:
+        out["mixed_precision_2048"] = leg_mixed_2048(args, dev)
+        torch.cuda.empty_cache()
+        out["monte_carlo_256"] = leg_monte_carlo(args, dev)
+        torch.cuda.empty_cache()
     # measured HBM ceiling: a 1 GiB device-to-device copy (read + write bytes / time);
     # not in counter runs, whose calibration copy is the only one
     if not args.copy_calib:

@@ -161,6 +161,17 @@ def predict(params, geoms, g_dev, v_in, ws=None):
     return vt, vb
 
 
+def describe_params(path=DEFAULT_PARAMS):
+    """What a stored network was trained on: the JSON file beside its weights
+    (same name, .json), written by `train`."""
+    meta = os.path.splitext(path)[0] + ".json"
+    try:
+        with open(meta) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {"weights": os.path.basename(path), "trained_on": "unknown"}
+
+
 def load_params(path=DEFAULT_PARAMS, device="cuda"):
     import torch
     flat = np.load(path, allow_pickle=False).astype(np.float32)
@@ -261,6 +272,13 @@ def main(argv=None):
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0 - t_gen
         np.save(a.out, params.cpu().numpy())
+        with open(os.path.splitext(a.out)[0] + ".json", "w") as f:
+            json.dump({"weights": os.path.basename(a.out),
+                       "trained_on": f"{a.count} solved {a.size} x {a.size} crossbars with the "
+                                     "Monte-Carlo distributions (synth.mc_device_batch, wire "
+                                     "conductance from synth.WIRE_LEVELS levels)",
+                       "size": a.size, "count": a.count, "epochs": a.epochs, "batch": a.batch,
+                       "lr": a.lr, "seed": a.seed}, f)
         del ds
         out = {"train": {"count": a.count, "size": a.size, "epochs": a.epochs, "batch": a.batch,
                          "lr": a.lr, "seed": a.seed, "generate_s": round(t_gen, 1),
