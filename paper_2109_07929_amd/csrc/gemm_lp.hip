@@ -23,6 +23,20 @@
 // 2 x 2 MFMA tiles each); K staged through LDS in double-buffered 64-deep
 // slices with two slices of global loads in flight.  One operand may have two
 // batches (the two layers) that share the other operand.
+//
+// LDS layout of a staged slice (register-staged path): 16-byte chunks, in
+// sub-slices of four chunks per row (32 bf16 or 16 floats of K).  Chunk c' of
+// row r in 16-row group g of sub-slice h sits at index
+//   h * 4 ROWS + g * 64 + c' * 16 + ((r mod 16) xor c'),
+// so one MFMA fragment (16 rows of one chunk column) is one 256-byte block,
+// its rows permuted by an xor of c'.  A slice is staged by lane quads that
+// each load one row's 64 contiguous bytes (coalesced global loads), the four
+// quads of a 16-lane group taking rows 4 apart.  Measured on gfx950
+// (rocprofv3 SQ_LDS_BANK_CONFLICT, 16-byte accesses): these fragment reads
+// and these stores run without bank conflicts, while rows padded to 80 bytes,
+// or 64-byte rows with a chunk swizzle, take twice the LDS cycles on the
+// fragment reads; lanes that each load a different row (one chunk column at a
+// time) avoid the conflicts but cost more in the global loads than they save.
 #include <hip/hip_bf16.h>
 
 #include "mca_internal.h"
@@ -45,22 +59,16 @@ constexpr int lp_threads()
 {
     return TS == 128 ? 64 * kWaves128 : (TS == 64 && KS == 64) ? 64 * kWaves64 : LTPB;
 }
-#ifndef MCA_LP_PAD
-#define MCA_LP_PAD 8
-#endif
-
 template <int MODE>
 struct Fmt {   // BF16 modes: two bf16 planes, 8 values per 16-byte chunk
     static constexpr int kPlanes = (MODE == MCA_PREC_BF16X3) ? 2 : 1;
     static constexpr int kPerChunk = 8;
-    static constexpr int kPad = MCA_LP_PAD;                // bf16 of LDS row padding
     using elem = __bf16;
 };
 template <>
 struct Fmt<MCA_PREC_FP32> {
     static constexpr int kPlanes = 1;
     static constexpr int kPerChunk = 4;
-    static constexpr int kPad = 4;
     using elem = float;
 };
 
@@ -69,11 +77,26 @@ struct Operand {
     const void *p[2];
 };
 
-// One operand slice in LDS: ROWS rows (tile edge) x KS values of K (+ padding).
+// One operand slice in LDS: ROWS rows (tile edge) x KS values of K, as
+// 16-byte chunks in the layout described above.
 template <int MODE, int ROWS, int KS>
 struct Tile {
-    typename Fmt<MODE>::elem v[Fmt<MODE>::kPlanes][ROWS][KS + Fmt<MODE>::kPad];
+    static constexpr int kChunks = ROWS * KS / Fmt<MODE>::kPerChunk;   // per plane
+    u4 c[Fmt<MODE>::kPlanes][kChunks];
 };
+
+// Chunk `id` of a staged slice: its row r and chunk column c (chunks of
+// Fmt::kPerChunk values along K) for the global load, and its LDS index.
+template <int ROWS>
+__device__ __forceinline__ void chunk_pos(int id, int &r, int &c, int &lds)
+{
+    const int h = id / (4 * ROWS), v = id % (4 * ROWS);
+    const int G = v >> 4, w = v & 15;
+    const int g = G >> 2, j = G & 3, q = w >> 2, i = w & 3;
+    r = g * 16 + q * 4 + j;
+    c = h * 4 + i;
+    lds = h * 4 * ROWS + g * 64 + i * 16 + ((q * 4 + j) ^ i);
+}
 
 // 16-byte chunks of one ROWS x KS operand slice per plane, per thread of NT.
 template <int MODE, int ROWS, int KS, int NT>
@@ -102,7 +125,7 @@ template <int MODE, int ROWS, int KS, int NT>
 __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int r0, int k0,
                                         bool fast, Regs<MODE, ROWS, KS, NT> &g)
 {
-    constexpr int PC = Fmt<MODE>::kPerChunk, CPR = KS / PC;
+    constexpr int PC = Fmt<MODE>::kPerChunk;
     constexpr int CPT = chunks_per_thread<MODE, ROWS, KS, NT>();
     using E = typename Fmt<MODE>::elem;
 #pragma unroll
@@ -110,8 +133,9 @@ __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int 
         const auto *base = global_ptr(static_cast<const E *>(op.p[pl]));
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int id = threadIdx.x + c * NT;
-            const int r = r0 + id / CPR, k = k0 + (id % CPR) * PC;
+            int rr, cc, li;
+            chunk_pos<ROWS>(threadIdx.x + c * NT, rr, cc, li);
+            const int r = r0 + rr, k = k0 + cc * PC;
             if (fast) {
                 g.c[pl][c] = *reinterpret_cast<const __attribute__((address_space(1))) u4 *>(
                     base + (size_t)r * K + k);
@@ -136,15 +160,31 @@ __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int 
 template <int MODE, int ROWS, int KS, int NT>
 __device__ __forceinline__ void stash_op(Tile<MODE, ROWS, KS> &t, const Regs<MODE, ROWS, KS, NT> &g)
 {
-    constexpr int PC = Fmt<MODE>::kPerChunk, CPR = KS / PC;
     constexpr int CPT = chunks_per_thread<MODE, ROWS, KS, NT>();
 #pragma unroll
-    for (int pl = 0; pl < Fmt<MODE>::kPlanes; ++pl)
+    for (int c = 0; c < CPT; ++c) {
+        int r, cc, li;
+        chunk_pos<ROWS>(threadIdx.x + c * NT, r, cc, li);
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int id = threadIdx.x + c * NT;
-            *reinterpret_cast<u4 *>(&t.v[pl][id / CPR][(id % CPR) * PC]) = g.c[pl][c];
-        }
+        for (int pl = 0; pl < Fmt<MODE>::kPlanes; ++pl) t.c[pl][li] = g.c[pl][c];
+    }
+}
+
+// MFMA fragments from a staged slice.  BF16 (16x16x32): lane l holds row
+// l % 16 of 16-row group g, k values 8 (l / 16) .. + 7 of k step s (sub-slice
+// s).  FP32 (16x16x4): lane l holds row l % 16, k value 4 s + l / 16.
+template <int MODE, int ROWS, int KS>
+__device__ __forceinline__ bf8 frag_bf16(const Tile<MODE, ROWS, KS> &t, int pl, int g, int s, int lane)
+{
+    const int cq = lane >> 4;
+    return *reinterpret_cast<const bf8 *>(&t.c[pl][s * 4 * ROWS + g * 64 + cq * 16 + ((lane & 15) ^ cq)]);
+}
+template <int MODE, int ROWS, int KS>
+__device__ __forceinline__ float frag_f32(const Tile<MODE, ROWS, KS> &t, int g, int s, int lane)
+{
+    const int cq = s & 3;
+    return reinterpret_cast<const float *>(
+        &t.c[0][(s >> 2) * 4 * ROWS + g * 64 + cq * 16 + ((lane & 15) ^ cq)])[lane >> 4];
 }
 
 // O = A B^T.  NB batches of A (A_BATCHED) or of B, sharing the other operand.
@@ -179,15 +219,20 @@ __device__ __forceinline__ void put(const LpArgs &a, int b, size_t o, T v, int o
 constexpr int DEPTH = 2;   // K slices in flight (deeper rings measured no faster)
 
 // One TS x TS output tile at (m0, n0) of O = A B^T: four waves of (TS/2)^2 or
-// eight of (TS/2) x (TS/4), FI x FJ MFMA tiles of 16 x 16 each; K staged in
-// slices of KS.
+// eight waves, FI x FJ MFMA tiles of 16 x 16 each; K staged in slices of KS.
+// With eight waves a wave covers half the tile along the operand that has one
+// batch and a quarter along the one with two (the layers), which keeps the
+// fragment reads per MFMA lowest: 16 reads for 48 split-BF16 MFMAs per k step.
 template <int MODE, int NB, bool A_BATCHED, int OUT, int EPI, int TS, int KS>
 __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 {
     constexpr int NA = A_BATCHED ? NB : 1, NBB = A_BATCHED ? 1 : NB;
     constexpr int NT = lp_threads<TS, KS>(), WAVES = NT / 64;
-    constexpr int WTM = TS / 2, WTN = (WAVES == 8) ? TS / 4 : TS / 2;
+    constexpr bool TWO_A = A_BATCHED && NB == 2;
+    constexpr int WTM = (WAVES == 8) ? (TWO_A ? TS / 4 : TS / 2) : TS / 2;
+    constexpr int WTN = (WAVES == 8) ? (TWO_A ? TS / 2 : TS / 4) : TS / 2;
     constexpr int FI = WTM / 16, FJ = WTN / 16;
+    constexpr int PL = Fmt<MODE>::kPlanes;
     using TileT = Tile<MODE, TS, KS>;
     using RegsT = Regs<MODE, TS, KS, NT>;
     __shared__ TileT As[2][NA];
@@ -196,6 +241,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave / (TS / WTN)) * WTM, wn = (wave % (TS / WTN)) * WTN;
+    const int gm = wm / 16, gn = wn / 16;   // first 16-row group of the wave's A / B rows
     const bool fast_m = a.vec && (m0 + TS <= M);
     const bool fast_n = a.vec && (n0 + TS <= N);
 
@@ -233,60 +279,80 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 #pragma unroll
             for (int j = 0; j < FJ; ++j) acc[b][i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
+    // the MFMAs of one k step of split-BF16 / BF16 fragments: lo.hi and hi.lo
+    // first, then hi.hi, each over every accumulator (no two MFMAs in a row
+    // share an accumulator)
+    auto mfma_bf16 = [&](const bf8 (&fa)[NA][PL][FI], const bf8 (&fb)[NBB][PL][FJ]) {
+        if constexpr (MODE == MCA_PREC_BF16X3) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int i = 0; i < FI; ++i)
+#pragma unroll
+                    for (int j = 0; j < FJ; ++j)
+                        acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            fa[A_BATCHED ? b : 0][1][i], fb[A_BATCHED ? 0 : b][0][j], acc[b][i][j], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int i = 0; i < FI; ++i)
+#pragma unroll
+                    for (int j = 0; j < FJ; ++j)
+                        acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            fa[A_BATCHED ? b : 0][0][i], fb[A_BATCHED ? 0 : b][PL - 1][j], acc[b][i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int i = 0; i < FI; ++i)
+#pragma unroll
+                for (int j = 0; j < FJ; ++j)
+                    acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        fa[A_BATCHED ? b : 0][0][i], fb[A_BATCHED ? 0 : b][0][j], acc[b][i][j], 0, 0, 0);
+    };
+    auto read_bf16 = [&](int buf, int s, bf8 (&fa)[NA][PL][FI], bf8 (&fb)[NBB][PL][FJ]) {
+#pragma unroll
+        for (int b = 0; b < NA; ++b)
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl)
+#pragma unroll
+                for (int i = 0; i < FI; ++i) fa[b][pl][i] = frag_bf16(As[buf][b], pl, gm + i, s, lane);
+#pragma unroll
+        for (int b = 0; b < NBB; ++b)
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl)
+#pragma unroll
+                for (int j = 0; j < FJ; ++j) fb[b][pl][j] = frag_bf16(Bs[buf][b], pl, gn + j, s, lane);
+    };
+
     auto compute = [&](int buf) {
+        if constexpr (MODE == MCA_PREC_FP32) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const TileT &TA_ = As[buf][A_BATCHED ? b : 0];
-            const TileT &TB_ = Bs[buf][A_BATCHED ? 0 : b];
-            if constexpr (MODE == MCA_PREC_FP32) {
-                // A fragment: row l%16, k l/16; B fragment: k l/16, column l%16
+            for (int s4 = 0; s4 < KS / 4; ++s4) {
+                float fa[NA][FI], fb[NBB][FJ];
 #pragma unroll
-                for (int k4 = 0; k4 < KS / 4; ++k4) {
-                    const int kk = k4 * 4 + (lane >> 4);
-                    float fa[FI], fb[FJ];
+                for (int b = 0; b < NA; ++b)
 #pragma unroll
-                    for (int i = 0; i < FI; ++i) fa[i] = TA_.v[0][wm + i * 16 + (lane & 15)][kk];
+                    for (int i = 0; i < FI; ++i) fa[b][i] = frag_f32(As[buf][b], gm + i, s4, lane);
 #pragma unroll
-                    for (int j = 0; j < FJ; ++j) fb[j] = TB_.v[0][wn + j * 16 + (lane & 15)][kk];
+                for (int b = 0; b < NBB; ++b)
+#pragma unroll
+                    for (int j = 0; j < FJ; ++j) fb[b][j] = frag_f32(Bs[buf][b], gn + j, s4, lane);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
 #pragma unroll
                     for (int i = 0; i < FI; ++i)
 #pragma unroll
                         for (int j = 0; j < FJ; ++j)
-                            acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j],
-                                                                                acc[b][i][j], 0, 0, 0);
-                }
-            } else {
-                // A fragment: row l%16, k 8(l/16)..+7; B fragment: column l%16, same k
+                            acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                fa[A_BATCHED ? b : 0][i], fb[A_BATCHED ? 0 : b][j], acc[b][i][j], 0, 0, 0);
+            }
+        } else {
 #pragma unroll
-                for (int k32 = 0; k32 < KS / 32; ++k32) {
-                    const int kk = k32 * 32 + (lane >> 4) * 8;
-                    bf8 ah[FI], al[FI], bh[FJ], bl[FJ];
-#pragma unroll
-                    for (int i = 0; i < FI; ++i) {
-                        ah[i] = *reinterpret_cast<const bf8 *>(&TA_.v[0][wm + i * 16 + (lane & 15)][kk]);
-                        if constexpr (MODE == MCA_PREC_BF16X3)
-                            al[i] = *reinterpret_cast<const bf8 *>(&TA_.v[1][wm + i * 16 + (lane & 15)][kk]);
-                    }
-#pragma unroll
-                    for (int j = 0; j < FJ; ++j) {
-                        bh[j] = *reinterpret_cast<const bf8 *>(&TB_.v[0][wn + j * 16 + (lane & 15)][kk]);
-                        if constexpr (MODE == MCA_PREC_BF16X3)
-                            bl[j] = *reinterpret_cast<const bf8 *>(&TB_.v[1][wn + j * 16 + (lane & 15)][kk]);
-                    }
-#pragma unroll
-                    for (int i = 0; i < FI; ++i)
-#pragma unroll
-                        for (int j = 0; j < FJ; ++j) {
-                            if constexpr (MODE == MCA_PREC_BF16X3) {
-                                acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                    al[i], bh[j], acc[b][i][j], 0, 0, 0);
-                                acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                    ah[i], bl[j], acc[b][i][j], 0, 0, 0);
-                            }
-                            acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                ah[i], bh[j], acc[b][i][j], 0, 0, 0);
-                        }
-                }
+            for (int s = 0; s < KS / 32; ++s) {
+                bf8 fa[NA][PL][FI], fb[NBB][PL][FJ];
+                read_bf16(buf, s, fa, fb);
+                mfma_bf16(fa, fb);
             }
         }
     };
@@ -299,13 +365,12 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
         if (fast_m && fast_n && K % KS == 0 && gridDim.x <= 256) {
             // Interior tile: every slice goes from global memory straight into
             // LDS (global_load_lds_dwordx4, 16 bytes per lane), two buffers.
-            // The slice layout drops the row padding: plane p, row r, 16-byte
-            // chunk c of the row's 32 values sits at byte p 8192 + 64 r +
-            // 16 (c ^ ((r >> 2) & 3)), so the 16 rows one fragment read
-            // touches per chunk fall on distinct banks.  Each step reads its
-            // fragments, then issues the next slice into the other buffer,
-            // then runs its MFMAs.
-            constexpr int PL = Fmt<MODE>::kPlanes;
+            // This path keeps a layout of its own: plane p, row r, 16-byte
+            // chunk c of the row's 32 values at byte p 8192 + 64 r +
+            // 16 (c ^ ((r >> 2) & 3)), so that each lane quad loads one row's
+            // 64 contiguous bytes (the load writes LDS in lane order).  Each
+            // step reads its fragments, then issues the next slice into the
+            // other buffer, then runs its MFMAs.
             constexpr int NI = (NA + NBB) * PL * 8;   // 1 KB instructions per slice
             constexpr int NQ = NI / 8;                 // per wave
             static_assert(NI % 8 == 0, "instructions per wave");
@@ -371,23 +436,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
                         for (int j = 0; j < FJ; ++j)
                             fb[b][pl][j] = frag(buf, NA + b, pl, wn + j * 16 + (lane & 15));
                 if (k + 1 < nk) issue(buf ^ 1, (k + 1) * KS);
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const int ba = A_BATCHED ? b : 0, bb = A_BATCHED ? 0 : b;
-#pragma unroll
-                    for (int i = 0; i < FI; ++i)
-#pragma unroll
-                        for (int j = 0; j < FJ; ++j) {
-                            if constexpr (MODE == MCA_PREC_BF16X3) {
-                                acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                    fa[ba][1][i], fb[bb][0][j], acc[b][i][j], 0, 0, 0);
-                                acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                    fa[ba][0][i], fb[bb][PL - 1][j], acc[b][i][j], 0, 0, 0);
-                            }
-                            acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                fa[ba][0][i], fb[bb][0][j], acc[b][i][j], 0, 0, 0);
-                        }
-                }
+                mfma_bf16(fa, fb);
             }
             done = true;
         }
