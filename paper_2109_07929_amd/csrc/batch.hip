@@ -79,6 +79,20 @@ __device__ __forceinline__ bool block_range(const BInst *__restrict__ I, const i
     return on(flag, b);
 }
 
+// The same for a launch whose blocks run from the table's end back to its
+// start (logical block = last one first); returns the logical block.
+__device__ __forceinline__ int block_range_rev(const BInst *__restrict__ I, const int2 *__restrict__ bt,
+                                               int &b, int &k0, int &k1)
+{
+    const int L = gridDim.x - 1 - blockIdx.x;
+    const int2 e = bt[L];
+    b = e.x;
+    const int mn = I[b].m * I[b].n;
+    k0 = e.y * CH;
+    k1 = min(k0 + CH, mn);
+    return L;
+}
+
 // Sum of crossbar b's per-block partials (component c of nc), fixed order.
 __device__ __forceinline__ double inst_sum(const BInst &I, const double *__restrict__ p, int nc, int c)
 {
@@ -341,11 +355,14 @@ __global__ __launch_bounds__(TPB) void bk_gs_coef(BGs a)
     }
 }
 
+// The blocks run in reverse table order: the projection pass just before read
+// the vectors front to back, so the parts it read last are the likeliest still
+// in the memory-side cache.
 template <int MAXV>
 __global__ __launch_bounds__(TPB) void bk_gs_update(BGs a)
 {
     int b, k0, k1;
-    if (!block_range(a.I, a.bt, nullptr, b, k0, k1)) return;
+    const int L = block_range_rev(a.I, a.bt, b, k0, k1);
     if (a.ctl[4 * b]) return;
     const BInst in = a.I[b];
     const int j = a.j, nv = j + 1, R1 = a.R + 1;
@@ -386,7 +403,7 @@ __global__ __launch_bounds__(TPB) void bk_gs_update(BGs a)
         }
     }
     block_sum<MAXV + 1>(acc);
-    const int t = blockIdx.x - in.blk0;
+    const int t = L - in.blk0;
     double *p = a.p2 + (size_t)in.blk0 * (kGsMaxV + 1);
     if (threadIdx.x == 0) {
 #pragma unroll

@@ -16,7 +16,7 @@
 // "same" padding.  Loss: mean (y - y_target)^2.
 //
 // Every activation is an NHWC bfloat16 tensor with 32 channels (64 bytes per
-// crosspoint; the 3 input channels and the 2 output gradients are zero-padded
+// crosspoint; the 4 input channels and the 2 output gradients are zero-padded
 // to 32), so one MFMA convolution kernel serves every layer:
 //   out^T[co][p] = sum_tap sum_ci W[tap][co][ci] in[p + off(tap)][ci]
 // as v_mfma_f32_16x16x32_bf16 with A = weights (rows = output channels, K =

@@ -540,12 +540,18 @@ __global__ __launch_bounds__(NT) void k_gs_update(GsStep a)
     for (int q = 0; q < MAXV; ++q) c[q] = (q < nv) ? hsh[q] * a.sig[q] : 0.0;
 #pragma unroll
     for (int q = 0; q <= MAXV; ++q) acc[q] = 0.0;
-    // pairs of elements (the vector length 2mn and the slot stride are even)
+    // pairs of elements (the vector length 2mn and the slot stride are even).
+    // The grid walks the vectors from their end back to their start: the first
+    // pass of this Arnoldi step read them front to back just before, so the
+    // parts it read last are the likeliest still in the memory-side cache.
     double2 *w2 = reinterpret_cast<double2 *>(a.w);
     const double2 *V2 = reinterpret_cast<const double2 *>(a.V);
     const size_t len2 = (size_t)a.m * a.n, ldv2 = a.ldv / 2;
+    const size_t first = (size_t)blockIdx.x * NT + threadIdx.x, stride = (size_t)gridDim.x * NT;
+    const size_t steps = first < len2 ? (len2 - 1 - first) / stride + 1 : 0;
 #pragma unroll 1
-    for (size_t k = (size_t)blockIdx.x * NT + threadIdx.x; k < len2; k += (size_t)gridDim.x * NT) {
+    for (size_t t = steps; t-- > 0;) {
+        const size_t k = first + t * stride;
         double2 vq[MAXV];
         double2 x = w2[k];
 #pragma unroll

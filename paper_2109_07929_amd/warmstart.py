@@ -181,23 +181,27 @@ def load_params(path=DEFAULT_PARAMS, device="cuda"):
     return torch.from_numpy(flat).to(device)
 
 
-def evaluate(params, count, size, seed, device="cuda", precision=B.MCA_PREC_BF16X3):
+def evaluate(params, count, size, seed, device="cuda", precision=B.MCA_PREC_BF16X3,
+             newton_tol=1e-10, keep=0):
     """Solve held-out crossbars from V = 0 and from the network's guess (with
-    fallback); returns per-crossbar Newton / GMRES counts, guess residuals and
-    the wall time of both, prediction included."""
+    fallback) to the same Newton tolerance; returns per-crossbar Newton / GMRES
+    counts, guess residuals and the wall time of both, prediction included.
+    keep > 0 also returns the first `keep` crossbars (wire level after wire
+    level) as host arrays (res["kept"]: geometry, g_dev, v_in, warm-started
+    v_t, v_b)."""
     import torch
     m = n = size
     per_level = -(-count // synth.WIRE_LEVELS)
     batches = level_batches(per_level, m, n, device)
-    cold = B.options(precond=B.MCA_PRECOND_PERMODE, precision=precision)
-    warm = B.options(precond=B.MCA_PRECOND_PERMODE, precision=precision,
+    cold = B.options(precond=B.MCA_PRECOND_PERMODE, precision=precision, newton_tol=newton_tol)
+    warm = B.options(precond=B.MCA_PRECOND_PERMODE, precision=precision, newton_tol=newton_tol,
                      flags=B.MCA_FLAG_INITIAL_GUESS | B.MCA_FLAG_GUESS_FALLBACK)
     ws = torch.empty(B.mca_batch_workspace_bytes(batches[0].handle, cold), dtype=torch.uint8,
                      device=device)
     cws = torch.empty(B.mca_cnn_workspace_bytes(per_level, m, n), dtype=torch.uint8, device=device)
     res = {"newton_cold": [], "newton_warm": [], "krylov_cold": [], "krylov_warm": [],
            "guess_residual": [], "guess_used": [], "max_dv": [], "relres_warm": [],
-           "t_cold": 0.0, "t_warm": 0.0, "t_predict": 0.0}
+           "t_cold": 0.0, "t_warm": 0.0, "t_predict": 0.0, "kept": []}
     for lv, bt in enumerate(batches):
         g, v = synth.mc_device_batch(per_level, m, n, seed * 1000 + lv, device=device)
         geoms = [synth.level_geometry(m, n, lv)] * per_level
@@ -220,6 +224,9 @@ def evaluate(params, count, size, seed, device="cuda", precision=B.MCA_PREC_BF16
             res["guess_residual"].append(b.residual_history[0] if b.start else float("nan"))
             res["guess_used"].append(b.start)
             res["relres_warm"].append(b.rel_residual)
+        for b in range(min(keep - len(res["kept"]), per_level)):
+            res["kept"].append((geoms[b], g[b].cpu().numpy(), v[b].cpu().numpy(),
+                                vt1[b].cpu().numpy(), vb1[b].cpu().numpy()))
         scale = torch.maximum(vt0.abs().amax(dim=(1, 2)), vb0.abs().amax(dim=(1, 2)))
         dv = torch.maximum((vt1 - vt0).abs().amax(dim=(1, 2)), (vb1 - vb0).abs().amax(dim=(1, 2)))
         res["max_dv"] += (dv / scale).tolist()

@@ -60,16 +60,38 @@ def test_guess_fallback_batched():
 
 @pytest.mark.skipif(not os.path.exists(warmstart.DEFAULT_PARAMS), reason="no trained network")
 def test_trained_network_gains_on_held_out_crossbars():
+    """At the workload's Newton tolerance (||F|| <= 1e-10 ||Y||, both starts)
+    the network's guesses save Newton steps and GMRES iterations."""
     params = warmstart.load_params()
     res = warmstart.evaluate(params, count=64, size=512, seed=424242)
     s = warmstart.summary(res)
     say(f"  {s}")
-    # both solves stop at ||F|| <= 1e-10 ||Y||: the same residual tolerance
     assert s["max_relres_warm"] <= 1e-10
-    assert s["max_rel_dv_warm_vs_cold"] <= 1e-6
     assert s["guess_used_fraction"] >= 0.9
     assert s["newton_warm"] < s["newton_cold"]
     assert s["krylov_warm"] < s["krylov_cold"]
+
+
+@pytest.mark.skipif(not os.path.exists(warmstart.DEFAULT_PARAMS), reason="no trained network")
+def test_warm_started_voltages_match_cold_and_oracle():
+    """A warm start changes only the path: run to ||F|| <= 1e-12 ||Y|| (a
+    1e-10 stop certifies far less than the voltage bar: the certified bound
+    ||F|| / lambda_min is then about 1e-4 of max |V| at 512^2), warm and cold
+    voltages agree to 1e-8 and four warm-started crossbars match the oracle's
+    steady state to 1e-8."""
+    params = warmstart.load_params()
+    res = warmstart.evaluate(params, count=64, size=512, seed=424243, newton_tol=1e-12, keep=4)
+    s = warmstart.summary(res)
+    say(f"  {s}")
+    assert s["max_relres_warm"] <= 1e-12
+    assert s["max_rel_dv_warm_vs_cold"] <= 1e-8
+    assert len(res["kept"]) == 4
+    for geom, g, v, vt, vb in res["kept"]:
+        rt, rb, _, _ = oracle.solve(geom, g, v, method="cg")
+        scale = max(np.abs(rt).max(), np.abs(rb).max())
+        err = max(np.abs(vt - rt).max(), np.abs(vb - rb).max()) / scale
+        say(f"  warm-started {geom.m}x{geom.n} vs oracle: {err:.1e}")
+        assert err <= 1e-8
 
 
 # A Newton tolerance no start can miss: the solve returns its starting point.
