@@ -628,14 +628,19 @@ __global__ void bk_newton_begin(const BInst *__restrict__ I, int count, BState *
 // sum of per-block counters (one thread)
 // out[0] = sum of c[0..n); with host_out (the device address of pinned host
 // memory) also written through to the host.
+// Sum of the per-block counters into out[0] and, with host_out, into a pinned
+// host flag slot as (1 << 32) | sum in one release store at system scope (the
+// host cleared the slot before enqueueing this kernel and spins on it).
 __global__ void bk_sum_counters(const int *__restrict__ c, int n, int *__restrict__ out,
-                                int *__restrict__ host_out)
+                                long long *__restrict__ host_out)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int s = 0;
     for (int i = 0; i < n; ++i) s += c[i];
     out[0] = s;
-    if (host_out) __hip_atomic_store(host_out, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (host_out)
+        __hip_atomic_store(host_out, (long long)((1ULL << 32) | (unsigned)s), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // GMRES cycle start for crossbars in their Newton step's GMRES solve
@@ -1384,7 +1389,9 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     const int cb = cblocks(cnt), ct = std::min(cnt, 1024);
     const int *actf = &w.S[0].active, *lsf = &w.S[0].ls_todo, *rsf = &w.S[0].restart;
     const int *accf = &w.S[0].accept;
-    if (!B->host) MCA_BTRY(hipHostMalloc((void **)&B->host, 4096 * sizeof(int), hipHostMallocDefault));
+    if (!B->host)
+        MCA_BTRY(hipHostMalloc((void **)&B->host, 4096 * sizeof(int),
+                               hipHostMallocMapped | hipHostMallocCoherent));
     int *host = B->host, *host_dev = nullptr;
     MCA_BTRY(hipHostGetDevicePointer((void **)&host_dev, host, 0));
     const bool graph = (o.flags & MCA_FLAG_GRAPH) != 0;
@@ -1403,26 +1410,19 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         G.two_pass = (int)two_pass;
         G.exec.resize(R, nullptr);
     }
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    struct EvFree {
-        hipEvent_t *e;
-        ~EvFree()
-        {
-            for (int i = 0; i < 2; ++i)
-                if (e[i]) (void)hipEventDestroy(e[i]);
-        }
-    } ef{ev};
-    for (auto &e : ev) MCA_BTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // pinned flag slots (64-bit, from int 16 of the host block): slot j for
+    // Arnoldi step j, slot kCountSlot for count_now
+    long long *flag = reinterpret_cast<long long *>(host + 16);
+    long long *flag_dev = reinterpret_cast<long long *>(host_dev + 16);
+    constexpr int kCountSlot = 127;
 
     // read the sum of the per-block counters written by the last control kernel
     auto count_now = [&](int *out) -> mca_status {
+        __atomic_store_n(&flag[kCountSlot], 0LL, __ATOMIC_RELAXED);
         hipLaunchKernelGGL(bk_sum_counters, dim3(1), dim3(64), 0, s, w.counter, cb, w.counter + cb,
-                           (int *)nullptr);
+                           flag_dev + kCountSlot);
         MCA_BTRY(hipGetLastError());
-        MCA_BTRY(hipMemcpyAsync(host, w.counter + cb, sizeof(int), hipMemcpyDeviceToHost, s));
-        MCA_BTRY(hipStreamSynchronize(s));
-        *out = host[0];
-        return MCA_OK;
+        return wait_flag64(&flag[kCountSlot], s, out);
     };
 
     GroupedChain gc{};
@@ -1467,7 +1467,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     // Arnoldi step j of every crossbar still in its cycle: preconditioner,
     // Jacobian product fused with <w, v_0>, the projection passes, the
     // normalisation, the Givens update, and the count of running cycles
-    // written to host[16 + j]
+    // written to flag slot j
     auto enqueue_step = [&](int j, hipStream_t q) -> hipError_t {
         double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
         double *wv = w.V + (size_t)(j + 1) * len;
@@ -1494,7 +1494,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
             else hipLaunchKernelGGL(bk_gs_update<32>, gridB, blk, 0, q, a);
             hipLaunchKernelGGL(bk_gs_finish, dim3(cnt), blk, 0, q, a);
             hipLaunchKernelGGL(bk_sum_counters, dim3(1), dim3(64), 0, q, w.run, cnt,
-                               w.counter + cb + 1, host_dev + 16 + j);
+                               w.counter + cb + 1, flag_dev + j);
         } else {
             hipLaunchKernelGGL(bk_jacobian, gridB, blk, 0, q, B->d_inst, B->d_btab, w.ctl, w.D, zj,
                                wv, w.V, w.pa);
@@ -1510,7 +1510,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
             hipLaunchKernelGGL(bk_givens, dim3(cb), dim3(ct), 0, q, cnt, w.S, w.H, ldh, hsize, j,
                                w.g, w.cs, w.sn, R, w.ctl, w.counter);
             hipLaunchKernelGGL(bk_sum_counters, dim3(1), dim3(64), 0, q, w.counter, cb,
-                               w.counter + cb + 1, host_dev + 16 + j);
+                               w.counter + cb + 1, flag_dev + j);
         }
         return hipGetLastError();
     };
@@ -1562,8 +1562,10 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         for (;;) {
             hipLaunchKernelGGL(bk_cycle_init, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.ctl, w.g, R,
                                o.max_krylov, two_pass ? w.sig : nullptr);
-            int last = -1;
             for (int j = 0; j < R; ++j) {
+                // (every kernel that wrote slot j before has completed: the last
+                // wait of the previous cycle came after it in stream order)
+                __atomic_store_n(&flag[j], 0LL, __ATOMIC_RELAXED);
                 if (graph) {
                     hipGraphExec_t &ex = G.exec[j];
                     if (!ex) {
@@ -1587,14 +1589,14 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
                 } else {
                     MCA_BTRY(enqueue_step(j, s));
                 }
-                MCA_BTRY(hipEventRecord(ev[j & 1], s));
-                last = j;
                 if (j > 0) {
-                    MCA_BTRY(hipEventSynchronize(ev[(j - 1) & 1]));
-                    if (host[16 + j - 1] == 0) break;   // every crossbar's cycle has stopped
+                    // step j runs while the host reads step j-1's count of crossbars
+                    // still in their cycle
+                    int running = 0;
+                    if ((st = wait_flag64(&flag[j - 1], s, &running)) != MCA_OK) return st;
+                    if (running == 0) break;   // every crossbar's cycle has stopped
                 }
             }
-            if (last >= 0) MCA_BTRY(hipEventSynchronize(ev[last & 1]));
             hipLaunchKernelGGL(bk_cycle_end, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.H, ldh, hsize, w.g,
                                R, w.ctl, w.Y, o.max_krylov, w.counter,
                                two_pass ? (const double *)w.sig : nullptr);

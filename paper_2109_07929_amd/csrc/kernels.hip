@@ -69,7 +69,7 @@ __global__ __launch_bounds__(TPB) void k_residual(
 }
 
 __global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ p, int nb, int nc,
-                                                double *__restrict__ out)
+                                                double *__restrict__ out, int *mark, int epoch)
 {
     // one block; component c summed in a fixed order
     for (int c = 0; c < nc; ++c) {
@@ -78,6 +78,9 @@ __global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ p, in
         block_sum<1>(v);
         if (threadIdx.x == 0) out[c] = v[0];
     }
+    // the sums are out (thread 0 stored them): publish them to a waiting host
+    if (mark && threadIdx.x == 0)
+        __hip_atomic_store(mark, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ---------------------------------------------------------------- Jacobian
@@ -306,11 +309,13 @@ __device__ __forceinline__ void sum_partials_1024(const double *__restrict__ p, 
 }
 
 // Copy of the cycle control block (stop flag, steps done, reason) to the
-// host's pinned snapshot slot (16-byte aligned); the host reads it after the
-// kernel has completed.
-__device__ __forceinline__ void write_snapshot(int *snap, const int *ctl)
+// host's pinned snapshot slot (16-byte aligned), then the slot's marker
+// (snap[4]) set to `epoch` with a release store at system scope: a host that
+// reads the marker with acquire order sees the control block.
+__device__ __forceinline__ void write_snapshot(int *snap, const int *ctl, int epoch)
 {
     *reinterpret_cast<int4 *>(snap) = int4{ctl[0], ctl[1], ctl[2], ctl[3]};
+    __hip_atomic_store(snap + 4, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Givens update of Hessenberg column j: apply rotations 0..j-1, then the
@@ -633,7 +638,7 @@ __device__ __forceinline__ void gs_finish_block(const GsStep &a)
     }
     if (t == 0) gj = a.g[j];
     if (stop) {   // a stopped cycle: the snapshot only
-        if (t == 0) write_snapshot(a.snap, a.ctl);
+        if (t == 0) write_snapshot(a.snap, a.ctl, a.epoch);
         return;
     }
     // fixed-order sums of the partials: waves, then the 16 wave sums
@@ -696,7 +701,7 @@ __device__ __forceinline__ void gs_finish_block(const GsStep &a)
             }
         }
     }
-    write_snapshot(a.snap, ctl);
+    write_snapshot(a.snap, ctl, a.epoch);
 }
 
 __global__ __launch_bounds__(1024) void k_gs_finish(GsStep a) { gs_finish_block(a); }
@@ -761,15 +766,16 @@ __global__ void k_cycle_init(int *__restrict__ ctl, double *__restrict__ g, int 
 // One Givens update of Hessenberg column j (givens_block), then the snapshot.
 __global__ void k_givens(double *__restrict__ H, int ldh, int j, double *__restrict__ g,
                          double *__restrict__ cs, double *__restrict__ sn, double abs_tol,
-                         int *__restrict__ ctl, double *__restrict__ resid, int *__restrict__ snap)
+                         int *__restrict__ ctl, double *__restrict__ resid, int *__restrict__ snap,
+                         int epoch)
 {
     if (ctl[0]) {
-        if (threadIdx.x == 0) write_snapshot(snap, ctl);
+        if (threadIdx.x == 0) write_snapshot(snap, ctl, epoch);
         return;
     }
     const double hlast = H[(size_t)j * ldh + j + 1];
     givens_block(H, ldh, j, hlast, g, cs, sn, abs_tol, ctl, resid);
-    if (threadIdx.x == 0) write_snapshot(snap, ctl);
+    if (threadIdx.x == 0) write_snapshot(snap, ctl, epoch);
 }
 
 // y = R^{-1} g over the ctl[1] completed columns (upper triangular R in H).
@@ -867,9 +873,10 @@ hipError_t launch_residual(const mca_plan *P, const double *g_dev, const double 
 }
 
 hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double *out,
-                         hipStream_t s)
+                         hipStream_t s, int *mark, int epoch)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, partials, nblocks, ncomp, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, partials, nblocks, ncomp, out, mark,
+                       epoch);
     return hipGetLastError();
 }
 
@@ -1014,10 +1021,11 @@ hipError_t launch_cycle_init(int *ctl, double *g, int R, double beta, hipStream_
 }
 
 hipError_t launch_givens(double *H, int ldh, int j, double *g, double *cs, double *sn,
-                         double abs_tol, int *ctl, double *resid, int *snap, hipStream_t s)
+                         double abs_tol, int *ctl, double *resid, int *snap, int epoch,
+                         hipStream_t s)
 {
     hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, H, ldh, j, g, cs, sn, abs_tol, ctl,
-                       resid, snap);
+                       resid, snap, epoch);
     return hipGetLastError();
 }
 

@@ -69,9 +69,16 @@ int reduce_blocks(size_t len);
 hipError_t launch_residual(const mca_plan *P, const double *g_dev, const double *v_in,
                            const double *vt, const double *vb, double *ft, double *fb,
                            double *d, double *partials, hipStream_t s);
-// final sums of partials: out[c] = sum_b partials[b*ncomp + c], c < ncomp
+// Host wait for a 64-bit flag slot in pinned host memory that a kernel sets to
+// (1 << 32) | value with a release store at system scope (the host clears the
+// slot to 0 before enqueueing that kernel); *value receives the low word.
+mca_status wait_flag64(const long long *slot, hipStream_t s, int *value);
+
+// final sums of partials: out[c] = sum_b partials[b*ncomp + c], c < ncomp;
+// with mark set, *mark = epoch afterwards (release store at system scope: a
+// host polling a pinned marker then sees out)
 hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double *out,
-                         hipStream_t s);
+                         hipStream_t s, int *mark = nullptr, int epoch = 0);
 
 // y = J x (eq. (J)); with v0 also per-block partials of <y, v0> (grid of
 // reduce_blocks(2mn) blocks).  Kernels given a skip flag return at once when
@@ -260,6 +267,8 @@ struct GsStep {
     double abs_tol;
     int *ctl;                     // cycle control block (stop flag first)
     int *snap;                    // device address of the host's snapshot slot of step j
+                                  // (5 ints: the control block, then the marker)
+    int epoch;                    // marker value written after the snapshot
     // with xp[0][0] set, the update pass also writes the new vector in the
     // reduced-precision preconditioner's operand format (per layer: FP32, or
     // bfloat16 hi [+ lo]), the conversion the next step's chain would make
@@ -289,8 +298,10 @@ enum CycleReason { CYCLE_RUNNING = 0, CYCLE_CONVERGED = 1, CYCLE_BREAKDOWN = 2,
 hipError_t launch_cycle_init(int *ctl, double *g, int R, double beta, hipStream_t s,
                              double *sig = nullptr);
 // ... then ctl[0..3] written to snap (pinned host memory, device address)
+// and snap[4] = epoch
 hipError_t launch_givens(double *H, int ldh, int j, double *g, double *cs, double *sn,
-                         double abs_tol, int *ctl, double *resid, int *snap, hipStream_t s);
+                         double abs_tol, int *ctl, double *resid, int *snap, int epoch,
+                         hipStream_t s);
 hipError_t launch_backsolve(const double *H, int ldh, const double *g, const int *ctl,
                             double *y, hipStream_t s, const double *sig = nullptr);
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -272,7 +273,8 @@ double *pinned_scratch()
     thread_local PinnedScratch ps;
     if (!ps.buf) {
         void *p = nullptr;
-        if (hipHostMalloc(&p, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc(&p, 4096 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess)
             return nullptr;
         ps.buf = static_cast<double *>(p);
     }
@@ -289,6 +291,50 @@ double *pinned_scratch()
     } while (0)
 
 bool plan_ready(const mca_plan *P) { return P && P->dev_buf != nullptr; }
+
+// Markers in pinned host memory: a kernel publishes data for the host (a
+// snapshot, a reduced norm) and then stores a fresh marker value with release
+// order at system scope; the host spins on the marker with acquire order.
+// Unlike an event recorded between two kernels, this leaves no gap between
+// them on the GPU.  Values come from a per-thread counter, so a marker left
+// by an earlier wait never matches.
+int next_epoch()
+{
+    thread_local unsigned counter = 0;
+    ++counter;
+    if ((int)counter == 0) ++counter;
+    return (int)counter;
+}
+
+mca_status wait_marker(const int *mark, int epoch, hipStream_t s)
+{
+    // Only the marker is read for the first 20 ms: a stream query enqueues
+    // work of its own, which delays the next kernel of the stream by a few
+    // microseconds.  After that, every millisecond, the stream is asked
+    // whether it still has work.
+    using clock = std::chrono::steady_clock;
+    const auto t0 = clock::now();
+    auto next_check = t0 + std::chrono::milliseconds(20);
+    for (unsigned spin = 1;; ++spin) {
+        if (__atomic_load_n(mark, __ATOMIC_ACQUIRE) == epoch) return MCA_OK;
+        __builtin_ia32_pause();
+        if ((spin & 1023) == 0 && clock::now() >= next_check) {
+            next_check = clock::now() + std::chrono::milliseconds(1);
+            // a stream with no work left and no marker: the publishing kernel failed
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) {
+                if (__atomic_load_n(mark, __ATOMIC_ACQUIRE) == epoch) return MCA_OK;
+                set_hip_error("marker wait: the stream drained without the marker",
+                              hipErrorLaunchFailure);
+                return MCA_ERR_HIP;
+            }
+            if (q != hipErrorNotReady) {
+                set_hip_error("hipStreamQuery", q);
+                return MCA_ERR_HIP;
+            }
+        }
+    }
+}
 
 // GPU time per kernel class, from HIP events recorded around each group of
 // launches.  Two slots alternate between consecutive Arnoldi steps (the host
@@ -350,6 +396,10 @@ struct Timing {
             if (count) {
                 float t = 0.f;
                 hipError_t r = hipEventElapsedTime(&t, ev[slot][c][0], ev[slot][c][1]);
+                if (r == hipErrorNotReady) {   // (seen through a marker, not yet by the runtime)
+                    r = hipEventSynchronize(ev[slot][c][1]);
+                    if (r == hipSuccess) r = hipEventElapsedTime(&t, ev[slot][c][0], ev[slot][c][1]);
+                }
                 if (r != hipSuccess) return r;
                 ms[c] += t;
                 launches[c] += pending[slot][c];
@@ -386,7 +436,7 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
     // fin_done is recorded right after it
     if (fin && !(form == MCA_PRECOND_LITERAL && precision == MCA_PREC_FP64 && P->persym)) {
         MCA_TRY(launch_gs_step(*fin, 2, s));
-        MCA_TRY(hipEventRecord(fin_done, s));
+        if (fin_done) MCA_TRY(hipEventRecord(fin_done, s));
         fin = nullptr;
     }
     if (form == MCA_PRECOND_APPROX) {
@@ -463,7 +513,7 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
         // P = w_top + J w_bot, Q = w_top - J w_bot with w = r_b + (G_b + a2 I) r_t / a1
         if (fin) {
             MCA_TRY(launch_finish_fold(*fin, P, a1, a2, rt, rb, w.b0t, s, skip));
-            MCA_TRY(hipEventRecord(fin_done, s));
+            if (fin_done) MCA_TRY(hipEventRecord(fin_done, s));
         } else {
             MCA_TRY(launch_precond_pre_fold(P, a1, a2, rt, rb, w.b0t, s, skip));
         }
@@ -557,21 +607,13 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
         set_hip_error("hipHostMalloc", hipErrorOutOfMemory);
         return MCA_ERR_HIP;
     }
-    // host snapshots of the control block, one slot per Arnoldi step, written
-    // by the step's last kernel
+    // host snapshots of the control block, one slot of kSnapInts ints per
+    // Arnoldi step, written by the step's last kernel with a fresh marker
+    constexpr int kSnapInts = 8;
     int *snap = reinterpret_cast<int *>(host + 256);
     int *snap_dev = nullptr;
     MCA_TRY(hipHostGetDevicePointer((void **)&snap_dev, snap, 0));
-    hipEvent_t done[2] = {nullptr, nullptr};
-    struct EvGuard {
-        hipEvent_t *e;
-        ~EvGuard()
-        {
-            for (int i = 0; i < 2; ++i)
-                if (e[i]) (void)hipEventDestroy(e[i]);
-        }
-    } guard{done};
-    for (auto &e : done) MCA_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    int epoch[MCA_MAX_RESTART];
 
     double beta = fnorm;
     const double abs_tol = o->gmres_tol * fnorm;
@@ -628,7 +670,7 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
     for (;;) {
         MCA_TRY(launch_cycle_init(w.ctl, w.g, R, beta, s, two_pass ? w.sig : nullptr));
         const int jmax = std::min(R, o->max_krylov - its);
-        int last = -1;
+        int last = -1, stopped_at = -1;
         for (int j = 0; j < jmax; ++j) {
             const int slot = j & 1;
             double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
@@ -638,7 +680,7 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
             mca_status st = precond_run(P, o->precond, o->precision, a, a, vj, vj + mn, zj,
                                         zj + mn, w.pw, s, tm, slot, skip, w.D,
                                         lp_fused && j > 0, post_fused,
-                                        fin_pending ? &fin : nullptr, done[slot ^ 1]);
+                                        fin_pending ? &fin : nullptr, nullptr);
             fin_pending = false;
             if (st != MCA_OK) return st;
             double *hcol = w.H + (size_t)j * ldh;
@@ -654,7 +696,8 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
                 }
                 gs.w = wv;
                 gs.hcol = hcol;
-                gs.snap = snap_dev + 4 * j;
+                gs.snap = snap_dev + kSnapInts * j;
+                gs.epoch = epoch[j] = next_epoch();
                 MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
                 MCA_TRY(launch_gs_step(gs, 0, s));
                 MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1, slot));
@@ -684,31 +727,42 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
                 }
                 MCA_TRY(launch_normalize(wv, len, pin, hcol + j + 1, s, skip));
                 MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 2, slot));
+                epoch[j] = next_epoch();
                 MCA_TRY(launch_givens(w.H, ldh, j, w.g, w.cs, w.sn, abs_tol, w.ctl, w.resid,
-                                      snap_dev + 4 * j, s));
+                                      snap_dev + kSnapInts * j, epoch[j], s));
             }
-            // (with the finish pending, done[slot] is recorded after it, at the
-            // start of the next step or below)
-            if (!fin_pending) MCA_TRY(hipEventRecord(done[slot], s));
             last = j;
             if (j > 0) {
                 // step j runs on the GPU while the host reads step j-1's outcome
-                MCA_TRY(hipEventSynchronize(done[slot ^ 1]));
-                const int *c = snap + 4 * (j - 1);
+                // (step j-1's snapshot is written by its finish, which with the
+                // finish merged runs in step j's first launch)
+                const int *c = snap + kSnapInts * (j - 1);
+                const mca_status ws = wait_marker(c + 4, epoch[j - 1], s);
+                if (ws != MCA_OK) return ws;
                 MCA_TRY(tm->collect(slot ^ 1, c[1] == j));
-                if (c[0]) break;
+                if (c[0]) {
+                    // the cycle stopped at step j - 1: step j, already enqueued,
+                    // returns at once (its timing slot is dropped); the update
+                    // below needs no further wait
+                    stopped_at = j - 1;
+                    break;
+                }
             }
         }
         if (fin_pending) {   // the last enqueued step's finish, alone
             MCA_TRY(launch_gs_step(fin, 2, s));
-            MCA_TRY(hipEventRecord(done[last & 1], s));
             fin_pending = false;
         }
-        if (last >= 0) {
-            MCA_TRY(hipEventSynchronize(done[last & 1]));
-            MCA_TRY(tm->collect(last & 1, snap[4 * last + 1] == last + 1));
+        const int *c = nullptr;
+        if (stopped_at >= 0) {
+            c = snap + kSnapInts * stopped_at;
+            MCA_TRY(tm->collect(last & 1, false));
+        } else if (last >= 0) {
+            c = snap + kSnapInts * last;
+            const mca_status ws = wait_marker(c + 4, epoch[last], s);
+            if (ws != MCA_OK) return ws;
+            MCA_TRY(tm->collect(last & 1, c[1] == last + 1));
         }
-        const int *c = (last >= 0) ? snap + 4 * last : nullptr;
         const int k = c ? c[1] : 0;
         const int reason = c ? c[2] : CYCLE_RUNNING;
         if (reason == CYCLE_NONFINITE) return MCA_ERR_NONFINITE;
@@ -767,9 +821,13 @@ mca_status residual_norms(const mca_plan *P, const double *g_dev, const double *
     MCA_TRY(tm->begin(MCA_KCLASS_RESIDUAL, s));
     MCA_TRY(launch_residual(P, g_dev, v_in, vt, vb, F, F + mn, D, w.pa, s));
     MCA_TRY(tm->end(MCA_KCLASS_RESIDUAL, s, 1));
-    // the one-block reduction stores ||F||^2 and sum D straight into host memory
-    MCA_TRY(launch_reduce(w.pa, reduce_blocks(mn), 2, host_dev, s));
-    MCA_TRY(hipStreamSynchronize(s));
+    // the one-block reduction stores ||F||^2 and sum D straight into host memory,
+    // then its marker (host word 4 as ints)
+    int *mark = reinterpret_cast<int *>(host + 4), *mark_dev = reinterpret_cast<int *>(host_dev + 4);
+    const int e = next_epoch();
+    MCA_TRY(launch_reduce(w.pa, reduce_blocks(mn), 2, host_dev, s, mark_dev, e));
+    const mca_status ws = wait_marker(mark, e, s);
+    if (ws != MCA_OK) return ws;
     MCA_TRY(tm->collect());
     *fnorm = std::sqrt(host[0]);
     *dsum = host[1];
@@ -810,6 +868,38 @@ mca_status noalloc_scratch(void **out)
 void set_hip_error(const char *what, hipError_t e)
 {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+}
+
+mca_status wait_flag64(const long long *slot, hipStream_t s, int *value)
+{
+    // as wait_marker: the stream is queried only after 20 ms without the flag
+    using clock = std::chrono::steady_clock;
+    auto next_check = clock::now() + std::chrono::milliseconds(20);
+    for (unsigned spin = 1;; ++spin) {
+        const long long v = __atomic_load_n(slot, __ATOMIC_ACQUIRE);
+        if ((v >> 32) == 1) {
+            *value = (int)(v & 0xffffffffLL);
+            return MCA_OK;
+        }
+        __builtin_ia32_pause();
+        if ((spin & 1023) == 0 && clock::now() >= next_check) {
+            next_check = clock::now() + std::chrono::milliseconds(1);
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) {
+                const long long w = __atomic_load_n(slot, __ATOMIC_ACQUIRE);
+                if ((w >> 32) == 1) {
+                    *value = (int)(w & 0xffffffffLL);
+                    return MCA_OK;
+                }
+                set_hip_error("flag wait: the stream drained without the flag", hipErrorLaunchFailure);
+                return MCA_ERR_HIP;
+            }
+            if (q != hipErrorNotReady) {
+                set_hip_error("hipStreamQuery", q);
+                return MCA_ERR_HIP;
+            }
+        }
+    }
 }
 
 }  // namespace mca
@@ -1113,8 +1203,13 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     double *host_dev = nullptr;
     MCA_TRY(hipHostGetDevicePointer((void **)&host_dev, host, 0));
     MCA_TRY(launch_dot_partials(v_in, v_in, P->geom.m, w.pa, s));
-    MCA_TRY(launch_reduce(w.pa, reduce_blocks(P->geom.m), 1, host_dev, s));
-    MCA_TRY(hipStreamSynchronize(s));
+    {
+        const int e = next_epoch();
+        MCA_TRY(launch_reduce(w.pa, reduce_blocks(P->geom.m), 1, host_dev, s,
+                              reinterpret_cast<int *>(host_dev + 4), e));
+        const mca_status ws = wait_marker(reinterpret_cast<int *>(host + 4), e, s);
+        if (ws != MCA_OK) return ws;
+    }
     const double ynorm = P->geom.g_src * std::sqrt(host[0]);
     if (!std::isfinite(ynorm)) return MCA_ERR_NONFINITE;
     if (ynorm == 0.0) {
