@@ -262,23 +262,44 @@ SolveWs solve_layout(const mca_plan *P, const mca_options *o, void *base)
 // per host thread, released when the thread ends.
 struct PinnedScratch {
     double *buf = nullptr;
+    double *dev = nullptr;   // the same words as the device addresses them
     ~PinnedScratch()
     {
         if (buf) (void)hipHostFree(buf);
     }
 };
 
-double *pinned_scratch()
+PinnedScratch *pinned()
 {
     thread_local PinnedScratch ps;
     if (!ps.buf) {
-        void *p = nullptr;
+        void *p = nullptr, *d = nullptr;
         if (hipHostMalloc(&p, 4096 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess)
             return nullptr;
+        if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+            (void)hipHostFree(p);
+            return nullptr;
+        }
         ps.buf = static_cast<double *>(p);
+        ps.dev = static_cast<double *>(d);
     }
-    return ps.buf;
+    return &ps;
+}
+
+double *pinned_scratch()
+{
+    PinnedScratch *ps = pinned();
+    return ps ? ps->buf : nullptr;
+}
+
+// device address of a pointer into the pinned scratch block
+template <class T>
+T *pinned_dev(T *host_ptr)
+{
+    PinnedScratch *ps = pinned();
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(ps->dev) +
+                                 (reinterpret_cast<char *>(host_ptr) - reinterpret_cast<char *>(ps->buf)));
 }
 
 #define MCA_TRY(expr)                                   \
@@ -612,7 +633,7 @@ mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, dou
     constexpr int kSnapInts = 8;
     int *snap = reinterpret_cast<int *>(host + 256);
     int *snap_dev = nullptr;
-    MCA_TRY(hipHostGetDevicePointer((void **)&snap_dev, snap, 0));
+    snap_dev = pinned_dev(snap);
     int epoch[MCA_MAX_RESTART];
 
     double beta = fnorm;
@@ -816,8 +837,7 @@ mca_status residual_norms(const mca_plan *P, const double *g_dev, const double *
         set_hip_error("hipHostMalloc", hipErrorOutOfMemory);
         return MCA_ERR_HIP;
     }
-    double *host_dev = nullptr;   // the same pinned words, as the device sees them
-    MCA_TRY(hipHostGetDevicePointer((void **)&host_dev, host, 0));
+    double *host_dev = pinned_dev(host);   // the same pinned words, as the device sees them
     MCA_TRY(tm->begin(MCA_KCLASS_RESIDUAL, s));
     MCA_TRY(launch_residual(P, g_dev, v_in, vt, vb, F, F + mn, D, w.pa, s));
     MCA_TRY(tm->end(MCA_KCLASS_RESIDUAL, s, 1));
@@ -1200,25 +1220,13 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     }
 
     // ||Y|| = g_src ||v_in||
-    double *host_dev = nullptr;
-    MCA_TRY(hipHostGetDevicePointer((void **)&host_dev, host, 0));
+    double *host_dev = pinned_dev(host);
+    // (into host word 2, its marker at host word 6; read after the first
+    // residual, which is enqueued behind it without a wait in between)
     MCA_TRY(launch_dot_partials(v_in, v_in, P->geom.m, w.pa, s));
-    {
-        const int e = next_epoch();
-        MCA_TRY(launch_reduce(w.pa, reduce_blocks(P->geom.m), 1, host_dev, s,
-                              reinterpret_cast<int *>(host_dev + 4), e));
-        const mca_status ws = wait_marker(reinterpret_cast<int *>(host + 4), e, s);
-        if (ws != MCA_OK) return ws;
-    }
-    const double ynorm = P->geom.g_src * std::sqrt(host[0]);
-    if (!std::isfinite(ynorm)) return MCA_ERR_NONFINITE;
-    if (ynorm == 0.0) {
-        // no drive: V = 0 solves F = 0 exactly
-        MCA_TRY(launch_fill(v_t, 0.0, mn, s));
-        MCA_TRY(launch_fill(v_b, 0.0, mn, s));
-        MCA_TRY(hipStreamSynchronize(s));
-        return MCA_OK;
-    }
+    const int e_y = next_epoch();
+    MCA_TRY(launch_reduce(w.pa, reduce_blocks(P->geom.m), 1, host_dev + 2, s,
+                          reinterpret_cast<int *>(host_dev + 6), e_y));
     double *Vc = w.Vc, *Vn = w.Vn, *F = w.F, *Fn = w.Fn, *D = w.D, *Dn = w.Dn;
     if (o.flags & MCA_FLAG_INITIAL_GUESS) {
         MCA_TRY(hipMemcpyAsync(Vc, v_t, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1236,6 +1244,19 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     SolveWs wk = w;
     st = residual_norms(P, g_dev, v_in, Vc, Vc + mn, F, D, wk, s, &tm, &fnorm, &dsum);
     if (st == MCA_ERR_HIP) return st;
+    {
+        const mca_status ws = wait_marker(reinterpret_cast<int *>(host + 6), e_y, s);
+        if (ws != MCA_OK) return ws;
+    }
+    const double ynorm = P->geom.g_src * std::sqrt(host[2]);
+    if (!std::isfinite(ynorm)) return MCA_ERR_NONFINITE;
+    if (ynorm == 0.0) {
+        // no drive: V = 0 solves F = 0 exactly
+        MCA_TRY(launch_fill(v_t, 0.0, mn, s));
+        MCA_TRY(launch_fill(v_b, 0.0, mn, s));
+        MCA_TRY(hipStreamSynchronize(s));
+        return MCA_OK;
+    }
     int from_guess = (o.flags & (MCA_FLAG_INITIAL_GUESS | MCA_FLAG_SWEEP_START)) ? 1 : 0;
     if (from_guess && (o.flags & MCA_FLAG_GUESS_FALLBACK) && !(st == MCA_OK && fnorm < ynorm)) {
         // the guess is no better than V = 0, whose residual is ||Y||: start from 0
