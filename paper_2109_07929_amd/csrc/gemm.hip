@@ -74,7 +74,10 @@ __device__ __forceinline__ void store_tile(const GemmArgs &a, const d4 (&acc)[NB
                                            int n0, int wm, int wn, int lane)
 {
     const int M = a.M, N = a.N;
-    const double inv_a1 = (EPI != EPI_STORE) ? 1.0 / a.a1 : 0.0;
+    // the shift a1 = a2 from the device when the launch carries it there
+    const double a1 = (EPI != EPI_STORE && a.shift) ? a.shift[0] : a.a1;
+    const double a2 = (EPI != EPI_STORE && a.shift) ? a.shift[0] : a.a2;
+    const double inv_a1 = (EPI != EPI_STORE) ? (a.shift ? a.shift[1] : 1.0 / a1) : 0.0;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -92,15 +95,15 @@ __device__ __forceinline__ void store_tile(const GemmArgs &a, const d4 (&acc)[NB
                 } else if constexpr (EPI == EPI_DIV_MU) {
                     // eigenvalue of M (eq. (M)) for mode (row, col), summed without cancellation
                     const double lb = a.lb[row], lt = a.lt[col];
-                    const double mu = lb * lt * inv_a1 + lb + a.a2 * inv_a1 * lt;
+                    const double mu = lb * lt * inv_a1 + lb + a2 * inv_a1 * lt;
                     a.O0[o] = acc[0][i][j][r] / mu;
                 } else {
                     // per-mode block solve [[lt + a1, -a1], [-a2, lb + a2]] x = r
                     const double lb = a.lb[row], lt = a.lt[col];
-                    const double det = lt * lb + a.a2 * lt + a.a1 * lb;
+                    const double det = lt * lb + a2 * lt + a1 * lb;
                     const double rt = acc[0][i][j][r], rb = acc[NB - 1][i][j][r];
-                    a.O0[o] = ((lb + a.a2) * rt + a.a1 * rb) / det;
-                    a.O1[o] = (a.a2 * rt + (lt + a.a1) * rb) / det;
+                    a.O0[o] = ((lb + a2) * rt + a1 * rb) / det;
+                    a.O1[o] = (a2 * rt + (lt + a1) * rb) / det;
                 }
             }
 }

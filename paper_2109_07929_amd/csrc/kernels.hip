@@ -136,12 +136,17 @@ __global__ __launch_bounds__(TPB) void k_precond_pre(
 }
 
 // w = r_b + ((G_b + a2 I) r_t) / a1 at rows i and m-1-i, folded: P = sum, Q = difference
+// (with shift set: a2 = shift[0], 1 / a1 = shift[1] from the device)
 __global__ __launch_bounds__(TPB) void k_precond_pre_fold(
     int m, int n, Wire bot, double inv_a1, double a2,
     const double *__restrict__ rt, const double *__restrict__ rb, double *__restrict__ f,
-    const int *__restrict__ skip)
+    const int *__restrict__ skip, const double *__restrict__ shift)
 {
     if (skip && *skip) return;
+    if (shift) {
+        a2 = shift[0];
+        inv_a1 = shift[1];
+    }
     const int h = m / 2;
     const size_t hn = (size_t)h * n;
     auto w_at = [&](int i, int j) {
@@ -409,6 +414,8 @@ __global__ __launch_bounds__(NT) void k_jacobian_proj(GsStep a)
             if (q < nv) acc[q] += y1 * a.V[q * a.ldv + k] + y2 * a.V[q * a.ldv + mn + k];
     };
     if constexpr (POST) {
+        const double pa1 = a.shift ? a.shift[0] : a.post_a1;
+        const double pinv = a.shift ? a.shift[1] : a.post_inv_a1;
         const int strips = (m + kPostRows - 1) / kPostRows;
         const size_t units = (size_t)strips * n;
 #pragma unroll 1
@@ -423,7 +430,7 @@ __global__ __launch_bounds__(NT) void k_jacobian_proj(GsStep a)
             };
             auto zb_of = [&](int i, double zl, double zc, double zr) {
                 const double s = wire_apply(a.top, jj, zc, zl, zr);
-                return (s + a.post_a1 * zc - a.post_rt[(size_t)i * n + jj]) * a.post_inv_a1;
+                return (s + pa1 * zc - a.post_rt[(size_t)i * n + jj]) * pinv;
             };
             double cl, cc, cr;
             row(i0, cl, cc, cr);
@@ -695,7 +702,7 @@ __device__ __forceinline__ void gs_finish_block(const GsStep &a)
             a.g[j] = c * gj;
             ctl[1] = j + 1;
             a.resid[j] = fabs(sn * gj);
-            if (fabs(sn * gj) <= a.abs_tol) {   // includes nrm == 0 (invariant subspace)
+            if (fabs(sn * gj) <= (a.tol ? a.tol[0] : a.abs_tol)) {   // includes nrm == 0
                 ctl[0] = 1;
                 ctl[2] = CYCLE_CONVERGED;
             }
@@ -717,6 +724,7 @@ struct FoldArgs {
     int m, n;
     Wire bot;
     double inv_a1, a2;
+    const double *shift;    // optional: a2 = shift[0], 1 / a1 = shift[1] (device)
     const double *rt, *rb;
     double *f;
     const int *skip;
@@ -731,12 +739,13 @@ __global__ __launch_bounds__(1024) void k_finish_fold(GsStep g, FoldArgs a)
     if (a.skip && *a.skip) return;
     const int m = a.m, n = a.n, h = m / 2;
     const size_t hn = (size_t)h * n;
+    const double a2 = a.shift ? a.shift[0] : a.a2, inv_a1 = a.shift ? a.shift[1] : a.inv_a1;
     auto w_at = [&](int i, int j) {
         const size_t k = (size_t)i * n + j;
         const double r = a.rt[k];
         const double s = wire_apply(a.bot, i, r, (i > 0) ? a.rt[k - n] : 0.0,
                                     (i + 1 < m) ? a.rt[k + n] : 0.0);
-        return a.rb[k] + (s + a.a2 * r) * a.inv_a1;
+        return a.rb[k] + (s + a2 * r) * inv_a1;
     };
     const size_t stride = (size_t)(gridDim.x - 1) * 1024;
     for (size_t k = (size_t)(blockIdx.x - 1) * 1024 + threadIdx.x; k < hn; k += stride) {
@@ -904,7 +913,7 @@ hipError_t launch_precond_pre(const mca_plan *P, double a1, double a2, const dou
 
 hipError_t launch_finish_fold(const GsStep &g, const mca_plan *P, double a1, double a2,
                               const double *rt, const double *rb, double *f, hipStream_t s,
-                              const int *skip)
+                              const int *skip, const double *shift)
 {
     const int nv = g.j + 1;
     if (g.j < 0 || nv > kGsMaxV || g.j + 1 >= g.ldl || g.j + 1 >= g.ldh) return hipErrorInvalidValue;
@@ -912,8 +921,9 @@ hipError_t launch_finish_fold(const GsStep &g, const mca_plan *P, double a1, dou
     a.m = P->geom.m;
     a.n = P->geom.n;
     a.bot = P->bot;
-    a.inv_a1 = 1.0 / a1;
+    a.inv_a1 = shift ? 0.0 : 1.0 / a1;
     a.a2 = a2;
+    a.shift = shift;
     a.rt = rt;
     a.rb = rb;
     a.f = f;
@@ -929,7 +939,16 @@ hipError_t launch_precond_pre_fold(const mca_plan *P, double a1, double a2, cons
 {
     const int m = P->geom.m, n = P->geom.n;
     hipLaunchKernelGGL(k_precond_pre_fold, dim3(elementwise_blocks((size_t)(m / 2) * n)), dim3(TPB),
-                       0, s, m, n, P->bot, 1.0 / a1, a2, rt, rb, f, skip);
+                       0, s, m, n, P->bot, 1.0 / a1, a2, rt, rb, f, skip, (const double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_pre_fold_dev(const mca_plan *P, const double *shift, const double *rt,
+                                       const double *rb, double *f, hipStream_t s, const int *skip)
+{
+    const int m = P->geom.m, n = P->geom.n;
+    hipLaunchKernelGGL(k_precond_pre_fold, dim3(elementwise_blocks((size_t)(m / 2) * n)), dim3(TPB),
+                       0, s, m, n, P->bot, 0.0, 0.0, rt, rb, f, skip, shift);
     return hipGetLastError();
 }
 
@@ -1010,6 +1029,56 @@ hipError_t launch_gs_step(const GsStep &g, int pass, hipStream_t s)
     } else {
         hipLaunchKernelGGL(k_gs_finish, dim3(1), dim3(1024), 0, s, g);
     }
+    return hipGetLastError();
+}
+
+// The Newton scalars of a residual and the start of the first GMRES cycle
+// on them (one thread; see launch_newton_next).
+__global__ void k_newton_next(const double *__restrict__ sums, double mn, double gmres_tol,
+                              double accept2, double conv2, double *__restrict__ nsc,
+                              int *__restrict__ ctl, double *__restrict__ g, int R,
+                              double *__restrict__ sig)
+{
+    for (int i = threadIdx.x + 1; i <= R; i += blockDim.x) g[i] = 0.0;
+    if (threadIdx.x != 0) return;
+    const double x = sums[0], ds = sums[1];
+    const double a = ds / mn, beta = sqrt(x);
+    nsc[0] = a;
+    nsc[1] = 1.0 / a;
+    nsc[2] = beta;
+    nsc[3] = -1.0 / beta;
+    nsc[4] = gmres_tol * beta;
+    const bool ok = isfinite(x) && isfinite(ds) && x <= accept2 && !(x <= conv2);
+    g[0] = beta;
+    ctl[0] = ok ? 0 : 1;
+    ctl[1] = 0;
+    ctl[2] = CYCLE_RUNNING;
+    ctl[3] = 0;
+    if (sig) sig[0] = 1.0;
+}
+
+hipError_t launch_newton_next(const double *sums, double mn, double gmres_tol, double accept2,
+                              double conv2, double *nsc, int *ctl, double *g, int R, double *sig,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_newton_next, dim3(1), dim3(64), 0, s, sums, mn, gmres_tol, accept2, conv2,
+                       nsc, ctl, g, R, sig);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(TPB) void k_scale_dev(const double *__restrict__ x,
+                                                   const double *__restrict__ alpha,
+                                                   double *__restrict__ y, size_t len)
+{
+    const double al = alpha[0];
+    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < len; k += (size_t)gridDim.x * TPB)
+        y[k] = al * x[k];
+}
+
+hipError_t launch_scale_dev(const double *x, const double *alpha, double *y, size_t len,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_dev, dim3(elementwise_blocks(len)), dim3(TPB), 0, s, x, alpha, y, len);
     return hipGetLastError();
 }
 

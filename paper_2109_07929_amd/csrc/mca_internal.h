@@ -128,6 +128,7 @@ struct GemmArgs {
     double *O0, *O1;
     const double *lb, *lt;     // for the epilogues (length M and N)
     double a1, a2;
+    const double *shift;       // optional: a1 = a2 = shift[0], 1 / a1 = shift[1] (device)
     int vec;                   // set by the launcher: rows are 16-byte aligned
     const int *skip;           // optional: return at once when *skip != 0
     int ldo;                   // output row stride (0: N)
@@ -280,6 +281,10 @@ struct GsStep {
     const double *post_rt;
     double *zb_store;
     double post_a1, post_inv_a1;
+    // optional device copies (Newton scalars, see launch_newton_next): with
+    // shift set, post_a1 = shift[0] and post_inv_a1 = shift[1]; with tol set,
+    // abs_tol = tol[0]
+    const double *shift, *tol;
 };
 // pass 0: the Jacobian product with the projections; pass 1: the update;
 // pass 2: ||w||, sig_{j+1}, row j + 1 of L, the Givens update and the snapshot
@@ -289,7 +294,27 @@ hipError_t launch_gs_step(const GsStep &g, int pass, hipStream_t s);
 // launch_precond_pre_fold), in one launch
 hipError_t launch_finish_fold(const GsStep &g, const mca_plan *P, double a1, double a2,
                               const double *rt, const double *rb, double *f, hipStream_t s,
-                              const int *skip);
+                              const int *skip, const double *shift = nullptr);
+
+// Newton scalars on the device (8 doubles): [0] a = sum D / mn (the shift
+// a1 = a2 of eq. (P)), [1] 1 / a, [2] beta = ||F||, [3] -1 / beta, [4] the
+// GMRES stop gmres_tol * beta.  launch_newton_next derives them from the
+// residual's reduced sums (sums[0] = ||F||^2, sums[1] = sum D; may be pinned
+// host memory) and starts the first GMRES cycle: g = (beta, 0, ...), sig[0] = 1
+// (if sig), ctl = (stop, 0, running, 0) with stop set unless
+// ||F||^2 <= accept2 and ||F||^2 > conv2 (both finite): a cycle enqueued
+// ahead of the host's decision on the trial point then does nothing when
+// the host is going to reject it or stop.
+hipError_t launch_newton_next(const double *sums, double mn, double gmres_tol, double accept2,
+                              double conv2, double *nsc, int *ctl, double *g, int R, double *sig,
+                              hipStream_t s);
+// y = x * alpha[0] (alpha on the device)
+hipError_t launch_scale_dev(const double *x, const double *alpha, double *y, size_t len,
+                            hipStream_t s);
+// the persymmetric fold with the shift from the device (shift[0] = a, shift[1] = 1 / a)
+hipError_t launch_precond_pre_fold_dev(const mca_plan *P, const double *shift, const double *rt,
+                                       const double *rb, double *f, hipStream_t s,
+                                       const int *skip);
 
 // Device-side least squares of one GMRES cycle (see k_givens).
 enum CycleReason { CYCLE_RUNNING = 0, CYCLE_CONVERGED = 1, CYCLE_BREAKDOWN = 2,

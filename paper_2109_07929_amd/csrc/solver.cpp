@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -217,6 +218,7 @@ struct SolveWs {
     double *H;        // Hessenberg, column-major, ld = restart + 1
     double *coef;     // least-squares solution y
     double *scal;     // reduced scalars
+    double *nsc;      // Newton scalars on the device (launch_newton_next)
     double *g, *cs, *sn, *resid;   // Givens state of the current cycle
     int *ctl;         // cycle control block (stop flag, steps done, reason)
     PrecondWs pw;
@@ -248,6 +250,7 @@ SolveWs solve_layout(const mca_plan *P, const mca_options *o, void *base)
     w.H = c.take<double>((R + 1) * R);
     w.coef = c.take<double>(R);
     w.scal = c.take<double>(8);
+    w.nsc = c.take<double>(8);
     w.g = c.take<double>(R + 1);
     w.cs = c.take<double>(R);
     w.sn = c.take<double>(R);
@@ -408,12 +411,12 @@ struct Timing {
         pending[slot][c] = nlaunch;
         return hipEventRecord(ev[slot][c][1], s);
     }
-    // after the events of `slot` have completed
-    hipError_t collect(int slot = 0, bool count = true)
+    // after the events of `slot` have completed (only class `only` if >= 0)
+    hipError_t collect(int slot = 0, bool count = true, int only = -1)
     {
         if (!on) return hipSuccess;
         for (int c = 0; c < MCA_NUM_KCLASS; ++c) {
-            if (!pending[slot][c]) continue;
+            if (!pending[slot][c] || (only >= 0 && c != only)) continue;
             if (count) {
                 float t = 0.f;
                 hipError_t r = hipEventElapsedTime(&t, ev[slot][c][0], ev[slot][c][1]);
@@ -448,8 +451,10 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
                        const PrecondWs &w, hipStream_t s, Timing *tm = nullptr, int slot = 0,
                        const int *skip = nullptr, const double *D = nullptr, bool r_split = false,
                        bool defer_post = false, const GsStep *fin = nullptr,
-                       hipEvent_t fin_done = nullptr)
+                       hipEvent_t fin_done = nullptr, const double *shift = nullptr)
 {
+    // shift (persymmetric literal FP64 form only): a1 = a2 = shift[0] and
+    // 1 / a1 = shift[1] are read on the device instead of a1, a2
     Timing off;
     if (!tm) tm = &off;
     // fin: the previous Arnoldi step's finish, launched with this application's
@@ -533,11 +538,14 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
         const size_t hn = (size_t)h * n;
         // P = w_top + J w_bot, Q = w_top - J w_bot with w = r_b + (G_b + a2 I) r_t / a1
         if (fin) {
-            MCA_TRY(launch_finish_fold(*fin, P, a1, a2, rt, rb, w.b0t, s, skip));
+            MCA_TRY(launch_finish_fold(*fin, P, a1, a2, rt, rb, w.b0t, s, skip, shift));
             if (fin_done) MCA_TRY(hipEventRecord(fin_done, s));
+        } else if (shift) {
+            MCA_TRY(launch_precond_pre_fold_dev(P, shift, rt, rb, w.b0t, s, skip));
         } else {
             MCA_TRY(launch_precond_pre_fold(P, a1, a2, rt, rb, w.b0t, s, skip));
         }
+        g.shift = shift;
         MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
         // W_hat^T = [P^T U_s | Q^T U_a]   (n x m, modes: symmetric, antisymmetric; one launch)
         g.M = n; g.N = h; g.K = h; g.ldo = m; g.pair = 1;
@@ -573,7 +581,10 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
         }
         MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, nl, slot));
         // (deferred: the caller's Jacobian pass forms z_b)
-        if (!defer_post) MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s, skip));
+        if (!defer_post) {
+            if (shift) return MCA_ERR_INVALID_ARG;   // (not a combination the solver makes)
+            MCA_TRY(launch_precond_post(P, a1, zt, rt, zb, s, skip));
+        }
         return MCA_OK;
     }
     if (form == MCA_PRECOND_LITERAL) {
@@ -612,224 +623,295 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
 }
 
 // Flexible GMRES(restart) with modified Gram-Schmidt for J X = -F, right
-// preconditioned by P(a, a).  On return X holds the correction.  Gram-Schmidt
-// runs in two passes per Arnoldi step (compact WY form) when restart <= 32 and
-// MCA_FLAG_MGS_PASSES is not set, else in one pass per basis vector.
-mca_status fgmres(const mca_plan *P, const mca_options *o, const SolveWs &w, double fnorm,
-                  double a, hipStream_t s, Timing *tm, int *its_out, int *restarts_out,
-                  bool *conv_out)
-{
-    const size_t mn = (size_t)P->geom.m * P->geom.n, len = 2 * mn;
-    const int R = o->restart;
-    const int ldh = R + 1;
-    const bool two_pass = !(o->flags & MCA_FLAG_MGS_PASSES) && R <= kGsMaxV;
-    double *host = pinned_scratch();
-    if (!host) {
-        set_hip_error("hipHostMalloc", hipErrorOutOfMemory);
-        return MCA_ERR_HIP;
-    }
-    // host snapshots of the control block, one slot of kSnapInts ints per
-    // Arnoldi step, written by the step's last kernel with a fresh marker
-    constexpr int kSnapInts = 8;
-    int *snap = reinterpret_cast<int *>(host + 256);
-    int *snap_dev = nullptr;
-    snap_dev = pinned_dev(snap);
-    int epoch[MCA_MAX_RESTART];
-
-    double beta = fnorm;
-    const double abs_tol = o->gmres_tol * fnorm;
-    GsStep gs{};
-    gs.m = P->geom.m;
-    gs.n = P->geom.n;
-    gs.top = P->top;
-    gs.bot = P->bot;
-    gs.d = w.D;
-    gs.V = w.V;
-    gs.ldv = len;
-    gs.sig = w.sig;
-    gs.L = w.Lg;
-    gs.ldl = R + 1;
-    gs.H = w.H;
-    gs.ldh = ldh;
-    gs.p1 = w.pg1;
-    gs.p2 = w.pg2;
-    gs.g = w.g;
-    gs.cs = w.cs;
-    gs.sn = w.sn;
-    gs.resid = w.resid;
-    gs.abs_tol = abs_tol;
-    gs.ctl = w.ctl;
-    // the reduced-precision per-mode chain: the update pass converts the new
-    // vector into the chain's operand planes itself
-    const bool lp_fused = two_pass && o->precond == MCA_PRECOND_PERMODE &&
-                          o->precision != MCA_PREC_FP64;
-    if (lp_fused) {
-        for (int b = 0; b < 2; ++b)
-            for (int pl = 0; pl < 2; ++pl) gs.xp[b][pl] = w.pw.lp[b].p[pl];
-        gs.prec = o->precision;
-    }
-    // the literal form's last step (z_b from z_t) runs inside the Jacobian pass
-    const bool post_fused = two_pass && o->precond == MCA_PRECOND_LITERAL &&
-                            o->precision == MCA_PREC_FP64;
-    // persymmetric literal form: step j's finish shares a launch with step j + 1's
-    // first stencil (the finish of the cycle's last enqueued step runs alone)
-    const bool merge_fin = post_fused && P->persym;
-    GsStep fin{};
+// preconditioned by P(a, a), for one Newton step.  On return X holds the
+// correction.  Gram-Schmidt runs in two passes per Arnoldi step (compact WY
+// form) when restart <= 32 and MCA_FLAG_MGS_PASSES is not set, else in one
+// pass per basis vector.
+//
+// start() enqueues the Newton scalars of F (launch_newton_next: the shift a,
+// ||F||, the GMRES stop) and v_0 = -F / ||F||; step(j) enqueues Arnoldi step
+// j; run() enqueues the rest and drives the cycles.  The two calls before
+// run() may come before the host knows F's norm: the Newton loop enqueues
+// them behind a trial point's residual, gated on the device by the trial's
+// acceptance, so the GPU goes on into the next Newton step while the host
+// reads the trial's norm.  In the persymmetric literal FP64 form the kernels
+// take the shift and the stop from the device scalars (the form in which the
+// start is enqueued ahead); the other forms take the host's values.
+struct Fgmres {
+    const mca_plan *P;
+    const mca_options *o;
+    SolveWs w;
+    hipStream_t s;
+    Timing *tm;
+    size_t mn, len;
+    int R, ldh;
+    bool two_pass, lp_fused, post_fused, merge_fin;
+    static constexpr int kSnapInts = 8;   // ints per step's snapshot slot (marker at [4])
+    double *host = nullptr;
+    int *snap = nullptr, *snap_dev = nullptr;
+    int epoch[MCA_MAX_RESTART] = {};
+    GsStep gs{}, fin{};
     bool fin_pending = false;
-    if (post_fused) {
-        gs.post_a1 = a;
-        gs.post_inv_a1 = 1.0 / a;
-    }
-    int its = 0, restarts = 0;
-    bool converged = false, first = true;
-    // v_0 = -F / ||F||
-    MCA_TRY(launch_scale(w.F, -1.0 / beta, w.V, len, s));
-    {
-        const mca_status st = precond_setup(P, o->precond, a, a, w.pw, s);
-        if (st != MCA_OK) return st;
-    }
-    for (;;) {
-        MCA_TRY(launch_cycle_init(w.ctl, w.g, R, beta, s, two_pass ? w.sig : nullptr));
-        const int jmax = std::min(R, o->max_krylov - its);
-        int last = -1, stopped_at = -1;
-        for (int j = 0; j < jmax; ++j) {
-            const int slot = j & 1;
-            double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
-            double *wv = w.V + (size_t)(j + 1) * len;
-            const int *skip = w.ctl;
-            // (the previous step's update pass left v_j in operand format)
-            mca_status st = precond_run(P, o->precond, o->precision, a, a, vj, vj + mn, zj,
-                                        zj + mn, w.pw, s, tm, slot, skip, w.D,
-                                        lp_fused && j > 0, post_fused,
-                                        fin_pending ? &fin : nullptr, nullptr);
-            fin_pending = false;
-            if (st != MCA_OK) return st;
-            double *hcol = w.H + (size_t)j * ldh;
-            if (two_pass) {
-                // w = sig_j J z~_j fused with the projections on the basis and
-                // MGS's coefficients, then w -= V h with the Givens update
-                gs.j = j;
-                gs.zt = zj;
-                gs.zb = zj + mn;
-                if (post_fused) {
-                    gs.post_rt = vj;
-                    gs.zb_store = zj + mn;
-                }
-                gs.w = wv;
-                gs.hcol = hcol;
-                gs.snap = snap_dev + kSnapInts * j;
-                gs.epoch = epoch[j] = next_epoch();
-                MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
-                MCA_TRY(launch_gs_step(gs, 0, s));
-                MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1, slot));
-                MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s, slot));
-                MCA_TRY(launch_gs_step(gs, 1, s));
-                MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 1 <= kGsFusedMaxV ? 1 : 2, slot));
-                if (merge_fin) {
-                    fin = gs;
-                    fin_pending = true;
-                } else {
-                    MCA_TRY(launch_gs_step(gs, 2, s));
-                }
-            } else {
-                // w = J z_j, fused with the partial sums of <w, v_0>
-                MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
-                MCA_TRY(launch_jacobian(P, w.D, zj, zj + mn, wv, wv + mn, s, w.V, w.pa, skip));
-                MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1, slot));
-                // modified Gram-Schmidt, one pass per basis vector:
-                // h_ij = <w, v_i>, w -= h_ij v_i, i = 0..j
-                MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s, slot));
-                double *pin = w.pa, *pout = w.pb;
-                for (int i = 0; i <= j; ++i) {
-                    const double *vnext = (i < j) ? w.V + (size_t)(i + 1) * len : nullptr;
-                    MCA_TRY(launch_mgs_step(wv, w.V + (size_t)i * len, vnext, len, pin, pout,
-                                            hcol + i, s, skip));
-                    std::swap(pin, pout);
-                }
-                MCA_TRY(launch_normalize(wv, len, pin, hcol + j + 1, s, skip));
-                MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 2, slot));
-                epoch[j] = next_epoch();
-                MCA_TRY(launch_givens(w.H, ldh, j, w.g, w.cs, w.sn, abs_tol, w.ctl, w.resid,
-                                      snap_dev + kSnapInts * j, epoch[j], s));
-            }
-            last = j;
-            if (j > 0) {
-                // step j runs on the GPU while the host reads step j-1's outcome
-                // (step j-1's snapshot is written by its finish, which with the
-                // finish merged runs in step j's first launch)
-                const int *c = snap + kSnapInts * (j - 1);
-                const mca_status ws = wait_marker(c + 4, epoch[j - 1], s);
-                if (ws != MCA_OK) return ws;
-                MCA_TRY(tm->collect(slot ^ 1, c[1] == j));
-                if (c[0]) {
-                    // the cycle stopped at step j - 1: step j, already enqueued,
-                    // returns at once (its timing slot is dropped); the update
-                    // below needs no further wait
-                    stopped_at = j - 1;
-                    break;
-                }
-            }
-        }
-        if (fin_pending) {   // the last enqueued step's finish, alone
-            MCA_TRY(launch_gs_step(fin, 2, s));
-            fin_pending = false;
-        }
-        const int *c = nullptr;
-        if (stopped_at >= 0) {
-            c = snap + kSnapInts * stopped_at;
-            MCA_TRY(tm->collect(last & 1, false));
-        } else if (last >= 0) {
-            c = snap + kSnapInts * last;
-            const mca_status ws = wait_marker(c + 4, epoch[last], s);
-            if (ws != MCA_OK) return ws;
-            MCA_TRY(tm->collect(last & 1, c[1] == last + 1));
-        }
-        const int k = c ? c[1] : 0;
-        const int reason = c ? c[2] : CYCLE_RUNNING;
-        if (reason == CYCLE_NONFINITE) return MCA_ERR_NONFINITE;
-        its += k;
-        if (k > 0) {
-            MCA_TRY(launch_backsolve(w.H, ldh, w.g, w.ctl, w.coef, s,
-                                     two_pass ? w.sig : nullptr));
-            // the number of completed steps is ctl[1]
-            MCA_TRY(launch_update(w.Z, len, w.coef, 0, w.ctl + 1, len, w.X, first ? 0 : 1, s));
-            first = false;
-        } else if (first) {
-            MCA_TRY(launch_fill(w.X, 0.0, len, s));
-            first = false;
-        }
-        converged = reason == CYCLE_CONVERGED;
-        if (converged || its >= o->max_krylov || reason == CYCLE_BREAKDOWN || k == 0) break;
-        // restart from the true residual  r = -F - J X
-        ++restarts;
-        MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s));
-        MCA_TRY(launch_jacobian(P, w.D, w.X, w.X + mn, w.tmp, w.tmp + mn, s));
-        MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1));
-        MCA_TRY(launch_neg_sum(w.F, w.tmp, w.V, len, s));
-        MCA_TRY(launch_dot_partials(w.V, w.V, len, w.pa, s));
-        MCA_TRY(launch_reduce(w.pa, reduce_blocks(len), 1, w.scal, s));
-        MCA_TRY(hipMemcpyAsync(host, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
-        MCA_TRY(hipStreamSynchronize(s));
-        MCA_TRY(tm->collect());
-        beta = std::sqrt(host[0]);
-        if (!std::isfinite(beta)) return MCA_ERR_NONFINITE;
-        if (beta <= abs_tol) {
-            converged = true;
-            break;
-        }
-        MCA_TRY(launch_scale(w.V, 1.0 / beta, w.V, len, s));
-    }
-    *its_out = its;
-    *restarts_out = restarts;
-    *conv_out = converged;
-    return MCA_OK;
-}
+    double a = 0.0;          // host shift (forms without the device shift)
+    double fnorm_host = 0.0; // ||F|| as the host has it (set by run)
+    int enqueued = 0;        // Arnoldi steps of the first cycle already enqueued
 
-// Residual at (vt, vb) into F/D, returning ||F|| and sum(D) on the host.
-mca_status residual_norms(const mca_plan *P, const double *g_dev, const double *v_in,
-                          const double *vt, const double *vb, double *F, double *D,
-                          const SolveWs &w, hipStream_t s, Timing *tm, double *fnorm,
-                          double *dsum)
+    Fgmres(const mca_plan *P_, const mca_options *o_, const SolveWs &w_, hipStream_t s_, Timing *tm_)
+        : P(P_), o(o_), w(w_), s(s_), tm(tm_)
+    {
+        mn = (size_t)P->geom.m * P->geom.n;
+        len = 2 * mn;
+        R = o->restart;
+        ldh = R + 1;
+        two_pass = !(o->flags & MCA_FLAG_MGS_PASSES) && R <= kGsMaxV;
+        // the reduced-precision per-mode chain: the update pass converts the new
+        // vector into the chain's operand planes itself
+        lp_fused = two_pass && o->precond == MCA_PRECOND_PERMODE && o->precision != MCA_PREC_FP64;
+        // the literal form's last step (z_b from z_t) runs inside the Jacobian pass
+        post_fused = two_pass && o->precond == MCA_PRECOND_LITERAL && o->precision == MCA_PREC_FP64;
+        // persymmetric literal form: step j's finish shares a launch with step j + 1's
+        // first stencil (the finish of the cycle's last enqueued step runs alone)
+        merge_fin = post_fused && P->persym;
+        host = pinned_scratch();
+        if (host) {
+            snap = reinterpret_cast<int *>(host + 256);
+            snap_dev = pinned_dev(snap);
+        }
+        gs.m = P->geom.m;
+        gs.n = P->geom.n;
+        gs.top = P->top;
+        gs.bot = P->bot;
+        gs.d = w.D;
+        gs.V = w.V;
+        gs.ldv = len;
+        gs.sig = w.sig;
+        gs.L = w.Lg;
+        gs.ldl = R + 1;
+        gs.H = w.H;
+        gs.ldh = ldh;
+        gs.p1 = w.pg1;
+        gs.p2 = w.pg2;
+        gs.g = w.g;
+        gs.cs = w.cs;
+        gs.sn = w.sn;
+        gs.resid = w.resid;
+        gs.ctl = w.ctl;
+        gs.tol = w.nsc + 4;
+        if (lp_fused) {
+            for (int b = 0; b < 2; ++b)
+                for (int pl = 0; pl < 2; ++pl) gs.xp[b][pl] = w.pw.lp[b].p[pl];
+            gs.prec = o->precision;
+        }
+        if (merge_fin) gs.shift = w.nsc;
+    }
+
+    // whether the kernels of this form read the shift from the device
+    bool device_shift() const { return merge_fin; }
+
+    // Newton scalars of F from its reduced sums (device address; ||F||^2,
+    // sum D), the first cycle's start (gated by accept2 / conv2, see
+    // launch_newton_next) and v_0 = -F / ||F||.
+    mca_status start(const double *sums_dev, double accept2, double conv2)
+    {
+        if (!host) {
+            set_hip_error("hipHostMalloc", hipErrorOutOfMemory);
+            return MCA_ERR_HIP;
+        }
+        MCA_TRY(launch_newton_next(sums_dev, (double)mn, o->gmres_tol, accept2, conv2, w.nsc, w.ctl,
+                                   w.g, R, two_pass ? w.sig : nullptr, s));
+        MCA_TRY(launch_scale_dev(w.F, w.nsc + 3, w.V, len, s));
+        return MCA_OK;
+    }
+
+    // Arnoldi step j of the current cycle
+    mca_status step(int j)
+    {
+        const int slot = j & 1;
+        double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
+        double *wv = w.V + (size_t)(j + 1) * len;
+        const int *skip = w.ctl;
+        // (the previous step's update pass left v_j in operand format)
+        mca_status st = precond_run(P, o->precond, o->precision, a, a, vj, vj + mn, zj, zj + mn,
+                                    w.pw, s, tm, slot, skip, w.D, lp_fused && j > 0, post_fused,
+                                    fin_pending ? &fin : nullptr, nullptr,
+                                    device_shift() ? w.nsc : nullptr);
+        fin_pending = false;
+        if (st != MCA_OK) return st;
+        double *hcol = w.H + (size_t)j * ldh;
+        if (two_pass) {
+            // w = sig_j J z~_j fused with the projections on the basis and
+            // MGS's coefficients, then w -= V h with the Givens update
+            gs.j = j;
+            gs.zt = zj;
+            gs.zb = zj + mn;
+            if (post_fused) {
+                gs.post_rt = vj;
+                gs.zb_store = zj + mn;
+                gs.post_a1 = a;
+                gs.post_inv_a1 = device_shift() ? 0.0 : 1.0 / a;
+            }
+            gs.w = wv;
+            gs.hcol = hcol;
+            gs.snap = snap_dev + kSnapInts * j;
+            gs.epoch = epoch[j] = next_epoch();
+            MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
+            MCA_TRY(launch_gs_step(gs, 0, s));
+            MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1, slot));
+            MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s, slot));
+            MCA_TRY(launch_gs_step(gs, 1, s));
+            MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 1 <= kGsFusedMaxV ? 1 : 2, slot));
+            if (merge_fin) {
+                fin = gs;
+                fin_pending = true;
+            } else {
+                MCA_TRY(launch_gs_step(gs, 2, s));
+            }
+        } else {
+            // w = J z_j, fused with the partial sums of <w, v_0>
+            MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s, slot));
+            MCA_TRY(launch_jacobian(P, w.D, zj, zj + mn, wv, wv + mn, s, w.V, w.pa, skip));
+            MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1, slot));
+            // modified Gram-Schmidt, one pass per basis vector:
+            // h_ij = <w, v_i>, w -= h_ij v_i, i = 0..j
+            MCA_TRY(tm->begin(MCA_KCLASS_ORTHO, s, slot));
+            double *pin = w.pa, *pout = w.pb;
+            for (int i = 0; i <= j; ++i) {
+                const double *vnext = (i < j) ? w.V + (size_t)(i + 1) * len : nullptr;
+                MCA_TRY(launch_mgs_step(wv, w.V + (size_t)i * len, vnext, len, pin, pout, hcol + i,
+                                        s, skip));
+                std::swap(pin, pout);
+            }
+            MCA_TRY(launch_normalize(wv, len, pin, hcol + j + 1, s, skip));
+            MCA_TRY(tm->end(MCA_KCLASS_ORTHO, s, j + 2, slot));
+            epoch[j] = next_epoch();
+            MCA_TRY(launch_givens(w.H, ldh, j, w.g, w.cs, w.sn, o->gmres_tol * fnorm_host, w.ctl,
+                                  w.resid, snap_dev + kSnapInts * j, epoch[j], s));
+        }
+        return MCA_OK;
+    }
+
+    // a first step enqueued ahead that the host does not take: its timing slot
+    // is dropped (its kernels return at once on the gated stop flag)
+    mca_status abandon()
+    {
+        if (enqueued > 0) MCA_TRY(tm->collect(0, false));
+        enqueued = 0;
+        fin_pending = false;
+        return MCA_OK;
+    }
+
+    // step 0 enqueued ahead of run()
+    mca_status prelaunch_first_step()
+    {
+        const mca_status st = step(0);
+        if (st == MCA_OK) enqueued = 1;
+        return st;
+    }
+
+    // The GMRES solve from F with ||F|| = fnorm and shift a (host values),
+    // after start() (and possibly step(0)) were enqueued.
+    mca_status run(double fnorm, double a_host, int *its_out, int *restarts_out, bool *conv_out)
+    {
+        a = a_host;
+        fnorm_host = fnorm;
+        double beta = fnorm;
+        const double abs_tol = o->gmres_tol * fnorm;
+        if (!device_shift()) {
+            const mca_status st = precond_setup(P, o->precond, a, a, w.pw, s);
+            if (st != MCA_OK) return st;
+        }
+        int its = 0, restarts = 0;
+        bool converged = false, first = true, cycle_started = true;
+        for (;;) {
+            if (!cycle_started)
+                MCA_TRY(launch_cycle_init(w.ctl, w.g, R, beta, s, two_pass ? w.sig : nullptr));
+            cycle_started = false;
+            const int jmax = std::min(R, o->max_krylov - its);
+            const int j0 = std::min(enqueued, jmax);
+            enqueued = 0;
+            int last = j0 - 1, stopped_at = -1;
+            for (int j = j0; j < jmax; ++j) {
+                const mca_status st = step(j);
+                if (st != MCA_OK) return st;
+                last = j;
+                if (j > 0) {
+                    // step j runs on the GPU while the host reads step j-1's outcome
+                    // (step j-1's snapshot is written by its finish, which with the
+                    // finish merged runs in step j's first launch)
+                    const int *c = snap + kSnapInts * (j - 1);
+                    const mca_status ws = wait_marker(c + 4, epoch[j - 1], s);
+                    if (ws != MCA_OK) return ws;
+                    MCA_TRY(tm->collect((j - 1) & 1, c[1] == j));
+                    if (c[0]) {
+                        // the cycle stopped at step j - 1: step j, already enqueued,
+                        // returns at once (its timing slot is dropped); the update
+                        // below needs no further wait
+                        stopped_at = j - 1;
+                        break;
+                    }
+                }
+            }
+            if (fin_pending) {   // the last enqueued step's finish, alone
+                MCA_TRY(launch_gs_step(fin, 2, s));
+                fin_pending = false;
+            }
+            const int *c = nullptr;
+            if (stopped_at >= 0) {
+                c = snap + kSnapInts * stopped_at;
+                MCA_TRY(tm->collect(last & 1, false));
+            } else if (last >= 0) {
+                c = snap + kSnapInts * last;
+                const mca_status ws = wait_marker(c + 4, epoch[last], s);
+                if (ws != MCA_OK) return ws;
+                MCA_TRY(tm->collect(last & 1, c[1] == last + 1));
+            }
+            const int k = c ? c[1] : 0;
+            const int reason = c ? c[2] : CYCLE_RUNNING;
+            if (reason == CYCLE_NONFINITE) return MCA_ERR_NONFINITE;
+            its += k;
+            if (k > 0) {
+                MCA_TRY(launch_backsolve(w.H, ldh, w.g, w.ctl, w.coef, s, two_pass ? w.sig : nullptr));
+                // the number of completed steps is ctl[1]
+                MCA_TRY(launch_update(w.Z, len, w.coef, 0, w.ctl + 1, len, w.X, first ? 0 : 1, s));
+                first = false;
+            } else if (first) {
+                MCA_TRY(launch_fill(w.X, 0.0, len, s));
+                first = false;
+            }
+            converged = reason == CYCLE_CONVERGED;
+            if (converged || its >= o->max_krylov || reason == CYCLE_BREAKDOWN || k == 0) break;
+            // restart from the true residual  r = -F - J X
+            ++restarts;
+            MCA_TRY(tm->begin(MCA_KCLASS_JACOBIAN, s));
+            MCA_TRY(launch_jacobian(P, w.D, w.X, w.X + mn, w.tmp, w.tmp + mn, s));
+            MCA_TRY(tm->end(MCA_KCLASS_JACOBIAN, s, 1));
+            MCA_TRY(launch_neg_sum(w.F, w.tmp, w.V, len, s));
+            MCA_TRY(launch_dot_partials(w.V, w.V, len, w.pa, s));
+            MCA_TRY(launch_reduce(w.pa, reduce_blocks(len), 1, w.scal, s));
+            MCA_TRY(hipMemcpyAsync(host, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+            MCA_TRY(hipStreamSynchronize(s));
+            MCA_TRY(tm->collect());
+            beta = std::sqrt(host[0]);
+            if (!std::isfinite(beta)) return MCA_ERR_NONFINITE;
+            if (beta <= abs_tol) {
+                converged = true;
+                break;
+            }
+            MCA_TRY(launch_scale(w.V, 1.0 / beta, w.V, len, s));
+        }
+        *its_out = its;
+        *restarts_out = restarts;
+        *conv_out = converged;
+        return MCA_OK;
+    }
+};
+
+// Residual at (vt, vb) into F/D: residual_enqueue launches it and its reduction
+// into host words 0 and 1 (||F||^2, sum D) with a marker (host word 4 as ints);
+// residual_wait returns ||F||, ||F||^2 and sum D on the host once they are there.
+mca_status residual_enqueue(const mca_plan *P, const double *g_dev, const double *v_in,
+                            const double *vt, const double *vb, double *F, double *D,
+                            const SolveWs &w, hipStream_t s, Timing *tm, int *epoch)
 {
     const size_t mn = (size_t)P->geom.m * P->geom.n;
     double *host = pinned_scratch();
@@ -841,18 +923,35 @@ mca_status residual_norms(const mca_plan *P, const double *g_dev, const double *
     MCA_TRY(tm->begin(MCA_KCLASS_RESIDUAL, s));
     MCA_TRY(launch_residual(P, g_dev, v_in, vt, vb, F, F + mn, D, w.pa, s));
     MCA_TRY(tm->end(MCA_KCLASS_RESIDUAL, s, 1));
-    // the one-block reduction stores ||F||^2 and sum D straight into host memory,
-    // then its marker (host word 4 as ints)
-    int *mark = reinterpret_cast<int *>(host + 4), *mark_dev = reinterpret_cast<int *>(host_dev + 4);
-    const int e = next_epoch();
-    MCA_TRY(launch_reduce(w.pa, reduce_blocks(mn), 2, host_dev, s, mark_dev, e));
-    const mca_status ws = wait_marker(mark, e, s);
+    *epoch = next_epoch();
+    MCA_TRY(launch_reduce(w.pa, reduce_blocks(mn), 2, host_dev, s,
+                          reinterpret_cast<int *>(host_dev + 4), *epoch));
+    return MCA_OK;
+}
+
+mca_status residual_wait(int epoch, hipStream_t s, Timing *tm, double *fnorm, double *fnorm2,
+                         double *dsum)
+{
+    double *host = pinned_scratch();
+    const mca_status ws = wait_marker(reinterpret_cast<int *>(host + 4), epoch, s);
     if (ws != MCA_OK) return ws;
-    MCA_TRY(tm->collect());
+    MCA_TRY(tm->collect(0, true, MCA_KCLASS_RESIDUAL));
+    *fnorm2 = host[0];
     *fnorm = std::sqrt(host[0]);
     *dsum = host[1];
     if (!std::isfinite(*fnorm) || !std::isfinite(*dsum)) return MCA_ERR_NONFINITE;
     return MCA_OK;
+}
+
+mca_status residual_norms(const mca_plan *P, const double *g_dev, const double *v_in,
+                          const double *vt, const double *vb, double *F, double *D,
+                          const SolveWs &w, hipStream_t s, Timing *tm, double *fnorm,
+                          double *fnorm2, double *dsum)
+{
+    int e = 0;
+    const mca_status st = residual_enqueue(P, g_dev, v_in, vt, vb, F, D, w, s, tm, &e);
+    if (st != MCA_OK) return st;
+    return residual_wait(e, s, tm, fnorm, fnorm2, dsum);
 }
 
 // Workspace of mca_precond_apply_noalloc: one array per GPU, held by the code
@@ -1240,9 +1339,9 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     Timing tm;
     if (o.flags & (MCA_FLAG_TIMING | MCA_FLAG_TIMING_SAMPLED))
         MCA_TRY(tm.init(!(o.flags & MCA_FLAG_TIMING)));
-    double fnorm = 0.0, dsum = 0.0;
+    double fnorm = 0.0, fn2 = 0.0, dsum = 0.0;
     SolveWs wk = w;
-    st = residual_norms(P, g_dev, v_in, Vc, Vc + mn, F, D, wk, s, &tm, &fnorm, &dsum);
+    st = residual_norms(P, g_dev, v_in, Vc, Vc + mn, F, D, wk, s, &tm, &fnorm, &fn2, &dsum);
     if (st == MCA_ERR_HIP) return st;
     {
         const mca_status ws = wait_marker(reinterpret_cast<int *>(host + 6), e_y, s);
@@ -1261,7 +1360,7 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     if (from_guess && (o.flags & MCA_FLAG_GUESS_FALLBACK) && !(st == MCA_OK && fnorm < ynorm)) {
         // the guess is no better than V = 0, whose residual is ||Y||: start from 0
         MCA_TRY(launch_fill(Vc, 0.0, len, s));
-        st = residual_norms(P, g_dev, v_in, Vc, Vc + mn, F, D, wk, s, &tm, &fnorm, &dsum);
+        st = residual_norms(P, g_dev, v_in, Vc, Vc + mn, F, D, wk, s, &tm, &fnorm, &fn2, &dsum);
         if (st == MCA_ERR_HIP) return st;
         from_guess = 0;
     }
@@ -1269,9 +1368,17 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
     mca_status result = (st == MCA_OK) ? MCA_ERR_NOT_CONVERGED : st;
     int k = 0, total_its = 0, backtracks = 0, restarts = 0;
     double a = 0.0;
+    // Tests on squared norms, so that the host and a gated start enqueued ahead
+    // (launch_newton_next) decide alike on the same reduced sum.
+    const double conv = o.newton_tol * ynorm, conv2 = conv * conv;
+    const double *sums_dev = pinned_dev(host);   // the last residual's ||F||^2, sum D
+    // the next Newton step's GMRES, its start and first Arnoldi step enqueued
+    // behind the full-step trial point before the host has read that point's norm
+    std::unique_ptr<Fgmres> ahead;
+    const bool look_ahead = Fgmres(P, &o, wk, s, &tm).device_shift();
     for (; st == MCA_OK; ++k) {
         if (stats) stats->residual_history[k] = fnorm / ynorm;
-        if (fnorm <= o.newton_tol * ynorm) {
+        if (fn2 <= conv2) {
             result = MCA_OK;
             break;
         }
@@ -1279,9 +1386,16 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
         a = dsum / (double)mn;   // a1 = a2 = mean device slope (Section III-A)
         wk.F = F;
         wk.D = D;
+        std::unique_ptr<Fgmres> fg = std::move(ahead);
+        if (!fg) {
+            fg.reset(new Fgmres(P, &o, wk, s, &tm));
+            st = fg->start(sums_dev, INFINITY, -1.0);
+            if (st != MCA_OK) return st;
+        }
         int its = 0, rs = 0;
-        bool conv = false;
-        st = fgmres(P, &o, wk, fnorm, a, s, &tm, &its, &rs, &conv);
+        bool cv = false;
+        st = fg->run(fnorm, a, &its, &rs, &cv);
+        fg.reset();
         if (st != MCA_OK) {
             result = st;
             break;
@@ -1290,14 +1404,30 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
         restarts += rs;
         if (stats) stats->krylov_history[k] = its;
         // damped update: halve s while ||F(V + s X)|| > (1 - 1e-4 s) ||F(V)||
-        double step = 1.0, fn_new = 0.0, ds_new = 0.0;
+        double step = 1.0, fn_new = 0.0, fn2_new = 0.0, ds_new = 0.0;
         int halvings = 0;
         for (;;) {
             MCA_TRY(launch_axpby(Vc, step, w.X, Vn, len, s));
-            st = residual_norms(P, g_dev, v_in, Vn, Vn + mn, Fn, Dn, wk, s, &tm, &fn_new,
-                                &ds_new);
+            int e = 0;
+            st = residual_enqueue(P, g_dev, v_in, Vn, Vn + mn, Fn, Dn, wk, s, &tm, &e);
+            if (st != MCA_OK) return st;
+            const double thr = (1.0 - 1e-4 * step) * fnorm, accept2 = thr * thr;
+            if (look_ahead && step == 1.0 && k + 1 < o.max_newton) {
+                SolveWs wn = wk;
+                wn.F = Fn;
+                wn.D = Dn;
+                ahead.reset(new Fgmres(P, &o, wn, s, &tm));
+                st = ahead->start(sums_dev, accept2, conv2);
+                if (st == MCA_OK) st = ahead->prelaunch_first_step();
+                if (st != MCA_OK) return st;
+            }
+            st = residual_wait(e, s, &tm, &fn_new, &fn2_new, &ds_new);
             if (st != MCA_OK && st != MCA_ERR_NONFINITE) return st;
-            if (st == MCA_OK && fn_new <= (1.0 - 1e-4 * step) * fnorm) break;
+            if (st == MCA_OK && fn2_new <= accept2) break;
+            if (ahead) {   // (its kernels return at once: the device saw the rejection too)
+                if ((st = ahead->abandon()) != MCA_OK) return st;
+                ahead.reset();
+            }
             if (halvings >= 30) break;
             step *= 0.5;
             ++halvings;
@@ -1312,7 +1442,13 @@ mca_status mca_solve(const mca_plan *P, const double *g_dev, const double *v_in,
         std::swap(F, Fn);
         std::swap(D, Dn);
         fnorm = fn_new;
+        fn2 = fn2_new;
         dsum = ds_new;
+    }
+    if (ahead) {   // converged (the device saw it too) or out of steps: nothing to take
+        const mca_status sa = ahead->abandon();
+        if (sa != MCA_OK) return sa;
+        ahead.reset();
     }
     MCA_TRY(hipMemcpyAsync(v_t, Vc, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
     MCA_TRY(hipMemcpyAsync(v_b, Vc + mn, mn * sizeof(double), hipMemcpyDeviceToDevice, s));
