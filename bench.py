@@ -634,12 +634,13 @@ def main():
     # roofline of the dominant kernel: the FP64 eigenbasis GEMMs
     roofline = None
     if not args.no_timing and klaunch[B.MCA_KCLASS_GEMM] > 0 and form == B.MCA_PRECOND_APPROX:
-        # two PCR line-solve launches per application: columns read r_b and write z_b
-        # (16 B per crosspoint), rows read r_t, z_b and write z_t (24 B)
+        # two tridiagonal line-solve launches per application: columns read r_b and
+        # write z_b (16 B per crosspoint), rows read r_t, z_b and write z_t (24 B)
         bytes_per_launch = 20.0 * m * n
         avg_ms = kms[B.MCA_KCLASS_GEMM] / klaunch[B.MCA_KCLASS_GEMM]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": "k_pcr_solve (tridiagonal line solves)",
+        roofline = {"bound": "hbm", "kernel": "k_chunk_solve (tridiagonal line solves, chunked Thomas; "
+                              "cyclic reduction past 2048 elements per line)",
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "avg_launch_us": round(avg_ms * 1e3, 2),

@@ -199,22 +199,31 @@ hipError_t launch_precond_lowprec_grouped(int precision, const GroupedChain &c, 
 void split_host(const double *src, size_t count, int precision, void *p0, void *p1);
 
 // The paper's approximate preconditioner (tridiag.hip): batched tridiagonal
-// solves with (wire + shift I) by parallel cyclic reduction.  PcrTables holds
-// one shifted wire's multipliers; lines of up to kPcrMaxLen elements.
-constexpr int kPcrMaxLen = 8192;
-struct PcrTables {
-    int len, levels;
-    double *alpha, *gamma, *invb;   // levels x len, levels x len, len
-    double *work;                   // 6 x len set-up scratch
+// solves with (wire + shift I), every line of a launch with the same matrix.
+// TridiagTables holds one shifted wire's factorisation: chunked Thomas tables
+// (P > 0, lines of up to kChunkMaxLen elements) or parallel cyclic reduction
+// multipliers (longer lines, up to kTridiagMaxLen).
+constexpr int kTridiagMaxLen = 8192;
+constexpr int kChunkMaxLen = 2048;
+struct TridiagTables {
+    int len, levels, K, P;          // chunked: K elements per chunk, P chunks
+    double g;                       // the wire's coupling
+    double *q;                      // chunked: inverse pivots, K x P
+    double *alpha, *gamma, *invb;   // PCR: levels x len, levels x len, len
+    double *work;                   // PCR: 6 x len set-up scratch
 };
-size_t pcr_table_doubles(int len);
-PcrTables pcr_carve(double *base, int len);
-hipError_t launch_pcr_setup(const Wire &w, double shift, const PcrTables &t, hipStream_t s);
+size_t tridiag_table_doubles(int len);
+TridiagTables tridiag_carve(double *base, int len, double g);
+hipError_t launch_tridiag_setup(const Wire &w, double shift, const TridiagTables &t, hipStream_t s);
+// both wires' set-ups (one launch when both are chunked)
+hipError_t launch_tridiag_setup2(const Wire &w1, double shift1, const TridiagTables &t1,
+                                 const Wire &w2, double shift2, const TridiagTables &t2,
+                                 hipStream_t s);
 // out = T^{-1} (in + in2_scale * in2) along `lines` lines; rows: lines are
 // contiguous (elem_stride 1), else consecutive lines are adjacent (line_stride 1)
-hipError_t launch_pcr_solve(const PcrTables &t, int lines, bool rows, size_t line_stride,
-                            size_t elem_stride, const double *in, const double *in2,
-                            double in2_scale, double *out, const int *skip, hipStream_t s);
+hipError_t launch_tridiag_solve(const TridiagTables &t, int lines, bool rows, size_t line_stride,
+                                size_t elem_stride, const double *in, const double *in2,
+                                double in2_scale, double *out, const int *skip, hipStream_t s);
 // One block Gauss-Seidel sweep on the linearisation at V = 0 (a start for
 // Newton's method): V_t = (G_t + D)^{-1} Y_t, V_b = (G_b + D)^{-1} D V_t with
 // D = g_dev, by per-wire tridiagonal solves (lines of up to kSweepMaxLen).

@@ -93,7 +93,7 @@ mca_status validate_options(const mca_options *o)
 }
 
 // The approximate form holds whole wires in LDS.
-bool approx_fits(const mca_plan *P) { return P->geom.m <= kPcrMaxLen && P->geom.n <= kPcrMaxLen; }
+bool approx_fits(const mca_plan *P) { return P->geom.m <= kTridiagMaxLen && P->geom.n <= kTridiagMaxLen; }
 
 // Wire matrix of eq. (G) with the two end terminations (see mca.h).
 Wire make_wire(int len, double g, double end0, double end1) { return Wire{g, end0, end1, len}; }
@@ -162,7 +162,7 @@ PlanLayout plan_layout(const mca_plan *P, void *base)
 struct PrecondWs {
     double *b0t, *b0b, *b1t, *b1b;
     LpPlanes lp[6];
-    PcrTables g1, g2;   // approximate form: G_top + a1 I (len n), G_bot + a2 I (len m)
+    TridiagTables g1, g2;   // approximate form: G_top + a1 I (len n), G_bot + a2 I (len m)
 };
 
 PrecondWs precond_layout(const mca_plan *P, Carver &c, int form, int precision = MCA_PREC_FP64)
@@ -177,8 +177,8 @@ PrecondWs precond_layout(const mca_plan *P, Carver &c, int form, int precision =
         return w;
     }
     if (form == MCA_PRECOND_APPROX) {
-        w.g1 = pcr_carve(c.take<double>(pcr_table_doubles(P->geom.n)), P->geom.n);
-        w.g2 = pcr_carve(c.take<double>(pcr_table_doubles(P->geom.m)), P->geom.m);
+        w.g1 = tridiag_carve(c.take<double>(tridiag_table_doubles(P->geom.n)), P->geom.n, P->top.g);
+        w.g2 = tridiag_carve(c.take<double>(tridiag_table_doubles(P->geom.m)), P->geom.m, P->bot.g);
         return w;
     }
     if (precision != MCA_PREC_FP64) {
@@ -435,14 +435,13 @@ struct Timing {
 };
 
 // z = P^{-1} r (eq. (P)) in the chosen evaluation form.
-// Per-shift set-up of the approximate form (the PCR multipliers of
+// Per-shift set-up of the approximate form (the factorisations of
 // G_top + a1 I and G_bot + a2 I); nothing for the other forms.
 mca_status precond_setup(const mca_plan *P, int form, double a1, double a2, const PrecondWs &w,
                          hipStream_t s)
 {
     if (form != MCA_PRECOND_APPROX) return MCA_OK;
-    MCA_TRY(launch_pcr_setup(P->top, a1, w.g1, s));
-    MCA_TRY(launch_pcr_setup(P->bot, a2, w.g2, s));
+    MCA_TRY(launch_tridiag_setup2(P->top, a1, w.g1, P->bot, a2, w.g2, s));
     return MCA_OK;
 }
 
@@ -471,8 +470,8 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
         // z_t = (G_t + a1 I)^{-1} (r_t + a1 z_b) along the rows
         const int m = P->geom.m, n = P->geom.n;
         MCA_TRY(tm->begin(MCA_KCLASS_GEMM, s, slot));
-        MCA_TRY(launch_pcr_solve(w.g2, n, false, 1, (size_t)n, rb, nullptr, 0.0, zb, skip, s));
-        MCA_TRY(launch_pcr_solve(w.g1, m, true, (size_t)n, 1, rt, zb, a1, zt, skip, s));
+        MCA_TRY(launch_tridiag_solve(w.g2, n, false, 1, (size_t)n, rb, nullptr, 0.0, zb, skip, s));
+        MCA_TRY(launch_tridiag_solve(w.g1, m, true, (size_t)n, 1, rt, zb, a1, zt, skip, s));
         MCA_TRY(tm->end(MCA_KCLASS_GEMM, s, 2, slot));
         return MCA_OK;
     }

@@ -160,14 +160,17 @@ def test_precond_inverts_P_at_1024(m, n, form):
     assert err <= (1e-9 if form == B.MCA_PRECOND_PERMODE else 1e-5)
 
 
-APPROX_SHAPES = SHAPES + [(300, 77), (40, 3000), (3, 8192), (8192, 3)]
+# line lengths across the solver's forms: chunks of 8 (up to 1024), chunks of
+# 16 (up to 2048, ragged last chunk), cyclic reduction (longer)
+APPROX_SHAPES = SHAPES + [(300, 77), (40, 3000), (3, 8192), (8192, 3), (1500, 37), (20, 1100),
+                          (2048, 6), (1024, 9)]
 
 
 @pytest.mark.parametrize("m,n", APPROX_SHAPES)
 @pytest.mark.parametrize("a1,a2", [(2.2e-5, 2.2e-5), (3e-4, 4e-5)])
 def test_precond_approx_parity(m, n, a1, a2):
-    """The paper's approximation M ~ Mhat: GPU block back-substitution by PCR
-    against the oracle's literal order (eq. (block) with Mhat^{-1} by eq. (2matrix4))."""
+    """The paper's approximation M ~ Mhat: GPU block back-substitution by line
+    solves against the oracle's literal order (eq. (block) with Mhat^{-1} by eq. (2matrix4))."""
     say(f"precond approx {m}x{n} a=({a1},{a2})")
     geom = synth.Geometry(m, n)
     rt, rb = synth.vector(m, n, seed=m * 7 + n)
