@@ -453,6 +453,57 @@ def leg_mixed_2048(args, dev, size=2048, reps=3):
     return out
 
 
+def leg_approx(args, dev, size=1024, reps=10):
+    """The paper's own approximation of the preconditioner (M ~ Mhat, eq. (Mhat):
+    tridiagonal line solves instead of the eigenbasis transforms) inside the
+    same FP64 Newton-FGMRES on the metric's crossbar: time per solve (HIP events,
+    `reps` solves after one warm-up), iterations, and the largest relative
+    voltage difference from the exact-preconditioner (FP64 literal) solve."""
+    import torch
+
+    from paper_2109_07929_amd import Plan, synth
+    from paper_2109_07929_amd import binding as B
+
+    cb = synth.crossbar(size, size, seed=args.seed)
+    plan = Plan(cb.geom, device=dev)
+    g = torch.from_numpy(cb.g_dev).to(dev)
+    v = torch.from_numpy(cb.v_in).to(dev)
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"{size}x{size} crossbar ({2 * size * size} unknowns), seed {args.seed}",
+           "forms": {}}
+    ref = None
+    for name, form in (("exact (literal)", B.MCA_PRECOND_LITERAL), ("approx (Mhat)", B.MCA_PRECOND_APPROX)):
+        o = B.options(precond=form, precision=B.MCA_PREC_FP64)
+        ws = plan.workspace(o)
+        vt = torch.zeros((size, size), dtype=torch.float64, device=dev)
+        vb = torch.zeros_like(vt)
+        status, st = B.mca_solve(plan.handle, size, size, g, v, vt, vb, o, ws, stream, check=False)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            status, st = B.mca_solve(plan.handle, size, size, g, v, vt, vb, o, ws, stream,
+                                     check=False)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        rec = {"ms_per_solve": round(ms, 3), "solves_per_s": round(1e3 / ms, 2),
+               "status": B.status_string(status), "newton_iters": st.newton_iters,
+               "krylov_history": list(st.krylov_history[:st.newton_iters]),
+               "rel_residual": st.rel_residual}
+        if ref is None:
+            ref = (vt.clone(), vb.clone(), ms)
+        else:
+            scale = float(torch.maximum(ref[0].abs().max(), ref[1].abs().max()))
+            dv = float(torch.maximum((vt - ref[0]).abs().max(), (vb - ref[1]).abs().max()))
+            rec["max_rel_dv_vs_exact"] = dv / scale
+            rec["speedup_vs_exact"] = round(ref[2] / ms, 3)
+        out["forms"][name] = rec
+        print(f"# {size}^2 {name}: {ms:.2f} ms per solve", file=sys.stderr, flush=True)
+        del ws
+    return out
+
+
 def leg_monte_carlo(args, dev, count=256):
     """The Monte-Carlo workload: `count` crossbars with m, n drawn from
     {64, ..., 512} (seed args.seed), split-BF16 per-mode preconditioner, solved
@@ -736,6 +787,8 @@ def main():
         del cmp
         torch.cuda.empty_cache()
     if not args.no_extra_configs and m == 1024:
+        out["approx_preconditioner_1024"] = leg_approx(args, dev)
+        torch.cuda.empty_cache()
         out["mixed_precision_2048"] = leg_mixed_2048(args, dev)
         torch.cuda.empty_cache()
         out["monte_carlo_256"] = leg_monte_carlo(args, dev)
