@@ -216,6 +216,36 @@ __device__ __forceinline__ void put(const LpArgs &a, int b, size_t o, T v, int o
     }
 }
 
+// Four consecutive outputs from offset o (o a multiple of 4, the plane
+// 16-byte aligned): one 8-, 16- or two 16-byte stores per plane.  The values
+// are rounded as put() rounds them one by one.
+__device__ __forceinline__ bool aligned_out(const void *p)
+{
+    return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+__device__ __forceinline__ void put4(const LpArgs &a, int b, size_t o, const double (&v)[4], int out)
+{
+    if (out == OUT_F64) {
+        double2 *d = reinterpret_cast<double2 *>(static_cast<double *>(a.O[b][0]) + o);
+        d[0] = double2{v[0], v[1]};
+        d[1] = double2{v[2], v[3]};
+    } else if (out == OUT_F32) {
+        *reinterpret_cast<float4 *>(static_cast<float *>(a.O[b][0]) + o) =
+            float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    } else {
+        typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+        bf4 hi, lo;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float f = (float)v[r];
+            hi[r] = (__bf16)f;
+            lo[r] = (__bf16)(f - (float)hi[r]);
+        }
+        *reinterpret_cast<bf4 *>(static_cast<__bf16 *>(a.O[b][0]) + o) = hi;
+        if (out == OUT_BF2) *reinterpret_cast<bf4 *>(static_cast<__bf16 *>(a.O[b][1]) + o) = lo;
+    }
+}
+
 constexpr int DEPTH = 2;   // K slices in flight (deeper rings measured no faster)
 
 // One TS x TS output tile at (m0, n0) of O = A B^T: four waves of (TS/2)^2 or
@@ -281,7 +311,10 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 
     // the MFMAs of one k step of split-BF16 / BF16 fragments: lo.hi and hi.lo
     // first, then hi.hi, each over every accumulator (no two MFMAs in a row
-    // share an accumulator)
+    // share an accumulator).  Every MFMA takes the B fragment as its first
+    // operand, so it forms the transposed 16 x 16 block: lane l then holds
+    // row l % 16 and the four consecutive columns 4 (l / 16) .. + 3 of the
+    // output, which the epilogue stores as one vector per plane.
     auto mfma_bf16 = [&](const bf8 (&fa)[NA][PL][FI], const bf8 (&fb)[NBB][PL][FJ]) {
         if constexpr (MODE == MCA_PREC_BF16X3) {
 #pragma unroll
@@ -291,7 +324,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 #pragma unroll
                     for (int j = 0; j < FJ; ++j)
                         acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            fa[A_BATCHED ? b : 0][1][i], fb[A_BATCHED ? 0 : b][0][j], acc[b][i][j], 0, 0, 0);
+                            fb[A_BATCHED ? 0 : b][0][j], fa[A_BATCHED ? b : 0][1][i], acc[b][i][j], 0, 0, 0);
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -299,7 +332,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 #pragma unroll
                     for (int j = 0; j < FJ; ++j)
                         acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            fa[A_BATCHED ? b : 0][0][i], fb[A_BATCHED ? 0 : b][PL - 1][j], acc[b][i][j], 0, 0, 0);
+                            fb[A_BATCHED ? 0 : b][PL - 1][j], fa[A_BATCHED ? b : 0][0][i], acc[b][i][j], 0, 0, 0);
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -308,7 +341,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 #pragma unroll
                 for (int j = 0; j < FJ; ++j)
                     acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        fa[A_BATCHED ? b : 0][0][i], fb[A_BATCHED ? 0 : b][0][j], acc[b][i][j], 0, 0, 0);
+                        fb[A_BATCHED ? 0 : b][0][j], fa[A_BATCHED ? b : 0][0][i], acc[b][i][j], 0, 0, 0);
     };
     auto read_bf16 = [&](int buf, int s, bf8 (&fa)[NA][PL][FI], bf8 (&fb)[NBB][PL][FJ]) {
 #pragma unroll
@@ -345,7 +378,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 #pragma unroll
                         for (int j = 0; j < FJ; ++j)
                             acc[b][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                fa[A_BATCHED ? b : 0][i], fb[A_BATCHED ? 0 : b][j], acc[b][i][j], 0, 0, 0);
+                                fb[A_BATCHED ? 0 : b][j], fa[A_BATCHED ? b : 0][i], acc[b][i][j], 0, 0, 0);
             }
         } else {
 #pragma unroll
@@ -489,29 +522,60 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
         }
     }
 
-    // accumulator element r of lane l: row 4 (l/16) + r, column l%16
+    // accumulator element r of lane l: row l % 16, column 4 (l / 16) + r (the
+    // transposed block, see above).  Four consecutive outputs go out as one
+    // vector store per plane where the row holds them and the planes allow it.
+    bool ovec = (N % 4 == 0);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl) ovec = ovec && aligned_out(a.O[b][pl]);
 #pragma unroll
     for (int i = 0; i < FI; ++i)
 #pragma unroll
-        for (int j = 0; j < FJ; ++j)
+        for (int j = 0; j < FJ; ++j) {
+            const int row = m0 + wm + i * 16 + (lane & 15);
+            const int col0 = n0 + wn + j * 16 + (lane >> 4) * 4;
+            if (row >= M || col0 >= N) continue;
+            const size_t o = (size_t)row * N + col0;
+            const bool whole = ovec && col0 + 4 <= N;
+            if constexpr (EPI == EPI_PERMODE) {
+                // mode (p, q) = (col, row): [[lt + a1, -a1], [-a2, lb + a2]] x = r
+                const double lt = global_ptr(a.lam_row)[row];
+                double x0[4], x1[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
-                const int col = n0 + wn + j * 16 + (lane & 15);
-                if (row >= M || col >= N) continue;
-                const size_t o = (size_t)row * N + col;
-                if constexpr (EPI == EPI_PERMODE) {
-                    // mode (p, q) = (col, row): [[lt + a1, -a1], [-a2, lb + a2]] x = r
-                    const double lt = global_ptr(a.lam_row)[row], lb = global_ptr(a.lam_col)[col];
+                for (int r = 0; r < 4; ++r) {
+                    const double lb = global_ptr(a.lam_col)[min(col0 + r, N - 1)];
                     const double det = lt * lb + a.a2 * lt + a.a1 * lb;
                     const double rt = acc[0][i][j][r], rb = acc[NB - 1][i][j][r];
-                    put(a, 0, o, ((lb + a.a2) * rt + a.a1 * rb) / det, OUT);
-                    put(a, 1, o, (a.a2 * rt + (lt + a.a1) * rb) / det, OUT);
+                    x0[r] = ((lb + a.a2) * rt + a.a1 * rb) / det;
+                    x1[r] = (a.a2 * rt + (lt + a.a1) * rb) / det;
+                }
+                if (whole) {
+                    put4(a, 0, o, x0, OUT);
+                    put4(a, 1, o, x1, OUT);
                 } else {
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) put(a, b, o, acc[b][i][j][r], OUT);
+                    for (int r = 0; r < 4; ++r)
+                        if (col0 + r < N) {
+                            put(a, 0, o + r, x0[r], OUT);
+                            put(a, 1, o + r, x1[r], OUT);
+                        }
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (whole) {
+                        const double x[4] = {acc[b][i][j][0], acc[b][i][j][1], acc[b][i][j][2], acc[b][i][j][3]};
+                        put4(a, b, o, x, OUT);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (col0 + r < N) put(a, b, o + r, acc[b][i][j][r], OUT);
+                    }
                 }
             }
+        }
 }
 
 // XCD-aware order: every XCD owns a contiguous run of workgroup ids.
