@@ -959,6 +959,7 @@ struct mca_batch {
     std::vector<int> pidx;                  // plan of each crossbar
     std::vector<long long> ox, orow;        // offsets (count + 1 entries)
     std::vector<int2> btab;                 // block table
+    std::vector<int2> ftab;                 // (crossbar, chunk) of the folded crossbars' row folds
     std::vector<mca::BInst> inst;
     size_t len = 0;                         // sum 2 m n
     size_t dev_bytes = 0;
@@ -966,6 +967,7 @@ struct mca_batch {
     // device pointers (inside dev_buf)
     mca::BInst *d_inst = nullptr;
     int2 *d_btab = nullptr;
+    int2 *d_ftab = nullptr;
     mca::LpDesc *d_desc[2][4] = {};         // [fp32 | bf16][step]
     int4 *d_tiles[4] = {};
     int ntiles[4] = {};
@@ -1001,6 +1003,7 @@ struct BCarver {
 struct BatchLayout {
     BInst *inst;
     int2 *btab;
+    int2 *ftab;
     LpDesc *desc[2][4];
     int4 *tiles[4];
     std::vector<float *> q32[4];                  // per plan: QnT, QmT, Qm, Qn
@@ -1008,6 +1011,11 @@ struct BatchLayout {
     std::vector<double *> lt, lb;
     size_t bytes;
 };
+
+// A crossbar's reduced-precision chain is folded (its Q_m-side products at half
+// depth, see the single-crossbar chain) when its G_bot is persymmetric and each
+// half is a whole number of the batch's product tiles.
+bool plan_fold(const mca_plan *P, int tile) { return P->persym && (P->geom.m / 2) % tile == 0; }
 
 // Tile edge of a batch's grouped products: 128 (four times the operand reuse)
 // when every crossbar's sides are at least 256 and the batch still gives 256 or
@@ -1029,6 +1037,7 @@ BatchLayout batch_layout(const mca_batch *B, void *base)
     const size_t cnt = B->geoms.size();
     L.inst = c.take<BInst>(cnt);
     L.btab = c.take<int2>(B->btab.size());
+    L.ftab = c.take<int2>(std::max<size_t>(1, B->ftab.size()));
     for (auto &p : L.desc)
         for (auto &d : p) d = c.take<LpDesc>(cnt);
     for (int s = 0; s < 4; ++s) L.tiles[s] = c.take<int4>(B->ntiles[s]);
@@ -1225,6 +1234,12 @@ mca_status mca_batch_create(int32_t count, const mca_geometry *geoms, mca_batch 
         }
         B->ntiles[s] = t;
     }
+    // the folded crossbars' row folds, in chunks of kFoldChunk (m/2) x n elements
+    for (int b = 0; b < count; ++b)
+        if (plan_fold(B->plans[B->pidx[b]], T)) {
+            const size_t half = (size_t)geoms[b].m / 2 * geoms[b].n;
+            for (size_t c = 0; c * kFoldChunk < half; ++c) B->ftab.push_back(int2{b, (int)c});
+        }
     B->dev_bytes = batch_layout(B, nullptr).bytes;
     *out = B;
     return MCA_OK;
@@ -1265,6 +1280,7 @@ mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *str
     BatchLayout D = batch_layout(B, dev_buf);      // device addresses
     std::memcpy(H.inst, B->inst.data(), cnt * sizeof(BInst));
     std::memcpy(H.btab, B->btab.data(), B->btab.size() * sizeof(int2));
+    if (!B->ftab.empty()) std::memcpy(H.ftab, B->ftab.data(), B->ftab.size() * sizeof(int2));
     // every plan's operand planes, spread over host threads (disjoint parts of the image)
     const size_t np = B->plans.size();
     auto convert = [&](size_t first, size_t stride) {
@@ -1272,19 +1288,39 @@ mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *str
         for (size_t u = first; u < np; u += stride) {
             const mca_plan *P = B->plans[u];
             const size_t m = P->geom.m, n = P->geom.n;
-            // QnT, QmT, Qm, Qn in FP64 from the host eigenvectors
+            // QnT, QmT, Qm, Qn in FP64 from the host eigenvectors; a folded
+            // chain's QmT and Qm are [U_s^T; U_a^T] and [U_s; U_a] (m x m/2) and
+            // its eigenvalues of G_bot run symmetric modes first
+            const bool fold = plan_fold(P, B->tile);
+            const size_t h = m / 2;
             for (int q = 0; q < 4; ++q) {
                 const size_t L = (q == 0 || q == 3) ? n : m;
                 const std::vector<double> &src = (q == 0 || q == 3) ? P->Qn : P->Qm;
                 const bool tr = (q == 0 || q == 1);
+                size_t cnt = L * L;
                 tmp.resize(L * L);
-                for (size_t i = 0; i < L; ++i)
-                    for (size_t j = 0; j < L; ++j) tmp[i * L + j] = tr ? src[j * L + i] : src[i * L + j];
-                split_host(tmp.data(), L * L, MCA_PREC_FP32, H.q32[q][u], nullptr);
-                split_host(tmp.data(), L * L, MCA_PREC_BF16X3, H.qh[q][u], H.ql[q][u]);
+                if (fold && (q == 1 || q == 2)) {
+                    cnt = m * h;
+                    for (int part = 0; part < 2; ++part) {
+                        const std::vector<double> &U = part ? P->Ua : P->Us;
+                        for (size_t i = 0; i < h; ++i)
+                            for (size_t k = 0; k < h; ++k)
+                                tmp[(part * h + i) * h + k] = (q == 1) ? U[k * h + i] : U[i * h + k];
+                    }
+                } else {
+                    for (size_t i = 0; i < L; ++i)
+                        for (size_t j = 0; j < L; ++j) tmp[i * L + j] = tr ? src[j * L + i] : src[i * L + j];
+                }
+                split_host(tmp.data(), cnt, MCA_PREC_FP32, H.q32[q][u], nullptr);
+                split_host(tmp.data(), cnt, MCA_PREC_BF16X3, H.qh[q][u], H.ql[q][u]);
             }
             std::memcpy(H.lt[u], P->lt.data(), n * sizeof(double));
-            std::memcpy(H.lb[u], P->lb.data(), m * sizeof(double));
+            if (fold) {
+                std::memcpy(H.lb[u], P->ls.data(), h * sizeof(double));
+                std::memcpy(H.lb[u] + h, P->la.data(), h * sizeof(double));
+            } else {
+                std::memcpy(H.lb[u], P->lb.data(), m * sizeof(double));
+            }
         }
     };
     {
@@ -1323,8 +1359,25 @@ mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *str
                 d.mn = m * n;
                 d.lam_row = (st < 2) ? D.lt[u] : nullptr;
                 d.lam_col = (st < 2) ? D.lb[u] : nullptr;
+                if (plan_fold(B->plans[u], B->tile)) {
+                    const int h = (int)m / 2;
+                    if (st == 0) d.alt = 1;   // reads the folded rows
+                    if (st == 1) {            // symmetric / antisymmetric modes from the two halves
+                        d.K = h;
+                        d.lda = (int)m;
+                        d.split = 1;
+                    }
+                    if (st == 2) {            // rows of both halves, interleaved by 16
+                        d.K = h;
+                        d.ldb = (int)m;
+                        d.split = 2;
+                        d.ileave = 1;
+                    }
+                    if (st == 3) d.unfold = 1;
+                }
                 // data rows are m*n-offset slices: aligned when 2 ox and mn are multiples of 8
-                d.vec = (d.K % 8 == 0) && ((2 * (size_t)B->ox[b]) % 8 == 0) && (d.mn % 8 == 0);
+                d.vec = (d.K % 8 == 0) && (d.lda % 8 == 0) && (d.ldb % 8 == 0) &&
+                        ((2 * (size_t)B->ox[b]) % 8 == 0) && (d.mn % 8 == 0);
                 H.desc[f][st][b] = d;
             }
     }
@@ -1342,6 +1395,7 @@ mca_status mca_batch_upload(mca_batch *B, void *dev_buf, size_t bytes, void *str
     B->dev_buf = dev_buf;
     B->d_inst = D.inst;
     B->d_btab = D.btab;
+    B->d_ftab = D.ftab;
     for (int f = 0; f < 2; ++f)
         for (int st = 0; st < 4; ++st) B->d_desc[f][st] = D.desc[f][st];
     for (int st = 0; st < 4; ++st) B->d_tiles[st] = D.tiles[st];
@@ -1434,6 +1488,8 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     }
     gc.len = len;
     gc.tile = B->tile;
+    gc.fold_tab = B->d_ftab;
+    gc.fold_blocks = (int)B->ftab.size();
     gc.x = w.x;
     gc.u = w.u;
     gc.w = w.w;

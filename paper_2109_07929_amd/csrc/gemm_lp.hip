@@ -122,15 +122,15 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T *global_ptr
 }
 
 template <int MODE, int ROWS, int KS, int NT>
-__device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int r0, int k0,
-                                        bool fast, Regs<MODE, ROWS, KS, NT> &g)
+__device__ __forceinline__ void load_op(const Operand &op, int rows, int K, size_t ld, int koff, int r0,
+                                        int k0, bool fast, Regs<MODE, ROWS, KS, NT> &g)
 {
     constexpr int PC = Fmt<MODE>::kPerChunk;
     constexpr int CPT = chunks_per_thread<MODE, ROWS, KS, NT>();
     using E = typename Fmt<MODE>::elem;
 #pragma unroll
     for (int pl = 0; pl < Fmt<MODE>::kPlanes; ++pl) {
-        const auto *base = global_ptr(static_cast<const E *>(op.p[pl]));
+        const auto *base = global_ptr(static_cast<const E *>(op.p[pl])) + koff;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             int rr, cc, li;
@@ -138,7 +138,7 @@ __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int 
             const int r = r0 + rr, k = k0 + cc * PC;
             if (fast) {
                 g.c[pl][c] = *reinterpret_cast<const __attribute__((address_space(1))) u4 *>(
-                    base + (size_t)r * K + k);
+                    base + (size_t)r * ld + k);
             } else {
                 // clamped element loads; out-of-range elements become zero
                 union {
@@ -148,7 +148,7 @@ __device__ __forceinline__ void load_op(const Operand &op, int rows, int K, int 
                 const size_t rc = (size_t)min(r, rows - 1);
 #pragma unroll
                 for (int e = 0; e < PC; ++e) {
-                    const E x = base[rc * K + min(k + e, K - 1)];
+                    const E x = base[rc * ld + min(k + e, K - 1)];
                     u.e[e] = (r < rows && k + e < K) ? x : (E)0.0f;
                 }
                 g.c[pl][c] = u.v;
@@ -199,6 +199,13 @@ struct LpArgs {
     double a1, a2;
     int vec;                           // all operands 16-byte aligned with K % 8 == 0
     const int *skip;
+    // Persymmetric fold (see chain below).  lda, ldb: row strides of A and B
+    // (0: K).  split 1: tiles of output columns >= N / 2 read A from K on
+    // (A's second half along K); split 2: tiles of output rows >= M / 2 read B
+    // from K on.  ileave: output row r of the first half goes to row
+    // 32 (r / 16) + r % 16, of the second half to that + 16.
+    int lda, ldb, split, ileave;
+    int unfold;   // as EPI_UNFOLD16, chosen at run time (grouped launches)
 };
 
 template <typename T>
@@ -274,6 +281,9 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
     const int gm = wm / 16, gn = wn / 16;   // first 16-row group of the wave's A / B rows
     const bool fast_m = a.vec && (m0 + TS <= M);
     const bool fast_n = a.vec && (n0 + TS <= N);
+    const size_t lda = a.lda ? a.lda : K, ldb = a.ldb ? a.ldb : K;
+    const int koa = (a.split == 1 && n0 >= N / 2) ? K : 0;
+    const int kob = (a.split == 2 && m0 >= M / 2) ? K : 0;
 
     struct Stage {
         RegsT ra[NA], rb[NBB];
@@ -282,17 +292,17 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
         const bool kin = k0 + KS <= K;
 #pragma unroll
         for (int b = 0; b < NA; ++b)
-            load_op<MODE, TS, KS, NT>(a.A[b], M, K, m0, k0, fast_m && kin, st.ra[b]);
+            load_op<MODE, TS, KS, NT>(a.A[b], M, K, lda, koa, m0, k0, fast_m && kin, st.ra[b]);
 #pragma unroll
         for (int b = 0; b < NBB; ++b)
-            load_op<MODE, TS, KS, NT>(a.B[b], N, K, n0, k0, fast_n && kin, st.rb[b]);
+            load_op<MODE, TS, KS, NT>(a.B[b], N, K, ldb, kob, n0, k0, fast_n && kin, st.rb[b]);
     };
     // interior tiles with K a whole number of slices: unconditional 16-byte loads
     auto load_fast = [&](Stage &st, int k0) {
 #pragma unroll
-        for (int b = 0; b < NA; ++b) load_op<MODE, TS, KS, NT>(a.A[b], M, K, m0, k0, true, st.ra[b]);
+        for (int b = 0; b < NA; ++b) load_op<MODE, TS, KS, NT>(a.A[b], M, K, lda, koa, m0, k0, true, st.ra[b]);
 #pragma unroll
-        for (int b = 0; b < NBB; ++b) load_op<MODE, TS, KS, NT>(a.B[b], N, K, n0, k0, true, st.rb[b]);
+        for (int b = 0; b < NBB; ++b) load_op<MODE, TS, KS, NT>(a.B[b], N, K, ldb, kob, n0, k0, true, st.rb[b]);
     };
     auto stash = [&](const Stage &st, int buf) {
 #pragma unroll
@@ -431,7 +441,8 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
                 for (int u = 0; u < NBB; ++u)
                     if (t == NA + u) base = pl ? a.B[u].p[PL - 1] : a.B[u].p[0];
                 const int r0 = t < NA ? m0 : n0;
-                src[q] = static_cast<const __bf16 *>(base) + (size_t)(r0 + r) * K + c * 8;
+                src[q] = static_cast<const __bf16 *>(base) + (t < NA ? koa : kob) +
+                         (size_t)(r0 + r) * (t < NA ? lda : ldb) + c * 8;
                 dst_t[q] = t;
                 dst_off[q] = pl * 8192 + rb * 1024;
             }
@@ -530,6 +541,45 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int pl = 0; pl < 2; ++pl) ovec = ovec && aligned_out(a.O[b][pl]);
+    if (EPI == EPI_UNFOLD16 || a.unfold) {
+        // rows of A come in 16-row groups, alternately of the symmetric and the
+        // antisymmetric half (the interleave of the product that made A): the
+        // lane's rows in MFMA blocks 2t and 2t + 1 are row p of both halves,
+        // and the output rows are p (sum) and M - 1 - p (difference)
+        static_assert(FI % 2 == 0, "pairs of 16-row blocks");
+#pragma unroll
+        for (int t = 0; t < FI / 2; ++t)
+#pragma unroll
+            for (int j = 0; j < FJ; ++j) {
+                const int p = (m0 + wm + 32 * t) / 2 + (lane & 15);
+                const int col0 = n0 + wn + j * 16 + (lane >> 4) * 4;
+                if (2 * p >= M || col0 >= N) continue;
+                const size_t o0 = (size_t)p * N + col0, o1 = (size_t)(M - 1 - p) * N + col0;
+                const bool whole = ovec && col0 + 4 <= N;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    double x0[4], x1[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double sym = acc[b][2 * t][j][r], anti = acc[b][2 * t + 1][j][r];
+                        x0[r] = sym + anti;
+                        x1[r] = sym - anti;
+                    }
+                    if (whole) {
+                        put4(a, b, o0, x0, OUT);
+                        put4(a, b, o1, x1, OUT);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (col0 + r < N) {
+                                put(a, b, o0 + r, x0[r], OUT);
+                                put(a, b, o1 + r, x1[r], OUT);
+                            }
+                    }
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < FI; ++i)
 #pragma unroll
@@ -537,7 +587,12 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
             const int row = m0 + wm + i * 16 + (lane & 15);
             const int col0 = n0 + wn + j * 16 + (lane >> 4) * 4;
             if (row >= M || col0 >= N) continue;
-            const size_t o = (size_t)row * N + col0;
+            int orow = row;
+            if (a.ileave) {
+                const int hh = M / 2, q = row < hh ? row : row - hh;
+                orow = 32 * (q / 16) + q % 16 + (row < hh ? 0 : 16);
+            }
+            const size_t o = (size_t)orow * N + col0;
             const bool whole = ovec && col0 + 4 <= N;
             if constexpr (EPI == EPI_PERMODE) {
                 // mode (p, q) = (col, row): [[lt + a1, -a1], [-a2, lb + a2]] x = r
@@ -609,11 +664,12 @@ __global__ __launch_bounds__((lp_threads<TS, KS>())) void k_gemm_nt_lp_grouped(G
     a.N = d.N;
     a.K = d.K;
     const size_t es = g.data_elem_bytes, os = g.out_elem_bytes;
+    const void *const *dbase = d.alt ? g.data_alt : g.data;
     for (int b = 0; b < 2; ++b) {
         Operand data;
         for (int pl = 0; pl < 2; ++pl)
-            data.p[pl] = g.data[pl] ? static_cast<const char *>(g.data[pl]) + (d.off_data + b * d.mn) * es
-                                    : nullptr;
+            data.p[pl] = dbase[pl] ? static_cast<const char *>(dbase[pl]) + (d.off_data + b * d.mn) * es
+                                   : nullptr;
         if (A_BATCHED) a.A[b] = data;
         else a.B[b] = data;
         for (int pl = 0; pl < 2; ++pl)
@@ -629,6 +685,11 @@ __global__ __launch_bounds__((lp_threads<TS, KS>())) void k_gemm_nt_lp_grouped(G
     a.lam_col = d.lam_col;
     if (g.a_inst) a.a1 = a.a2 = g.a_inst[d.inst * g.a_stride];
     a.vec = d.vec;
+    a.lda = d.lda;
+    a.ldb = d.ldb;
+    a.split = d.split;
+    a.ileave = d.ileave;
+    a.unfold = d.unfold;
     gemm_nt_tile<MODE, NB, A_BATCHED, OUT, EPI, TS, KS>(a, tile.y, tile.z);
 }
 
@@ -652,6 +713,85 @@ __global__ __launch_bounds__(256) void k_split(const double *__restrict__ x0,
                 if constexpr (MODE == MCA_PREC_BF16X3)
                     static_cast<__bf16 *>(b == 0 ? o01 : o11)[k] = (__bf16)(f - (float)hi);
             }
+        }
+    }
+}
+
+// The same with the rows folded for a persymmetric G_bot (m = 2h): output row
+// i < h is x_i + x_{m-1-i}, row h + i is x_i - x_{m-1-i} (in FP64, then split).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_split_fold(const double *__restrict__ x0,
+                                                    const double *__restrict__ x1, int m, int n,
+                                                    void *o00, void *o01, void *o10, void *o11,
+                                                    const int *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    const int h = m / 2;
+    const size_t half = (size_t)h * n;
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < half; k += (size_t)gridDim.x * 256) {
+        const size_t i = k / n, j = k - i * n;
+        const size_t lo = i * n + j, hi = ((size_t)m - 1 - i) * n + j;
+        for (int b = 0; b < 2; ++b) {
+            const double *x = b == 0 ? x0 : x1;
+            const double sv[2] = {x[lo] + x[hi], x[lo] - x[hi]};
+            for (int q = 0; q < 2; ++q) {
+                const size_t e = q == 0 ? k : half + k;
+                const float f = (float)sv[q];
+                if constexpr (MODE == MCA_PREC_FP32) {
+                    static_cast<float *>(b == 0 ? o00 : o10)[e] = f;
+                } else {
+                    const __bf16 hv = (__bf16)f;
+                    static_cast<__bf16 *>(b == 0 ? o00 : o10)[e] = hv;
+                    if constexpr (MODE == MCA_PREC_BF16X3)
+                        static_cast<__bf16 *>(b == 0 ? o01 : o11)[e] = (__bf16)(f - (float)hv);
+                }
+            }
+        }
+    }
+}
+
+// Grouped form over a batch: block b takes chunk fold_tab[b].y (kFoldChunk
+// elements of the m/2 x n half) of crossbar fold_tab[b].x, whose chain is
+// folded, and writes its operand-format Krylov vector x (both layers) into w
+// with the rows folded as above: the planes are read back to FP32 (hi + lo),
+// summed / subtracted there, and split again.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_fold_grouped(const LpDesc *__restrict__ descs,
+                                                      const int2 *__restrict__ fold_tab,
+                                                      const void *x0, const void *x1, void *w0,
+                                                      void *w1, const int *ctl)
+{
+    const int2 fb = fold_tab[blockIdx.x];
+    const LpDesc &d = descs[fb.x];
+    if (ctl && ctl[4 * d.inst]) return;
+    const int m = d.N, n = d.M, h = m / 2;   // product 1 is n x m
+    const size_t half = (size_t)h * n;
+    auto get = [&](size_t e) -> float {
+        if constexpr (MODE == MCA_PREC_FP32) {
+            return static_cast<const float *>(x0)[e];
+        } else {
+            float v = (float)static_cast<const __bf16 *>(x0)[e];
+            if constexpr (MODE == MCA_PREC_BF16X3) v += (float)static_cast<const __bf16 *>(x1)[e];
+            return v;
+        }
+    };
+    auto put1 = [&](size_t e, float f) {
+        if constexpr (MODE == MCA_PREC_FP32) {
+            static_cast<float *>(w0)[e] = f;
+        } else {
+            const __bf16 hv = (__bf16)f;
+            static_cast<__bf16 *>(w0)[e] = hv;
+            if constexpr (MODE == MCA_PREC_BF16X3) static_cast<__bf16 *>(w1)[e] = (__bf16)(f - (float)hv);
+        }
+    };
+    const size_t k0 = (size_t)fb.y * kFoldChunk, k1 = std::min(half, k0 + kFoldChunk);
+    for (size_t k = k0 + threadIdx.x; k < k1; k += 256) {
+        const size_t i = k / n, j = k - i * n;
+        for (int b = 0; b < 2; ++b) {
+            const size_t base = d.off_data + b * d.mn;
+            const float lo = get(base + i * n + j), hi = get(base + ((size_t)m - 1 - i) * n + j);
+            put1(base + k, lo + hi);
+            put1(base + half + k, lo - hi);
         }
     }
 }
@@ -686,11 +826,61 @@ hipError_t chain(const LowPrecChain &c, hipStream_t s)
         return o;
     };
     auto vec_ok = [&](const LpArgs &g) {
-        bool ok = (g.K % 8 == 0);
+        bool ok = (g.K % 8 == 0) && (g.lda % 8 == 0) && (g.ldb % 8 == 0);
         for (int b = 0; b < 2; ++b)
             for (int pl = 0; pl < 2; ++pl) ok = ok && aligned16(g.A[b].p[pl]) && aligned16(g.B[b].p[pl]);
         return ok ? 1 : 0;
     };
+    if (c.fold) {
+        // Persymmetric G_bot (m = 2h, h a multiple of 128): its eigenvectors are
+        // [u; J u] (symmetric) and [u; -J u] (antisymmetric), u from the halves
+        // U_s, U_a (h x h, scaled by 1/sqrt2), so both Q_m-side products split
+        // into two products of half the depth on folded data.  The modes run
+        // symmetric first (eigenvalues lbp).
+        const int h = m / 2;
+        // 0. r -> folded rows (sums, then differences), operand format
+        {
+            const int blocks = (int)std::min<size_t>(((size_t)h * n + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_split_fold<MODE>, dim3(blocks), dim3(256), 0, s, c.rt, c.rb, m, n,
+                               c.x[0].p[0], c.x[0].p[1], c.x[1].p[0], c.x[1].p[1], c.skip);
+        }
+        LpArgs g{};
+        // 1. U'^T (n x m) = Q_n^T . X'^T: columns i < h from the sums, h + i from the differences
+        g.skip = c.skip;
+        g.M = n; g.N = m; g.K = n;
+        g.A[0] = op(c.QnT); g.B[0] = op(c.x[0]); g.B[1] = op(c.x[1]);
+        for (int b = 0; b < 2; ++b) { g.O[b][0] = c.u[b].p[0]; g.O[b][1] = c.u[b].p[1]; }
+        g.vec = vec_ok(g);
+        launch_nt<MODE, 2, false, OUT, EPI_STORE>(g, s);
+        // 2. W'^T (n x m): symmetric modes = U'^T[:, :h] . U_s, antisymmetric =
+        //    U'^T[:, h:] . U_a (B = [U_s^T; U_a^T], m x h); per-mode solve
+        g = LpArgs{};
+        g.skip = c.skip; g.a1 = c.a1; g.a2 = c.a2;
+        g.M = n; g.N = m; g.K = h; g.lda = m; g.split = 1;
+        g.A[0] = op(c.u[0]); g.A[1] = op(c.u[1]); g.B[0] = op(c.QmTf);
+        for (int b = 0; b < 2; ++b) { g.O[b][0] = c.w[b].p[0]; g.O[b][1] = c.w[b].p[1]; }
+        g.lam_row = c.lt; g.lam_col = c.lbp;
+        g.vec = vec_ok(g);
+        launch_nt<MODE, 2, true, OUT, EPI_PERMODE>(g, s);
+        // 3. Y' (m x n) = [U_s . X^hat_s; U_a . X^hat_a] (A = [U_s; U_a], m x h; B
+        //    from K = h on for the antisymmetric rows), rows interleaved in groups of 16
+        g = LpArgs{};
+        g.skip = c.skip;
+        g.M = m; g.N = n; g.K = h; g.ldb = m; g.split = 2; g.ileave = 1;
+        g.A[0] = op(c.Qmf); g.B[0] = op(c.w[0]); g.B[1] = op(c.w[1]);
+        for (int b = 0; b < 2; ++b) { g.O[b][0] = c.u[b].p[0]; g.O[b][1] = c.u[b].p[1]; }
+        g.vec = vec_ok(g);
+        launch_nt<MODE, 2, false, OUT, EPI_STORE>(g, s);
+        // 4. Z = unfold(Y' . Q_n^T): row p of both halves gives rows p and m-1-p
+        g = LpArgs{};
+        g.skip = c.skip;
+        g.M = m; g.N = n; g.K = n;
+        g.A[0] = op(c.u[0]); g.A[1] = op(c.u[1]); g.B[0] = op(c.Qn);
+        g.O[0][0] = c.zt; g.O[1][0] = c.zb;
+        g.vec = vec_ok(g);
+        launch_nt<MODE, 2, true, OUT_F64, EPI_UNFOLD16>(g, s);
+        return hipGetLastError();
+    }
     // 0. r (FP64) -> operand format
     if (!c.r_split) {
         const int blocks = (int)std::min<size_t>((mn + 255) / 256, 4096);
@@ -775,8 +965,14 @@ hipError_t chain_grouped(const GroupedChain &c, hipStream_t s)
         g.data[1] = in.p[1];
         g.out[0] = out.p[0];
         g.out[1] = out.p[1];
+        g.data_alt[0] = g.data_alt[1] = nullptr;
     };
+    if (c.fold_blocks > 0)   // folded crossbars: x -> w with the rows folded; product 1 reads w
+        hipLaunchKernelGGL(k_fold_grouped<MODE>, dim3(c.fold_blocks), dim3(256), 0, s, c.descs[0],
+                           c.fold_tab, c.x.p[0], c.x.p[1], c.w.p[0], c.w.p[1], c.ctl);
     set(0, c.x, c.u);
+    g.data_alt[0] = c.w.p[0];
+    g.data_alt[1] = c.w.p[1];
     launch_grouped<MODE, 2, false, OUT, EPI_STORE>(g, c.ntiles[0], c.tile, s);
     set(1, c.u, c.w);
     launch_grouped<MODE, 2, true, OUT, EPI_PERMODE>(g, c.ntiles[1], c.tile, s);

@@ -34,6 +34,9 @@ struct DevPlan {
     // transposes; lbp = (lambda_sym, lambda_anti), the mode order of the folded
     // transforms.  Null when G_bot is not persymmetric.
     const double *Us, *UsT, *Ua, *UaT, *lbp;
+    // reduced-precision [U_s^T; U_a^T] and [U_s; U_a] (m x h) for the folded chain
+    const float *QmTf32, *Qmf32;
+    const void *QmTfH, *QmTfL, *QmfH, *QmfL;
 };
 
 }  // namespace mca
@@ -108,7 +111,7 @@ hipError_t launch_precond_post(const mca_plan *P, double a1, const double *zt,
                                const int *skip = nullptr);
 
 // GEMM epilogues
-enum GemmEpi { EPI_STORE = 0, EPI_DIV_MU = 1, EPI_PERMODE = 2, EPI_UNFOLD = 3 };
+enum GemmEpi { EPI_STORE = 0, EPI_DIV_MU = 1, EPI_PERMODE = 2, EPI_UNFOLD = 3, EPI_UNFOLD16 = 4 };
 
 // O = L^T R (one or two batches sharing R), FP64 MFMA.
 //   L: K x M row-major (ld = M), R: K x N row-major (ld = N), O: M x N row-major.
@@ -155,6 +158,12 @@ struct LowPrecChain {
     int r_split;                        // x already holds r in operand format
     LpPlanes x[2], u[2], w[2];          // workspace: split r and two intermediates, m*n each
     double *zt, *zb;                    // output z (FP64)
+    // persymmetric G_bot with m / 2 a multiple of 128: the folded chain, with
+    // QmTf = [U_s^T; U_a^T] and Qmf = [U_s; U_a] (m x m/2 each) and the
+    // eigenvalues of G_bot in the folded mode order (symmetric first)
+    int fold;
+    LpPlanes QmTf, Qmf;
+    const double *lbp;
 };
 hipError_t launch_precond_lowprec(int precision, const LowPrecChain &c, hipStream_t s);
 
@@ -167,11 +176,16 @@ struct LpDesc {
     size_t off_data, off_out, mn;
     const double *lam_row, *lam_col;    // eigenvalues along output rows / columns
     int vec;                            // 16-byte aligned rows, K % 8 == 0
+    // persymmetric fold of the crossbar's Q_m-side products (see the
+    // single-crossbar chain): row strides, split, interleave, unfold, and alt:
+    // the data operand comes from the launch's alternative planes
+    int lda, ldb, split, ileave, unfold, alt;
 };
 struct GroupedLp {
     const LpDesc *descs;
     const int4 *tiles;                  // (descriptor, m0, n0, unused)
     const void *data[2];
+    const void *data_alt[2];            // the data planes of descriptors with alt set
     void *out[2];
     size_t data_elem_bytes, out_elem_bytes;
     const double *a_inst;               // per-crossbar a1 = a2, stride a_stride doubles
@@ -193,7 +207,13 @@ struct GroupedChain {
     const double *a_inst;
     int a_stride;
     const int *ctl;
+    // crossbars with a folded chain (their product-1 descriptors have alt set):
+    // x is folded into w first, block b of that pass taking chunk fold_tab[b].y
+    // (kFoldChunk elements of the m/2 x n half) of crossbar fold_tab[b].x
+    const int2 *fold_tab;
+    int fold_blocks;
 };
+constexpr int kFoldChunk = 2048;
 hipError_t launch_precond_lowprec_grouped(int precision, const GroupedChain &c, hipStream_t s);
 // host: FP64 -> FP32 (p0) or bfloat16 hi (p0) + lo (p1)
 void split_host(const double *src, size_t count, int precision, void *p0, void *p1);

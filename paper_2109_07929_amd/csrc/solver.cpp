@@ -95,6 +95,10 @@ mca_status validate_options(const mca_options *o)
 // The approximate form holds whole wires in LDS.
 bool approx_fits(const mca_plan *P) { return P->geom.m <= kTridiagMaxLen && P->geom.n <= kTridiagMaxLen; }
 
+// The reduced-precision chain folds the Q_m-side products (half their depth)
+// when G_bot is persymmetric and each half is a whole number of 128-row tiles.
+bool lp_fold(const mca_plan *P) { return P->persym && (P->geom.m / 2) % 128 == 0; }
+
 // Wire matrix of eq. (G) with the two end terminations (see mca.h).
 Wire make_wire(int len, double g, double end0, double end1) { return Wire{g, end0, end1, len}; }
 
@@ -117,6 +121,9 @@ struct PlanLayout {
     float *Qm32, *QmT32, *Qn32, *QnT32;
     uint16_t *QmH, *QmL, *QmTH, *QmTL, *QnH, *QnL, *QnTH, *QnTL;   // bfloat16 planes
     double *Us, *UsT, *Ua, *UaT, *lbp;                               // persymmetric halves
+    // the folded reduced-precision chain's halves: [U_s^T; U_a^T], [U_s; U_a] (m x h)
+    float *QmTf32, *Qmf32;
+    uint16_t *QmTfH, *QmTfL, *QmfH, *QmfL;
     size_t bytes;
 };
 
@@ -144,6 +151,8 @@ PlanLayout plan_layout(const mca_plan *P, void *base)
     L.QnTH = c.take<uint16_t>(n * n);
     L.QnTL = c.take<uint16_t>(n * n);
     L.Us = L.UsT = L.Ua = L.UaT = L.lbp = nullptr;
+    L.QmTf32 = L.Qmf32 = nullptr;
+    L.QmTfH = L.QmTfL = L.QmfH = L.QmfL = nullptr;
     if (P->persym) {
         const size_t h = m / 2;
         L.Us = c.take<double>(h * h);
@@ -151,6 +160,12 @@ PlanLayout plan_layout(const mca_plan *P, void *base)
         L.Ua = c.take<double>(h * h);
         L.UaT = c.take<double>(h * h);
         L.lbp = c.take<double>(m);
+        L.QmTf32 = c.take<float>(m * h);
+        L.Qmf32 = c.take<float>(m * h);
+        L.QmTfH = c.take<uint16_t>(m * h);
+        L.QmTfL = c.take<uint16_t>(m * h);
+        L.QmfH = c.take<uint16_t>(m * h);
+        L.QmfL = c.take<uint16_t>(m * h);
     }
     L.bytes = c.size();
     return L;
@@ -503,8 +518,17 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
             c.Qm = planes(d.QmH, d.QmL); c.Qn = planes(d.QnH, d.QnL);
         }
         c.lt = d.lt; c.lb = d.lb;
+        c.fold = lp_fold(P) ? 1 : 0;
+        if (c.fold) {
+            if (precision == MCA_PREC_FP32) {
+                c.QmTf = planes(d.QmTf32, nullptr); c.Qmf = planes(d.Qmf32, nullptr);
+            } else {
+                c.QmTf = planes(d.QmTfH, d.QmTfL); c.Qmf = planes(d.QmfH, d.QmfL);
+            }
+            c.lbp = d.lbp;
+        }
         c.rt = rt; c.rb = rb;
-        c.r_split = r_split ? 1 : 0;
+        c.r_split = (r_split && !c.fold) ? 1 : 0;
         for (int b = 0; b < 2; ++b) {
             c.x[b] = w.lp[b];
             c.u[b] = w.lp[2 + b];
@@ -665,7 +689,9 @@ struct Fgmres {
         two_pass = !(o->flags & MCA_FLAG_MGS_PASSES) && R <= kGsMaxV;
         // the reduced-precision per-mode chain: the update pass converts the new
         // vector into the chain's operand planes itself
-        lp_fused = two_pass && o->precond == MCA_PRECOND_PERMODE && o->precision != MCA_PREC_FP64;
+        // (the folded chain splits its input itself: its rows pair i with m - 1 - i)
+        lp_fused = two_pass && o->precond == MCA_PRECOND_PERMODE && o->precision != MCA_PREC_FP64 &&
+                   !lp_fold(P);
         // the literal form's last step (z_b from z_t) runs inside the Jacobian pass
         post_fused = two_pass && o->precond == MCA_PRECOND_LITERAL && o->precision == MCA_PREC_FP64;
         // persymmetric literal form: step j's finish shares a launch with step j + 1's
@@ -1189,6 +1215,15 @@ mca_status mca_plan_upload(mca_plan *P, void *dev_buf, size_t bytes, void *strea
             }
         std::memcpy(H.lbp, P->ls.data(), h * sizeof(double));
         std::memcpy(H.lbp + h, P->la.data(), h * sizeof(double));
+        std::vector<double> qtf(m * h), qf(m * h);
+        std::memcpy(qtf.data(), H.UsT, h * h * sizeof(double));
+        std::memcpy(qtf.data() + h * h, H.UaT, h * h * sizeof(double));
+        std::memcpy(qf.data(), H.Us, h * h * sizeof(double));
+        std::memcpy(qf.data() + h * h, H.Ua, h * h * sizeof(double));
+        split_host(qtf.data(), m * h, MCA_PREC_FP32, H.QmTf32, nullptr);
+        split_host(qf.data(), m * h, MCA_PREC_FP32, H.Qmf32, nullptr);
+        split_host(qtf.data(), m * h, MCA_PREC_BF16X3, H.QmTfH, H.QmTfL);
+        split_host(qf.data(), m * h, MCA_PREC_BF16X3, H.QmfH, H.QmfL);
     }
     MCA_TRY(hipMemcpyAsync(dev_buf, img.data(), P->dev_bytes, hipMemcpyHostToDevice, s));
     MCA_TRY(hipStreamSynchronize(s));
@@ -1209,6 +1244,8 @@ mca_status mca_plan_upload(mca_plan *P, void *dev_buf, size_t bytes, void *strea
     P->dev.QnH = L.QnH; P->dev.QnL = L.QnL; P->dev.QnTH = L.QnTH; P->dev.QnTL = L.QnTL;
     P->dev.Us = L.Us; P->dev.UsT = L.UsT; P->dev.Ua = L.Ua; P->dev.UaT = L.UaT;
     P->dev.lbp = L.lbp;
+    P->dev.QmTf32 = L.QmTf32; P->dev.Qmf32 = L.Qmf32;
+    P->dev.QmTfH = L.QmTfH; P->dev.QmTfL = L.QmTfL; P->dev.QmfH = L.QmfH; P->dev.QmfL = L.QmfL;
     return MCA_OK;
 }
 
