@@ -207,6 +207,43 @@ def test_batch_large_tiles_ragged(prec):
         f"worst err {worst:.1e}")
 
 
+@pytest.mark.parametrize("prec", [B.MCA_PREC_FP32, B.MCA_PREC_BF16X3])
+def test_batch_folded_and_full_chains(prec):
+    """64-tile batch mixing crossbars whose chain folds (persymmetric G_bot, m/2 a
+    multiple of 64: m = 128, 256) with ones that keep the full chain (m/2 off the
+    tile, or unequal bottom ends), n off the tile grid.  Every crossbar against the
+    oracle."""
+    shapes = [(128, 100, 0.1), (192, 72, 0.1), (256, 136, 0.1), (256, 136, 0.07), (320, 64, 0.1),
+              (128, 200, 0.1)]
+    cbs = [synth.crossbar(m, n, seed=20 + k, g_bot_end1=e1) for k, (m, n, e1) in enumerate(shapes)]
+    bt, vts, vbs, status, stats = batch_solve(cbs, precision=prec)
+    assert bt.product_tile == 64
+    assert status == B.MCA_OK
+    for b, c in enumerate(cbs):
+        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="cg")
+        err = rel_err(vts[b], vbs[b], rt, rb)
+        say(f"  {c.geom.m}x{c.geom.n} ends {c.geom.g_bot_end0},{c.geom.g_bot_end1}: "
+            f"newton {stats[b].newton_iters} err {err:.1e}")
+        assert err <= TOL
+
+
+@pytest.mark.parametrize("prec", [B.MCA_PREC_BF16X3])
+def test_batch_folded_large_tiles_ragged(prec):
+    """22 crossbars of 512 x 300 give 22 x 12 = 264 tiles of 128 per product: the
+    folded chain on 128 x 128 tiles with the products' other side cut at
+    300 = 2 x 128 + 44.  Four crossbars against the oracle, every residual checked."""
+    cbs = [synth.crossbar(512, 300, seed=40 + s) for s in range(22)]
+    bt, vts, vbs, status, stats = batch_solve(cbs, precision=prec)
+    assert bt.product_tile == 128
+    assert status == B.MCA_OK
+    assert all(st.rel_residual <= 1e-10 for st in stats)
+    for b in (0, 7, 14, 21):
+        rt, rb = _oracle_cg(cbs[b], ("512x300", b))
+        err = rel_err(vts[b], vbs[b], rt, rb)
+        say(f"  512x300 #{b}: newton {stats[b].newton_iters} err {err:.1e}")
+        assert err <= TOL
+
+
 @pytest.mark.parametrize("count", [4, 5])
 def test_batch_large_tiles_1024(count):
     """1024 x 1024 crossbars on 128 x 128 tiles, split-BF16: 4 crossbars give

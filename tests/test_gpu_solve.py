@@ -314,6 +314,24 @@ def test_mixed_precision_solve_1024(prec):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("prec", [B.MCA_PREC_FP32, B.MCA_PREC_BF16X3])
+@pytest.mark.parametrize("m,n,ends", [(512, 300, (0.1, 0.1)), (256, 136, (0.1, 0.1)),
+                                      (512, 300, (0.1, 0.07))])
+def test_mixed_precision_folded_chain(prec, m, n, ends):
+    """Equal bottom terminations with m/2 a multiple of 128 fold the reduced-precision
+    chain's Q_m-side products (half depth, interleaved rows, pairwise unfold); n off
+    the tile grid cuts the products' other side.  Unequal ends keep the full chain.
+    Both against the oracle."""
+    say(f"mixed solve {m}x{n} ends {ends} prec={prec}")
+    cb = synth.crossbar(m, n, seed=7, g_bot_end0=ends[0], g_bot_end1=ends[1])
+    vt, vb, status, st = gpu_solve(cb, precond=B.MCA_PRECOND_PERMODE, precision=prec)
+    assert status == B.MCA_OK
+    rt, rb, _, _ = oracle.solve(cb.geom, cb.g_dev, cb.v_in, method="cg")
+    err = rel_err(vt, vb, rt, rb)
+    say(f"  newton {st.newton_iters} krylov {list(st.krylov_history[:st.newton_iters])} err {err:.2e}")
+    assert err <= TOL
+
+
 @pytest.mark.parametrize("m,n", [(5, 3), (32, 32), (17, 45), (96, 64)])
 @pytest.mark.parametrize("form", [B.MCA_PRECOND_APPROX, B.MCA_PRECOND_JACOBI])
 def test_solve_approx_and_jacobi_forms(m, n, form):
