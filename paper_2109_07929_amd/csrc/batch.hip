@@ -149,27 +149,30 @@ __global__ __launch_bounds__(TPB) void bk_residual(
     }
 }
 
-// J x at crosspoint k of a crossbar (eq. (J)): (top row, bottom row)
-__device__ __forceinline__ void jac_point(const BInst &in, const double *__restrict__ xt,
-                                          const double *__restrict__ xb, double d, int k,
+// J x at crosspoint k of a crossbar (eq. (J)): (top row, bottom row); x in
+// FP64 or FP32 (the preconditioned vectors), the arithmetic in FP64
+template <typename T>
+__device__ __forceinline__ void jac_point(const BInst &in, const T *__restrict__ xt,
+                                          const T *__restrict__ xb, double d, int k,
                                           double &y1, double &y2)
 {
     const int m = in.m, n = in.n;
     const int i = k / n, j = k - i * n;
     const double t = xt[k], bv = xb[k];
-    const double st = wire_apply(in.top, j, t, (j > 0) ? xt[k - 1] : 0.0,
-                                 (j + 1 < n) ? xt[k + 1] : 0.0);
-    const double sb = wire_apply(in.bot, i, bv, (i > 0) ? xb[k - n] : 0.0,
-                                 (i + 1 < m) ? xb[k + n] : 0.0);
+    const double st = wire_apply(in.top, j, t, (j > 0) ? (double)xt[k - 1] : 0.0,
+                                 (j + 1 < n) ? (double)xt[k + 1] : 0.0);
+    const double sb = wire_apply(in.bot, i, bv, (i > 0) ? (double)xb[k - n] : 0.0,
+                                 (i + 1 < m) ? (double)xb[k + n] : 0.0);
     const double c = d * (t - bv);
     y1 = st + c;
     y2 = sb - c;
 }
 
-// y = J x per crossbar; with v0, per-block partials of <y, v0>.
+// y = J x per crossbar (x: the FP32 preconditioned vector); with v0,
+// per-block partials of <y, v0>.
 __global__ __launch_bounds__(TPB) void bk_jacobian(
     const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *__restrict__ ctl,
-    const double *__restrict__ D, const double *__restrict__ X, double *__restrict__ Y,
+    const double *__restrict__ D, const float *__restrict__ X, double *__restrict__ Y,
     const double *__restrict__ v0, double *__restrict__ part)
 {
     int b, k0, k1;
@@ -177,7 +180,7 @@ __global__ __launch_bounds__(TPB) void bk_jacobian(
     if (ctl[4 * b]) return;
     const BInst in = I[b];
     const size_t mn = (size_t)in.m * in.n;
-    const double *xt = X + 2 * in.ox, *xb = xt + mn;
+    const float *xt = X + 2 * in.ox, *xb = xt + mn;
     double *yt = Y + 2 * in.ox, *yb = yt + mn;
     const double *d = D + in.ox;
     double acc[1] = {0.0};
@@ -261,7 +264,7 @@ struct BGs {
     const int2 *bt;
     int *ctl;                   // per crossbar: stop flag first (stride 4)
     const double *D;
-    const double *Z;            // slot j of Z: the preconditioned u_j
+    const float *Z;             // slot j of Z: the preconditioned u_j (FP32)
     double *W;                  // slot j + 1 of V
     const double *V;            // slot 0 of V
     size_t len;                 // slot stride
@@ -289,7 +292,7 @@ __global__ __launch_bounds__(TPB) void bk_jacobian_proj(BGs a)
     const BInst in = a.I[b];
     const int j = a.j, nv = j + 1, R1 = a.R + 1;
     const size_t mn = (size_t)in.m * in.n, base = 2 * in.ox;
-    const double *zt = a.Z + base, *zb = zt + mn;
+    const float *zt = a.Z + base, *zb = zt + mn;
     const double *d = a.D + in.ox;
     const double *sg = a.sig + (size_t)b * R1;
     const double sj = sg[j];
@@ -477,7 +480,7 @@ __global__ __launch_bounds__(TPB) void bk_copy_cross(
 // X (+)= sum_{i < upd_b} y_b[i] Z_i for crossbars with upd_b > 0 or first_b set
 __global__ __launch_bounds__(TPB) void bk_update(
     const BInst *__restrict__ I, const int2 *__restrict__ bt, const BState *__restrict__ S,
-    const double *__restrict__ Z, size_t zstride, const double *__restrict__ Y, int R,
+    const float *__restrict__ Z, size_t zstride, const double *__restrict__ Y, int R,
     double *__restrict__ X)
 {
     int b, k0, k1;
@@ -493,7 +496,7 @@ __global__ __launch_bounds__(TPB) void bk_update(
         for (int l = 0; l < 2; ++l) {
             const size_t e = base + l * mn + kk;
             double s = overwrite ? 0.0 : X[e];
-            for (int v = 0; v < k; ++v) s += y[v] * Z[(size_t)v * zstride + e];
+            for (int v = 0; v < k; ++v) s += y[v] * (double)Z[(size_t)v * zstride + e];
             X[e] = s;
         }
     }
@@ -1065,7 +1068,8 @@ BatchLayout batch_layout(const mca_batch *B, void *base)
 }
 
 struct BatchWs {
-    double *V, *Z, *X, *Vc, *T, *F, *Ft, *D, *Dt;
+    double *V, *X, *Vc, *T, *F, *Ft, *D, *Dt;
+    float *Z;   // the preconditioned vectors: FP32, as the products form them
     double *pa, *pb;
     double *pg1, *pg2, *sig, *Lg;   // two-pass Gram-Schmidt
     int *run;
@@ -1085,7 +1089,7 @@ BatchWs batch_ws(const mca_batch *B, const mca_options *o, void *base)
     BCarver c(base);
     BatchWs w;
     w.V = c.take<double>((R + 1) * len);
-    w.Z = c.take<double>(R * len);
+    w.Z = c.take<float>(R * len);
     w.X = c.take<double>(len);
     w.Vc = c.take<double>(len);
     w.T = c.take<double>(len);
@@ -1525,7 +1529,8 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     // normalisation, the Givens update, and the count of running cycles
     // written to flag slot j
     auto enqueue_step = [&](int j, hipStream_t q) -> hipError_t {
-        double *vj = w.V + (size_t)j * len, *zj = w.Z + (size_t)j * len;
+        double *vj = w.V + (size_t)j * len;
+        float *zj = w.Z + (size_t)j * len;
         double *wv = w.V + (size_t)(j + 1) * len;
         GroupedChain c = gc;
         c.r = vj;

@@ -982,8 +982,8 @@ hipError_t chain_grouped(const GroupedChain &c, hipStream_t s)
     z.p[0] = c.z;
     z.p[1] = nullptr;
     set(3, c.u, z);
-    g.out_elem_bytes = 8;
-    launch_grouped<MODE, 2, true, OUT_F64, EPI_STORE>(g, c.ntiles[3], c.tile, s);
+    g.out_elem_bytes = 4;
+    launch_grouped<MODE, 2, true, OUT_F32, EPI_STORE>(g, c.ntiles[3], c.tile, s);
     return hipGetLastError();
 }
 

@@ -203,7 +203,7 @@ struct GroupedChain {
     size_t len;
     int r_split;                        // x already holds r in operand format
     LpPlanes x, u, w;
-    double *z;
+    float *z;                           // output z in FP32 (the products accumulate in FP32)
     const double *a_inst;
     int a_stride;
     const int *ctl;
