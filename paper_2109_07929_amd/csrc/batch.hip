@@ -39,7 +39,8 @@ using dev::wire_apply;
 constexpr int CH = 2048;   // crosspoints per block of the streaming kernels
 
 struct BInst {             // device descriptor of one crossbar
-    int m, n, linear, blk0, nblk, pad;
+    int m, n, linear, blk0, nblk;
+    int fold;              // its preconditioner chain is folded (persymmetric rows)
     Wire top, bot;
     double v0, g_src;
     long long ox, orow;
@@ -275,8 +276,12 @@ struct BGs {
     double *p1, *p2;
     // with xp[0] set, the update pass also writes the new vector in the
     // preconditioner's operand format (FP32, or bfloat16 hi [+ lo]), the
-    // conversion the next step's chain would otherwise make of it
+    // conversion the next step's chain would otherwise make of it; for a
+    // crossbar with a folded chain it writes the folded rows into xf instead
+    // (row i < m/2: x_i + x_{m-1-i}, row m/2 + i: x_i - x_{m-1-i}), the input
+    // of that chain's first product
     void *xp[2];
+    void *xf[2];
     int prec;
     double *g, *cs, *sn;        // Givens state, per crossbar
     const BState *S;
@@ -361,6 +366,20 @@ __global__ __launch_bounds__(TPB) void bk_gs_coef(BGs a)
 // The blocks run in reverse table order: the projection pass just before read
 // the vectors front to back, so the parts it read last are the likeliest still
 // in the memory-side cache.
+// x in the preconditioner's operand format at element e: FP64 -> FP32 ->
+// bfloat16 hi, lo = the rest (as k_split)
+__device__ __forceinline__ void put_operand(void *const (&xp)[2], int prec, size_t e, double x)
+{
+    const float f = (float)x;
+    if (prec == MCA_PREC_FP32) {
+        static_cast<float *>(xp[0])[e] = f;
+    } else {
+        const __bf16 hi = (__bf16)f;
+        static_cast<__bf16 *>(xp[0])[e] = hi;
+        if (prec == MCA_PREC_BF16X3) static_cast<__bf16 *>(xp[1])[e] = (__bf16)(f - (float)hi);
+    }
+}
+
 template <int MAXV>
 __global__ __launch_bounds__(TPB) void bk_gs_update(BGs a)
 {
@@ -377,32 +396,45 @@ __global__ __launch_bounds__(TPB) void bk_gs_update(BGs a)
     for (int q = 0; q < MAXV; ++q) c[q] = (q < nv) ? hcol[q] * sg[q] : 0.0;
 #pragma unroll
     for (int q = 0; q <= MAXV; ++q) acc[q] = 0.0;
-    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+    // w -= sum_q c_q v_q at element e; accumulates <w, v_q> and ||w||^2
+    auto update = [&](size_t e) -> double {
+        double vq[MAXV];
+        double x = a.W[e];
 #pragma unroll
-        for (int l = 0; l < 2; ++l) {
-            const size_t e = base + l * mn + k;
-            double vq[MAXV];
-            double x = a.W[e];
+        for (int q = 0; q < MAXV; ++q) {
+            vq[q] = (q < nv) ? a.V[q * a.len + e] : 0.0;
+            x -= c[q] * vq[q];
+        }
+        a.W[e] = x;
 #pragma unroll
-            for (int q = 0; q < MAXV; ++q) {
-                vq[q] = (q < nv) ? a.V[q * a.len + e] : 0.0;
-                x -= c[q] * vq[q];
+        for (int q = 0; q < MAXV; ++q) acc[q] += x * vq[q];
+        acc[MAXV] += x * x;
+        return x;
+    };
+    if (a.xp[0] && in.fold) {
+        // pairs of rows (i, m - 1 - i): this block takes pairs k0/2 .. k1/2 of
+        // the m/2 x n half (k0, k1 and m n are even) and writes both folded rows
+        const int n = in.n, h = in.m / 2;
+        const size_t half = (size_t)h * n;
+        for (int q = k0 / 2 + threadIdx.x; q < k1 / 2; q += TPB) {
+            const int i = q / n, jj = q - i * n;
+            const size_t p0 = (size_t)i * n + jj, p1 = (size_t)(in.m - 1 - i) * n + jj;
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                const size_t o = base + l * mn;
+                const double x0 = update(o + p0), x1 = update(o + p1);
+                put_operand(a.xf, a.prec, o + q, x0 + x1);
+                put_operand(a.xf, a.prec, o + half + q, x0 - x1);
             }
-            a.W[e] = x;
-            if (a.xp[0]) {   // as k_split: FP64 -> FP32 -> bfloat16 hi, lo = rest
-                const float f = (float)x;
-                if (a.prec == MCA_PREC_FP32) {
-                    static_cast<float *>(a.xp[0])[e] = f;
-                } else {
-                    const __bf16 hi = (__bf16)f;
-                    static_cast<__bf16 *>(a.xp[0])[e] = hi;
-                    if (a.prec == MCA_PREC_BF16X3)
-                        static_cast<__bf16 *>(a.xp[1])[e] = (__bf16)(f - (float)hi);
-                }
-            }
+        }
+    } else {
+        for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
 #pragma unroll
-            for (int q = 0; q < MAXV; ++q) acc[q] += x * vq[q];
-            acc[MAXV] += x * x;
+            for (int l = 0; l < 2; ++l) {
+                const size_t e = base + l * mn + k;
+                const double x = update(e);
+                if (a.xp[0]) put_operand(a.xp, a.prec, e, x);
+            }
         }
     }
     block_sum<MAXV + 1>(acc);
@@ -1240,7 +1272,9 @@ mca_status mca_batch_create(int32_t count, const mca_geometry *geoms, mca_batch 
     }
     // the folded crossbars' row folds, in chunks of kFoldChunk (m/2) x n elements
     for (int b = 0; b < count; ++b)
-        if (plan_fold(B->plans[B->pidx[b]], T)) {
+        B->inst[b].fold = plan_fold(B->plans[B->pidx[b]], T) ? 1 : 0;
+    for (int b = 0; b < count; ++b)
+        if (B->inst[b].fold) {
             const size_t half = (size_t)geoms[b].m / 2 * geoms[b].n;
             for (size_t c = 0; c * kFoldChunk < half; ++c) B->ftab.push_back(int2{b, (int)c});
         }
@@ -1523,6 +1557,8 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     gs.run = w.run;
     gs.xp[0] = w.x.p[0];
     gs.xp[1] = w.x.p[1];
+    gs.xf[0] = w.w.p[0];
+    gs.xf[1] = w.w.p[1];
     gs.prec = o.precision;
     // Arnoldi step j of every crossbar still in its cycle: preconditioner,
     // Jacobian product fused with <w, v_0>, the projection passes, the
@@ -1535,7 +1571,9 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         GroupedChain c = gc;
         c.r = vj;
         c.z = zj;
-        c.r_split = (two_pass && j > 0) ? 1 : 0;   // the previous update pass converted v_j
+        // the previous update pass converted v_j (and folded it for the folded chains)
+        c.r_split = (two_pass && j > 0) ? 1 : 0;
+        c.r_folded = c.r_split;
         hipError_t e = launch_precond_lowprec_grouped(o.precision, c, q);
         if (e != hipSuccess) return e;
         if (two_pass) {

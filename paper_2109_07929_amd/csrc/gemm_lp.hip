@@ -967,7 +967,9 @@ hipError_t chain_grouped(const GroupedChain &c, hipStream_t s)
         g.out[1] = out.p[1];
         g.data_alt[0] = g.data_alt[1] = nullptr;
     };
-    if (c.fold_blocks > 0)   // folded crossbars: x -> w with the rows folded; product 1 reads w
+    // folded crossbars: x -> w with the rows folded (unless the pass that
+    // converted r did so); product 1 reads w
+    if (c.fold_blocks > 0 && !(c.r_split && c.r_folded))
         hipLaunchKernelGGL(k_fold_grouped<MODE>, dim3(c.fold_blocks), dim3(256), 0, s, c.descs[0],
                            c.fold_tab, c.x.p[0], c.x.p[1], c.w.p[0], c.w.p[1], c.ctl);
     set(0, c.x, c.u);

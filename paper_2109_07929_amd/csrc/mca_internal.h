@@ -202,6 +202,7 @@ struct GroupedChain {
     const double *r;
     size_t len;
     int r_split;                        // x already holds r in operand format
+    int r_folded;                       // and w the folded chains' input (with r_split)
     LpPlanes x, u, w;
     float *z;                           // output z in FP32 (the products accumulate in FP32)
     const double *a_inst;
