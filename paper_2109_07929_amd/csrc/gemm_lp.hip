@@ -39,6 +39,8 @@
 // time) avoid the conflicts but cost more in the global loads than they save.
 #include <hip/hip_bf16.h>
 
+#include <type_traits>
+
 #include "mca_internal.h"
 
 namespace mca {
@@ -272,8 +274,15 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
     constexpr int PL = Fmt<MODE>::kPlanes;
     using TileT = Tile<MODE, TS, KS>;
     using RegsT = Regs<MODE, TS, KS, NT>;
-    __shared__ TileT As[2][NA];
-    __shared__ TileT Bs[2][NBB];
+    // One K slice of every operand tile (the A tiles first) per LDS buffer; the
+    // buffers are distinct objects, so that the compiler's wait for the
+    // direct-to-LDS loads before a fragment read covers only that buffer's.
+    struct SliceBuf {
+        TileT t[NA + NBB];
+    };
+    __shared__ SliceBuf L0, L1;
+    auto As = [&](int buf, int b) -> TileT & { return buf ? L1.t[b] : L0.t[b]; };
+    auto Bs = [&](int buf, int b) -> TileT & { return buf ? L1.t[NA + b] : L0.t[NA + b]; };
     const int M = a.M, N = a.N, K = a.K;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -306,9 +315,9 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
     };
     auto stash = [&](const Stage &st, int buf) {
 #pragma unroll
-        for (int b = 0; b < NA; ++b) stash_op<MODE, TS, KS, NT>(As[buf][b], st.ra[b]);
+        for (int b = 0; b < NA; ++b) stash_op<MODE, TS, KS, NT>(As(buf, b), st.ra[b]);
 #pragma unroll
-        for (int b = 0; b < NBB; ++b) stash_op<MODE, TS, KS, NT>(Bs[buf][b], st.rb[b]);
+        for (int b = 0; b < NBB; ++b) stash_op<MODE, TS, KS, NT>(Bs(buf, b), st.rb[b]);
     };
 
     f4 acc[NB][FI][FJ];
@@ -359,13 +368,13 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 #pragma unroll
             for (int pl = 0; pl < PL; ++pl)
 #pragma unroll
-                for (int i = 0; i < FI; ++i) fa[b][pl][i] = frag_bf16(As[buf][b], pl, gm + i, s, lane);
+                for (int i = 0; i < FI; ++i) fa[b][pl][i] = frag_bf16(As(buf, b), pl, gm + i, s, lane);
 #pragma unroll
         for (int b = 0; b < NBB; ++b)
 #pragma unroll
             for (int pl = 0; pl < PL; ++pl)
 #pragma unroll
-                for (int j = 0; j < FJ; ++j) fb[b][pl][j] = frag_bf16(Bs[buf][b], pl, gn + j, s, lane);
+                for (int j = 0; j < FJ; ++j) fb[b][pl][j] = frag_bf16(Bs(buf, b), pl, gn + j, s, lane);
     };
 
     auto compute = [&](int buf) {
@@ -376,11 +385,11 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 #pragma unroll
                 for (int b = 0; b < NA; ++b)
 #pragma unroll
-                    for (int i = 0; i < FI; ++i) fa[b][i] = frag_f32(As[buf][b], gm + i, s4, lane);
+                    for (int i = 0; i < FI; ++i) fa[b][i] = frag_f32(As(buf, b), gm + i, s4, lane);
 #pragma unroll
                 for (int b = 0; b < NBB; ++b)
 #pragma unroll
-                    for (int j = 0; j < FJ; ++j) fb[b][j] = frag_f32(Bs[buf][b], gn + j, s4, lane);
+                    for (int j = 0; j < FJ; ++j) fb[b][j] = frag_f32(Bs(buf, b), gn + j, s4, lane);
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -402,86 +411,147 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
 
     bool done = false;
     if constexpr (TS == 128 && KS == 32 && MODE != MCA_PREC_FP32 && NT == 512) {
-        // only in launches of at most one tile per CU (one 2048^2 split-BF16
-        // solve 16.3 -> 14.7 ms); with more, the register path measured faster
-        // (8 x 1024^2 batch 21.0 vs 21.3 ms)
-        if (fast_m && fast_n && K % KS == 0 && gridDim.x <= 256) {
+        if (fast_m && fast_n && K % KS == 0 && K >= 3 * KS) {
             // Interior tile: every slice goes from global memory straight into
-            // LDS (global_load_lds_dwordx4, 16 bytes per lane), two buffers.
-            // This path keeps a layout of its own: plane p, row r, 16-byte
-            // chunk c of the row's 32 values at byte p 8192 + 64 r +
+            // LDS (global_load_lds_dwordx4, 16 bytes per lane), three buffers,
+            // software-pipelined: step k multiplies slice k from one register
+            // set of fragments while the other set is read from slice k + 1's
+            // buffer and slice k + 3 is loaded into the buffer slice k left, so
+            // that the LDS reads and the loads overlap the MFMAs.  Layout of a
+            // buffer: operand tile t, plane p, row r, 16-byte chunk c of the
+            // row's 32 values at byte t sizeof(Tile) + p 8192 + 64 r +
             // 16 (c ^ ((r >> 2) & 3)), so that each lane quad loads one row's
-            // 64 contiguous bytes (the load writes LDS in lane order).  Each
-            // step reads its fragments, then issues the next slice into the
-            // other buffer, then runs its MFMAs.
+            // 64 contiguous bytes (the load writes LDS in lane order) and the
+            // fragment reads are free of bank conflicts.
+            __shared__ SliceBuf L2;
             constexpr int NI = (NA + NBB) * PL * 8;   // 1 KB instructions per slice
             constexpr int NQ = NI / 8;                 // per wave
             static_assert(NI % 8 == 0, "instructions per wave");
             typedef const void __attribute__((address_space(1))) *gptr;
             typedef void __attribute__((address_space(3))) *lptr;
-            auto tile_base = [&](int buf, int t) -> char * {
-                return t < NA ? reinterpret_cast<char *>(&As[buf][t])
-                              : reinterpret_cast<char *>(&Bs[buf][t - NA]);
+            using I0 = std::integral_constant<int, 0>;
+            using I1 = std::integral_constant<int, 1>;
+            using I2 = std::integral_constant<int, 2>;
+            auto bufp = [&](auto bc) -> char * {
+                constexpr int B = decltype(bc)::value;
+                if constexpr (B == 0) return reinterpret_cast<char *>(&L0);
+                else if constexpr (B == 1) return reinterpret_cast<char *>(&L1);
+                else return reinterpret_cast<char *>(&L2);
             };
-            const __bf16 *src[NQ];
-            int dst_t[NQ], dst_off[NQ];
+            // Wave w loads row block w (16 rows) of every operand plane: its
+            // instruction q takes operand tile q / PL, plane q % PL.  Each lane
+            // quad loads one row's 64 bytes, chunk c of the row to chunk
+            // c ^ ((row >> 2) & 3) of LDS, which for 16-row blocks is
+            // c ^ ((lane >> 4) & 3).  Addresses: a wave-uniform base (scalar
+            // registers) plus a per-lane byte offset, one per operand side.
+            const int wv = __builtin_amdgcn_readfirstlane(wave);
+            const int lc = ((lane & 3) ^ ((lane >> 4) & 3)) * 16;
+            const unsigned voff_a = (unsigned)((lane >> 2) * lda * 2 + lc);
+            const unsigned voff_b = (unsigned)((lane >> 2) * ldb * 2 + lc);
+            const char *sbase[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const int idx = wave + 8 * q;
-                const int t = idx / (PL * 8), pl = (idx / 8) % PL, rb = idx % 8;
-                const int r = rb * 16 + (lane >> 2);
-                const int c = (lane & 3) ^ ((r >> 2) & 3);
-                // (selects over the few operands: indexing the argument copy
-                // with a per-wave value would move it to scratch memory)
+                const int t = q / PL, pl = q % PL;
                 const void *base = nullptr;
 #pragma unroll
                 for (int u = 0; u < NA; ++u)
-                    if (t == u) base = pl ? a.A[u].p[PL - 1] : a.A[u].p[0];
+                    if (t == u) base = a.A[u].p[pl];
 #pragma unroll
                 for (int u = 0; u < NBB; ++u)
-                    if (t == NA + u) base = pl ? a.B[u].p[PL - 1] : a.B[u].p[0];
-                const int r0 = t < NA ? m0 : n0;
-                src[q] = static_cast<const __bf16 *>(base) + (t < NA ? koa : kob) +
-                         (size_t)(r0 + r) * (t < NA ? lda : ldb) + c * 8;
-                dst_t[q] = t;
-                dst_off[q] = pl * 8192 + rb * 1024;
+                    if (t == NA + u) base = a.B[u].p[pl];
+                const size_t row0 = (size_t)((t < NA ? m0 : n0) + wv * 16);
+                sbase[q] = static_cast<const char *>(base) +
+                           2 * (row0 * (t < NA ? lda : ldb) + (t < NA ? koa : kob));
             }
-            auto issue = [&](int buf, int k0) {
+            const int dst_w = wv * 1024;
+            auto issue = [&](auto bc, int k0) {
+                char *lb = bufp(bc) + dst_w;
 #pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    __builtin_amdgcn_global_load_lds((gptr)(src[q] + k0),
-                                                     (lptr)(tile_base(buf, dst_t[q]) + dst_off[q]),
-                                                     16, 0, 0);
+                for (int q = 0; q < NQ; ++q) {
+                    const int t = q / PL, pl = q % PL;
+                    __builtin_amdgcn_global_load_lds(
+                        (gptr)(sbase[q] + 2 * (size_t)k0 + (t < NA ? voff_a : voff_b)),
+                        (lptr)(lb + t * (int)sizeof(TileT) + pl * 8192), 16, 0, 0);
+                }
             };
-            auto frag = [&](int buf, int t, int pl, int row) -> bf8 {
-                const int c = (lane >> 4) ^ ((row >> 2) & 3);
-                return *reinterpret_cast<const bf8 *>(tile_base(buf, t) + pl * 8192 + row * 64 + c * 16);
-            };
-            const int nk = K / KS;
-            issue(0, 0);
-            for (int k = 0; k < nk; ++k) {
-                const int buf = k & 1;
-                // this wave's part of slice k has landed; the barrier publishes
-                // every wave's part and frees the other buffer
-                __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0)
-                asm volatile("s_barrier" ::: "memory");
-                bf8 fa[NA][PL][FI], fb[NBB][PL][FJ];
+            using FA = bf8[NA][PL][FI];
+            using FB = bf8[NBB][PL][FJ];
+            auto read = [&](auto bc, FA &fa, FB &fb) {
+                const char *lb = bufp(bc);
+                auto frag = [&](int t, int pl, int row) -> bf8 {
+                    const int c = (lane >> 4) ^ ((row >> 2) & 3);
+                    return *reinterpret_cast<const bf8 *>(lb + t * (int)sizeof(TileT) + pl * 8192 + row * 64 + c * 16);
+                };
 #pragma unroll
                 for (int b = 0; b < NA; ++b)
 #pragma unroll
                     for (int pl = 0; pl < PL; ++pl)
 #pragma unroll
-                        for (int i = 0; i < FI; ++i) fa[b][pl][i] = frag(buf, b, pl, wm + i * 16 + (lane & 15));
+                        for (int i = 0; i < FI; ++i) fa[b][pl][i] = frag(b, pl, wm + i * 16 + (lane & 15));
 #pragma unroll
                 for (int b = 0; b < NBB; ++b)
 #pragma unroll
                     for (int pl = 0; pl < PL; ++pl)
 #pragma unroll
-                        for (int j = 0; j < FJ; ++j)
-                            fb[b][pl][j] = frag(buf, NA + b, pl, wn + j * 16 + (lane & 15));
-                if (k + 1 < nk) issue(buf ^ 1, (k + 1) * KS);
-                mfma_bf16(fa, fb);
+                        for (int j = 0; j < FJ; ++j) fb[b][pl][j] = frag(NA + b, pl, wn + j * 16 + (lane & 15));
+            };
+            // s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0 and 15:14,
+            // expcnt in 6:4, lgkmcnt in 11:8): the loads of one slice may stay in
+            // flight, LDS reads all done
+            constexpr int kWaitOne = (NQ & 15) | ((NQ >> 4) << 14) | (7 << 4);
+            constexpr int kWaitTwo = ((2 * NQ) & 15) | (((2 * NQ) >> 4) << 14) | (7 << 4);
+            constexpr int kWaitNone = 7 << 4;
+            static_assert(2 * NQ < 64, "vmcnt range");
+            const int nk = K / KS, last = nk - 1;
+            FA fa0, fa1;
+            FB fb0, fb1;
+            issue(I0{}, 0);
+            issue(I1{}, KS);
+            issue(I2{}, 2 * KS);
+            __builtin_amdgcn_s_waitcnt(kWaitTwo);   // slice 0 has landed
+            asm volatile("s_barrier" ::: "memory");
+            read(I0{}, fa0, fb0);
+            // Step k: slice k's fragments in (fc, gc), slice k in buffer BK =
+            // k mod 3 and slice k + 1 in the next.  Past the end the last slice
+            // is loaded and read again (in bounds, never multiplied), which keeps
+            // every step free of branches and the count of loads in flight the
+            // same at every wait.
+            auto step = [&](auto bk, int k, FA &fc, FB &gc, FA &fn, FB &gn) {
+                constexpr int BK = decltype(bk)::value;
+                // slice k + 1 has landed (k + 2 may still be in flight) and every
+                // wave has finished its reads of slice k: the barrier publishes
+                // the one and frees the other's buffer
+                __builtin_amdgcn_s_waitcnt(kWaitOne);
+                asm volatile("s_barrier" ::: "memory");
+                read(std::integral_constant<int, (BK + 1) % 3>{}, fn, gn);
+                // the reads go out before the next slice's loads (a read issued
+                // behind a load into LDS would wait for that load)
+                __builtin_amdgcn_sched_barrier(0);
+                issue(bk, min(k + 3, last) * KS);
+                mfma_bf16(fc, gc);
+                // (steps stay apart: MFMAs moved into the next step would keep
+                // both fragment sets and more live at once)
+                __builtin_amdgcn_sched_barrier(0);
+            };
+            // whole rounds of six steps (buffers and fragment sets back where
+            // they started) without branches between the steps, then the rest
+            int k = 0;
+            for (; k + 6 <= nk; k += 6) {
+                step(I0{}, k, fa0, fb0, fa1, fb1);
+                step(I1{}, k + 1, fa1, fb1, fa0, fb0);
+                step(I2{}, k + 2, fa0, fb0, fa1, fb1);
+                step(I0{}, k + 3, fa1, fb1, fa0, fb0);
+                step(I1{}, k + 4, fa0, fb0, fa1, fb1);
+                step(I2{}, k + 5, fa1, fb1, fa0, fb0);
             }
+            if (k < nk) step(I0{}, k, fa0, fb0, fa1, fb1);
+            if (k + 1 < nk) step(I1{}, k + 1, fa1, fb1, fa0, fb0);
+            if (k + 2 < nk) step(I2{}, k + 2, fa0, fb0, fa1, fb1);
+            if (k + 3 < nk) step(I0{}, k + 3, fa1, fb1, fa0, fb0);
+            if (k + 4 < nk) step(I1{}, k + 4, fa0, fb0, fa1, fb1);
+            // no LDS DMA may outlive the workgroup (nor land in a buffer the
+            // epilogue reuses)
+            __builtin_amdgcn_s_waitcnt(kWaitNone);
             done = true;
         }
     }
