@@ -59,6 +59,8 @@ struct BState {            // device control record of one crossbar
     int ls_todo, accept, halvings;
     int guess;             // started from the caller's guess
     int reject;            // the guess is dropped for V = 0
+    int vsel;              // the current voltages sit in T (1) or in Vc (0)
+    int pad_;
 };
 constexpr int kStateInts = sizeof(BState) / sizeof(int);
 static_assert(sizeof(BState) % sizeof(double) == 0, "state record");
@@ -104,17 +106,19 @@ __device__ __forceinline__ double inst_sum(const BInst &I, const double *__restr
 }
 
 // --------------------------------------------------------------- streaming
+// (with S given: the voltages of crossbar b are Va, or Vb when S[b].vsel is set)
 __global__ __launch_bounds__(TPB) void bk_residual(
     const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *flag,
     const double *__restrict__ g_dev, const double *__restrict__ v_in,
-    const double *__restrict__ V, double *__restrict__ F, double *__restrict__ D,
-    double *__restrict__ part)
+    const double *__restrict__ Va, const double *__restrict__ Vb, const BState *__restrict__ S,
+    double *__restrict__ F, double *__restrict__ D, double *__restrict__ part)
 {
     int b, k0, k1;
     if (!block_range(I, bt, flag, b, k0, k1)) return;
     const BInst in = I[b];
     const int m = in.m, n = in.n;
     const size_t mn = (size_t)m * n;
+    const double *V = (S && S[b].vsel) ? Vb : Va;
     const double *vt = V + 2 * in.ox, *vb = vt + mn;
     double *ft = F + 2 * in.ox, *fb = ft + mn;
     double acc[2] = {0.0, 0.0};
@@ -268,6 +272,7 @@ struct BGs {
     const float *Z;             // slot j of Z: the preconditioned u_j (FP32)
     double *W;                  // slot j + 1 of V
     const double *V;            // slot 0 of V
+    const double *v0;           // where u_0 is read: slot 0 of V, or F (sig_0 = -1 / beta)
     size_t len;                 // slot stride
     double *sig;                // per crossbar R + 1 scales
     double *L;                  // per crossbar (R + 1)^2, row-major
@@ -313,8 +318,10 @@ __global__ __launch_bounds__(TPB) void bk_jacobian_proj(BGs a)
         a.W[base + mn + k] = y2;
 #pragma unroll
         for (int q = 0; q < MAXV; ++q)
-            if (q < nv)
-                acc[q] += y1 * a.V[q * a.len + base + k] + y2 * a.V[q * a.len + base + mn + k];
+            if (q < nv) {
+                const double *u = (q == 0) ? a.v0 : a.V + q * a.len;
+                acc[q] += y1 * u[base + k] + y2 * u[base + mn + k];
+            }
     }
     block_sum<MAXV>(acc);
     const int t = blockIdx.x - in.blk0;
@@ -402,7 +409,7 @@ __global__ __launch_bounds__(TPB) void bk_gs_update(BGs a)
         double x = a.W[e];
 #pragma unroll
         for (int q = 0; q < MAXV; ++q) {
-            vq[q] = (q < nv) ? a.V[q * a.len + e] : 0.0;
+            vq[q] = (q < nv) ? ((q == 0) ? a.v0 : a.V + q * a.len)[e] : 0.0;
             x -= c[q] * vq[q];
         }
         a.W[e] = x;
@@ -498,6 +505,30 @@ __global__ __launch_bounds__(TPB) void bk_axpy(
     }
 }
 
+// Line-search trial of the flagged crossbars: into the buffer that does not
+// hold the current voltages, trial = current + step X.
+__global__ __launch_bounds__(TPB) void bk_trial(const BInst *__restrict__ I,
+                                                const int2 *__restrict__ bt, const int *flag,
+                                                const BState *__restrict__ S,
+                                                const double *__restrict__ X,
+                                                double *__restrict__ Vc, double *__restrict__ T)
+{
+    int b, k0, k1;
+    if (!block_range(I, bt, flag, b, k0, k1)) return;
+    const BInst in = I[b];
+    const size_t mn = (size_t)in.m * in.n, base = 2 * in.ox;
+    const BState s = S[b];
+    const double *cur = s.vsel ? T : Vc;
+    double *nxt = s.vsel ? Vc : T;
+    for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            const size_t e = base + l * mn + k;
+            nxt[e] = cur[e] + s.step * X[e];
+        }
+    }
+}
+
 // D copy for accepted crossbars (m n values per crossbar)
 __global__ __launch_bounds__(TPB) void bk_copy_cross(
     const BInst *__restrict__ I, const int2 *__restrict__ bt, const int *flag,
@@ -535,14 +566,17 @@ __global__ __launch_bounds__(TPB) void bk_update(
 }
 
 // scatter the iterate into the caller's v_t / v_b, or gather a guess from them
+// (to the user: the current voltages, Vc or, with vsel set, T)
 __global__ __launch_bounds__(TPB) void bk_user_io(const BInst *__restrict__ I,
                                                   const int2 *__restrict__ bt,
-                                                  const BState *__restrict__ S, double *V,
-                                                  double *vt, double *vb, int to_user)
+                                                  const BState *__restrict__ S, double *Vc,
+                                                  const double *T, double *vt, double *vb,
+                                                  int to_user)
 {
     int b, k0, k1;
     if (!block_range(I, bt, nullptr, b, k0, k1)) return;
     const BInst in = I[b];
+    double *V = (to_user && S[b].vsel) ? const_cast<double *>(T) : Vc;
     const size_t mn = (size_t)in.m * in.n;
     const bool zero = to_user && S[b].ynorm == 0.0;
     for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
@@ -679,14 +713,17 @@ __global__ void bk_sum_counters(const int *__restrict__ c, int n, int *__restric
 }
 
 // GMRES cycle start for crossbars in their Newton step's GMRES solve
+// With from_f set, a crossbar's first cycle of a Newton step takes u_0 = F
+// unscaled (sig_0 = -1 / beta, so that sig_0 u_0 = -F / beta); otherwise v_0
+// is stored normalised.
 __global__ void bk_cycle_init(int count, BState *__restrict__ S, int *__restrict__ ctl,
                               double *__restrict__ g, int R, int max_krylov,
-                              double *__restrict__ sig)
+                              double *__restrict__ sig, int from_f)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= count) return;
-    if (sig) sig[(size_t)b * (R + 1)] = 1.0;     // v_0 is stored normalised
     BState &s = S[b];
+    if (sig) sig[(size_t)b * (R + 1)] = (from_f && s.first) ? -1.0 / s.beta : 1.0;
     s.restart = 0;
     const bool run = s.gm_todo && s.kry_step < max_krylov;
     ctl[4 * b + 0] = run ? 0 : 1;
@@ -946,6 +983,7 @@ __global__ void bk_ls_finish(int count, BState *__restrict__ S)
         s.fnorm = s.fn_trial;
         s.dsum = s.ds_trial;
         s.newton += 1;
+        s.vsel ^= 1;   // the trial buffer now holds the current voltages
     } else {
         // no decrease: the rounding floor (accepted below 1e-12 ||Y||) or a failure
         s.active = 0;
@@ -1500,7 +1538,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         G.precision = o.precision;
         G.restart = R;
         G.two_pass = (int)two_pass;
-        G.exec.resize(R, nullptr);
+        G.exec.resize(R + 1, nullptr);   // [R]: step 0 of a restart cycle (see below)
     }
     // pinned flag slots (64-bit, from int 16 of the host block): slot j for
     // Arnoldi step j, slot kCountSlot for count_now
@@ -1541,6 +1579,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     gs.ctl = w.ctl;
     gs.D = w.D;
     gs.V = w.V;
+    gs.v0 = w.V;
     gs.len = len;
     gs.sig = w.sig;
     gs.L = w.Lg;
@@ -1569,7 +1608,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         float *zj = w.Z + (size_t)j * len;
         double *wv = w.V + (size_t)(j + 1) * len;
         GroupedChain c = gc;
-        c.r = vj;
+        c.r = (j == 0) ? gs.v0 : vj;
         c.z = zj;
         // the previous update pass converted v_j (and folded it for the folded chains)
         c.r_split = (two_pass && j > 0) ? 1 : 0;
@@ -1629,12 +1668,12 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
                                         v_in + in.orow, vt, vt + mn, s));
         }
     } else if (o.flags & MCA_FLAG_INITIAL_GUESS)
-        hipLaunchKernelGGL(bk_user_io, gridB, blk, 0, s, B->d_inst, B->d_btab, w.S, w.Vc, v_t, v_b,
-                           0);
+        hipLaunchKernelGGL(bk_user_io, gridB, blk, 0, s, B->d_inst, B->d_btab, w.S, w.Vc, w.T, v_t,
+                           v_b, 0);
     else
         MCA_BTRY(launch_fill(w.Vc, 0.0, len, s));
     hipLaunchKernelGGL(bk_residual, gridB, blk, 0, s, B->d_inst, B->d_btab, (const int *)nullptr, g_dev,
-                       v_in, w.Vc, w.F, w.D, w.pa);
+                       v_in, w.Vc, (const double *)nullptr, (const BState *)nullptr, w.F, w.D, w.pa);
     hipLaunchKernelGGL(bk_inst_norms, dim3(cnt), blk, 0, s, B->d_inst, cnt, (const int *)nullptr,
                        w.pa, 0, w.S);
     if (o.flags & (MCA_FLAG_INITIAL_GUESS | MCA_FLAG_SWEEP_START)) {
@@ -1644,7 +1683,7 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, rjf, w.S, 5,
                            (const double *)nullptr, (const double *)nullptr, w.Vc);
         hipLaunchKernelGGL(bk_residual, gridB, blk, 0, s, B->d_inst, B->d_btab, rjf, g_dev, v_in,
-                           w.Vc, w.F, w.D, w.pa);
+                           w.Vc, (const double *)nullptr, (const BState *)nullptr, w.F, w.D, w.pa);
         hipLaunchKernelGGL(bk_inst_norms, dim3(cnt), blk, 0, s, B->d_inst, cnt, rjf, w.pa, 0, w.S);
     }
     MCA_BTRY(hipGetLastError());
@@ -1655,18 +1694,25 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         int active = 0;
         if ((st = count_now(&active)) != MCA_OK) return st;
         if (active == 0) break;
-        // flexible GMRES for every active crossbar: v_0 = -F / beta
-        hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, actf, w.S, 0, w.F,
-                           (const double *)nullptr, w.V);
-        for (;;) {
+        // flexible GMRES for every active crossbar: v_0 = -F / beta, or with
+        // the two-pass form (eager launches) u_0 = F read in place, sig_0 =
+        // -1 / beta; restart cycles keep v_0 = r / beta in slot 0
+        const bool v0_from_f = two_pass;
+        if (!v0_from_f)
+            hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, actf, w.S, 0, w.F,
+                               (const double *)nullptr, w.V);
+        for (bool first_cycle = true;; first_cycle = false) {
+            gs.v0 = (v0_from_f && first_cycle) ? w.F : w.V;
             hipLaunchKernelGGL(bk_cycle_init, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.ctl, w.g, R,
-                               o.max_krylov, two_pass ? w.sig : nullptr);
+                               o.max_krylov, two_pass ? w.sig : nullptr, v0_from_f ? 1 : 0);
             for (int j = 0; j < R; ++j) {
                 // (every kernel that wrote slot j before has completed: the last
                 // wait of the previous cycle came after it in stream order)
                 __atomic_store_n(&flag[j], 0LL, __ATOMIC_RELAXED);
                 if (graph) {
-                    hipGraphExec_t &ex = G.exec[j];
+                    // step 0 reads u_0 from F in a Newton step's first cycle and
+                    // from slot 0 of V in its restarts: one graph each
+                    hipGraphExec_t &ex = G.exec[(j == 0 && gs.v0 != w.F) ? R : j];
                     if (!ex) {
                         MCA_BTRY(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
                         const hipError_t e1 = enqueue_step(j, G.cap);
@@ -1718,10 +1764,10 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         // damped update with a per-crossbar line search
         hipLaunchKernelGGL(bk_ls_init, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.khist, k);
         for (int round = 0; round < 32; ++round) {
-            hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, lsf, w.S, 1, w.Vc,
-                               w.X, w.T);
+            hipLaunchKernelGGL(bk_trial, gridB, blk, 0, s, B->d_inst, B->d_btab, lsf, w.S, w.X, w.Vc,
+                               w.T);
             hipLaunchKernelGGL(bk_residual, gridB, blk, 0, s, B->d_inst, B->d_btab, lsf, g_dev,
-                               v_in, w.T, w.Ft, w.Dt, w.pa);
+                               v_in, w.T, w.Vc, w.S, w.Ft, w.Dt, w.pa);
             hipLaunchKernelGGL(bk_inst_norms, dim3(cnt), blk, 0, s, B->d_inst, cnt, lsf, w.pa, 1,
                                w.S);
             hipLaunchKernelGGL(bk_ls_check, dim3(cb), dim3(ct), 0, s, cnt, w.S, w.counter);
@@ -1729,16 +1775,24 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
             if ((st = count_now(&todo)) != MCA_OK) return st;
             if (todo == 0) break;
         }
-        // accepted crossbars move to the trial point
-        hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, accf, w.S, 4, w.T,
-                           (const double *)nullptr, w.Vc);
-        hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, accf, w.S, 4, w.Ft,
-                           (const double *)nullptr, w.F);
-        hipLaunchKernelGGL(bk_copy_cross, gridB, blk, 0, s, B->d_inst, B->d_btab, accf, w.Dt, w.D);
+        // accepted crossbars move to the trial point: their voltages by the
+        // buffer flag (bk_ls_finish), F and D by exchanging the arrays (every
+        // crossbar still active has accepted; the others no longer read them),
+        // or with captured steps, which hold D's address, by copies
+        if (graph) {
+            hipLaunchKernelGGL(bk_axpy, gridB, blk, 0, s, B->d_inst, B->d_btab, accf, w.S, 4, w.Ft,
+                               (const double *)nullptr, w.F);
+            hipLaunchKernelGGL(bk_copy_cross, gridB, blk, 0, s, B->d_inst, B->d_btab, accf, w.Dt,
+                               w.D);
+        } else {
+            std::swap(w.F, w.Ft);
+            std::swap(w.D, w.Dt);
+            gs.D = w.D;
+        }
         hipLaunchKernelGGL(bk_ls_finish, dim3(cb), dim3(ct), 0, s, cnt, w.S);
         MCA_BTRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(bk_user_io, gridB, blk, 0, s, B->d_inst, B->d_btab, w.S, w.Vc, v_t, v_b, 1);
+    hipLaunchKernelGGL(bk_user_io, gridB, blk, 0, s, B->d_inst, B->d_btab, w.S, w.Vc, w.T, v_t, v_b, 1);
     MCA_BTRY(hipGetLastError());
     // per-crossbar results
     std::vector<BState> S(cnt);
