@@ -333,6 +333,20 @@ __global__ __launch_bounds__(TPB) void bk_jacobian_proj(BGs a)
     }
 }
 
+// Sum of p[u] over u = lane, lane + 64, ... < n (one wave; the result in
+// every lane), with eight loads in flight per lane and a fixed order.
+__device__ __forceinline__ double wave_strided_sum(const double *__restrict__ p, int n, int lane)
+{
+    double x[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int u = lane;
+    for (; u + 7 * 64 < n; u += 8 * 64) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] += p[u + t * 64];
+    }
+    for (int t = 0; u < n; u += 64, ++t) x[t & 7] += p[u];
+    return dev::wave_sum(((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7])));
+}
+
 // One block per crossbar: s_q = sig_q <w, u_q> from the crossbar's partials,
 // then (I + L) h = s by forward substitution; h to the crossbar's H column j.
 __global__ __launch_bounds__(TPB) void bk_gs_coef(BGs a)
@@ -347,9 +361,7 @@ __global__ __launch_bounds__(TPB) void bk_gs_coef(BGs a)
     __shared__ double Ls[kGsMaxV][kGsMaxV];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int q = wave; q < nv; q += TPB / 64) {
-        double x = 0.0;
-        for (int u = lane; u < in.nblk; u += 64) x += p[(size_t)q * in.nblk + u];
-        x = dev::wave_sum(x);
+        const double x = wave_strided_sum(p + (size_t)q * in.nblk, in.nblk, lane);
         if (lane == 0) sv[q] = sg[q] * x;
     }
     const double *Lb = a.L + (size_t)b * R1 * R1;
@@ -814,9 +826,7 @@ __global__ __launch_bounds__(TPB) void bk_gs_finish(BGs a)
     __shared__ double sv[kGsMaxV + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int q = wave; q <= nv; q += TPB / 64) {
-        double x = 0.0;
-        for (int u = lane; u < in.nblk; u += 64) x += p[(size_t)q * in.nblk + u];
-        x = dev::wave_sum(x);
+        const double x = wave_strided_sum(p + (size_t)q * in.nblk, in.nblk, lane);
         if (lane == 0) sv[q] = x;
     }
     __syncthreads();
