@@ -908,8 +908,9 @@ hipError_t chain(const LowPrecChain &c, hipStream_t s)
         // into two products of half the depth on folded data.  The modes run
         // symmetric first (eigenvalues lbp).
         const int h = m / 2;
-        // 0. r -> folded rows (sums, then differences), operand format
-        {
+        // 0. r -> folded rows (sums, then differences), operand format (unless
+        //    the pass that made r wrote them)
+        if (!c.r_split) {
             const int blocks = (int)std::min<size_t>(((size_t)h * n + 255) / 256, 4096);
             hipLaunchKernelGGL(k_split_fold<MODE>, dim3(blocks), dim3(256), 0, s, c.rt, c.rb, m, n,
                                c.x[0].p[0], c.x[0].p[1], c.x[1].p[0], c.x[1].p[1], c.skip);

@@ -560,10 +560,8 @@ __global__ __launch_bounds__(NT) void k_gs_update(GsStep a)
     const double2 *V2 = reinterpret_cast<const double2 *>(a.V);
     const size_t len2 = (size_t)a.m * a.n, ldv2 = a.ldv / 2;
     const size_t first = (size_t)blockIdx.x * NT + threadIdx.x, stride = (size_t)gridDim.x * NT;
-    const size_t steps = first < len2 ? (len2 - 1 - first) / stride + 1 : 0;
-#pragma unroll 1
-    for (size_t t = steps; t-- > 0;) {
-        const size_t k = first + t * stride;
+    // w -= sum_q c_q v_q at pair k, with the partial sums
+    auto update = [&](size_t k) -> double2 {
         double2 vq[MAXV];
         double2 x = w2[k];
 #pragma unroll
@@ -573,27 +571,101 @@ __global__ __launch_bounds__(NT) void k_gs_update(GsStep a)
             x.y -= c[q] * vq[q].y;
         }
         w2[k] = x;
-        if (a.xp[0][0]) {   // as k_split: FP64 -> FP32 -> bfloat16 hi, lo = rest
-            const size_t mn = (size_t)a.m * a.n;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                size_t e = 2 * k + h;
-                const int layer = e < mn ? 0 : 1;
-                e -= layer * mn;
-                const float f = (float)(h ? x.y : x.x);
-                if (a.prec == MCA_PREC_FP32) {
-                    static_cast<float *>(a.xp[layer][0])[e] = f;
-                } else {
-                    const __bf16 hi = (__bf16)f;
-                    static_cast<__bf16 *>(a.xp[layer][0])[e] = hi;
-                    if (a.prec == MCA_PREC_BF16X3)
-                        static_cast<__bf16 *>(a.xp[layer][1])[e] = (__bf16)(f - (float)hi);
-                }
-            }
-        }
 #pragma unroll
         for (int q = 0; q < MAXV; ++q) acc[q] += x.x * vq[q].x + x.y * vq[q].y;
         acc[MAXV] += x.x * x.x + x.y * x.y;
+        return x;
+    };
+    // as k_split: FP64 -> FP32 -> bfloat16 hi, lo = rest
+    auto put = [&](int layer, size_t e, double v) {
+        const float f = (float)v;
+        if (a.prec == MCA_PREC_FP32) {
+            static_cast<float *>(a.xp[layer][0])[e] = f;
+        } else {
+            const __bf16 hi = (__bf16)f;
+            static_cast<__bf16 *>(a.xp[layer][0])[e] = hi;
+            if (a.prec == MCA_PREC_BF16X3) static_cast<__bf16 *>(a.xp[layer][1])[e] = (__bf16)(f - (float)hi);
+        }
+    };
+    if (a.xp[0][0] && a.fold_h) {
+        // the folded chain's input: pairs of rows (i, m - 1 - i), written as
+        // row i (sum) and row h + i (difference)
+        const size_t half = (size_t)a.fold_h * a.n, mn = len2;
+        if constexpr (MAXV <= 4) {
+            // two columns at a time where n is even
+            if (a.n % 2 == 0) {
+                const int n2 = a.n / 2;
+                const size_t half2 = half / 2, units = 2 * half2, layer2 = len2 / 2;
+                const size_t steps = first < units ? (units - 1 - first) / stride + 1 : 0;
+#pragma unroll 1
+                for (size_t t = steps; t-- > 0;) {
+                    const size_t u = first + t * stride;
+                    const int layer = u < half2 ? 0 : 1;
+                    const size_t r = u - layer * half2;
+                    const int i = (int)(r / n2), c2 = (int)(r - (size_t)i * n2);
+                    const double2 x0 = update(layer * layer2 + r);
+                    const double2 x1 = update(layer * layer2 + (size_t)(a.m - 1 - i) * n2 + c2);
+                    put(layer, 2 * r, x0.x + x1.x);
+                    put(layer, 2 * r + 1, x0.y + x1.y);
+                    put(layer, 2 * r + half, x0.x - x1.x);
+                    put(layer, 2 * r + 1 + half, x0.y - x1.y);
+                }
+                goto folded_done;
+            }
+        }
+        {
+            // one element of each row per thread (a pair of double2 with eight
+            // basis vectors would not fit the registers of 1024-thread blocks)
+            const size_t units = 2 * half;
+            const size_t steps = first < units ? (units - 1 - first) / stride + 1 : 0;
+            auto update1 = [&](size_t e) -> double {
+                double vq[MAXV];
+                double x = a.w[e];
+#pragma unroll
+                for (int q = 0; q < MAXV; ++q) {
+                    vq[q] = (q < nv) ? a.V[q * a.ldv + e] : 0.0;
+                    x -= c[q] * vq[q];
+                }
+                a.w[e] = x;
+#pragma unroll
+                for (int q = 0; q < MAXV; ++q) acc[q] += x * vq[q];
+                acc[MAXV] += x * x;
+                return x;
+            };
+#pragma unroll 1
+            for (size_t t = steps; t-- > 0;) {
+                const size_t u = first + t * stride;
+                const int layer = u < half ? 0 : 1;
+                const size_t r = u - layer * half;
+                const int i = (int)(r / a.n), jj = (int)(r - (size_t)i * a.n);
+                const double x0 = update1(layer * mn + r);
+                const double x1 = update1(layer * mn + (size_t)(a.m - 1 - i) * a.n + jj);
+                put(layer, r, x0 + x1);
+                put(layer, r + half, x0 - x1);
+            }
+        }
+    folded_done:;
+    } else {
+        // pairs of elements (the vector length 2mn and the slot stride are even).
+        // The grid walks the vectors from their end back to their start: the first
+        // pass of this Arnoldi step read them front to back just before, so the
+        // parts it read last are the likeliest still in the memory-side cache.
+        const size_t steps = first < len2 ? (len2 - 1 - first) / stride + 1 : 0;
+#pragma unroll 1
+        for (size_t t = steps; t-- > 0;) {
+            const size_t k = first + t * stride;
+            const double2 x = update(k);
+            if (a.xp[0][0]) {
+                const size_t mn = (size_t)a.m * a.n;
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    size_t e = 2 * k + hh;
+                    const int layer = e < mn ? 0 : 1;
+                    e -= layer * mn;
+                    put(layer, e, hh ? x.y : x.x);
+                }
+            }
+        }
     }
     // block sums of <x, u_q> (q < nv) and ||x||^2 as values 0..nv
     __shared__ double sh[MAXV + 1][NT / 64];

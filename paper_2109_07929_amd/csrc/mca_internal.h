@@ -155,7 +155,7 @@ struct LowPrecChain {
     LpPlanes QnT, QmT, Qm, Qn;          // eigenbases
     const double *lt, *lb;              // eigenvalues of G_top, G_bot
     const double *rt, *rb;              // input r (FP64)
-    int r_split;                        // x already holds r in operand format
+    int r_split;                        // x already holds r in operand format (folded, with fold)
     LpPlanes x[2], u[2], w[2];          // workspace: split r and two intermediates, m*n each
     double *zt, *zb;                    // output z (FP64)
     // persymmetric G_bot with m / 2 a multiple of 128: the folded chain, with
@@ -305,6 +305,10 @@ struct GsStep {
     // bfloat16 hi [+ lo]), the conversion the next step's chain would make
     void *xp[2][2];
     int prec;
+    // with fold_h (= m / 2) set as well, the planes take the persymmetric fold
+    // of the new vector (rows i < m/2: x_i + x_{m-1-i}, rows m/2 + i:
+    // x_i - x_{m-1-i}), the input of the folded chain
+    int fold_h;
     // with post_rt set (literal form), pass 0 also forms the preconditioner's
     // last step z_b = ((G_t + a1 I) z_t - r_t) / a1 from z_t, stores it at
     // zb_store and uses it in place of zb

@@ -528,7 +528,7 @@ mca_status precond_run(const mca_plan *P, int form, int precision, double a1, do
             c.lbp = d.lbp;
         }
         c.rt = rt; c.rb = rb;
-        c.r_split = (r_split && !c.fold) ? 1 : 0;
+        c.r_split = r_split ? 1 : 0;
         for (int b = 0; b < 2; ++b) {
             c.x[b] = w.lp[b];
             c.u[b] = w.lp[2 + b];
@@ -688,10 +688,9 @@ struct Fgmres {
         ldh = R + 1;
         two_pass = !(o->flags & MCA_FLAG_MGS_PASSES) && R <= kGsMaxV;
         // the reduced-precision per-mode chain: the update pass converts the new
-        // vector into the chain's operand planes itself
-        // (the folded chain splits its input itself: its rows pair i with m - 1 - i)
-        lp_fused = two_pass && o->precond == MCA_PRECOND_PERMODE && o->precision != MCA_PREC_FP64 &&
-                   !lp_fold(P);
+        // vector into the chain's operand planes itself (for the folded chain,
+        // with its rows i and m - 1 - i folded)
+        lp_fused = two_pass && o->precond == MCA_PRECOND_PERMODE && o->precision != MCA_PREC_FP64;
         // the literal form's last step (z_b from z_t) runs inside the Jacobian pass
         post_fused = two_pass && o->precond == MCA_PRECOND_LITERAL && o->precision == MCA_PREC_FP64;
         // persymmetric literal form: step j's finish shares a launch with step j + 1's
@@ -726,6 +725,7 @@ struct Fgmres {
             for (int b = 0; b < 2; ++b)
                 for (int pl = 0; pl < 2; ++pl) gs.xp[b][pl] = w.pw.lp[b].p[pl];
             gs.prec = o->precision;
+            gs.fold_h = lp_fold(P) ? P->geom.m / 2 : 0;
         }
         if (merge_fin) gs.shift = w.nsc;
     }
