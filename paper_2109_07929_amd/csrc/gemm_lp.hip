@@ -410,7 +410,10 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
     };
 
     bool done = false;
-    if constexpr (TS == 128 && KS == 32 && MODE != MCA_PREC_FP32 && NT == 512) {
+    // (128 x 128 tiles, one wave per 16-row block of an operand plane; the same
+    // loop on 64 x 64 tiles, four waves, two workgroups per CU instead of three,
+    // measured slower: Monte-Carlo batch 41.1 vs 40.2 ms)
+    if constexpr (TS == 128 && KS == 32 && MODE != MCA_PREC_FP32 && WAVES == TS / 16) {
         if (fast_m && fast_n && K % KS == 0 && K >= 3 * KS) {
             // Interior tile: every slice goes from global memory straight into
             // LDS (global_load_lds_dwordx4, 16 bytes per lane), three buffers,
@@ -419,14 +422,14 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
             // buffer and slice k + 3 is loaded into the buffer slice k left, so
             // that the LDS reads and the loads overlap the MFMAs.  Layout of a
             // buffer: operand tile t, plane p, row r, 16-byte chunk c of the
-            // row's 32 values at byte t sizeof(Tile) + p 8192 + 64 r +
+            // row's 32 values at byte t sizeof(Tile) + p 64 TS + 64 r +
             // 16 (c ^ ((r >> 2) & 3)), so that each lane quad loads one row's
             // 64 contiguous bytes (the load writes LDS in lane order) and the
             // fragment reads are free of bank conflicts.
             __shared__ SliceBuf L2;
-            constexpr int NI = (NA + NBB) * PL * 8;   // 1 KB instructions per slice
-            constexpr int NQ = NI / 8;                 // per wave
-            static_assert(NI % 8 == 0, "instructions per wave");
+            constexpr int NQ = (NA + NBB) * PL;   // 1 KB loads per wave and slice
+            constexpr int kPlaneBytes = TS * 64;  // one plane of a slice: TS rows of 32 values
+            static_assert(sizeof(TileT) == PL * kPlaneBytes, "slice layout");
             typedef const void __attribute__((address_space(1))) *gptr;
             typedef void __attribute__((address_space(3))) *lptr;
             using I0 = std::integral_constant<int, 0>;
@@ -471,7 +474,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
                     const int t = q / PL, pl = q % PL;
                     __builtin_amdgcn_global_load_lds(
                         (gptr)(sbase[q] + 2 * (size_t)k0 + (t < NA ? voff_a : voff_b)),
-                        (lptr)(lb + t * (int)sizeof(TileT) + pl * 8192), 16, 0, 0);
+                        (lptr)(lb + t * (int)sizeof(TileT) + pl * kPlaneBytes), 16, 0, 0);
                 }
             };
             using FA = bf8[NA][PL][FI];
@@ -480,7 +483,8 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
                 const char *lb = bufp(bc);
                 auto frag = [&](int t, int pl, int row) -> bf8 {
                     const int c = (lane >> 4) ^ ((row >> 2) & 3);
-                    return *reinterpret_cast<const bf8 *>(lb + t * (int)sizeof(TileT) + pl * 8192 + row * 64 + c * 16);
+                    return *reinterpret_cast<const bf8 *>(lb + t * (int)sizeof(TileT) + pl * kPlaneBytes +
+                                                          row * 64 + c * 16);
                 };
 #pragma unroll
                 for (int b = 0; b < NA; ++b)
