@@ -423,9 +423,12 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
             // that the LDS reads and the loads overlap the MFMAs.  Layout of a
             // buffer: operand tile t, plane p, row r, 16-byte chunk c of the
             // row's 32 values at byte t sizeof(Tile) + p 64 TS + 64 r +
-            // 16 (c ^ ((r >> 2) & 3)), so that each lane quad loads one row's
+            // 16 (c ^ ((r >> 1) & 3)), so that each lane quad loads one row's
             // 64 contiguous bytes (the load writes LDS in lane order) and the
-            // fragment reads are free of bank conflicts.
+            // eight rows of a fragment read that one pass serves fall on
+            // distinct 16-byte bank groups of a 128-byte period (rocprofv3
+            // SQ_LDS_BANK_CONFLICT: half of the LDS cycles were conflicts with
+            // the chunk swizzled by bits 2-3 of the row).
             __shared__ SliceBuf L2;
             constexpr int NQ = (NA + NBB) * PL;   // 1 KB loads per wave and slice
             constexpr int kPlaneBytes = TS * 64;  // one plane of a slice: TS rows of 32 values
@@ -444,11 +447,11 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
             // Wave w loads row block w (16 rows) of every operand plane: its
             // instruction q takes operand tile q / PL, plane q % PL.  Each lane
             // quad loads one row's 64 bytes, chunk c of the row to chunk
-            // c ^ ((row >> 2) & 3) of LDS, which for 16-row blocks is
-            // c ^ ((lane >> 4) & 3).  Addresses: a wave-uniform base (scalar
+            // c ^ ((row >> 1) & 3) of LDS, which for 16-row blocks is
+            // c ^ ((lane >> 3) & 3).  Addresses: a wave-uniform base (scalar
             // registers) plus a per-lane byte offset, one per operand side.
             const int wv = __builtin_amdgcn_readfirstlane(wave);
-            const int lc = ((lane & 3) ^ ((lane >> 4) & 3)) * 16;
+            const int lc = ((lane & 3) ^ ((lane >> 3) & 3)) * 16;
             const unsigned voff_a = (unsigned)((lane >> 2) * lda * 2 + lc);
             const unsigned voff_b = (unsigned)((lane >> 2) * ldb * 2 + lc);
             const char *sbase[NQ];
@@ -482,7 +485,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
             auto read = [&](auto bc, FA &fa, FB &fb) {
                 const char *lb = bufp(bc);
                 auto frag = [&](int t, int pl, int row) -> bf8 {
-                    const int c = (lane >> 4) ^ ((row >> 2) & 3);
+                    const int c = (lane >> 4) ^ ((row >> 1) & 3);
                     return *reinterpret_cast<const bf8 *>(lb + t * (int)sizeof(TileT) + pl * kPlaneBytes +
                                                           row * 64 + c * 16);
                 };
