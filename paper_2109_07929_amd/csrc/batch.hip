@@ -712,12 +712,16 @@ __global__ void bk_newton_begin(const BInst *__restrict__ I, int count, BState *
 // Sum of the per-block counters into out[0] and, with host_out, into a pinned
 // host flag slot as (1 << 32) | sum in one release store at system scope (the
 // host cleared the slot before enqueueing this kernel and spins on it).
+// (one wave: each lane sums every 64th value, then the lanes' sums)
 __global__ void bk_sum_counters(const int *__restrict__ c, int n, int *__restrict__ out,
                                 long long *__restrict__ host_out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0 || threadIdx.x >= 64) return;
     int s = 0;
-    for (int i = 0; i < n; ++i) s += c[i];
+    for (int i = threadIdx.x; i < n; i += 64) s += c[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (threadIdx.x != 0) return;
     out[0] = s;
     if (host_out)
         __hip_atomic_store(host_out, (long long)((1ULL << 32) | (unsigned)s), __ATOMIC_RELEASE,
@@ -860,10 +864,30 @@ __global__ void bk_cycle_end(int count, BState *__restrict__ S, const double *__
             const double *Hb = H + (size_t)b * hsize;
             const double *gb = g + (size_t)b * (R + 1);
             double *y = Y + (size_t)b * R;
-            for (int i = k - 1; i >= 0; --i) {
-                double t = gb[i];
-                for (int cc = i + 1; cc < k; ++cc) t -= Hb[(size_t)cc * ldh + i] * y[cc];
-                y[i] = t / Hb[(size_t)i * ldh + i];
+            if (k <= kGsMaxV) {
+                // back substitution with y in registers (the loops run to the
+                // bound so that every index is a constant)
+                double yl[kGsMaxV];
+#pragma unroll
+                for (int i = kGsMaxV - 1; i >= 0; --i) {
+                    yl[i] = 0.0;
+                    if (i < k) {
+                        double t = gb[i];
+#pragma unroll
+                        for (int cc = i + 1; cc < kGsMaxV; ++cc)
+                            if (cc < k) t -= Hb[(size_t)cc * ldh + i] * yl[cc];
+                        yl[i] = t / Hb[(size_t)i * ldh + i];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < kGsMaxV; ++i)
+                    if (i < k) y[i] = yl[i];
+            } else {
+                for (int i = k - 1; i >= 0; --i) {
+                    double t = gb[i];
+                    for (int cc = i + 1; cc < k; ++cc) t -= Hb[(size_t)cc * ldh + i] * y[cc];
+                    y[i] = t / Hb[(size_t)i * ldh + i];
+                }
             }
             if (sig)   // an unnormalised basis: the update takes y_i sig_i
                 for (int i = 0; i < k; ++i) y[i] *= sig[(size_t)b * (R + 1) + i];
