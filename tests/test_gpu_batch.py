@@ -84,6 +84,50 @@ def test_batch_matches_single_solves():
         assert err <= TOL
 
 
+def nonlinear_batch():
+    # drives of 2-3 V against v0 = 0.25 V and devices up to 1e-2 S: the full
+    # Newton step overshoots the sinh devices, so the line search halves it
+    cases = [(24, 20, 1e-3, 2.0, 5), (40, 36, 1e-2, 3.0, 6), (64, 64, 1e-2, 2.0, 7),
+             (33, 70, 1e-3, 2.0, 8), (48, 40, 1e-2, 5.0, 9), (20, 24, 3e-2, 4.0, 10),
+             (32, 32, 1e-2, 6.0, 11), (28, 52, 5e-2, 3.0, 12)]
+    return [synth.crossbar(m, n, seed=sd, g_lo=1e-5, g_hi=ghi, v_hi=vhi)
+            for m, n, ghi, vhi, sd in cases]
+
+
+@pytest.mark.parametrize("prec", [B.MCA_PREC_FP32, B.MCA_PREC_BF16X3])
+def test_batch_line_search_backtracks(prec):
+    """Crossbars whose Newton steps are damped: the trial voltages go to the
+    buffer that does not hold the current ones and accepted crossbars switch
+    buffers, so halved trials, crossbars accepting at different rounds and
+    crossbars that stopped earlier must all end at the oracle's steady state
+    (1e-8) and agree with the single-crossbar solver."""
+    cbs = nonlinear_batch()
+    say(f"batch line search prec={prec}: " + " ".join(f"{c.geom.m}x{c.geom.n}" for c in cbs))
+    _, vts, vbs, status, stats = batch_solve(cbs, precision=prec)
+    assert status == B.MCA_OK
+    # several crossbars halve, some more than once, and they stop at different steps
+    assert sum(s.backtracks > 0 for s in stats) >= 2
+    assert max(s.backtracks for s in stats) >= 2
+    assert len({s.newton_iters for s in stats}) > 1
+    for b, c in enumerate(cbs):
+        rt, rb, _, _ = oracle.solve(c.geom, c.g_dev, c.v_in, method="band")
+        err = rel_err(vts[b], vbs[b], rt, rb)
+        st = stats[b]
+        plan = Plan(c.geom)
+        o = B.options(precond=B.MCA_PRECOND_PERMODE, precision=prec)
+        vt1, vb1, s1, st1 = plan.solve(torch.from_numpy(c.g_dev).cuda(),
+                                       torch.from_numpy(c.v_in).cuda(), o)
+        torch.cuda.synchronize()
+        err1 = rel_err(vts[b], vbs[b], vt1.cpu().numpy(), vb1.cpu().numpy())
+        say(f"  {c.geom.m}x{c.geom.n}: newton {st.newton_iters} backtracks {st.backtracks} "
+            f"(single: {st1.newton_iters}, {st1.backtracks}) err {err:.1e} vs single {err1:.1e}")
+        assert s1 == B.MCA_OK
+        assert st.rel_residual <= 1e-10
+        assert err <= TOL
+        assert err1 <= TOL
+        assert st.newton_iters == st1.newton_iters and st.backtracks == st1.backtracks
+
+
 @pytest.mark.parametrize("restart", [1, 3])
 def test_batch_restarts(restart):
     cbs = ragged_batch(seed=5)
