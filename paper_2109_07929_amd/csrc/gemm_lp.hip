@@ -19,10 +19,14 @@
 // eigenbases are converted once in the plan, the FP64 input r by a split
 // kernel, and every intermediate by the epilogue of the product that makes it.
 //
-// Tiling: 64 x 64 output tile per 256-thread workgroup (four waves of 32 x 32,
-// 2 x 2 MFMA tiles each); K staged through LDS in double-buffered 64-deep
-// slices with two slices of global loads in flight.  One operand may have two
-// batches (the two layers) that share the other operand.
+// Tiling: 64 x 64 output tiles (four waves of 32 x 32, K slices of 64, or of
+// 32 in launches with many tiles) or, where those still give 256 or more
+// workgroups, 128 x 128 tiles (eight waves, K slices of 32).  K is staged
+// through LDS either from registers (two slices of global loads in flight,
+// double-buffered LDS) or, for interior 128 x 128 split-BF16 / BF16 tiles,
+// straight from global memory into three LDS buffers in a software-pipelined
+// loop (see gemm_nt_tile).  One operand may have two batches (the two layers)
+// that share the other operand.
 //
 // LDS layout of a staged slice (register-staged path): 16-byte chunks, in
 // sub-slices of four chunks per row (32 bf16 or 16 floats of K).  Chunk c' of
