@@ -258,7 +258,7 @@ def test_batch_folded_and_full_chains(prec):
     tile, or unequal bottom ends), n off the tile grid.  Every crossbar against the
     oracle."""
     shapes = [(128, 100, 0.1), (192, 72, 0.1), (256, 136, 0.1), (256, 136, 0.07), (320, 64, 0.1),
-              (128, 200, 0.1)]
+              (128, 200, 0.1), (256, 135, 0.1)]
     cbs = [synth.crossbar(m, n, seed=20 + k, g_bot_end1=e1) for k, (m, n, e1) in enumerate(shapes)]
     bt, vts, vbs, status, stats = batch_solve(cbs, precision=prec)
     assert bt.product_tile == 64

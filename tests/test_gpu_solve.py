@@ -316,11 +316,12 @@ def test_mixed_precision_solve_1024(prec):
 
 @pytest.mark.parametrize("prec", [B.MCA_PREC_FP32, B.MCA_PREC_BF16X3])
 @pytest.mark.parametrize("m,n,ends", [(512, 300, (0.1, 0.1)), (256, 136, (0.1, 0.1)),
-                                      (512, 300, (0.1, 0.07))])
+                                      (256, 135, (0.1, 0.1)), (512, 300, (0.1, 0.07))])
 def test_mixed_precision_folded_chain(prec, m, n, ends):
     """Equal bottom terminations with m/2 a multiple of 128 fold the reduced-precision
     chain's Q_m-side products (half depth, interleaved rows, pairwise unfold); n off
-    the tile grid cuts the products' other side.  Unequal ends keep the full chain.
+    the tile grid cuts the products' other side, and odd n makes the update pass
+    fold one element of each row at a time.  Unequal ends keep the full chain.
     Both against the oracle."""
     say(f"mixed solve {m}x{n} ends {ends} prec={prec}")
     cb = synth.crossbar(m, n, seed=7, g_bot_end0=ends[0], g_bot_end1=ends[1])
