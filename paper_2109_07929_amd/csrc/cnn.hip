@@ -91,16 +91,26 @@ __global__ __launch_bounds__(CT) void k_conv(ConvArgs a)
     const int m = a.m, n = a.n;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    // input tile with a one-crosspoint halo; zeros outside the array
+    // input tile with a one-crosspoint halo; zeros outside the array.  All of
+    // a thread's loads go out before its LDS stores (a load-store loop would
+    // wait for each load in turn).
     constexpr int HPX = (TR + 2) * (TC + 2);
-    for (int q = threadIdx.x; q < HPX * 4; q += CT) {
+    constexpr int NLD = (HPX * 4 + CT - 1) / CT;
+    u4 ld[NLD];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int q = threadIdx.x + k * CT;
         const int px = q >> 2, part = q & 3;
         const int hr = px / (TC + 2), hc = px - hr * (TC + 2);
         const int i = i0 + hr - 1, j = j0 + hc - 1;
-        u4 v = {0u, 0u, 0u, 0u};
-        if (i >= 0 && i < m && j >= 0 && j < n)
-            v = *reinterpret_cast<const u4 *>(a.in + (((size_t)b * m + i) * n + j) * NC + part * 8);
-        *reinterpret_cast<u4 *>(&sIn[px * PIX + part * 8]) = v;
+        ld[k] = u4{0u, 0u, 0u, 0u};
+        if (q < HPX * 4 && i >= 0 && i < m && j >= 0 && j < n)
+            ld[k] = *reinterpret_cast<const u4 *>(a.in + (((size_t)b * m + i) * n + j) * NC + part * 8);
+    }
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int q = threadIdx.x + k * CT;
+        if (q < HPX * 4) *reinterpret_cast<u4 *>(&sIn[(q >> 2) * PIX + (q & 3) * 8]) = ld[k];
     }
     // weights: A fragments (row = output channel lane%16, K = 8 input channels)
     bf8 wa[TAPS][2];
