@@ -361,8 +361,16 @@ __global__ __launch_bounds__(CT) void k_meanfield(int m, int n, const double *__
 {
     const int b = blockIdx.x;
     const size_t mn = (size_t)m * n;
-    double acc = 0.0;
-    for (size_t k = threadIdx.x; k < mn; k += CT) acc += g_dev[(size_t)b * mn + k];
+    const double *gd = g_dev + (size_t)b * mn;
+    // eight loads in flight per thread, summed in a fixed order
+    double part[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    size_t k0 = threadIdx.x;
+    for (; k0 + 7 * CT < mn; k0 += 8 * CT) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) part[t] += gd[k0 + t * CT];
+    }
+    for (int t = 0; k0 < mn; k0 += CT, ++t) part[t & 7] += gd[k0];
+    double acc = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
     __shared__ double sh[CT / 64];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
@@ -374,14 +382,24 @@ __global__ __launch_bounds__(CT) void k_meanfield(int m, int n, const double *__
     const double g = wires[3 * b], gsrc = wires[3 * b + 1], gend = wires[3 * b + 2];
     double *ph = phi + (size_t)b * n, *c = cp + (size_t)b * n;
     // forward elimination: diag_k = g (neighbours) + end terms + a, off = -g
+    // (the previous step's c' and phi' carried in registers, not re-read)
+    double cprev = 0.0, pprev = 0.0;
     for (int k = 0; k < n; ++k) {
         const double diag = ((k > 0) ? g : gsrc) + ((k + 1 < n) ? g : gend) + a;
         const double rhs = (k == 0) ? gsrc : 0.0;
-        const double den = (k > 0) ? diag + g * c[k - 1] : diag;   // diag - (-g) c'[k-1]
-        c[k] = (k + 1 < n) ? -g / den : 0.0;
-        ph[k] = (k > 0) ? (rhs + g * ph[k - 1]) / den : rhs / den;
+        const double den = (k > 0) ? diag + g * cprev : diag;   // diag - (-g) c'[k-1]
+        const double ck = (k + 1 < n) ? -g / den : 0.0;
+        const double pk = (k > 0) ? (rhs + g * pprev) / den : rhs / den;
+        c[k] = ck;
+        ph[k] = pk;
+        cprev = ck;
+        pprev = pk;
     }
-    for (int k = n - 2; k >= 0; --k) ph[k] -= c[k] * ph[k + 1];
+    double pnext = ph[n - 1];
+    for (int k = n - 2; k >= 0; --k) {
+        pnext = ph[k] - c[k] * pnext;
+        ph[k] = pnext;
+    }
 }
 
 // input channels (zero-padded to 32)
