@@ -309,13 +309,13 @@ __global__ __launch_bounds__(TPB) void bk_jacobian_proj(BGs a)
     double acc[MAXV];
 #pragma unroll
     for (int q = 0; q < MAXV; ++q) acc[q] = 0.0;
+    // (w = sig_j J z~_j is not stored: the update pass forms it again, with the
+    // same arithmetic, from z~_j and D, which it reads in place of w)
     for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
         double y1, y2;
         jac_point(in, zt, zb, d[k], k, y1, y2);
         y1 *= sj;
         y2 *= sj;
-        a.W[base + k] = y1;
-        a.W[base + mn + k] = y2;
 #pragma unroll
         for (int q = 0; q < MAXV; ++q)
             if (q < nv) {
@@ -415,10 +415,19 @@ __global__ __launch_bounds__(TPB) void bk_gs_update(BGs a)
     for (int q = 0; q < MAXV; ++q) c[q] = (q < nv) ? hcol[q] * sg[q] : 0.0;
 #pragma unroll
     for (int q = 0; q <= MAXV; ++q) acc[q] = 0.0;
-    // w -= sum_q c_q v_q at element e; accumulates <w, v_q> and ||w||^2
-    auto update = [&](size_t e) -> double {
+    // w = sig_j J z~_j at crosspoint k (both layers), as the projection pass
+    // formed it
+    const float *zt = a.Z + base, *zb = zt + mn;
+    const double *d = a.D + in.ox;
+    const double sj = sg[j];
+    auto jw = [&](size_t k, double &y1, double &y2) {
+        jac_point(in, zt, zb, d[k], (int)k, y1, y2);
+        y1 *= sj;
+        y2 *= sj;
+    };
+    // w -= sum_q c_q v_q at element e (w there: x); accumulates <w, v_q> and ||w||^2
+    auto update = [&](size_t e, double x) -> double {
         double vq[MAXV];
-        double x = a.W[e];
 #pragma unroll
         for (int q = 0; q < MAXV; ++q) {
             vq[q] = (q < nv) ? ((q == 0) ? a.v0 : a.V + q * a.len)[e] : 0.0;
@@ -438,20 +447,25 @@ __global__ __launch_bounds__(TPB) void bk_gs_update(BGs a)
         for (int q = k0 / 2 + threadIdx.x; q < k1 / 2; q += TPB) {
             const int i = q / n, jj = q - i * n;
             const size_t p0 = (size_t)i * n + jj, p1 = (size_t)(in.m - 1 - i) * n + jj;
+            double w0[2], w1[2];
+            jw(p0, w0[0], w0[1]);
+            jw(p1, w1[0], w1[1]);
 #pragma unroll
             for (int l = 0; l < 2; ++l) {
                 const size_t o = base + l * mn;
-                const double x0 = update(o + p0), x1 = update(o + p1);
+                const double x0 = update(o + p0, w0[l]), x1 = update(o + p1, w1[l]);
                 put_operand(a.xf, a.prec, o + q, x0 + x1);
                 put_operand(a.xf, a.prec, o + half + q, x0 - x1);
             }
         }
     } else {
         for (int k = k0 + threadIdx.x; k < k1; k += TPB) {
+            double w[2];
+            jw(k, w[0], w[1]);
 #pragma unroll
             for (int l = 0; l < 2; ++l) {
                 const size_t e = base + l * mn + k;
-                const double x = update(e);
+                const double x = update(e, w[l]);
                 if (a.xp[0]) put_operand(a.xp, a.prec, e, x);
             }
         }
