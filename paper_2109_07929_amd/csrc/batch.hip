@@ -585,7 +585,16 @@ __global__ __launch_bounds__(TPB) void bk_update(
         for (int l = 0; l < 2; ++l) {
             const size_t e = base + l * mn + kk;
             double s = overwrite ? 0.0 : X[e];
-            for (int v = 0; v < k; ++v) s += y[v] * (double)Z[(size_t)v * zstride + e];
+            // four vectors' loads in flight at a time, added in order
+            int v = 0;
+            for (; v + 4 <= k; v += 4) {
+                float z4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) z4[u] = Z[(size_t)(v + u) * zstride + e];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) s += y[v + u] * (double)z4[u];
+            }
+            for (; v < k; ++v) s += y[v] * (double)Z[(size_t)v * zstride + e];
             X[e] = s;
         }
     }
