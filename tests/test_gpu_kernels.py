@@ -267,16 +267,43 @@ def test_precond_lowprec_parity(m, n, prec, tol):
     assert err <= tol
 
 
-@pytest.mark.parametrize("prec,tol", [(B.MCA_PREC_FP32, 1e-3), (B.MCA_PREC_BF16X3, 1e-2)])
+@pytest.mark.parametrize("prec,tol", [(B.MCA_PREC_FP32, 1e-4), (B.MCA_PREC_BF16X3, 2e-4)])
 def test_precond_lowprec_large_tiles(prec, tol):
     """Products of 2048-class sizes take the 128 x 128 tiles; a ragged size (not a
     multiple of 128) against the FP64 per-mode path (itself oracle-checked above).
-    An indexing slip gives errors of order one; rounding stays far below the bound."""
+    Bounds as in the folded 1024 test (measured 4.6e-6 and 1.2e-5); an indexing slip
+    gives errors of order one."""
     m, n = 2112, 2080
     a1, a2 = 2.2e-5, 3e-5
     say(f"precond lowprec large tiles {m}x{n} prec={prec}")
     geom = synth.Geometry(m, n)
     rt, rb = synth.vector(m, n, seed=11)
+    plan = Plan(geom)
+    ft, fb = plan.precond_apply(a1, a2, dev(rt), dev(rb), form=B.MCA_PRECOND_PERMODE)
+    gt, gb = plan.precond_apply(a1, a2, dev(rt), dev(rb), form=B.MCA_PRECOND_PERMODE,
+                                precision=prec)
+    zt, zb = host(ft), host(fb)
+    scale = max(np.abs(zt).max(), np.abs(zb).max())
+    err = max(np.abs(host(gt) - zt).max(), np.abs(host(gb) - zb).max()) / scale
+    say(f"  rel err vs FP64 {err:.3e} (tol {tol:.0e})")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [(B.MCA_PREC_FP32, 1e-4), (B.MCA_PREC_BF16X3, 2e-4)])
+def test_precond_lowprec_folded_1024(prec, tol):
+    """The standard 1024 x 1024 crossbar (persymmetric bottom wires, m/2 a multiple
+    of 128): the reduced-precision chain folds and runs on 128 x 128 tiles through
+    the direct-to-LDS loop.  Element by element against the FP64 per-mode path
+    (oracle-checked above).  Rounding: four chained products of depth <= 1024,
+    ~sqrt(K) 2^-24 each in FP32 (~1e-5 in all), ~2^-16 per operand in split-BF16
+    (~2e-5); the bounds leave a factor of ten over those (measured 2.5e-6 and 1.2e-5),
+    and an indexing slip in the fold, the interleave or the unfold gives errors of
+    order one."""
+    m = n = 1024
+    a1, a2 = 2.2e-5, 3e-5
+    say(f"precond lowprec folded {m}x{n} prec={prec}")
+    geom = synth.Geometry(m, n)
+    rt, rb = synth.vector(m, n, seed=17)
     plan = Plan(geom)
     ft, fb = plan.precond_apply(a1, a2, dev(rt), dev(rb), form=B.MCA_PRECOND_PERMODE)
     gt, gb = plan.precond_apply(a1, a2, dev(rt), dev(rb), form=B.MCA_PRECOND_PERMODE,
