@@ -288,11 +288,33 @@ def test_batch_folded_large_tiles_ragged(prec):
         assert err <= TOL
 
 
+def test_batch_folded_short_depth_large_tiles():
+    """16 crossbars of 256 x 1024 give 16 x 16 = 256 tiles of 128: the folded chain
+    contracts over m / 2 = 128 (four 32-deep slices, fewer than one whole round of
+    the software-pipelined loop, so only its tail steps run) and over n = 1024.
+    Every residual recomputed by the oracle, four crossbars against its steady
+    state element by element."""
+    cbs = [synth.crossbar(256, 1024, seed=60 + s) for s in range(16)]
+    bt, vts, vbs, status, stats = batch_solve(cbs)
+    assert bt.product_tile == 128
+    assert status == B.MCA_OK
+    for b, c in enumerate(cbs):
+        ft, fb = oracle.residual(c.geom, c.g_dev, c.v_in, vts[b], vbs[b])[:2]
+        rel = np.sqrt((ft ** 2).sum() + (fb ** 2).sum()) / oracle.source_norm(c.geom, c.v_in)
+        assert rel <= 1e-10, (b, rel)
+    for b in (0, 5, 10, 15):
+        rt, rb = _oracle_cg(cbs[b], ("256x1024", b))
+        err = rel_err(vts[b], vbs[b], rt, rb)
+        say(f"  256x1024 #{b}: newton {stats[b].newton_iters} krylov {stats[b].krylov_iters} "
+            f"err {err:.1e}")
+        assert err <= TOL
+
+
 @pytest.mark.parametrize("count", [4, 5])
 def test_batch_large_tiles_1024(count):
     """1024 x 1024 crossbars on 128 x 128 tiles, split-BF16: 4 crossbars give
-    256 tiles per product (one per CU: slices go straight into LDS), 5 give 320
-    (register-staged slices, the path of larger batches).  Every crossbar's
+    256 tiles per product (one per CU), 5 give 320 (some CUs take two); interior
+    tiles take the direct-to-LDS loop either way.  Every crossbar's
     residual is recomputed by the oracle; crossbars 0 and 1 are compared with
     the oracle's steady state element by element."""
     cbs = [synth.crossbar(1024, 1024, seed=s) for s in range(count)]
