@@ -25,7 +25,8 @@
 // through LDS either from registers (two slices of global loads in flight,
 // double-buffered LDS) or, for interior 128 x 128 split-BF16 / BF16 tiles,
 // straight from global memory into three LDS buffers in a software-pipelined
-// loop (see gemm_nt_tile).  One operand may have two batches (the two layers)
+// loop whose waves read and multiply in two groups of opposite phase (see
+// gemm_nt_tile).  One operand may have two batches (the two layers)
 // that share the other operand.
 //
 // LDS layout of a staged slice (register-staged path): 16-byte chunks, in
@@ -421,10 +422,8 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
         if (fast_m && fast_n && K % KS == 0 && K >= 3 * KS) {
             // Interior tile: every slice goes from global memory straight into
             // LDS (global_load_lds_dwordx4, 16 bytes per lane), three buffers,
-            // software-pipelined: step k multiplies slice k from one register
-            // set of fragments while the other set is read from slice k + 1's
-            // buffer and slice k + 3 is loaded into the buffer slice k left, so
-            // that the LDS reads and the loads overlap the MFMAs.  Layout of a
+            // two slices ahead of the one being read; the waves read and
+            // multiply in two groups of opposite phase (below).  Layout of a
             // buffer: operand tile t, plane p, row r, 16-byte chunk c of the
             // row's 32 values at byte t sizeof(Tile) + p 64 TS + 64 r +
             // 16 (c ^ ((r >> 1) & 3)), so that each lane quad loads one row's
@@ -510,56 +509,104 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
             // expcnt in 6:4, lgkmcnt in 11:8): the loads of one slice may stay in
             // flight, LDS reads all done
             constexpr int kWaitOne = (NQ & 15) | ((NQ >> 4) << 14) | (7 << 4);
-            constexpr int kWaitTwo = ((2 * NQ) & 15) | (((2 * NQ) >> 4) << 14) | (7 << 4);
             constexpr int kWaitNone = 7 << 4;
             static_assert(2 * NQ < 64, "vmcnt range");
             const int nk = K / KS, last = nk - 1;
-            FA fa0, fa1;
-            FB fb0, fb1;
+            // Two groups of four waves, one wave of each group per SIMD, work in
+            // opposite phases: while one group multiplies the slice it read in
+            // the previous phase, the other reads its fragments of a slice from
+            // LDS and issues the next slice's loads, so that the MFMA pipe and
+            // the LDS serve different waves at the same time.  Group 0 reads
+            // slice j in phase 2j and multiplies it in phase 2j + 1; group 1
+            // one phase later.  Phases end at a barrier; before the barrier
+            // that opens an even phase (group 0 reads slice j + 1 there) every
+            // wave has its part of slice j + 1 in LDS, and at every phase end
+            // its own fragment reads are done, so slice j - 1's buffer is free
+            // for slice j + 2 once both groups have read it.  Both groups pass
+            // the same number of barriers (2 nk).
+            constexpr int kWaitLgkm = 15 | (3 << 14) | (7 << 4);   // LDS reads done, loads may fly
+            // (the dispatcher places waves w and w + 4 of a workgroup on one
+            // SIMD, measured on gfx950 through the hardware wave id; grouping
+            // w and w + 1 instead measured 6% slower than the one-phase loop)
+            const int grp = wv >> 2;
+            FA fa;
+            FB fb;
             issue(I0{}, 0);
             issue(I1{}, KS);
-            issue(I2{}, 2 * KS);
-            __builtin_amdgcn_s_waitcnt(kWaitTwo);   // slice 0 has landed
+            __builtin_amdgcn_s_waitcnt(kWaitOne);   // slice 0 has landed
             asm volatile("s_barrier" ::: "memory");
-            read(I0{}, fa0, fb0);
-            // Step k: slice k's fragments in (fc, gc), slice k in buffer BK =
-            // k mod 3 and slice k + 1 in the next.  Past the end the last slice
-            // is loaded and read again (in bounds, never multiplied), which keeps
-            // every step free of branches and the count of loads in flight the
-            // same at every wait.
-            auto step = [&](auto bk, int k, FA &fc, FB &gc, FA &fn, FB &gn) {
-                constexpr int BK = decltype(bk)::value;
-                // slice k + 1 has landed (k + 2 may still be in flight) and every
-                // wave has finished its reads of slice k: the barrier publishes
-                // the one and frees the other's buffer
-                __builtin_amdgcn_s_waitcnt(kWaitOne);
-                asm volatile("s_barrier" ::: "memory");
-                read(std::integral_constant<int, (BK + 1) % 3>{}, fn, gn);
-                // the reads go out before the next slice's loads (a read issued
-                // behind a load into LDS would wait for that load)
+            auto phase_end = [&](auto vm_wait) {
+                __builtin_amdgcn_sched_barrier(0);   // the wait stays at the end of the phase
+                if constexpr (decltype(vm_wait)::value) __builtin_amdgcn_s_waitcnt(kWaitOne);
+                else __builtin_amdgcn_s_waitcnt(kWaitLgkm);
                 __builtin_amdgcn_sched_barrier(0);
-                issue(bk, min(k + 3, last) * KS);
-                mfma_bf16(fc, gc);
-                // (steps stay apart: MFMAs moved into the next step would keep
-                // both fragment sets and more live at once)
+                asm volatile("s_barrier" ::: "memory");
                 __builtin_amdgcn_sched_barrier(0);
             };
-            // whole rounds of six steps (buffers and fragment sets back where
-            // they started) without branches between the steps, then the rest
-            int k = 0;
-            for (; k + 6 <= nk; k += 6) {
-                step(I0{}, k, fa0, fb0, fa1, fb1);
-                step(I1{}, k + 1, fa1, fb1, fa0, fb0);
-                step(I2{}, k + 2, fa0, fb0, fa1, fb1);
-                step(I0{}, k + 3, fa1, fb1, fa0, fb0);
-                step(I1{}, k + 4, fa0, fb0, fa1, fb1);
-                step(I2{}, k + 5, fa1, fb1, fa0, fb0);
+            using Odd = std::true_type;    // the barrier that opens an even phase
+            using Even = std::false_type;  // the barrier that opens an odd phase
+            // read slice j (buffer BJ) and load slice min(j + 2, last) into the
+            // buffer after the next (it held slice j - 1)
+            auto fetch = [&](auto bj, int j) {
+                constexpr int BJ = decltype(bj)::value;
+                read(bj, fa, fb);
+                __builtin_amdgcn_sched_barrier(0);
+                issue(std::integral_constant<int, (BJ + 2) % 3>{}, min(j + 2, last) * KS);
+            };
+            if (grp == 0) {
+                // phase 0 reads slice 0; every step then multiplies slice j and
+                // reads slice j + 1 (the loop starts after the barrier whose wait
+                // covers the reads' slice)
+                fetch(I0{}, 0);
+                auto step0 = [&](auto bn, int j) {
+                    phase_end(Even{});
+                    mfma_bf16(fa, fb);
+                    phase_end(Odd{});
+                    fetch(bn, j + 1);
+                };
+                int j = 0;
+                for (; j + 3 < nk; j += 3) {
+                    step0(I1{}, j);
+                    step0(I2{}, j + 1);
+                    step0(I0{}, j + 2);
+                }
+                // one to three steps left, the last without a read
+                auto tail0 = [&](auto bn, int jj) {
+                    phase_end(Even{});
+                    mfma_bf16(fa, fb);
+                    phase_end(Odd{});
+                    if (jj + 1 < nk) fetch(bn, jj + 1);
+                };
+                tail0(I1{}, j);
+                if (j + 1 < nk) tail0(I2{}, j + 1);
+                if (j + 2 < nk) tail0(I0{}, j + 2);
+            } else {
+                phase_end(Even{});   // phase 0: group 1 waits
+                auto step1 = [&](auto bj, int j) {
+                    fetch(bj, j);
+                    phase_end(Odd{});
+                    mfma_bf16(fa, fb);
+                    phase_end(Even{});
+                };
+                // every step but the last ends at a barrier
+                int j = 0;
+                for (; j + 3 <= nk - 1; j += 3) {
+                    step1(I0{}, j);
+                    step1(I1{}, j + 1);
+                    step1(I2{}, j + 2);
+                }
+                if (j < nk - 1) step1(I0{}, j);
+                if (j + 1 < nk - 1) step1(I1{}, j + 1);
+                auto last1 = [&](auto bj) {
+                    fetch(bj, last);
+                    phase_end(Odd{});
+                    mfma_bf16(fa, fb);
+                };
+                const int bl = last % 3;
+                if (bl == 0) last1(I0{});
+                else if (bl == 1) last1(I1{});
+                else last1(I2{});
             }
-            if (k < nk) step(I0{}, k, fa0, fb0, fa1, fb1);
-            if (k + 1 < nk) step(I1{}, k + 1, fa1, fb1, fa0, fb0);
-            if (k + 2 < nk) step(I2{}, k + 2, fa0, fb0, fa1, fb1);
-            if (k + 3 < nk) step(I0{}, k + 3, fa1, fb1, fa0, fb0);
-            if (k + 4 < nk) step(I1{}, k + 4, fa0, fb0, fa1, fb1);
             // no LDS DMA may outlive the workgroup (nor land in a buffer the
             // epilogue reuses)
             __builtin_amdgcn_s_waitcnt(kWaitNone);
