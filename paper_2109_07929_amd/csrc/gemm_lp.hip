@@ -543,8 +543,8 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
                 asm volatile("s_barrier" ::: "memory");
                 __builtin_amdgcn_sched_barrier(0);
             };
-            using Odd = std::true_type;    // the barrier that opens an even phase
-            using Even = std::false_type;  // the barrier that opens an odd phase
+            using ToEven = std::true_type;   // the barrier that opens an even phase
+            using ToOdd = std::false_type;   // the barrier that opens an odd phase
             // read slice j (buffer BJ) and load slice min(j + 2, last) into the
             // buffer after the next (it held slice j - 1)
             auto fetch = [&](auto bj, int j) {
@@ -559,9 +559,9 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
                 // covers the reads' slice)
                 fetch(I0{}, 0);
                 auto step0 = [&](auto bn, int j) {
-                    phase_end(Even{});
+                    phase_end(ToOdd{});
                     mfma_bf16(fa, fb);
-                    phase_end(Odd{});
+                    phase_end(ToEven{});
                     fetch(bn, j + 1);
                 };
                 int j = 0;
@@ -572,21 +572,21 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
                 }
                 // one to three steps left, the last without a read
                 auto tail0 = [&](auto bn, int jj) {
-                    phase_end(Even{});
+                    phase_end(ToOdd{});
                     mfma_bf16(fa, fb);
-                    phase_end(Odd{});
+                    phase_end(ToEven{});
                     if (jj + 1 < nk) fetch(bn, jj + 1);
                 };
                 tail0(I1{}, j);
                 if (j + 1 < nk) tail0(I2{}, j + 1);
                 if (j + 2 < nk) tail0(I0{}, j + 2);
             } else {
-                phase_end(Even{});   // phase 0: group 1 waits
+                phase_end(ToOdd{});   // phase 0: group 1 waits
                 auto step1 = [&](auto bj, int j) {
                     fetch(bj, j);
-                    phase_end(Odd{});
+                    phase_end(ToEven{});
                     mfma_bf16(fa, fb);
-                    phase_end(Even{});
+                    phase_end(ToOdd{});
                 };
                 // every step but the last ends at a barrier
                 int j = 0;
@@ -599,7 +599,7 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
                 if (j + 1 < nk - 1) step1(I1{}, j + 1);
                 auto last1 = [&](auto bj) {
                     fetch(bj, last);
-                    phase_end(Odd{});
+                    phase_end(ToEven{});
                     mfma_bf16(fa, fb);
                 };
                 const int bl = last % 3;
