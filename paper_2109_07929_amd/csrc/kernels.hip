@@ -819,8 +819,16 @@ __global__ __launch_bounds__(1024) void k_finish_fold(GsStep g, FoldArgs a)
                                     (i + 1 < m) ? a.rt[k + n] : 0.0);
         return a.rb[k] + (s + a2 * r) * inv_a1;
     };
-    const size_t stride = (size_t)(gridDim.x - 1) * 1024;
-    for (size_t k = (size_t)(blockIdx.x - 1) * 1024 + threadIdx.x; k < hn; k += stride) {
+    // Workgroups go to the eight XCDs (each with its own L2) in turn: fold
+    // block x (1 .. F) runs on XCD x mod 8.  Each XCD's blocks take one
+    // contiguous run of 1024-element chunks, so that the rows above and below
+    // a chunk, which the stencil also reads, are mostly in that XCD's L2.
+    const int F = gridDim.x - 1, x = blockIdx.x, c = x & 7;
+    int run0 = 0;   // chunks of the XCDs before c: XCD 0 holds F / 8 blocks, XCD c > 0 (F - c) / 8 + 1
+    for (int cc = 0; cc < c; ++cc) run0 += (cc == 0) ? F / 8 : (cc <= F ? (F - cc) / 8 + 1 : 0);
+    const int chunk = run0 + x / 8 - (c == 0 ? 1 : 0);
+    const size_t stride = (size_t)F * 1024;
+    for (size_t k = (size_t)chunk * 1024 + threadIdx.x; k < hn; k += stride) {
         const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
         const double w0 = w_at(i, j), w1 = w_at(m - 1 - i, j);
         a.f[k] = w0 + w1;
