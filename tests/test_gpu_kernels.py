@@ -268,7 +268,8 @@ def test_precond_lowprec_parity(m, n, prec, tol):
 
 
 @pytest.mark.parametrize("m,n", [(2112, 2080), (2144, 2016)])
-@pytest.mark.parametrize("prec,tol", [(B.MCA_PREC_FP32, 1e-4), (B.MCA_PREC_BF16X3, 2e-4)])
+@pytest.mark.parametrize("prec,tol", [(B.MCA_PREC_FP32, 1e-4), (B.MCA_PREC_BF16X3, 2e-4),
+                                      (B.MCA_PREC_BF16, 3e-2)])
 def test_precond_lowprec_large_tiles(m, n, prec, tol):
     """Products of 2048-class sizes take the 128 x 128 tiles; ragged sizes (not a
     multiple of 128) against the FP64 per-mode path (itself oracle-checked above).
@@ -276,7 +277,8 @@ def test_precond_lowprec_large_tiles(m, n, prec, tol):
     whole rounds of six 32-deep slices and then the rest one by one: depths of
     66, 65, 67 and 63 slices leave 0, 5, 1 and 3 (the batch tests' 1024-class
     depths leave 2 and 4).  Bounds as in the folded 1024 test (measured 4.6e-6 and
-    1.2e-5); an indexing slip gives errors of order one."""
+    1.2e-5); plain BF16 (one plane, 8 bits per operand) as in the small-size test
+    above; an indexing slip gives errors of order one."""
     a1, a2 = 2.2e-5, 3e-5
     say(f"precond lowprec large tiles {m}x{n} prec={prec}")
     geom = synth.Geometry(m, n)
