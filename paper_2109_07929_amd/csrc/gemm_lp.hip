@@ -527,7 +527,8 @@ __device__ __forceinline__ void gemm_nt_tile(const LpArgs &a, int m0, int n0)
             constexpr int kWaitLgkm = 15 | (3 << 14) | (7 << 4);   // LDS reads done, loads may fly
             // (the dispatcher places waves w and w + 4 of a workgroup on one
             // SIMD, measured on gfx950 through the hardware wave id; grouping
-            // w and w + 1 instead measured 6% slower than the one-phase loop)
+            // w and w + 1 instead, both waves of a SIMD in one group, measured
+            // 6% slower than all eight waves reading and multiplying in step)
             const int grp = wv >> 2;
             FA fa;
             FB fb;
