@@ -21,6 +21,22 @@ using dev::wire_apply;
 
 constexpr int kMaxReduceBlocks = 1024;
 
+// Workgroups go to the eight XCDs (each with its own L2) in turn: workgroup x
+// runs on XCD x mod 8.  For the F workgroups x0 .. x0 + F - 1 of a grid-stride
+// stencil this gives each XCD's workgroups one contiguous run of the F chunks
+// of a pass, so that the rows above and below a chunk, which the stencil also
+// reads, are mostly in that XCD's L2.
+__device__ __forceinline__ int xcd_run_chunk(int x, int x0, int F)
+{
+    const int c = x & 7;
+    int before = 0;
+    for (int cc = 0; cc < c; ++cc) {
+        const int f = (cc - x0) & 7;   // first workgroup of XCD cc, counted from x0
+        before += (F > f) ? (F - f + 7) / 8 : 0;
+    }
+    return before + (x - x0 - ((c - x0) & 7)) / 8;
+}
+
 // --------------------------------------------------------------- residual
 // F_t = G_t V_t + I - Y_t, F_b = G_b V_b - I (eqs. (MNA)/(F)); D = dI/du.
 // partials[2*block + 0] = sum F^2, partials[2*block + 1] = sum D (skipped when null).
@@ -33,7 +49,8 @@ __global__ __launch_bounds__(TPB) void k_residual(
 {
     const size_t mn = (size_t)m * n;
     double acc[2] = {0.0, 0.0};
-    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < mn; k += (size_t)gridDim.x * TPB) {
+    const size_t k0 = (size_t)xcd_run_chunk(blockIdx.x, 0, gridDim.x) * TPB + threadIdx.x;
+    for (size_t k = k0; k < mn; k += (size_t)gridDim.x * TPB) {
         const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
         const double t = vt[k], b = vb[k];
         // top wire i along j; its first node is fed by the drive through g_src (= top.end0)
@@ -156,7 +173,8 @@ __global__ __launch_bounds__(TPB) void k_precond_pre_fold(
                                     (i + 1 < m) ? rt[k + n] : 0.0);
         return rb[k] + (s + a2 * r) * inv_a1;
     };
-    for (size_t k = (size_t)blockIdx.x * TPB + threadIdx.x; k < hn; k += (size_t)gridDim.x * TPB) {
+    const size_t k0 = (size_t)xcd_run_chunk(blockIdx.x, 0, gridDim.x) * TPB + threadIdx.x;
+    for (size_t k = k0; k < hn; k += (size_t)gridDim.x * TPB) {
         const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
         const double w0 = w_at(i, j), w1 = w_at(m - 1 - i, j);
         f[k] = w0 + w1;
@@ -819,14 +837,8 @@ __global__ __launch_bounds__(1024) void k_finish_fold(GsStep g, FoldArgs a)
                                     (i + 1 < m) ? a.rt[k + n] : 0.0);
         return a.rb[k] + (s + a2 * r) * inv_a1;
     };
-    // Workgroups go to the eight XCDs (each with its own L2) in turn: fold
-    // block x (1 .. F) runs on XCD x mod 8.  Each XCD's blocks take one
-    // contiguous run of 1024-element chunks, so that the rows above and below
-    // a chunk, which the stencil also reads, are mostly in that XCD's L2.
-    const int F = gridDim.x - 1, x = blockIdx.x, c = x & 7;
-    int run0 = 0;   // chunks of the XCDs before c: XCD 0 holds F / 8 blocks, XCD c > 0 (F - c) / 8 + 1
-    for (int cc = 0; cc < c; ++cc) run0 += (cc == 0) ? F / 8 : (cc <= F ? (F - cc) / 8 + 1 : 0);
-    const int chunk = run0 + x / 8 - (c == 0 ? 1 : 0);
+    // fold workgroups 1 .. F, in runs of rows per XCD
+    const int F = gridDim.x - 1, chunk = xcd_run_chunk(blockIdx.x, 1, F);
     const size_t stride = (size_t)F * 1024;
     for (size_t k = (size_t)chunk * 1024 + threadIdx.x; k < hn; k += stride) {
         const int i = (int)(k / n), j = (int)(k - (size_t)i * n);
