@@ -87,5 +87,22 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ p, int
     return v[0];
 }
 
+
+// Workgroups go to the eight XCDs (each with its own L2) in turn: workgroup x
+// runs on XCD x mod 8.  For the F workgroups x0 .. x0 + F - 1 of a launch over
+// F chunks of a stencil, this gives each XCD's workgroups one contiguous run
+// of chunks, so that the rows above and below a chunk, which the stencil also
+// reads, are mostly in that XCD's L2.
+__device__ __forceinline__ int xcd_run_chunk(int x, int x0, int F)
+{
+    const int c = x & 7;
+    int before = 0;
+    for (int cc = 0; cc < c; ++cc) {
+        const int f = (cc - x0) & 7;   // first workgroup of XCD cc, counted from x0
+        before += (F > f) ? (F - f + 7) / 8 : 0;
+    }
+    return before + (x - x0 - ((c - x0) & 7)) / 8;
+}
+
 }  // namespace dev
 }  // namespace mca

@@ -18,24 +18,9 @@ using dev::sum_partials;
 using dev::sinh_cosh;
 using dev::TPB;
 using dev::wire_apply;
+using dev::xcd_run_chunk;
 
 constexpr int kMaxReduceBlocks = 1024;
-
-// Workgroups go to the eight XCDs (each with its own L2) in turn: workgroup x
-// runs on XCD x mod 8.  For the F workgroups x0 .. x0 + F - 1 of a grid-stride
-// stencil this gives each XCD's workgroups one contiguous run of the F chunks
-// of a pass, so that the rows above and below a chunk, which the stencil also
-// reads, are mostly in that XCD's L2.
-__device__ __forceinline__ int xcd_run_chunk(int x, int x0, int F)
-{
-    const int c = x & 7;
-    int before = 0;
-    for (int cc = 0; cc < c; ++cc) {
-        const int f = (cc - x0) & 7;   // first workgroup of XCD cc, counted from x0
-        before += (F > f) ? (F - f + 7) / 8 : 0;
-    }
-    return before + (x - x0 - ((c - x0) & 7)) / 8;
-}
 
 // --------------------------------------------------------------- residual
 // F_t = G_t V_t + I - Y_t, F_b = G_b V_b - I (eqs. (MNA)/(F)); D = dI/du.
