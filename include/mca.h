@@ -338,8 +338,14 @@ size_t     mca_batch_workspace_bytes(const mca_batch *batch, const mca_options *
 /* Steady state of every crossbar of the batch (as mca_solve, per crossbar).
  * g_dev, v_in, v_t, v_b: concatenated device arrays (see above); v_t/v_b
  * carry the initial guesses with MCA_FLAG_INITIAL_GUESS.  stats: host array
- * of count records (may be NULL).  MCA_FLAG_TIMING and MCA_FLAG_TIMING_SAMPLED
- * are accepted and ignored.
+ * of count records (may be NULL).  With MCA_FLAG_TIMING (every
+ * preconditioner application of the batch) or MCA_FLAG_TIMING_SAMPLED (every
+ * fourth), and without MCA_FLAG_GRAPH, stats[0].kernel_ms[MCA_KCLASS_GEMM]
+ * holds the GPU time between HIP events recorded on the stream just before
+ * and just after the four grouped products of those applications (each
+ * interval also holds the few microseconds an event leaves the GPU idle), and
+ * stats[0].kernel_launches[MCA_KCLASS_GEMM] four per timed application; the
+ * other classes and records stay zero.
  * The batch keeps pinned host counters and, with MCA_FLAG_GRAPH, the captured
  * Arnoldi steps (dropped when the workspace address, precision, restart
  * length, Gram-Schmidt form or uploaded block change): calls on one batch

@@ -1057,6 +1057,48 @@ int cblocks(int count) { return (count + 1023) / 1024; }
 // and replayed by later cycles and later solves.  The kernels' pointers
 // depend on the workspace address, the precision, the restart length and the
 // uploaded batch block, so a change of any of them drops the cache.
+// HIP events around the four products of the preconditioner chains
+// (MCA_FLAG_TIMING: every chain; MCA_FLAG_TIMING_SAMPLED: every fourth), eager
+// launches only, at most kMaxPairs chains per solve.
+struct ChainTimer {
+    static constexpr int kMaxPairs = 1024;
+    bool on = false;
+    int stride = 1;
+    unsigned chains = 0;
+    std::vector<hipEvent_t> ev;   // start, end of each timed chain
+    ~ChainTimer()
+    {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    // the events for the next chain, or nullptr when it is not timed
+    hipError_t next(hipEvent_t (&pair)[2])
+    {
+        pair[0] = pair[1] = nullptr;
+        if (!on || chains++ % stride != 0 || (int)ev.size() >= 2 * kMaxPairs) return hipSuccess;
+        for (int i = 0; i < 2; ++i) {
+            hipEvent_t e = nullptr;
+            const hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            ev.push_back(e);
+            pair[i] = e;
+        }
+        return hipSuccess;
+    }
+    // after the stream has completed the timed chains
+    hipError_t total(double &ms) const
+    {
+        ms = 0.0;
+        for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+            float t = 0.f;
+            const hipError_t r = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+            if (r != hipSuccess) return r;
+            ms += t;
+        }
+        return hipSuccess;
+    }
+};
+
 struct StepGraphs {
     void *ws = nullptr;
     const void *dev = nullptr;
@@ -1582,6 +1624,9 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     int *host = B->host, *host_dev = nullptr;
     MCA_BTRY(hipHostGetDevicePointer((void **)&host_dev, host, 0));
     const bool graph = (o.flags & MCA_FLAG_GRAPH) != 0;
+    ChainTimer ctm;
+    ctm.on = !graph && (o.flags & (MCA_FLAG_TIMING | MCA_FLAG_TIMING_SAMPLED)) != 0;
+    ctm.stride = (o.flags & MCA_FLAG_TIMING) ? 1 : 4;
     // the Gram-Schmidt form decides which kernels an Arnoldi step holds
     const bool two_pass = !(o.flags & MCA_FLAG_MGS_PASSES) && R <= kGsMaxV;
     StepGraphs &G = B->graphs;
@@ -1667,6 +1712,10 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
         GroupedChain c = gc;
         c.r = (j == 0) ? gs.v0 : vj;
         c.z = zj;
+        {
+            const hipError_t e = ctm.next(c.ev);
+            if (e != hipSuccess) return e;
+        }
         // the previous update pass converted v_j (and folded it for the folded chains)
         c.r_split = (two_pass && j > 0) ? 1 : 0;
         c.r_folded = c.r_split;
@@ -1859,6 +1908,12 @@ mca_status mca_solve_batched(const mca_batch *B, const double *g_dev, const doub
     MCA_BTRY(hipMemcpyAsync(rh.data(), w.rhist, rh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     MCA_BTRY(hipMemcpyAsync(kh.data(), w.khist, kh.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     MCA_BTRY(hipStreamSynchronize(s));
+    if (stats && ctm.on) {
+        double ms = 0.0;
+        MCA_BTRY(ctm.total(ms));
+        stats[0].kernel_ms[MCA_KCLASS_GEMM] = ms;
+        stats[0].kernel_launches[MCA_KCLASS_GEMM] = 4 * (int)(ctm.ev.size() / 2);
+    }
     mca_status result = MCA_OK;
     for (int b = 0; b < cnt; ++b) {
         const BState &x = S[b];

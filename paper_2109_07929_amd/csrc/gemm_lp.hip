@@ -1105,6 +1105,10 @@ hipError_t chain_grouped(const GroupedChain &c, hipStream_t s)
     set(0, c.x, c.u);
     g.data_alt[0] = c.w.p[0];
     g.data_alt[1] = c.w.p[1];
+    if (c.ev[0]) {
+        const hipError_t e = hipEventRecord(c.ev[0], s);
+        if (e != hipSuccess) return e;
+    }
     launch_grouped<MODE, 2, false, OUT, EPI_STORE>(g, c.ntiles[0], c.tile, s);
     set(1, c.u, c.w);
     launch_grouped<MODE, 2, true, OUT, EPI_PERMODE>(g, c.ntiles[1], c.tile, s);
@@ -1116,6 +1120,10 @@ hipError_t chain_grouped(const GroupedChain &c, hipStream_t s)
     set(3, c.u, z);
     g.out_elem_bytes = 4;
     launch_grouped<MODE, 2, true, OUT_F32, EPI_STORE>(g, c.ntiles[3], c.tile, s);
+    if (c.ev[1]) {
+        const hipError_t e = hipEventRecord(c.ev[1], s);
+        if (e != hipSuccess) return e;
+    }
     return hipGetLastError();
 }
 

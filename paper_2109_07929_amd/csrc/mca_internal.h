@@ -213,6 +213,9 @@ struct GroupedChain {
     // (kFoldChunk elements of the m/2 x n half) of crossbar fold_tab[b].x
     const int2 *fold_tab;
     int fold_blocks;
+    // optional: recorded on the stream just before the first product and just
+    // after the fourth (timing of the products alone)
+    hipEvent_t ev[2];
 };
 constexpr int kFoldChunk = 2048;
 hipError_t launch_precond_lowprec_grouped(int precision, const GroupedChain &c, hipStream_t s);

@@ -333,6 +333,32 @@ def test_batch_large_tiles_1024(count):
         assert err <= TOL
 
 
+@pytest.mark.parametrize("flag,stride", [(B.MCA_FLAG_TIMING, 1), (B.MCA_FLAG_TIMING_SAMPLED, 4)])
+def test_batch_timing_of_the_products(flag, stride):
+    """MCA_FLAG_TIMING(_SAMPLED) on a batch: HIP events around the four grouped
+    products of every (every fourth) preconditioner application; the solution
+    and the counts are those of the untimed solve bit for bit, stats[0] holds a
+    positive time and four launches per timed application, the other records
+    none; under MCA_FLAG_GRAPH nothing is timed."""
+    cbs = ragged_batch(seed=8)
+    bt, vt0, vb0, s0, st0 = batch_solve(cbs)
+    _, vt1, vb1, s1, st1 = batch_solve(cbs, flags=flag)
+    assert s0 == s1 == B.MCA_OK
+    for b in range(len(cbs)):
+        assert np.array_equal(vt0[b], vt1[b]) and np.array_equal(vb0[b], vb1[b])
+        assert st0[b].krylov_iters == st1[b].krylov_iters
+    ms = st1[0].kernel_ms[B.MCA_KCLASS_GEMM]
+    n = st1[0].kernel_launches[B.MCA_KCLASS_GEMM]
+    say(f"  timed {n // 4} applications, {ms:.3f} ms")
+    assert ms > 0 and n > 0 and n % 4 == 0
+    # every application of the batch is enqueued once per Arnoldi step; at least
+    # the steps of the longest-running crossbar
+    assert n // 4 >= max(s.krylov_iters for s in st1) // stride
+    assert all(s.kernel_ms[B.MCA_KCLASS_GEMM] == 0 for s in st1[1:])
+    _, _, _, s2, st2 = batch_solve(cbs, flags=flag | B.MCA_FLAG_GRAPH)
+    assert s2 == B.MCA_OK and st2[0].kernel_launches[B.MCA_KCLASS_GEMM] == 0
+
+
 def test_batch_graph_replays_match_eager():
     """Arnoldi steps captured as HIP graphs (MCA_FLAG_GRAPH) reproduce the eager
     launches bit for bit: at capture, on replays in later cycles (restart 5) and
