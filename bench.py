@@ -323,6 +323,42 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def batched_products_roofline(B, bt, cbs, g, v, vt, vb, ws, stream, **base):
+    """The batch's dominant kernels, the four grouped split-BF16 products of each
+    preconditioner application: one more batched solve from V = 0 (outside any
+    timed region) with every application's products bracketed by HIP events;
+    their algorithmic flops over that time.  None unless the solve succeeds."""
+    import torch
+
+    o = B.options(flags=B.MCA_FLAG_TIMING, **base)
+    status, stats = B.mca_solve_batched(bt.handle, bt.count, bt.total, int(bt.rows[-1]), g, v, vt,
+                                        vb, o, ws, stream, check=False)
+    torch.cuda.synchronize()
+    pms = float(stats[0].kernel_ms[B.MCA_KCLASS_GEMM])
+    apps = int(stats[0].kernel_launches[B.MCA_KCLASS_GEMM]) // 4
+    # algorithmic flops of the per-mode form: 8 (m + n) per crosspoint and
+    # application, every Arnoldi step applying P once per running crossbar
+    flops = sum(8.0 * (c.geom.m + c.geom.n) * c.geom.m * c.geom.n * st.krylov_iters
+                for c, st in zip(cbs, stats))
+    if status != B.MCA_OK or pms <= 0 or apps <= 0:
+        return None
+    tf = flops / (pms * 1e-3) / 1e12
+    return {
+        "bound": "mfma", "kernel": "the four grouped split-BF16 products of one "
+                                   "preconditioner application (k_gemm_nt_lp_grouped)",
+        "achieved": round(tf, 1), "peak": 2500.0, "unit": "TFLOP/s",
+        "frac": round(tf / 2500.0, 4),
+        "flops_unit": "algorithmic: 8(m+n) per crosspoint per application (per-mode form), "
+                      "counted once per split-BF16 product",
+        "executed_note": "split-BF16 runs three BF16 MFMA products per product; the "
+                         "persymmetric fold runs the two Q_m-side products at half depth",
+        "ms_per_application": round(pms / apps, 4), "applications_timed": apps,
+        "timing": "HIP events before the first and after the fourth product of every "
+                  "application of one batched solve from V = 0; applications enqueued past "
+                  "convergence (products that return at once) and the idle time an event "
+                  "leaves are in the time, not in the flops"}
+
+
 def compare_forms(args, dev):
     """The metric's other side at the same size and tolerance: batches of
     args.compare_batch crossbars (seeds seed .. seed + count - 1) solved by
@@ -395,35 +431,9 @@ def compare_forms(args, dev):
             "guess_used": sum(s.start for s in stats) / count,
             "max_rel_residual": max(s.rel_residual for s in stats)}
         print(f"# {form}: {ms:.2f} ms per batch of {count}", file=sys.stderr, flush=True)
-    # the batch's dominant kernels, the four grouped split-BF16 products of each
-    # preconditioner application: one more solve from V = 0 with every
-    # application's products bracketed by HIP events (outside the timed runs)
-    o = B.options(flags=B.MCA_FLAG_TIMING, **base)
-    status, stats = B.mca_solve_batched(bt.handle, count, bt.total, rows, g, v, vt, vb, o, ws,
-                                        stream, check=False)
-    torch.cuda.synchronize()
-    pms = float(stats[0].kernel_ms[B.MCA_KCLASS_GEMM])
-    apps = int(stats[0].kernel_launches[B.MCA_KCLASS_GEMM]) // 4
-    # algorithmic flops of the per-mode form: 8 (m + n) per crosspoint and
-    # application, every Arnoldi step applying P once per crossbar
-    flops = sum(8.0 * (c.geom.m + c.geom.n) * c.geom.m * c.geom.n * s.krylov_iters
-                for c, s in zip(cbs, stats))
-    if status == B.MCA_OK and pms > 0 and apps > 0:
-        tf = flops / (pms * 1e-3) / 1e12
-        out["products_roofline"] = {
-            "bound": "mfma", "kernel": "the four grouped split-BF16 products of one "
-                                       "preconditioner application (k_gemm_nt_lp_grouped)",
-            "achieved": round(tf, 1), "peak": 2500.0, "unit": "TFLOP/s",
-            "frac": round(tf / 2500.0, 4),
-            "flops_unit": "algorithmic: 8(m+n) per crosspoint per application (per-mode form), "
-                          "counted once per split-BF16 product",
-            "executed_note": "split-BF16 runs three BF16 MFMA products per product; the "
-                             "persymmetric fold runs the two Q_m-side products at half depth",
-            "ms_per_application": round(pms / apps, 4), "applications_timed": apps,
-            "timing": "HIP events before the first and after the fourth product of every "
-                      "application of one batched solve from V = 0; applications enqueued past "
-                      "convergence (products that return at once) and the idle time an event "
-                      "leaves are in the time, not in the flops"}
+    rf = batched_products_roofline(B, bt, cbs, g, v, vt, vb, ws, stream, **base)
+    if rf is not None:
+        out["products_roofline"] = rf
     return out
 
 
@@ -572,6 +582,8 @@ def leg_monte_carlo(args, dev, count=256):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
     print(f"# Monte-Carlo {count}: {ms:.2f} ms per batch", file=sys.stderr, flush=True)
+    rf = batched_products_roofline(B, bt, cbs, g, v, vt, vb, ws, stream,
+                                   precond=B.MCA_PRECOND_PERMODE, precision=B.MCA_PREC_BF16X3)
     del ws
     torch.cuda.empty_cache()
     # the loop: one plan and workspace per crossbar, one mca_solve after another
@@ -607,7 +619,8 @@ def leg_monte_carlo(args, dev, count=256):
             "batched": {"ms_per_batch": round(ms, 3), "solves_per_s": round(count * 1e3 / ms, 1),
                         "status": B.status_string(status), "setup_ms": round(setup_ms, 1),
                         "solves_per_s_with_setup": round(count * 1e3 / (ms + setup_ms), 1),
-                        "newton_iters": [min(newton), max(newton)]},
+                        "newton_iters": [min(newton), max(newton)],
+                        "products_roofline": rf},
             "loop": {"ms_per_batch": round(loop_ms, 3),
                      "solves_per_s": round(count * 1e3 / loop_ms, 1),
                      "status": B.status_string(lstatus), "setup_ms": round(loop_setup_ms, 1),
